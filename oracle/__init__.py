@@ -1,0 +1,217 @@
+"""CPU oracle for the Hankel tensor-vector product -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never uses it.
+
+The arithmetic lives in ``hk_oracle.c`` (plain C, FP64 and complex int64, no
+FFT): the Section 1 / Section 2.1 definition of the products, with the terms of
+each output gathered by their index sum into direct convolutions followed by a
+correlation with the generating vector.  This module only marshals numpy
+arrays to it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hk_oracle.c")
+_LIB = os.path.join(_HERE, "libhk_oracle.so")
+_lib_handle = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP, -O2).  Returns the library path."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.hko_conv_range.argtypes = [P, I64, P, I64, I64, I64, P]
+        lib.hko_conv.argtypes = [P, I64, P, I64, P]
+        lib.hko_corr.argtypes = [P, I64, P, I64, I64, P]
+        lib.hko_tvp.argtypes = [ctypes.c_int, P, P, P, P, P]
+        lib.hko_tvp_sampled.argtypes = [ctypes.c_int, P, P, P, P, I64, P, P]
+        lib.hko_tvp_i64.argtypes = [ctypes.c_int, P, P, P, P, P]
+        lib.hko_block_tvp.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+        lib.hko_block_tvp_i64.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+        lib.hko_tvp_backward.argtypes = [ctypes.c_int, I64, P, P, P, P, P, P]
+        lib.hko_max_threads.argtypes = []
+        for f in (lib.hko_conv_range, lib.hko_conv, lib.hko_corr, lib.hko_tvp, lib.hko_tvp_sampled,
+                  lib.hko_tvp_i64, lib.hko_block_tvp, lib.hko_block_tvp_i64, lib.hko_tvp_backward,
+                  lib.hko_max_threads):
+            f.restype = ctypes.c_int
+        _lib_handle = lib
+    return _lib_handle
+
+
+def max_threads() -> int:
+    return int(_lib().hko_max_threads())
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def _vec_ptrs(vectors: Sequence[Optional[np.ndarray]]):
+    arr = (ctypes.c_void_p * len(vectors))()
+    for i, v in enumerate(vectors):
+        arr[i] = None if v is None else v.ctypes.data
+    return arr
+
+
+def conv(a, b, k0: int = 0, k1: Optional[int] = None) -> np.ndarray:
+    """Linear convolution (a * b)_k for k in [k0, k1)."""
+    a, b = _c128(a), _c128(b)
+    if k1 is None:
+        k1 = len(a) + len(b) - 1
+    out = np.empty(max(k1 - k0, 0), np.complex128)
+    _check(_lib().hko_conv_range(_ptr(a), len(a), _ptr(b), len(b), k0, k1, _ptr(out)), "conv")
+    return out
+
+
+def corr(h, w, ny: int) -> np.ndarray:
+    """y_i = sum_k h_{i+k} w_k, i < ny."""
+    h, w = _c128(h), _c128(w)
+    out = np.empty(ny, np.complex128)
+    _check(_lib().hko_corr(_ptr(h), len(h), _ptr(w), len(w), ny, _ptr(out)), "corr")
+    return out
+
+
+def _prep(m, dims, h, vectors, need_first):
+    dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int64))
+    if len(dims) != m:
+        raise ValueError("dims must have m entries")
+    h = _c128(h)
+    vecs: List[Optional[np.ndarray]] = []
+    for p in range(m):
+        v = vectors[p] if p < len(vectors) else None
+        if v is None:
+            if p == 0 and not need_first:
+                vecs.append(None)
+                continue
+            raise ValueError(f"vector {p + 1} is required")
+        v = _c128(v)
+        vecs.append(v)
+    return dims, h, vecs
+
+
+def tvp(m: int, dims, h, vectors, want_y: bool = True, want_alpha: bool = False):
+    """Returns (y, alpha): y = H x_2 ... x_m (length dims[0]), alpha = H x_1 ... x_m."""
+    dims, h, vecs = _prep(m, dims, h, vectors, want_alpha)
+    y = np.empty(int(dims[0]), np.complex128) if want_y else None
+    alpha = np.zeros(1, np.complex128) if want_alpha else None
+    keep = _vec_ptrs(vecs)
+    _check(_lib().hko_tvp(m, _ptr(dims), _ptr(h), keep, _ptr(y), _ptr(alpha)), "tvp")
+    return y, (None if alpha is None else complex(alpha[0]))
+
+
+def tvp_sampled(m: int, dims, h, vectors, idx, want_alpha: bool = False):
+    """y at the given output indices (and alpha if asked)."""
+    dims, h, vecs = _prep(m, dims, h, vectors, want_alpha)
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    y = np.empty(len(idx), np.complex128)
+    alpha = np.zeros(1, np.complex128) if want_alpha else None
+    keep = _vec_ptrs(vecs)
+    _check(_lib().hko_tvp_sampled(m, _ptr(dims), _ptr(h), keep, _ptr(idx), len(idx), _ptr(y),
+                                  _ptr(alpha)), "tvp_sampled")
+    return y, (None if alpha is None else complex(alpha[0]))
+
+
+def _i64pairs(a) -> np.ndarray:
+    a = np.asarray(a)
+    re = np.real(a)
+    im = np.imag(a) if np.iscomplexobj(a) else np.zeros_like(re)
+    if not (np.all(re == np.round(re)) and np.all(im == np.round(im))):
+        raise ValueError("integer oracle needs integer-valued inputs")
+    out = np.empty((len(a), 2), np.int64)
+    out[:, 0] = re.astype(np.int64)
+    out[:, 1] = im.astype(np.int64)
+    return np.ascontiguousarray(out)
+
+
+def tvp_i64(m: int, dims, h, vectors, want_y: bool = True, want_alpha: bool = False):
+    """Exact complex-int64 product.  Returns (y, alpha) as (n,2)/(2,) int64 arrays."""
+    dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int64))
+    hi = _i64pairs(h)
+    vecs = [None if (v is None) else _i64pairs(v) for v in vectors]
+    y = np.empty((int(dims[0]), 2), np.int64) if want_y else None
+    alpha = np.zeros(2, np.int64) if want_alpha else None
+    keep = _vec_ptrs(vecs)
+    _check(_lib().hko_tvp_i64(m, _ptr(dims), _ptr(hi), keep, _ptr(y), _ptr(alpha)), "tvp_i64")
+    return y, alpha
+
+
+def block_tvp(m: int, dims, block_dims, H, vectors, want_y: bool = True, want_alpha: bool = False):
+    """BHHB product.  H column-major (sum n - m + 1) x (sum N - m + 1); y = vec(Y), Y n_1 x N_1."""
+    dims, H, vecs = _prep(m, dims, H, vectors, want_alpha)
+    bd = np.ascontiguousarray(np.asarray(block_dims, dtype=np.int64))
+    y = np.empty(int(dims[0] * bd[0]), np.complex128) if want_y else None
+    alpha = np.zeros(1, np.complex128) if want_alpha else None
+    keep = _vec_ptrs(vecs)
+    _check(_lib().hko_block_tvp(m, _ptr(dims), _ptr(bd), _ptr(H), keep, _ptr(y), _ptr(alpha)),
+           "block_tvp")
+    return y, (None if alpha is None else complex(alpha[0]))
+
+
+def block_tvp_i64(m: int, dims, block_dims, H, vectors, want_y: bool = True, want_alpha: bool = False):
+    dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int64))
+    bd = np.ascontiguousarray(np.asarray(block_dims, dtype=np.int64))
+    Hi = _i64pairs(H)
+    vecs = [None if (v is None) else _i64pairs(v) for v in vectors]
+    y = np.empty((int(dims[0] * bd[0]), 2), np.int64) if want_y else None
+    alpha = np.zeros(2, np.int64) if want_alpha else None
+    keep = _vec_ptrs(vecs)
+    _check(_lib().hko_block_tvp_i64(m, _ptr(dims), _ptr(bd), _ptr(Hi), keep, _ptr(y), _ptr(alpha)),
+           "block_tvp_i64")
+    return y, alpha
+
+
+def tvp_backward(m: int, h, x, v=None, phi=None, want_grad_x: bool = True, want_grad_h: bool = True):
+    """J^H applied to cotangents v (of g = H x^{m-1}) and phi (of f = H x^m).
+
+    Returns (grad_x, grad_h)."""
+    h, x = _c128(h), _c128(x)
+    n = len(x)
+    if len(h) != m * (n - 1) + 1:
+        raise ValueError("h must have m(n-1)+1 entries")
+    v = None if v is None else _c128(v)
+    ph = None if phi is None else np.array([phi], np.complex128)
+    gx = np.empty(n, np.complex128) if want_grad_x else None
+    gh = np.empty(len(h), np.complex128) if want_grad_h else None
+    _check(_lib().hko_tvp_backward(m, n, _ptr(h), _ptr(x), _ptr(v), _ptr(ph), _ptr(gx), _ptr(gh)),
+           "tvp_backward")
+    return gx, gh
+
+
+def problem_tvp(prob, want_y: Optional[bool] = None, want_alpha: Optional[bool] = None):
+    """Oracle result for a ``workloads.Problem``."""
+    wy = prob.want_y if want_y is None else want_y
+    wa = prob.want_alpha if want_alpha is None else want_alpha
+    if prob.is_block:
+        return block_tvp(prob.m, prob.dims, prob.block_dims, prob.h, prob.vectors, wy, wa)
+    return tvp(prob.m, prob.dims, prob.h, prob.vectors, wy, wa)
