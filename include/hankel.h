@@ -1,0 +1,255 @@
+/*
+ * hankel.h -- C ABI of the MI355X (gfx950) fast Hankel tensor-vector product.
+ *
+ * Method (Ding, Qi, Wei, "Fast Hankel tensor-vector products and application
+ * to exponential data fitting"): an order-m Hankel tensor H of size
+ * n_1 x ... x n_m is fixed by its generating vector h of length
+ * d_H = n_1 + ... + n_m - m + 1 (Section 1).  It sits in the corner of the
+ * anti-circulant tensor with compressed generating vector h, which the Fourier
+ * matrix diagonalizes (Theorem 2.1), so each product becomes zero padding,
+ * FFTs, one pointwise spectral product, an FFT and a slice (Section 3):
+ *
+ *   y     = H x_2 x_3 ... x_m  = fft( ifft(h~) .* fft(x~_2) .* ... .* fft(x~_m) )[0 : n_1)
+ *   alpha = H x_1 x_2 ... x_m  = ifft(h~)^T ( fft(x~_1) .* ... .* fft(x~_m) )
+ *
+ * with fft(v)_k = sum_j v_j e^{-2 pi i jk/N}, ifft = (1/N) * conjugate kernel,
+ * "~" = zero padding to length N >= d_H, and products taken without complex
+ * conjugation (Section 2.1 mode-p product).  The library pads to the next power
+ * of two N >= d_H; any N >= d_H gives the same result.  The 2-level block
+ * (BHHB) form uses 2D FFTs on a grid of at least
+ * (sum n_p - m + 1) x (sum N_p - m + 1) (Section 3, BHHB procedure).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Data pointers are DEVICE pointers owned by the caller.  Arrays are
+ *    contiguous (stride 1).  Complex dtypes are interleaved (re, im) pairs;
+ *    real dtypes (HK_F32, HK_F64) mean real inputs and real outputs (the
+ *    imaginary part of the complex result, pure rounding noise for real data,
+ *    is dropped).  Each pointer must be aligned to its element size.
+ *  - Arrays of vector pointers ("vectors") are HOST arrays of device pointers.
+ *  - Calls are asynchronous and stream-ordered on `stream` (NULL = default
+ *    stream).  Outputs are fully overwritten; outputs must not alias inputs.
+ *  - Workspace: `ws`/`ws_bytes` is caller-owned device scratch of at least the
+ *    size the matching *_workspace_size call reports (it may be NULL when that
+ *    size is 0).  The library allocates no device memory in these calls apart
+ *    from a one-time, per-device twiddle-table setup on first use.
+ *  - Errors are return codes; nothing is thrown or aborted across the ABI.
+ *    Arguments are validated on the host before anything is enqueued.
+ *    hk_last_error() gives a thread-local description of the last failure.
+ */
+#ifndef HANKEL_H_
+#define HANKEL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+struct ihipStream_t;
+typedef struct ihipStream_t *hipStream_t;
+
+typedef enum {
+    HK_C64 = 0,  /* complex float  (8-byte elements)  */
+    HK_C128 = 1, /* complex double (16-byte elements) */
+    HK_F32 = 2,  /* real float                        */
+    HK_F64 = 3   /* real double                       */
+} hk_dtype_t;
+
+typedef int hk_status_t;
+#define HK_SUCCESS 0
+#define HK_ERR_INVALID_VALUE 1 /* m outside [2, HK_MAX_ORDER], a dim < 1, bad dtype/flags  */
+#define HK_ERR_NULL_POINTER 2  /* a required pointer is NULL, or no output requested       */
+#define HK_ERR_MISALIGNED 3    /* a data pointer is not aligned to its element size         */
+#define HK_ERR_WORKSPACE 4     /* ws_bytes smaller than the reported workspace size         */
+#define HK_ERR_SIZE_LIMIT 5    /* padded length (per axis) above HK_MAX_FFT_LOG2 or overflow */
+#define HK_ERR_DEVICE 6        /* current device is not gfx950                              */
+#define HK_ERR_HIP 7           /* a HIP runtime call or kernel launch failed                */
+#define HK_ERR_DEVICE_FAULT 8  /* a batched plan's kernel reported an error (see status)    */
+#define HK_ERR_NOT_SUPPORTED 9 /* valid request outside what this build implements          */
+
+#define HK_MAX_ORDER 8
+#define HK_MAX_FFT_LOG2 24 /* 1D: N <= 2^24; BHHB: each grid axis <= 2^12 */
+
+/* -------------------------------------------------------------------------
+ * Square Hankel tensor, all vectors equal (Section 3 procedures with
+ * x_1 = ... = x_m = x; Qi's notation H x^{m-1}, H x^m, Section 2.1).
+ *   h     : d_H = m(n-1)+1 elements
+ *   x     : n elements
+ *   y     : if non-NULL, receives H x^{m-1} (n elements)
+ *   alpha : if non-NULL, receives H x^m (1 element, on the device)
+ * At least one of y, alpha must be non-NULL.  Both come from one set of FFTs.
+ * ------------------------------------------------------------------------- */
+hk_status_t hankel_tvp_workspace_size(hk_dtype_t dt, int m, int64_t n, size_t *bytes);
+hk_status_t hankel_tvp(hk_dtype_t dt, const void *h, int m, int64_t n, const void *x,
+                       void *y, void *alpha, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* -------------------------------------------------------------------------
+ * General Hankel tensor n_1 x ... x n_m, distinct vectors (Section 3, the two
+ * product types y = H x_2 ... x_m and alpha = H x_1 ... x_m).
+ *   dims    : host array of m sizes n_p >= 1
+ *   h       : sum(dims) - m + 1 elements
+ *   vectors : host array of m device pointers; vectors[p] has dims[p]
+ *             elements.  vectors[0] is read only when alpha is requested.
+ *             Identical pointers with identical lengths are transformed once.
+ *   y       : if non-NULL, receives H x_2 ... x_m (dims[0] elements)
+ *   alpha   : if non-NULL, receives H x_1 ... x_m (1 element)
+ * ------------------------------------------------------------------------- */
+hk_status_t hankel_mode_products_workspace_size(hk_dtype_t dt, int m, const int64_t *dims,
+                                                const void *const *vectors, int want_y,
+                                                int want_alpha, size_t *bytes);
+hk_status_t hankel_mode_products(hk_dtype_t dt, const void *h, int m, const int64_t *dims,
+                                 const void *const *vectors, void *y, void *alpha, void *ws,
+                                 size_t ws_bytes, hipStream_t stream);
+
+/* -------------------------------------------------------------------------
+ * 2-level block Hankel tensor with Hankel blocks (BHHB; Section 2.2
+ * generating matrix, Section 3 BHHB procedure).  Mode p has N_p blocks of
+ * size n_p; the tensor entry at in-block indices (i_p) and block indices
+ * (j_p) is H[i_1+...+i_m, j_1+...+j_m].
+ *   inner_dims : n_p (host array, m entries)
+ *   block_dims : N_p (host array, m entries)
+ *   H          : generating matrix, column-major,
+ *                (sum n_p - m + 1) rows x (sum N_p - m + 1) columns
+ *   vectors[p] : vec(X_p), n_p * N_p elements, X_p[i, j] = vectors[p][i + n_p j]
+ *   y          : if non-NULL, receives vec(Y), Y = (H x_2 ... x_m) as an
+ *                n_1 x N_1 column-major matrix
+ *   alpha      : if non-NULL, receives H x_1 ... x_m (needs vectors[0])
+ * ------------------------------------------------------------------------- */
+hk_status_t block_hankel_tvp_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims,
+                                            const int64_t *block_dims, const void *const *vectors,
+                                            int want_y, int want_alpha, size_t *bytes);
+hk_status_t block_hankel_tvp(hk_dtype_t dt, const void *H, int m, const int64_t *inner_dims,
+                             const int64_t *block_dims, const void *const *vectors, void *y,
+                             void *alpha, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* -------------------------------------------------------------------------
+ * Batched products: heterogeneous problems (any mix of orders, sizes, 1D and
+ * BHHB, equal or distinct vectors) executed together.  The paper motivates
+ * this with the Hankel tensor-matrix products of HOOI (Section 4.2), which
+ * are batches of tensor-vector products.
+ *
+ * One hk_problem_t per product.  For 1D problems block_dims is ignored; for
+ * BHHB problems (is_block = 1) dims are the n_p and block_dims the N_p.
+ * vectors[0] is read only when alpha != NULL.  y / alpha as above (at least
+ * one non-NULL).  Problems must not write to overlapping outputs.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t m;
+    int32_t is_block;
+    int32_t reserved0;
+    int32_t reserved1;
+    int64_t dims[HK_MAX_ORDER];
+    int64_t block_dims[HK_MAX_ORDER];
+    const void *h;
+    const void *vectors[HK_MAX_ORDER];
+    void *y;
+    void *alpha;
+} hk_problem_t;
+
+typedef struct hk_plan_s *hk_plan_t;
+
+#define HK_PLAN_PERSISTENT 0x1u /* one persistent launch with an in-kernel task queue          */
+#define HK_PLAN_MULTIKERNEL 0x2u /* one launch per pass (per-pass profiling; same kernels)     */
+#define HK_PLAN_GRAPH 0x4u      /* capture the plan's launches in a hipGraph on first execute */
+#define HK_PLAN_AUTOTUNE 0x8u   /* time the candidate schedules on the device at creation     */
+
+/* Creates a plan for `count` problems.  The plan copies the descriptors
+ * (pointers included) and owns only host memory and, with HK_PLAN_GRAPH, a
+ * graph.  flags = 0 picks the persistent schedule.  Autotuning runs kernels
+ * on the current device, writing only into a temporary workspace that it
+ * allocates and frees itself. */
+hk_status_t hk_plan_create(hk_plan_t *plan, hk_dtype_t dt, const hk_problem_t *probs,
+                           int64_t count, unsigned flags);
+hk_status_t hk_plan_workspace_size(hk_plan_t plan, size_t *bytes);
+/* Enqueues the plan.  The workspace must stay untouched until the plan's work
+ * on `stream` has finished. */
+hk_status_t hk_plan_execute(hk_plan_t plan, void *ws, size_t ws_bytes, hipStream_t stream);
+/* Synchronizes the last execute's stream and returns HK_SUCCESS or
+ * HK_ERR_DEVICE_FAULT if the persistent kernel flagged an error (a
+ * dependency wait that exceeded its spin bound). */
+hk_status_t hk_plan_status(hk_plan_t plan);
+hk_status_t hk_plan_destroy(hk_plan_t plan);
+
+/* One-shot convenience: create (no autotune), execute, destroy. */
+hk_status_t hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs,
+                                              int64_t count, size_t *bytes);
+hk_status_t hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t count,
+                               void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* -------------------------------------------------------------------------
+ * Adjoint of the equal-vector products g = H x^{m-1} (n values) and
+ * f = H x^m (a scalar).  The paper does not differentiate; this follows
+ * complex autograd's convention for holomorphic maps: the returned gradients
+ * are J^H applied to the cotangents,
+ *   grad_h = conj( ifft( x^^{m-1} .* (V^ + conj(phi) x^) ) )[0 : d_H)
+ *   grad_x = conj( fft( h^ .* x^^{m-2} .* ((m-1) V^ + m conj(phi) x^) ) )[0 : n)
+ * with h^ = ifft(h~), x^ = fft(x~), V^ = fft(conj(v)~): spectral
+ * correlations on the same padded grid as the forward product.
+ *   grad_y     : cotangent v of g (n elements) or NULL (zero)
+ *   grad_alpha : cotangent phi of f (1 element, device) or NULL (zero)
+ *   grad_x     : n elements or NULL (not requested)
+ *   grad_h     : d_H elements or NULL (not requested)
+ * Complex dtypes only.
+ * ------------------------------------------------------------------------- */
+hk_status_t hankel_tvp_backward_workspace_size(hk_dtype_t dt, int m, int64_t n, size_t *bytes);
+hk_status_t hankel_tvp_backward(hk_dtype_t dt, const void *h, int m, int64_t n, const void *x,
+                                const void *grad_y, const void *grad_alpha, void *grad_x,
+                                void *grad_h, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Strided batch of equal-vector products of one shape (m, n): instance b uses
+ * h + b*h_stride, x + b*x_stride, y + b*y_stride, alpha + b (elements).
+ * y or alpha may be NULL.  One launch per pass covers the whole batch. */
+hk_status_t hankel_tvp_strided_batched_workspace_size(hk_dtype_t dt, int m, int64_t n,
+                                                      int64_t batch, size_t *bytes);
+hk_status_t hankel_tvp_strided_batched(hk_dtype_t dt, const void *h, int64_t h_stride, int m,
+                                       int64_t n, const void *x, int64_t x_stride, void *y,
+                                       int64_t y_stride, void *alpha, int64_t batch, void *ws,
+                                       size_t ws_bytes, hipStream_t stream);
+hk_status_t hankel_tvp_backward_strided_batched_workspace_size(hk_dtype_t dt, int m, int64_t n,
+                                                               int64_t batch, size_t *bytes);
+hk_status_t hankel_tvp_backward_strided_batched(
+    hk_dtype_t dt, const void *h, int64_t h_stride, int m, int64_t n, const void *x,
+    int64_t x_stride, const void *grad_y, int64_t gy_stride, const void *grad_alpha,
+    void *grad_x, int64_t gx_stride, void *grad_h, int64_t gh_stride, int64_t batch, void *ws,
+    size_t ws_bytes, hipStream_t stream);
+
+/* Strided batch of BHHB products of one shape: instance b uses
+ * H + b*H_stride, x + b*x_stride (all m vectors equal), y + b*y_stride,
+ * alpha + b. */
+hk_status_t block_hankel_tvp_strided_batched_workspace_size(hk_dtype_t dt, int m,
+                                                            const int64_t *inner_dims,
+                                                            const int64_t *block_dims,
+                                                            int64_t batch, size_t *bytes);
+hk_status_t block_hankel_tvp_strided_batched(hk_dtype_t dt, const void *H, int64_t H_stride,
+                                             int m, const int64_t *inner_dims,
+                                             const int64_t *block_dims, const void *x,
+                                             int64_t x_stride, void *y, int64_t y_stride,
+                                             void *alpha, int64_t batch, void *ws,
+                                             size_t ws_bytes, hipStream_t stream);
+
+/* -------------------------------------------------------------------------
+ * Schedule control and diagnostics.
+ * ------------------------------------------------------------------------- */
+/* Padded FFT length (1D) chosen for a given d_H, and its row x column split
+ * (N = n_row * n_col; n_col = 1 means one workgroup holds the whole
+ * transform). */
+hk_status_t hk_fft_layout(int64_t d_h, int64_t *n_fft, int64_t *n_row, int64_t *n_col);
+/* Runs the in-house autotuner for the plain 1D path of one (dtype, m, n)
+ * shape on the current device and stores the winner in the process-wide
+ * schedule cache (and in the JSON file named by HK_TUNE_CACHE, if set).
+ * Allocates and frees its own temporary device buffers. */
+hk_status_t hk_autotune_tvp(hk_dtype_t dt, int m, int64_t n, int verbose);
+/* Number of the library's kernel launches enqueued by the last call made on
+ * this thread (diagnostics). */
+int hk_last_launch_count(void);
+
+const char *hk_status_string(hk_status_t s);
+const char *hk_last_error(void);
+int hk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HANKEL_H_ */

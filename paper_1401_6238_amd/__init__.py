@@ -1,0 +1,22 @@
+"""Fast Hankel tensor-vector products on MI355X (gfx950).
+
+The arithmetic runs in libhankel.so (hand-written HIP kernels); this package
+marshals torch tensors to its C ABI.  Importing the package does not load the
+library; the first call does, and raises if it has not been built.
+"""
+__all__ = [
+    "hankel_tvp", "hankel_mode_products", "block_hankel_tvp", "hankel_tvp_backward",
+    "hankel_tvp_strided_batched", "hankel_tvp_backward_strided_batched", "block_hankel_tvp_strided_batched",
+    "hankel_tvp_batched", "Plan", "hk_fft_layout", "hk_autotune_tvp", "hk_last_launch_count",
+    "HankelTVPFunction", "hankel_tvp_autograd",
+]
+
+
+def __getattr__(name):
+    if name in ("HankelTVPFunction", "hankel_tvp_autograd"):
+        from . import autograd
+        return getattr(autograd, name)
+    if name in __all__:
+        from . import binding
+        return getattr(binding, name)
+    raise AttributeError(name)

@@ -1,0 +1,309 @@
+"""Python entry points with the names of the C ABI (marshalling only).
+
+Every function takes torch tensors already resident on the GPU, allocates the
+outputs and the workspace with torch (device memory and the current stream
+are all torch provides here), and calls libhankel.so.  No arithmetic of the
+product happens in Python.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+_DT = {
+    torch.complex64: _lib.HK_C64,
+    torch.complex128: _lib.HK_C128,
+    torch.float32: _lib.HK_F32,
+    torch.float64: _lib.HK_F64,
+}
+
+
+def _dtype(t: torch.Tensor) -> int:
+    try:
+        return _DT[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t.dtype}") from None
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev(t: torch.Tensor) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("tensors must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return t
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int, device) -> Tuple[Optional[torch.Tensor], int]:
+    if nbytes == 0:
+        return None, 0
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device), int(nbytes)
+
+
+def _i64arr(vals):
+    arr = (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def _vecarr(vals):
+    arr = (ctypes.c_void_p * len(vals))()
+    for i, v in enumerate(vals):
+        arr[i] = None if v is None else v.data_ptr()
+    return arr
+
+
+def _same_device(*ts):
+    devs = {t.device for t in ts if t is not None}
+    if len(devs) > 1:
+        raise ValueError("all tensors must be on one device")
+
+
+def hankel_tvp(h: torch.Tensor, x: torch.Tensor, m: int, want_y: bool = True, want_alpha: bool = False):
+    """Square Hankel tensor, equal vectors: (H x^{m-1}, H x^m).  Returns (y, alpha)."""
+    _dev(h), _dev(x)
+    _same_device(h, x)
+    if h.dtype != x.dtype:
+        raise TypeError("h and x must share a dtype")
+    n = x.numel()
+    dt = _dtype(x)
+    y = torch.empty(n, dtype=x.dtype, device=x.device) if want_y else None
+    alpha = torch.empty(1, dtype=x.dtype, device=x.device) if want_alpha else None
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_tvp_workspace_size(dt, m, n, ctypes.byref(nb)), "hankel_tvp_workspace_size")
+    ws, wsb = _workspace(nb.value, x.device)
+    check(lib().hankel_tvp(dt, _ptr(h), m, n, _ptr(x), _ptr(y), _ptr(alpha), _ptr(ws), wsb, _stream(x.device)),
+          "hankel_tvp")
+    return y, (None if alpha is None else alpha[0])
+
+
+def hankel_mode_products(h: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]], dims: Sequence[int] = None,
+                         want_y: bool = True, want_alpha: bool = False):
+    """General Hankel tensor: y = H x_2 ... x_m, alpha = H x_1 ... x_m.
+
+    vectors[0] (x_1) may be None when want_alpha is False.  dims default to
+    the vector lengths (dims[0] must be given if vectors[0] is None)."""
+    m = len(vectors)
+    if dims is None:
+        if vectors[0] is None:
+            raise ValueError("dims[0] is needed when vectors[0] is None")
+        dims = [v.numel() for v in vectors]
+    ref = next(v for v in vectors if v is not None)
+    _dev(h)
+    for v in vectors:
+        if v is not None:
+            _dev(v)
+    _same_device(h, *vectors)
+    dt = _dtype(ref)
+    y = torch.empty(int(dims[0]), dtype=ref.dtype, device=ref.device) if want_y else None
+    alpha = torch.empty(1, dtype=ref.dtype, device=ref.device) if want_alpha else None
+    d = _i64arr(dims)
+    va = _vecarr(vectors)
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_mode_products_workspace_size(dt, m, d, va, int(want_y), int(want_alpha), ctypes.byref(nb)),
+          "hankel_mode_products_workspace_size")
+    ws, wsb = _workspace(nb.value, ref.device)
+    check(lib().hankel_mode_products(dt, _ptr(h), m, d, va, _ptr(y), _ptr(alpha), _ptr(ws), wsb,
+                                     _stream(ref.device)), "hankel_mode_products")
+    return y, (None if alpha is None else alpha[0])
+
+
+def block_hankel_tvp(H: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]], inner_dims: Sequence[int],
+                     block_dims: Sequence[int], want_y: bool = True, want_alpha: bool = False):
+    """BHHB tensor: H is the column-major generating matrix (flat); vectors are vec(X_p)."""
+    m = len(vectors)
+    ref = next(v for v in vectors if v is not None)
+    _dev(H)
+    _same_device(H, *vectors)
+    dt = _dtype(ref)
+    ny = int(inner_dims[0]) * int(block_dims[0])
+    y = torch.empty(ny, dtype=ref.dtype, device=ref.device) if want_y else None
+    alpha = torch.empty(1, dtype=ref.dtype, device=ref.device) if want_alpha else None
+    di, db = _i64arr(inner_dims), _i64arr(block_dims)
+    va = _vecarr(vectors)
+    nb = ctypes.c_size_t(0)
+    check(lib().block_hankel_tvp_workspace_size(dt, m, di, db, va, int(want_y), int(want_alpha), ctypes.byref(nb)),
+          "block_hankel_tvp_workspace_size")
+    ws, wsb = _workspace(nb.value, ref.device)
+    check(lib().block_hankel_tvp(dt, _ptr(H), m, di, db, va, _ptr(y), _ptr(alpha), _ptr(ws), wsb,
+                                 _stream(ref.device)), "block_hankel_tvp")
+    return y, (None if alpha is None else alpha[0])
+
+
+def hankel_tvp_backward(h: torch.Tensor, x: torch.Tensor, m: int, grad_y: Optional[torch.Tensor],
+                        grad_alpha: Optional[torch.Tensor], want_grad_x: bool = True, want_grad_h: bool = True):
+    """J^H [grad_y; grad_alpha] for g = H x^{m-1}, f = H x^m.  Returns (grad_x, grad_h)."""
+    _dev(h), _dev(x)
+    n = x.numel()
+    dt = _dtype(x)
+    gx = torch.empty(n, dtype=x.dtype, device=x.device) if want_grad_x else None
+    gh = torch.empty(h.numel(), dtype=x.dtype, device=x.device) if want_grad_h else None
+    ga = None if grad_alpha is None else grad_alpha.reshape(1).contiguous()
+    gy = None if grad_y is None else grad_y.contiguous()
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_tvp_backward_workspace_size(dt, m, n, ctypes.byref(nb)), "hankel_tvp_backward_workspace_size")
+    ws, wsb = _workspace(nb.value, x.device)
+    check(lib().hankel_tvp_backward(dt, _ptr(h), m, n, _ptr(x), _ptr(gy), _ptr(ga), _ptr(gx), _ptr(gh), _ptr(ws), wsb,
+                                    _stream(x.device)), "hankel_tvp_backward")
+    return gx, gh
+
+
+def hankel_tvp_strided_batched(h: torch.Tensor, x: torch.Tensor, m: int, want_y: bool = True,
+                               want_alpha: bool = False):
+    """Batch of equal-vector products: h (B, d_H), x (B, n).  Returns (y (B, n), alpha (B,))."""
+    _dev(h), _dev(x)
+    B, n = x.shape
+    dt = _dtype(x)
+    y = torch.empty(B, n, dtype=x.dtype, device=x.device) if want_y else None
+    alpha = torch.empty(B, dtype=x.dtype, device=x.device) if want_alpha else None
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_tvp_strided_batched_workspace_size(dt, m, n, B, ctypes.byref(nb)),
+          "hankel_tvp_strided_batched_workspace_size")
+    ws, wsb = _workspace(nb.value, x.device)
+    check(lib().hankel_tvp_strided_batched(dt, _ptr(h), h.shape[1], m, n, _ptr(x), n, _ptr(y), n, _ptr(alpha), B,
+                                           _ptr(ws), wsb, _stream(x.device)), "hankel_tvp_strided_batched")
+    return y, alpha
+
+
+def hankel_tvp_backward_strided_batched(h: torch.Tensor, x: torch.Tensor, m: int, grad_y: Optional[torch.Tensor],
+                                        grad_alpha: Optional[torch.Tensor], want_grad_x: bool = True,
+                                        want_grad_h: bool = True):
+    _dev(h), _dev(x)
+    B, n = x.shape
+    dt = _dtype(x)
+    gx = torch.empty(B, n, dtype=x.dtype, device=x.device) if want_grad_x else None
+    gh = torch.empty(B, h.shape[1], dtype=x.dtype, device=x.device) if want_grad_h else None
+    gy = None if grad_y is None else grad_y.contiguous()
+    ga = None if grad_alpha is None else grad_alpha.contiguous()
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_tvp_backward_strided_batched_workspace_size(dt, m, n, B, ctypes.byref(nb)),
+          "hankel_tvp_backward_strided_batched_workspace_size")
+    ws, wsb = _workspace(nb.value, x.device)
+    check(lib().hankel_tvp_backward_strided_batched(
+        dt, _ptr(h), h.shape[1], m, n, _ptr(x), n, _ptr(gy), n, _ptr(ga), _ptr(gx), n, _ptr(gh), h.shape[1], B,
+        _ptr(ws), wsb, _stream(x.device)), "hankel_tvp_backward_strided_batched")
+    return gx, gh
+
+
+def block_hankel_tvp_strided_batched(H: torch.Tensor, x: torch.Tensor, m: int, inner: int, blocks: int,
+                                     want_y: bool = True, want_alpha: bool = False):
+    """Batch of equal-vector BHHB products: H (B, rows*cols) column-major, x (B, inner*blocks)."""
+    _dev(H), _dev(x)
+    B = x.shape[0]
+    dt = _dtype(x)
+    ny = inner * blocks
+    y = torch.empty(B, ny, dtype=x.dtype, device=x.device) if want_y else None
+    alpha = torch.empty(B, dtype=x.dtype, device=x.device) if want_alpha else None
+    di, db = _i64arr([inner] * m), _i64arr([blocks] * m)
+    nb = ctypes.c_size_t(0)
+    check(lib().block_hankel_tvp_strided_batched_workspace_size(dt, m, di, db, B, ctypes.byref(nb)),
+          "block_hankel_tvp_strided_batched_workspace_size")
+    ws, wsb = _workspace(nb.value, x.device)
+    check(lib().block_hankel_tvp_strided_batched(dt, _ptr(H), H.shape[1], m, di, db, _ptr(x), x.shape[1], _ptr(y), ny,
+                                                 _ptr(alpha), B, _ptr(ws), wsb, _stream(x.device)),
+          "block_hankel_tvp_strided_batched")
+    return y, alpha
+
+
+class Plan:
+    """A batched plan over heterogeneous problems (hk_plan_*).
+
+    problems: sequence of dicts with keys m, dims, h, vectors, and optionally
+    block_dims (BHHB), want_y (default True), want_alpha (default False).
+    The plan allocates each problem's outputs; results are in .outputs."""
+
+    def __init__(self, problems, flags: int = _lib.HK_PLAN_PERSISTENT):
+        self.problems = list(problems)
+        self.outputs = []
+        arr = (_lib.hk_problem_t * max(1, len(self.problems)))()
+        dtype = None
+        self._keep = []
+        for i, p in enumerate(self.problems):
+            vecs = p["vectors"]
+            ref = next(v for v in vecs if v is not None)
+            dtype = ref.dtype if dtype is None else dtype
+            if ref.dtype != dtype:
+                raise TypeError("all problems of a plan share one dtype")
+            m = p["m"]
+            dims = p["dims"]
+            bd = p.get("block_dims")
+            want_y = p.get("want_y", True)
+            want_a = p.get("want_alpha", False)
+            ny = int(dims[0]) * (int(bd[0]) if bd is not None else 1)
+            y = torch.empty(ny, dtype=dtype, device=ref.device) if want_y else None
+            a = torch.empty(1, dtype=dtype, device=ref.device) if want_a else None
+            self.outputs.append((y, a))
+            self._keep.extend([y, a, p["h"]] + list(vecs))
+            q = arr[i]
+            q.m = m
+            q.is_block = 1 if bd is not None else 0
+            for k in range(m):
+                q.dims[k] = int(dims[k])
+                q.block_dims[k] = int(bd[k]) if bd is not None else 0
+                q.vectors[k] = None if vecs[k] is None else vecs[k].data_ptr()
+            q.h = p["h"].data_ptr()
+            q.y = None if y is None else y.data_ptr()
+            q.alpha = None if a is None else a.data_ptr()
+        self.device = ref.device if self.problems else torch.device("cuda")
+        self.dt = _DT[dtype] if dtype is not None else _lib.HK_C64
+        self._arr = arr
+        self._plan = ctypes.c_void_p()
+        check(lib().hk_plan_create(ctypes.byref(self._plan), self.dt, arr, len(self.problems), flags),
+              "hk_plan_create")
+        nb = ctypes.c_size_t(0)
+        check(lib().hk_plan_workspace_size(self._plan, ctypes.byref(nb)), "hk_plan_workspace_size")
+        self.ws, self.ws_bytes = _workspace(max(256, nb.value), self.device)
+
+    def execute(self):
+        check(lib().hk_plan_execute(self._plan, _ptr(self.ws), self.ws_bytes, _stream(self.device)), "hk_plan_execute")
+        return self.outputs
+
+    def status(self):
+        check(lib().hk_plan_status(self._plan), "hk_plan_status")
+
+    def close(self):
+        if self._plan:
+            lib().hk_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hankel_tvp_batched(problems):
+    """One-shot heterogeneous batch.  Returns a list of (y, alpha) per problem."""
+    plan = Plan(problems)
+    try:
+        out = plan.execute()
+        plan.status()
+    finally:
+        plan.close()
+    return out
+
+
+def hk_fft_layout(d_h: int):
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    check(lib().hk_fft_layout(d_h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "hk_fft_layout")
+    return a.value, b.value, c.value
+
+
+def hk_autotune_tvp(dtype: torch.dtype, m: int, n: int, verbose: bool = False):
+    check(lib().hk_autotune_tvp(_DT[dtype], m, n, int(verbose)), "hk_autotune_tvp")
+
+
+def hk_last_launch_count() -> int:
+    return int(lib().hk_last_launch_count())

@@ -1,0 +1,444 @@
+// C ABI of the fast Hankel tensor-vector product (see include/hankel.h).
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "hk_batch.hpp"
+#include "hk_plan.hpp"
+
+using namespace hk;
+
+namespace hk {
+int launches_and_reset();
+}
+
+static thread_local std::string tl_err;
+static thread_local int tl_last_launches = 0;
+
+static hk_status_t finish(const Status &s) {
+  tl_last_launches = launches_and_reset();
+  if (!s.ok()) tl_err = s.msg;
+  return s.code;
+}
+
+static Status check_ws(size_t need, const void *ws, size_t ws_bytes) {
+  if (need == 0) return Status();
+  if (!ws) return fail(HK_ERR_WORKSPACE, "workspace pointer is NULL but " + std::to_string(need) + " bytes are needed");
+  if (ws_bytes < need)
+    return fail(HK_ERR_WORKSPACE, "workspace of " + std::to_string(ws_bytes) + " bytes is smaller than the " +
+                                      std::to_string(need) + " bytes needed");
+  if (((uintptr_t)ws) % 256 != 0) return fail(HK_ERR_MISALIGNED, "workspace must be 256-byte aligned");
+  return Status();
+}
+
+// Picks the schedule (autotuned if cached, else the default) and builds the shape.
+static Status prepare(const Problem &p, int64_t batch, Shape *sh, Ptrs *P, Sched *sc) {
+  Layout lay;
+  Status s = layout_for(p, 0, &lay);
+  if (!s.ok()) return s;
+  Sched sch;
+  const int logN = lay.logR + lay.logC;
+  if (sched_lookup(p.dt, p.prog, p.is_block ? 1 : 0, logN, p.is_block ? lay.logC : -1, batch, &sch)) {
+    Layout l2;
+    if (layout_for(p, sch.split, &l2).ok() && sched_valid(p.dt, l2, sch))
+      lay = l2;
+    else
+      sch = default_sched(p.dt, lay, p.prog, batch);
+  } else {
+    sch = default_sched(p.dt, lay, p.prog, batch);
+  }
+  if (!sched_valid(p.dt, lay, sch)) return fail(HK_ERR_NOT_SUPPORTED, "no valid schedule for this shape");
+  s = build_shape(p, lay, sch, sh, P, nullptr);
+  if (!s.ok()) return s;
+  *sc = sch;
+  return Status();
+}
+
+static Status ws_size(const Problem &p, int64_t batch, size_t *bytes) {
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  Status s = prepare(p, batch, &sh, &P, &sc);
+  if (!s.ok()) return s;
+  *bytes = instance_ws_bytes(sh, p.dt) * (size_t)batch;
+  return Status();
+}
+
+static Status run_one(const Problem &p, void *ws, size_t ws_bytes, hipStream_t st) {
+  Status s = ensure_device();
+  if (!s.ok()) return s;
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  s = prepare(p, 1, &sh, &P, &sc);
+  if (!s.ok()) return s;
+  s = check_ws(instance_ws_bytes(sh, p.dt), ws, ws_bytes);
+  if (!s.ok()) return s;
+  P.ws = ws;
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  return launch_shape(p.dt, sh, sc, P, str, nullptr, 1, st);
+}
+
+static Problem tvp_problem(hk_dtype_t dt, const void *h, int m, int64_t n, const void *x, void *y, void *alpha) {
+  Problem p;
+  p.dt = dt;
+  p.prog = PROG_FWD;
+  p.m = m;
+  for (int q = 0; q < m && q < HK_MAX_ORDER; ++q) {
+    p.dims[q] = n;
+    p.vec[q] = x;
+  }
+  if (!alpha) p.vec[0] = x;  // unused for the vector product; keeps grouping uniform
+  p.h = h;
+  p.y = y;
+  p.alpha = alpha;
+  return p;
+}
+
+static Status mode_problem(hk_dtype_t dt, const void *h, int m, const int64_t *dims, const void *const *vectors,
+                           void *y, void *alpha, Problem *out) {
+  if (!dims) return fail(HK_ERR_NULL_POINTER, "dims is NULL");
+  if (!vectors) return fail(HK_ERR_NULL_POINTER, "vectors is NULL");
+  if (m < 2 || m > HK_MAX_ORDER) return fail(HK_ERR_INVALID_VALUE, "order m must be in [2, 8]");
+  Problem p;
+  p.dt = dt;
+  p.prog = PROG_FWD;
+  p.m = m;
+  for (int q = 0; q < m; ++q) {
+    p.dims[q] = dims[q];
+    p.vec[q] = vectors[q];
+  }
+  if (!alpha) p.vec[0] = nullptr;
+  p.h = h;
+  p.y = y;
+  p.alpha = alpha;
+  *out = p;
+  return Status();
+}
+
+static Status block_problem(hk_dtype_t dt, const void *H, int m, const int64_t *inner, const int64_t *blocks,
+                            const void *const *vectors, void *y, void *alpha, Problem *out) {
+  if (!inner || !blocks) return fail(HK_ERR_NULL_POINTER, "inner_dims or block_dims is NULL");
+  Status s = mode_problem(dt, H, m, inner, vectors, y, alpha, out);
+  if (!s.ok()) return s;
+  out->is_block = true;
+  for (int q = 0; q < m; ++q) out->bdims[q] = blocks[q];
+  return Status();
+}
+
+static Problem bwd_problem(hk_dtype_t dt, const void *h, int m, int64_t n, const void *x, const void *gy,
+                           const void *ga, void *gx, void *gh) {
+  Problem p;
+  p.dt = dt;
+  p.prog = PROG_BWD;
+  p.m = m;
+  for (int q = 0; q < m && q < HK_MAX_ORDER; ++q) p.dims[q] = n;
+  p.h = h;
+  p.vec[1] = x;
+  p.v = gy;
+  p.phi = ga;
+  p.gx = gx;
+  p.gh = gh;
+  return p;
+}
+
+extern "C" {
+
+int hk_version(void) { return 10000; }
+
+const char *hk_status_string(hk_status_t s) {
+  switch (s) {
+    case HK_SUCCESS: return "success";
+    case HK_ERR_INVALID_VALUE: return "invalid value";
+    case HK_ERR_NULL_POINTER: return "null pointer";
+    case HK_ERR_MISALIGNED: return "misaligned pointer";
+    case HK_ERR_WORKSPACE: return "workspace too small";
+    case HK_ERR_SIZE_LIMIT: return "size limit exceeded";
+    case HK_ERR_DEVICE: return "unsupported device";
+    case HK_ERR_HIP: return "HIP runtime error";
+    case HK_ERR_DEVICE_FAULT: return "device-side error reported";
+    case HK_ERR_NOT_SUPPORTED: return "not supported";
+  }
+  return "unknown status";
+}
+
+const char *hk_last_error(void) { return tl_err.c_str(); }
+
+int hk_last_launch_count(void) { return tl_last_launches; }
+
+hk_status_t hk_fft_layout(int64_t d_h, int64_t *n_fft, int64_t *n_row, int64_t *n_col) {
+  if (!n_fft || !n_row || !n_col) return finish(fail(HK_ERR_NULL_POINTER, "output pointer is NULL"));
+  if (d_h < 1) return finish(fail(HK_ERR_INVALID_VALUE, "d_h must be >= 1"));
+  Problem p;
+  p.m = 2;
+  p.dims[0] = d_h;
+  p.dims[1] = 1;
+  Layout lay;
+  Status s = layout_for(p, 0, &lay);
+  if (!s.ok()) return finish(s);
+  *n_fft = (int64_t)1 << (lay.logR + lay.logC);
+  *n_row = (int64_t)1 << lay.logR;
+  *n_col = (int64_t)1 << lay.logC;
+  return finish(Status());
+}
+
+// ---------------------------------------------------------------------------
+hk_status_t hankel_tvp_workspace_size(hk_dtype_t dt, int m, int64_t n, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  Problem p = tvp_problem(dt, (const void *)16, m, n, (const void *)16, (void *)16, nullptr);
+  Status s = validate_forward(p);
+  if (!s.ok()) return finish(s);
+  return finish(ws_size(p, 1, bytes));
+}
+
+hk_status_t hankel_tvp(hk_dtype_t dt, const void *h, int m, int64_t n, const void *x, void *y, void *alpha, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+  Problem p = tvp_problem(dt, h, m, n, x, y, alpha);
+  Status s = validate_forward(p);
+  if (!s.ok()) return finish(s);
+  return finish(run_one(p, ws, ws_bytes, stream));
+}
+
+hk_status_t hankel_mode_products_workspace_size(hk_dtype_t dt, int m, const int64_t *dims, const void *const *vectors,
+                                                int want_y, int want_alpha, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  Problem p;
+  Status s = mode_problem(dt, (const void *)16, m, dims, vectors, want_y ? (void *)16 : nullptr,
+                          want_alpha ? (void *)16 : nullptr, &p);
+  if (!s.ok()) return finish(s);
+  s = validate_forward(p);
+  if (!s.ok()) return finish(s);
+  return finish(ws_size(p, 1, bytes));
+}
+
+hk_status_t hankel_mode_products(hk_dtype_t dt, const void *h, int m, const int64_t *dims, const void *const *vectors,
+                                 void *y, void *alpha, void *ws, size_t ws_bytes, hipStream_t stream) {
+  Problem p;
+  Status s = mode_problem(dt, h, m, dims, vectors, y, alpha, &p);
+  if (!s.ok()) return finish(s);
+  s = validate_forward(p);
+  if (!s.ok()) return finish(s);
+  return finish(run_one(p, ws, ws_bytes, stream));
+}
+
+hk_status_t block_hankel_tvp_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims, const int64_t *block_dims,
+                                            const void *const *vectors, int want_y, int want_alpha, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  Problem p;
+  Status s = block_problem(dt, (const void *)16, m, inner_dims, block_dims, vectors, want_y ? (void *)16 : nullptr,
+                           want_alpha ? (void *)16 : nullptr, &p);
+  if (!s.ok()) return finish(s);
+  s = validate_forward(p);
+  if (!s.ok()) return finish(s);
+  return finish(ws_size(p, 1, bytes));
+}
+
+hk_status_t block_hankel_tvp(hk_dtype_t dt, const void *H, int m, const int64_t *inner_dims, const int64_t *block_dims,
+                             const void *const *vectors, void *y, void *alpha, void *ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  Problem p;
+  Status s = block_problem(dt, H, m, inner_dims, block_dims, vectors, y, alpha, &p);
+  if (!s.ok()) return finish(s);
+  s = validate_forward(p);
+  if (!s.ok()) return finish(s);
+  return finish(run_one(p, ws, ws_bytes, stream));
+}
+
+hk_status_t hankel_tvp_backward_workspace_size(hk_dtype_t dt, int m, int64_t n, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  // The size with every optional operand present is an upper bound.
+  Problem p = bwd_problem(dt, (const void *)16, m, n, (const void *)16, (const void *)16, (const void *)16,
+                          (void *)16, (void *)16);
+  Status s = validate_backward(p);
+  if (!s.ok()) return finish(s);
+  return finish(ws_size(p, 1, bytes));
+}
+
+hk_status_t hankel_tvp_backward(hk_dtype_t dt, const void *h, int m, int64_t n, const void *x, const void *grad_y,
+                                const void *grad_alpha, void *grad_x, void *grad_h, void *ws, size_t ws_bytes,
+                                hipStream_t stream) {
+  Problem p = bwd_problem(dt, h, m, n, x, grad_y, grad_alpha, grad_x, grad_h);
+  Status s = validate_backward(p);
+  if (!s.ok()) return finish(s);
+  return finish(run_one(p, ws, ws_bytes, stream));
+}
+
+// ---------------------------------------------------------------------------
+// Strided batches of one shape.
+// ---------------------------------------------------------------------------
+static Status run_strided(const Problem &p, const Strides &str_elems, int64_t batch, void *ws, size_t ws_bytes,
+                          hipStream_t st) {
+  if (batch < 0) return fail(HK_ERR_INVALID_VALUE, "batch must be >= 0");
+  if (batch == 0) return Status();
+  Status s = ensure_device();
+  if (!s.ok()) return s;
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  s = prepare(p, batch, &sh, &P, &sc);
+  if (!s.ok()) return s;
+  const size_t per = instance_ws_bytes(sh, p.dt);
+  s = check_ws(per * (size_t)batch, ws, ws_bytes);
+  if (!s.ok()) return s;
+  P.ws = ws;
+  // Map the caller's element strides onto the shape's operand slots.
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  for (int o = 0; o < sh.nops; ++o) str.op[o] = str_elems.op[o];
+  str.y = str_elems.y;
+  str.alpha = str_elems.alpha;
+  str.out1 = str_elems.out1;
+  str.phi = str_elems.phi;
+  str.ws = (int64_t)per;
+  return launch_shape(p.dt, sh, sc, P, str, nullptr, batch, st);
+}
+
+hk_status_t hankel_tvp_strided_batched_workspace_size(hk_dtype_t dt, int m, int64_t n, int64_t batch, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  if (batch < 0) return finish(fail(HK_ERR_INVALID_VALUE, "batch must be >= 0"));
+  Problem p = tvp_problem(dt, (const void *)16, m, n, (const void *)16, (void *)16, nullptr);
+  Status s = validate_forward(p);
+  if (!s.ok()) return finish(s);
+  return finish(ws_size(p, batch, bytes));
+}
+
+hk_status_t hankel_tvp_strided_batched(hk_dtype_t dt, const void *h, int64_t h_stride, int m, int64_t n, const void *x,
+                                       int64_t x_stride, void *y, int64_t y_stride, void *alpha, int64_t batch,
+                                       void *ws, size_t ws_bytes, hipStream_t stream) {
+  Problem p = tvp_problem(dt, h, m, n, x, y, alpha);
+  Status s = validate_forward(p);
+  if (!s.ok()) return finish(s);
+  const int64_t eb = (int64_t)elem_bytes(dt);
+  // Operand order of the equal-vector shape: H, X.
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  str.op[0] = h_stride * eb;
+  str.op[1] = x_stride * eb;
+  str.y = y_stride * eb;
+  str.alpha = eb;
+  return finish(run_strided(p, str, batch, ws, ws_bytes, stream));
+}
+
+hk_status_t hankel_tvp_backward_strided_batched_workspace_size(hk_dtype_t dt, int m, int64_t n, int64_t batch,
+                                                               size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  if (batch < 0) return finish(fail(HK_ERR_INVALID_VALUE, "batch must be >= 0"));
+  Problem p = bwd_problem(dt, (const void *)16, m, n, (const void *)16, (const void *)16, (const void *)16,
+                          (void *)16, (void *)16);
+  Status s = validate_backward(p);
+  if (!s.ok()) return finish(s);
+  return finish(ws_size(p, batch, bytes));
+}
+
+hk_status_t hankel_tvp_backward_strided_batched(hk_dtype_t dt, const void *h, int64_t h_stride, int m, int64_t n,
+                                                const void *x, int64_t x_stride, const void *grad_y,
+                                                int64_t gy_stride, const void *grad_alpha, void *grad_x,
+                                                int64_t gx_stride, void *grad_h, int64_t gh_stride, int64_t batch,
+                                                void *ws, size_t ws_bytes, hipStream_t stream) {
+  Problem p = bwd_problem(dt, h, m, n, x, grad_y, grad_alpha, grad_x, grad_h);
+  Status s = validate_backward(p);
+  if (!s.ok()) return finish(s);
+  const int64_t eb = (int64_t)elem_bytes(dt);
+  // Operand order of the adjoint shape: X, [V], [H].
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  int o = 0;
+  str.op[o++] = x_stride * eb;
+  if (grad_y) str.op[o++] = gy_stride * eb;
+  if (grad_x) str.op[o++] = h_stride * eb;
+  str.y = gh_stride * eb;
+  str.out1 = gx_stride * eb;
+  str.phi = eb;
+  return finish(run_strided(p, str, batch, ws, ws_bytes, stream));
+}
+
+hk_status_t block_hankel_tvp_strided_batched_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims,
+                                                            const int64_t *block_dims, int64_t batch, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  if (batch < 0) return finish(fail(HK_ERR_INVALID_VALUE, "batch must be >= 0"));
+  const void *vecs[HK_MAX_ORDER];
+  for (int q = 0; q < HK_MAX_ORDER; ++q) vecs[q] = (const void *)16;
+  Problem p;
+  Status s = block_problem(dt, (const void *)16, m, inner_dims, block_dims, vecs, (void *)16, nullptr, &p);
+  if (!s.ok()) return finish(s);
+  s = validate_forward(p);
+  if (!s.ok()) return finish(s);
+  return finish(ws_size(p, batch, bytes));
+}
+
+hk_status_t block_hankel_tvp_strided_batched(hk_dtype_t dt, const void *H, int64_t H_stride, int m,
+                                             const int64_t *inner_dims, const int64_t *block_dims, const void *x,
+                                             int64_t x_stride, void *y, int64_t y_stride, void *alpha, int64_t batch,
+                                             void *ws, size_t ws_bytes, hipStream_t stream) {
+  const void *vecs[HK_MAX_ORDER];
+  for (int q = 0; q < HK_MAX_ORDER; ++q) vecs[q] = x;
+  Problem p;
+  Status s = block_problem(dt, H, m, inner_dims, block_dims, vecs, y, alpha, &p);
+  if (!s.ok()) return finish(s);
+  if (!alpha) p.vec[0] = x;
+  s = validate_forward(p);
+  if (!s.ok()) return finish(s);
+  if (inner_dims && block_dims)
+    for (int q = 1; q < m; ++q)
+      if (inner_dims[q] != inner_dims[0] || block_dims[q] != block_dims[0])
+        return finish(fail(HK_ERR_INVALID_VALUE, "the strided block batch shares one vector: all modes need equal sizes"));
+  const int64_t eb = (int64_t)elem_bytes(dt);
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  str.op[0] = H_stride * eb;
+  str.op[1] = x_stride * eb;
+  str.y = y_stride * eb;
+  str.alpha = eb;
+  return finish(run_strided(p, str, batch, ws, ws_bytes, stream));
+}
+
+// ---------------------------------------------------------------------------
+// Heterogeneous batches and plans.
+// ---------------------------------------------------------------------------
+hk_status_t hk_plan_create(hk_plan_t *plan, hk_dtype_t dt, const hk_problem_t *probs, int64_t count, unsigned flags) {
+  Status s = plan_create(plan, dt, probs, count, flags);
+  return finish(s);
+}
+
+hk_status_t hk_plan_workspace_size(hk_plan_t plan, size_t *bytes) { return finish(plan_ws_size(plan, bytes)); }
+
+hk_status_t hk_plan_execute(hk_plan_t plan, void *ws, size_t ws_bytes, hipStream_t stream) {
+  return finish(plan_execute(plan, ws, ws_bytes, stream));
+}
+
+hk_status_t hk_plan_status(hk_plan_t plan) { return finish(plan_status(plan)); }
+
+hk_status_t hk_plan_destroy(hk_plan_t plan) { return finish(plan_destroy(plan)); }
+
+hk_status_t hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs, int64_t count, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  hk_plan_t plan = nullptr;
+  Status s = plan_create(&plan, dt, probs, count, HK_PLAN_PERSISTENT);
+  if (!s.ok()) return finish(s);
+  s = plan_ws_size(plan, bytes);
+  plan_destroy(plan);
+  return finish(s);
+}
+
+hk_status_t hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t count, void *ws, size_t ws_bytes,
+                               hipStream_t stream) {
+  hk_plan_t plan = nullptr;
+  Status s = plan_create(&plan, dt, probs, count, HK_PLAN_PERSISTENT);
+  if (!s.ok()) return finish(s);
+  plan_set_oneshot(plan);
+  s = plan_execute(plan, ws, ws_bytes, stream);
+  if (s.ok())
+    s = plan_release_after(plan, stream);
+  else
+    plan_destroy(plan);
+  return finish(s);
+}
+
+hk_status_t hk_autotune_tvp(hk_dtype_t dt, int m, int64_t n, int verbose) {
+  return finish(autotune_tvp(dt, m, n, verbose != 0));
+}
+
+}  // extern "C"

@@ -1,0 +1,502 @@
+// Heterogeneous batched execution (task list + persistent kernel), plans,
+// hipGraph capture and the in-house schedule autotuner.
+#include "hk_batch.hpp"
+
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <string>
+#include <vector>
+
+namespace hk {
+
+static bool dbl(hk_dtype_t dt) { return dt == HK_C128 || dt == HK_F64; }
+
+static Status hip_fail(hipError_t e, const char *what) {
+  return fail(HK_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace hk
+
+struct hk_plan_s {
+  hk_dtype_t dt = HK_C64;
+  unsigned flags = 0;
+  int64_t count = 0;
+  std::vector<hk::Shape> shapes;
+  std::vector<hk::Ptrs> ptrs;  // ws holds the offset of the instance region
+  std::vector<hk::Task> tasks;
+  std::vector<int32_t> res_list;
+  int32_t phase_end[3] = {0, 0, 0};  // [0, e0): pass A + resident, [e0, e1): pass B, [e1, e2): pass D
+  size_t ctl_bytes = 0;              // BatchCtl + InstCtl[count]
+  size_t tables_bytes = 0;           // descriptor tables (when stored in the workspace)
+  size_t inst_bytes = 0;             // instance regions
+  bool tables_in_ws = false;
+  // device copies of the tables (plan-owned) or offsets inside the workspace
+  char *d_tables = nullptr;
+  size_t off_shapes = 0, off_ptrs = 0, off_tasks = 0, off_res = 0;
+  std::vector<char> host_tables;
+  int grid = 1;
+  bool persistent = true;
+  // graph
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  void *graph_ws = nullptr;
+  hipStream_t graph_stream = nullptr;
+  // status
+  hipStream_t last_stream = nullptr;
+  void *last_ws = nullptr;
+};
+
+namespace hk {
+
+static void tables_layout(hk_plan_s *p) {
+  size_t off = 0;
+  p->off_shapes = off;
+  off = align256(off + sizeof(Shape) * p->shapes.size());
+  p->off_ptrs = off;
+  off = align256(off + sizeof(Ptrs) * p->ptrs.size());
+  p->off_tasks = off;
+  off = align256(off + sizeof(Task) * std::max<size_t>(1, p->tasks.size()));
+  p->off_res = off;
+  off = align256(off + sizeof(int32_t) * std::max<size_t>(1, p->res_list.size()));
+  p->tables_bytes = off;
+  p->host_tables.assign(off, 0);
+  memcpy(p->host_tables.data() + p->off_shapes, p->shapes.data(), sizeof(Shape) * p->shapes.size());
+  memcpy(p->host_tables.data() + p->off_ptrs, p->ptrs.data(), sizeof(Ptrs) * p->ptrs.size());
+  if (!p->tasks.empty()) memcpy(p->host_tables.data() + p->off_tasks, p->tasks.data(), sizeof(Task) * p->tasks.size());
+  if (!p->res_list.empty())
+    memcpy(p->host_tables.data() + p->off_res, p->res_list.data(), sizeof(int32_t) * p->res_list.size());
+}
+
+static Problem problem_of(hk_dtype_t dt, const hk_problem_t &q) {
+  Problem p;
+  p.dt = dt;
+  p.prog = PROG_FWD;
+  p.is_block = q.is_block != 0;
+  p.m = q.m;
+  for (int i = 0; i < HK_MAX_ORDER && i < q.m; ++i) {
+    p.dims[i] = q.dims[i];
+    p.bdims[i] = q.block_dims[i];
+    p.vec[i] = q.vectors[i];
+  }
+  if (!q.alpha) p.vec[0] = nullptr;
+  p.h = q.h;
+  p.y = q.y;
+  p.alpha = q.alpha;
+  return p;
+}
+
+Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int64_t count, unsigned flags) {
+  if (!out) return fail(HK_ERR_NULL_POINTER, "plan pointer is NULL");
+  *out = nullptr;
+  if (count < 0) return fail(HK_ERR_INVALID_VALUE, "count must be >= 0");
+  if (count > 0 && !probs) return fail(HK_ERR_NULL_POINTER, "problems is NULL");
+  if (count > (1 << 24)) return fail(HK_ERR_SIZE_LIMIT, "too many problems in one plan");
+  if (flags & ~(unsigned)(HK_PLAN_PERSISTENT | HK_PLAN_MULTIKERNEL | HK_PLAN_GRAPH | HK_PLAN_AUTOTUNE))
+    return fail(HK_ERR_INVALID_VALUE, "unknown plan flags");
+  if ((flags & HK_PLAN_PERSISTENT) && (flags & HK_PLAN_MULTIKERNEL))
+    return fail(HK_ERR_INVALID_VALUE, "PERSISTENT and MULTIKERNEL are exclusive");
+  if (dt < HK_C64 || dt > HK_F64) return fail(HK_ERR_INVALID_VALUE, "unknown dtype");
+  hk_plan_s *p = new hk_plan_s();
+  p->dt = dt;
+  p->flags = flags;
+  p->count = count;
+  p->persistent = !(flags & HK_PLAN_MULTIKERNEL);
+  int blk, er, ec;
+  size_t lds;
+  if (dbl(dt))
+    batch_geometry_f64(&blk, &er, &ec, &lds);
+  else
+    batch_geometry_f32(&blk, &er, &ec, &lds);
+  auto tps = [&](int logL, int E) {
+    KernelLimits k;
+    if (dbl(dt))
+      limits_f64(logL, E, &k);
+    else
+      limits_f32(logL, E, &k);
+    return k.tps;
+  };
+  p->shapes.resize(count);
+  p->ptrs.resize(count);
+  p->ctl_bytes = align256(sizeof(BatchCtl)) + align256(sizeof(InstCtl) * (size_t)std::max<int64_t>(count, 1));
+  size_t inst_off = 0;
+  struct Inst {
+    int64_t idx;
+    double cost;
+  };
+  std::vector<Inst> multi;
+  std::map<std::tuple<int, int, int, int, int>, std::vector<int32_t>> groups;
+  for (int64_t i = 0; i < count; ++i) {
+    Problem pr = problem_of(dt, probs[i]);
+    Status s = validate_forward(pr);
+    if (!s.ok()) {
+      delete p;
+      return fail(s.code, "problem " + std::to_string(i) + ": " + s.msg);
+    }
+    Layout lay;
+    layout_for(pr, 0, &lay);
+    Sched sc;
+    if (!lay.resident) sc.rows_per_wg = std::max(1, blk / tps(lay.logR, er));
+    Shape sh;
+    Ptrs P;
+    build_shape(pr, lay, sc, &sh, &P, nullptr);
+    if (!lay.resident) {
+      P.ws = (void *)(uintptr_t)inst_off;
+      inst_off += align256((size_t)sh.ws_bytes);
+      multi.push_back({i, (double)((int64_t)1 << (sh.logR + sh.logC)) * (sh.nops + 1)});
+    } else {
+      P.ws = nullptr;
+      groups[std::make_tuple(sh.logR, sh.nops, sh.want_y, sh.want_alpha, sh.real_out)].push_back((int32_t)i);
+    }
+    p->shapes[i] = sh;
+    p->ptrs[i] = P;
+  }
+  p->inst_bytes = inst_off;
+  std::sort(multi.begin(), multi.end(), [](const Inst &a, const Inst &b) { return a.cost > b.cost; });
+  // Phase 1a: pass A of the multipass instances (largest first).
+  std::vector<int32_t> ncola(count, 0), nrowb(count, 0);
+  for (const Inst &in : multi) {
+    const Shape &sh = p->shapes[in.idx];
+    const int tw = std::max(1, blk / tps(sh.logC, ec));
+    for (int o = 0; o < sh.nops; ++o)
+      for (int64_t c0 = 0; c0 < sh.ops[o].ncol_nz; c0 += tw) {
+        Task t = {TASK_COLA, (int32_t)in.idx, o, (int32_t)c0, 0, -1, 0, 0};
+        p->tasks.push_back(t);
+        ncola[in.idx]++;
+      }
+  }
+  // Phase 1b: resident instances, grouped so that a workgroup's rows share
+  // their control flow; groups of long transforms first.
+  std::vector<std::pair<int, std::vector<int32_t> *>> gl;
+  for (auto &kv : groups) gl.push_back({std::get<0>(kv.first) * 16 + std::get<1>(kv.first), &kv.second});
+  std::sort(gl.begin(), gl.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+  for (auto &g : gl) {
+    const Shape &sh0 = p->shapes[(*g.second)[0]];
+    const int rows = std::max(1, blk / tps(sh0.logR, er));
+    for (size_t k = 0; k < g.second->size(); k += rows) {
+      const int n = (int)std::min<size_t>(rows, g.second->size() - k);
+      Task t = {TASK_RES, (int32_t)p->res_list.size(), n, 0, 0, -1, -1, 0};
+      for (int j = 0; j < n; ++j) p->res_list.push_back((*g.second)[k + j]);
+      p->tasks.push_back(t);
+    }
+  }
+  p->phase_end[0] = (int32_t)p->tasks.size();
+  // Phase 2: pass B.
+  for (const Inst &in : multi) {
+    const Shape &sh = p->shapes[in.idx];
+    const int rows = std::max(1, blk / tps(sh.logR, er));
+    const int64_t C = (int64_t)1 << sh.logC;
+    const int32_t nb = (int32_t)((C + rows - 1) / rows);
+    for (int32_t b = 0; b < nb; ++b) {
+      Task t = {TASK_ROWB, (int32_t)in.idx, (int32_t)(b * rows), b, ncola[in.idx], 0, 1, nb};
+      p->tasks.push_back(t);
+    }
+    nrowb[in.idx] = nb;
+  }
+  p->phase_end[1] = (int32_t)p->tasks.size();
+  // Phase 3: pass D.
+  for (const Inst &in : multi) {
+    const Shape &sh = p->shapes[in.idx];
+    if (!sh.want_y) continue;
+    const int tw = std::max(1, blk / tps(sh.logC, ec));
+    const int64_t ncols = std::min<int64_t>((int64_t)1 << sh.logR, sh.out_rows);
+    for (int64_t c0 = 0; c0 < ncols; c0 += tw) {
+      Task t = {TASK_COLD, (int32_t)in.idx, 0, (int32_t)c0, nrowb[in.idx], 1, -1, 0};
+      p->tasks.push_back(t);
+    }
+  }
+  p->phase_end[2] = (int32_t)p->tasks.size();
+  tables_layout(p);
+  int dev = 0, ncu = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    ncu = prop.multiProcessorCount;
+  const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
+  p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::min(per_cu, 2), p->tasks.size()));
+  *out = p;
+  return Status();
+}
+
+Status plan_ws_size(hk_plan_t p, size_t *bytes) {
+  if (!p) return fail(HK_ERR_NULL_POINTER, "plan is NULL");
+  if (!bytes) return fail(HK_ERR_NULL_POINTER, "bytes is NULL");
+  // Room for the descriptor tables is always reserved so that one-shot
+  // execution can keep them in the workspace.
+  *bytes = p->ctl_bytes + p->tables_bytes + p->inst_bytes;
+  return Status();
+}
+
+static Status upload_tables(hk_plan_s *p) {
+  if (p->d_tables) return Status();
+  hipError_t e = hipMalloc((void **)&p->d_tables, p->tables_bytes);
+  if (e != hipSuccess) return hip_fail(e, "plan table allocation");
+  e = hipMemcpy(p->d_tables, p->host_tables.data(), p->tables_bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "plan table upload");
+  return Status();
+}
+
+static Status enqueue(hk_plan_s *p, char *ws, hipStream_t st) {
+  char *tables = p->tables_in_ws ? ws + p->ctl_bytes : p->d_tables;
+  BatchArgs A;
+  memset(&A, 0, sizeof(A));
+  A.tasks = (const Task *)(tables + p->off_tasks);
+  A.shapes = (const Shape *)(tables + p->off_shapes);
+  A.ptrs = (const Ptrs *)(tables + p->off_ptrs);
+  A.res_list = (const int32_t *)(tables + p->off_res);
+  A.bctl = (BatchCtl *)ws;
+  A.ictl = (InstCtl *)(ws + align256(sizeof(BatchCtl)));
+  A.ws_base = ws + p->ctl_bytes + p->tables_bytes;
+  A.spin_limit = 1u << 22;
+  auto launch = [&](const BatchArgs &a, int grid, bool reset) {
+    count_launch();
+    return dbl(p->dt) ? launch_batch_f64(a, grid, p->count, reset, st) : launch_batch_f32(a, grid, p->count, reset, st);
+  };
+  if (p->tasks.empty()) return Status();
+  hipError_t e;
+  if (p->persistent) {
+    A.begin = 0;
+    A.end = p->phase_end[2];
+    A.use_queue = 1;
+    e = launch(A, p->grid, true);
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
+  } else {
+    int32_t b = 0;
+    bool first = true;
+    for (int ph = 0; ph < 3; ++ph) {
+      const int32_t en = p->phase_end[ph];
+      if (en > b) {
+        A.begin = b;
+        A.end = en;
+        A.use_queue = 0;
+        e = launch(A, en - b, first);
+        if (e != hipSuccess) return hip_fail(e, "batched phase launch");
+        first = false;
+      }
+      b = en;
+    }
+  }
+  return Status();
+}
+
+Status plan_execute(hk_plan_t p, void *ws, size_t ws_bytes, hipStream_t st) {
+  if (!p) return fail(HK_ERR_NULL_POINTER, "plan is NULL");
+  Status s = ensure_device();
+  if (!s.ok()) return s;
+  size_t need = 0;
+  plan_ws_size(p, &need);
+  if (!ws) return fail(HK_ERR_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < need) return fail(HK_ERR_WORKSPACE, "workspace smaller than hk_plan_workspace_size");
+  if ((uintptr_t)ws % 256) return fail(HK_ERR_MISALIGNED, "workspace must be 256-byte aligned");
+  p->last_stream = st;
+  p->last_ws = ws;
+  if (p->tables_in_ws) {
+    hipError_t e = hipMemcpyAsync((char *)ws + p->ctl_bytes, p->host_tables.data(), p->tables_bytes,
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+  } else {
+    s = upload_tables(p);
+    if (!s.ok()) return s;
+  }
+  if ((p->flags & HK_PLAN_GRAPH) && !p->tables_in_ws) {
+    if (!st) return fail(HK_ERR_INVALID_VALUE, "graph plans need a non-default stream");
+    if (p->gexec && p->graph_ws == ws) {
+      count_launch();
+      hipError_t e = hipGraphLaunch(p->gexec, st);
+      if (e != hipSuccess) return hip_fail(e, "graph launch");
+      return Status();
+    }
+    if (p->gexec) {
+      (void)hipGraphExecDestroy(p->gexec);
+      (void)hipGraphDestroy(p->graph);
+      p->gexec = nullptr;
+      p->graph = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "stream capture begin");
+    s = enqueue(p, (char *)ws, st);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (!s.ok()) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "stream capture end");
+    e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(e, "graph instantiate");
+    }
+    p->graph = g;
+    p->graph_ws = ws;
+    p->graph_stream = st;
+    count_launch();
+    e = hipGraphLaunch(p->gexec, st);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return Status();
+  }
+  return enqueue(p, (char *)ws, st);
+}
+
+Status plan_status(hk_plan_t p) {
+  if (!p) return fail(HK_ERR_NULL_POINTER, "plan is NULL");
+  if (!p->last_ws) return Status();
+  hipError_t e = hipStreamSynchronize(p->last_stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  BatchCtl c;
+  e = hipMemcpy(&c, p->last_ws, sizeof(c), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "status readback");
+  if (c.error) return fail(HK_ERR_DEVICE_FAULT, "a dependency wait of the persistent kernel exceeded its bound");
+  return Status();
+}
+
+Status plan_destroy(hk_plan_t p) {
+  if (!p) return Status();
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->d_tables) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p->d_tables);
+  }
+  delete p;
+  return Status();
+}
+
+Status plan_set_oneshot(hk_plan_t p) {
+  if (!p) return fail(HK_ERR_NULL_POINTER, "plan is NULL");
+  p->tables_in_ws = true;
+  return Status();
+}
+
+Status plan_release_after(hk_plan_t p, hipStream_t st) {
+  // The descriptor tables were copied into the caller's workspace from the
+  // plan's host buffer; wait for the stream before that buffer goes away.
+  hipError_t e = hipStreamSynchronize(st);
+  delete p;
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  return Status();
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner for the plain 1D path: times every valid schedule variant on
+// scratch buffers and keeps the fastest.
+// ---------------------------------------------------------------------------
+Status autotune_tvp(hk_dtype_t dt, int m, int64_t n, bool verbose) {
+  Status s = ensure_device();
+  if (!s.ok()) return s;
+  Problem p;
+  p.dt = dt;
+  p.prog = PROG_FWD;
+  p.m = m;
+  for (int q = 0; q < m && q < HK_MAX_ORDER; ++q) p.dims[q] = n;
+  int64_t dh = m * (n - 1) + 1;
+  const size_t eb = elem_bytes(dt);
+  void *dh_buf = nullptr, *dx = nullptr, *dy = nullptr, *da = nullptr, *dws = nullptr;
+  Layout lay0;
+  p.h = (void *)16;
+  p.vec[1] = (void *)16;
+  p.y = (void *)16;
+  s = validate_forward(p);
+  if (!s.ok()) return s;
+  layout_for(p, 0, &lay0);
+  std::vector<Sched> cands;
+  std::vector<Layout> lays;
+  const int splits[] = {0, -1, 1, -2, 2};
+  for (int sp : splits) {
+    Layout lay;
+    if (!layout_for(p, sp, &lay).ok()) continue;
+    if (sp != 0 && (lay.resident || (lay.logR == lay0.logR && lay.logC == lay0.logC))) continue;
+    for (int er : {8, 16})
+      for (int rows : {1, 2, 4, 8, 16, 32})
+        for (int ec : {8, 16})
+          for (int tw : {1, 2, 4, 8, 16, 32}) {
+            if (lay.resident && (ec != 8 || tw != 1)) continue;
+            Sched sc;
+            sc.E_row = er;
+            sc.rows_per_wg = rows;
+            sc.E_col = ec;
+            sc.tw = tw;
+            sc.split = sp;
+            if (!sched_valid(dt, lay, sc)) continue;
+            if (lay.resident && rows > 1) continue;
+            cands.push_back(sc);
+            lays.push_back(lay);
+          }
+  }
+  if (cands.empty()) return fail(HK_ERR_NOT_SUPPORTED, "no schedule candidates");
+  size_t wsb = 0;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    Shape sh;
+    Ptrs P;
+    build_shape(p, lays[i], cands[i], &sh, &P, nullptr);
+    wsb = std::max(wsb, instance_ws_bytes(sh, dt));
+  }
+  hipError_t e = hipMalloc(&dh_buf, dh * eb);
+  if (e == hipSuccess) e = hipMalloc(&dx, n * eb);
+  if (e == hipSuccess) e = hipMalloc(&dy, n * eb);
+  if (e == hipSuccess) e = hipMalloc(&da, 2 * eb);
+  if (e == hipSuccess && wsb) e = hipMalloc(&dws, wsb);
+  if (e == hipSuccess) e = hipMemset(dh_buf, 0, dh * eb);
+  if (e == hipSuccess) e = hipMemset(dx, 0, n * eb);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  double best = 1e30;
+  int besti = -1;
+  if (e == hipSuccess) {
+    p.h = dh_buf;
+    for (int q = 0; q < m; ++q) p.vec[q] = dx;
+    p.y = dy;
+    p.alpha = da;
+    for (size_t i = 0; i < cands.size() && s.ok(); ++i) {
+      Shape sh;
+      Ptrs P;
+      build_shape(p, lays[i], cands[i], &sh, &P, nullptr);
+      P.ws = dws;
+      Strides str;
+      memset(&str, 0, sizeof(str));
+      const int reps = 5;
+      s = launch_shape(dt, sh, cands[i], P, str, nullptr, 1, nullptr);  // warm-up
+      if (!s.ok()) break;
+      (void)hipEventRecord(e0, nullptr);
+      for (int r = 0; r < reps && s.ok(); ++r) s = launch_shape(dt, sh, cands[i], P, str, nullptr, 1, nullptr);
+      (void)hipEventRecord(e1, nullptr);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double t = ms / reps;
+      if (verbose)
+        fprintf(stderr, "[hk autotune] split=%d E_row=%d rows=%d E_col=%d tw=%d : %.4f ms\n", cands[i].split,
+                cands[i].E_row, cands[i].rows_per_wg, cands[i].E_col, cands[i].tw, t);
+      if (t < best) {
+        best = t;
+        besti = (int)i;
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(dh_buf);
+  (void)hipFree(dx);
+  (void)hipFree(dy);
+  (void)hipFree(da);
+  if (dws) (void)hipFree(dws);
+  if (e != hipSuccess) return hip_fail(e, "autotune buffers");
+  if (!s.ok()) return s;
+  if (besti < 0) return fail(HK_ERR_NOT_SUPPORTED, "autotune found no schedule");
+  const Layout &bl = lays[besti];
+  sched_store(dt, PROG_FWD, 0, lay0.logR + lay0.logC, -1, 1, cands[besti]);
+  if (verbose)
+    fprintf(stderr, "[hk autotune] best: split=%d (R=2^%d C=2^%d) E_row=%d rows=%d E_col=%d tw=%d %.4f ms\n",
+            cands[besti].split, bl.logR, bl.logC, cands[besti].E_row, cands[besti].rows_per_wg, cands[besti].E_col,
+            cands[besti].tw, best);
+  return Status();
+}
+
+}  // namespace hk

@@ -1,0 +1,134 @@
+// Descriptors shared by the host planner and the device kernels.
+//
+// A product (1D Hankel or BHHB, forward or adjoint) is described by a Shape
+// (sizes, operand roles, FFT layout) plus per-instance pointers (Ptrs).  All
+// transforms are powers of two.  Data live on a 2D "storage grid" of
+// 2^logC rows of 2^logR contiguous elements:
+//   * 1D, one workgroup per transform ("resident"): logC = 0, the row is the
+//     whole padded vector of length N = 2^logR.
+//   * 1D, multipass: N = 2^logR * 2^logC, element n at n1 + R n2 with
+//     n = n1 + R n2 (four-step / Bailey decomposition; twiddles between the
+//     column and row transforms).
+//   * BHHB: the padded 2D grid itself, element (i, j) at i + R j; the 2D FFT
+//     is a column FFT (along j) and a row FFT (along i), no twiddles.
+// Pass A transforms columns of every input operand into workspace buffers;
+// pass B does the row transforms, the pointwise spectral product and the row
+// transform of the output; pass D does the output's column transform and the
+// slice.  See hk_bodies.hpp for the index algebra.
+#pragma once
+#include <stdint.h>
+
+namespace hk {
+
+enum : int { MAXOPS = 10 };  // generating vector + up to 8 vectors + adjoint cotangent
+
+enum Role : int32_t { ROLE_H = 0, ROLE_X = 1, ROLE_V = 2 };
+
+enum OpFlag : int32_t {
+  OPF_CONJ = 1,   // load conj(x)
+  OPF_REAL = 2,   // source array is real
+  OPF_ALPHA = 4,  // spectrum multiplies into the scalar product (x_1)
+};
+
+enum Prog : int32_t { PROG_FWD = 0, PROG_BWD = 1 };
+
+enum ColKind : int32_t { COL_A = 0, COL_D = 1 };
+
+struct OpDesc {
+  int32_t role;     // Role
+  int32_t exp;      // multiplicity in the spectral product (ROLE_X)
+  int32_t flags;    // OpFlag bits
+  int32_t buf;      // multipass: workspace buffer that holds its column transform
+  int64_t len;      // 1D: number of stored elements. BHHB: rows of the source matrix
+  int64_t cols;     // BHHB: columns of the source matrix (1 for 1D)
+  int64_t ncol_nz;  // multipass: storage columns that may be nonzero (rest are zero)
+};
+
+struct Shape {
+  int32_t prog;        // Prog
+  int32_t is_block;    // BHHB
+  int32_t m;           // tensor order
+  int32_t nops;        // operands in processing order (H first, scalar operand last)
+  int32_t logR;        // contiguous (row) FFT length 2^logR
+  int32_t logC;        // strided (column) FFT length 2^logC (0 for resident)
+  int32_t resident;    // whole transform in one workgroup
+  int32_t want_y;      // vector output (forward) / grad_h (adjoint)
+  int32_t want_alpha;  // scalar output (forward)
+  int32_t want_out1;   // adjoint: grad_x
+  int32_t real_out;    // store only the real part
+  int32_t rows_per_wg; // multipass row pass: rows per workgroup
+  int64_t out_rows;    // output slice: 1D length / BHHB rows n_1; adjoint grad_h length
+  int64_t out_cols;    // BHHB columns N_1 (1 for 1D)
+  int64_t out1_len;    // adjoint grad_x length
+  int64_t nbuf;        // multipass workspace buffers per instance
+  int64_t partials;    // multipass: number of row-pass workgroups (alpha partial sums)
+  int64_t ws_bytes;    // multipass workspace bytes per instance
+  OpDesc ops[MAXOPS];
+};
+
+struct Ptrs {
+  const void *op[MAXOPS];
+  void *y;           // forward vector output / adjoint grad_h
+  void *alpha;       // forward scalar output
+  void *out1;        // adjoint grad_x
+  const void *phi;   // adjoint scalar cotangent (nullable)
+  void *ws;          // instance workspace (multipass)
+};
+
+// Byte strides between consecutive instances of a strided batch (0 = shared).
+struct Strides {
+  int64_t op[MAXOPS];
+  int64_t y, alpha, out1, phi, ws;
+};
+
+struct ColJob {
+  int32_t kind;   // COL_A: operand `op` -> buffer `buf`;  COL_D: buffer `buf` -> output `op` (0: y, 1: out1)
+  int32_t op;
+  int32_t buf;
+  int32_t conj_out;
+  int64_t ncols;  // storage columns to transform (pruned)
+};
+
+// Persistent batched execution: task list entries.
+enum TaskType : int32_t { TASK_RES = 0, TASK_COLA = 1, TASK_ROWB = 2, TASK_COLD = 3 };
+
+struct Task {
+  int32_t type;
+  int32_t inst;          // instance index (RES: first entry in the resident list)
+  int32_t a;             // RES: number of instances; COLA: operand; COLD: output; ROWB: first row
+  int32_t b;             // COLA/COLD: first column; ROWB: task index within the instance
+  int32_t wait;          // completions of phase `wait_phase` of `inst` required first
+  int32_t wait_phase;    // 0: pass A counter, 1: pass B counter, -1: no wait
+  int32_t signal_phase;  // counter to bump on completion (-1: none)
+  int32_t nrowb;         // ROWB: number of row tasks of the instance (scalar reduction)
+};
+
+struct InstCtl {  // per-instance counters (persistent schedule), zeroed before each run
+  uint32_t done[2];      // completed pass-A / pass-B tasks
+  uint32_t alpha_count;  // row tasks that have published their scalar partial sum
+  uint32_t pad;
+};
+
+struct BatchCtl {
+  uint32_t next;   // task queue head
+  uint32_t error;  // nonzero: a dependency wait exceeded its bound
+  uint32_t pad[2];
+};
+
+// Arguments of the batched (task-list) kernel.  Ptrs.ws of each instance is
+// an offset from ws_base.
+struct BatchArgs {
+  const Task *tasks;
+  const Shape *shapes;
+  const Ptrs *ptrs;
+  const int32_t *res_list;
+  InstCtl *ictl;
+  BatchCtl *bctl;
+  char *ws_base;
+  int32_t begin, end;   // task range of this launch
+  int32_t use_queue;    // 1: persistent workgroups pull tasks and honour dependencies
+  uint32_t spin_limit;  // bound on dependency polling iterations
+};
+
+
+}  // namespace hk

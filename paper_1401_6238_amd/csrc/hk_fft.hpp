@@ -1,0 +1,224 @@
+// Device building blocks: complex arithmetic, in-register DFTs and a
+// workgroup-level Stockham FFT for power-of-two lengths on gfx950.
+//
+// Transform convention (the paper's Matlab-type fft, Section 2.1):
+//   X_k = sum_j x_j exp(-2 pi i j k / L).
+// Only the forward transform is implemented; the inverse used for the
+// generating vector, ifft(v) = conj(fft(conj(v))) / L, is obtained by
+// conjugating on load and store.
+//
+// Layout contract of fft_seq<T, L, E>: a sequence of length L is owned by
+// TPS = L / E consecutive lanes; lane t holds elements t + s*TPS in register
+// slot s (s < E) before the call and the transform's outputs t + s*TPS after
+// it, so consecutive transforms and pointwise products chain in registers.
+// Internally the transform is a Stockham autosort sequence of radix-E passes
+// (last pass radix L / E^(P-1)); consecutive passes exchange data through a
+// padded LDS buffer private to the sequence.  The in-register radix-R DFTs
+// (R <= 32) are radix-2 decimation-in-frequency networks with compile-time
+// twiddles.  Published methods: Cooley-Tukey (1965) radix-2 DIF, Stockham
+// autosort formulation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hk {
+
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b) {
+  cx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) {
+  return mk(a.x + b.x, a.y + b.y);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) {
+  return mk(a.x - b.x, a.y - b.y);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return mk(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> c) {  // a*b + c
+  return mk(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) {
+  return mk(a.x, -a.y);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) {
+  return mk(a.x * s, a.y * s);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> czero() {
+  return mk(T(0), T(0));
+}
+
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+__host__ __device__ constexpr int ipowc(int b, int e) { return e == 0 ? 1 : b * ipowc(b, e - 1); }
+__host__ __device__ constexpr int bitrevc(int v, int bits) {
+  return bits == 0 ? 0 : ((v & 1) << (bits - 1)) | bitrevc(v >> 1, bits - 1);
+}
+
+// cos(2 pi k / 32) for k = 0..8 (sin follows by symmetry).
+__host__ __device__ constexpr double cos32_base(int k) {
+  return k == 0   ? 1.0
+         : k == 1 ? 0.980785280403230449126182236134
+         : k == 2 ? 0.923879532511286756128183189397
+         : k == 3 ? 0.831469612302545237078788377618
+         : k == 4 ? 0.707106781186547524400844362105
+         : k == 5 ? 0.555570233019602224742830813949
+         : k == 6 ? 0.382683432365089771728459984030
+         : k == 7 ? 0.195090322016128267848284868477
+                  : 0.0;
+}
+// cos / sin of 2 pi k / 32 for k in [0, 16).
+__host__ __device__ constexpr double cos32(int k) { return k <= 8 ? cos32_base(k) : -cos32_base(16 - k); }
+__host__ __device__ constexpr double sin32(int k) { return k <= 8 ? cos32_base(8 - k) : cos32_base(k - 8); }
+
+// a * exp(-2 pi i k / 32), k a compile-time constant after unrolling (k < 16).
+template <typename T>
+__device__ __forceinline__ cx<T> twmul32(cx<T> a, int k) {
+  if (k == 0) return a;
+  if (k == 8) return mk(a.y, -a.x);  // * (-i)
+  if (k == 4) {
+    const T c = T(0.707106781186547524400844362105);
+    return mk((a.x + a.y) * c, (a.y - a.x) * c);
+  }
+  if (k == 12) {
+    const T c = T(0.707106781186547524400844362105);
+    return mk((a.y - a.x) * c, -(a.x + a.y) * c);
+  }
+  const T cr = T(cos32(k));
+  const T si = T(sin32(k));
+  return mk(fma(a.x, cr, a.y * si), fma(a.y, cr, -(a.x * si)));
+}
+
+// In-register forward DFT of size R (natural order in and out), R <= 32.
+template <typename T, int R>
+__device__ __forceinline__ void dft(cx<T> (&v)[R]) {
+  static_assert(R >= 1 && R <= 32 && (R & (R - 1)) == 0, "radix");
+  if constexpr (R > 1) {
+#pragma unroll
+    for (int s = R / 2; s >= 1; s >>= 1) {
+#pragma unroll
+      for (int g = 0; g < R; g += 2 * s) {
+#pragma unroll
+        for (int j = 0; j < s; ++j) {
+          const cx<T> u = v[g + j];
+          const cx<T> w = v[g + j + s];
+          v[g + j] = cadd(u, w);
+          v[g + j + s] = twmul32(csub(u, w), j * (32 / (2 * s)));
+        }
+      }
+    }
+    constexpr int bits = ilog2c(R);
+    cx<T> o[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) o[k] = v[bitrevc(k, bits)];
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = o[k];
+  }
+}
+
+// Static layout of a length-L transform with (at most) E elements per lane.
+template <int L, int E>
+struct FFTShape {
+  static_assert(L >= 1 && (L & (L - 1)) == 0, "L must be a power of two");
+  static_assert(E >= 1 && E <= 32 && (E & (E - 1)) == 0, "E must be a power of two <= 32");
+  static constexpr int EE = E < L ? E : L;  // elements per lane
+  static constexpr int TPS = L / EE;        // lanes per sequence
+  static constexpr int LOGL = ilog2c(L);
+  static constexpr int LOGE = ilog2c(EE);
+  static constexpr int P = LOGL == 0 ? 0 : (LOGL + LOGE - 1) / LOGE;  // Stockham passes
+  static constexpr int LOG_LAST = LOGL - LOGE * (P > 0 ? P - 1 : 0);
+  // LDS elements per sequence (padded by one element every EE elements).
+  static constexpr int LDS = P > 1 ? L + L / EE : 0;
+  static __host__ __device__ constexpr int radix(int p) { return p < P - 1 ? EE : (1 << LOG_LAST); }
+  static __device__ __forceinline__ int pad(int i) { return i + (i >> LOGE); }
+};
+
+// Register array holding one lane's share of a length-L sequence.
+template <typename T, int L, int E>
+using Regs = cx<T>[FFTShape<L, E>::EE];
+
+// One Stockham pass.  Slot (q, r) of lane t holds input b + r*(L/R) with
+// butterfly b = t + q*TPS; span Ns = EE^p; outputs go to
+// (b - k) R + k + r Ns, k = b mod Ns.
+template <typename T, int L, int E, int p>
+__device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
+                                         const cx<T> *__restrict__ tw4096) {
+  using S = FFTShape<L, E>;
+  constexpr int EE = S::EE;
+  constexpr int TPS = S::TPS;
+  constexpr int R = S::radix(p);
+  constexpr int B = EE / R;
+  constexpr int Ns = ipowc(EE, p);
+  constexpr bool last = (p == S::P - 1);
+  if constexpr (p > 0) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[q + r * B] = lds[S::pad(t + q * TPS + r * (L / R))];
+  }
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    const int b = t + q * TPS;
+    cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = a[q + r * B];
+    if constexpr (p > 0) {
+      const int k = b & (Ns - 1);
+      constexpr int step = 4096 / (Ns * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw4096[(r * k) * step]);
+    }
+    dft<T, R>(v);
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[q + r * B] = v[r];
+  }
+  if constexpr (!last) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int b = t + q * TPS;
+      const int k = b & (Ns - 1);
+      const int base = (b - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[S::pad(base + r * Ns)] = a[q + r * B];
+    }
+    fft_pass<T, L, E, p + 1>(a, t, lds, tw4096);
+  }
+}
+
+// Forward FFT of one length-L sequence held in registers (see file comment).
+// Every lane of the workgroup must call this (it contains barriers when
+// the transform needs more than one pass).
+template <typename T, int L, int E>
+__device__ __forceinline__ void fft_seq(Regs<T, L, E> &a, int t, cx<T> *lds,
+                                        const cx<T> *__restrict__ tw4096) {
+  if constexpr (FFTShape<L, E>::P > 0) fft_pass<T, L, E, 0>(a, t, lds, tw4096);
+}
+
+// exp(-2 pi i e / 2^logN) for 0 <= e < 2^logN <= 2^24 from two 4096-entry
+// tables: tw24[j] = exp(-2 pi i j / 2^24), tw4096[j] = exp(-2 pi i j / 4096).
+template <typename T>
+__device__ __forceinline__ cx<T> twiddle_big(int64_t e, int logN, const cx<T> *__restrict__ tw24,
+                                             const cx<T> *__restrict__ tw4096) {
+  const uint32_t bidx = (uint32_t)(e << (24 - logN));
+  // tw24[0] is exactly 1, so the product is exact when the low part vanishes.
+  return cmul(tw24[bidx & 4095u], tw4096[bidx >> 12]);
+}
+
+}  // namespace hk

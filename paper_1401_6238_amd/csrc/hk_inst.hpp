@@ -1,0 +1,227 @@
+// Explicit instantiation and dispatch of the kernels for one precision.
+// Included by hk_f32.hip / hk_f64.hip with HK_REAL, HK_NS and HK_SUFFIX set.
+#pragma once
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "hk_kernels.hpp"
+
+namespace hk {
+namespace HK_NS {
+
+template <int L, int E>
+static void *row_fn(int prog) {
+  return prog == PROG_BWD ? (void *)&k_rows<L, E, ROW_MAXT, PROG_BWD> : (void *)&k_rows<L, E, ROW_MAXT, PROG_FWD>;
+}
+template <int L, int E>
+static void *col_fn() {
+  return (void *)&k_cols<L, E, COL_MAXT>;
+}
+
+template <int E>
+static void *pick_row(int logL, int prog) {
+  switch (logL) {
+    case 0: return row_fn<1, E>(prog);
+    case 1: return row_fn<2, E>(prog);
+    case 2: return row_fn<4, E>(prog);
+    case 3: return row_fn<8, E>(prog);
+    case 4: return row_fn<16, E>(prog);
+    case 5: return row_fn<32, E>(prog);
+    case 6: return row_fn<64, E>(prog);
+    case 7: return row_fn<128, E>(prog);
+    case 8: return row_fn<256, E>(prog);
+    case 9: return row_fn<512, E>(prog);
+    case 10: return row_fn<1024, E>(prog);
+    case 11: return row_fn<2048, E>(prog);
+    case 12: return row_fn<4096, E>(prog);
+  }
+  return nullptr;
+}
+template <int E>
+static void *pick_col(int logL) {
+  switch (logL) {
+    case 0: return col_fn<1, E>();
+    case 1: return col_fn<2, E>();
+    case 2: return col_fn<4, E>();
+    case 3: return col_fn<8, E>();
+    case 4: return col_fn<16, E>();
+    case 5: return col_fn<32, E>();
+    case 6: return col_fn<64, E>();
+    case 7: return col_fn<128, E>();
+    case 8: return col_fn<256, E>();
+    case 9: return col_fn<512, E>();
+    case 10: return col_fn<1024, E>();
+    case 11: return col_fn<2048, E>();
+    case 12: return col_fn<4096, E>();
+  }
+  return nullptr;
+}
+
+static void *row_kernel(int logL, int E, int prog) {
+  if (logL < 0 || logL > MAX_LOGL) return nullptr;
+  if (E == 8) return pick_row<8>(logL, prog);
+  if (E == 16) return pick_row<16>(logL, prog);
+  return nullptr;
+}
+static void *col_kernel(int logL, int E) {
+  if (logL < 0 || logL > MAX_LOGL) return nullptr;
+  if (E == 8) return pick_col<8>(logL);
+  if (E == 16) return pick_col<16>(logL);
+  return nullptr;
+}
+
+template <int L, int E>
+static KernelLimits lim_of() {
+  using S = FFTShape<L, E>;
+  KernelLimits k;
+  k.tps = S::TPS;
+  k.seq_lds = S::LDS > 0 ? S::LDS + 1 : 0;
+  k.elem_bytes = (int)sizeof(cx<T>);
+  return k;
+}
+
+template <int E>
+static KernelLimits lim_pick(int logL) {
+  switch (logL) {
+    case 0: return lim_of<1, E>();
+    case 1: return lim_of<2, E>();
+    case 2: return lim_of<4, E>();
+    case 3: return lim_of<8, E>();
+    case 4: return lim_of<16, E>();
+    case 5: return lim_of<32, E>();
+    case 6: return lim_of<64, E>();
+    case 7: return lim_of<128, E>();
+    case 8: return lim_of<256, E>();
+    case 9: return lim_of<512, E>();
+    case 10: return lim_of<1024, E>();
+    case 11: return lim_of<2048, E>();
+    default: return lim_of<4096, E>();
+  }
+}
+
+static std::mutex g_attr_mu;
+
+static hipError_t ensure_lds(void *fn, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  std::lock_guard<std::mutex> lk(g_attr_mu);
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace HK_NS
+
+#define HK_CAT2(a, b) a##b
+#define HK_CAT(a, b) HK_CAT2(a, b)
+
+hipError_t HK_CAT(init_tables_, HK_SUFFIX)(const double *tw4096, const double *tw24) {
+  using namespace HK_NS;
+  std::vector<cx<T>> a(4096), b(4096);
+  for (int j = 0; j < 4096; ++j) {
+    a[j].x = (T)tw4096[2 * j];
+    a[j].y = (T)tw4096[2 * j + 1];
+    b[j].x = (T)tw24[2 * j];
+    b[j].y = (T)tw24[2 * j + 1];
+  }
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_tw4096), a.data(), sizeof(cx<T>) * 4096, 0, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_tw24), b.data(), sizeof(cx<T>) * 4096, 0, hipMemcpyHostToDevice);
+}
+
+bool HK_CAT(limits_, HK_SUFFIX)(int logL, int E, KernelLimits *out) {
+  using namespace HK_NS;
+  if (logL < 0 || logL > MAX_LOGL) return false;
+  if (E == 8) *out = lim_pick<8>(logL);
+  else if (E == 16) *out = lim_pick<16>(logL);
+  else return false;
+  return true;
+}
+
+hipError_t HK_CAT(launch_rows_, HK_SUFFIX)(int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh,
+                                           const Ptrs &p0, const Strides &str, const Ptrs *ptab, int64_t count,
+                                           hipStream_t st) {
+  using namespace HK_NS;
+  void *fn = row_kernel(logL, E, sh.prog);
+  KernelLimits k;
+  if (!fn || !HK_CAT(limits_, HK_SUFFIX)(logL, E, &k)) return hipErrorInvalidValue;
+  const int threads = rows_per_wg * k.tps;
+  if (threads < 1 || threads > ROW_MAXT) return hipErrorInvalidValue;
+  size_t lds = (size_t)rows_per_wg * k.seq_lds * sizeof(cx<T>);
+  const size_t red = (size_t)threads * sizeof(cx<T>);
+  if (lds < red) lds = red;
+  hipError_t e = ensure_lds(fn, lds);
+  if (e != hipSuccess) return e;
+  Shape shc = sh;
+  Ptrs pc = p0;
+  Strides sc = str;
+  const Ptrs *pt = ptab;
+  int64_t cnt = count;
+  void *args[] = {&shc, &pc, &sc, &pt, &cnt};
+  return hipLaunchKernel(fn, grid, dim3(threads), args, lds, st);
+}
+
+hipError_t HK_CAT(launch_cols_, HK_SUFFIX)(int logL, int E, int tw, dim3 grid, const Shape &sh, const Ptrs &p0,
+                                           const Strides &str, const Ptrs *ptab, const ColJob *jobs, int njobs,
+                                           hipStream_t st) {
+  using namespace HK_NS;
+  void *fn = col_kernel(logL, E);
+  KernelLimits k;
+  if (!fn || !HK_CAT(limits_, HK_SUFFIX)(logL, E, &k)) return hipErrorInvalidValue;
+  const int threads = tw * k.tps;
+  if (threads < 1 || threads > COL_MAXT || njobs < 1 || njobs > MAXOPS) return hipErrorInvalidValue;
+  size_t lds = (size_t)tw * k.seq_lds * sizeof(cx<T>);
+  if (lds == 0) lds = 16;
+  hipError_t e = ensure_lds(fn, lds);
+  if (e != hipSuccess) return e;
+  Shape shc = sh;
+  Ptrs pc = p0;
+  Strides sc = str;
+  const Ptrs *pt = ptab;
+  ColJobs cj;
+  memset(&cj, 0, sizeof(cj));
+  for (int i = 0; i < njobs; ++i) cj.j[i] = jobs[i];
+  cj.n = njobs;
+  void *args[] = {&shc, &pc, &sc, &pt, &cj};
+  return hipLaunchKernel(fn, grid, dim3(threads), args, lds, st);
+}
+
+void HK_CAT(batch_geometry_, HK_SUFFIX)(int *blk, int *e_row, int *e_col, size_t *lds_bytes) {
+  using namespace HK_NS;
+  *blk = BATCH_BLK;
+  *e_row = BATCH_E_ROW;
+  *e_col = BATCH_E_COL;
+  size_t mx = (size_t)BATCH_BLK;  // reduction scratch
+  for (int l = 0; l <= MAX_LOGL; ++l) {
+    KernelLimits kr, kc;
+    HK_CAT(limits_, HK_SUFFIX)(l, BATCH_E_ROW, &kr);
+    HK_CAT(limits_, HK_SUFFIX)(l, BATCH_E_COL, &kc);
+    if (kr.tps <= BATCH_BLK) mx = std::max(mx, (size_t)(BATCH_BLK / kr.tps) * kr.seq_lds);
+    if (kc.tps <= BATCH_BLK) mx = std::max(mx, (size_t)(BATCH_BLK / kc.tps) * kc.seq_lds);
+  }
+  *lds_bytes = mx * sizeof(cx<T>);
+}
+
+hipError_t HK_CAT(launch_batch_, HK_SUFFIX)(const BatchArgs &args, int grid, int64_t ninst, bool reset,
+                                            hipStream_t st) {
+  using namespace HK_NS;
+  if (reset) {
+    BatchCtl *b = args.bctl;
+    InstCtl *ic = args.ictl;
+    int64_t n = ninst;
+    void *rargs[] = {&b, &ic, &n};
+    const int64_t blocks = (ninst + 255) / 256 + 1;
+    hipError_t e = hipLaunchKernel((void *)&k_batch_reset, dim3((unsigned)blocks), dim3(256), rargs, 0, st);
+    if (e != hipSuccess) return e;
+  }
+  int blk, er, ec;
+  size_t lds;
+  HK_CAT(batch_geometry_, HK_SUFFIX)(&blk, &er, &ec, &lds);
+  hipError_t e = ensure_lds((void *)&k_batch, lds);
+  if (e != hipSuccess) return e;
+  BatchArgs a = args;
+  void *kargs[] = {&a};
+  return hipLaunchKernel((void *)&k_batch, dim3((unsigned)grid), dim3(blk), kargs, lds, st);
+}
+
+}  // namespace hk

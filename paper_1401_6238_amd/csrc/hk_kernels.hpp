@@ -1,0 +1,274 @@
+// Kernels and their host-side launchers, instantiated once per real type by
+// hk_f32.hip and hk_f64.hip (HK_REAL = float / double).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hk_bodies.hpp"
+#include "hk_launch.hpp"
+
+#ifndef HK_REAL
+#error "HK_REAL must be defined"
+#endif
+
+namespace hk {
+namespace HK_NS {
+
+using T = HK_REAL;
+
+// Twiddle tables of this precision, filled once per device by init_tables():
+// g_tw4096[j] = exp(-2 pi i j / 4096), g_tw24[j] = exp(-2 pi i j / 2^24).
+static __device__ cx<T> g_tw4096[4096];
+static __device__ cx<T> g_tw24[4096];
+
+struct ColJobs {
+  ColJob j[MAXOPS];
+  int32_t n;
+};
+
+// Rows of length L: resident instances (blockIdx.x * rows + rw) or pass-B
+// rows of instance blockIdx.y.
+template <int L, int E, int MAXT, int PROG>
+__global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, const Ptrs *__restrict__ ptab, int64_t count) {
+  using RB = RowBody<T, L, E>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *smem = (cx<T> *)smem_raw;
+  const int tid = threadIdx.x;
+  const int rows = blockDim.x / RB::TPS;
+  const int rw = tid / RB::TPS;
+  const int t = tid % RB::TPS;
+  cx<T> *lds = smem + rw * RB::SEQ_LDS;
+  cx<T> *red = smem;  // reused for reductions after the transforms
+  if (sh.resident) {
+    const int64_t inst = (int64_t)blockIdx.x * rows + rw;
+    const bool valid = inst < count;
+    const Ptrs P = ptab ? ptab[valid ? inst : 0] : inst_ptrs(p0, str, valid ? inst : 0);
+    if (PROG == PROG_BWD) {
+      RB::run_bwd(sh, P, 0, valid, t, lds, true, g_tw24, g_tw4096);
+      return;
+    }
+    const cx<T> part = RB::run_fwd(sh, P, 0, valid, t, lds, true, g_tw24, g_tw4096);
+    if (sh.want_alpha) {
+      const cx<T> tot = segment_sum(part, red, tid, RB::TPS);
+      if (valid && t == 0) store_out<T>(P.alpha, 0, tot, sh.real_out);
+    }
+  } else {
+    const int64_t inst = blockIdx.y;
+    const Ptrs P = ptab ? ptab[inst] : inst_ptrs(p0, str, inst);
+    const int64_t row = (int64_t)blockIdx.x * rows + rw;
+    const bool valid = row < ((int64_t)1 << sh.logC);
+    if (PROG == PROG_BWD) {
+      RB::run_bwd(sh, P, row, valid, t, lds, false, g_tw24, g_tw4096);
+      return;
+    }
+    const cx<T> part = RB::run_fwd(sh, P, row, valid, t, lds, false, g_tw24, g_tw4096);
+    if (sh.want_alpha) {
+      const int nthr = blockDim.x;
+      const cx<T> tot = segment_sum(part, red, tid, nthr);
+      if (tid == 0) {
+        cx<T> *partials = ws_partials<T>(sh, P);
+        uint32_t *counter = ws_counter<T>(sh, P);
+        partials[blockIdx.x] = tot;
+        __threadfence();
+        const uint32_t prev = atomicAdd(counter, 1u);
+        if (prev == (uint32_t)(gridDim.x - 1)) {
+          __threadfence();
+          // Sum the partials in index order (deterministic regardless of
+          // which workgroup finished last).
+          cx<T> s = czero<T>();
+          for (int64_t i = 0; i < (int64_t)gridDim.x; ++i) s = cadd(s, partials[i]);
+          store_out<T>(P.alpha, 0, s, sh.real_out);
+        }
+      }
+    }
+  }
+}
+
+template <int L, int E, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_cols(Shape sh, Ptrs p0, Strides str, const Ptrs *__restrict__ ptab, ColJobs jobs) {
+  using CB = ColBody<T, L, E>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *smem = (cx<T> *)smem_raw;
+  const ColJob &job = jobs.j[blockIdx.y];
+  const int TW = blockDim.x / CB::TPS;
+  const int64_t c0 = (int64_t)blockIdx.x * TW;
+  const Ptrs P = ptab ? ptab[blockIdx.z] : inst_ptrs(p0, str, blockIdx.z);
+  if (job.kind == COL_A && sh.want_alpha && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+    *ws_counter<T>(sh, P) = 0u;  // pass B's last-arriver counter (pass A always precedes pass B)
+  if (c0 >= job.ncols) return;
+  CB::run(sh, P, job, c0, TW, threadIdx.x, smem, g_tw24, g_tw4096);
+}
+
+}  // namespace HK_NS
+}  // namespace hk
+
+namespace hk {
+namespace HK_NS {
+
+// ---------------------------------------------------------------------------
+// Batched task-list kernel.  With use_queue = 1 it is a persistent kernel:
+// each workgroup pulls task indices from a global counter, waits (bounded)
+// until the instance phase it depends on is complete, runs the task and
+// publishes its completion.  Tasks only depend on tasks with smaller
+// indices, and a task index is only handed to a running workgroup, so the
+// oldest unfinished task never waits: the schedule cannot deadlock, whatever
+// the number of resident workgroups.  With use_queue = 0 the same kernel
+// runs one task per workgroup (one launch per phase).
+// ---------------------------------------------------------------------------
+enum : int { BATCH_BLK = 512, BATCH_E_ROW = 8, BATCH_E_COL = sizeof(T) == 4 ? 16 : 8 };
+
+template <int L>
+__device__ __noinline__ void batch_res(const BatchArgs &A, const Task &tk, cx<T> *smem, int tid) {
+  using RB = RowBody<T, L, BATCH_E_ROW>;
+  const int rw = tid / RB::TPS;
+  const int t = tid % RB::TPS;
+  const bool valid = rw < tk.a;
+  const int32_t inst = A.res_list[tk.inst + (valid ? rw : 0)];
+  const Shape &sh = A.shapes[inst];
+  const Ptrs &P = A.ptrs[inst];
+  const cx<T> part = RB::run_fwd(sh, P, 0, valid, t, smem + rw * RB::SEQ_LDS, true, g_tw24, g_tw4096);
+  if (sh.want_alpha) {
+    const cx<T> tot = segment_sum(part, smem, tid, RB::TPS);
+    if (valid && t == 0) store_out<T>(P.alpha, 0, tot, sh.real_out);
+  }
+}
+
+template <int L>
+__device__ __noinline__ void batch_rowb(const BatchArgs &A, const Task &tk, const Shape &sh, const Ptrs &P,
+                                           cx<T> *smem, int tid) {
+  using RB = RowBody<T, L, BATCH_E_ROW>;
+  const int rw = tid / RB::TPS;
+  const int t = tid % RB::TPS;
+  const int64_t row = (int64_t)tk.a + rw;
+  const bool valid = row < ((int64_t)1 << sh.logC);
+  const cx<T> part = RB::run_fwd(sh, P, row, valid, t, smem + rw * RB::SEQ_LDS, false, g_tw24, g_tw4096);
+  if (sh.want_alpha) {
+    const cx<T> tot = segment_sum(part, smem, tid, BATCH_BLK);
+    if (tid == 0) {
+      cx<T> *partials = ws_partials<T>(sh, P);
+      partials[tk.b] = tot;
+      __threadfence();
+      const uint32_t prev = atomicAdd(&A.ictl[tk.inst].alpha_count, 1u);
+      if (prev == (uint32_t)(tk.nrowb - 1)) {
+        __threadfence();
+        cx<T> s = czero<T>();
+        for (int i = 0; i < tk.nrowb; ++i) s = cadd(s, partials[i]);
+        store_out<T>(P.alpha, 0, s, sh.real_out);
+      }
+    }
+  }
+}
+
+template <int L>
+__device__ __noinline__ void batch_col(const Task &tk, const Shape &sh, const Ptrs &P, cx<T> *smem, int tid) {
+  using CB = ColBody<T, L, BATCH_E_COL>;
+  constexpr int TW = BATCH_BLK / CB::TPS;
+  ColJob job;
+  if (tk.type == TASK_COLA) {
+    job.kind = COL_A;
+    job.op = tk.a;
+    job.buf = sh.ops[tk.a].buf;
+    job.conj_out = 0;
+    job.ncols = sh.ops[tk.a].ncol_nz;
+  } else {
+    job.kind = COL_D;
+    job.op = tk.a;
+    job.buf = sh.ops[tk.a].buf;
+    job.conj_out = (sh.prog == PROG_BWD && tk.a == 1) ? 1 : 0;
+    const int64_t lim = tk.a == 0 ? sh.out_rows : sh.out1_len;
+    job.ncols = min(((int64_t)1 << sh.logR), lim);
+  }
+  CB::run(sh, P, job, tk.b, TW, tid, smem, g_tw24, g_tw4096);
+}
+
+#define HK_LSWITCH(logv, FN, ...)                  \
+  switch (logv) {                                 \
+    case 0: FN<1>(__VA_ARGS__); break;            \
+    case 1: FN<2>(__VA_ARGS__); break;            \
+    case 2: FN<4>(__VA_ARGS__); break;            \
+    case 3: FN<8>(__VA_ARGS__); break;            \
+    case 4: FN<16>(__VA_ARGS__); break;           \
+    case 5: FN<32>(__VA_ARGS__); break;           \
+    case 6: FN<64>(__VA_ARGS__); break;           \
+    case 7: FN<128>(__VA_ARGS__); break;          \
+    case 8: FN<256>(__VA_ARGS__); break;          \
+    case 9: FN<512>(__VA_ARGS__); break;          \
+    case 10: FN<1024>(__VA_ARGS__); break;        \
+    case 11: FN<2048>(__VA_ARGS__); break;        \
+    case 12: FN<4096>(__VA_ARGS__); break;        \
+    default: break;                               \
+  }
+
+__global__ void __launch_bounds__(BATCH_BLK) k_batch(BatchArgs A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *smem = (cx<T> *)smem_raw;
+  __shared__ int32_t s_task;
+  const int tid = threadIdx.x;
+  for (int iter = 0;; ++iter) {
+    int32_t ti;
+    if (A.use_queue) {
+      if (tid == 0) s_task = A.begin + (int32_t)atomicAdd(&A.bctl->next, 1u);
+      __syncthreads();
+      ti = s_task;
+      __syncthreads();
+    } else {
+      if (iter > 0) break;
+      ti = A.begin + (int32_t)blockIdx.x;
+    }
+    if (ti >= A.end) break;
+    const Task tk = A.tasks[ti];
+    if (A.use_queue && tk.wait_phase >= 0) {
+      if (tid == 0) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&A.ictl[tk.inst].done[tk.wait_phase], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)tk.wait) {
+          __builtin_amdgcn_s_sleep(2);
+          // Bounded wait: after the limit (or once any wait has failed) the
+          // error word is set and the task runs anyway, so the grid drains.
+          if (++spins > A.spin_limit ||
+              __hip_atomic_load(&A.bctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            atomicOr(&A.bctl->error, 1u);
+            break;
+          }
+        }
+      }
+      __syncthreads();
+      __threadfence();  // acquire: observe the producer workgroups' stores
+    }
+    if (tk.type == TASK_RES) {
+      const Shape &sh0 = A.shapes[A.res_list[tk.inst]];
+      HK_LSWITCH(sh0.logR, batch_res, A, tk, smem, tid)
+    } else {
+      const Shape &sh = A.shapes[tk.inst];
+      Ptrs P = A.ptrs[tk.inst];
+      P.ws = A.ws_base + (uintptr_t)P.ws;
+      if (tk.type == TASK_ROWB) {
+        HK_LSWITCH(sh.logR, batch_rowb, A, tk, sh, P, smem, tid)
+      } else {
+        HK_LSWITCH(sh.logC, batch_col, tk, sh, P, smem, tid)
+      }
+    }
+    if (tk.signal_phase >= 0) {
+      __threadfence();  // release this lane's stores
+      __syncthreads();
+      if (tid == 0) atomicAdd(&A.ictl[tk.inst].done[tk.signal_phase], 1u);
+    }
+  }
+}
+
+// Zeroes the batch control block and the per-instance counters (a plain
+// kernel rather than a memset node, so that graph replays stay exact).
+__global__ void k_batch_reset(BatchCtl *bctl, InstCtl *ictl, int64_t ninst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    bctl->next = 0;
+    bctl->error = 0;
+  }
+  if (i < ninst) {
+    ictl[i].done[0] = 0;
+    ictl[i].done[1] = 0;
+    ictl[i].alpha_count = 0;
+  }
+}
+
+}  // namespace HK_NS
+}  // namespace hk

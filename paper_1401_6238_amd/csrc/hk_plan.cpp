@@ -1,0 +1,453 @@
+// Planning and launch sequencing of the plain (single-shape) path.
+#include "hk_plan.hpp"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+namespace hk {
+
+static thread_local int tl_launches = 0;
+void count_launch() { ++tl_launches; }
+int launches_and_reset() {
+  const int v = tl_launches;
+  tl_launches = 0;
+  return v;
+}
+
+Status fail(hk_status_t code, const std::string &msg) {
+  Status s;
+  s.code = code;
+  s.msg = msg;
+  return s;
+}
+
+bool is_complex(hk_dtype_t dt) { return dt == HK_C64 || dt == HK_C128; }
+size_t elem_bytes(hk_dtype_t dt) {
+  switch (dt) {
+    case HK_C64: return 8;
+    case HK_C128: return 16;
+    case HK_F32: return 4;
+    case HK_F64: return 8;
+  }
+  return 0;
+}
+size_t cplx_bytes(hk_dtype_t dt) { return (dt == HK_C128 || dt == HK_F64) ? 16 : 8; }
+static bool is_double(hk_dtype_t dt) { return dt == HK_C128 || dt == HK_F64; }
+
+int ceil_log2(int64_t v) {
+  int l = 0;
+  while (((int64_t)1 << l) < v) ++l;
+  return l;
+}
+
+static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+static Status check_common(const Problem &p) {
+  if (p.dt < HK_C64 || p.dt > HK_F64) return fail(HK_ERR_INVALID_VALUE, "unknown dtype");
+  if (p.m < 2 || p.m > HK_MAX_ORDER) return fail(HK_ERR_INVALID_VALUE, "order m must be in [2, 8]");
+  for (int q = 0; q < p.m; ++q) {
+    if (p.dims[q] < 1) return fail(HK_ERR_INVALID_VALUE, "every dimension must be >= 1");
+    if (p.dims[q] > ((int64_t)1 << 40)) return fail(HK_ERR_SIZE_LIMIT, "dimension too large");
+    if (p.is_block) {
+      if (p.bdims[q] < 1) return fail(HK_ERR_INVALID_VALUE, "every block count must be >= 1");
+      if (p.bdims[q] > ((int64_t)1 << 40)) return fail(HK_ERR_SIZE_LIMIT, "block count too large");
+    }
+  }
+  return Status();
+}
+
+Status validate_forward(const Problem &p) {
+  Status s = check_common(p);
+  if (!s.ok()) return s;
+  if (!p.y && !p.alpha) return fail(HK_ERR_NULL_POINTER, "neither y nor alpha requested");
+  if (!p.h) return fail(HK_ERR_NULL_POINTER, "generating vector/matrix is NULL");
+  for (int q = 1; q < p.m; ++q)
+    if (!p.vec[q]) return fail(HK_ERR_NULL_POINTER, "vector " + std::to_string(q + 1) + " is NULL");
+  if (p.alpha && !p.vec[0]) return fail(HK_ERR_NULL_POINTER, "alpha requested but vector 1 is NULL");
+  const size_t a = elem_bytes(p.dt);
+  if (!aligned(p.h, a) || (p.y && !aligned(p.y, a)) || (p.alpha && !aligned(p.alpha, a)))
+    return fail(HK_ERR_MISALIGNED, "pointer not aligned to the element size");
+  for (int q = 0; q < p.m; ++q)
+    if (p.vec[q] && !aligned(p.vec[q], a)) return fail(HK_ERR_MISALIGNED, "vector not aligned to the element size");
+  Layout lay;
+  return layout_for(p, 0, &lay);
+}
+
+Status validate_backward(const Problem &p) {
+  Status s = check_common(p);
+  if (!s.ok()) return s;
+  if (!is_complex(p.dt)) return fail(HK_ERR_NOT_SUPPORTED, "the adjoint is implemented for complex dtypes");
+  if (!p.gx && !p.gh) return fail(HK_ERR_NULL_POINTER, "neither grad_x nor grad_h requested");
+  if (!p.h || !p.vec[1]) return fail(HK_ERR_NULL_POINTER, "h or x is NULL");
+  const size_t a = elem_bytes(p.dt);
+  const void *ps[] = {p.h, p.vec[1], p.v, p.phi, p.gx, p.gh};
+  for (const void *q : ps)
+    if (q && !aligned(q, a)) return fail(HK_ERR_MISALIGNED, "pointer not aligned to the element size");
+  Layout lay;
+  return layout_for(p, 0, &lay);
+}
+
+// ---------------------------------------------------------------------------
+// Layout
+// ---------------------------------------------------------------------------
+Status layout_for(const Problem &p, int split, Layout *out) {
+  Layout lay;
+  if (!p.is_block) {
+    int64_t dh = 1 - p.m;
+    for (int q = 0; q < p.m; ++q) dh += p.dims[q];
+    const int logN = ceil_log2(dh);
+    if (logN > HK_MAX_FFT_LOG2) return fail(HK_ERR_SIZE_LIMIT, "padded length exceeds 2^24");
+    if (logN <= RES_MAX_LOG) {
+      lay.resident = true;
+      lay.logR = logN;
+      lay.logC = 0;
+    } else {
+      int logR = (logN + 1) / 2 + split;
+      logR = std::max<int>(logN - MAX_LOGL, std::min<int>(MAX_LOGL, logR));
+      lay.logR = logR;
+      lay.logC = logN - logR;
+    }
+  } else {
+    int64_t rows = 1 - p.m, cols = 1 - p.m;
+    for (int q = 0; q < p.m; ++q) {
+      rows += p.dims[q];
+      cols += p.bdims[q];
+    }
+    lay.logR = ceil_log2(rows);
+    lay.logC = ceil_log2(cols);
+    if (lay.logR > MAX_LOGL || lay.logC > MAX_LOGL)
+      return fail(HK_ERR_SIZE_LIMIT, "padded BHHB grid exceeds 4096 along an axis");
+    lay.resident = false;
+  }
+  *out = lay;
+  return Status();
+}
+
+// ---------------------------------------------------------------------------
+// Shape
+// ---------------------------------------------------------------------------
+Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *shp, Ptrs *ptrs,
+                   int op_src[MAXOPS]) {
+  Shape sh;
+  memset(&sh, 0, sizeof(sh));
+  Ptrs P;
+  memset(&P, 0, sizeof(P));
+  sh.prog = p.prog;
+  sh.is_block = p.is_block ? 1 : 0;
+  sh.m = p.m;
+  sh.logR = lay.logR;
+  sh.logC = lay.logC;
+  sh.resident = lay.resident ? 1 : 0;
+  sh.real_out = is_complex(p.dt) ? 0 : 1;
+  const int real_flag = is_complex(p.dt) ? 0 : OPF_REAL;
+  const int64_t R = (int64_t)1 << lay.logR;
+  int64_t hrows = 1 - p.m, hcols = 1 - p.m;
+  for (int q = 0; q < p.m; ++q) {
+    hrows += p.dims[q];
+    hcols += p.bdims[q];
+  }
+  auto add_op = [&](int role, int exp, int flags, int64_t len, int64_t cols, const void *ptr, int src) {
+    OpDesc &od = sh.ops[sh.nops];
+    od.role = role;
+    od.exp = exp;
+    od.flags = flags;
+    od.len = len;
+    od.cols = cols;
+    od.buf = sh.nops;
+    od.ncol_nz = std::min<int64_t>(R, len);
+    P.op[sh.nops] = ptr;
+    if (op_src) op_src[sh.nops] = src;
+    ++sh.nops;
+  };
+  if (p.prog == PROG_FWD) {
+    sh.want_y = p.y ? 1 : 0;
+    sh.want_alpha = p.alpha ? 1 : 0;
+    add_op(ROLE_H, 1, OPF_CONJ | real_flag, p.is_block ? hrows : hrows, p.is_block ? hcols : 1, p.h, -1);
+    // Group identical vectors of modes 2..m (same pointer and shape).
+    struct G {
+      const void *ptr;
+      int64_t n, nb;
+      int exp;
+      int src;
+    };
+    std::vector<G> groups;
+    for (int q = 1; q < p.m; ++q) {
+      bool found = false;
+      for (auto &g : groups)
+        if (g.ptr == p.vec[q] && g.n == p.dims[q] && g.nb == (p.is_block ? p.bdims[q] : 1)) {
+          g.exp++;
+          found = true;
+          break;
+        }
+      if (!found) groups.push_back({p.vec[q], p.dims[q], p.is_block ? p.bdims[q] : 1, 1, q});
+    }
+    int alpha_group = -1;
+    if (p.alpha) {
+      for (size_t i = 0; i < groups.size(); ++i)
+        if (groups[i].ptr == p.vec[0] && groups[i].n == p.dims[0] &&
+            groups[i].nb == (p.is_block ? p.bdims[0] : 1))
+          alpha_group = (int)i;
+      if (alpha_group < 0) {
+        groups.push_back({p.vec[0], p.dims[0], p.is_block ? p.bdims[0] : 1, 0, 0});
+        alpha_group = (int)groups.size() - 1;
+      }
+      std::swap(groups[alpha_group], groups.back());  // scalar operand is processed last
+      alpha_group = (int)groups.size() - 1;
+    }
+    for (size_t i = 0; i < groups.size(); ++i) {
+      const int flags = real_flag | ((int)i == alpha_group ? OPF_ALPHA : 0);
+      add_op(ROLE_X, groups[i].exp, flags, groups[i].n, groups[i].nb, groups[i].ptr, groups[i].src);
+    }
+    sh.out_rows = p.dims[0];
+    sh.out_cols = p.is_block ? p.bdims[0] : 1;
+    P.y = p.y;
+    P.alpha = p.alpha;
+  } else {
+    // Adjoint of the equal-vector products: X, [V], [H].
+    const int64_t n = p.dims[0];
+    sh.want_y = p.gh ? 1 : 0;
+    sh.want_out1 = p.gx ? 1 : 0;
+    add_op(ROLE_X, 0, 0, n, 1, p.vec[1], 1);
+    if (p.v) add_op(ROLE_V, 0, OPF_CONJ, n, 1, p.v, -2);
+    if (p.gx) add_op(ROLE_H, 1, OPF_CONJ, hrows, 1, p.h, -1);
+    sh.out_rows = hrows;  // grad_h length d_H
+    sh.out_cols = 1;
+    sh.out1_len = n;      // grad_x length
+    P.y = p.gh;
+    P.out1 = p.gx;
+    P.phi = p.phi;
+  }
+  if (!lay.resident) {
+    // The workspace size does not depend on the schedule: partial sums are
+    // reserved for the largest possible number of row-pass workgroups.
+    sh.rows_per_wg = sc.rows_per_wg;
+    sh.nbuf = sh.nops;
+    sh.partials = (int64_t)1 << MAX_LOGL;
+    const size_t eb = cplx_bytes(p.dt);
+    const size_t bytes = (size_t)sh.nbuf * ((size_t)1 << (lay.logR + lay.logC)) * eb + (size_t)sh.partials * eb + 16;
+    sh.ws_bytes = (int64_t)((bytes + 255) & ~(size_t)255);
+  }
+  *shp = sh;
+  *ptrs = P;
+  return Status();
+}
+
+size_t instance_ws_bytes(const Shape &sh, hk_dtype_t) { return sh.resident ? 0 : (size_t)sh.ws_bytes; }
+
+// ---------------------------------------------------------------------------
+// Schedules
+// ---------------------------------------------------------------------------
+static bool lim(hk_dtype_t dt, int logL, int E, KernelLimits *k) {
+  return is_double(dt) ? limits_f64(logL, E, k) : limits_f32(logL, E, k);
+}
+
+bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
+  KernelLimits kr, kc;
+  if (!lim(dt, lay.logR, sc.E_row, &kr)) return false;
+  if (sc.rows_per_wg < 1 || sc.rows_per_wg * kr.tps > ROW_MAXT) return false;
+  const size_t row_lds = std::max((size_t)sc.rows_per_wg * kr.seq_lds, (size_t)sc.rows_per_wg * kr.tps) * kr.elem_bytes;
+  if (row_lds > 160 * 1024) return false;
+  if (!lay.resident) {
+    if (!lim(dt, lay.logC, sc.E_col, &kc)) return false;
+    if (sc.tw < 1 || sc.tw * kc.tps > COL_MAXT) return false;
+    if ((size_t)sc.tw * kc.seq_lds * kc.elem_bytes > 160 * 1024) return false;
+  }
+  return true;
+}
+
+Sched default_sched(hk_dtype_t dt, const Layout &lay, int prog, int64_t batch) {
+  Sched sc;
+  const bool dbl = is_double(dt);
+  sc.E_row = 8;
+  sc.E_col = dbl ? 8 : 16;
+  KernelLimits kr, kc;
+  lim(dt, lay.logR, sc.E_row, &kr);
+  if (kr.tps > ROW_MAXT) {  // 4096-point rows need 16 elements per lane
+    sc.E_row = 16;
+    lim(dt, lay.logR, sc.E_row, &kr);
+  }
+  if (lay.resident) {
+    // One instance per row; pack rows up to 256 lanes when batched.
+    const int max_rows = std::max(1, ROW_MAXT / kr.tps);
+    sc.rows_per_wg = (int)std::max<int64_t>(1, std::min<int64_t>(max_rows, batch));
+  } else {
+    sc.rows_per_wg = std::max(1, std::min(ROW_MAXT / kr.tps, 1 << lay.logC));
+    lim(dt, lay.logC, sc.E_col, &kc);
+    const int want_tw = dbl ? 8 : 16;  // 128-byte row segments
+    int tw = std::max(1, std::min(want_tw, COL_MAXT / kc.tps));
+    while (tw > 1 && (size_t)tw * kc.seq_lds * kc.elem_bytes > 144 * 1024) tw >>= 1;
+    sc.tw = tw;
+  }
+  (void)prog;
+  return sc;
+}
+
+// ---------------------------------------------------------------------------
+// Launch sequences
+// ---------------------------------------------------------------------------
+static hipError_t rows(hk_dtype_t dt, int logL, int E, int rpw, dim3 g, const Shape &sh, const Ptrs &p0,
+                       const Strides &str, const Ptrs *pt, int64_t cnt, hipStream_t st) {
+  count_launch();
+  return is_double(dt) ? launch_rows_f64(logL, E, rpw, g, sh, p0, str, pt, cnt, st)
+                       : launch_rows_f32(logL, E, rpw, g, sh, p0, str, pt, cnt, st);
+}
+static hipError_t cols(hk_dtype_t dt, int logL, int E, int tw, dim3 g, const Shape &sh, const Ptrs &p0,
+                       const Strides &str, const Ptrs *pt, const ColJob *jobs, int nj, hipStream_t st) {
+  count_launch();
+  return is_double(dt) ? launch_cols_f64(logL, E, tw, g, sh, p0, str, pt, jobs, nj, st)
+                       : launch_cols_f32(logL, E, tw, g, sh, p0, str, pt, jobs, nj, st);
+}
+
+static Status hip_fail(hipError_t e, const char *what) {
+  return fail(HK_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs &p0, const Strides &str,
+                    const Ptrs *ptab, int64_t count, hipStream_t st) {
+  if (count < 1) return Status();
+  if (count > 65535 && !sh.resident) return fail(HK_ERR_SIZE_LIMIT, "batch too large for one launch");
+  hipError_t e;
+  if (sh.resident) {
+    const int64_t blocks = (count + sc.rows_per_wg - 1) / sc.rows_per_wg;
+    if (blocks > 0x7fffffff) return fail(HK_ERR_SIZE_LIMIT, "batch too large");
+    e = rows(dt, sh.logR, sc.E_row, sc.rows_per_wg, dim3((unsigned)blocks), sh, p0, str, ptab, count, st);
+    if (e != hipSuccess) return hip_fail(e, "resident launch");
+    return Status();
+  }
+  const int64_t R = (int64_t)1 << sh.logR;
+  const int64_t C = (int64_t)1 << sh.logC;
+  // Pass A: column transforms of every operand.
+  ColJob ja[MAXOPS];
+  int64_t max_cols = 0;
+  for (int o = 0; o < sh.nops; ++o) {
+    ja[o].kind = COL_A;
+    ja[o].op = o;
+    ja[o].buf = sh.ops[o].buf;
+    ja[o].conj_out = 0;
+    ja[o].ncols = sh.ops[o].ncol_nz;
+    max_cols = std::max(max_cols, ja[o].ncols);
+  }
+  dim3 ga((unsigned)((max_cols + sc.tw - 1) / sc.tw), (unsigned)sh.nops, (unsigned)count);
+  e = cols(dt, sh.logC, sc.E_col, sc.tw, ga, sh, p0, str, ptab, ja, sh.nops, st);
+  if (e != hipSuccess) return hip_fail(e, "pass A launch");
+  // Pass B: row transforms, spectral product, row transform of the output.
+  dim3 gb((unsigned)((C + sc.rows_per_wg - 1) / sc.rows_per_wg), (unsigned)count);
+  e = rows(dt, sh.logR, sc.E_row, sc.rows_per_wg, gb, sh, p0, str, ptab, count, st);
+  if (e != hipSuccess) return hip_fail(e, "pass B launch");
+  // Pass D: column transforms of the outputs and the slice.
+  ColJob jd[2];
+  int nd = 0;
+  int64_t dcols = 0;
+  if (sh.want_y) {
+    jd[nd].kind = COL_D;
+    jd[nd].op = 0;
+    jd[nd].buf = sh.ops[0].buf;
+    jd[nd].conj_out = 0;
+    jd[nd].ncols = std::min<int64_t>(R, sh.out_rows);
+    dcols = std::max(dcols, jd[nd].ncols);
+    ++nd;
+  }
+  if (sh.prog == PROG_BWD && sh.want_out1) {
+    jd[nd].kind = COL_D;
+    jd[nd].op = 1;
+    jd[nd].buf = sh.ops[1].buf;
+    jd[nd].conj_out = 1;
+    jd[nd].ncols = std::min<int64_t>(R, sh.out1_len);
+    dcols = std::max(dcols, jd[nd].ncols);
+    ++nd;
+  }
+  if (nd > 0) {
+    dim3 gd((unsigned)((dcols + sc.tw - 1) / sc.tw), (unsigned)nd, (unsigned)count);
+    e = cols(dt, sh.logC, sc.E_col, sc.tw, gd, sh, p0, str, ptab, jd, nd, st);
+    if (e != hipSuccess) return hip_fail(e, "pass D launch");
+  }
+  return Status();
+}
+
+// ---------------------------------------------------------------------------
+// Device setup
+// ---------------------------------------------------------------------------
+static void twiddle_tables(std::vector<double> &t4096, std::vector<double> &t24) {
+  t4096.resize(8192);
+  t24.resize(8192);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int j = 0; j < 4096; ++j) {
+    const long double a = two_pi * ((long double)j / 4096.0L);
+    t4096[2 * j] = (double)cosl(a);
+    t4096[2 * j + 1] = (double)-sinl(a);
+    const long double b = two_pi * ((long double)j / 16777216.0L);
+    t24[2 * j] = (double)cosl(b);
+    t24[2 * j + 1] = (double)-sinl(b);
+  }
+  // Exact values at the quarter points.
+  t4096[0] = 1.0;
+  t4096[1] = 0.0;
+  t4096[2 * 1024] = 0.0;
+  t4096[2 * 1024 + 1] = -1.0;
+  t4096[2 * 2048] = -1.0;
+  t4096[2 * 2048 + 1] = 0.0;
+  t4096[2 * 3072] = 0.0;
+  t4096[2 * 3072 + 1] = 1.0;
+  t24[0] = 1.0;
+  t24[1] = 0.0;
+}
+
+Status ensure_device() {
+  static std::mutex mu;
+  static std::map<int, int> state;  // device -> 1 ok, -1 not gfx950
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = state.find(dev);
+  if (it != state.end()) {
+    if (it->second == 1) return Status();
+    return fail(HK_ERR_DEVICE, "current device is not gfx950");
+  }
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    state[dev] = -1;
+    return fail(HK_ERR_DEVICE, std::string("current device is ") + prop.gcnArchName + ", not gfx950");
+  }
+  std::vector<double> a, b;
+  twiddle_tables(a, b);
+  e = init_tables_f32(a.data(), b.data());
+  if (e == hipSuccess) e = init_tables_f64(a.data(), b.data());
+  if (e != hipSuccess) return hip_fail(e, "twiddle table upload");
+  state[dev] = 1;
+  return Status();
+}
+
+// ---------------------------------------------------------------------------
+// Schedule cache
+// ---------------------------------------------------------------------------
+using SchedKey = std::tuple<int, int, int, int, int, int>;
+static std::mutex g_sched_mu;
+static std::map<SchedKey, Sched> g_sched;
+
+static int batch_class(int64_t b) { return b <= 1 ? 0 : (b < 16 ? 1 : 2); }
+
+bool sched_lookup(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint, int64_t batch, Sched *sc) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  auto it = g_sched.find(SchedKey((int)dt, prog, is_block, logN, logC_hint, batch_class(batch)));
+  if (it == g_sched.end()) return false;
+  *sc = it->second;
+  return true;
+}
+
+void sched_store(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint, int64_t batch, const Sched &sc) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  g_sched[SchedKey((int)dt, prog, is_block, logN, logC_hint, batch_class(batch))] = sc;
+}
+
+}  // namespace hk

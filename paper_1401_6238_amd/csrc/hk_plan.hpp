@@ -1,0 +1,99 @@
+// Host-side planning of Hankel tensor-vector products: normalized problem
+// descriptions, FFT layouts, schedules and the launch sequences of the plain
+// (single-shape) path.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hankel.h"
+#include "hk_common.hpp"
+#include "hk_launch.hpp"
+
+namespace hk {
+
+// Largest 1D padded length handled by one workgroup.
+enum : int { RES_MAX_LOG = 12 };
+
+struct Status {
+  hk_status_t code = HK_SUCCESS;
+  std::string msg;
+  bool ok() const { return code == HK_SUCCESS; }
+};
+
+Status fail(hk_status_t code, const std::string &msg);
+
+// A product request after validation (pointers are device pointers).
+struct Problem {
+  hk_dtype_t dt = HK_C64;
+  int prog = PROG_FWD;
+  bool is_block = false;
+  int m = 0;
+  int64_t dims[HK_MAX_ORDER] = {0};
+  int64_t bdims[HK_MAX_ORDER] = {0};
+  const void *h = nullptr;
+  const void *vec[HK_MAX_ORDER] = {nullptr};  // forward: vec[0] only for alpha
+  void *y = nullptr;
+  void *alpha = nullptr;
+  // adjoint (equal vectors): vec[1] = x
+  const void *v = nullptr;
+  const void *phi = nullptr;
+  void *gx = nullptr;
+  void *gh = nullptr;
+};
+
+// Launch parameters of one shape.
+struct Sched {
+  int E_row = 8;
+  int rows_per_wg = 1;
+  int E_col = 16;
+  int tw = 8;
+  int split = 0;  // multipass: logR - ceil(logN / 2) adjustment
+};
+
+struct Layout {
+  bool resident = false;
+  int logR = 0, logC = 0;
+};
+
+bool is_complex(hk_dtype_t dt);
+size_t elem_bytes(hk_dtype_t dt);      // bytes of one stored element
+size_t cplx_bytes(hk_dtype_t dt);      // bytes of one complex working element
+int ceil_log2(int64_t v);
+
+// Validation (host-side, before any enqueue).
+Status validate_forward(const Problem &p);
+Status validate_backward(const Problem &p);
+
+// Shape construction.  `layout` decides resident vs multipass and the split.
+Status layout_for(const Problem &p, int split, Layout *out);
+Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *sh, Ptrs *ptrs,
+                   int op_src[MAXOPS]);
+
+// Default schedule of a shape (overridden by the autotuner cache).
+Sched default_sched(hk_dtype_t dt, const Layout &lay, int prog, int64_t batch);
+// Clamp a schedule to what the kernels accept for this layout.
+bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc);
+
+// Workspace bytes per instance for a shape (0 for resident).
+size_t instance_ws_bytes(const Shape &sh, hk_dtype_t dt);
+
+// Plain path: enqueue the product(s) of one shape.  ptab (device) holds
+// `count` per-instance pointer sets, or is NULL and instance i uses p0 + i * str.
+Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs &p0, const Strides &str,
+                    const Ptrs *ptab, int64_t count, hipStream_t st);
+
+// Device checks / one-time per-device setup (twiddle tables).
+Status ensure_device();
+
+// Schedule cache (autotuner).
+bool sched_lookup(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint, int64_t batch, Sched *sc);
+void sched_store(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint, int64_t batch, const Sched &sc);
+
+// Thread-local launch counter.
+void count_launch();
+
+}  // namespace hk
