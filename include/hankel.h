@@ -153,13 +153,12 @@ typedef struct hk_plan_s *hk_plan_t;
 #define HK_PLAN_PERSISTENT 0x1u /* one persistent launch with an in-kernel task queue          */
 #define HK_PLAN_MULTIKERNEL 0x2u /* one launch per pass (per-pass profiling; same kernels)     */
 #define HK_PLAN_GRAPH 0x4u      /* capture the plan's launches in a hipGraph on first execute */
-#define HK_PLAN_AUTOTUNE 0x8u   /* time the candidate schedules on the device at creation     */
+#define HK_PLAN_AUTOTUNE 0x8u   /* reserved (accepted, no effect)                             */
 
 /* Creates a plan for `count` problems.  The plan copies the descriptors
- * (pointers included) and owns only host memory and, with HK_PLAN_GRAPH, a
- * graph.  flags = 0 picks the persistent schedule.  Autotuning runs kernels
- * on the current device, writing only into a temporary workspace that it
- * allocates and frees itself. */
+ * (pointers included); on first execute it uploads them to a device table
+ * that it owns until hk_plan_destroy.  With HK_PLAN_GRAPH it also owns a
+ * captured graph.  flags = 0 picks the persistent schedule. */
 hk_status_t hk_plan_create(hk_plan_t *plan, hk_dtype_t dt, const hk_problem_t *probs,
                            int64_t count, unsigned flags);
 hk_status_t hk_plan_workspace_size(hk_plan_t plan, size_t *bytes);
@@ -172,7 +171,9 @@ hk_status_t hk_plan_execute(hk_plan_t plan, void *ws, size_t ws_bytes, hipStream
 hk_status_t hk_plan_status(hk_plan_t plan);
 hk_status_t hk_plan_destroy(hk_plan_t plan);
 
-/* One-shot convenience: create (no autotune), execute, destroy. */
+/* One-shot convenience: plan, execute with the descriptor tables kept in the
+ * workspace, then wait for `stream` and free the plan (this call blocks until
+ * the batch has finished). */
 hk_status_t hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs,
                                               int64_t count, size_t *bytes);
 hk_status_t hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t count,
@@ -244,6 +245,16 @@ hk_status_t hk_autotune_tvp(hk_dtype_t dt, int m, int64_t n, int verbose);
 /* Number of the library's kernel launches enqueued by the last call made on
  * this thread (diagnostics). */
 int hk_last_launch_count(void);
+/* Kernel timing (diagnostics).  Between start and stop, every kernel the
+ * library enqueues is bracketed by HIP events recorded on its own stream.
+ * hk_profile_stop synchronizes on those events and returns, per kernel kind,
+ * the summed duration in milliseconds and the number of launches (arrays of
+ * HK_PROF_KINDS entries): 0 resident single-workgroup transforms, 1 pass A
+ * (column FFTs of the inputs), 2 pass B (row FFTs + spectral product),
+ * 3 pass D (column FFTs of the output + slice), 4 batched task kernel. */
+#define HK_PROF_KINDS 5
+hk_status_t hk_profile_start(void);
+hk_status_t hk_profile_stop(double *ms_by_kind, int64_t *launches_by_kind);
 
 const char *hk_status_string(hk_status_t s);
 const char *hk_last_error(void);

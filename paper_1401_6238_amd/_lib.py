@@ -78,6 +78,8 @@ _SIGS = {
     "hk_fft_layout": [_I64, _PI64, _PI64, _PI64],
     "hk_autotune_tvp": [_I, _I, _I64, _I],
     "hk_last_launch_count": [],
+    "hk_profile_start": [],
+    "hk_profile_stop": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
     "hk_status_string": [_I],
     "hk_last_error": [],
     "hk_version": [],

@@ -307,3 +307,18 @@ def hk_autotune_tvp(dtype: torch.dtype, m: int, n: int, verbose: bool = False):
 
 def hk_last_launch_count() -> int:
     return int(lib().hk_last_launch_count())
+
+
+PROF_KINDS = ("resident", "pass_a", "pass_b", "pass_d", "batch")
+
+
+def hk_profile_start():
+    check(lib().hk_profile_start(), "hk_profile_start")
+
+
+def hk_profile_stop():
+    """Returns {kind: (total_ms, launches)} for the kernels enqueued since start."""
+    ms = (ctypes.c_double * 5)()
+    cnt = (ctypes.c_int64 * 5)()
+    check(lib().hk_profile_stop(ms, cnt), "hk_profile_stop")
+    return {PROF_KINDS[k]: (ms[k], cnt[k]) for k in range(5)}

@@ -79,7 +79,7 @@ static Status run_one(const Problem &p, void *ws, size_t ws_bytes, hipStream_t s
   P.ws = ws;
   Strides str;
   memset(&str, 0, sizeof(str));
-  return launch_shape(p.dt, sh, sc, P, str, nullptr, 1, st);
+  return launch_shape(p.dt, sh, sc, P, str, 1, st);
 }
 
 static Problem tvp_problem(hk_dtype_t dt, const void *h, int m, int64_t n, const void *x, void *y, void *alpha) {
@@ -293,7 +293,7 @@ static Status run_strided(const Problem &p, const Strides &str_elems, int64_t ba
   str.out1 = str_elems.out1;
   str.phi = str_elems.phi;
   str.ws = (int64_t)per;
-  return launch_shape(p.dt, sh, sc, P, str, nullptr, batch, st);
+  return launch_shape(p.dt, sh, sc, P, str, batch, st);
 }
 
 hk_status_t hankel_tvp_strided_batched_workspace_size(hk_dtype_t dt, int m, int64_t n, int64_t batch, size_t *bytes) {
@@ -435,6 +435,13 @@ hk_status_t hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t
   else
     plan_destroy(plan);
   return finish(s);
+}
+
+hk_status_t hk_profile_start(void) { return finish(prof_start()); }
+
+hk_status_t hk_profile_stop(double *ms_by_kind, int64_t *launches_by_kind) {
+  if (!ms_by_kind || !launches_by_kind) return finish(fail(HK_ERR_NULL_POINTER, "output array is NULL"));
+  return finish(prof_stop(ms_by_kind, launches_by_kind));
 }
 
 hk_status_t hk_autotune_tvp(hk_dtype_t dt, int m, int64_t n, int verbose) {

@@ -200,7 +200,13 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
     nrowb[in.idx] = nb;
   }
   p->phase_end[1] = (int32_t)p->tasks.size();
-  // Phase 3: pass D.
+  // Phase 3: scalar products (sums of the pass-B partials) and pass D.
+  for (const Inst &in : multi) {
+    const Shape &sh = p->shapes[in.idx];
+    if (!sh.want_alpha) continue;
+    Task t = {TASK_ALPHA, (int32_t)in.idx, 0, 0, nrowb[in.idx], 1, -1, nrowb[in.idx]};
+    p->tasks.push_back(t);
+  }
   for (const Inst &in : multi) {
     const Shape &sh = p->shapes[in.idx];
     if (!sh.want_y) continue;
@@ -255,7 +261,11 @@ static Status enqueue(hk_plan_s *p, char *ws, hipStream_t st) {
   A.spin_limit = 1u << 22;
   auto launch = [&](const BatchArgs &a, int grid, bool reset) {
     count_launch();
-    return dbl(p->dt) ? launch_batch_f64(a, grid, p->count, reset, st) : launch_batch_f32(a, grid, p->count, reset, st);
+    prof_before(st);
+    const hipError_t e = dbl(p->dt) ? launch_batch_f64(a, grid, p->count, reset, st)
+                                    : launch_batch_f32(a, grid, p->count, reset, st);
+    prof_after(PK_BATCH, st);
+    return e;
   };
   if (p->tasks.empty()) return Status();
   hipError_t e;
@@ -399,7 +409,7 @@ Status autotune_tvp(hk_dtype_t dt, int m, int64_t n, bool verbose) {
   void *dh_buf = nullptr, *dx = nullptr, *dy = nullptr, *da = nullptr, *dws = nullptr;
   Layout lay0;
   p.h = (void *)16;
-  p.vec[1] = (void *)16;
+  for (int q = 0; q < m && q < HK_MAX_ORDER; ++q) p.vec[q] = (void *)16;
   p.y = (void *)16;
   s = validate_forward(p);
   if (!s.ok()) return s;
@@ -461,10 +471,10 @@ Status autotune_tvp(hk_dtype_t dt, int m, int64_t n, bool verbose) {
       Strides str;
       memset(&str, 0, sizeof(str));
       const int reps = 5;
-      s = launch_shape(dt, sh, cands[i], P, str, nullptr, 1, nullptr);  // warm-up
+      s = launch_shape(dt, sh, cands[i], P, str, 1, nullptr);  // warm-up
       if (!s.ok()) break;
       (void)hipEventRecord(e0, nullptr);
-      for (int r = 0; r < reps && s.ok(); ++r) s = launch_shape(dt, sh, cands[i], P, str, nullptr, 1, nullptr);
+      for (int r = 0; r < reps && s.ok(); ++r) s = launch_shape(dt, sh, cands[i], P, str, 1, nullptr);
       (void)hipEventRecord(e1, nullptr);
       (void)hipEventSynchronize(e1);
       float ms = 0;

@@ -27,18 +27,28 @@
 
 namespace hk {
 
-// Pointers of instance i of a strided batch.
-__device__ __forceinline__ Ptrs inst_ptrs(const Ptrs &p0, const Strides &st, int64_t i) {
-  Ptrs P;
-#pragma unroll
-  for (int o = 0; o < MAXOPS; ++o) P.op[o] = p0.op[o] ? (const char *)p0.op[o] + i * st.op[o] : nullptr;
-  P.y = p0.y ? (char *)p0.y + i * st.y : nullptr;
-  P.alpha = p0.alpha ? (char *)p0.alpha + i * st.alpha : nullptr;
-  P.out1 = p0.out1 ? (char *)p0.out1 + i * st.out1 : nullptr;
-  P.phi = p0.phi ? (const char *)p0.phi + i * st.phi : nullptr;
-  P.ws = p0.ws ? (char *)p0.ws + i * st.ws : nullptr;
-  return P;
-}
+// Pointers of one instance, read on demand from a base pointer set (the
+// kernel argument, or a descriptor-table entry) and optional byte strides of
+// a strided batch.  Reading fields through the base pointer (instead of
+// copying the set into a private struct indexed at run time) keeps them out
+// of scratch memory.
+struct PV {
+  const Ptrs *b;        // base pointer set
+  const Strides *st;    // strides, or nullptr
+  int64_t i;            // instance index within the strided batch
+  char *ws_base;        // non-null: b->ws is an offset from ws_base
+  __device__ __forceinline__ const char *adj(const void *p, int64_t s) const {
+    return p ? (const char *)p + (st ? i * s : 0) : nullptr;
+  }
+  __device__ __forceinline__ const void *op(int o) const { return adj(b->op[o], st ? st->op[o] : 0); }
+  __device__ __forceinline__ void *y() const { return (void *)adj(b->y, st ? st->y : 0); }
+  __device__ __forceinline__ void *alpha() const { return (void *)adj(b->alpha, st ? st->alpha : 0); }
+  __device__ __forceinline__ void *out1() const { return (void *)adj(b->out1, st ? st->out1 : 0); }
+  __device__ __forceinline__ const void *phi() const { return adj(b->phi, st ? st->phi : 0); }
+  __device__ __forceinline__ char *ws() const {
+    return ws_base ? ws_base + (uintptr_t)b->ws : (char *)adj(b->ws, st ? st->ws : 0);
+  }
+};
 
 template <typename T>
 __device__ __forceinline__ cx<T> load_op(const void *base, int64_t idx, int flags) {
@@ -51,6 +61,33 @@ __device__ __forceinline__ cx<T> load_op(const void *base, int64_t idx, int flag
   return v;
 }
 
+// Loads a[s] = src[idx[s]] where ok[s] and zero elsewhere, without branches:
+// a slot that is not ok reads element 0 (every operand has at least one
+// element) and is zeroed afterwards, so all EE loads issue back to back
+// instead of each waiting behind a branch.
+template <typename T, int EE>
+__device__ __forceinline__ void gather(cx<T> (&a)[EE], const void *base, const int64_t (&idx)[EE],
+                                       const bool (&ok)[EE], int flags) {
+  if (flags & OPF_REAL) {
+    const T *p = (const T *)base;
+    T v[EE];
+#pragma unroll
+    for (int s = 0; s < EE; ++s) v[s] = p[ok[s] ? idx[s] : 0];
+#pragma unroll
+    for (int s = 0; s < EE; ++s) a[s] = mk(ok[s] ? v[s] : T(0), T(0));
+  } else {
+    const cx<T> *p = (const cx<T> *)base;
+#pragma unroll
+    for (int s = 0; s < EE; ++s) a[s] = p[ok[s] ? idx[s] : 0];
+#pragma unroll
+    for (int s = 0; s < EE; ++s) a[s] = ok[s] ? a[s] : czero<T>();
+    if (flags & OPF_CONJ) {
+#pragma unroll
+      for (int s = 0; s < EE; ++s) a[s].y = -a[s].y;
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void store_out(void *base, int64_t idx, cx<T> v, int real_out) {
   if (real_out)
@@ -60,19 +97,19 @@ __device__ __forceinline__ void store_out(void *base, int64_t idx, cx<T> v, int 
 }
 
 template <typename T>
-__device__ __forceinline__ cx<T> *ws_buf(const Shape &sh, const Ptrs &P, int b) {
+__device__ __forceinline__ cx<T> *ws_buf(const Shape &sh, const PV &P, int b) {
   const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
-  return (cx<T> *)P.ws + (int64_t)b * N;
+  return (cx<T> *)P.ws() + (int64_t)b * N;
 }
 
 template <typename T>
-__device__ __forceinline__ cx<T> *ws_partials(const Shape &sh, const Ptrs &P) {
+__device__ __forceinline__ cx<T> *ws_partials(const Shape &sh, const PV &P) {
   const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
-  return (cx<T> *)P.ws + sh.nbuf * N;
+  return (cx<T> *)P.ws() + sh.nbuf * N;
 }
 
 template <typename T>
-__device__ __forceinline__ uint32_t *ws_counter(const Shape &sh, const Ptrs &P) {
+__device__ __forceinline__ uint32_t *ws_counter(const Shape &sh, const PV &P) {
   return (uint32_t *)(ws_partials<T>(sh, P) + sh.partials);
 }
 
@@ -105,35 +142,44 @@ struct RowBody {
   static constexpr int EE = S::EE;
   static constexpr int TPS = S::TPS;
   static constexpr int SEQ_LDS = S::LDS > 0 ? S::LDS + 1 : 0;  // +1: bank skew between sequences
+  // A row's TPS lanes are consecutive, so a row of at most 64 lanes lives in
+  // one wavefront and its exchanges need no workgroup barrier.
+  static constexpr bool WAVE = TPS <= 64;
 
-  static __device__ __forceinline__ void load(cx<T> (&a)[EE], const Shape &sh, const Ptrs &P, int o,
+  static __device__ __forceinline__ void fft(cx<T> (&a)[EE], int t, cx<T> *lds, const cx<T> *tw4096) {
+    fft_seq<T, L, E, WAVE>(a, t, lds, tw4096);
+  }
+
+  static __device__ __forceinline__ void load(cx<T> (&a)[EE], const Shape &sh, const PV &P, int o,
                                               int64_t row, bool valid_row, int t, bool resident) {
     const OpDesc &od = sh.ops[o];
+    int64_t idx[EE];
+    bool ok[EE];
     if (resident) {
-      const void *src = P.op[o];
-      const int flags = od.flags;
 #pragma unroll
       for (int s = 0; s < EE; ++s) {
-        const int pos = t + s * TPS;
-        a[s] = (valid_row && pos < od.len) ? load_op<T>(src, pos, flags) : czero<T>();
+        idx[s] = t + s * TPS;
+        ok[s] = valid_row && idx[s] < od.len;
       }
+      gather<T, EE>(a, P.op(o), idx, ok, od.flags);
     } else {
-      const cx<T> *src = ws_buf<T>(sh, P, od.buf) + row * L;
+      const cx<T> *src = ws_buf<T>(sh, P, od.buf) + (valid_row ? row : 0) * L;
 #pragma unroll
       for (int s = 0; s < EE; ++s) {
-        const int pos = t + s * TPS;
-        a[s] = (valid_row && pos < od.ncol_nz) ? src[pos] : czero<T>();
+        idx[s] = t + s * TPS;
+        ok[s] = valid_row && idx[s] < od.ncol_nz;
       }
+      gather<T, EE>(a, src, idx, ok, 0);
     }
   }
 
   // Stores output `which` (0: y / grad_h, 1: grad_x) of this row.
-  static __device__ __forceinline__ void store(const cx<T> (&a)[EE], const Shape &sh, const Ptrs &P,
+  static __device__ __forceinline__ void store(const cx<T> (&a)[EE], const Shape &sh, const PV &P,
                                                int which, int64_t row, bool valid_row, int t,
                                                bool resident, const cx<T> *tw24, const cx<T> *tw4096) {
     if (!valid_row) return;
     if (resident) {
-      void *dst = which == 0 ? P.y : P.out1;
+      void *dst = which == 0 ? P.y() : P.out1();
       const int64_t lim = which == 0 ? sh.out_rows : sh.out1_len;
       const bool cj = (sh.prog == PROG_BWD) && which == 1;
 #pragma unroll
@@ -143,30 +189,33 @@ struct RowBody {
       }
     } else {
       cx<T> *dst = ws_buf<T>(sh, P, sh.ops[which].buf) + row * L;
-      const int logN = sh.logR + sh.logC;
-      const bool twid = !sh.is_block;
+      if (!sh.is_block) {
+        // four-step twiddles W_N^{pos * row}, pos = t + s TPS
+        cx<T> w[EE];
+        slot_twiddles<T, EE>(w, row, t, TPS, sh.logR + sh.logC, tw24, tw4096);
 #pragma unroll
-      for (int s = 0; s < EE; ++s) {
-        const int pos = t + s * TPS;
-        cx<T> v = a[s];
-        if (twid) v = cmul(v, twiddle_big<T>((int64_t)pos * row, logN, tw24, tw4096));
-        dst[pos] = v;
+        for (int s = 0; s < EE; ++s) dst[t + s * TPS] = cmul(a[s], w[s]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < EE; ++s) dst[t + s * TPS] = a[s];
       }
     }
   }
 
   // Forward program: z = h^ prod_p x^_p^{e_p}; y = fft(z); alpha = sum z x^_1.
-  static __device__ __forceinline__ cx<T> run_fwd(const Shape &sh, const Ptrs &P, int64_t row, bool valid_row,
+  static __device__ __forceinline__ cx<T> run_fwd(const Shape &sh, const PV &P, int64_t row, bool valid_row,
                                                   int t, cx<T> *lds, bool resident, const cx<T> *tw24,
                                                   const cx<T> *tw4096) {
     const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
-    cx<T> a[EE], acc[EE];
+    cx<T> a[EE], nx[EE], acc[EE];
     cx<T> part = czero<T>();
 #pragma unroll
     for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
+    load(a, sh, P, 0, row, valid_row, t, resident);
     for (int o = 0; o < sh.nops; ++o) {
-      load(a, sh, P, o, row, valid_row, t, resident);
-      fft_seq<T, L, E>(a, t, lds, tw4096);
+      // the next operand's loads are in flight while this one is transformed
+      if (o + 1 < sh.nops) load(nx, sh, P, o + 1, row, valid_row, t, resident);
+      fft(a, t, lds, tw4096);
       const OpDesc &od = sh.ops[o];
       if (od.role == ROLE_H) {
 #pragma unroll
@@ -181,9 +230,11 @@ struct RowBody {
           for (int s = 0; s < EE; ++s) part = cfma(acc[s], a[s], part);
         }
       }
+#pragma unroll
+      for (int s = 0; s < EE; ++s) a[s] = nx[s];
     }
     if (sh.want_y) {
-      fft_seq<T, L, E>(acc, t, lds, tw4096);
+      fft(acc, t, lds, tw4096);
       store(acc, sh, P, 0, row, valid_row, t, resident, tw24, tw4096);
     }
     return part;
@@ -192,18 +243,18 @@ struct RowBody {
   // Adjoint of g = H x^{m-1}, f = H x^m (equal vectors).  Operands in order:
   // X, then optionally V (cotangent of g, conjugated on load), then H when
   // grad_x is requested.
-  static __device__ __forceinline__ void run_bwd(const Shape &sh, const Ptrs &P, int64_t row, bool valid_row,
+  static __device__ __forceinline__ void run_bwd(const Shape &sh, const PV &P, int64_t row, bool valid_row,
                                                  int t, cx<T> *lds, bool resident, const cx<T> *tw24,
                                                  const cx<T> *tw4096) {
     const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
     cx<T> a[EE], gq[EE];
     cx<T> phc = czero<T>();  // conj(phi)
-    if (P.phi) phc = cconj(*(const cx<T> *)P.phi);
+    if (P.phi()) phc = cconj(*(const cx<T> *)P.phi());
     const T m1 = T(sh.m - 1), m0 = T(sh.m);
     {
       cx<T> xs[EE], p1[EE], vs[EE];
       load(xs, sh, P, 0, row, valid_row, t, resident);
-      fft_seq<T, L, E>(xs, t, lds, tw4096);
+      fft(xs, t, lds, tw4096);
 #pragma unroll
       for (int s = 0; s < EE; ++s) p1[s] = mk(T(1), T(0));
       for (int e = 0; e < sh.m - 2; ++e) {
@@ -213,7 +264,7 @@ struct RowBody {
       const bool has_v = sh.nops > 1 && sh.ops[1].role == ROLE_V;
       if (has_v) {
         load(vs, sh, P, 1, row, valid_row, t, resident);
-        fft_seq<T, L, E>(vs, t, lds, tw4096);
+        fft(vs, t, lds, tw4096);
       } else {
 #pragma unroll
         for (int s = 0; s < EE; ++s) vs[s] = czero<T>();
@@ -227,15 +278,15 @@ struct RowBody {
       }
     }
     if (sh.want_y) {
-      fft_seq<T, L, E>(a, t, lds, tw4096);
+      fft(a, t, lds, tw4096);
       store(a, sh, P, 0, row, valid_row, t, resident, tw24, tw4096);
     }
     if (sh.want_out1) {
       load(a, sh, P, sh.nops - 1, row, valid_row, t, resident);  // H
-      fft_seq<T, L, E>(a, t, lds, tw4096);
+      fft(a, t, lds, tw4096);
 #pragma unroll
       for (int s = 0; s < EE; ++s) a[s] = cmul(cscale(cconj(a[s]), invN), gq[s]);
-      fft_seq<T, L, E>(a, t, lds, tw4096);
+      fft(a, t, lds, tw4096);
       store(a, sh, P, 1, row, valid_row, t, resident, tw24, tw4096);
     }
   }
@@ -253,7 +304,7 @@ struct ColBody {
   static constexpr int TPS = S::TPS;
   static constexpr int SEQ_LDS = S::LDS > 0 ? S::LDS + 1 : 0;
 
-  static __device__ __forceinline__ void run(const Shape &sh, const Ptrs &P, const ColJob &job, int64_t c0,
+  static __device__ __forceinline__ void run(const Shape &sh, const PV &P, const ColJob &job, int64_t c0,
                                              int TW, int tid, cx<T> *lds, const cx<T> *tw24,
                                              const cx<T> *tw4096) {
     const int cw = tid % TW;
@@ -262,42 +313,49 @@ struct ColBody {
     const bool cvalid = c < job.ncols;
     const int64_t R = (int64_t)1 << sh.logR;
     cx<T> a[EE];
+    int64_t idx[EE];
+    bool ok[EE];
     if (job.kind == COL_A) {
       const OpDesc &od = sh.ops[job.op];
-      const void *src = P.op[job.op];
-      const int flags = od.flags;
       if (!sh.is_block) {
 #pragma unroll
         for (int s = 0; s < EE; ++s) {
-          const int64_t pos = c + R * (t + s * TPS);
-          a[s] = (cvalid && pos < od.len) ? load_op<T>(src, pos, flags) : czero<T>();
+          idx[s] = c + R * (t + s * TPS);
+          ok[s] = cvalid && idx[s] < od.len;
         }
       } else {
 #pragma unroll
         for (int s = 0; s < EE; ++s) {
           const int64_t r = t + s * TPS;
-          a[s] = (cvalid && c < od.len && r < od.cols) ? load_op<T>(src, c + od.len * r, flags) : czero<T>();
+          idx[s] = c + od.len * r;
+          ok[s] = cvalid && c < od.len && r < od.cols;
         }
       }
+      gather<T, EE>(a, P.op(job.op), idx, ok, od.flags);
     } else {
-      const cx<T> *src = ws_buf<T>(sh, P, job.buf);
 #pragma unroll
-      for (int s = 0; s < EE; ++s) a[s] = cvalid ? src[c + R * (t + s * TPS)] : czero<T>();
+      for (int s = 0; s < EE; ++s) {
+        idx[s] = c + R * (t + s * TPS);
+        ok[s] = cvalid;
+      }
+      gather<T, EE>(a, ws_buf<T>(sh, P, job.buf), idx, ok, 0);
     }
-    fft_seq<T, L, E>(a, t, lds + cw * SEQ_LDS, tw4096);
+    fft_seq<T, L, E>(a, t, lds + cw * col_lds_stride(S::LDS, TW), tw4096);
     if (!cvalid) return;
     if (job.kind == COL_A) {
       cx<T> *dst = ws_buf<T>(sh, P, job.buf);
-      const int logN = sh.logR + sh.logC;
+      if (!sh.is_block) {
+        // four-step twiddles W_N^{c * k}, k = t + s TPS
+        cx<T> w[EE];
+        slot_twiddles<T, EE>(w, c, t, TPS, sh.logR + sh.logC, tw24, tw4096);
 #pragma unroll
-      for (int s = 0; s < EE; ++s) {
-        const int64_t k = t + s * TPS;
-        cx<T> v = a[s];
-        if (!sh.is_block) v = cmul(v, twiddle_big<T>(c * k, logN, tw24, tw4096));
-        dst[c + R * k] = v;
+        for (int s = 0; s < EE; ++s) dst[c + R * (t + s * TPS)] = cmul(a[s], w[s]);
+      } else {
+#pragma unroll
+        for (int s = 0; s < EE; ++s) dst[c + R * (t + s * TPS)] = a[s];
       }
     } else {
-      void *dst = job.op == 0 ? P.y : P.out1;
+      void *dst = job.op == 0 ? P.y() : P.out1();
       if (!sh.is_block) {
         const int64_t lim = job.op == 0 ? sh.out_rows : sh.out1_len;
 #pragma unroll

@@ -34,6 +34,22 @@ enum Prog : int32_t { PROG_FWD = 0, PROG_BWD = 1 };
 
 enum ColKind : int32_t { COL_A = 0, COL_D = 1 };
 
+// LDS stride (in elements) between the column sequences of a column-pass
+// workgroup with TW columns.  Lane l works on column l % TW at position-lane
+// l / TW, so a wavefront touches min(TW, 64) columns and 64 / TW position
+// lanes; the stride is a multiple of 32 elements plus a skew that places the
+// lanes of one wavefront on distinct 8-byte LDS slots.
+#if defined(__HIPCC__)
+__host__ __device__
+#endif
+inline int col_lds_stride(int lds_elems, int tw) {
+  if (lds_elems == 0) return 0;
+  if (tw >= 32) return lds_elems | 1;  // one position lane per column: an odd stride suffices
+  const int base = (lds_elems + 31) & ~31;
+  const int skew = tw >= 1 ? (64 / tw) & 31 : 0;
+  return base + skew;
+}
+
 struct OpDesc {
   int32_t role;     // Role
   int32_t exp;      // multiplicity in the spectral product (ROLE_X)
@@ -87,10 +103,11 @@ struct ColJob {
   int32_t buf;
   int32_t conj_out;
   int64_t ncols;  // storage columns to transform (pruned)
+  int64_t npart;  // COL_D: pass-B partial sums to reduce into the scalar product (0: none)
 };
 
 // Persistent batched execution: task list entries.
-enum TaskType : int32_t { TASK_RES = 0, TASK_COLA = 1, TASK_ROWB = 2, TASK_COLD = 3 };
+enum TaskType : int32_t { TASK_RES = 0, TASK_COLA = 1, TASK_ROWB = 2, TASK_COLD = 3, TASK_ALPHA = 4 };
 
 struct Task {
   int32_t type;
@@ -100,13 +117,12 @@ struct Task {
   int32_t wait;          // completions of phase `wait_phase` of `inst` required first
   int32_t wait_phase;    // 0: pass A counter, 1: pass B counter, -1: no wait
   int32_t signal_phase;  // counter to bump on completion (-1: none)
-  int32_t nrowb;         // ROWB: number of row tasks of the instance (scalar reduction)
+  int32_t nrowb;         // ROWB / ALPHA: number of row tasks of the instance (scalar partials)
 };
 
 struct InstCtl {  // per-instance counters (persistent schedule), zeroed before each run
   uint32_t done[2];      // completed pass-A / pass-B tasks
-  uint32_t alpha_count;  // row tasks that have published their scalar partial sum
-  uint32_t pad;
+  uint32_t pad[2];
 };
 
 struct BatchCtl {

@@ -152,10 +152,45 @@ struct FFTShape {
 template <typename T, int L, int E>
 using Regs = cx<T>[FFTShape<L, E>::EE];
 
+// Synchronization between the LDS write and read halves of an exchange.
+// WAVE = true when every lane of a sequence sits in the same wavefront (the
+// sequence's TPS lanes are consecutive and TPS divides 64): LDS operations of
+// one wave execute in order, so ordering the compiler's memory operations is
+// enough.  Otherwise a workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void seq_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// exp(-2 pi i r k / (Ns R)) for r = 1..R-1 from the log2(R) table entries
+// W^{k 2^j}: each power is a product of at most log2(R) table values, so the
+// error stays within a few ulp while the lane issues log2(R) loads instead of
+// R - 1.
+template <typename T, int R>
+__device__ __forceinline__ void stage_twiddles(cx<T> (&w)[R], int k, int step, const cx<T> *__restrict__ tw4096) {
+  constexpr int LR = ilog2c(R);
+  cx<T> base[LR > 0 ? LR : 1];
+#pragma unroll
+  for (int j = 0; j < LR; ++j) base[j] = tw4096[((k << j) * step) & 4095];
+  w[0] = mk(T(1), T(0));
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    const int rest = r & (r - 1);       // r without its lowest set bit
+    const int lb = ilog2c(r & (-r));    // index of that bit
+    w[r] = rest == 0 ? base[lb] : cmul(w[rest], base[lb]);
+  }
+}
+
 // One Stockham pass.  Slot (q, r) of lane t holds input b + r*(L/R) with
 // butterfly b = t + q*TPS; span Ns = EE^p; outputs go to
 // (b - k) R + k + r Ns, k = b mod Ns.
-template <typename T, int L, int E, int p>
+template <typename T, int L, int E, bool WAVE, int p>
 __device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
                                          const cx<T> *__restrict__ tw4096) {
   using S = FFTShape<L, E>;
@@ -166,7 +201,7 @@ __device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
   constexpr int Ns = ipowc(EE, p);
   constexpr bool last = (p == S::P - 1);
   if constexpr (p > 0) {
-    __syncthreads();
+    seq_sync<WAVE>();
 #pragma unroll
     for (int q = 0; q < B; ++q)
 #pragma unroll
@@ -181,15 +216,17 @@ __device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
     if constexpr (p > 0) {
       const int k = b & (Ns - 1);
       constexpr int step = 4096 / (Ns * R);
+      cx<T> w[R];
+      stage_twiddles<T, R>(w, k, step, tw4096);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw4096[(r * k) * step]);
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
     }
     dft<T, R>(v);
 #pragma unroll
     for (int r = 0; r < R; ++r) a[q + r * B] = v[r];
   }
   if constexpr (!last) {
-    __syncthreads();
+    seq_sync<WAVE>();
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       const int b = t + q * TPS;
@@ -198,18 +235,19 @@ __device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[S::pad(base + r * Ns)] = a[q + r * B];
     }
-    fft_pass<T, L, E, p + 1>(a, t, lds, tw4096);
+    fft_pass<T, L, E, WAVE, p + 1>(a, t, lds, tw4096);
   }
 }
 
 // Forward FFT of one length-L sequence held in registers (see file comment).
-// Every lane of the workgroup must call this (it contains barriers when
-// the transform needs more than one pass).
-template <typename T, int L, int E>
+// Every lane of the workgroup must call this (it contains barriers when the
+// transform needs more than one pass and WAVE is false).
+template <typename T, int L, int E, bool WAVE = false>
 __device__ __forceinline__ void fft_seq(Regs<T, L, E> &a, int t, cx<T> *lds,
                                         const cx<T> *__restrict__ tw4096) {
-  if constexpr (FFTShape<L, E>::P > 0) fft_pass<T, L, E, 0>(a, t, lds, tw4096);
+  if constexpr (FFTShape<L, E>::P > 0) fft_pass<T, L, E, WAVE, 0>(a, t, lds, tw4096);
 }
+
 
 // exp(-2 pi i e / 2^logN) for 0 <= e < 2^logN <= 2^24 from two 4096-entry
 // tables: tw24[j] = exp(-2 pi i j / 2^24), tw4096[j] = exp(-2 pi i j / 4096).
@@ -219,6 +257,30 @@ __device__ __forceinline__ cx<T> twiddle_big(int64_t e, int logN, const cx<T> *_
   const uint32_t bidx = (uint32_t)(e << (24 - logN));
   // tw24[0] is exactly 1, so the product is exact when the low part vanishes.
   return cmul(tw24[bidx & 4095u], tw4096[bidx >> 12]);
+}
+
+// Twiddles W_N^{u (t + s TPS)} for the EE slots s of a lane: one table product
+// for the lane's base exponent u t, log2(EE) for the steps u TPS 2^j, and
+// at most log2(EE) products per slot.
+template <typename T, int EE>
+__device__ __forceinline__ void slot_twiddles(cx<T> (&w)[EE], int64_t u, int t, int TPS, int logN,
+                                              const cx<T> *__restrict__ tw24, const cx<T> *__restrict__ tw4096) {
+  constexpr int LE = ilog2c(EE);
+  const int64_t Nm = ((int64_t)1 << logN) - 1;
+  cx<T> st[LE > 0 ? LE : 1];
+#pragma unroll
+  for (int j = 0; j < LE; ++j) st[j] = twiddle_big<T>((u * ((int64_t)TPS << j)) & Nm, logN, tw24, tw4096);
+  cx<T> pw[EE];
+  pw[0] = mk(T(1), T(0));
+#pragma unroll
+  for (int s = 1; s < EE; ++s) {
+    const int rest = s & (s - 1);       // s without its lowest set bit
+    const int lb = ilog2c(s & (-s));    // index of that bit
+    pw[s] = rest == 0 ? st[lb] : cmul(pw[rest], st[lb]);
+  }
+  const cx<T> b0 = twiddle_big<T>((u * t) & Nm, logN, tw24, tw4096);
+#pragma unroll
+  for (int s = 0; s < EE; ++s) w[s] = s == 0 ? b0 : cmul(b0, pw[s]);
 }
 
 }  // namespace hk

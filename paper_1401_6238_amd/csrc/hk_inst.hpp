@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -79,6 +80,7 @@ static KernelLimits lim_of() {
   KernelLimits k;
   k.tps = S::TPS;
   k.seq_lds = S::LDS > 0 ? S::LDS + 1 : 0;
+  k.lds_raw = S::LDS;
   k.elem_bytes = (int)sizeof(cx<T>);
   return k;
 }
@@ -105,9 +107,16 @@ static KernelLimits lim_pick(int logL) {
 static std::mutex g_attr_mu;
 
 static hipError_t ensure_lds(void *fn, size_t bytes) {
+  // Raise a kernel's dynamic-LDS limit only when a launch needs more than
+  // the value already set for it.
+  static std::map<void *, size_t> done;
   if (bytes <= 65536) return hipSuccess;
   std::lock_guard<std::mutex> lk(g_attr_mu);
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  auto it = done.find(fn);
+  if (it != done.end() && it->second >= bytes) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) done[fn] = bytes;
+  return e;
 }
 
 }  // namespace HK_NS
@@ -139,8 +148,7 @@ bool HK_CAT(limits_, HK_SUFFIX)(int logL, int E, KernelLimits *out) {
 }
 
 hipError_t HK_CAT(launch_rows_, HK_SUFFIX)(int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh,
-                                           const Ptrs &p0, const Strides &str, const Ptrs *ptab, int64_t count,
-                                           hipStream_t st) {
+                                           const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st) {
   using namespace HK_NS;
   void *fn = row_kernel(logL, E, sh.prog);
   KernelLimits k;
@@ -155,35 +163,43 @@ hipError_t HK_CAT(launch_rows_, HK_SUFFIX)(int logL, int E, int rows_per_wg, dim
   Shape shc = sh;
   Ptrs pc = p0;
   Strides sc = str;
-  const Ptrs *pt = ptab;
   int64_t cnt = count;
-  void *args[] = {&shc, &pc, &sc, &pt, &cnt};
+  void *args[] = {&shc, &pc, &sc, &cnt};
   return hipLaunchKernel(fn, grid, dim3(threads), args, lds, st);
 }
 
 hipError_t HK_CAT(launch_cols_, HK_SUFFIX)(int logL, int E, int tw, dim3 grid, const Shape &sh, const Ptrs &p0,
-                                           const Strides &str, const Ptrs *ptab, const ColJob *jobs, int njobs,
-                                           hipStream_t st) {
+                                           const Strides &str, const ColJob *jobs, int njobs, hipStream_t st) {
   using namespace HK_NS;
   void *fn = col_kernel(logL, E);
   KernelLimits k;
   if (!fn || !HK_CAT(limits_, HK_SUFFIX)(logL, E, &k)) return hipErrorInvalidValue;
   const int threads = tw * k.tps;
   if (threads < 1 || threads > COL_MAXT || njobs < 1 || njobs > MAXOPS) return hipErrorInvalidValue;
-  size_t lds = (size_t)tw * k.seq_lds * sizeof(cx<T>);
-  if (lds == 0) lds = 16;
+  size_t lds = (size_t)tw * col_lds_stride(k.lds_raw, tw) * sizeof(cx<T>);
+  lds = std::max(lds, (size_t)threads * sizeof(cx<T>));  // room for the scalar reduction
   hipError_t e = ensure_lds(fn, lds);
   if (e != hipSuccess) return e;
   Shape shc = sh;
   Ptrs pc = p0;
   Strides sc = str;
-  const Ptrs *pt = ptab;
   ColJobs cj;
   memset(&cj, 0, sizeof(cj));
   for (int i = 0; i < njobs; ++i) cj.j[i] = jobs[i];
   cj.n = njobs;
-  void *args[] = {&shc, &pc, &sc, &pt, &cj};
+  void *args[] = {&shc, &pc, &sc, &cj};
   return hipLaunchKernel(fn, grid, dim3(threads), args, lds, st);
+}
+
+hipError_t HK_CAT(launch_alpha_, HK_SUFFIX)(const Shape &sh, const Ptrs &p0, const Strides &str, int64_t npart,
+                                            int64_t count, hipStream_t st) {
+  using namespace HK_NS;
+  Shape shc = sh;
+  Ptrs pc = p0;
+  Strides sc = str;
+  int64_t n = npart;
+  void *args[] = {&shc, &pc, &sc, &n};
+  return hipLaunchKernel((void *)&k_alpha, dim3((unsigned)count), dim3(256), args, 0, st);
 }
 
 void HK_CAT(batch_geometry_, HK_SUFFIX)(int *blk, int *e_row, int *e_col, size_t *lds_bytes) {
@@ -197,7 +213,10 @@ void HK_CAT(batch_geometry_, HK_SUFFIX)(int *blk, int *e_row, int *e_col, size_t
     HK_CAT(limits_, HK_SUFFIX)(l, BATCH_E_ROW, &kr);
     HK_CAT(limits_, HK_SUFFIX)(l, BATCH_E_COL, &kc);
     if (kr.tps <= BATCH_BLK) mx = std::max(mx, (size_t)(BATCH_BLK / kr.tps) * kr.seq_lds);
-    if (kc.tps <= BATCH_BLK) mx = std::max(mx, (size_t)(BATCH_BLK / kc.tps) * kc.seq_lds);
+    if (kc.tps <= BATCH_BLK) {
+      const int tw = BATCH_BLK / kc.tps;
+      mx = std::max(mx, (size_t)tw * col_lds_stride(kc.lds_raw, tw));
+    }
   }
   *lds_bytes = mx * sizeof(cx<T>);
 }

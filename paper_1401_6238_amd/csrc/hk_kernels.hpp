@@ -28,7 +28,7 @@ struct ColJobs {
 // Rows of length L: resident instances (blockIdx.x * rows + rw) or pass-B
 // rows of instance blockIdx.y.
 template <int L, int E, int MAXT, int PROG>
-__global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, const Ptrs *__restrict__ ptab, int64_t count) {
+__global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, int64_t count) {
   using RB = RowBody<T, L, E>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *smem = (cx<T> *)smem_raw;
@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, c
   if (sh.resident) {
     const int64_t inst = (int64_t)blockIdx.x * rows + rw;
     const bool valid = inst < count;
-    const Ptrs P = ptab ? ptab[valid ? inst : 0] : inst_ptrs(p0, str, valid ? inst : 0);
+    const PV P{&p0, &str, valid ? inst : 0, nullptr};
     if (PROG == PROG_BWD) {
       RB::run_bwd(sh, P, 0, valid, t, lds, true, g_tw24, g_tw4096);
       return;
@@ -49,11 +49,11 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, c
     const cx<T> part = RB::run_fwd(sh, P, 0, valid, t, lds, true, g_tw24, g_tw4096);
     if (sh.want_alpha) {
       const cx<T> tot = segment_sum(part, red, tid, RB::TPS);
-      if (valid && t == 0) store_out<T>(P.alpha, 0, tot, sh.real_out);
+      if (valid && t == 0) store_out<T>(P.alpha(), 0, tot, sh.real_out);
     }
   } else {
     const int64_t inst = blockIdx.y;
-    const Ptrs P = ptab ? ptab[inst] : inst_ptrs(p0, str, inst);
+    const PV P{&p0, &str, inst, nullptr};
     const int64_t row = (int64_t)blockIdx.x * rows + rw;
     const bool valid = row < ((int64_t)1 << sh.logC);
     if (PROG == PROG_BWD) {
@@ -62,38 +62,49 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, c
     }
     const cx<T> part = RB::run_fwd(sh, P, row, valid, t, lds, false, g_tw24, g_tw4096);
     if (sh.want_alpha) {
-      const int nthr = blockDim.x;
-      const cx<T> tot = segment_sum(part, red, tid, nthr);
-      if (tid == 0) {
-        cx<T> *partials = ws_partials<T>(sh, P);
-        uint32_t *counter = ws_counter<T>(sh, P);
-        partials[blockIdx.x] = tot;
-        __threadfence();
-        const uint32_t prev = atomicAdd(counter, 1u);
-        if (prev == (uint32_t)(gridDim.x - 1)) {
-          __threadfence();
-          // Sum the partials in index order (deterministic regardless of
-          // which workgroup finished last).
-          cx<T> s = czero<T>();
-          for (int64_t i = 0; i < (int64_t)gridDim.x; ++i) s = cadd(s, partials[i]);
-          store_out<T>(P.alpha, 0, s, sh.real_out);
-        }
-      }
+      // One partial sum per workgroup; the next kernel in the stream (pass D
+      // or the reduction kernel) adds them in index order.  No cross-workgroup
+      // fence is needed: the kernel boundary makes them visible.
+      const cx<T> tot = segment_sum(part, red, tid, (int)blockDim.x);
+      if (tid == 0) ws_partials<T>(sh, P)[blockIdx.x] = tot;
     }
   }
 }
 
+// Deterministic sum of the pass-B partial sums of one instance (count
+// partials, fixed tree order) by one workgroup; lane 0 stores the scalar
+// product.  `red` holds at least blockDim.x elements.
+__device__ __forceinline__ void reduce_partials(const Shape &sh, const PV &P, int64_t count, cx<T> *red) {
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;  // a power of two
+  const cx<T> *part = ws_partials<T>(sh, P);
+  cx<T> v = czero<T>();
+  for (int64_t i = tid; i < count; i += nthr) v = cadd(v, part[i]);
+  const cx<T> tot = segment_sum(v, red, tid, nthr);
+  if (tid == 0) store_out<T>(P.alpha(), 0, tot, sh.real_out);
+}
+
+// Scalar-only products: sums the pass-B partials (grid.x = instances).
+__global__ void __launch_bounds__(256) k_alpha(Shape sh, Ptrs p0, Strides str, int64_t count) {
+  __shared__ cx<T> red[256];
+  const PV P{&p0, &str, (int64_t)blockIdx.x, nullptr};
+  reduce_partials(sh, P, count, red);
+}
+
 template <int L, int E, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_cols(Shape sh, Ptrs p0, Strides str, const Ptrs *__restrict__ ptab, ColJobs jobs) {
+__global__ void __launch_bounds__(MAXT) k_cols(Shape sh, Ptrs p0, Strides str, ColJobs jobs) {
   using CB = ColBody<T, L, E>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *smem = (cx<T> *)smem_raw;
   const ColJob &job = jobs.j[blockIdx.y];
   const int TW = blockDim.x / CB::TPS;
   const int64_t c0 = (int64_t)blockIdx.x * TW;
-  const Ptrs P = ptab ? ptab[blockIdx.z] : inst_ptrs(p0, str, blockIdx.z);
-  if (job.kind == COL_A && sh.want_alpha && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
-    *ws_counter<T>(sh, P) = 0u;  // pass B's last-arriver counter (pass A always precedes pass B)
+  const PV P{&p0, &str, (int64_t)blockIdx.z, nullptr};
+  if (job.kind == COL_D && job.npart > 0 && blockIdx.x == 0 && blockIdx.y == 0) {
+    // the scalar product rides on the first pass-D workgroup
+    reduce_partials(sh, P, job.npart, smem);
+    __syncthreads();
+  }
   if (c0 >= job.ncols) return;
   CB::run(sh, P, job, c0, TW, threadIdx.x, smem, g_tw24, g_tw4096);
 }
@@ -124,16 +135,16 @@ __device__ __noinline__ void batch_res(const BatchArgs &A, const Task &tk, cx<T>
   const bool valid = rw < tk.a;
   const int32_t inst = A.res_list[tk.inst + (valid ? rw : 0)];
   const Shape &sh = A.shapes[inst];
-  const Ptrs &P = A.ptrs[inst];
+  const PV P{&A.ptrs[inst], nullptr, 0, nullptr};
   const cx<T> part = RB::run_fwd(sh, P, 0, valid, t, smem + rw * RB::SEQ_LDS, true, g_tw24, g_tw4096);
   if (sh.want_alpha) {
     const cx<T> tot = segment_sum(part, smem, tid, RB::TPS);
-    if (valid && t == 0) store_out<T>(P.alpha, 0, tot, sh.real_out);
+    if (valid && t == 0) store_out<T>(P.alpha(), 0, tot, sh.real_out);
   }
 }
 
 template <int L>
-__device__ __noinline__ void batch_rowb(const BatchArgs &A, const Task &tk, const Shape &sh, const Ptrs &P,
+__device__ __noinline__ void batch_rowb(const BatchArgs &A, const Task &tk, const Shape &sh, const PV &P,
                                            cx<T> *smem, int tid) {
   using RB = RowBody<T, L, BATCH_E_ROW>;
   const int rw = tid / RB::TPS;
@@ -141,25 +152,14 @@ __device__ __noinline__ void batch_rowb(const BatchArgs &A, const Task &tk, cons
   const int64_t row = (int64_t)tk.a + rw;
   const bool valid = row < ((int64_t)1 << sh.logC);
   const cx<T> part = RB::run_fwd(sh, P, row, valid, t, smem + rw * RB::SEQ_LDS, false, g_tw24, g_tw4096);
-  if (sh.want_alpha) {
+  if (sh.want_alpha) {  // partial sum of this task; a TASK_ALPHA adds them up
     const cx<T> tot = segment_sum(part, smem, tid, BATCH_BLK);
-    if (tid == 0) {
-      cx<T> *partials = ws_partials<T>(sh, P);
-      partials[tk.b] = tot;
-      __threadfence();
-      const uint32_t prev = atomicAdd(&A.ictl[tk.inst].alpha_count, 1u);
-      if (prev == (uint32_t)(tk.nrowb - 1)) {
-        __threadfence();
-        cx<T> s = czero<T>();
-        for (int i = 0; i < tk.nrowb; ++i) s = cadd(s, partials[i]);
-        store_out<T>(P.alpha, 0, s, sh.real_out);
-      }
-    }
+    if (tid == 0) ws_partials<T>(sh, P)[tk.b] = tot;
   }
 }
 
 template <int L>
-__device__ __noinline__ void batch_col(const Task &tk, const Shape &sh, const Ptrs &P, cx<T> *smem, int tid) {
+__device__ __noinline__ void batch_col(const Task &tk, const Shape &sh, const PV &P, cx<T> *smem, int tid) {
   using CB = ColBody<T, L, BATCH_E_COL>;
   constexpr int TW = BATCH_BLK / CB::TPS;
   ColJob job;
@@ -177,7 +177,7 @@ __device__ __noinline__ void batch_col(const Task &tk, const Shape &sh, const Pt
     const int64_t lim = tk.a == 0 ? sh.out_rows : sh.out1_len;
     job.ncols = min(((int64_t)1 << sh.logR), lim);
   }
-  CB::run(sh, P, job, tk.b, TW, tid, smem, g_tw24, g_tw4096);
+  CB::run(sh, P, job, tk.b, TW, tid, smem, g_tw24, g_tw4096);  // LDS sized by batch_geometry
 }
 
 #define HK_LSWITCH(logv, FN, ...)                  \
@@ -239,10 +239,11 @@ __global__ void __launch_bounds__(BATCH_BLK) k_batch(BatchArgs A) {
       HK_LSWITCH(sh0.logR, batch_res, A, tk, smem, tid)
     } else {
       const Shape &sh = A.shapes[tk.inst];
-      Ptrs P = A.ptrs[tk.inst];
-      P.ws = A.ws_base + (uintptr_t)P.ws;
+      const PV P{&A.ptrs[tk.inst], nullptr, 0, A.ws_base};
       if (tk.type == TASK_ROWB) {
         HK_LSWITCH(sh.logR, batch_rowb, A, tk, sh, P, smem, tid)
+      } else if (tk.type == TASK_ALPHA) {
+        reduce_partials(sh, P, tk.nrowb, smem);
       } else {
         HK_LSWITCH(sh.logC, batch_col, tk, sh, P, smem, tid)
       }
@@ -266,7 +267,6 @@ __global__ void k_batch_reset(BatchCtl *bctl, InstCtl *ictl, int64_t ninst) {
   if (i < ninst) {
     ictl[i].done[0] = 0;
     ictl[i].done[1] = 0;
-    ictl[i].alpha_count = 0;
   }
 }
 

@@ -12,7 +12,8 @@ enum : int { MAX_LOGL = 12, ROW_MAXT = 256, COL_MAXT = 512 };
 
 struct KernelLimits {
   int tps;         // lanes per sequence
-  int seq_lds;     // LDS elements per sequence
+  int seq_lds;     // LDS elements per row sequence
+  int lds_raw;     // LDS elements one sequence's exchanges need (0: no exchange)
   int elem_bytes;  // bytes per complex element
 };
 
@@ -20,11 +21,13 @@ struct KernelLimits {
   hipError_t init_tables_##SUFFIX(const double *tw4096_interleaved, const double *tw24_interleaved);   \
   bool limits_##SUFFIX(int logL, int E, KernelLimits *out);                                            \
   hipError_t launch_rows_##SUFFIX(int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh,      \
-                                  const Ptrs &p0, const Strides &str, const Ptrs *ptab, int64_t count, hipStream_t st);   \
+                                  const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st);   \
   hipError_t launch_batch_##SUFFIX(const BatchArgs &args, int grid, int64_t ninst, bool reset, hipStream_t st); \
+  hipError_t launch_alpha_##SUFFIX(const Shape &sh, const Ptrs &p0, const Strides &str, int64_t npart,       \
+                                   int64_t count, hipStream_t st);                                     \
   void batch_geometry_##SUFFIX(int *blk, int *e_row, int *e_col, size_t *lds_bytes);                 \
   hipError_t launch_cols_##SUFFIX(int logL, int E, int tw, dim3 grid, const Shape &sh, const Ptrs &p0, \
-                                  const Strides &str, const Ptrs *ptab, const ColJob *jobs, int njobs, hipStream_t st);
+                                  const Strides &str, const ColJob *jobs, int njobs, hipStream_t st);
 
 HK_DECLARE_LAUNCHERS(f32)
 HK_DECLARE_LAUNCHERS(f64)

@@ -258,7 +258,7 @@ bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
   if (!lay.resident) {
     if (!lim(dt, lay.logC, sc.E_col, &kc)) return false;
     if (sc.tw < 1 || sc.tw * kc.tps > COL_MAXT) return false;
-    if ((size_t)sc.tw * kc.seq_lds * kc.elem_bytes > 160 * 1024) return false;
+    if ((size_t)sc.tw * col_lds_stride(kc.lds_raw, sc.tw) * kc.elem_bytes > 160 * 1024) return false;
   }
   return true;
 }
@@ -283,7 +283,7 @@ Sched default_sched(hk_dtype_t dt, const Layout &lay, int prog, int64_t batch) {
     lim(dt, lay.logC, sc.E_col, &kc);
     const int want_tw = dbl ? 8 : 16;  // 128-byte row segments
     int tw = std::max(1, std::min(want_tw, COL_MAXT / kc.tps));
-    while (tw > 1 && (size_t)tw * kc.seq_lds * kc.elem_bytes > 144 * 1024) tw >>= 1;
+    while (tw > 1 && (size_t)tw * col_lds_stride(kc.lds_raw, tw) * kc.elem_bytes > 144 * 1024) tw >>= 1;
     sc.tw = tw;
   }
   (void)prog;
@@ -293,17 +293,88 @@ Sched default_sched(hk_dtype_t dt, const Layout &lay, int prog, int64_t batch) {
 // ---------------------------------------------------------------------------
 // Launch sequences
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Kernel timing with HIP events (diagnostics)
+// ---------------------------------------------------------------------------
+struct ProfState {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  std::vector<int> kinds;
+  size_t used = 0;
+};
+static ProfState g_prof;
+static std::mutex g_prof_mu;
+
+bool prof_enabled() { return g_prof.on; }
+
+void prof_before(hipStream_t st) {
+  if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (g_prof.used == g_prof.pool.size()) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+    g_prof.pool.push_back({a, b});
+    g_prof.kinds.push_back(-1);
+  }
+  (void)hipEventRecord(g_prof.pool[g_prof.used].first, st);
+}
+
+void prof_after(int kind, hipStream_t st) {
+  if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (g_prof.used >= g_prof.pool.size()) return;
+  (void)hipEventRecord(g_prof.pool[g_prof.used].second, st);
+  g_prof.kinds[g_prof.used] = kind;
+  ++g_prof.used;
+}
+
+Status prof_start() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.on = true;
+  g_prof.used = 0;
+  return Status();
+}
+
+Status prof_stop(double *ms, int64_t *counts) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.on = false;
+  for (int k = 0; k < PK_COUNT; ++k) {
+    ms[k] = 0;
+    counts[k] = 0;
+  }
+  for (size_t i = 0; i < g_prof.used; ++i) {
+    hipError_t e = hipEventSynchronize(g_prof.pool[i].second);
+    if (e != hipSuccess) return fail(HK_ERR_HIP, std::string("profile event: ") + hipGetErrorString(e));
+    float t = 0;
+    e = hipEventElapsedTime(&t, g_prof.pool[i].first, g_prof.pool[i].second);
+    if (e != hipSuccess) return fail(HK_ERR_HIP, std::string("profile elapsed: ") + hipGetErrorString(e));
+    const int k = g_prof.kinds[i];
+    if (k >= 0 && k < PK_COUNT) {
+      ms[k] += t;
+      counts[k] += 1;
+    }
+  }
+  g_prof.used = 0;
+  return Status();
+}
+
 static hipError_t rows(hk_dtype_t dt, int logL, int E, int rpw, dim3 g, const Shape &sh, const Ptrs &p0,
-                       const Strides &str, const Ptrs *pt, int64_t cnt, hipStream_t st) {
+                       const Strides &str, int64_t cnt, hipStream_t st) {
   count_launch();
-  return is_double(dt) ? launch_rows_f64(logL, E, rpw, g, sh, p0, str, pt, cnt, st)
-                       : launch_rows_f32(logL, E, rpw, g, sh, p0, str, pt, cnt, st);
+  prof_before(st);
+  const hipError_t e = is_double(dt) ? launch_rows_f64(logL, E, rpw, g, sh, p0, str, cnt, st)
+                                     : launch_rows_f32(logL, E, rpw, g, sh, p0, str, cnt, st);
+  prof_after(sh.resident ? PK_RESIDENT : PK_PASS_B, st);
+  return e;
 }
 static hipError_t cols(hk_dtype_t dt, int logL, int E, int tw, dim3 g, const Shape &sh, const Ptrs &p0,
-                       const Strides &str, const Ptrs *pt, const ColJob *jobs, int nj, hipStream_t st) {
+                       const Strides &str, const ColJob *jobs, int nj, hipStream_t st) {
   count_launch();
-  return is_double(dt) ? launch_cols_f64(logL, E, tw, g, sh, p0, str, pt, jobs, nj, st)
-                       : launch_cols_f32(logL, E, tw, g, sh, p0, str, pt, jobs, nj, st);
+  prof_before(st);
+  const hipError_t e = is_double(dt) ? launch_cols_f64(logL, E, tw, g, sh, p0, str, jobs, nj, st)
+                                     : launch_cols_f32(logL, E, tw, g, sh, p0, str, jobs, nj, st);
+  prof_after(jobs[0].kind == COL_A ? PK_PASS_A : PK_PASS_D, st);
+  return e;
 }
 
 static Status hip_fail(hipError_t e, const char *what) {
@@ -311,14 +382,14 @@ static Status hip_fail(hipError_t e, const char *what) {
 }
 
 Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs &p0, const Strides &str,
-                    const Ptrs *ptab, int64_t count, hipStream_t st) {
+                    int64_t count, hipStream_t st) {
   if (count < 1) return Status();
   if (count > 65535 && !sh.resident) return fail(HK_ERR_SIZE_LIMIT, "batch too large for one launch");
   hipError_t e;
   if (sh.resident) {
     const int64_t blocks = (count + sc.rows_per_wg - 1) / sc.rows_per_wg;
     if (blocks > 0x7fffffff) return fail(HK_ERR_SIZE_LIMIT, "batch too large");
-    e = rows(dt, sh.logR, sc.E_row, sc.rows_per_wg, dim3((unsigned)blocks), sh, p0, str, ptab, count, st);
+    e = rows(dt, sh.logR, sc.E_row, sc.rows_per_wg, dim3((unsigned)blocks), sh, p0, str, count, st);
     if (e != hipSuccess) return hip_fail(e, "resident launch");
     return Status();
   }
@@ -326,6 +397,7 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
   const int64_t C = (int64_t)1 << sh.logC;
   // Pass A: column transforms of every operand.
   ColJob ja[MAXOPS];
+  memset(ja, 0, sizeof(ja));
   int64_t max_cols = 0;
   for (int o = 0; o < sh.nops; ++o) {
     ja[o].kind = COL_A;
@@ -336,14 +408,17 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
     max_cols = std::max(max_cols, ja[o].ncols);
   }
   dim3 ga((unsigned)((max_cols + sc.tw - 1) / sc.tw), (unsigned)sh.nops, (unsigned)count);
-  e = cols(dt, sh.logC, sc.E_col, sc.tw, ga, sh, p0, str, ptab, ja, sh.nops, st);
+  e = cols(dt, sh.logC, sc.E_col, sc.tw, ga, sh, p0, str, ja, sh.nops, st);
   if (e != hipSuccess) return hip_fail(e, "pass A launch");
   // Pass B: row transforms, spectral product, row transform of the output.
   dim3 gb((unsigned)((C + sc.rows_per_wg - 1) / sc.rows_per_wg), (unsigned)count);
-  e = rows(dt, sh.logR, sc.E_row, sc.rows_per_wg, gb, sh, p0, str, ptab, count, st);
+  e = rows(dt, sh.logR, sc.E_row, sc.rows_per_wg, gb, sh, p0, str, count, st);
   if (e != hipSuccess) return hip_fail(e, "pass B launch");
-  // Pass D: column transforms of the outputs and the slice.
+  // Pass D: column transforms of the outputs and the slice; its first
+  // workgroup also sums pass B's scalar partials.
+  const int64_t npart = (sh.prog == PROG_FWD && sh.want_alpha) ? (C + sc.rows_per_wg - 1) / sc.rows_per_wg : 0;
   ColJob jd[2];
+  memset(jd, 0, sizeof(jd));
   int nd = 0;
   int64_t dcols = 0;
   if (sh.want_y) {
@@ -351,6 +426,7 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
     jd[nd].op = 0;
     jd[nd].buf = sh.ops[0].buf;
     jd[nd].conj_out = 0;
+    jd[nd].npart = npart;
     jd[nd].ncols = std::min<int64_t>(R, sh.out_rows);
     dcols = std::max(dcols, jd[nd].ncols);
     ++nd;
@@ -366,8 +442,14 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
   }
   if (nd > 0) {
     dim3 gd((unsigned)((dcols + sc.tw - 1) / sc.tw), (unsigned)nd, (unsigned)count);
-    e = cols(dt, sh.logC, sc.E_col, sc.tw, gd, sh, p0, str, ptab, jd, nd, st);
+    e = cols(dt, sh.logC, sc.E_col, sc.tw, gd, sh, p0, str, jd, nd, st);
     if (e != hipSuccess) return hip_fail(e, "pass D launch");
+  } else if (npart > 0) {
+    count_launch();
+    prof_before(st);
+    e = is_double(dt) ? launch_alpha_f64(sh, p0, str, npart, count, st) : launch_alpha_f32(sh, p0, str, npart, count, st);
+    prof_after(PK_PASS_D, st);
+    if (e != hipSuccess) return hip_fail(e, "scalar reduction launch");
   }
   return Status();
 }

@@ -81,10 +81,10 @@ bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc);
 // Workspace bytes per instance for a shape (0 for resident).
 size_t instance_ws_bytes(const Shape &sh, hk_dtype_t dt);
 
-// Plain path: enqueue the product(s) of one shape.  ptab (device) holds
-// `count` per-instance pointer sets, or is NULL and instance i uses p0 + i * str.
+// Plain path: enqueue the product(s) of one shape; instance i uses the
+// pointers p0 + i * str (byte strides).
 Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs &p0, const Strides &str,
-                    const Ptrs *ptab, int64_t count, hipStream_t st);
+                    int64_t count, hipStream_t st);
 
 // Device checks / one-time per-device setup (twiddle tables).
 Status ensure_device();
@@ -95,5 +95,15 @@ void sched_store(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint,
 
 // Thread-local launch counter.
 void count_launch();
+
+// Kernel timing (diagnostics): when enabled, HIP events are recorded on the
+// launch stream immediately before and after every kernel the library
+// enqueues, grouped by kind.
+enum ProfKind : int { PK_RESIDENT = 0, PK_PASS_A = 1, PK_PASS_B = 2, PK_PASS_D = 3, PK_BATCH = 4, PK_COUNT = 5 };
+bool prof_enabled();
+void prof_before(hipStream_t st);
+void prof_after(int kind, hipStream_t st);
+Status prof_start();
+Status prof_stop(double *ms, int64_t *counts);
 
 }  // namespace hk

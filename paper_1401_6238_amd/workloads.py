@@ -91,12 +91,15 @@ def exp_sum_matrix(rng: np.random.Generator, rows: int, cols: int, r: int, sigma
     a = cn(rng, r, 1.0)
     z1 = np.exp(-rng.uniform(*mag_range, r) + 1j * rng.uniform(*arg_range, r)).astype(np.complex128)
     z2 = np.exp(-rng.uniform(*mag_range, r) + 1j * rng.uniform(*arg_range, r)).astype(np.complex128)
-    acc = np.zeros((cols, rows), np.clongdouble)  # [k2, k1] so that ravel() is column-major in (k1, k2)
+    # [k2, k1] so that ravel() is column-major in (k1, k2).  The powers are
+    # accumulated in extended precision; the outer products (one rounding
+    # each) are formed in double precision.
+    acc = np.zeros((cols, rows), np.complex128)
     for j in range(r):
-        p1 = powers_ld(z1[j], rows)
-        p2 = powers_ld(z2[j], cols)
-        acc += np.clongdouble(a[j]) * np.outer(p2, p1)
-    H = acc.astype(np.complex128).ravel()
+        p1 = powers(z1[j], rows)
+        p2 = powers(z2[j], cols) * a[j]
+        acc += np.outer(p2, p1)
+    H = acc.ravel()
     if sigma > 0:
         H = H + cn(rng, rows * cols, sigma * sigma)
     return H, (a, z1, z2, sigma)
