@@ -239,9 +239,19 @@ hk_status_t block_hankel_tvp_strided_batched(hk_dtype_t dt, const void *H, int64
 hk_status_t hk_fft_layout(int64_t d_h, int64_t *n_fft, int64_t *n_row, int64_t *n_col);
 /* Runs the in-house autotuner for the plain 1D path of one (dtype, m, n)
  * shape on the current device and stores the winner in the process-wide
- * schedule cache (and in the JSON file named by HK_TUNE_CACHE, if set).
- * Allocates and frees its own temporary device buffers. */
+ * schedule cache that later calls of that shape consult.  Allocates and
+ * frees its own temporary device buffers and synchronizes the device. */
 hk_status_t hk_autotune_tvp(hk_dtype_t dt, int m, int64_t n, int verbose);
+/* General form: kind 0 = hankel_tvp / hankel_tvp_strided_batched shape
+ * (m, n); kind 1 = the adjoint of that shape; kind 2 = equal-vector BHHB
+ * shape (m, inner_dims, block_dims; n ignored).  batch = instances per call
+ * (1 for single products); the cache is kept per batch class (1, < 16,
+ * >= 16). */
+#define HK_TUNE_FORWARD 0
+#define HK_TUNE_ADJOINT 1
+#define HK_TUNE_BLOCK 2
+hk_status_t hk_autotune(hk_dtype_t dt, int kind, int m, int64_t n, const int64_t *inner_dims,
+                        const int64_t *block_dims, int64_t batch, int verbose);
 /* Number of the library's kernel launches enqueued by the last call made on
  * this thread (diagnostics). */
 int hk_last_launch_count(void);

@@ -50,10 +50,12 @@ def _lib():
         lib.hko_tvp_i64.argtypes = [ctypes.c_int, P, P, P, P, P]
         lib.hko_block_tvp.argtypes = [ctypes.c_int, P, P, P, P, P, P]
         lib.hko_block_tvp_i64.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+        lib.hko_block_tvp_sampled.argtypes = [ctypes.c_int, P, P, P, P, P, I64, P, P]
         lib.hko_tvp_backward.argtypes = [ctypes.c_int, I64, P, P, P, P, P, P]
         lib.hko_max_threads.argtypes = []
         for f in (lib.hko_conv_range, lib.hko_conv, lib.hko_corr, lib.hko_tvp, lib.hko_tvp_sampled,
-                  lib.hko_tvp_i64, lib.hko_block_tvp, lib.hko_block_tvp_i64, lib.hko_tvp_backward,
+                  lib.hko_tvp_i64, lib.hko_block_tvp, lib.hko_block_tvp_i64, lib.hko_block_tvp_sampled,
+                  lib.hko_tvp_backward,
                   lib.hko_max_threads):
             f.restype = ctypes.c_int
         _lib_handle = lib
@@ -175,6 +177,19 @@ def block_tvp(m: int, dims, block_dims, H, vectors, want_y: bool = True, want_al
     keep = _vec_ptrs(vecs)
     _check(_lib().hko_block_tvp(m, _ptr(dims), _ptr(bd), _ptr(H), keep, _ptr(y), _ptr(alpha)),
            "block_tvp")
+    return y, (None if alpha is None else complex(alpha[0]))
+
+
+def block_tvp_sampled(m: int, dims, block_dims, H, vectors, idx, want_alpha: bool = False):
+    """BHHB product at flat output indices idx (column-major in the n_1 x N_1 result)."""
+    dims, H, vecs = _prep(m, dims, H, vectors, want_alpha)
+    bd = np.ascontiguousarray(np.asarray(block_dims, dtype=np.int64))
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    y = np.empty(len(idx), np.complex128)
+    alpha = np.zeros(1, np.complex128) if want_alpha else None
+    keep = _vec_ptrs(vecs)
+    _check(_lib().hko_block_tvp_sampled(m, _ptr(dims), _ptr(bd), _ptr(H), keep, _ptr(idx), len(idx), _ptr(y),
+                                        _ptr(alpha)), "block_tvp_sampled")
     return y, (None if alpha is None else complex(alpha[0]))
 
 

@@ -333,6 +333,51 @@ int hko_block_tvp(int m, const int64_t *n, const int64_t *nblk, const hkc *H,
     return 0;
 }
 
+/* BHHB product at the listed output indices only (flat column-major indices
+ * into the n_1 x N_1 result), and/or the scalar.  Same sums as
+ * hko_block_tvp. */
+int hko_block_tvp_sampled(int m, const int64_t *n, const int64_t *nblk, const hkc *H,
+                          const hkc *const *vectors, const int64_t *idx, int64_t nidx,
+                          hkc *y, hkc *alpha) {
+    if (check_dims(m, n) || check_dims(m, nblk)) return -1;
+    for (int64_t t = 0; t < nidx; ++t)
+        if (idx[t] < 0 || idx[t] >= n[0] * nblk[0]) return -1;
+    int64_t hr = 1 - m, hcols = 1 - m;
+    for (int p = 0; p < m; ++p) { hr += n[p]; hcols += nblk[p]; }
+    int64_t wr = 1, wc = 1;
+    hkc *w = (hkc *)malloc(sizeof(hkc));
+    if (!w) return -2;
+    w[0].re = 1.0; w[0].im = 0.0;
+    for (int p = 1; p < m; ++p) {
+        hkc *nw = conv2(w, wr, wc, vectors[p], n[p], nblk[p]);
+        free(w);
+        if (!nw) return -2;
+        w = nw;
+        wr += n[p] - 1;
+        wc += nblk[p] - 1;
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nidx; ++t) {
+        const int64_t i = idx[t] % n[0], j = idx[t] / n[0];
+        hkc total = { 0.0, 0.0 }, part = { 0.0, 0.0 };
+        int cnt = 0;
+        for (int64_t l = 0; l < wc; ++l)
+            for (int64_t k = 0; k < wr; ++k) {
+                part = cadd(part, cmul(H[(i + k) + hr * (j + l)], w[k + wr * l]));
+                if (++cnt == BLOCK) { total = cadd(total, part); part.re = part.im = 0.0; cnt = 0; }
+            }
+        y[t] = cadd(total, part);
+    }
+    if (alpha) {
+        hkc *u = conv2(vectors[0], n[0], nblk[0], w, wr, wc);
+        if (!u) { free(w); return -2; }
+        *alpha = dot_plain(H, u, hr * hcols);
+        free(u);
+    }
+    free(w);
+    return 0;
+}
+
 static hki *iconv2(const hki *a, int64_t ar, int64_t ac, const hki *b, int64_t br, int64_t bc) {
     int64_t orr = ar + br - 1, oc = ac + bc - 1;
     hki *out = (hki *)calloc((size_t)(orr * oc), sizeof(hki));

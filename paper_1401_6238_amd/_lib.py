@@ -77,6 +77,7 @@ _SIGS = {
                                          _SZ, _P],
     "hk_fft_layout": [_I64, _PI64, _PI64, _PI64],
     "hk_autotune_tvp": [_I, _I, _I64, _I],
+    "hk_autotune": [_I, _I, _I, _I64, _PI64, _PI64, _I64, _I],
     "hk_last_launch_count": [],
     "hk_profile_start": [],
     "hk_profile_stop": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],

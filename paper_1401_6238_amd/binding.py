@@ -305,6 +305,15 @@ def hk_autotune_tvp(dtype: torch.dtype, m: int, n: int, verbose: bool = False):
     check(lib().hk_autotune_tvp(_DT[dtype], m, n, int(verbose)), "hk_autotune_tvp")
 
 
+def hk_autotune(dtype: torch.dtype, kind: str, m: int, n: int = 0, inner=None, blocks=None, batch: int = 1,
+                verbose: bool = False):
+    """kind: 'forward', 'adjoint' (1D equal-vector shapes) or 'block' (BHHB, inner/blocks per mode)."""
+    k = {"forward": 0, "adjoint": 1, "block": 2}[kind]
+    di = _i64arr(inner) if inner is not None else None
+    db = _i64arr(blocks) if blocks is not None else None
+    check(lib().hk_autotune(_DT[dtype], k, m, n, di, db, batch, int(verbose)), "hk_autotune")
+
+
 def hk_last_launch_count() -> int:
     return int(lib().hk_last_launch_count())
 

@@ -67,14 +67,15 @@ static Status ws_size(const Problem &p, int64_t batch, size_t *bytes) {
 }
 
 static Status run_one(const Problem &p, void *ws, size_t ws_bytes, hipStream_t st) {
-  Status s = ensure_device();
-  if (!s.ok()) return s;
+  // host-side checks first: argument errors never need the device
   Shape sh;
   Ptrs P;
   Sched sc;
-  s = prepare(p, 1, &sh, &P, &sc);
+  Status s = prepare(p, 1, &sh, &P, &sc);
   if (!s.ok()) return s;
   s = check_ws(instance_ws_bytes(sh, p.dt), ws, ws_bytes);
+  if (!s.ok()) return s;
+  s = ensure_device();
   if (!s.ok()) return s;
   P.ws = ws;
   Strides str;
@@ -273,15 +274,15 @@ static Status run_strided(const Problem &p, const Strides &str_elems, int64_t ba
                           hipStream_t st) {
   if (batch < 0) return fail(HK_ERR_INVALID_VALUE, "batch must be >= 0");
   if (batch == 0) return Status();
-  Status s = ensure_device();
-  if (!s.ok()) return s;
   Shape sh;
   Ptrs P;
   Sched sc;
-  s = prepare(p, batch, &sh, &P, &sc);
+  Status s = prepare(p, batch, &sh, &P, &sc);
   if (!s.ok()) return s;
   const size_t per = instance_ws_bytes(sh, p.dt);
   s = check_ws(per * (size_t)batch, ws, ws_bytes);
+  if (!s.ok()) return s;
+  s = ensure_device();
   if (!s.ok()) return s;
   P.ws = ws;
   // Map the caller's element strides onto the shape's operand slots.
@@ -446,6 +447,12 @@ hk_status_t hk_profile_stop(double *ms_by_kind, int64_t *launches_by_kind) {
 
 hk_status_t hk_autotune_tvp(hk_dtype_t dt, int m, int64_t n, int verbose) {
   return finish(autotune_tvp(dt, m, n, verbose != 0));
+}
+
+hk_status_t hk_autotune(hk_dtype_t dt, int kind, int m, int64_t n, const int64_t *inner_dims,
+                        const int64_t *block_dims, int64_t batch, int verbose) {
+  if (kind == 2 && (!inner_dims || !block_dims)) return finish(fail(HK_ERR_NULL_POINTER, "block dims are NULL"));
+  return finish(autotune_shape(dt, kind, m, n, inner_dims, block_dims, batch, verbose != 0));
 }
 
 }  // extern "C"

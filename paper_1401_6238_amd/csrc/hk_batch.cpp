@@ -393,32 +393,28 @@ Status plan_release_after(hk_plan_t p, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Autotuner for the plain 1D path: times every valid schedule variant on
-// scratch buffers and keeps the fastest.
+// Autotuner: times every valid schedule of one shape (split of N = R * C,
+// elements per lane of the row and column transforms, rows per workgroup,
+// column-tile width) on scratch buffers, and caches the fastest under the key
+// the call path looks up (dtype, program, 1D/BHHB, N, batch class).  All
+// instances of a tuning batch read the same zero-filled inputs and write
+// their own outputs and workspace.
 // ---------------------------------------------------------------------------
-Status autotune_tvp(hk_dtype_t dt, int m, int64_t n, bool verbose) {
+Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   Status s = ensure_device();
   if (!s.ok()) return s;
-  Problem p;
-  p.dt = dt;
-  p.prog = PROG_FWD;
-  p.m = m;
-  for (int q = 0; q < m && q < HK_MAX_ORDER; ++q) p.dims[q] = n;
-  int64_t dh = m * (n - 1) + 1;
-  const size_t eb = elem_bytes(dt);
-  void *dh_buf = nullptr, *dx = nullptr, *dy = nullptr, *da = nullptr, *dws = nullptr;
+  if (batch < 1) return fail(HK_ERR_INVALID_VALUE, "batch must be >= 1");
+  Problem p = proto;
+  const hk_dtype_t dt = p.dt;
   Layout lay0;
-  p.h = (void *)16;
-  for (int q = 0; q < m && q < HK_MAX_ORDER; ++q) p.vec[q] = (void *)16;
-  p.y = (void *)16;
-  s = validate_forward(p);
+  s = layout_for(p, 0, &lay0);
   if (!s.ok()) return s;
-  layout_for(p, 0, &lay0);
   std::vector<Sched> cands;
   std::vector<Layout> lays;
   const int splits[] = {0, -1, 1, -2, 2};
   for (int sp : splits) {
     Layout lay;
+    if (p.is_block && sp != 0) continue;
     if (!layout_for(p, sp, &lay).ok()) continue;
     if (sp != 0 && (lay.resident || (lay.logR == lay0.logR && lay.logC == lay0.logC))) continue;
     for (int er : {8, 16})
@@ -433,12 +429,21 @@ Status autotune_tvp(hk_dtype_t dt, int m, int64_t n, bool verbose) {
             sc.tw = tw;
             sc.split = sp;
             if (!sched_valid(dt, lay, sc)) continue;
-            if (lay.resident && rows > 1) continue;
             cands.push_back(sc);
             lays.push_back(lay);
           }
   }
   if (cands.empty()) return fail(HK_ERR_NOT_SUPPORTED, "no schedule candidates");
+  // buffer sizes
+  const size_t eb = elem_bytes(dt);
+  int64_t hrows = 1 - p.m, hcols = 1 - p.m, vmax = 1;
+  for (int q = 0; q < p.m; ++q) {
+    hrows += p.dims[q];
+    hcols += p.bdims[q];
+    vmax = std::max<int64_t>(vmax, p.dims[q] * (p.is_block ? p.bdims[q] : 1));
+  }
+  const int64_t hlen = p.is_block ? hrows * hcols : hrows;
+  const int64_t ylen = std::max<int64_t>(hlen, vmax);  // room for y, grad_h or grad_x
   size_t wsb = 0;
   for (size_t i = 0; i < cands.size(); ++i) {
     Shape sh;
@@ -446,23 +451,34 @@ Status autotune_tvp(hk_dtype_t dt, int m, int64_t n, bool verbose) {
     build_shape(p, lays[i], cands[i], &sh, &P, nullptr);
     wsb = std::max(wsb, instance_ws_bytes(sh, dt));
   }
-  hipError_t e = hipMalloc(&dh_buf, dh * eb);
-  if (e == hipSuccess) e = hipMalloc(&dx, n * eb);
-  if (e == hipSuccess) e = hipMalloc(&dy, n * eb);
-  if (e == hipSuccess) e = hipMalloc(&da, 2 * eb);
-  if (e == hipSuccess && wsb) e = hipMalloc(&dws, wsb);
-  if (e == hipSuccess) e = hipMemset(dh_buf, 0, dh * eb);
-  if (e == hipSuccess) e = hipMemset(dx, 0, n * eb);
+  void *dh = nullptr, *dx = nullptr, *dy = nullptr, *dy1 = nullptr, *da = nullptr, *dws = nullptr;
+  hipError_t e = hipMalloc(&dh, hlen * eb);
+  if (e == hipSuccess) e = hipMalloc(&dx, vmax * eb);
+  if (e == hipSuccess) e = hipMalloc(&dy, batch * ylen * eb);
+  if (e == hipSuccess) e = hipMalloc(&dy1, batch * ylen * eb);
+  if (e == hipSuccess) e = hipMalloc(&da, batch * 2 * eb);
+  if (e == hipSuccess && wsb) e = hipMalloc(&dws, batch * wsb);
+  if (e == hipSuccess) e = hipMemset(dh, 0, hlen * eb);
+  if (e == hipSuccess) e = hipMemset(dx, 0, vmax * eb);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   double best = 1e30;
   int besti = -1;
   if (e == hipSuccess) {
-    p.h = dh_buf;
-    for (int q = 0; q < m; ++q) p.vec[q] = dx;
-    p.y = dy;
-    p.alpha = da;
+    p.h = dh;
+    for (int q = 0; q < p.m; ++q)
+      if (p.vec[q]) p.vec[q] = dx;
+    if (p.prog == PROG_FWD) {
+      if (p.y) p.y = dy;
+      if (p.alpha) p.alpha = da;
+    } else {
+      if (p.v) p.v = dx;
+      if (p.phi) p.phi = da;
+      if (p.gh) p.gh = dy;
+      if (p.gx) p.gx = dy1;
+    }
+    const int reps = batch > 8 ? 2 : 5;
     for (size_t i = 0; i < cands.size() && s.ok(); ++i) {
       Shape sh;
       Ptrs P;
@@ -470,11 +486,14 @@ Status autotune_tvp(hk_dtype_t dt, int m, int64_t n, bool verbose) {
       P.ws = dws;
       Strides str;
       memset(&str, 0, sizeof(str));
-      const int reps = 5;
-      s = launch_shape(dt, sh, cands[i], P, str, 1, nullptr);  // warm-up
+      str.y = ylen * eb;
+      str.out1 = ylen * eb;
+      str.alpha = eb;
+      str.ws = (int64_t)instance_ws_bytes(sh, dt);
+      s = launch_shape(dt, sh, cands[i], P, str, batch, nullptr);  // warm-up
       if (!s.ok()) break;
       (void)hipEventRecord(e0, nullptr);
-      for (int r = 0; r < reps && s.ok(); ++r) s = launch_shape(dt, sh, cands[i], P, str, 1, nullptr);
+      for (int r = 0; r < reps && s.ok(); ++r) s = launch_shape(dt, sh, cands[i], P, str, batch, nullptr);
       (void)hipEventRecord(e1, nullptr);
       (void)hipEventSynchronize(e1);
       float ms = 0;
@@ -492,21 +511,63 @@ Status autotune_tvp(hk_dtype_t dt, int m, int64_t n, bool verbose) {
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipDeviceSynchronize();
-  (void)hipFree(dh_buf);
+  (void)hipFree(dh);
   (void)hipFree(dx);
   (void)hipFree(dy);
+  (void)hipFree(dy1);
   (void)hipFree(da);
   if (dws) (void)hipFree(dws);
   if (e != hipSuccess) return hip_fail(e, "autotune buffers");
   if (!s.ok()) return s;
   if (besti < 0) return fail(HK_ERR_NOT_SUPPORTED, "autotune found no schedule");
   const Layout &bl = lays[besti];
-  sched_store(dt, PROG_FWD, 0, lay0.logR + lay0.logC, -1, 1, cands[besti]);
+  sched_store(dt, p.prog, p.is_block ? 1 : 0, lay0.logR + lay0.logC, p.is_block ? lay0.logC : -1, batch,
+              cands[besti]);
   if (verbose)
     fprintf(stderr, "[hk autotune] best: split=%d (R=2^%d C=2^%d) E_row=%d rows=%d E_col=%d tw=%d %.4f ms\n",
             cands[besti].split, bl.logR, bl.logC, cands[besti].E_row, cands[besti].rows_per_wg, cands[besti].E_col,
             cands[besti].tw, best);
   return Status();
+}
+
+Status autotune_tvp(hk_dtype_t dt, int m, int64_t n, bool verbose) {
+  return autotune_shape(dt, 0, m, n, nullptr, nullptr, 1, verbose);
+}
+
+Status autotune_shape(hk_dtype_t dt, int kind, int m, int64_t n, const int64_t *inner, const int64_t *blocks,
+                      int64_t batch, bool verbose) {
+  if (m < 2 || m > HK_MAX_ORDER) return fail(HK_ERR_INVALID_VALUE, "order m must be in [2, 8]");
+  Problem p;
+  p.dt = dt;
+  p.m = m;
+  const void *dummy = (const void *)256;
+  p.h = dummy;
+  Status s;
+  if (kind == 0 || kind == 2) {  // forward, equal vectors (1D or BHHB)
+    p.prog = PROG_FWD;
+    p.is_block = kind == 2;
+    for (int q = 0; q < m; ++q) {
+      p.dims[q] = p.is_block ? (inner ? inner[q] : 0) : n;
+      if (p.is_block) p.bdims[q] = blocks ? blocks[q] : 0;
+      p.vec[q] = dummy;
+    }
+    p.y = (void *)256;
+    p.alpha = (void *)256;
+    s = validate_forward(p);
+  } else if (kind == 1) {  // adjoint with both cotangents and both gradients
+    p.prog = PROG_BWD;
+    for (int q = 0; q < m; ++q) p.dims[q] = n;
+    p.vec[1] = dummy;
+    p.v = dummy;
+    p.phi = dummy;
+    p.gx = (void *)256;
+    p.gh = (void *)256;
+    s = validate_backward(p);
+  } else {
+    return fail(HK_ERR_INVALID_VALUE, "unknown autotune kind");
+  }
+  if (!s.ok()) return s;
+  return autotune_problem(p, batch, verbose);
 }
 
 }  // namespace hk

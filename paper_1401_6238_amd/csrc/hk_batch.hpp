@@ -16,8 +16,11 @@ Status plan_set_oneshot(hk_plan_t plan);
 // Waits for the stream, then frees a one-shot plan.
 Status plan_release_after(hk_plan_t plan, hipStream_t st);
 
-// Times the candidate schedules of the plain 1D path for (dt, m, n) and
-// stores the winner in the schedule cache.
+// Times the candidate schedules of one shape and stores the winner in the
+// schedule cache.  kind 0: forward 1D equal vectors (m, n); 1: adjoint 1D;
+// 2: forward BHHB equal vectors (inner/blocks); batch = instances per call.
 Status autotune_tvp(hk_dtype_t dt, int m, int64_t n, bool verbose);
+Status autotune_shape(hk_dtype_t dt, int kind, int m, int64_t n, const int64_t *inner, const int64_t *blocks,
+                      int64_t batch, bool verbose);
 
 }  // namespace hk

@@ -146,8 +146,8 @@ struct RowBody {
   // one wavefront and its exchanges need no workgroup barrier.
   static constexpr bool WAVE = TPS <= 64;
 
-  static __device__ __forceinline__ void fft(cx<T> (&a)[EE], int t, cx<T> *lds, const cx<T> *tw4096) {
-    fft_seq<T, L, E, WAVE>(a, t, lds, tw4096);
+  static __device__ __forceinline__ void fft(cx<T> (&a)[EE], int t, cx<T> *lds, const StageTw<T, L, E> &tw) {
+    fft_seq<T, L, E, WAVE>(a, t, lds, tw);
   }
 
   static __device__ __forceinline__ void load(cx<T> (&a)[EE], const Shape &sh, const PV &P, int o,
@@ -212,10 +212,12 @@ struct RowBody {
 #pragma unroll
     for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
     load(a, sh, P, 0, row, valid_row, t, resident);
+    StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
     for (int o = 0; o < sh.nops; ++o) {
       // the next operand's loads are in flight while this one is transformed
       if (o + 1 < sh.nops) load(nx, sh, P, o + 1, row, valid_row, t, resident);
-      fft(a, t, lds, tw4096);
+      fft(a, t, lds, stw);
       const OpDesc &od = sh.ops[o];
       if (od.role == ROLE_H) {
 #pragma unroll
@@ -234,7 +236,7 @@ struct RowBody {
       for (int s = 0; s < EE; ++s) a[s] = nx[s];
     }
     if (sh.want_y) {
-      fft(acc, t, lds, tw4096);
+      fft(acc, t, lds, stw);
       store(acc, sh, P, 0, row, valid_row, t, resident, tw24, tw4096);
     }
     return part;
@@ -251,10 +253,12 @@ struct RowBody {
     cx<T> phc = czero<T>();  // conj(phi)
     if (P.phi()) phc = cconj(*(const cx<T> *)P.phi());
     const T m1 = T(sh.m - 1), m0 = T(sh.m);
+    StageTw<T, L, E> stw;
     {
       cx<T> xs[EE], p1[EE], vs[EE];
       load(xs, sh, P, 0, row, valid_row, t, resident);
-      fft(xs, t, lds, tw4096);
+      stw.init(t, tw4096);
+      fft(xs, t, lds, stw);
 #pragma unroll
       for (int s = 0; s < EE; ++s) p1[s] = mk(T(1), T(0));
       for (int e = 0; e < sh.m - 2; ++e) {
@@ -264,7 +268,7 @@ struct RowBody {
       const bool has_v = sh.nops > 1 && sh.ops[1].role == ROLE_V;
       if (has_v) {
         load(vs, sh, P, 1, row, valid_row, t, resident);
-        fft(vs, t, lds, tw4096);
+        fft(vs, t, lds, stw);
       } else {
 #pragma unroll
         for (int s = 0; s < EE; ++s) vs[s] = czero<T>();
@@ -278,15 +282,15 @@ struct RowBody {
       }
     }
     if (sh.want_y) {
-      fft(a, t, lds, tw4096);
+      fft(a, t, lds, stw);
       store(a, sh, P, 0, row, valid_row, t, resident, tw24, tw4096);
     }
     if (sh.want_out1) {
       load(a, sh, P, sh.nops - 1, row, valid_row, t, resident);  // H
-      fft(a, t, lds, tw4096);
+      fft(a, t, lds, stw);
 #pragma unroll
       for (int s = 0; s < EE; ++s) a[s] = cmul(cscale(cconj(a[s]), invN), gq[s]);
-      fft(a, t, lds, tw4096);
+      fft(a, t, lds, stw);
       store(a, sh, P, 1, row, valid_row, t, resident, tw24, tw4096);
     }
   }
@@ -340,16 +344,20 @@ struct ColBody {
       }
       gather<T, EE>(a, ws_buf<T>(sh, P, job.buf), idx, ok, 0);
     }
-    fft_seq<T, L, E>(a, t, lds + cw * col_lds_stride(S::LDS, TW), tw4096);
+    StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
+    // pass A's four-step twiddles W_N^{c k}, k = t + s TPS: their table loads
+    // are issued before the transform so that they overlap it
+    cx<T> wst[EE];
+    const bool twid = job.kind == COL_A && !sh.is_block;
+    if (twid) slot_twiddles<T, EE>(wst, c, t, TPS, sh.logR + sh.logC, tw24, tw4096);
+    fft_seq<T, L, E>(a, t, lds + cw * col_lds_stride(S::LDS, TW), stw);
     if (!cvalid) return;
     if (job.kind == COL_A) {
       cx<T> *dst = ws_buf<T>(sh, P, job.buf);
-      if (!sh.is_block) {
-        // four-step twiddles W_N^{c * k}, k = t + s TPS
-        cx<T> w[EE];
-        slot_twiddles<T, EE>(w, c, t, TPS, sh.logR + sh.logC, tw24, tw4096);
+      if (twid) {
 #pragma unroll
-        for (int s = 0; s < EE; ++s) dst[c + R * (t + s * TPS)] = cmul(a[s], w[s]);
+        for (int s = 0; s < EE; ++s) dst[c + R * (t + s * TPS)] = cmul(a[s], wst[s]);
       } else {
 #pragma unroll
         for (int s = 0; s < EE; ++s) dst[c + R * (t + s * TPS)] = a[s];

@@ -145,6 +145,14 @@ struct FFTShape {
   // LDS elements per sequence (padded by one element every EE elements).
   static constexpr int LDS = P > 1 ? L + L / EE : 0;
   static __host__ __device__ constexpr int radix(int p) { return p < P - 1 ? EE : (1 << LOG_LAST); }
+  static __host__ __device__ constexpr int nbf(int p) { return EE / radix(p); }  // butterflies per lane
+  // offset of pass p's twiddles in a lane's precomputed set (passes 1..P-1)
+  static __host__ __device__ constexpr int tw_off(int p) {
+    int o = 0;
+    for (int i = 1; i < p; ++i) o += nbf(i) * (radix(i) - 1);
+    return o;
+  }
+  static constexpr int TWN = tw_off(P) > 0 ? tw_off(P) : 1;
   static __device__ __forceinline__ int pad(int i) { return i + (i >> LOGE); }
 };
 
@@ -187,12 +195,40 @@ __device__ __forceinline__ void stage_twiddles(cx<T> (&w)[R], int k, int step, c
   }
 }
 
+// A lane's twiddles for every pass p >= 1 of a length-L transform.  They
+// depend only on the lane, so a kernel computes them once (their table loads
+// overlap the first data loads) and reuses them for all its transforms.
+template <typename T, int L, int E>
+struct StageTw {
+  using S = FFTShape<L, E>;
+  cx<T> w[S::TWN];
+
+  template <int p>
+  __device__ __forceinline__ void init_pass(int t, const cx<T> *__restrict__ tw4096) {
+    if constexpr (p < S::P) {
+      constexpr int R = S::radix(p);
+      constexpr int Ns = ipowc(S::EE, p);
+      constexpr int step = 4096 / (Ns * R);
+#pragma unroll
+      for (int q = 0; q < S::nbf(p); ++q) {
+        cx<T> tmp[R];
+        stage_twiddles<T, R>(tmp, (t + q * S::TPS) & (Ns - 1), step, tw4096);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[S::tw_off(p) + q * (R - 1) + r - 1] = tmp[r];
+      }
+      init_pass<p + 1>(t, tw4096);
+    }
+  }
+  __device__ __forceinline__ void init(int t, const cx<T> *__restrict__ tw4096) { init_pass<1>(t, tw4096); }
+};
+
 // One Stockham pass.  Slot (q, r) of lane t holds input b + r*(L/R) with
 // butterfly b = t + q*TPS; span Ns = EE^p; outputs go to
-// (b - k) R + k + r Ns, k = b mod Ns.
-template <typename T, int L, int E, bool WAVE, int p>
+// (b - k) R + k + r Ns, k = b mod Ns.  With PRE the twiddles come from the
+// lane's precomputed set, otherwise from the table.
+template <typename T, int L, int E, bool WAVE, bool PRE, int p>
 __device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
-                                         const cx<T> *__restrict__ tw4096) {
+                                         const cx<T> *__restrict__ tw4096, const StageTw<T, L, E> &pre) {
   using S = FFTShape<L, E>;
   constexpr int EE = S::EE;
   constexpr int TPS = S::TPS;
@@ -214,12 +250,17 @@ __device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = a[q + r * B];
     if constexpr (p > 0) {
-      const int k = b & (Ns - 1);
-      constexpr int step = 4096 / (Ns * R);
-      cx<T> w[R];
-      stage_twiddles<T, R>(w, k, step, tw4096);
+      if constexpr (PRE) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], pre.w[S::tw_off(p) + q * (R - 1) + r - 1]);
+      } else {
+        const int k = b & (Ns - 1);
+        constexpr int step = 4096 / (Ns * R);
+        cx<T> w[R];
+        stage_twiddles<T, R>(w, k, step, tw4096);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
+      }
     }
     dft<T, R>(v);
 #pragma unroll
@@ -235,7 +276,7 @@ __device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[S::pad(base + r * Ns)] = a[q + r * B];
     }
-    fft_pass<T, L, E, WAVE, p + 1>(a, t, lds, tw4096);
+    fft_pass<T, L, E, WAVE, PRE, p + 1>(a, t, lds, tw4096, pre);
   }
 }
 
@@ -245,7 +286,14 @@ __device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
 template <typename T, int L, int E, bool WAVE = false>
 __device__ __forceinline__ void fft_seq(Regs<T, L, E> &a, int t, cx<T> *lds,
                                         const cx<T> *__restrict__ tw4096) {
-  if constexpr (FFTShape<L, E>::P > 0) fft_pass<T, L, E, WAVE, 0>(a, t, lds, tw4096);
+  StageTw<T, L, E> none;
+  if constexpr (FFTShape<L, E>::P > 0) fft_pass<T, L, E, WAVE, false, 0>(a, t, lds, tw4096, none);
+}
+
+// Same, with the lane's precomputed twiddles.
+template <typename T, int L, int E, bool WAVE = false>
+__device__ __forceinline__ void fft_seq(Regs<T, L, E> &a, int t, cx<T> *lds, const StageTw<T, L, E> &pre) {
+  if constexpr (FFTShape<L, E>::P > 0) fft_pass<T, L, E, WAVE, true, 0>(a, t, lds, nullptr, pre);
 }
 
 

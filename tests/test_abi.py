@@ -1,0 +1,131 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/hankel.h, and rejects bad arguments on the host with the
+documented status codes before anything is enqueued."""
+import ctypes
+import os
+
+import pytest
+
+from paper_1401_6238_amd import _lib
+
+HK_C64, HK_C128, HK_F32, HK_F64 = 0, 1, 2, 3
+OK, INVALID, NULLP, MISALIGNED, WORKSPACE, SIZE, DEVICE, HIP, FAULT, NOTSUP = range(10)
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1401_6238_amd import build
+        build.build()
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _lib.header_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in hankel.h but not exported"
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libhankel.so")
+    with pytest.raises(ImportError):
+        _lib.lib()
+
+
+def ws(L, dt, m, n):
+    b = ctypes.c_size_t(0)
+    rc = L.hankel_tvp_workspace_size(dt, m, n, ctypes.byref(b))
+    return rc, b.value
+
+
+def test_workspace_sizes(L):
+    assert ws(L, HK_C64, 3, 64) == (OK, 0)          # resident: no workspace
+    rc, b = ws(L, HK_C64, 4, 1 << 18)               # N = 2^20, two buffers
+    assert rc == OK and b == ((2 * (1 << 20) * 8 + 4096 * 8 + 16 + 255) // 256) * 256
+    rc, b128 = ws(L, HK_C128, 4, 1 << 18)
+    assert rc == OK and b128 > b
+
+
+@pytest.mark.parametrize("dt,m,n,code", [
+    (7, 3, 10, INVALID), (HK_C64, 1, 10, INVALID), (HK_C64, 9, 10, INVALID), (HK_C64, 3, 0, INVALID),
+    (HK_C64, 3, -5, INVALID), (HK_C64, 4, (1 << 23), SIZE), (HK_C128, 2, (1 << 24) + 1, SIZE),
+])
+def test_workspace_size_rejects(L, dt, m, n, code):
+    assert ws(L, dt, m, n)[0] == code
+    assert L.hk_last_error()
+
+
+def test_null_bytes_pointer(L):
+    assert L.hankel_tvp_workspace_size(HK_C64, 3, 10, None) == NULLP
+
+
+def P(v):
+    return ctypes.c_void_p(v)
+
+
+def test_tvp_argument_errors_without_device(L):
+    h, x, y = P(0x10000), P(0x20000), P(0x30000)
+    assert L.hankel_tvp(HK_C64, h, 3, 10, x, None, None, None, 0, None) == NULLP       # no output
+    assert L.hankel_tvp(HK_C64, None, 3, 10, x, y, None, None, 0, None) == NULLP       # no h
+    assert L.hankel_tvp(HK_C64, P(0x10004), 3, 10, x, y, None, None, 0, None) == MISALIGNED
+    assert L.hankel_tvp(HK_C128, h, 3, 10, P(0x20008), y, None, None, 0, None) == MISALIGNED
+    # 3-pass size with no workspace
+    assert L.hankel_tvp(HK_C64, h, 4, 1 << 18, x, y, None, None, 0, None) == WORKSPACE
+    assert L.hankel_tvp(HK_C64, h, 4, 1 << 18, x, y, None, P(0x40000), 1024, None) == WORKSPACE
+    assert b"workspace" in L.hk_last_error()
+
+
+def test_mode_products_argument_errors(L):
+    dims = (ctypes.c_int64 * 3)(5, 6, 7)
+    vecs = (ctypes.c_void_p * 3)(0x1000, 0x2000, None)
+    h, y = P(0x10000), P(0x30000)
+    assert L.hankel_mode_products(HK_C64, h, 3, dims, vecs, y, None, None, 0, None) == NULLP  # x_3 missing
+    vecs2 = (ctypes.c_void_p * 3)(None, 0x2000, 0x3000)
+    assert L.hankel_mode_products(HK_C64, h, 3, dims, vecs2, None, P(0x5000), None, 0, None) == NULLP  # alpha needs x_1
+    bad = (ctypes.c_int64 * 3)(5, 0, 7)
+    assert L.hankel_mode_products(HK_C64, h, 3, bad, vecs2, y, None, None, 0, None) == INVALID
+    assert L.hankel_mode_products(HK_C64, h, 3, None, vecs2, y, None, None, 0, None) == NULLP
+
+
+def test_block_argument_errors(L):
+    inner = (ctypes.c_int64 * 2)(3000, 2000)
+    blocks = (ctypes.c_int64 * 2)(4, 4)
+    vecs = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    b = ctypes.c_size_t(0)
+    # the padded grid would exceed 4096 rows
+    assert L.block_hankel_tvp_workspace_size(HK_C64, 2, inner, blocks, vecs, 1, 0, ctypes.byref(b)) == SIZE
+    inner = (ctypes.c_int64 * 2)(30, 20)
+    assert L.block_hankel_tvp_workspace_size(HK_C64, 2, inner, blocks, vecs, 1, 0, ctypes.byref(b)) == OK
+    assert b.value > 0
+
+
+def test_backward_argument_errors(L):
+    h, x, g = P(0x10000), P(0x20000), P(0x30000)
+    assert L.hankel_tvp_backward(HK_F64, h, 3, 10, x, g, None, g, None, None, 0, None) == NOTSUP
+    assert L.hankel_tvp_backward(HK_C64, h, 3, 10, x, g, None, None, None, None, 0, None) == NULLP
+
+
+def test_plan_argument_errors(L):
+    plan = ctypes.c_void_p()
+    assert L.hk_plan_create(ctypes.byref(plan), HK_C64, None, 1, 1) == NULLP
+    assert L.hk_plan_create(ctypes.byref(plan), HK_C64, None, -1, 1) == INVALID
+    assert L.hk_plan_create(ctypes.byref(plan), HK_C64, None, 0, 0x100) == INVALID
+    assert L.hk_plan_create(ctypes.byref(plan), HK_C64, None, 0, 0x3) == INVALID  # persistent + per-pass
+    assert L.hk_plan_create(None, HK_C64, None, 0, 1) == NULLP
+
+
+def test_fft_layout(L):
+    a, r, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    assert L.hk_fft_layout(1048573, ctypes.byref(a), ctypes.byref(r), ctypes.byref(c)) == OK
+    assert (a.value, r.value * c.value) == (1 << 20, 1 << 20)
+    assert L.hk_fft_layout(190, ctypes.byref(a), ctypes.byref(r), ctypes.byref(c)) == OK
+    assert (a.value, r.value, c.value) == (256, 256, 1)   # one workgroup holds it
+    assert L.hk_fft_layout(0, ctypes.byref(a), ctypes.byref(r), ctypes.byref(c)) == INVALID
+
+
+def test_status_strings(L):
+    for code in range(10):
+        assert L.hk_status_string(code)
+    assert L.hk_version() > 0

@@ -1,0 +1,205 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (autotuned plain path, strided batches, persistent plans).
+
+Expected values come from the CPU oracle through tests/golden/make_golden.py
+(sampled outputs; the oracle's direct sums are too slow to run here), and
+from closed forms that hold at any size (Vandermonde generating vectors,
+Section 4.1 / 4.3), which check every output.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1401_6238_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import TOL, host, print_case, rel, to_dev  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    path = os.path.join(GOLD, f"{name}_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated (python tests/golden/make_golden.py)")
+    return np.load(path)
+
+
+def fingerprint(a):
+    a = np.asarray(a, np.complex128)
+    return np.array([a.real.sum(), a.imag.sum(), np.abs(a).sum()])
+
+
+def same_inputs(fp_stored, arr):
+    assert np.allclose(fp_stored, fingerprint(arr), rtol=1e-12, atol=1e-9), "generator drift"
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_config2_golden(dtype):
+    import paper_1401_6238_amd as hk
+    g = golden("config2")
+    tag = "c128" if dtype == torch.complex128 else "c64"
+    print_case(test="config2_golden", dtype=tag)
+    p = wl.config2(0)
+    same_inputs(g["config2_fp_h"], p.h)
+    same_inputs(g["config2_fp_x"], p.vectors[1])
+    hk.hk_autotune_tvp(dtype, 4, p.dims[0])
+    y, a = hk.hankel_tvp(to_dev(p.h, dtype), to_dev(p.vectors[1], dtype), 4, True, True)
+    torch.cuda.synchronize()
+    idx = g["config2_idx"]
+    e = rel(host(y)[idx], g[f"config2_{tag}_y"])
+    ao = complex(g[f"config2_{tag}_alpha"][0])
+    ea = abs(complex(host(a.reshape(1))[0]) - ao) / abs(ao)
+    print(f"config2 {tag}: y rel err {e:.3e}, alpha rel err {ea:.3e}")
+    assert e <= TOL[dtype]
+    assert ea <= TOL[dtype]
+
+
+def test_config2_vandermonde_all_outputs():
+    """Noise-free twin of the config-2 input: every output against the closed form.
+
+    FP64 only: rounding h to complex64 would perturb the exponential sum by
+    more than the closed form can account for (the complex64 path is checked
+    against the oracle on its rounded inputs above)."""
+    import paper_1401_6238_amd as hk
+    dtype = torch.complex128
+    print_case(test="config2_vandermonde", dtype=dtype)
+    p = wl.config2(0, sigma=0.0)
+    params = p.meta["expsum"]
+    n = p.dims[0]
+    x = p.vectors[1]
+    xs = np.asarray(x, np.complex128)
+    y_cf = np.zeros(n, np.clongdouble)
+    a_cf = np.clongdouble(0)
+    for j in range(len(params.a)):
+        zp = wl.powers_ld(params.z[j], n)
+        s = np.sum(np.asarray(xs, np.clongdouble) * zp)
+        y_cf += np.clongdouble(params.a[j]) * s ** 3 * zp
+        a_cf += np.clongdouble(params.a[j]) * s ** 4
+    y, a = hk.hankel_tvp(to_dev(p.h, dtype), to_dev(x, dtype), 4, True, True)
+    e = rel(host(y), y_cf.astype(np.complex128))
+    ea = abs(complex(host(a.reshape(1))[0]) - complex(a_cf)) / abs(complex(a_cf))
+    print(f"vandermonde {dtype}: y {e:.3e} alpha {ea:.3e}")
+    assert e <= TOL[dtype]
+    assert ea <= TOL[dtype]
+
+
+@pytest.mark.parametrize("flags", ["persistent", "per_pass"])
+def test_config3_all_instances(flags):
+    """All 4096 mixed instances in one plan, sampled outputs against the oracle."""
+    import paper_1401_6238_amd as hk
+    from paper_1401_6238_amd import _lib
+    g = golden("config3")
+    print_case(test="config3", flags=flags)
+    dtype = torch.complex64
+    items, probs = [], []
+    for i in range(4096):
+        p = wl.config3_instance(i)
+        probs.append(p)
+        h = to_dev(p.h, dtype)
+        if p.equal:
+            x = to_dev(p.vectors[1], dtype)
+            vecs = [None] + [x] * (p.m - 1)
+        else:
+            vecs = [None] + [to_dev(v, dtype) for v in p.vectors[1:]]
+        items.append({"m": p.m, "dims": p.dims, "h": h, "vectors": vecs})
+    same_inputs(g["config3_fp_h"][0], probs[0].h)
+    same_inputs(g["config3_fp_h"][4095], probs[4095].h)
+    f = _lib.HK_PLAN_PERSISTENT if flags == "persistent" else _lib.HK_PLAN_MULTIKERNEL
+    plan = hk.Plan(items, flags=f)
+    outs = plan.execute()
+    plan.status()
+    off, idx, ys = g["config3_off"], g["config3_idx"], g["config3_y"]
+    worst = 0.0
+    for i in range(4096):
+        sl = slice(off[i], off[i + 1])
+        e = rel(host(outs[i][0])[idx[sl]], ys[sl])
+        worst = max(worst, e)
+    plan.close()
+    print(f"config3 worst instance rel err {worst:.3e}")
+    assert worst <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_config4_forward_and_adjoint(dtype):
+    """Batch of 256 (m=4, n=2^16): forward g, f and gradients of sampled instances."""
+    import paper_1401_6238_amd as hk
+    g = golden("config4")
+    tag = "c128" if dtype == torch.complex128 else "c64"
+    print_case(test="config4", dtype=tag)
+    insts = [int(i) for i in g["config4_instances"]]
+    data = {i: wl.config4_instance(i) for i in insts}
+    for i in insts:
+        same_inputs(g[f"config4_{i}_fp_h"], data[i]["h"])
+    # the 252 other slots repeat instance 0: their results must equal slot 0 bit for bit
+    order = [i if i in data else 0 for i in range(256)]
+    H = torch.stack([to_dev(data[i]["h"], dtype) for i in order])
+    X = torch.stack([to_dev(data[i]["x"], dtype) for i in order])
+    V = torch.stack([to_dev(data[i]["v"], dtype) for i in order])
+    PHI = to_dev(np.array([data[i]["phi"] for i in order]), dtype)
+    gy, f = hk.hankel_tvp_strided_batched(H, X, 4, True, True)
+    gx, gh = hk.hankel_tvp_backward_strided_batched(H, X, 4, V, PHI)
+    torch.cuda.synchronize()
+    tol = TOL[dtype]
+    for i in insts:
+        ix, ih = g[f"config4_{i}_idx_x"], g[f"config4_{i}_idx_h"]
+        assert rel(host(gy[i])[ix], g[f"config4_{i}_{tag}_g"]) <= tol
+        fo = complex(g[f"config4_{i}_{tag}_f"][0])
+        assert abs(complex(host(f[i:i + 1])[0]) - fo) <= tol * abs(fo)
+        assert rel(host(gx[i])[ix], g[f"config4_{i}_{tag}_gx"]) <= tol
+        assert rel(host(gh[i])[ih], g[f"config4_{i}_{tag}_gh"]) <= tol
+    ref = host(gx[0])
+    for b in (2, 77, 200):
+        assert np.array_equal(host(gx[b]), ref)
+        assert np.array_equal(host(gy[b]), host(gy[0]))
+
+
+def test_config5_block_batch():
+    """64 BHHB tensors (m=3, 512 blocks of 512, 2048^2 grid), sampled outputs of tensors 0 and 63."""
+    import paper_1401_6238_amd as hk
+    g = golden("config5")
+    print_case(test="config5")
+    dtype = torch.complex64
+    insts = [int(i) for i in g["config5_instances"]]
+    data = {i: wl.config5_instance(i) for i in insts}
+    for i in insts:
+        same_inputs(g[f"config5_{i}_fp_h"], data[i].h)
+    order = [i if i in data else 0 for i in range(64)]
+    Hs = torch.stack([to_dev(data[i].h, dtype) for i in order])
+    Xs = torch.stack([to_dev(data[i].vectors[1], dtype) for i in order])
+    y, a = hk.block_hankel_tvp_strided_batched(Hs, Xs, 3, 512, 512, True, True)
+    torch.cuda.synchronize()
+    for i in insts:
+        e = rel(host(y[i])[g[f"config5_{i}_idx"]], g[f"config5_{i}_y"])
+        ao = complex(g[f"config5_{i}_alpha"][0])
+        ea = abs(complex(host(a[i:i + 1])[0]) - ao) / abs(ao)
+        print(f"config5 tensor {i}: y {e:.3e} alpha {ea:.3e}")
+        assert e <= TOL[dtype] and ea <= TOL[dtype]
+    for b in (1, 30):
+        assert np.array_equal(host(y[b]), host(y[0]))
+
+
+def test_config5_level2_closed_form():
+    """Noise-free twin of tensor 0: every output against the level-2 Vandermonde form."""
+    import paper_1401_6238_amd as hk
+    dtype = torch.complex128
+    p = wl.config5_instance(0, sigma=0.0)
+    a_, z1, z2, _ = p.meta["expsum2"]
+    nb = 512
+    xs = p.vectors[1].reshape(nb, nb)  # [j, i]
+    Y = np.zeros((nb, nb), np.clongdouble)
+    alpha = np.clongdouble(0)
+    for t in range(len(a_)):
+        p1, p2 = wl.powers_ld(z1[t], nb), wl.powers_ld(z2[t], nb)
+        s = np.sum(np.asarray(xs, np.clongdouble) * np.outer(p2, p1))
+        Y += np.clongdouble(a_[t]) * s * s * np.outer(p2, p1)
+        alpha += np.clongdouble(a_[t]) * s ** 3
+    x = to_dev(p.vectors[1], dtype)
+    y, a = hk.block_hankel_tvp(to_dev(p.h, dtype), [x] * 3, [nb] * 3, [nb] * 3, True, True)
+    e = rel(host(y), Y.astype(np.complex128).ravel())
+    ea = abs(complex(host(a.reshape(1))[0]) - complex(alpha)) / abs(complex(alpha))
+    print(f"config5 closed form: y {e:.3e} alpha {ea:.3e}")
+    assert e <= TOL[dtype] and ea <= TOL[dtype]
