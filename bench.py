@@ -47,23 +47,23 @@ def log(*a):
 # ---------------------------------------------------------------------------
 # CPU-side generation (runs before the GPU is touched; forked workers only)
 # ---------------------------------------------------------------------------
-def _gen_c2(i):
-    p = wl.config2(i)
+def _gen_large(i):
+    p = wl.large_single(i)
     return p.h.astype(np.complex64), p.vectors[1].astype(np.complex64), p.h, p.vectors[1]
 
 
-def _gen_c3(i):
-    p = wl.config3_instance(i)
+def _gen_mixed(i):
+    p = wl.mixed_instance(i)
     return p
 
 
-def _gen_c4(i):
-    d = wl.config4_instance(i)
+def _gen_adjoint(i):
+    d = wl.adjoint_instance(i)
     return d
 
 
-def _gen_c5(i):
-    return wl.config5_instance(i)
+def _gen_block(i):
+    return wl.block_instance(i)
 
 
 def generate(pool_size, extras, workers):
@@ -72,11 +72,11 @@ def generate(pool_size, extras, workers):
     out = {}
     t0 = time.time()
     with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
-        out["c2"] = list(ex.map(_gen_c2, range(pool_size)))
+        out["large"] = list(ex.map(_gen_large, range(pool_size)))
         if extras:
-            out["c3"] = list(ex.map(_gen_c3, range(4096), chunksize=64))
-            out["c4"] = list(ex.map(_gen_c4, range(256), chunksize=8))
-            out["c5"] = list(ex.map(_gen_c5, range(64), chunksize=2))
+            out["mixed"] = list(ex.map(_gen_mixed, range(4096), chunksize=64))
+            out["adjoint"] = list(ex.map(_gen_adjoint, range(256), chunksize=8))
+            out["block"] = list(ex.map(_gen_block, range(64), chunksize=2))
     log(f"generated inputs in {time.time() - t0:.1f}s with {workers} workers")
     return out
 
@@ -101,9 +101,10 @@ def cpu_baseline(x):
     import oracle
     n = len(x)
     threads = oracle.max_threads()
-    # sample: outputs [k0, k1) of the oracle's first convolution x * x, the
-    # step that dominates nothing in particular but runs the same summation
-    # loop as every other stage; scaled by the product's total MAC count.
+    # sample: outputs [k0, k1) of the oracle's first convolution x * x.  Every
+    # stage of the oracle (the repeated convolutions and the final correlation
+    # with h) runs the same blocked multiply-add loop, so the MAC rate of this
+    # slice, divided by the MACs of a whole product, gives products per second.
     half = min(n - 1, 15000 * max(1, threads))
     k0, k1 = n - half, n + half
     macs = sum(min(k, n - 1) - max(0, k - (n - 1)) + 1 for k in range(k0, k1))
@@ -119,6 +120,163 @@ def cpu_baseline(x):
 
 
 # ---------------------------------------------------------------------------
+# rocprofv3 summaries (profiles/) and the traffic figures read back from them
+# ---------------------------------------------------------------------------
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ("hk_fft.hpp", "hk_bodies.hpp", "hk_kernels.hpp", "hk_common.hpp", "hk_inst.hpp",
+                  "hk_launch.hpp", "hk_f32.hip", "hk_f64.hip", "hk_plan.cpp")
+
+
+def kernel_source_hash():
+    """SHA-256 over the device sources and the schedule logic: counters taken
+    from an older build no longer describe the kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1401_6238_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    db = os.path.join(ROOT, "paper_1401_6238_amd", "tune_db.txt")
+    if os.path.exists(db):
+        with open(db, "rb") as fh:
+            h.update(b"tune_db\0" + fh.read())
+    return h.hexdigest()
+
+
+def traffic_path(dtype):
+    return os.path.join(PROFILES, f"passes_large_single_{dtype}_hbm_traffic.txt")
+
+
+def load_traffic(dtype):
+    """{pass: HBM bytes per launch} from the committed counter summary, or None
+    when it is missing or was taken on other kernel sources."""
+    path = traffic_path(dtype)
+    if not os.path.exists(path):
+        return None
+    vals, sha = {}, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("source_sha256:"):
+                sha = line.split(":", 1)[1].strip()
+            elif line.startswith("pass_") and "traffic_bytes=" in line:
+                name = line.split(":", 1)[0]
+                kv = dict(t.split("=") for t in line.split(":", 1)[1].split())
+                vals[name] = int(kv["traffic_bytes"])
+    if sha != kernel_source_hash():
+        log(f"{path} was taken on other kernel sources: traffic reported as null")
+        return None
+    return vals
+
+
+def _read_csv(d, suffix):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {d}")
+    with open(files[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def classify_passes(names):
+    """Pass of each dispatch of the plain multipass product (A, B, D order per
+    product): a column kernel followed by a row kernel is pass A, one that
+    follows a row kernel is pass D."""
+    out = [None] * len(names)
+    hk_idx = [i for i, n in enumerate(names) if "k_cols" in n or "k_rows" in n or "k_alpha" in n]
+    for j, i in enumerate(hk_idx):
+        n = names[i]
+        if "k_rows" in n:
+            out[i] = "pass_b"
+        elif "k_cols" in n:
+            nxt = names[hk_idx[j + 1]] if j + 1 < len(hk_idx) else ""
+            out[i] = "pass_a" if "k_rows" in nxt else "pass_d"
+    return out
+
+
+def summarize_counters(fetch_dir, write_dir, dtype, calib_mib, command):
+    """Per-pass FETCH_SIZE / WRITE_SIZE (KiB per dispatch) scaled by the same
+    counters read on a plain device copy of calib_mib MiB."""
+    res = {}
+    for tag, d, ctr in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = [r for r in _read_csv(d, "counter_collection.csv") if r["Counter_Name"] == ctr]
+        by_disp = {}
+        for r in rows:
+            k = int(r["Dispatch_Id"])
+            by_disp.setdefault(k, [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+        order = sorted(by_disp)
+        names = [by_disp[k][0] for k in order]
+        kinds = classify_passes(names)
+        acc = {}
+        copy_vals = []
+        for k, kind, name in zip(order, kinds, names):
+            v = by_disp[k][1]
+            if kind:
+                acc.setdefault(kind, []).append(v)
+            elif "copy" in name.lower():
+                copy_vals.append(v)
+        if not copy_vals:
+            raise SystemExit(f"{ctr}: no copy dispatches found for the calibration")
+        copy_kib = float(np.median(copy_vals))
+        factor = (calib_mib * 1024.0) / copy_kib
+        res[tag] = {"factor": factor, "copy_kib": copy_kib, "n_copy": len(copy_vals),
+                    "kib": {k: float(np.mean(v)) for k, v in acc.items()},
+                    "n": {k: len(v) for k, v in acc.items()}}
+    esz = 8 if dtype == "c64" else 16
+    alg = {"pass_a": (DH + NVEC + 2 * NFFT) * esz, "pass_b": 3 * NFFT * esz, "pass_d": (NFFT + NVEC) * esz}
+    lines = [
+        f"# HBM traffic per launch, large single product (order 4, n=2^18, d_H=1048573, N=2^20), {dtype}",
+        "# from two rocprofv3 --pmc runs of the same command (FETCH_SIZE, then WRITE_SIZE):",
+        f"#   {command}",
+        f"# counter calibration: a plain device copy of {calib_mib} MiB (8 dispatches in the same run);",
+        f"#   FETCH_SIZE read {res['fetch']['copy_kib']:.1f} KiB per copy -> factor {res['fetch']['factor']:.4f}",
+        f"#   WRITE_SIZE read {res['write']['copy_kib']:.1f} KiB per copy -> factor {res['write']['factor']:.4f}",
+        "# traffic_bytes = (FETCH_SIZE * fetch factor + WRITE_SIZE * write factor) * 1024, mean over dispatches;",
+        "# alg_bytes = the algorithmic bytes of the pass (reads + writes the pass needs at minimum)",
+        f"source_sha256: {kernel_source_hash()}",
+        f"fetch_factor: {res['fetch']['factor']:.6f}",
+        f"write_factor: {res['write']['factor']:.6f}",
+    ]
+    for k in ("pass_a", "pass_b", "pass_d"):
+        if k not in res["fetch"]["kib"] or k not in res["write"]["kib"]:
+            continue
+        fb = res["fetch"]["kib"][k] * res["fetch"]["factor"] * 1024
+        wb = res["write"]["kib"][k] * res["write"]["factor"] * 1024
+        lines.append(f"{k}: fetch_bytes={int(fb)} write_bytes={int(wb)} traffic_bytes={int(fb + wb)} "
+                     f"alg_bytes={alg[k]} ratio={(fb + wb) / alg[k]:.3f} dispatches={res['fetch']['n'][k]}")
+    return "\n".join(lines) + "\n"
+
+
+def summarize_trace(trace_dir, command):
+    """rocprofv3 --kernel-trace --stats summary plus the per-pass split."""
+    stats = _read_csv(trace_dir, "kernel_stats.csv")
+    trace = _read_csv(trace_dir, "kernel_trace.csv")
+    trace.sort(key=lambda r: int(r["Start_Timestamp"]))
+    names = [r["Kernel_Name"] for r in trace]
+    kinds = classify_passes(names)
+    per = {}
+    for r, k in zip(trace, kinds):
+        if k:
+            per.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = ["# rocprofv3 kernel trace of the benchmark (large single product, order 4, n=2^18, N=2^20)",
+             f"#   {command}", "", "## per-kernel statistics (rocprofv3 --stats)",
+             "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
+    for r in stats:
+        nm = r["Name"]
+        short = nm if len(nm) < 90 else nm[:87] + "..."
+        lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['Percentage']):.1f} |")
+    lines += ["", "## per pass of the product (dispatch order: A, B, D)", "| pass | dispatches | avg us | median us |",
+              "|---|---|---|---|"]
+    for k in ("pass_a", "pass_b", "pass_d"):
+        if k in per:
+            v = np.array(per[k])
+            lines.append(f"| {k} | {len(v)} | {v.mean():.2f} | {np.median(v):.2f} |")
+    return "\n".join(lines) + "\n"
+
+
+# ---------------------------------------------------------------------------
 # GPU measurements
 # ---------------------------------------------------------------------------
 def main():
@@ -130,14 +288,35 @@ def main():
     ap.add_argument("--pool", type=int, default=32)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="autotune every shape at run time")
+    ap.add_argument("--tune-save", default=None, help="write the schedule database here after tuning")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="also run 8 plain device copies of this many MiB (counter calibration)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--profile-delay-cycles", type=float, default=2e8,
+                    help="length of the delay kernel queued before the profiled pass")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 4))
+    ap.add_argument("--summarize-trace", metavar="DIR", help="write profiles/ summary of a rocprofv3 kernel trace")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the per-pass HBM traffic summary from two rocprofv3 --pmc runs")
+    ap.add_argument("--profiled-command", default="", help="command line recorded in the summaries")
+    ap.add_argument("--out", default=None)
     args = ap.parse_args()
+    if args.summarize_trace or args.summarize_counters:
+        if args.summarize_trace:
+            txt = summarize_trace(args.summarize_trace, args.profiled_command)
+        else:
+            txt = summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.dtype,
+                                     args.copy_calib, args.profiled_command)
+        if args.out:
+            with open(args.out, "w") as fh:
+                fh.write(txt)
+        print(txt)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this implementation runs on a single MI355X "
-              "(the multi-GPU sharding is described in DESIGN.md, not built).", file=sys.stderr)
+        print("bench.py measures one GPU only: the product runs on a single MI355X and no multi-GPU "
+              "path is built.", file=sys.stderr)
         sys.exit(2)
     extras = not args.no_extras
     data = generate(args.pool, extras, args.workers)
@@ -155,8 +334,8 @@ def main():
 
     # inputs resident in HBM before timing
     P = args.pool
-    hs = [torch.from_numpy(d[2] if tdt == torch.complex128 else d[0]).to(tdt).to(dev) for d in data["c2"]]
-    xs = [torch.from_numpy(d[3] if tdt == torch.complex128 else d[1]).to(tdt).to(dev) for d in data["c2"]]
+    hs = [torch.from_numpy(d[2] if tdt == torch.complex128 else d[0]).to(tdt).to(dev) for d in data["large"]]
+    xs = [torch.from_numpy(d[3] if tdt == torch.complex128 else d[1]).to(tdt).to(dev) for d in data["large"]]
     ys = [torch.empty(NVEC, dtype=tdt, device=dev) for _ in range(P)]
     als = torch.empty(P, dtype=tdt, device=dev)
     nb = ctypes.c_size_t(0)
@@ -170,11 +349,13 @@ def main():
     ap_ = [ctypes.c_void_p(als.data_ptr() + i * esz) for i in range(P)]
     wsp, wsb = ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(nb.value)
 
-    if not args.no_tune:
+    if args.tune:
         # in-house autotuner: times the schedule variants of this shape and
-        # caches the fastest for the calls below
+        # caches the fastest for the calls below (otherwise the schedules
+        # come from the package's shipped database, tune_db.txt)
         t0 = time.time()
-        hk.hk_autotune_tvp(tdt, M, NVEC, verbose=args.verbose)
+        for d in (torch.complex64, torch.complex128):
+            hk.hk_autotune_tvp(d, M, NVEC, verbose=args.verbose)
         log(f"autotune took {time.time() - t0:.2f}s")
 
     def step(i, sptr):
@@ -219,10 +400,14 @@ def main():
     t_wall = time.perf_counter() - t_wall
     ms = e0.elapsed_time(e1) / steps
     value = 1000.0 / ms
-    log(f"config2 {args.dtype}: {ms * 1e3:.1f} us/product, {value:.1f} TVP/s "
+    log(f"large single product {args.dtype}: {ms * 1e3:.1f} us/product, {value:.1f} TVP/s "
         f"(host {t_wall * 1e6 / steps:.1f} us/step, graph={graph is not None})")
 
-    # per-kernel durations from HIP events recorded by the library on `stream`
+    # per-kernel durations from HIP events recorded by the library on `stream`.
+    # A bounded delay kernel is queued first so that the host enqueues the
+    # profiled launches ahead of the GPU: the events then bracket kernels that
+    # run back to back, as in the timed region, not host launch latency.
+    torch.cuda._sleep(int(args.profile_delay_cycles))
     hk.hk_profile_start()
     for i in range(steps):
         step(i, sp)
@@ -252,7 +437,7 @@ def main():
         "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": "config2: order-4 square Hankel tensor, n=2^18, d_H=1048573, N=2^20; "
+        "config": {"workload": "large single product: order-4 square Hankel tensor, n=2^18, d_H=1048573, N=2^20; "
                                "y=Hx^3 and alpha=Hx^4 per step; h = 8-term exponential sum + CN(0,1e-6) noise, "
                                f"x ~ CN(0,1/n); pool of {P} instances",
                    "m": M, "n": NVEC, "fft_len": NFFT, "pool": P, "hip_graph": graph is not None},
@@ -260,12 +445,31 @@ def main():
         "compulsory_GB_s": round(compulsory / (ms * 1e-3) / 1e9, 1),
     }
 
+    traffic = load_traffic(args.dtype)
+    if traffic is not None and dom in traffic:
+        roofline["traffic"] = traffic[dom]
+
+    if args.copy_calib:
+        # a plain device-to-device copy of known size: FETCH_SIZE / WRITE_SIZE
+        # of these dispatches give the counter-to-bytes factors
+        nbytes = args.copy_calib << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(8):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(data["c2"][0][3])
+        out["cpu_baseline"] = cpu_baseline(data["large"][0][3])
         log("cpu baseline", out["cpu_baseline"])
 
     if extras:
         out["extras"] = run_extras(args, data, hk, _lib, L, torch, dev)
+
+    if args.tune_save:
+        hk.hk_tune_save(args.tune_save)
+        log("schedule database written to", args.tune_save)
 
     print(json.dumps(out), flush=True)
 
@@ -286,11 +490,11 @@ def time_region(torch, fn, reps, warm=2):
 
 def run_extras(args, data, hk, _lib, L, torch, dev):
     ex = {}
-    # config 2 in complex128 (same inputs, FP64 arithmetic)
+    # the large single product in complex128 (same inputs, FP64 arithmetic)
     if args.dtype == "c64":
         P = 16
-        hs = [torch.from_numpy(d[2]).to(dev) for d in data["c2"][:P]]
-        xs = [torch.from_numpy(d[3]).to(dev) for d in data["c2"][:P]]
+        hs = [torch.from_numpy(d[2]).to(dev) for d in data["large"][:P]]
+        xs = [torch.from_numpy(d[3]).to(dev) for d in data["large"][:P]]
         it = [0]
 
         def one():
@@ -298,14 +502,14 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
             it[0] += 1
             hk.hankel_tvp(hs[k], xs[k], M, True, True)
         ms = time_region(torch, one, 50)
-        ex["config2_c128"] = {"TVP_s": round(1000 / ms, 1), "ms": round(ms, 4)}
+        ex["large_single_c128"] = {"TVP_s": round(1000 / ms, 1), "ms": round(ms, 4)}
         del hs, xs
-        log("c128", ex["config2_c128"])
+        log("c128", ex["large_single_c128"])
 
-    # config 3: 4096 mixed instances, one persistent launch vs per-pass launches vs plain loop
-    c3 = data["c3"]
+    # mixed batch: 4096 instances, one persistent launch vs per-pass launches vs plain loop
+    mixed = data["mixed"]
     items = []
-    for p in c3:
+    for p in mixed:
         h = torch.from_numpy(p.h).to(torch.complex64).to(dev)
         if p.equal:
             x = torch.from_numpy(p.vectors[1]).to(torch.complex64).to(dev)
@@ -314,7 +518,7 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
             vecs = [None] + [torch.from_numpy(v).to(torch.complex64).to(dev) for v in p.vectors[1:]]
         items.append({"m": p.m, "dims": p.dims, "h": h, "vectors": vecs})
     res = {}
-    for name, flags in (("persistent", _lib.HK_PLAN_PERSISTENT), ("per_pass", _lib.HK_PLAN_MULTIKERNEL)):
+    for name, flags in (("persistent", _lib.HK_PLAN_PERSISTENT), ("grouped", _lib.HK_PLAN_MULTIKERNEL)):
         plan = hk.Plan(items, flags=flags)
         ms = time_region(torch, plan.execute, 10)
         plan.status()
@@ -333,19 +537,24 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
             hk.hankel_mode_products(it_["h"], it_["vectors"], it_["dims"], True, False)
     ms = time_region(torch, plain_loop, 2, warm=1)
     res["plain_loop"] = {"TVP_s": round(len(items) / ms * 1000, 1), "ms_per_batch": round(ms, 3)}
-    ex["config3_batched_c64"] = res
-    log("config3", res)
+    ex["mixed_batch_c64"] = res
+    log("mixed batch", res)
     del items
 
-    # config 4: batch 256, m=4, n=2^16: forward (g, f) and adjoint, c64 and c128
-    c4 = data["c4"]
+    # adjoint batch: 256 instances, m=4, n=2^16: forward (g, f) and adjoint, c64 and c128
+    adj = data["adjoint"]
     res4 = {}
     for tdt in (torch.complex64, torch.complex128):
-        H = torch.stack([torch.from_numpy(d["h"]) for d in c4]).to(tdt).to(dev)
-        X = torch.stack([torch.from_numpy(d["x"]) for d in c4]).to(tdt).to(dev)
-        V = torch.stack([torch.from_numpy(d["v"]) for d in c4]).to(tdt).to(dev)
-        PHI = torch.tensor([d["phi"] for d in c4], dtype=tdt, device=dev)
+        H = torch.stack([torch.from_numpy(d["h"]) for d in adj]).to(tdt).to(dev)
+        X = torch.stack([torch.from_numpy(d["x"]) for d in adj]).to(tdt).to(dev)
+        V = torch.stack([torch.from_numpy(d["v"]) for d in adj]).to(tdt).to(dev)
+        PHI = torch.tensor([d["phi"] for d in adj], dtype=tdt, device=dev)
         B = H.shape[0]
+        if args.tune:
+            t0 = time.time()
+            hk.hk_autotune(tdt, "forward", 4, X.shape[1], batch=B, verbose=args.verbose)
+            hk.hk_autotune(tdt, "adjoint", 4, X.shape[1], batch=B, verbose=args.verbose)
+            log(f"adjoint batch autotune ({tdt}) took {time.time() - t0:.1f}s")
         ms_f = time_region(torch, lambda: hk.hankel_tvp_strided_batched(H, X, 4, True, True), 5)
         ms_b = time_region(torch, lambda: hk.hankel_tvp_backward_strided_batched(H, X, 4, V, PHI), 5)
 
@@ -357,21 +566,26 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
         res4[key] = {"fwd_batched_TVP_s": round(B / ms_f * 1000, 1), "bwd_batched_per_s": round(B / ms_b * 1000, 1),
                      "fwd_plain_loop_TVP_s": round(B / ms_p * 1000, 1), "bwd_over_fwd_time": round(ms_b / ms_f, 3)}
         del H, X, V, PHI
-    ex["config4_adjoint"] = res4
-    log("config4", res4)
+    ex["adjoint_batch"] = res4
+    log("adjoint batch", res4)
 
-    # config 5: 64 BHHB tensors, m=3, 512 blocks of 512, 2048^2 grid, c64
-    c5 = data["c5"]
-    Hs = torch.stack([torch.from_numpy(p.h) for p in c5]).to(torch.complex64).to(dev)
-    Xs = torch.stack([torch.from_numpy(p.vectors[1]) for p in c5]).to(torch.complex64).to(dev)
+    # block batch: 64 BHHB tensors, m=3, 512 blocks of 512, 2048^2 grid, c64
+    blk = data["block"]
+    Hs = torch.stack([torch.from_numpy(p.h) for p in blk]).to(torch.complex64).to(dev)
+    Xs = torch.stack([torch.from_numpy(p.vectors[1]) for p in blk]).to(torch.complex64).to(dev)
+    if args.tune:
+        t0 = time.time()
+        hk.hk_autotune(torch.complex64, "block", 3, inner=[512] * 3, blocks=[512] * 3, batch=Hs.shape[0],
+                       verbose=args.verbose)
+        log(f"block batch autotune took {time.time() - t0:.1f}s")
     ms5 = time_region(torch, lambda: hk.block_hankel_tvp_strided_batched(Hs, Xs, 3, 512, 512, True, True), 3)
 
     def plain5():
         for b in range(Hs.shape[0]):
             hk.block_hankel_tvp(Hs[b], [Xs[b]] * 3, [512] * 3, [512] * 3, True, True)
     ms5p = time_region(torch, plain5, 1, warm=1)
-    ex["config5_block_c64"] = {"batched_TVP_s": round(64 / ms5 * 1000, 2), "plain_loop_TVP_s": round(64 / ms5p * 1000, 2)}
-    log("config5", ex["config5_block_c64"])
+    ex["block_batch_c64"] = {"batched_TVP_s": round(64 / ms5 * 1000, 2), "plain_loop_TVP_s": round(64 / ms5p * 1000, 2)}
+    log("block batch", ex["block_batch_c64"])
     return ex
 
 

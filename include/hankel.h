@@ -151,14 +151,18 @@ typedef struct {
 typedef struct hk_plan_s *hk_plan_t;
 
 #define HK_PLAN_PERSISTENT 0x1u /* one persistent launch with an in-kernel task queue          */
-#define HK_PLAN_MULTIKERNEL 0x2u /* one launch per pass (per-pass profiling; same kernels)     */
+#define HK_PLAN_MULTIKERNEL 0x2u /* grouped launches: per phase, one kernel specialised for each
+                                   (task kind, transform length) group; no in-kernel waits      */
 #define HK_PLAN_GRAPH 0x4u      /* capture the plan's launches in a hipGraph on first execute */
 #define HK_PLAN_AUTOTUNE 0x8u   /* reserved (accepted, no effect)                             */
 
 /* Creates a plan for `count` problems.  The plan copies the descriptors
  * (pointers included); on first execute it uploads them to a device table
  * that it owns until hk_plan_destroy.  With HK_PLAN_GRAPH it also owns a
- * captured graph.  flags = 0 picks the persistent schedule. */
+ * captured graph.  flags without PERSISTENT pick the grouped launches (the
+ * faster schedule on MI355X); PERSISTENT runs the whole batch in one launch
+ * whose workgroups pull tasks from a queue and wait (bounded) on per-instance
+ * completion counters. */
 hk_status_t hk_plan_create(hk_plan_t *plan, hk_dtype_t dt, const hk_problem_t *probs,
                            int64_t count, unsigned flags);
 hk_status_t hk_plan_workspace_size(hk_plan_t plan, size_t *bytes);
@@ -171,9 +175,9 @@ hk_status_t hk_plan_execute(hk_plan_t plan, void *ws, size_t ws_bytes, hipStream
 hk_status_t hk_plan_status(hk_plan_t plan);
 hk_status_t hk_plan_destroy(hk_plan_t plan);
 
-/* One-shot convenience: plan, execute with the descriptor tables kept in the
- * workspace, then wait for `stream` and free the plan (this call blocks until
- * the batch has finished). */
+/* One-shot convenience: plan (grouped launches), execute with the descriptor
+ * tables kept in the workspace, then wait for `stream` and free the plan
+ * (this call blocks until the batch has finished). */
 hk_status_t hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs,
                                               int64_t count, size_t *bytes);
 hk_status_t hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t count,
@@ -252,6 +256,17 @@ hk_status_t hk_autotune_tvp(hk_dtype_t dt, int m, int64_t n, int verbose);
 #define HK_TUNE_BLOCK 2
 hk_status_t hk_autotune(hk_dtype_t dt, int kind, int m, int64_t n, const int64_t *inner_dims,
                         const int64_t *block_dims, int64_t batch, int verbose);
+
+/* Schedule database.  hk_tune_save writes every cached schedule (autotuned or
+ * loaded) to a text file, one line per shape key; hk_tune_load merges such a
+ * file into the cache (*n_loaded = entries read, may be NULL) so that a
+ * process can reuse schedules tuned earlier on the same kind of device
+ * without running the autotuner.  A malformed or out-of-range line rejects
+ * the whole file with HK_ERR_INVALID_VALUE and leaves the cache unchanged;
+ * loaded entries that the kernels cannot run are ignored at use time.  Host
+ * only: no device work. */
+hk_status_t hk_tune_save(const char *path);
+hk_status_t hk_tune_load(const char *path, int *n_loaded);
 /* Number of the library's kernel launches enqueued by the last call made on
  * this thread (diagnostics). */
 int hk_last_launch_count(void);

@@ -78,6 +78,8 @@ _SIGS = {
     "hk_fft_layout": [_I64, _PI64, _PI64, _PI64],
     "hk_autotune_tvp": [_I, _I, _I64, _I],
     "hk_autotune": [_I, _I, _I, _I64, _PI64, _PI64, _I64, _I],
+    "hk_tune_save": [ctypes.c_char_p],
+    "hk_tune_load": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)],
     "hk_last_launch_count": [],
     "hk_profile_start": [],
     "hk_profile_stop": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
@@ -87,6 +89,7 @@ _SIGS = {
 }
 
 _lib = None
+TUNE_DB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_db.txt")
 
 
 def lib():
@@ -105,6 +108,12 @@ def lib():
         L.hk_status_string.restype = ctypes.c_char_p
         L.hk_last_error.restype = ctypes.c_char_p
         _lib = L
+        # schedules measured on MI355X and shipped with the package
+        if os.path.exists(TUNE_DB_PATH) and not os.environ.get("HK_NO_TUNE_DB"):
+            n = ctypes.c_int(0)
+            rc = L.hk_tune_load(TUNE_DB_PATH.encode(), ctypes.byref(n))
+            if rc != 0:
+                raise RuntimeError(f"{TUNE_DB_PATH}: " + L.hk_last_error().decode(errors="replace"))
     return _lib
 
 

@@ -223,7 +223,7 @@ class Plan:
     block_dims (BHHB), want_y (default True), want_alpha (default False).
     The plan allocates each problem's outputs; results are in .outputs."""
 
-    def __init__(self, problems, flags: int = _lib.HK_PLAN_PERSISTENT):
+    def __init__(self, problems, flags: int = 0):
         self.problems = list(problems)
         self.outputs = []
         arr = (_lib.hk_problem_t * max(1, len(self.problems)))()
@@ -312,6 +312,16 @@ def hk_autotune(dtype: torch.dtype, kind: str, m: int, n: int = 0, inner=None, b
     di = _i64arr(inner) if inner is not None else None
     db = _i64arr(blocks) if blocks is not None else None
     check(lib().hk_autotune(_DT[dtype], k, m, n, di, db, batch, int(verbose)), "hk_autotune")
+
+
+def hk_tune_save(path: str):
+    check(lib().hk_tune_save(str(path).encode()), "hk_tune_save")
+
+
+def hk_tune_load(path: str) -> int:
+    n = ctypes.c_int(0)
+    check(lib().hk_tune_load(str(path).encode(), ctypes.byref(n)), "hk_tune_load")
+    return n.value
 
 
 def hk_last_launch_count() -> int:

@@ -417,7 +417,7 @@ hk_status_t hk_plan_destroy(hk_plan_t plan) { return finish(plan_destroy(plan));
 hk_status_t hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs, int64_t count, size_t *bytes) {
   if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
   hk_plan_t plan = nullptr;
-  Status s = plan_create(&plan, dt, probs, count, HK_PLAN_PERSISTENT);
+  Status s = plan_create(&plan, dt, probs, count, 0);
   if (!s.ok()) return finish(s);
   s = plan_ws_size(plan, bytes);
   plan_destroy(plan);
@@ -427,7 +427,7 @@ hk_status_t hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t 
 hk_status_t hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t count, void *ws, size_t ws_bytes,
                                hipStream_t stream) {
   hk_plan_t plan = nullptr;
-  Status s = plan_create(&plan, dt, probs, count, HK_PLAN_PERSISTENT);
+  Status s = plan_create(&plan, dt, probs, count, 0);
   if (!s.ok()) return finish(s);
   plan_set_oneshot(plan);
   s = plan_execute(plan, ws, ws_bytes, stream);
@@ -448,6 +448,10 @@ hk_status_t hk_profile_stop(double *ms_by_kind, int64_t *launches_by_kind) {
 hk_status_t hk_autotune_tvp(hk_dtype_t dt, int m, int64_t n, int verbose) {
   return finish(autotune_tvp(dt, m, n, verbose != 0));
 }
+
+hk_status_t hk_tune_save(const char *path) { return finish(sched_save(path)); }
+
+hk_status_t hk_tune_load(const char *path, int *n_loaded) { return finish(sched_load(path, n_loaded)); }
 
 hk_status_t hk_autotune(hk_dtype_t dt, int kind, int m, int64_t n, const int64_t *inner_dims,
                         const int64_t *block_dims, int64_t batch, int verbose) {

@@ -39,7 +39,15 @@ struct hk_plan_s {
   bool tables_in_ws = false;
   // device copies of the tables (plan-owned) or offsets inside the workspace
   char *d_tables = nullptr;
-  size_t off_shapes = 0, off_ptrs = 0, off_tasks = 0, off_res = 0;
+  size_t off_shapes = 0, off_ptrs = 0, off_tasks = 0, off_res = 0, off_order = 0;
+  // grouped launches: task indices sorted by (phase, kind, length) and the
+  // launch list over them
+  struct Group {
+    int kind, logL;
+    int32_t begin, count;
+  };
+  std::vector<int32_t> order;
+  std::vector<Group> launches;
   std::vector<char> host_tables;
   int grid = 1;
   bool persistent = true;
@@ -65,6 +73,8 @@ static void tables_layout(hk_plan_s *p) {
   off = align256(off + sizeof(Task) * std::max<size_t>(1, p->tasks.size()));
   p->off_res = off;
   off = align256(off + sizeof(int32_t) * std::max<size_t>(1, p->res_list.size()));
+  p->off_order = off;
+  off = align256(off + sizeof(int32_t) * std::max<size_t>(1, p->order.size()));
   p->tables_bytes = off;
   p->host_tables.assign(off, 0);
   memcpy(p->host_tables.data() + p->off_shapes, p->shapes.data(), sizeof(Shape) * p->shapes.size());
@@ -72,6 +82,50 @@ static void tables_layout(hk_plan_s *p) {
   if (!p->tasks.empty()) memcpy(p->host_tables.data() + p->off_tasks, p->tasks.data(), sizeof(Task) * p->tasks.size());
   if (!p->res_list.empty())
     memcpy(p->host_tables.data() + p->off_res, p->res_list.data(), sizeof(int32_t) * p->res_list.size());
+  if (!p->order.empty())
+    memcpy(p->host_tables.data() + p->off_order, p->order.data(), sizeof(int32_t) * p->order.size());
+}
+
+// Sorts each phase's tasks by (kind, transform length) and records one launch
+// per run of equal keys.
+static void build_groups(hk_plan_s *p) {
+  p->order.clear();
+  p->launches.clear();
+  int32_t b = 0;
+  for (int ph = 0; ph < 3; ++ph) {
+    const int32_t e = p->phase_end[ph];
+    std::vector<std::pair<std::pair<int, int>, int32_t>> keyed;
+    for (int32_t i = b; i < e; ++i) {
+      const Task &t = p->tasks[i];
+      int kind, logL;
+      if (t.type == TASK_RES) {
+        kind = GK_RES;
+        logL = p->shapes[p->res_list[t.inst]].logR;
+      } else if (t.type == TASK_ROWB) {
+        kind = GK_ROWB;
+        logL = p->shapes[t.inst].logR;
+      } else if (t.type == TASK_ALPHA) {
+        kind = GK_ALPHA;
+        logL = 0;
+      } else {
+        kind = GK_COL;
+        logL = p->shapes[t.inst].logC;
+      }
+      keyed.push_back({{kind, logL}, i});
+    }
+    // longest transforms first within a phase
+    std::stable_sort(keyed.begin(), keyed.end(), [](const auto &x, const auto &y) {
+      if (x.first.first != y.first.first) return x.first.first < y.first.first;
+      return x.first.second > y.first.second;
+    });
+    for (size_t k = 0; k < keyed.size(); ++k) {
+      if (k == 0 || keyed[k].first != keyed[k - 1].first)
+        p->launches.push_back({keyed[k].first.first, keyed[k].first.second, (int32_t)p->order.size(), 0});
+      p->order.push_back(keyed[k].second);
+      p->launches.back().count++;
+    }
+    b = e;
+  }
 }
 
 static Problem problem_of(hk_dtype_t dt, const hk_problem_t &q) {
@@ -107,7 +161,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
   p->dt = dt;
   p->flags = flags;
   p->count = count;
-  p->persistent = !(flags & HK_PLAN_MULTIKERNEL);
+  p->persistent = (flags & HK_PLAN_PERSISTENT) != 0;
   int blk, er, ec;
   size_t lds;
   if (dbl(dt))
@@ -218,6 +272,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
     }
   }
   p->phase_end[2] = (int32_t)p->tasks.size();
+  build_groups(p);
   tables_layout(p);
   int dev = 0, ncu = 256;
   hipDeviceProp_t prop;
@@ -255,6 +310,7 @@ static Status enqueue(hk_plan_s *p, char *ws, hipStream_t st) {
   A.shapes = (const Shape *)(tables + p->off_shapes);
   A.ptrs = (const Ptrs *)(tables + p->off_ptrs);
   A.res_list = (const int32_t *)(tables + p->off_res);
+  A.order = (const int32_t *)(tables + p->off_order);
   A.bctl = (BatchCtl *)ws;
   A.ictl = (InstCtl *)(ws + align256(sizeof(BatchCtl)));
   A.ws_base = ws + p->ctl_bytes + p->tables_bytes;
@@ -276,19 +332,18 @@ static Status enqueue(hk_plan_s *p, char *ws, hipStream_t st) {
     e = launch(A, p->grid, true);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
   } else {
-    int32_t b = 0;
-    bool first = true;
-    for (int ph = 0; ph < 3; ++ph) {
-      const int32_t en = p->phase_end[ph];
-      if (en > b) {
-        A.begin = b;
-        A.end = en;
-        A.use_queue = 0;
-        e = launch(A, en - b, first);
-        if (e != hipSuccess) return hip_fail(e, "batched phase launch");
-        first = false;
-      }
-      b = en;
+    // one specialised launch per (phase, kind, length) group; the stream
+    // orders the phases
+    A.use_queue = 0;
+    for (const auto &g : p->launches) {
+      A.begin = g.begin;
+      A.end = g.begin + g.count;
+      count_launch();
+      prof_before(st);
+      e = dbl(p->dt) ? launch_group_f64(A, g.kind, g.logL, g.count, st)
+                     : launch_group_f32(A, g.kind, g.logL, g.count, st);
+      prof_after(PK_BATCH, st);
+      if (e != hipSuccess) return hip_fail(e, "grouped batch launch");
     }
   }
   return Status();
@@ -420,18 +475,20 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
     for (int er : {8, 16})
       for (int rows : {1, 2, 4, 8, 16, 32})
         for (int ec : {8, 16})
-          for (int tw : {1, 2, 4, 8, 16, 32}) {
-            if (lay.resident && (ec != 8 || tw != 1)) continue;
-            Sched sc;
-            sc.E_row = er;
-            sc.rows_per_wg = rows;
-            sc.E_col = ec;
-            sc.tw = tw;
-            sc.split = sp;
-            if (!sched_valid(dt, lay, sc)) continue;
-            cands.push_back(sc);
-            lays.push_back(lay);
-          }
+          for (int tw : {1, 2, 4, 8, 16, 32})
+            for (int xcd : {0, 1}) {
+              if (lay.resident && (ec != 8 || tw != 1 || xcd != 0)) continue;
+              Sched sc;
+              sc.E_row = er;
+              sc.rows_per_wg = rows;
+              sc.E_col = ec;
+              sc.tw = tw;
+              sc.split = sp;
+              sc.xcd = xcd;
+              if (!sched_valid(dt, lay, sc)) continue;
+              cands.push_back(sc);
+              lays.push_back(lay);
+            }
   }
   if (cands.empty()) return fail(HK_ERR_NOT_SUPPORTED, "no schedule candidates");
   // buffer sizes
@@ -451,15 +508,22 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
     build_shape(p, lays[i], cands[i], &sh, &P, nullptr);
     wsb = std::max(wsb, instance_ws_bytes(sh, dt));
   }
+  // Distinct inputs per instance, and for single products a pool of input
+  // sets larger than the 256 MB last-level cache that successive launches
+  // cycle through: schedules are timed with their inputs coming from HBM,
+  // as in use.
+  const int64_t in_bytes = (hlen + vmax) * (int64_t)eb;
+  const int64_t pool = batch > 1 ? 1 : std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)384 << 20) / in_bytes + 1));
+  const int64_t nin = batch > 1 ? batch : pool;
   void *dh = nullptr, *dx = nullptr, *dy = nullptr, *dy1 = nullptr, *da = nullptr, *dws = nullptr;
-  hipError_t e = hipMalloc(&dh, hlen * eb);
-  if (e == hipSuccess) e = hipMalloc(&dx, vmax * eb);
+  hipError_t e = hipMalloc(&dh, nin * hlen * eb);
+  if (e == hipSuccess) e = hipMalloc(&dx, nin * vmax * eb);
   if (e == hipSuccess) e = hipMalloc(&dy, batch * ylen * eb);
   if (e == hipSuccess) e = hipMalloc(&dy1, batch * ylen * eb);
   if (e == hipSuccess) e = hipMalloc(&da, batch * 2 * eb);
   if (e == hipSuccess && wsb) e = hipMalloc(&dws, batch * wsb);
-  if (e == hipSuccess) e = hipMemset(dh, 0, hlen * eb);
-  if (e == hipSuccess) e = hipMemset(dx, 0, vmax * eb);
+  if (e == hipSuccess) e = hipMemset(dh, 0, nin * hlen * eb);
+  if (e == hipSuccess) e = hipMemset(dx, 0, nin * vmax * eb);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -478,7 +542,7 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
       if (p.gh) p.gh = dy;
       if (p.gx) p.gx = dy1;
     }
-    const int reps = batch > 8 ? 2 : 5;
+    const int reps = batch > 8 ? 2 : (batch > 1 ? 5 : (int)std::max<int64_t>(16, pool));
     for (size_t i = 0; i < cands.size() && s.ok(); ++i) {
       Shape sh;
       Ptrs P;
@@ -486,22 +550,32 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
       P.ws = dws;
       Strides str;
       memset(&str, 0, sizeof(str));
+      int64_t op_stride[MAXOPS];
+      for (int o = 0; o < sh.nops; ++o) op_stride[o] = (sh.ops[o].role == ROLE_H ? hlen : vmax) * (int64_t)eb;
+      if (batch > 1)
+        for (int o = 0; o < sh.nops; ++o) str.op[o] = op_stride[o];
       str.y = ylen * eb;
       str.out1 = ylen * eb;
       str.alpha = eb;
       str.ws = (int64_t)instance_ws_bytes(sh, dt);
-      s = launch_shape(dt, sh, cands[i], P, str, batch, nullptr);  // warm-up
+      Ptrs P0 = P;
+      auto launch_k = [&](int k) {
+        if (batch == 1)
+          for (int o = 0; o < sh.nops; ++o) P.op[o] = (const char *)P0.op[o] + (k % pool) * op_stride[o];
+        return launch_shape(dt, sh, cands[i], P, str, batch, nullptr);
+      };
+      s = launch_k(0);  // warm-up
       if (!s.ok()) break;
       (void)hipEventRecord(e0, nullptr);
-      for (int r = 0; r < reps && s.ok(); ++r) s = launch_shape(dt, sh, cands[i], P, str, batch, nullptr);
+      for (int r = 0; r < reps && s.ok(); ++r) s = launch_k(r + 1);
       (void)hipEventRecord(e1, nullptr);
       (void)hipEventSynchronize(e1);
       float ms = 0;
       (void)hipEventElapsedTime(&ms, e0, e1);
       const double t = ms / reps;
       if (verbose)
-        fprintf(stderr, "[hk autotune] split=%d E_row=%d rows=%d E_col=%d tw=%d : %.4f ms\n", cands[i].split,
-                cands[i].E_row, cands[i].rows_per_wg, cands[i].E_col, cands[i].tw, t);
+        fprintf(stderr, "[hk autotune] split=%d E_row=%d rows=%d E_col=%d tw=%d xcd=%d : %.4f ms\n",
+                cands[i].split, cands[i].E_row, cands[i].rows_per_wg, cands[i].E_col, cands[i].tw, cands[i].xcd, t);
       if (t < best) {
         best = t;
         besti = (int)i;
@@ -524,9 +598,9 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   sched_store(dt, p.prog, p.is_block ? 1 : 0, lay0.logR + lay0.logC, p.is_block ? lay0.logC : -1, batch,
               cands[besti]);
   if (verbose)
-    fprintf(stderr, "[hk autotune] best: split=%d (R=2^%d C=2^%d) E_row=%d rows=%d E_col=%d tw=%d %.4f ms\n",
+    fprintf(stderr, "[hk autotune] best: split=%d (R=2^%d C=2^%d) E_row=%d rows=%d E_col=%d tw=%d xcd=%d %.4f ms\n",
             cands[besti].split, bl.logR, bl.logC, cands[besti].E_row, cands[besti].rows_per_wg, cands[besti].E_col,
-            cands[besti].tw, best);
+            cands[besti].tw, cands[besti].xcd, best);
   return Status();
 }
 

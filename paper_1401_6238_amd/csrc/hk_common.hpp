@@ -144,7 +144,11 @@ struct BatchArgs {
   int32_t begin, end;   // task range of this launch
   int32_t use_queue;    // 1: persistent workgroups pull tasks and honour dependencies
   uint32_t spin_limit;  // bound on dependency polling iterations
+  const int32_t *order; // grouped launches: task indices sorted by (phase, kind, length)
 };
+
+// Grouped launches: one specialised kernel per (task kind, transform length).
+enum GroupKind : int { GK_RES = 0, GK_ROWB = 1, GK_COL = 2, GK_ALPHA = 3 };
 
 
 }  // namespace hk

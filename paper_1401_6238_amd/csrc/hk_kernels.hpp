@@ -23,6 +23,7 @@ static __device__ cx<T> g_tw24[4096];
 struct ColJobs {
   ColJob j[MAXOPS];
   int32_t n;
+  int32_t xcd;  // 1: XCD-local tile numbering (xcd_local_tile)
 };
 
 // Rows of length L: resident instances (blockIdx.x * rows + rw) or pass-B
@@ -91,16 +92,38 @@ __global__ void __launch_bounds__(256) k_alpha(Shape sh, Ptrs p0, Strides str, i
   reduce_partials(sh, P, count, red);
 }
 
+// Workgroups are dealt to the eight XCDs round-robin by linear id.  The
+// column passes renumber them so that each XCD runs one contiguous eighth of
+// the column tiles of every (job, instance) slice: neighbouring tiles share
+// 128-byte lines (a tile is TW elements wide), which then meet in the same
+// L2 instead of being fetched and written back once per XCD, and every XCD
+// gets the same share of each operand.  Slices are taken in order, so the
+// tiles running at one time are close in memory.  A bijection of the grid
+// whatever the hardware's actual dealing order; grids whose x extent is not
+// a multiple of 8 keep the identity.
+struct Tile3 {
+  uint32_t x, y, z;
+};
+__device__ __forceinline__ Tile3 xcd_local_tile() {
+  const uint32_t gx = gridDim.x, gy = gridDim.y;
+  if (gx % 8 != 0) return Tile3{blockIdx.x, blockIdx.y, blockIdx.z};
+  const uint32_t lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const uint32_t per = gx / 8, xcd = lin % 8, j = lin / 8;
+  const uint32_t slice = j / per;
+  return Tile3{xcd * per + j % per, slice % gy, slice / gy};
+}
+
 template <int L, int E, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_cols(Shape sh, Ptrs p0, Strides str, ColJobs jobs) {
   using CB = ColBody<T, L, E>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *smem = (cx<T> *)smem_raw;
-  const ColJob &job = jobs.j[blockIdx.y];
+  const Tile3 b = jobs.xcd ? xcd_local_tile() : Tile3{blockIdx.x, blockIdx.y, blockIdx.z};
+  const ColJob &job = jobs.j[b.y];
   const int TW = blockDim.x / CB::TPS;
-  const int64_t c0 = (int64_t)blockIdx.x * TW;
-  const PV P{&p0, &str, (int64_t)blockIdx.z, nullptr};
-  if (job.kind == COL_D && job.npart > 0 && blockIdx.x == 0 && blockIdx.y == 0) {
+  const int64_t c0 = (int64_t)b.x * TW;
+  const PV P{&p0, &str, (int64_t)b.z, nullptr};
+  if (job.kind == COL_D && job.npart > 0 && b.x == 0 && b.y == 0) {
     // the scalar product rides on the first pass-D workgroup
     reduce_partials(sh, P, job.npart, smem);
     __syncthreads();
@@ -128,7 +151,7 @@ namespace HK_NS {
 enum : int { BATCH_BLK = 512, BATCH_E_ROW = 8, BATCH_E_COL = sizeof(T) == 4 ? 16 : 8 };
 
 template <int L>
-__device__ __noinline__ void batch_res(const BatchArgs &A, const Task &tk, cx<T> *smem, int tid) {
+__device__ __forceinline__ void batch_res_body(const BatchArgs &A, const Task &tk, cx<T> *smem, int tid) {
   using RB = RowBody<T, L, BATCH_E_ROW>;
   const int rw = tid / RB::TPS;
   const int t = tid % RB::TPS;
@@ -144,8 +167,8 @@ __device__ __noinline__ void batch_res(const BatchArgs &A, const Task &tk, cx<T>
 }
 
 template <int L>
-__device__ __noinline__ void batch_rowb(const BatchArgs &A, const Task &tk, const Shape &sh, const PV &P,
-                                           cx<T> *smem, int tid) {
+__device__ __forceinline__ void batch_rowb_body(const BatchArgs &A, const Task &tk, const Shape &sh, const PV &P,
+                                                cx<T> *smem, int tid) {
   using RB = RowBody<T, L, BATCH_E_ROW>;
   const int rw = tid / RB::TPS;
   const int t = tid % RB::TPS;
@@ -159,7 +182,7 @@ __device__ __noinline__ void batch_rowb(const BatchArgs &A, const Task &tk, cons
 }
 
 template <int L>
-__device__ __noinline__ void batch_col(const Task &tk, const Shape &sh, const PV &P, cx<T> *smem, int tid) {
+__device__ __forceinline__ void batch_col_body(const Task &tk, const Shape &sh, const PV &P, cx<T> *smem, int tid) {
   using CB = ColBody<T, L, BATCH_E_COL>;
   constexpr int TW = BATCH_BLK / CB::TPS;
   ColJob job;
@@ -178,6 +201,22 @@ __device__ __noinline__ void batch_col(const Task &tk, const Shape &sh, const PV
     job.ncols = min(((int64_t)1 << sh.logR), lim);
   }
   CB::run(sh, P, job, tk.b, TW, tid, smem, g_tw24, g_tw4096);  // LDS sized by batch_geometry
+}
+
+// The persistent kernel calls the bodies out of line, so that its register
+// allocation is the largest body's rather than the sum over the switch.
+template <int L>
+__device__ __noinline__ void batch_res(const BatchArgs &A, const Task &tk, cx<T> *smem, int tid) {
+  batch_res_body<L>(A, tk, smem, tid);
+}
+template <int L>
+__device__ __noinline__ void batch_rowb(const BatchArgs &A, const Task &tk, const Shape &sh, const PV &P,
+                                           cx<T> *smem, int tid) {
+  batch_rowb_body<L>(A, tk, sh, P, smem, tid);
+}
+template <int L>
+__device__ __noinline__ void batch_col(const Task &tk, const Shape &sh, const PV &P, cx<T> *smem, int tid) {
+  batch_col_body<L>(tk, sh, P, smem, tid);
 }
 
 #define HK_LSWITCH(logv, FN, ...)                  \
@@ -253,6 +292,32 @@ __global__ void __launch_bounds__(BATCH_BLK) k_batch(BatchArgs A) {
       __syncthreads();
       if (tid == 0) atomicAdd(&A.ictl[tk.inst].done[tk.signal_phase], 1u);
     }
+  }
+}
+
+// Grouped launches: the tasks of one phase that share a kind and a transform
+// length L run in one launch of a kernel specialised for them (one task per
+// workgroup, A.order[A.begin + blockIdx.x]), so that each gets the registers
+// and LDS of its own length instead of the largest one's.  Phases are
+// ordered by the stream; no counters or waits are involved.
+template <int L, int KIND>
+__global__ void __launch_bounds__(BATCH_BLK) k_group(BatchArgs A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *smem = (cx<T> *)smem_raw;
+  const int tid = threadIdx.x;
+  const int32_t ti = A.order[A.begin + (int32_t)blockIdx.x];
+  const Task tk = A.tasks[ti];
+  if (KIND == GK_RES) {
+    batch_res_body<L>(A, tk, smem, tid);
+  } else {
+    const Shape &sh = A.shapes[tk.inst];
+    const PV P{&A.ptrs[tk.inst], nullptr, 0, A.ws_base};
+    if (KIND == GK_ROWB)
+      batch_rowb_body<L>(A, tk, sh, P, smem, tid);
+    else if (KIND == GK_COL)
+      batch_col_body<L>(tk, sh, P, smem, tid);
+    else
+      reduce_partials(sh, P, tk.nrowb, smem);
   }
 }
 

@@ -17,6 +17,12 @@ struct KernelLimits {
   int elem_bytes;  // bytes per complex element
 };
 
+// Every kernel launch goes through here.  While per-kernel profiling is on,
+// the launch carries a start/stop event pair that the runtime timestamps at
+// the dispatch's own begin and end (hipExtLaunchKernel), so the recorded
+// duration is the kernel's execution, without event-packet overhead.
+hipError_t launch_kernel(const void *fn, dim3 grid, dim3 block, void **args, size_t lds, hipStream_t st);
+
 #define HK_DECLARE_LAUNCHERS(SUFFIX)                                                                   \
   hipError_t init_tables_##SUFFIX(const double *tw4096_interleaved, const double *tw24_interleaved);   \
   bool limits_##SUFFIX(int logL, int E, KernelLimits *out);                                            \
@@ -26,8 +32,10 @@ struct KernelLimits {
   hipError_t launch_alpha_##SUFFIX(const Shape &sh, const Ptrs &p0, const Strides &str, int64_t npart,       \
                                    int64_t count, hipStream_t st);                                     \
   void batch_geometry_##SUFFIX(int *blk, int *e_row, int *e_col, size_t *lds_bytes);                 \
-  hipError_t launch_cols_##SUFFIX(int logL, int E, int tw, dim3 grid, const Shape &sh, const Ptrs &p0, \
-                                  const Strides &str, const ColJob *jobs, int njobs, hipStream_t st);
+  hipError_t launch_group_##SUFFIX(const BatchArgs &args, int kind, int logL, int ntasks, hipStream_t st); \
+  hipError_t launch_cols_##SUFFIX(int logL, int E, int tw, int xcd, dim3 grid, const Shape &sh,         \
+                                  const Ptrs &p0, const Strides &str, const ColJob *jobs, int njobs,    \
+                                  hipStream_t st);
 
 HK_DECLARE_LAUNCHERS(f32)
 HK_DECLARE_LAUNCHERS(f64)

@@ -1,6 +1,8 @@
 // Planning and launch sequencing of the plain (single-shape) path.
 #include "hk_plan.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 #include <string.h>
 
@@ -301,13 +303,14 @@ struct ProfState {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
   std::vector<int> kinds;
   size_t used = 0;
+  bool armed = false;  // prof_before handed out pool[used] for the next launch
 };
 static ProfState g_prof;
 static std::mutex g_prof_mu;
 
 bool prof_enabled() { return g_prof.on; }
 
-void prof_before(hipStream_t st) {
+void prof_before(hipStream_t) {
   if (!g_prof.on) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (g_prof.used == g_prof.pool.size()) {
@@ -316,22 +319,37 @@ void prof_before(hipStream_t st) {
     g_prof.pool.push_back({a, b});
     g_prof.kinds.push_back(-1);
   }
-  (void)hipEventRecord(g_prof.pool[g_prof.used].first, st);
+  g_prof.armed = true;
 }
 
-void prof_after(int kind, hipStream_t st) {
+void prof_after(int kind, hipStream_t) {
   if (!g_prof.on) return;
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (g_prof.used >= g_prof.pool.size()) return;
-  (void)hipEventRecord(g_prof.pool[g_prof.used].second, st);
+  if (g_prof.armed) return;  // the launch did not take the events (failed)
   g_prof.kinds[g_prof.used] = kind;
   ++g_prof.used;
+}
+
+hipError_t launch_kernel(const void *fn, dim3 grid, dim3 block, void **args, size_t lds, hipStream_t st) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (g_prof.on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (g_prof.armed && g_prof.used < g_prof.pool.size()) {
+      a = g_prof.pool[g_prof.used].first;
+      b = g_prof.pool[g_prof.used].second;
+      g_prof.armed = false;
+    }
+  }
+  if (a) return hipExtLaunchKernel(fn, grid, block, args, lds, st, a, b, 0);
+  return hipLaunchKernel(fn, grid, block, args, lds, st);
 }
 
 Status prof_start() {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof.on = true;
   g_prof.used = 0;
+  g_prof.armed = false;
   return Status();
 }
 
@@ -367,12 +385,12 @@ static hipError_t rows(hk_dtype_t dt, int logL, int E, int rpw, dim3 g, const Sh
   prof_after(sh.resident ? PK_RESIDENT : PK_PASS_B, st);
   return e;
 }
-static hipError_t cols(hk_dtype_t dt, int logL, int E, int tw, dim3 g, const Shape &sh, const Ptrs &p0,
+static hipError_t cols(hk_dtype_t dt, int logL, int E, int tw, int xcd, dim3 g, const Shape &sh, const Ptrs &p0,
                        const Strides &str, const ColJob *jobs, int nj, hipStream_t st) {
   count_launch();
   prof_before(st);
-  const hipError_t e = is_double(dt) ? launch_cols_f64(logL, E, tw, g, sh, p0, str, jobs, nj, st)
-                                     : launch_cols_f32(logL, E, tw, g, sh, p0, str, jobs, nj, st);
+  const hipError_t e = is_double(dt) ? launch_cols_f64(logL, E, tw, xcd, g, sh, p0, str, jobs, nj, st)
+                                     : launch_cols_f32(logL, E, tw, xcd, g, sh, p0, str, jobs, nj, st);
   prof_after(jobs[0].kind == COL_A ? PK_PASS_A : PK_PASS_D, st);
   return e;
 }
@@ -408,7 +426,7 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
     max_cols = std::max(max_cols, ja[o].ncols);
   }
   dim3 ga((unsigned)((max_cols + sc.tw - 1) / sc.tw), (unsigned)sh.nops, (unsigned)count);
-  e = cols(dt, sh.logC, sc.E_col, sc.tw, ga, sh, p0, str, ja, sh.nops, st);
+  e = cols(dt, sh.logC, sc.E_col, sc.tw, sc.xcd, ga, sh, p0, str, ja, sh.nops, st);
   if (e != hipSuccess) return hip_fail(e, "pass A launch");
   // Pass B: row transforms, spectral product, row transform of the output.
   dim3 gb((unsigned)((C + sc.rows_per_wg - 1) / sc.rows_per_wg), (unsigned)count);
@@ -442,7 +460,7 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
   }
   if (nd > 0) {
     dim3 gd((unsigned)((dcols + sc.tw - 1) / sc.tw), (unsigned)nd, (unsigned)count);
-    e = cols(dt, sh.logC, sc.E_col, sc.tw, gd, sh, p0, str, jd, nd, st);
+    e = cols(dt, sh.logC, sc.E_col, sc.tw, sc.xcd, gd, sh, p0, str, jd, nd, st);
     if (e != hipSuccess) return hip_fail(e, "pass D launch");
   } else if (npart > 0) {
     count_launch();
@@ -530,6 +548,74 @@ bool sched_lookup(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint
 void sched_store(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint, int64_t batch, const Sched &sc) {
   std::lock_guard<std::mutex> lk(g_sched_mu);
   g_sched[SchedKey((int)dt, prog, is_block, logN, logC_hint, batch_class(batch))] = sc;
+}
+
+// Text database, one schedule per line:
+//   dtype prog is_block logN logC_hint batch_class : E_row rows_per_wg E_col tw split xcd
+// (xcd may be omitted: 0).  '#' starts a comment line.
+static const char *kDbHeader =
+    "# hankel schedule database v2: dt prog blk logN logC bclass : E_row rows E_col tw split xcd\n";
+
+Status sched_save(const char *path) {
+  if (!path) return fail(HK_ERR_NULL_POINTER, "path is NULL");
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  FILE *f = fopen(path, "w");
+  if (!f) return fail(HK_ERR_INVALID_VALUE, std::string("cannot open ") + path + " for writing");
+  fputs(kDbHeader, f);
+  for (const auto &kv : g_sched) {
+    const SchedKey &k = kv.first;
+    const Sched &s = kv.second;
+    fprintf(f, "%d %d %d %d %d %d : %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+            std::get<3>(k), std::get<4>(k), std::get<5>(k), s.E_row, s.rows_per_wg, s.E_col, s.tw, s.split, s.xcd);
+  }
+  const bool ok = fclose(f) == 0;
+  return ok ? Status() : fail(HK_ERR_INVALID_VALUE, std::string("error writing ") + path);
+}
+
+Status sched_load(const char *path, int *loaded) {
+  if (!path) return fail(HK_ERR_NULL_POINTER, "path is NULL");
+  FILE *f = fopen(path, "r");
+  if (!f) return fail(HK_ERR_INVALID_VALUE, std::string("cannot open ") + path);
+  std::map<SchedKey, Sched> add;
+  char line[256];
+  int lineno = 0;
+  Status st;
+  while (fgets(line, sizeof(line), f)) {
+    ++lineno;
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int k[6], v[6] = {0, 0, 0, 0, 0, 0};
+    const int got = sscanf(line, "%d %d %d %d %d %d : %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5],
+                           &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]);
+    if (got != 11 && got != 12) {
+      st = fail(HK_ERR_INVALID_VALUE, std::string(path) + ": malformed line " + std::to_string(lineno));
+      break;
+    }
+    const bool key_ok = k[0] >= HK_C64 && k[0] <= HK_F64 && (k[1] == PROG_FWD || k[1] == PROG_BWD) &&
+                        (k[2] == 0 || k[2] == 1) && k[3] >= 0 && k[3] <= HK_MAX_FFT_LOG2 && k[4] >= -1 &&
+                        k[4] <= HK_MAX_FFT_LOG2 && k[5] >= 0 && k[5] <= 2;
+    Sched s;
+    s.E_row = v[0];
+    s.rows_per_wg = v[1];
+    s.E_col = v[2];
+    s.tw = v[3];
+    s.split = v[4];
+    s.xcd = v[5];
+    // entries are re-checked against the kernel limits when used (sched_valid)
+    const bool val_ok = (s.E_row == 8 || s.E_row == 16) && (s.E_col == 8 || s.E_col == 16) && s.rows_per_wg >= 1 &&
+                        s.rows_per_wg <= 64 && s.tw >= 1 && s.tw <= 64 && s.split >= -4 && s.split <= 4 &&
+                        (s.xcd == 0 || s.xcd == 1);
+    if (!key_ok || !val_ok) {
+      st = fail(HK_ERR_INVALID_VALUE, std::string(path) + ": value out of range on line " + std::to_string(lineno));
+      break;
+    }
+    add[SchedKey(k[0], k[1], k[2], k[3], k[4], k[5])] = s;
+  }
+  fclose(f);
+  if (!st.ok()) return st;
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  for (const auto &kv : add) g_sched[kv.first] = kv.second;
+  if (loaded) *loaded = (int)add.size();
+  return Status();
 }
 
 }  // namespace hk

@@ -52,6 +52,7 @@ struct Sched {
   int E_col = 16;
   int tw = 8;
   int split = 0;  // multipass: logR - ceil(logN / 2) adjustment
+  int xcd = 0;    // column passes: XCD-local tile numbering (1) or identity (0)
 };
 
 struct Layout {
@@ -92,6 +93,8 @@ Status ensure_device();
 // Schedule cache (autotuner).
 bool sched_lookup(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint, int64_t batch, Sched *sc);
 void sched_store(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint, int64_t batch, const Sched &sc);
+Status sched_save(const char *path);
+Status sched_load(const char *path, int *loaded);
 
 // Thread-local launch counter.
 void count_launch();

@@ -28,9 +28,13 @@ import numpy as np
 SEED_BASE = 14016238
 
 
-def rng_for(config: int, instance: int = 0) -> np.random.Generator:
-    """Counter-style seeding: one independent PCG64 stream per (config, instance)."""
-    return np.random.Generator(np.random.PCG64(SEED_BASE + 1000 * config + instance))
+# one seed stream per workload family
+STREAM_SMALL_REAL, STREAM_LARGE_SINGLE, STREAM_MIXED, STREAM_ADJOINT, STREAM_BLOCK = 1, 2, 3, 4, 5
+
+
+def rng_for(stream: int, instance: int = 0) -> np.random.Generator:
+    """Counter-style seeding: one independent PCG64 stream per (workload family, instance)."""
+    return np.random.Generator(np.random.PCG64(SEED_BASE + 1000 * stream + instance))
 
 
 def cn(rng: np.random.Generator, shape, var: float) -> np.ndarray:
@@ -152,29 +156,29 @@ def _real_or_complex(rng, n, real, var=1.0):
     return cn(rng, n, var)
 
 
-def config1(instance: int = 0) -> Problem:
+def small_real(instance: int = 0) -> Problem:
     """m=3, n=64 square Hankel tensor, real float64 U[-1,1] inputs; y = H x^2 and H x^3."""
-    g = rng_for(1, instance)
+    g = rng_for(STREAM_SMALL_REAL, instance)
     m, n = 3, 64
     d = m * (n - 1) + 1
     h = g.uniform(-1.0, 1.0, d)
     x = g.uniform(-1.0, 1.0, n)
-    return Problem(m, [n] * m, h, [x] * m, True, True, True, meta={"config": 1, "real": True})
+    return Problem(m, [n] * m, h, [x] * m, True, True, True, meta={"workload": "small_real", "real": True})
 
 
-def config2(instance: int = 0, sigma: float = 1e-3, n: int = 1 << 18, r: int = 8) -> Problem:
+def large_single(instance: int = 0, sigma: float = 1e-3, n: int = 1 << 18, r: int = 8) -> Problem:
     """m=4, n=2^18 square Hankel tensor; h an 8-term exponential sum + noise; x ~ CN(0, 1/n)."""
-    g = rng_for(2, instance)
+    g = rng_for(STREAM_LARGE_SINGLE, instance)
     m = 4
     d = m * (n - 1) + 1
     h, params = exp_sum_vector(g, d, r, sigma)
     x = cn(g, n, 1.0 / n)
-    return Problem(m, [n] * m, h, [x] * m, True, True, True, meta={"config": 2, "expsum": params})
+    return Problem(m, [n] * m, h, [x] * m, True, True, True, meta={"workload": "large_single", "expsum": params})
 
 
-def config3_instance(instance: int) -> Problem:
+def mixed_instance(instance: int) -> Problem:
     """One instance of the 4096-problem mixed batch (m in {3,4,5}, n log-uniform in [64, 16384])."""
-    g = rng_for(3, instance)
+    g = rng_for(STREAM_MIXED, instance)
     m = int(g.integers(3, 6))
     n = int(round(math.exp(g.uniform(math.log(64), math.log(16384)))))
     r = int(g.integers(2, 17))
@@ -187,16 +191,16 @@ def config3_instance(instance: int) -> Problem:
     else:
         vecs = [None] + [cn(g, n, 1.0 / n) for _ in range(m - 1)]
     return Problem(m, [n] * m, h, vecs, equal, True, False,
-                   meta={"config": 3, "expsum": params, "instance": instance})
+                   meta={"workload": "mixed", "expsum": params, "instance": instance})
 
 
-def config3(count: int = 4096) -> List[Problem]:
-    return [config3_instance(i) for i in range(count)]
+def mixed_batch(count: int = 4096) -> List[Problem]:
+    return [mixed_instance(i) for i in range(count)]
 
 
-def config4_instance(instance: int, n: int = 1 << 16, sigma: float = 1e-3) -> dict:
+def adjoint_instance(instance: int, n: int = 1 << 16, sigma: float = 1e-3) -> dict:
     """m=4, n=2^16 forward (g = H x^3, f = H x^4) plus cotangents v ~ CN(0,1)^n, phi ~ CN(0,1)."""
-    g = rng_for(4, instance)
+    g = rng_for(STREAM_ADJOINT, instance)
     m = 4
     d = m * (n - 1) + 1
     h, params = exp_sum_vector(g, d, 8, sigma)
@@ -206,10 +210,10 @@ def config4_instance(instance: int, n: int = 1 << 16, sigma: float = 1e-3) -> di
     return {"m": m, "n": n, "h": h, "x": x, "v": v, "phi": phi, "expsum": params}
 
 
-def config5_instance(instance: int, nb: int = 512, sigma: float = 1e-3, r: int = 6,
+def block_instance(instance: int, nb: int = 512, sigma: float = 1e-3, r: int = 6,
                      m: int = 3) -> Problem:
     """BHHB order 3: block size n_p = 512, N_p = 512 blocks per mode; H is 1534 x 1534."""
-    g = rng_for(5, instance)
+    g = rng_for(STREAM_BLOCK, instance)
     dims = [nb] * m
     bdims = [nb] * m
     rows = sum(dims) - m + 1
@@ -217,7 +221,7 @@ def config5_instance(instance: int, nb: int = 512, sigma: float = 1e-3, r: int =
     H, params = exp_sum_matrix(g, rows, cols, r, sigma)
     x = cn(g, nb * nb, 1.0)
     return Problem(m, dims, H, [x] * m, True, True, True, block_dims=bdims,
-                   meta={"config": 5, "expsum2": params, "instance": instance})
+                   meta={"workload": "block", "expsum2": params, "instance": instance})
 
 
 def random_problem(seed: int, m: int, dims, equal: bool, complex_: bool = True,

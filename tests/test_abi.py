@@ -129,3 +129,33 @@ def test_status_strings(L):
     for code in range(10):
         assert L.hk_status_string(code)
     assert L.hk_version() > 0
+
+
+def test_autotune_argument_errors(L):
+    """Rejected before any device work: unknown kind, bad order, missing block dims."""
+    assert L.hk_autotune(HK_C64, 7, 3, 64, None, None, 1, 0) == INVALID
+    assert L.hk_autotune(HK_C64, 0, 1, 64, None, None, 1, 0) == INVALID
+    assert L.hk_autotune(HK_C64, 2, 3, 0, None, None, 1, 0) == NULLP
+    assert L.hk_autotune(HK_F32, 1, 3, 64, None, None, 1, 0) == NOTSUP
+    assert L.hk_autotune_tvp(HK_C64, 3, 1 << 26, 0) == SIZE
+
+
+def test_tune_db_round_trip(L, tmp_path):
+    """The schedule database loads, merges and saves on the host."""
+    good = tmp_path / "db.txt"
+    good.write_text("# comment\n0 0 0 23 -1 0 : 8 1 16 8 0\n1 1 0 23 -1 2 : 16 2 8 4 -1 1\n")
+    n = ctypes.c_int(-1)
+    assert L.hk_tune_load(str(good).encode(), ctypes.byref(n)) == OK
+    assert n.value == 2
+    out = tmp_path / "out.txt"
+    assert L.hk_tune_save(str(out).encode()) == OK
+    lines = [ln for ln in out.read_text().splitlines() if not ln.startswith("#")]
+    assert "1 1 0 23 -1 2 : 16 2 8 4 -1 1" in lines
+    assert "0 0 0 23 -1 0 : 8 1 16 8 0 0" in lines
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 0 0 20 -1 0 : 8 1 16 8\n")
+    assert L.hk_tune_load(str(bad).encode(), None) == INVALID
+    bad.write_text("0 0 0 20 -1 0 : 12 1 16 8 0\n")  # E_row 12 is not a kernel variant
+    assert L.hk_tune_load(str(bad).encode(), None) == INVALID
+    assert L.hk_tune_load(str(tmp_path / "missing.txt").encode(), None) == INVALID
+    assert L.hk_tune_load(None, None) == NULLP

@@ -165,11 +165,11 @@ def test_one_shot_batched():
     check_plan_outputs(probs, outs, dtype)
 
 
-def test_config3_subset():
+def test_mixed_batch_subset():
     """The first 48 instances of the 4096-problem mixed batch (m in {3,4,5}, n in [64, 16384])."""
     import paper_1401_6238_amd as hk
     dtype = torch.complex64
-    probs = [wl.config3_instance(i) for i in range(48)]
+    probs = [wl.mixed_instance(i) for i in range(48)]
     plan = hk.Plan(plan_inputs(probs, dtype))
     outs = plan.execute()
     plan.status()

@@ -38,36 +38,36 @@ def same_inputs(fp_stored, arr):
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-def test_config2_golden(dtype):
+def test_large_single_golden(dtype):
     import paper_1401_6238_amd as hk
-    g = golden("config2")
+    g = golden("large_single")
     tag = "c128" if dtype == torch.complex128 else "c64"
-    print_case(test="config2_golden", dtype=tag)
-    p = wl.config2(0)
-    same_inputs(g["config2_fp_h"], p.h)
-    same_inputs(g["config2_fp_x"], p.vectors[1])
+    print_case(test="large_golden", dtype=tag)
+    p = wl.large_single(0)
+    same_inputs(g["large_fp_h"], p.h)
+    same_inputs(g["large_fp_x"], p.vectors[1])
     hk.hk_autotune_tvp(dtype, 4, p.dims[0])
     y, a = hk.hankel_tvp(to_dev(p.h, dtype), to_dev(p.vectors[1], dtype), 4, True, True)
     torch.cuda.synchronize()
-    idx = g["config2_idx"]
-    e = rel(host(y)[idx], g[f"config2_{tag}_y"])
-    ao = complex(g[f"config2_{tag}_alpha"][0])
+    idx = g["large_idx"]
+    e = rel(host(y)[idx], g[f"large_{tag}_y"])
+    ao = complex(g[f"large_{tag}_alpha"][0])
     ea = abs(complex(host(a.reshape(1))[0]) - ao) / abs(ao)
-    print(f"config2 {tag}: y rel err {e:.3e}, alpha rel err {ea:.3e}")
+    print(f"large {tag}: y rel err {e:.3e}, alpha rel err {ea:.3e}")
     assert e <= TOL[dtype]
     assert ea <= TOL[dtype]
 
 
-def test_config2_vandermonde_all_outputs():
-    """Noise-free twin of the config-2 input: every output against the closed form.
+def test_large_single_vandermonde_all_outputs():
+    """Noise-free twin of the large single-product input: every output against the closed form.
 
     FP64 only: rounding h to complex64 would perturb the exponential sum by
     more than the closed form can account for (the complex64 path is checked
     against the oracle on its rounded inputs above)."""
     import paper_1401_6238_amd as hk
     dtype = torch.complex128
-    print_case(test="config2_vandermonde", dtype=dtype)
-    p = wl.config2(0, sigma=0.0)
+    print_case(test="large_vandermonde", dtype=dtype)
+    p = wl.large_single(0, sigma=0.0)
     params = p.meta["expsum"]
     n = p.dims[0]
     x = p.vectors[1]
@@ -87,17 +87,17 @@ def test_config2_vandermonde_all_outputs():
     assert ea <= TOL[dtype]
 
 
-@pytest.mark.parametrize("flags", ["persistent", "per_pass"])
-def test_config3_all_instances(flags):
+@pytest.mark.parametrize("flags", ["persistent", "grouped"])
+def test_mixed_batch_all_instances(flags):
     """All 4096 mixed instances in one plan, sampled outputs against the oracle."""
     import paper_1401_6238_amd as hk
     from paper_1401_6238_amd import _lib
-    g = golden("config3")
-    print_case(test="config3", flags=flags)
+    g = golden("mixed_batch")
+    print_case(test="mixed_batch", flags=flags)
     dtype = torch.complex64
     items, probs = [], []
     for i in range(4096):
-        p = wl.config3_instance(i)
+        p = wl.mixed_instance(i)
         probs.append(p)
         h = to_dev(p.h, dtype)
         if p.equal:
@@ -106,34 +106,34 @@ def test_config3_all_instances(flags):
         else:
             vecs = [None] + [to_dev(v, dtype) for v in p.vectors[1:]]
         items.append({"m": p.m, "dims": p.dims, "h": h, "vectors": vecs})
-    same_inputs(g["config3_fp_h"][0], probs[0].h)
-    same_inputs(g["config3_fp_h"][4095], probs[4095].h)
+    same_inputs(g["mixed_fp_h"][0], probs[0].h)
+    same_inputs(g["mixed_fp_h"][4095], probs[4095].h)
     f = _lib.HK_PLAN_PERSISTENT if flags == "persistent" else _lib.HK_PLAN_MULTIKERNEL
     plan = hk.Plan(items, flags=f)
     outs = plan.execute()
     plan.status()
-    off, idx, ys = g["config3_off"], g["config3_idx"], g["config3_y"]
+    off, idx, ys = g["mixed_off"], g["mixed_idx"], g["mixed_y"]
     worst = 0.0
     for i in range(4096):
         sl = slice(off[i], off[i + 1])
         e = rel(host(outs[i][0])[idx[sl]], ys[sl])
         worst = max(worst, e)
     plan.close()
-    print(f"config3 worst instance rel err {worst:.3e}")
+    print(f"mixed worst instance rel err {worst:.3e}")
     assert worst <= TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
-def test_config4_forward_and_adjoint(dtype):
+def test_adjoint_batch_forward_and_adjoint(dtype):
     """Batch of 256 (m=4, n=2^16): forward g, f and gradients of sampled instances."""
     import paper_1401_6238_amd as hk
-    g = golden("config4")
+    g = golden("adjoint_batch")
     tag = "c128" if dtype == torch.complex128 else "c64"
-    print_case(test="config4", dtype=tag)
-    insts = [int(i) for i in g["config4_instances"]]
-    data = {i: wl.config4_instance(i) for i in insts}
+    print_case(test="adjoint_batch", dtype=tag)
+    insts = [int(i) for i in g["adjoint_instances"]]
+    data = {i: wl.adjoint_instance(i) for i in insts}
     for i in insts:
-        same_inputs(g[f"config4_{i}_fp_h"], data[i]["h"])
+        same_inputs(g[f"adjoint_{i}_fp_h"], data[i]["h"])
     # the 252 other slots repeat instance 0: their results must equal slot 0 bit for bit
     order = [i if i in data else 0 for i in range(256)]
     H = torch.stack([to_dev(data[i]["h"], dtype) for i in order])
@@ -145,48 +145,48 @@ def test_config4_forward_and_adjoint(dtype):
     torch.cuda.synchronize()
     tol = TOL[dtype]
     for i in insts:
-        ix, ih = g[f"config4_{i}_idx_x"], g[f"config4_{i}_idx_h"]
-        assert rel(host(gy[i])[ix], g[f"config4_{i}_{tag}_g"]) <= tol
-        fo = complex(g[f"config4_{i}_{tag}_f"][0])
+        ix, ih = g[f"adjoint_{i}_idx_x"], g[f"adjoint_{i}_idx_h"]
+        assert rel(host(gy[i])[ix], g[f"adjoint_{i}_{tag}_g"]) <= tol
+        fo = complex(g[f"adjoint_{i}_{tag}_f"][0])
         assert abs(complex(host(f[i:i + 1])[0]) - fo) <= tol * abs(fo)
-        assert rel(host(gx[i])[ix], g[f"config4_{i}_{tag}_gx"]) <= tol
-        assert rel(host(gh[i])[ih], g[f"config4_{i}_{tag}_gh"]) <= tol
+        assert rel(host(gx[i])[ix], g[f"adjoint_{i}_{tag}_gx"]) <= tol
+        assert rel(host(gh[i])[ih], g[f"adjoint_{i}_{tag}_gh"]) <= tol
     ref = host(gx[0])
     for b in (2, 77, 200):
         assert np.array_equal(host(gx[b]), ref)
         assert np.array_equal(host(gy[b]), host(gy[0]))
 
 
-def test_config5_block_batch():
+def test_block_batch():
     """64 BHHB tensors (m=3, 512 blocks of 512, 2048^2 grid), sampled outputs of tensors 0 and 63."""
     import paper_1401_6238_amd as hk
-    g = golden("config5")
-    print_case(test="config5")
+    g = golden("block_batch")
+    print_case(test="block_batch")
     dtype = torch.complex64
-    insts = [int(i) for i in g["config5_instances"]]
-    data = {i: wl.config5_instance(i) for i in insts}
+    insts = [int(i) for i in g["block_instances"]]
+    data = {i: wl.block_instance(i) for i in insts}
     for i in insts:
-        same_inputs(g[f"config5_{i}_fp_h"], data[i].h)
+        same_inputs(g[f"block_{i}_fp_h"], data[i].h)
     order = [i if i in data else 0 for i in range(64)]
     Hs = torch.stack([to_dev(data[i].h, dtype) for i in order])
     Xs = torch.stack([to_dev(data[i].vectors[1], dtype) for i in order])
     y, a = hk.block_hankel_tvp_strided_batched(Hs, Xs, 3, 512, 512, True, True)
     torch.cuda.synchronize()
     for i in insts:
-        e = rel(host(y[i])[g[f"config5_{i}_idx"]], g[f"config5_{i}_y"])
-        ao = complex(g[f"config5_{i}_alpha"][0])
+        e = rel(host(y[i])[g[f"block_{i}_idx"]], g[f"block_{i}_y"])
+        ao = complex(g[f"block_{i}_alpha"][0])
         ea = abs(complex(host(a[i:i + 1])[0]) - ao) / abs(ao)
-        print(f"config5 tensor {i}: y {e:.3e} alpha {ea:.3e}")
+        print(f"block tensor {i}: y {e:.3e} alpha {ea:.3e}")
         assert e <= TOL[dtype] and ea <= TOL[dtype]
     for b in (1, 30):
         assert np.array_equal(host(y[b]), host(y[0]))
 
 
-def test_config5_level2_closed_form():
+def test_block_level2_closed_form():
     """Noise-free twin of tensor 0: every output against the level-2 Vandermonde form."""
     import paper_1401_6238_amd as hk
     dtype = torch.complex128
-    p = wl.config5_instance(0, sigma=0.0)
+    p = wl.block_instance(0, sigma=0.0)
     a_, z1, z2, _ = p.meta["expsum2"]
     nb = 512
     xs = p.vectors[1].reshape(nb, nb)  # [j, i]
@@ -201,5 +201,5 @@ def test_config5_level2_closed_form():
     y, a = hk.block_hankel_tvp(to_dev(p.h, dtype), [x] * 3, [nb] * 3, [nb] * 3, True, True)
     e = rel(host(y), Y.astype(np.complex128).ravel())
     ea = abs(complex(host(a.reshape(1))[0]) - complex(alpha)) / abs(complex(alpha))
-    print(f"config5 closed form: y {e:.3e} alpha {ea:.3e}")
+    print(f"block closed form: y {e:.3e} alpha {ea:.3e}")
     assert e <= TOL[dtype] and ea <= TOL[dtype]

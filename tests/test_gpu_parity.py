@@ -44,10 +44,10 @@ def check(prob, dtype, tol=None):
         assert e <= tol * 10, f"alpha rel err {e:.3e}"
 
 
-def test_config1_real_f64():
+def test_small_real_f64():
     """m=3, n=64, real FP64 inputs (the small published-shape case)."""
-    prob = wl.config1()
-    print_case(test="config1", dtype="f64")
+    prob = wl.small_real()
+    print_case(test="small_real", dtype="f64")
     check(prob, torch.float64)
 
 
