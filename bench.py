@@ -294,7 +294,7 @@ def main():
                     help="also run 8 plain device copies of this many MiB (counter calibration)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--profile-delay-cycles", type=float, default=2e8,
+    ap.add_argument("--profile-delay-cycles", type=float, default=2e7,
                     help="length of the delay kernel queued before the profiled pass")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 4))
     ap.add_argument("--summarize-trace", metavar="DIR", help="write profiles/ summary of a rocprofv3 kernel trace")

@@ -413,6 +413,7 @@ Status plan_status(hk_plan_t p) {
   if (!p->last_ws) return Status();
   hipError_t e = hipStreamSynchronize(p->last_stream);
   if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  if (!p->persistent) return Status();  // grouped launches have no waits and no error word
   BatchCtl c;
   e = hipMemcpy(&c, p->last_ws, sizeof(c), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "status readback");
@@ -451,9 +452,8 @@ Status plan_release_after(hk_plan_t p, hipStream_t st) {
 // Autotuner: times every valid schedule of one shape (split of N = R * C,
 // elements per lane of the row and column transforms, rows per workgroup,
 // column-tile width) on scratch buffers, and caches the fastest under the key
-// the call path looks up (dtype, program, 1D/BHHB, N, batch class).  All
-// instances of a tuning batch read the same zero-filled inputs and write
-// their own outputs and workspace.
+// the call path looks up (dtype, program, 1D/BHHB, N, batch class, XCD tile
+// numbering).  Inputs are zero-filled device buffers, distinct per instance.
 // ---------------------------------------------------------------------------
 Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   Status s = ensure_device();
