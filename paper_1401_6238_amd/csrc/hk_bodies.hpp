@@ -141,7 +141,7 @@ struct RowBody {
   using S = FFTShape<L, E>;
   static constexpr int EE = S::EE;
   static constexpr int TPS = S::TPS;
-  static constexpr int SEQ_LDS = S::LDS > 0 ? S::LDS + 1 : 0;  // +1: bank skew between sequences
+  static constexpr int SEQ_LDS = S::ROW_SEQ;
   // A row's TPS lanes are consecutive, so a row of at most 64 lanes lives in
   // one wavefront and its exchanges need no workgroup barrier.
   static constexpr bool WAVE = TPS <= 64;
@@ -306,7 +306,6 @@ struct ColBody {
   using S = FFTShape<L, E>;
   static constexpr int EE = S::EE;
   static constexpr int TPS = S::TPS;
-  static constexpr int SEQ_LDS = S::LDS > 0 ? S::LDS + 1 : 0;
 
   static __device__ __forceinline__ void run(const Shape &sh, const PV &P, const ColJob &job, int64_t c0,
                                              int TW, int tid, cx<T> *lds, const cx<T> *tw24,
@@ -351,7 +350,8 @@ struct ColBody {
     cx<T> wst[EE];
     const bool twid = job.kind == COL_A && !sh.is_block;
     if (twid) slot_twiddles<T, EE>(wst, c, t, TPS, sh.logR + sh.logC, tw24, tw4096);
-    fft_seq<T, L, E>(a, t, lds + cw * col_lds_stride(S::LDS, TW), stw);
+    // TW interleaved columns: element i of column cw at lds[(sw(i) << log2 TW) + cw]
+    fft_seq<T, L, E>(a, t, lds + cw, stw, __builtin_ctz((unsigned)TW));
     if (!cvalid) return;
     if (job.kind == COL_A) {
       cx<T> *dst = ws_buf<T>(sh, P, job.buf);

@@ -34,22 +34,6 @@ enum Prog : int32_t { PROG_FWD = 0, PROG_BWD = 1 };
 
 enum ColKind : int32_t { COL_A = 0, COL_D = 1 };
 
-// LDS stride (in elements) between the column sequences of a column-pass
-// workgroup with TW columns.  Lane l works on column l % TW at position-lane
-// l / TW, so a wavefront touches min(TW, 64) columns and 64 / TW position
-// lanes; the stride is a multiple of 32 elements plus a skew that places the
-// lanes of one wavefront on distinct 8-byte LDS slots.
-#if defined(__HIPCC__)
-__host__ __device__
-#endif
-inline int col_lds_stride(int lds_elems, int tw) {
-  if (lds_elems == 0) return 0;
-  if (tw >= 32) return lds_elems | 1;  // one position lane per column: an odd stride suffices
-  const int base = (lds_elems + 31) & ~31;
-  const int skew = tw >= 1 ? (64 / tw) & 31 : 0;
-  return base + skew;
-}
-
 struct OpDesc {
   int32_t role;     // Role
   int32_t exp;      // multiplicity in the spectral product (ROLE_X)

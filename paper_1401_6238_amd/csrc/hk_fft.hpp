@@ -142,8 +142,11 @@ struct FFTShape {
   static constexpr int LOGE = ilog2c(EE);
   static constexpr int P = LOGL == 0 ? 0 : (LOGL + LOGE - 1) / LOGE;  // Stockham passes
   static constexpr int LOG_LAST = LOGL - LOGE * (P > 0 ? P - 1 : 0);
-  // LDS elements per sequence (padded by one element every EE elements).
-  static constexpr int LDS = P > 1 ? L + L / EE : 0;
+  // LDS elements one sequence's exchanges need (no padding: see sw()).
+  static constexpr int LDS = P > 1 ? L : 0;
+  // Row sequences placed side by side in one wavefront (TPS < 32) are
+  // offset by TPS elements so that their lanes fall on different banks.
+  static constexpr int ROW_SEQ = P > 1 ? L + (TPS < 32 ? TPS : 0) : 0;
   static __host__ __device__ constexpr int radix(int p) { return p < P - 1 ? EE : (1 << LOG_LAST); }
   static __host__ __device__ constexpr int nbf(int p) { return EE / radix(p); }  // butterflies per lane
   // offset of pass p's twiddles in a lane's precomputed set (passes 1..P-1)
@@ -153,7 +156,13 @@ struct FFTShape {
     return o;
   }
   static constexpr int TWN = tw_off(P) > 0 ? tw_off(P) : 1;
-  static __device__ __forceinline__ int pad(int i) { return i + (i >> LOGE); }
+  // LDS slot of element i: the low five index bits are XORed with the bits
+  // above log2(EE).  Reads (consecutive i across lanes) stay a permutation of
+  // aligned 32-element blocks, and the strided writes of the first pass
+  // (i = EE b + r) land on distinct 8-byte slots, so every exchange of 32
+  // lanes touches 32 distinct slots: no bank conflicts, no padding.
+  static constexpr int SWM = (L < 32 ? L : 32) - 1;
+  static __device__ __forceinline__ int sw(int i) { return i ^ ((i >> LOGE) & SWM); }
 };
 
 // Register array holding one lane's share of a length-L sequence.
@@ -226,8 +235,12 @@ struct StageTw {
 // butterfly b = t + q*TPS; span Ns = EE^p; outputs go to
 // (b - k) R + k + r Ns, k = b mod Ns.  With PRE the twiddles come from the
 // lane's precomputed set, otherwise from the table.
+//
+// LDS layout: element i of the sequence sits at lds[sw(i) << ls]; ls = 0 for
+// a row sequence, log2(TW) for a column tile whose TW columns are
+// interleaved (lds already offset by the lane's column).
 template <typename T, int L, int E, bool WAVE, bool PRE, int p>
-__device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
+__device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds, int ls,
                                          const cx<T> *__restrict__ tw4096, const StageTw<T, L, E> &pre) {
   using S = FFTShape<L, E>;
   constexpr int EE = S::EE;
@@ -241,7 +254,7 @@ __device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
 #pragma unroll
     for (int q = 0; q < B; ++q)
 #pragma unroll
-      for (int r = 0; r < R; ++r) a[q + r * B] = lds[S::pad(t + q * TPS + r * (L / R))];
+      for (int r = 0; r < R; ++r) a[q + r * B] = lds[S::sw(t + q * TPS + r * (L / R)) << ls];
   }
 #pragma unroll
   for (int q = 0; q < B; ++q) {
@@ -274,9 +287,9 @@ __device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
       const int k = b & (Ns - 1);
       const int base = (b - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lds[S::pad(base + r * Ns)] = a[q + r * B];
+      for (int r = 0; r < R; ++r) lds[S::sw(base + r * Ns) << ls] = a[q + r * B];
     }
-    fft_pass<T, L, E, WAVE, PRE, p + 1>(a, t, lds, tw4096, pre);
+    fft_pass<T, L, E, WAVE, PRE, p + 1>(a, t, lds, ls, tw4096, pre);
   }
 }
 
@@ -285,15 +298,16 @@ __device__ __forceinline__ void fft_pass(Regs<T, L, E> &a, int t, cx<T> *lds,
 // transform needs more than one pass and WAVE is false).
 template <typename T, int L, int E, bool WAVE = false>
 __device__ __forceinline__ void fft_seq(Regs<T, L, E> &a, int t, cx<T> *lds,
-                                        const cx<T> *__restrict__ tw4096) {
+                                        const cx<T> *__restrict__ tw4096, int ls = 0) {
   StageTw<T, L, E> none;
-  if constexpr (FFTShape<L, E>::P > 0) fft_pass<T, L, E, WAVE, false, 0>(a, t, lds, tw4096, none);
+  if constexpr (FFTShape<L, E>::P > 0) fft_pass<T, L, E, WAVE, false, 0>(a, t, lds, ls, tw4096, none);
 }
 
 // Same, with the lane's precomputed twiddles.
 template <typename T, int L, int E, bool WAVE = false>
-__device__ __forceinline__ void fft_seq(Regs<T, L, E> &a, int t, cx<T> *lds, const StageTw<T, L, E> &pre) {
-  if constexpr (FFTShape<L, E>::P > 0) fft_pass<T, L, E, WAVE, true, 0>(a, t, lds, nullptr, pre);
+__device__ __forceinline__ void fft_seq(Regs<T, L, E> &a, int t, cx<T> *lds, const StageTw<T, L, E> &pre,
+                                        int ls = 0) {
+  if constexpr (FFTShape<L, E>::P > 0) fft_pass<T, L, E, WAVE, true, 0>(a, t, lds, ls, nullptr, pre);
 }
 
 

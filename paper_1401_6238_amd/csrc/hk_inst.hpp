@@ -79,7 +79,7 @@ static KernelLimits lim_of() {
   using S = FFTShape<L, E>;
   KernelLimits k;
   k.tps = S::TPS;
-  k.seq_lds = S::LDS > 0 ? S::LDS + 1 : 0;
+  k.seq_lds = S::ROW_SEQ;
   k.lds_raw = S::LDS;
   k.elem_bytes = (int)sizeof(cx<T>);
   return k;
@@ -206,7 +206,7 @@ hipError_t HK_CAT(launch_cols_, HK_SUFFIX)(int logL, int E, int tw, int xcd, dim
   if (!fn || !HK_CAT(limits_, HK_SUFFIX)(logL, E, &k)) return hipErrorInvalidValue;
   const int threads = tw * k.tps;
   if (threads < 1 || threads > COL_MAXT || njobs < 1 || njobs > MAXOPS) return hipErrorInvalidValue;
-  size_t lds = (size_t)tw * col_lds_stride(k.lds_raw, tw) * sizeof(cx<T>);
+  size_t lds = (size_t)tw * k.lds_raw * sizeof(cx<T>);
   lds = std::max(lds, (size_t)threads * sizeof(cx<T>));  // room for the scalar reduction
   hipError_t e = ensure_lds(fn, lds);
   if (e != hipSuccess) return e;
@@ -246,7 +246,7 @@ void HK_CAT(batch_geometry_, HK_SUFFIX)(int *blk, int *e_row, int *e_col, size_t
     if (kr.tps <= BATCH_BLK) mx = std::max(mx, (size_t)(BATCH_BLK / kr.tps) * kr.seq_lds);
     if (kc.tps <= BATCH_BLK) {
       const int tw = BATCH_BLK / kc.tps;
-      mx = std::max(mx, (size_t)tw * col_lds_stride(kc.lds_raw, tw));
+      mx = std::max(mx, (size_t)tw * kc.lds_raw);
     }
   }
   *lds_bytes = mx * sizeof(cx<T>);
@@ -266,7 +266,7 @@ static size_t group_lds_elems(int kind, int logL) {
     HK_CAT(limits_, HK_SUFFIX)(logL, BATCH_E_COL, &kc);
     if (kc.tps <= BATCH_BLK) {
       const int tw = BATCH_BLK / kc.tps;
-      mx = std::max(mx, (size_t)tw * col_lds_stride(kc.lds_raw, tw));
+      mx = std::max(mx, (size_t)tw * kc.lds_raw);
     }
   }
   return mx;

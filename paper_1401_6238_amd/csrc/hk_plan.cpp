@@ -260,7 +260,7 @@ bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
   if (!lay.resident) {
     if (!lim(dt, lay.logC, sc.E_col, &kc)) return false;
     if (sc.tw < 1 || sc.tw * kc.tps > COL_MAXT) return false;
-    if ((size_t)sc.tw * col_lds_stride(kc.lds_raw, sc.tw) * kc.elem_bytes > 160 * 1024) return false;
+    if ((size_t)sc.tw * kc.lds_raw * kc.elem_bytes > 160 * 1024) return false;
   }
   return true;
 }
@@ -285,7 +285,7 @@ Sched default_sched(hk_dtype_t dt, const Layout &lay, int prog, int64_t batch) {
     lim(dt, lay.logC, sc.E_col, &kc);
     const int want_tw = dbl ? 8 : 16;  // 128-byte row segments
     int tw = std::max(1, std::min(want_tw, COL_MAXT / kc.tps));
-    while (tw > 1 && (size_t)tw * col_lds_stride(kc.lds_raw, tw) * kc.elem_bytes > 144 * 1024) tw >>= 1;
+    while (tw > 1 && (size_t)tw * kc.lds_raw * kc.elem_bytes > 144 * 1024) tw >>= 1;
     sc.tw = tw;
   }
   (void)prog;
