@@ -271,12 +271,14 @@ hk_status_t hk_tune_load(const char *path, int *n_loaded);
  * this thread (diagnostics). */
 int hk_last_launch_count(void);
 /* Kernel timing (diagnostics).  Between start and stop, every kernel the
- * library enqueues is bracketed by HIP events recorded on its own stream.
- * hk_profile_stop synchronizes on those events and returns, per kernel kind,
+ * library enqueues is launched with a start/stop HIP event pair that the
+ * runtime timestamps at that dispatch's own begin and end (the kernel's
+ * execution time, as a kernel trace reports it).  Not for use during graph
+ * capture.  hk_profile_stop synchronizes on those events and returns, per kernel kind,
  * the summed duration in milliseconds and the number of launches (arrays of
  * HK_PROF_KINDS entries): 0 resident single-workgroup transforms, 1 pass A
  * (column FFTs of the inputs), 2 pass B (row FFTs + spectral product),
- * 3 pass D (column FFTs of the output + slice), 4 batched task kernel. */
+ * 3 pass D (column FFTs of the output + slice), 4 batched task kernels (persistent or grouped). */
 #define HK_PROF_KINDS 5
 hk_status_t hk_profile_start(void);
 hk_status_t hk_profile_stop(double *ms_by_kind, int64_t *launches_by_kind);

@@ -50,17 +50,123 @@ struct PV {
   }
 };
 
-template <typename T>
-__device__ __forceinline__ cx<T> load_op(const void *base, int64_t idx, int flags) {
-  if (flags & OPF_REAL) {
-    const T v = ((const T *)base)[idx];
-    return mk(v, T(0));
-  }
-  cx<T> v = ((const cx<T> *)base)[idx];
-  if (flags & OPF_CONJ) v.y = -v.y;
-  return v;
+// ---------------------------------------------------------------------------
+// Memory access through raw buffer resources.  A resource covers
+// [base, base + bytes); gfx9 range checking makes a load at an offset past
+// the end return zero and drops such a store.  The zero padding of the
+// operands, the output slice and the unused lanes of a tile therefore cost no
+// compares or selects, and addresses are 32-bit byte offsets from one scalar
+// base instead of 64-bit pointers per lane.  Every buffer here is below
+// 2^31 bytes (at most 2^24 elements of 16 bytes), so OOB_OFF is out of range
+// for all of them.
+// ---------------------------------------------------------------------------
+constexpr uint32_t OOB_OFF = 0x80000000u;
+constexpr int BUF_WORD3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
+
+// `base` and `bytes` must be the same on every lane of the wavefront (one
+// instance per workgroup); they are moved to scalar registers explicitly so
+// that the compiler need not prove it.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_buf(const void *base, int64_t bytes) {
+  const int64_t nb = bytes < 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : bytes);
+  const uint64_t b = (uint64_t)(uintptr_t)base;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  const int n = __builtin_amdgcn_readfirstlane((int)nb);
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(((uint64_t)hi << 32) | lo), (short)0, n, BUF_WORD3);
 }
 
+template <typename T>
+struct BufIO;
+template <>
+struct BufIO<float> {
+  static __device__ __forceinline__ cx<float> ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    return mk(__uint_as_float(v[0]), __uint_as_float(v[1]));
+  }
+  static __device__ __forceinline__ float ld1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ void st(cx<float> a, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    u2 v;
+    v[0] = __float_as_uint(a.x);
+    v[1] = __float_as_uint(a.y);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+  }
+  static __device__ __forceinline__ void st1(float a, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(a), r, off, 0, 0);
+  }
+};
+template <>
+struct BufIO<double> {
+  static __device__ __forceinline__ double u2d(unsigned lo, unsigned hi) {
+    return __hiloint2double((int)hi, (int)lo);
+  }
+  static __device__ __forceinline__ cx<double> ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return mk(u2d(v[0], v[1]), u2d(v[2], v[3]));
+  }
+  static __device__ __forceinline__ double ld1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    return u2d(v[0], v[1]);
+  }
+  static __device__ __forceinline__ void st(cx<double> a, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    u4 v;
+    v[0] = (unsigned)__double2loint(a.x);
+    v[1] = (unsigned)__double2hiint(a.x);
+    v[2] = (unsigned)__double2loint(a.y);
+    v[3] = (unsigned)__double2hiint(a.y);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+  }
+  static __device__ __forceinline__ void st1(double a, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    u2 v;
+    v[0] = (unsigned)__double2loint(a);
+    v[1] = (unsigned)__double2hiint(a);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+  }
+};
+
+// Bytes of one stored element of an operand (OPF_REAL: real part only).
+template <typename T>
+__device__ __forceinline__ int elem_size(int flags) {
+  return (flags & OPF_REAL) ? (int)sizeof(T) : (int)sizeof(cx<T>);
+}
+
+// a[s] = operand element at byte offset off[s] (zero past the resource's end),
+// with the operand's REAL / CONJ conventions.  All EE loads issue back to back.
+template <typename T, int EE>
+__device__ __forceinline__ void bgather(cx<T> (&a)[EE], __amdgpu_buffer_rsrc_t r, const uint32_t (&off)[EE],
+                                        int flags) {
+  if (flags & OPF_REAL) {
+    T v[EE];
+#pragma unroll
+    for (int s = 0; s < EE; ++s) v[s] = BufIO<T>::ld1(r, off[s]);
+#pragma unroll
+    for (int s = 0; s < EE; ++s) a[s] = mk(v[s], T(0));
+  } else {
+#pragma unroll
+    for (int s = 0; s < EE; ++s) a[s] = BufIO<T>::ld(r, off[s]);
+    if (flags & OPF_CONJ) {
+#pragma unroll
+      for (int s = 0; s < EE; ++s) a[s].y = -a[s].y;
+    }
+  }
+}
+
+// Stores v at byte offset off (dropped past the resource's end).
+template <typename T>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, cx<T> v, int real_out) {
+  if (real_out)
+    BufIO<T>::st1(v.x, r, off);
+  else
+    BufIO<T>::st(v, r, off);
+}
+
+// Flat (64-bit per-lane address) access, for the resident rows of a
+// workgroup that belong to different instances: a buffer resource must be
+// uniform across the wave, per-lane bases would need a waterfall loop.
 // Loads a[s] = src[idx[s]] where ok[s] and zero elsewhere, without branches:
 // a slot that is not ok reads element 0 (every operand has at least one
 // element) and is zeroed afterwards, so all EE loads issue back to back
@@ -153,9 +259,11 @@ struct RowBody {
   static __device__ __forceinline__ void load(cx<T> (&a)[EE], const Shape &sh, const PV &P, int o,
                                               int64_t row, bool valid_row, int t, bool resident) {
     const OpDesc &od = sh.ops[o];
-    int64_t idx[EE];
-    bool ok[EE];
+    uint32_t off[EE];
     if (resident) {
+      // the rows of a workgroup may be different instances: flat loads
+      int64_t idx[EE];
+      bool ok[EE];
 #pragma unroll
       for (int s = 0; s < EE; ++s) {
         idx[s] = t + s * TPS;
@@ -163,13 +271,17 @@ struct RowBody {
       }
       gather<T, EE>(a, P.op(o), idx, ok, od.flags);
     } else {
-      const cx<T> *src = ws_buf<T>(sh, P, od.buf) + (valid_row ? row : 0) * L;
+      // row `row` of the operand's column transform; its columns past
+      // ncol_nz were never written and read as zero
+      const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+      const auto r = make_buf(ws_buf<T>(sh, P, od.buf), N * (int64_t)sizeof(cx<T>));
+      const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
 #pragma unroll
       for (int s = 0; s < EE; ++s) {
-        idx[s] = t + s * TPS;
-        ok[s] = valid_row && idx[s] < od.ncol_nz;
+        const int i = t + s * TPS;
+        off[s] = (valid_row && i < od.ncol_nz) ? rbase + (uint32_t)(i * (int)sizeof(cx<T>)) : OOB_OFF;
       }
-      gather<T, EE>(a, src, idx, ok, 0);
+      bgather<T, EE>(a, r, off, 0);
     }
   }
 
@@ -188,16 +300,19 @@ struct RowBody {
         if (pos < lim) store_out<T>(dst, pos, cj ? cconj(a[s]) : a[s], sh.real_out);
       }
     } else {
-      cx<T> *dst = ws_buf<T>(sh, P, sh.ops[which].buf) + row * L;
+      const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+      const auto r = make_buf(ws_buf<T>(sh, P, sh.ops[which].buf), N * (int64_t)sizeof(cx<T>));
+      const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
       if (!sh.is_block) {
         // four-step twiddles W_N^{pos * row}, pos = t + s TPS
         cx<T> w[EE];
         slot_twiddles<T, EE>(w, row, t, TPS, sh.logR + sh.logC, tw24, tw4096);
 #pragma unroll
-        for (int s = 0; s < EE; ++s) dst[t + s * TPS] = cmul(a[s], w[s]);
+        for (int s = 0; s < EE; ++s)
+          BufIO<T>::st(cmul(a[s], w[s]), r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
       } else {
 #pragma unroll
-        for (int s = 0; s < EE; ++s) dst[t + s * TPS] = a[s];
+        for (int s = 0; s < EE; ++s) BufIO<T>::st(a[s], r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
       }
     }
   }
@@ -316,32 +431,33 @@ struct ColBody {
     const bool cvalid = c < job.ncols;
     const int64_t R = (int64_t)1 << sh.logR;
     cx<T> a[EE];
-    int64_t idx[EE];
-    bool ok[EE];
+    uint32_t off[EE];
+    constexpr int CB = (int)sizeof(cx<T>);
+    const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
     if (job.kind == COL_A) {
       const OpDesc &od = sh.ops[job.op];
+      const int es = elem_size<T>(od.flags);
       if (!sh.is_block) {
+        // element c + R k of the padded operand; past its end reads zero
+        const auto r = make_buf(P.op(job.op), od.len * es);
 #pragma unroll
-        for (int s = 0; s < EE; ++s) {
-          idx[s] = c + R * (t + s * TPS);
-          ok[s] = cvalid && idx[s] < od.len;
-        }
+        for (int s = 0; s < EE; ++s) off[s] = (uint32_t)((c + R * (t + s * TPS)) * es);
+        bgather<T, EE>(a, r, off, od.flags);
       } else {
+        // generating matrix (len rows x cols columns, column-major): row c,
+        // column k; rows past len are zero padding (k past cols falls past
+        // the end of the resource)
+        const auto r = make_buf(P.op(job.op), od.len * od.cols * es);
+        const bool crow = c < od.len;
 #pragma unroll
-        for (int s = 0; s < EE; ++s) {
-          const int64_t r = t + s * TPS;
-          idx[s] = c + od.len * r;
-          ok[s] = cvalid && c < od.len && r < od.cols;
-        }
+        for (int s = 0; s < EE; ++s) off[s] = crow ? (uint32_t)((c + od.len * (t + s * TPS)) * es) : OOB_OFF;
+        bgather<T, EE>(a, r, off, od.flags);
       }
-      gather<T, EE>(a, P.op(job.op), idx, ok, od.flags);
     } else {
+      const auto r = make_buf(ws_buf<T>(sh, P, job.buf), N * CB);
 #pragma unroll
-      for (int s = 0; s < EE; ++s) {
-        idx[s] = c + R * (t + s * TPS);
-        ok[s] = cvalid;
-      }
-      gather<T, EE>(a, ws_buf<T>(sh, P, job.buf), idx, ok, 0);
+      for (int s = 0; s < EE; ++s) off[s] = (uint32_t)((c + R * (t + s * TPS)) * CB);
+      bgather<T, EE>(a, r, off, 0);
     }
     StageTw<T, L, E> stw;
     stw.init(t, tw4096);
@@ -354,31 +470,38 @@ struct ColBody {
     fft_seq<T, L, E>(a, t, lds + cw, stw, __builtin_ctz((unsigned)TW));
     if (!cvalid) return;
     if (job.kind == COL_A) {
-      cx<T> *dst = ws_buf<T>(sh, P, job.buf);
+      const auto r = make_buf(ws_buf<T>(sh, P, job.buf), N * CB);
       if (twid) {
 #pragma unroll
-        for (int s = 0; s < EE; ++s) dst[c + R * (t + s * TPS)] = cmul(a[s], wst[s]);
+        for (int s = 0; s < EE; ++s) BufIO<T>::st(cmul(a[s], wst[s]), r, off_ws(c, R, t + s * TPS));
       } else {
 #pragma unroll
-        for (int s = 0; s < EE; ++s) dst[c + R * (t + s * TPS)] = a[s];
+        for (int s = 0; s < EE; ++s) BufIO<T>::st(a[s], r, off_ws(c, R, t + s * TPS));
       }
     } else {
       void *dst = job.op == 0 ? P.y() : P.out1();
+      const int es = sh.real_out ? (int)sizeof(T) : CB;
       if (!sh.is_block) {
+        // the slice [0, lim) is the resource: later positions are dropped
         const int64_t lim = job.op == 0 ? sh.out_rows : sh.out1_len;
+        const auto r = make_buf(dst, lim * es);
 #pragma unroll
-        for (int s = 0; s < EE; ++s) {
-          const int64_t pos = c + R * (t + s * TPS);
-          if (pos < lim) store_out<T>(dst, pos, job.conj_out ? cconj(a[s]) : a[s], sh.real_out);
-        }
+        for (int s = 0; s < EE; ++s)
+          bstore<T>(r, (uint32_t)((c + R * (t + s * TPS)) * es), job.conj_out ? cconj(a[s]) : a[s], sh.real_out);
       } else if (c < sh.out_rows) {
+        // out_rows x out_cols corner, column-major; columns past out_cols fall
+        // past the end of the resource
+        const auto r = make_buf(dst, sh.out_rows * sh.out_cols * es);
 #pragma unroll
-        for (int s = 0; s < EE; ++s) {
-          const int64_t k = t + s * TPS;
-          if (k < sh.out_cols) store_out<T>(dst, c + sh.out_rows * k, job.conj_out ? cconj(a[s]) : a[s], sh.real_out);
-        }
+        for (int s = 0; s < EE; ++s)
+          bstore<T>(r, (uint32_t)((c + sh.out_rows * (t + s * TPS)) * es), job.conj_out ? cconj(a[s]) : a[s],
+                    sh.real_out);
       }
     }
+  }
+
+  static __device__ __forceinline__ uint32_t off_ws(int64_t c, int64_t R, int k) {
+    return (uint32_t)((c + R * k) * (int64_t)sizeof(cx<T>));
   }
 };
 

@@ -99,9 +99,9 @@ Status sched_load(const char *path, int *loaded);
 // Thread-local launch counter.
 void count_launch();
 
-// Kernel timing (diagnostics): when enabled, HIP events are recorded on the
-// launch stream immediately before and after every kernel the library
-// enqueues, grouped by kind.
+// Kernel timing (diagnostics): when enabled, every kernel the library
+// enqueues carries a start/stop event pair timestamped at its dispatch's
+// begin and end (launch_kernel), grouped by kind.
 enum ProfKind : int { PK_RESIDENT = 0, PK_PASS_A = 1, PK_PASS_B = 2, PK_PASS_D = 3, PK_BATCH = 4, PK_COUNT = 5 };
 bool prof_enabled();
 void prof_before(hipStream_t st);
