@@ -4,11 +4,14 @@
 // 2^logC "column" length) and store element n = n1 + R n2 at offset n.
 // With n = n1 + R n2 and k = k2 + C k1 (Bailey's four-step decomposition):
 //   X[k2 + C k1] = sum_n1 W_R^{n1 k1} W_N^{n1 k2} sum_n2 x[n1 + R n2] W_C^{n2 k2}.
-// Pass A: for each column n1, a length-C FFT along n2, times W_N^{n1 k2},
-//         stored at n1 + R k2.
-// Pass B: for each row k2, a length-R FFT along n1 gives X[k2 + C k1] at
-//         offset k1 + R k2 ("transposed" spectral order).  Every operand uses
-//         the same order, so the pointwise spectral product is done here.
+// Pass A: for each column n1, a length-C FFT along n2, stored at n1 + R k2.
+// Pass B: for each row k2, the twiddle W_N^{n1 k2} and a length-R FFT along
+//         n1 give X[k2 + C k1] at offset k1 + R k2 ("transposed" spectral
+//         order).  Every operand uses the same order, so the pointwise
+//         spectral product is done here.  The input twiddles of row k2 are the
+//         same numbers W_N^{pos k2}, pos = t + s TPS, as its output twiddles
+//         below, so a row computes them once for all its operands and its
+//         output, and pass A needs none.
 //         The output transform y = fft(z) starts on the same row:
 //           y[j1 + R j2] = sum_k2 W_C^{j2 k2} W_N^{j1 k2} sum_k1 z[k2 + C k1] W_R^{j1 k1},
 //         i.e. a length-R FFT along k1, times W_N^{j1 k2}, stored at j1 + R k2.
@@ -62,6 +65,15 @@ struct PV {
 // ---------------------------------------------------------------------------
 constexpr uint32_t OOB_OFF = 0x80000000u;
 constexpr int BUF_WORD3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
+// Stores of whole 128-byte lines are non-temporal ("nt"): the pass outputs
+// are read by the next kernel, mostly on another XCD, so keeping them in
+// this XCD's L2 only delays the end of the kernel, which must write dirty
+// lines back before the next launch can see them.  Streaming them out as
+// they are produced shortened the column pass of the large single product
+// from 10.3 to 8.9 us.  Narrower segments (column tiles of < 128 bytes) keep
+// the default policy, so that L2 merges neighbouring tiles' halves of a line
+// instead of memory doing partial-line writes.
+constexpr int ST_NT = 2, ST_DEFAULT = 0;
 
 // `base` and `bytes` must be the same on every lane of the wavefront (one
 // instance per workgroup); they are moved to scalar registers explicitly so
@@ -86,15 +98,17 @@ struct BufIO<float> {
   static __device__ __forceinline__ float ld1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
   }
+  template <int POL = ST_NT>
   static __device__ __forceinline__ void st(cx<float> a, __amdgpu_buffer_rsrc_t r, uint32_t off) {
     typedef unsigned int u2 __attribute__((ext_vector_type(2)));
     u2 v;
     v[0] = __float_as_uint(a.x);
     v[1] = __float_as_uint(a.y);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, POL);
   }
+  template <int POL = ST_NT>
   static __device__ __forceinline__ void st1(float a, __amdgpu_buffer_rsrc_t r, uint32_t off) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(a), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(a), r, off, 0, POL);
   }
 };
 template <>
@@ -110,6 +124,7 @@ struct BufIO<double> {
     const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
     return u2d(v[0], v[1]);
   }
+  template <int POL = ST_NT>
   static __device__ __forceinline__ void st(cx<double> a, __amdgpu_buffer_rsrc_t r, uint32_t off) {
     typedef unsigned int u4 __attribute__((ext_vector_type(4)));
     u4 v;
@@ -117,14 +132,15 @@ struct BufIO<double> {
     v[1] = (unsigned)__double2hiint(a.x);
     v[2] = (unsigned)__double2loint(a.y);
     v[3] = (unsigned)__double2hiint(a.y);
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, POL);
   }
+  template <int POL = ST_NT>
   static __device__ __forceinline__ void st1(double a, __amdgpu_buffer_rsrc_t r, uint32_t off) {
     typedef unsigned int u2 __attribute__((ext_vector_type(2)));
     u2 v;
     v[0] = (unsigned)__double2loint(a);
     v[1] = (unsigned)__double2hiint(a);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, POL);
   }
 };
 
@@ -156,12 +172,12 @@ __device__ __forceinline__ void bgather(cx<T> (&a)[EE], __amdgpu_buffer_rsrc_t r
 }
 
 // Stores v at byte offset off (dropped past the resource's end).
-template <typename T>
+template <typename T, int POL = ST_NT>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, cx<T> v, int real_out) {
   if (real_out)
-    BufIO<T>::st1(v.x, r, off);
+    BufIO<T>::template st1<POL>(v.x, r, off);
   else
-    BufIO<T>::st(v, r, off);
+    BufIO<T>::template st<POL>(v, r, off);
 }
 
 // Flat (64-bit per-lane address) access, for the resident rows of a
@@ -288,7 +304,7 @@ struct RowBody {
   // Stores output `which` (0: y / grad_h, 1: grad_x) of this row.
   static __device__ __forceinline__ void store(const cx<T> (&a)[EE], const Shape &sh, const PV &P,
                                                int which, int64_t row, bool valid_row, int t,
-                                               bool resident, const cx<T> *tw24, const cx<T> *tw4096) {
+                                               bool resident, const cx<T> (&w)[EE]) {
     if (!valid_row) return;
     if (resident) {
       void *dst = which == 0 ? P.y() : P.out1();
@@ -304,9 +320,7 @@ struct RowBody {
       const auto r = make_buf(ws_buf<T>(sh, P, sh.ops[which].buf), N * (int64_t)sizeof(cx<T>));
       const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
       if (!sh.is_block) {
-        // four-step twiddles W_N^{pos * row}, pos = t + s TPS
-        cx<T> w[EE];
-        slot_twiddles<T, EE>(w, row, t, TPS, sh.logR + sh.logC, tw24, tw4096);
+        // four-step twiddles W_N^{pos * row}, pos = t + s TPS (from twiddles())
 #pragma unroll
         for (int s = 0; s < EE; ++s)
           BufIO<T>::st(cmul(a[s], w[s]), r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
@@ -314,6 +328,21 @@ struct RowBody {
 #pragma unroll
         for (int s = 0; s < EE; ++s) BufIO<T>::st(a[s], r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
       }
+    }
+  }
+
+  // Pass-B rows of a 1D instance: w[s] = W_N^{(t + s TPS) row}, used on the
+  // loaded operands (pass A's twiddle) and on the stored output.
+  static __device__ __forceinline__ bool twiddles(cx<T> (&w)[EE], const Shape &sh, int64_t row, int t,
+                                                  bool resident, const cx<T> *tw24, const cx<T> *tw4096) {
+    const bool on = !resident && !sh.is_block;
+    if (on) slot_twiddles<T, EE>(w, row, t, TPS, sh.logR + sh.logC, tw24, tw4096);
+    return on;
+  }
+  static __device__ __forceinline__ void twiddle_in(cx<T> (&a)[EE], const cx<T> (&w)[EE], bool on) {
+    if (on) {
+#pragma unroll
+      for (int s = 0; s < EE; ++s) a[s] = cmul(a[s], w[s]);
     }
   }
 
@@ -329,9 +358,12 @@ struct RowBody {
     load(a, sh, P, 0, row, valid_row, t, resident);
     StageTw<T, L, E> stw;
     stw.init(t, tw4096);
+    cx<T> w[EE];
+    const bool tw_on = twiddles(w, sh, row, t, resident, tw24, tw4096);
     for (int o = 0; o < sh.nops; ++o) {
       // the next operand's loads are in flight while this one is transformed
       if (o + 1 < sh.nops) load(nx, sh, P, o + 1, row, valid_row, t, resident);
+      twiddle_in(a, w, tw_on);
       fft(a, t, lds, stw);
       const OpDesc &od = sh.ops[o];
       if (od.role == ROLE_H) {
@@ -352,7 +384,7 @@ struct RowBody {
     }
     if (sh.want_y) {
       fft(acc, t, lds, stw);
-      store(acc, sh, P, 0, row, valid_row, t, resident, tw24, tw4096);
+      store(acc, sh, P, 0, row, valid_row, t, resident, w);
     }
     return part;
   }
@@ -369,10 +401,14 @@ struct RowBody {
     if (P.phi()) phc = cconj(*(const cx<T> *)P.phi());
     const T m1 = T(sh.m - 1), m0 = T(sh.m);
     StageTw<T, L, E> stw;
+    cx<T> w[EE];
+    bool tw_on;
     {
       cx<T> xs[EE], p1[EE], vs[EE];
       load(xs, sh, P, 0, row, valid_row, t, resident);
       stw.init(t, tw4096);
+      tw_on = twiddles(w, sh, row, t, resident, tw24, tw4096);
+      twiddle_in(xs, w, tw_on);
       fft(xs, t, lds, stw);
 #pragma unroll
       for (int s = 0; s < EE; ++s) p1[s] = mk(T(1), T(0));
@@ -383,6 +419,7 @@ struct RowBody {
       const bool has_v = sh.nops > 1 && sh.ops[1].role == ROLE_V;
       if (has_v) {
         load(vs, sh, P, 1, row, valid_row, t, resident);
+        twiddle_in(vs, w, tw_on);
         fft(vs, t, lds, stw);
       } else {
 #pragma unroll
@@ -398,15 +435,16 @@ struct RowBody {
     }
     if (sh.want_y) {
       fft(a, t, lds, stw);
-      store(a, sh, P, 0, row, valid_row, t, resident, tw24, tw4096);
+      store(a, sh, P, 0, row, valid_row, t, resident, w);
     }
     if (sh.want_out1) {
       load(a, sh, P, sh.nops - 1, row, valid_row, t, resident);  // H
+      twiddle_in(a, w, tw_on);
       fft(a, t, lds, stw);
 #pragma unroll
       for (int s = 0; s < EE; ++s) a[s] = cmul(cscale(cconj(a[s]), invN), gq[s]);
       fft(a, t, lds, stw);
-      store(a, sh, P, 1, row, valid_row, t, resident, tw24, tw4096);
+      store(a, sh, P, 1, row, valid_row, t, resident, w);
     }
   }
 };
@@ -461,23 +499,25 @@ struct ColBody {
     }
     StageTw<T, L, E> stw;
     stw.init(t, tw4096);
-    // pass A's four-step twiddles W_N^{c k}, k = t + s TPS: their table loads
-    // are issued before the transform so that they overlap it
-    cx<T> wst[EE];
-    const bool twid = job.kind == COL_A && !sh.is_block;
-    if (twid) slot_twiddles<T, EE>(wst, c, t, TPS, sh.logR + sh.logC, tw24, tw4096);
     // TW interleaved columns: element i of column cw at lds[(sw(i) << log2 TW) + cw]
     fft_seq<T, L, E>(a, t, lds + cw, stw, __builtin_ctz((unsigned)TW));
     if (!cvalid) return;
+    // a row segment of the tile is TW elements: whole lines stream out
+    // (non-temporal), narrower ones merge in L2
+    if (TW * CB >= 128)
+      store_tile<ST_NT>(a, sh, P, job, c, R, t, N);
+    else
+      store_tile<ST_DEFAULT>(a, sh, P, job, c, R, t, N);
+  }
+
+  template <int POL>
+  static __device__ __forceinline__ void store_tile(const cx<T> (&a)[EE], const Shape &sh, const PV &P,
+                                                    const ColJob &job, int64_t c, int64_t R, int t, int64_t N) {
+    constexpr int CB = (int)sizeof(cx<T>);
     if (job.kind == COL_A) {
       const auto r = make_buf(ws_buf<T>(sh, P, job.buf), N * CB);
-      if (twid) {
 #pragma unroll
-        for (int s = 0; s < EE; ++s) BufIO<T>::st(cmul(a[s], wst[s]), r, off_ws(c, R, t + s * TPS));
-      } else {
-#pragma unroll
-        for (int s = 0; s < EE; ++s) BufIO<T>::st(a[s], r, off_ws(c, R, t + s * TPS));
-      }
+      for (int s = 0; s < EE; ++s) BufIO<T>::template st<POL>(a[s], r, off_ws(c, R, t + s * TPS));
     } else {
       void *dst = job.op == 0 ? P.y() : P.out1();
       const int es = sh.real_out ? (int)sizeof(T) : CB;
@@ -487,15 +527,16 @@ struct ColBody {
         const auto r = make_buf(dst, lim * es);
 #pragma unroll
         for (int s = 0; s < EE; ++s)
-          bstore<T>(r, (uint32_t)((c + R * (t + s * TPS)) * es), job.conj_out ? cconj(a[s]) : a[s], sh.real_out);
+          bstore<T, POL>(r, (uint32_t)((c + R * (t + s * TPS)) * es), job.conj_out ? cconj(a[s]) : a[s],
+                         sh.real_out);
       } else if (c < sh.out_rows) {
         // out_rows x out_cols corner, column-major; columns past out_cols fall
         // past the end of the resource
         const auto r = make_buf(dst, sh.out_rows * sh.out_cols * es);
 #pragma unroll
         for (int s = 0; s < EE; ++s)
-          bstore<T>(r, (uint32_t)((c + sh.out_rows * (t + s * TPS)) * es), job.conj_out ? cconj(a[s]) : a[s],
-                    sh.real_out);
+          bstore<T, POL>(r, (uint32_t)((c + sh.out_rows * (t + s * TPS)) * es), job.conj_out ? cconj(a[s]) : a[s],
+                         sh.real_out);
       }
     }
   }
