@@ -488,8 +488,31 @@ def time_region(torch, fn, reps, warm=2):
     return e0.elapsed_time(e1) / reps
 
 
+def cpu_fft_method(h, x, m, reps=3):
+    """The paper's fast procedure on the host CPU (scipy.fft, FP64, all cores):
+    a cross-check of what the method costs on a CPU, not the oracle."""
+    import scipy.fft as sf
+    n, dh = len(x), len(h)
+    N = 1 << (dh - 1).bit_length()
+    workers = os.cpu_count() or 1
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        hh = sf.ifft(h, N, workers=workers)
+        xx = sf.fft(x, N, workers=workers)
+        z = hh * xx ** (m - 1)
+        y = sf.fft(z, workers=workers)[:n]
+        a = np.sum(z * xx)
+        ts.append(time.perf_counter() - t0)
+        del y, a
+    t = float(np.median(ts))
+    return {"TVP_s": round(1.0 / t, 2), "ms": round(t * 1e3, 2), "cores": workers, "kind": "scipy.fft c128"}
+
+
 def run_extras(args, data, hk, _lib, L, torch, dev):
     ex = {}
+    ex["large_single_cpu_fft_method"] = cpu_fft_method(data["large"][0][2], data["large"][0][3], M)
+    log("cpu fft method", ex["large_single_cpu_fft_method"])
     # the large single product in complex128 (same inputs, FP64 arithmetic)
     if args.dtype == "c64":
         P = 16

@@ -449,11 +449,16 @@ Status plan_release_after(hk_plan_t p, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Autotuner: times every valid schedule of one shape (split of N = R * C,
-// elements per lane of the row and column transforms, rows per workgroup,
-// column-tile width) on scratch buffers, and caches the fastest under the key
-// the call path looks up (dtype, program, 1D/BHHB, N, batch class, XCD tile
-// numbering).  Inputs are zero-filled device buffers, distinct per instance.
+// Autotuner.  For each row/column split of N it runs a coordinate descent:
+// the row-pass parameters (elements per lane, rows per workgroup, rows in
+// turn) and the column-pass parameters (elements per lane, tile width, XCD
+// tile numbering) drive different kernels, so each group is searched with the
+// other fixed, twice.  Every candidate is timed on scratch buffers: inputs
+// distinct per instance (zero-filled), and for single products a pool of
+// input sets larger than the 256 MB last-level cache that successive launches
+// cycle through, so that inputs come from HBM as in use.  The winner is
+// cached under the key the call path looks up (dtype, program, 1D/BHHB, N,
+// batch class).
 // ---------------------------------------------------------------------------
 Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   Status s = ensure_device();
@@ -464,34 +469,16 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   Layout lay0;
   s = layout_for(p, 0, &lay0);
   if (!s.ok()) return s;
-  std::vector<Sched> cands;
-  std::vector<Layout> lays;
-  const int splits[] = {0, -1, 1, -2, 2};
-  for (int sp : splits) {
+  // layouts to search
+  std::vector<std::pair<int, Layout>> layouts;
+  for (int sp : {0, -1, 1, -2, 2}) {
     Layout lay;
     if (p.is_block && sp != 0) continue;
     if (!layout_for(p, sp, &lay).ok()) continue;
     if (sp != 0 && (lay.resident || (lay.logR == lay0.logR && lay.logC == lay0.logC))) continue;
-    for (int er : {8, 16})
-      for (int rows : {1, 2, 4, 8, 16, 32})
-        for (int ec : {8, 16})
-          for (int tw : {1, 2, 4, 8, 16, 32})
-            for (int xcd : {0, 1}) {
-              if (lay.resident && (ec != 8 || tw != 1 || xcd != 0)) continue;
-              Sched sc;
-              sc.E_row = er;
-              sc.rows_per_wg = rows;
-              sc.E_col = ec;
-              sc.tw = tw;
-              sc.split = sp;
-              sc.xcd = xcd;
-              if (!sched_valid(dt, lay, sc)) continue;
-              cands.push_back(sc);
-              lays.push_back(lay);
-            }
+    layouts.push_back({sp, lay});
   }
-  if (cands.empty()) return fail(HK_ERR_NOT_SUPPORTED, "no schedule candidates");
-  // buffer sizes
+  // buffer sizes (workspace does not depend on the schedule)
   const size_t eb = elem_bytes(dt);
   int64_t hrows = 1 - p.m, hcols = 1 - p.m, vmax = 1;
   for (int q = 0; q < p.m; ++q) {
@@ -502,16 +489,14 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   const int64_t hlen = p.is_block ? hrows * hcols : hrows;
   const int64_t ylen = std::max<int64_t>(hlen, vmax);  // room for y, grad_h or grad_x
   size_t wsb = 0;
-  for (size_t i = 0; i < cands.size(); ++i) {
+  for (const auto &sl : layouts) {
+    Sched sc = default_sched(dt, sl.second, p.prog, batch);
+    sc.split = sl.first;
     Shape sh;
     Ptrs P;
-    build_shape(p, lays[i], cands[i], &sh, &P, nullptr);
+    build_shape(p, sl.second, sc, &sh, &P, nullptr);
     wsb = std::max(wsb, instance_ws_bytes(sh, dt));
   }
-  // Distinct inputs per instance, and for single products a pool of input
-  // sets larger than the 256 MB last-level cache that successive launches
-  // cycle through: schedules are timed with their inputs coming from HBM,
-  // as in use.
   const int64_t in_bytes = (hlen + vmax) * (int64_t)eb;
   const int64_t pool = batch > 1 ? 1 : std::max<int64_t>(1, std::min<int64_t>(64, ((int64_t)384 << 20) / in_bytes + 1));
   const int64_t nin = batch > 1 ? batch : pool;
@@ -527,58 +512,124 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  double best = 1e30;
-  int besti = -1;
-  if (e == hipSuccess) {
-    p.h = dh;
-    for (int q = 0; q < p.m; ++q)
-      if (p.vec[q]) p.vec[q] = dx;
-    if (p.prog == PROG_FWD) {
-      if (p.y) p.y = dy;
-      if (p.alpha) p.alpha = da;
-    } else {
-      if (p.v) p.v = dx;
-      if (p.phi) p.phi = da;
-      if (p.gh) p.gh = dy;
-      if (p.gx) p.gx = dy1;
-    }
-    const int reps = batch > 8 ? 2 : (batch > 1 ? 5 : (int)std::max<int64_t>(16, pool));
-    for (size_t i = 0; i < cands.size() && s.ok(); ++i) {
-      Shape sh;
-      Ptrs P;
-      build_shape(p, lays[i], cands[i], &sh, &P, nullptr);
-      P.ws = dws;
-      Strides str;
-      memset(&str, 0, sizeof(str));
-      int64_t op_stride[MAXOPS];
-      for (int o = 0; o < sh.nops; ++o) op_stride[o] = (sh.ops[o].role == ROLE_H ? hlen : vmax) * (int64_t)eb;
-      if (batch > 1)
-        for (int o = 0; o < sh.nops; ++o) str.op[o] = op_stride[o];
-      str.y = ylen * eb;
-      str.out1 = ylen * eb;
-      str.alpha = eb;
-      str.ws = (int64_t)instance_ws_bytes(sh, dt);
-      Ptrs P0 = P;
-      auto launch_k = [&](int k) {
-        if (batch == 1)
-          for (int o = 0; o < sh.nops; ++o) P.op[o] = (const char *)P0.op[o] + (k % pool) * op_stride[o];
-        return launch_shape(dt, sh, cands[i], P, str, batch, nullptr);
-      };
-      s = launch_k(0);  // warm-up
-      if (!s.ok()) break;
-      (void)hipEventRecord(e0, nullptr);
-      for (int r = 0; r < reps && s.ok(); ++r) s = launch_k(r + 1);
-      (void)hipEventRecord(e1, nullptr);
-      (void)hipEventSynchronize(e1);
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      const double t = ms / reps;
+  p.h = dh;
+  for (int q = 0; q < p.m; ++q)
+    if (p.vec[q]) p.vec[q] = dx;
+  if (p.prog == PROG_FWD) {
+    if (p.y) p.y = dy;
+    if (p.alpha) p.alpha = da;
+  } else {
+    if (p.v) p.v = dx;
+    if (p.phi) p.phi = da;
+    if (p.gh) p.gh = dy;
+    if (p.gx) p.gx = dy1;
+  }
+  const int reps = batch > 8 ? 2 : (batch > 1 ? 5 : (int)std::max<int64_t>(16, pool));
+  int ntimed = 0;
+  double best_seen = 1e30;
+  // time of one schedule in ms (infinite if the kernels cannot run it)
+  auto time_sched = [&](const Layout &lay, const Sched &sc) -> double {
+    if (!sched_valid(dt, lay, sc)) return 1e30;
+    Shape sh;
+    Ptrs P;
+    build_shape(p, lay, sc, &sh, &P, nullptr);
+    P.ws = dws;
+    Strides str;
+    memset(&str, 0, sizeof(str));
+    int64_t op_stride[MAXOPS];
+    for (int o = 0; o < sh.nops; ++o) op_stride[o] = (sh.ops[o].role == ROLE_H ? hlen : vmax) * (int64_t)eb;
+    if (batch > 1)
+      for (int o = 0; o < sh.nops; ++o) str.op[o] = op_stride[o];
+    str.y = ylen * eb;
+    str.out1 = ylen * eb;
+    str.alpha = eb;
+    str.ws = (int64_t)instance_ws_bytes(sh, dt);
+    const Ptrs P0 = P;
+    auto launch_k = [&](int k) {
+      if (batch == 1)
+        for (int o = 0; o < sh.nops; ++o) P.op[o] = (const char *)P0.op[o] + (k % pool) * op_stride[o];
+      return launch_shape(dt, sh, sc, P, str, batch, nullptr);
+    };
+    // warm-up launch, timed: a candidate already 4x slower than the best so
+    // far is not timed further
+    (void)hipEventRecord(e0, nullptr);
+    s = launch_k(0);
+    (void)hipEventRecord(e1, nullptr);
+    (void)hipEventSynchronize(e1);
+    if (!s.ok()) return 1e30;
+    float wms = 0;
+    (void)hipEventElapsedTime(&wms, e0, e1);
+    if (wms > 4.0 * best_seen) {
       if (verbose)
-        fprintf(stderr, "[hk autotune] split=%d E_row=%d rows=%d E_col=%d tw=%d xcd=%d : %.4f ms\n",
-                cands[i].split, cands[i].E_row, cands[i].rows_per_wg, cands[i].E_col, cands[i].tw, cands[i].xcd, t);
-      if (t < best) {
-        best = t;
-        besti = (int)i;
+        fprintf(stderr, "[hk autotune] split=%d E_row=%d rows=%d iters=%d E_col=%d tw=%d xcd=%d : %.4f ms (skipped)\n",
+                sc.split, sc.E_row, sc.rows_per_wg, sc.iters, sc.E_col, sc.tw, sc.xcd, wms);
+      return (double)wms;
+    }
+    (void)hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps && s.ok(); ++r) s = launch_k(r + 1);
+    (void)hipEventRecord(e1, nullptr);
+    (void)hipEventSynchronize(e1);
+    if (!s.ok()) return 1e30;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ++ntimed;
+    const double t = ms / reps;
+    best_seen = std::min(best_seen, t);
+    if (verbose)
+      fprintf(stderr, "[hk autotune] split=%d E_row=%d rows=%d iters=%d E_col=%d tw=%d xcd=%d : %.4f ms\n", sc.split,
+              sc.E_row, sc.rows_per_wg, sc.iters, sc.E_col, sc.tw, sc.xcd, t);
+    return t;
+  };
+  double best = 1e30;
+  Sched bestsc;
+  Layout bestlay;
+  if (e == hipSuccess) {
+    for (const auto &sl : layouts) {
+      const Layout &lay = sl.second;
+      Sched cur = default_sched(dt, lay, p.prog, batch);
+      cur.split = sl.first;
+      double tcur = time_sched(lay, cur);
+      if (!s.ok()) break;
+      for (int round = 0; round < 2 && s.ok(); ++round) {
+        // row-pass parameters
+        for (int er : {8, 16})
+          for (int rows : {1, 2, 4, 8, 16, 32})
+            for (int it : {1, 2, 4}) {
+              if (lay.resident && it != 1) continue;
+              Sched c = cur;
+              c.E_row = er;
+              c.rows_per_wg = rows;
+              c.iters = it;
+              if (c.E_row == cur.E_row && c.rows_per_wg == cur.rows_per_wg && c.iters == cur.iters) continue;
+              const double tc = time_sched(lay, c);
+              if (!s.ok()) break;
+              if (tc < tcur) {
+                tcur = tc;
+                cur = c;
+              }
+            }
+        if (lay.resident || !s.ok()) break;
+        // column-pass parameters
+        for (int ec : {8, 16})
+          for (int tw : {1, 2, 4, 8, 16, 32})
+            for (int xcd : {0, 1}) {
+              Sched c = cur;
+              c.E_col = ec;
+              c.tw = tw;
+              c.xcd = xcd;
+              if (c.E_col == cur.E_col && c.tw == cur.tw && c.xcd == cur.xcd) continue;
+              const double tc = time_sched(lay, c);
+              if (!s.ok()) break;
+              if (tc < tcur) {
+                tcur = tc;
+                cur = c;
+              }
+            }
+      }
+      if (tcur < best) {
+        best = tcur;
+        bestsc = cur;
+        bestlay = lay;
       }
     }
   }
@@ -593,14 +644,14 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   if (dws) (void)hipFree(dws);
   if (e != hipSuccess) return hip_fail(e, "autotune buffers");
   if (!s.ok()) return s;
-  if (besti < 0) return fail(HK_ERR_NOT_SUPPORTED, "autotune found no schedule");
-  const Layout &bl = lays[besti];
-  sched_store(dt, p.prog, p.is_block ? 1 : 0, lay0.logR + lay0.logC, p.is_block ? lay0.logC : -1, batch,
-              cands[besti]);
+  if (best >= 1e30) return fail(HK_ERR_NOT_SUPPORTED, "autotune found no schedule");
+  sched_store(dt, p.prog, p.is_block ? 1 : 0, lay0.logR + lay0.logC, p.is_block ? lay0.logC : -1, batch, bestsc);
   if (verbose)
-    fprintf(stderr, "[hk autotune] best: split=%d (R=2^%d C=2^%d) E_row=%d rows=%d E_col=%d tw=%d xcd=%d %.4f ms\n",
-            cands[besti].split, bl.logR, bl.logC, cands[besti].E_row, cands[besti].rows_per_wg, cands[besti].E_col,
-            cands[besti].tw, cands[besti].xcd, best);
+    fprintf(stderr,
+            "[hk autotune] best of %d: split=%d (R=2^%d C=2^%d) E_row=%d rows=%d iters=%d E_col=%d tw=%d xcd=%d "
+            "%.4f ms\n",
+            ntimed, bestsc.split, bestlay.logR, bestlay.logC, bestsc.E_row, bestsc.rows_per_wg, bestsc.iters,
+            bestsc.E_col, bestsc.tw, bestsc.xcd, best);
   return Status();
 }
 

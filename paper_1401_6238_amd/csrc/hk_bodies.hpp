@@ -389,6 +389,63 @@ struct RowBody {
     return part;
   }
 
+  // Pass B, forward program, over K rows row0, row0 + rstride, ... handled in
+  // turn by this lane group: while a row's last operand is transformed, the
+  // first operand of the next row is already loading, so the memory traffic
+  // of one row overlaps the arithmetic of the previous one.  Returns the lane's
+  // share of the scalar product over its rows.
+  static __device__ __forceinline__ cx<T> run_fwd_rows(const Shape &sh, const PV &P, int64_t row0, int rstride,
+                                                       int K, int t, cx<T> *lds, const cx<T> *tw24,
+                                                       const cx<T> *tw4096) {
+    const int64_t C = (int64_t)1 << sh.logC;
+    const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
+    cx<T> a[EE], nx[EE], acc[EE], w[EE];
+    cx<T> part = czero<T>();
+    int64_t row = row0;
+    bool valid = row < C;
+    load(a, sh, P, 0, row, valid, t, false);
+    StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
+    for (int it = 0; it < K; ++it) {
+      const bool tw_on = twiddles(w, sh, row, t, false, tw24, tw4096);
+      const int64_t nrow = row + rstride;
+      const bool nvalid = (it + 1 < K) && nrow < C;
+#pragma unroll
+      for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
+      for (int o = 0; o < sh.nops; ++o) {
+        if (o + 1 < sh.nops)
+          load(nx, sh, P, o + 1, row, valid, t, false);
+        else if (it + 1 < K)
+          load(nx, sh, P, 0, nrow, nvalid, t, false);
+        twiddle_in(a, w, tw_on);
+        fft(a, t, lds, stw);
+        const OpDesc &od = sh.ops[o];
+        if (od.role == ROLE_H) {
+#pragma unroll
+          for (int s = 0; s < EE; ++s) acc[s] = cscale(cconj(a[s]), invN);
+        } else {
+          for (int e = 0; e < od.exp; ++e) {
+#pragma unroll
+            for (int s = 0; s < EE; ++s) acc[s] = cmul(acc[s], a[s]);
+          }
+          if (od.flags & OPF_ALPHA) {
+#pragma unroll
+            for (int s = 0; s < EE; ++s) part = cfma(acc[s], a[s], part);
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < EE; ++s) a[s] = nx[s];
+      }
+      if (sh.want_y) {
+        fft(acc, t, lds, stw);
+        store(acc, sh, P, 0, row, valid, t, false, w);
+      }
+      row = nrow;
+      valid = nvalid;
+    }
+    return part;
+  }
+
   // Adjoint of g = H x^{m-1}, f = H x^m (equal vectors).  Operands in order:
   // X, then optionally V (cotangent of g, conjugated on load), then H when
   // grad_x is requested.

@@ -56,7 +56,8 @@ struct Shape {
   int32_t want_alpha;  // scalar output (forward)
   int32_t want_out1;   // adjoint: grad_x
   int32_t real_out;    // store only the real part
-  int32_t rows_per_wg; // multipass row pass: rows per workgroup
+  int32_t rows_per_wg; // multipass row pass: rows per workgroup (side by side)
+  int32_t row_iters;   // multipass row pass: rows each lane group handles in turn
   int64_t out_rows;    // output slice: 1D length / BHHB rows n_1; adjoint grad_h length
   int64_t out_cols;    // BHHB columns N_1 (1 for 1D)
   int64_t out1_len;    // adjoint grad_x length

@@ -55,13 +55,17 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
   } else {
     const int64_t inst = blockIdx.y;
     const PV P{&p0, &str, inst, nullptr};
-    const int64_t row = (int64_t)blockIdx.x * rows + rw;
-    const bool valid = row < ((int64_t)1 << sh.logC);
+    // rows of this workgroup: (blockIdx.x * K + it) * rows + rw, it < K
+    const int K = sh.row_iters > 1 ? sh.row_iters : 1;
+    const int64_t row0 = (int64_t)blockIdx.x * K * rows + rw;
     if (PROG == PROG_BWD) {
-      RB::run_bwd(sh, P, row, valid, t, lds, false, g_tw24, g_tw4096);
+      for (int it = 0; it < K; ++it) {
+        const int64_t row = row0 + (int64_t)it * rows;
+        RB::run_bwd(sh, P, row, row < ((int64_t)1 << sh.logC), t, lds, false, g_tw24, g_tw4096);
+      }
       return;
     }
-    const cx<T> part = RB::run_fwd(sh, P, row, valid, t, lds, false, g_tw24, g_tw4096);
+    const cx<T> part = RB::run_fwd_rows(sh, P, row0, rows, K, t, lds, g_tw24, g_tw4096);
     if (sh.want_alpha) {
       // One partial sum per workgroup; the next kernel in the stream (pass D
       // or the reduction kernel) adds them in index order.  No cross-workgroup

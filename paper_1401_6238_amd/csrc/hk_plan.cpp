@@ -231,6 +231,7 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
     // The workspace size does not depend on the schedule: partial sums are
     // reserved for the largest possible number of row-pass workgroups.
     sh.rows_per_wg = sc.rows_per_wg;
+    sh.row_iters = sc.iters;
     sh.nbuf = sh.nops;
     sh.partials = (int64_t)1 << MAX_LOGL;
     const size_t eb = cplx_bytes(p.dt);
@@ -257,6 +258,7 @@ bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
   if (sc.rows_per_wg < 1 || sc.rows_per_wg * kr.tps > ROW_MAXT) return false;
   const size_t row_lds = std::max((size_t)sc.rows_per_wg * kr.seq_lds, (size_t)sc.rows_per_wg * kr.tps) * kr.elem_bytes;
   if (row_lds > 160 * 1024) return false;
+  if (sc.iters != 1 && (lay.resident || (sc.iters != 2 && sc.iters != 4))) return false;
   if (!lay.resident) {
     if (!lim(dt, lay.logC, sc.E_col, &kc)) return false;
     if (sc.tw < 1 || sc.tw * kc.tps > COL_MAXT) return false;
@@ -429,12 +431,13 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
   e = cols(dt, sh.logC, sc.E_col, sc.tw, sc.xcd, ga, sh, p0, str, ja, sh.nops, st);
   if (e != hipSuccess) return hip_fail(e, "pass A launch");
   // Pass B: row transforms, spectral product, row transform of the output.
-  dim3 gb((unsigned)((C + sc.rows_per_wg - 1) / sc.rows_per_wg), (unsigned)count);
+  const int64_t rows_wg = (int64_t)sc.rows_per_wg * sc.iters;  // rows per workgroup
+  dim3 gb((unsigned)((C + rows_wg - 1) / rows_wg), (unsigned)count);
   e = rows(dt, sh.logR, sc.E_row, sc.rows_per_wg, gb, sh, p0, str, count, st);
   if (e != hipSuccess) return hip_fail(e, "pass B launch");
   // Pass D: column transforms of the outputs and the slice; its first
   // workgroup also sums pass B's scalar partials.
-  const int64_t npart = (sh.prog == PROG_FWD && sh.want_alpha) ? (C + sc.rows_per_wg - 1) / sc.rows_per_wg : 0;
+  const int64_t npart = (sh.prog == PROG_FWD && sh.want_alpha) ? (C + rows_wg - 1) / rows_wg : 0;
   ColJob jd[2];
   memset(jd, 0, sizeof(jd));
   int nd = 0;
@@ -551,10 +554,10 @@ void sched_store(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint,
 }
 
 // Text database, one schedule per line:
-//   dtype prog is_block logN logC_hint batch_class : E_row rows_per_wg E_col tw split xcd
-// (xcd may be omitted: 0).  '#' starts a comment line.
+//   dtype prog is_block logN logC_hint batch_class : E_row rows_per_wg E_col tw split xcd iters
+// (xcd and iters may be omitted: 0 and 1).  '#' starts a comment line.
 static const char *kDbHeader =
-    "# hankel schedule database v2: dt prog blk logN logC bclass : E_row rows E_col tw split xcd\n";
+    "# hankel schedule database v3: dt prog blk logN logC bclass : E_row rows E_col tw split xcd iters\n";
 
 Status sched_save(const char *path) {
   if (!path) return fail(HK_ERR_NULL_POINTER, "path is NULL");
@@ -565,8 +568,9 @@ Status sched_save(const char *path) {
   for (const auto &kv : g_sched) {
     const SchedKey &k = kv.first;
     const Sched &s = kv.second;
-    fprintf(f, "%d %d %d %d %d %d : %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
-            std::get<3>(k), std::get<4>(k), std::get<5>(k), s.E_row, s.rows_per_wg, s.E_col, s.tw, s.split, s.xcd);
+    fprintf(f, "%d %d %d %d %d %d : %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+            std::get<3>(k), std::get<4>(k), std::get<5>(k), s.E_row, s.rows_per_wg, s.E_col, s.tw, s.split, s.xcd,
+            s.iters);
   }
   const bool ok = fclose(f) == 0;
   return ok ? Status() : fail(HK_ERR_INVALID_VALUE, std::string("error writing ") + path);
@@ -583,10 +587,10 @@ Status sched_load(const char *path, int *loaded) {
   while (fgets(line, sizeof(line), f)) {
     ++lineno;
     if (line[0] == '#' || line[0] == '\n') continue;
-    int k[6], v[6] = {0, 0, 0, 0, 0, 0};
-    const int got = sscanf(line, "%d %d %d %d %d %d : %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5],
-                           &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]);
-    if (got != 11 && got != 12) {
+    int k[6], v[7] = {0, 0, 0, 0, 0, 0, 1};
+    const int got = sscanf(line, "%d %d %d %d %d %d : %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4],
+                           &k[5], &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6]);
+    if (got < 11 || got > 13) {
       st = fail(HK_ERR_INVALID_VALUE, std::string(path) + ": malformed line " + std::to_string(lineno));
       break;
     }
@@ -600,10 +604,11 @@ Status sched_load(const char *path, int *loaded) {
     s.tw = v[3];
     s.split = v[4];
     s.xcd = v[5];
+    s.iters = v[6];
     // entries are re-checked against the kernel limits when used (sched_valid)
     const bool val_ok = (s.E_row == 8 || s.E_row == 16) && (s.E_col == 8 || s.E_col == 16) && s.rows_per_wg >= 1 &&
                         s.rows_per_wg <= 64 && s.tw >= 1 && s.tw <= 64 && s.split >= -4 && s.split <= 4 &&
-                        (s.xcd == 0 || s.xcd == 1);
+                        (s.xcd == 0 || s.xcd == 1) && (s.iters == 1 || s.iters == 2 || s.iters == 4);
     if (!key_ok || !val_ok) {
       st = fail(HK_ERR_INVALID_VALUE, std::string(path) + ": value out of range on line " + std::to_string(lineno));
       break;

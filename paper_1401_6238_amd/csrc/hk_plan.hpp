@@ -53,6 +53,8 @@ struct Sched {
   int tw = 8;
   int split = 0;  // multipass: logR - ceil(logN / 2) adjustment
   int xcd = 0;    // column passes: XCD-local tile numbering (1) or identity (0)
+  int iters = 1;  // row pass: rows a workgroup's lane group transforms in turn, the
+                  // next row's operands loading while the current one is transformed
 };
 
 struct Layout {

@@ -150,8 +150,16 @@ def test_tune_db_round_trip(L, tmp_path):
     out = tmp_path / "out.txt"
     assert L.hk_tune_save(str(out).encode()) == OK
     lines = [ln for ln in out.read_text().splitlines() if not ln.startswith("#")]
-    assert "1 1 0 23 -1 2 : 16 2 8 4 -1 1" in lines
-    assert "0 0 0 23 -1 0 : 8 1 16 8 0 0" in lines
+    assert "1 1 0 23 -1 2 : 16 2 8 4 -1 1 1" in lines
+    assert "0 0 0 23 -1 0 : 8 1 16 8 0 0 1" in lines
+    seven = tmp_path / "seven.txt"
+    seven.write_text("0 0 0 22 -1 0 : 8 2 16 8 0 1 4\n")
+    assert L.hk_tune_load(str(seven).encode(), None) == OK
+    assert L.hk_tune_save(str(out).encode()) == OK
+    assert "0 0 0 22 -1 0 : 8 2 16 8 0 1 4" in out.read_text()
+    three = tmp_path / "three.txt"
+    three.write_text("0 0 0 20 -1 0 : 8 1 16 8 0 0 3\n")  # 3 rows in turn is not offered
+    assert L.hk_tune_load(str(three).encode(), None) == INVALID
     bad = tmp_path / "bad.txt"
     bad.write_text("0 0 0 20 -1 0 : 8 1 16 8\n")
     assert L.hk_tune_load(str(bad).encode(), None) == INVALID

@@ -1,6 +1,7 @@
 """Every schedule gives the same products: the plain 3-pass path, the BHHB
 path and the adjoint are run under a sweep of schedules (row/column split,
-elements per lane, rows per workgroup, column-tile width, XCD tile numbering)
+elements per lane, rows per workgroup, rows in turn, column-tile width, XCD
+tile numbering)
 installed through the schedule database, and each result is compared with
 the CPU oracle."""
 import itertools
@@ -21,17 +22,17 @@ DT_CODE = {torch.complex64: 0, torch.complex128: 1}
 
 
 def sweep():
-    combos = list(itertools.product([8, 16], [1, 2], [8, 16], [1, 4, 16], [-1, 0, 1], [0, 1]))
+    combos = list(itertools.product([8, 16], [1, 2], [8, 16], [1, 4, 16], [-1, 0, 1], [0, 1], [1, 2, 4]))
     g = np.random.Generator(np.random.PCG64(77))
-    idx = g.choice(len(combos), 20, replace=False)
-    return [combos[i] for i in sorted(idx)] + [(8, 1, 8, 8, 0, 0), (8, 1, 16, 16, 1, 1)]
+    idx = g.choice(len(combos), 24, replace=False)
+    return [combos[i] for i in sorted(idx)] + [(8, 1, 8, 8, 0, 0, 1), (8, 1, 16, 16, 1, 1, 2), (8, 2, 8, 4, 0, 1, 4)]
 
 
 def install(tmp_path, key, sched):
     import paper_1401_6238_amd as hk
-    er, rows, ec, tw, split, xcd = sched
+    er, rows, ec, tw, split, xcd, iters = sched
     path = tmp_path / "db.txt"
-    path.write_text(" ".join(map(str, key)) + f" : {er} {rows} {ec} {tw} {split} {xcd}\n")
+    path.write_text(" ".join(map(str, key)) + f" : {er} {rows} {ec} {tw} {split} {xcd} {iters}\n")
     assert hk.hk_tune_load(str(path)) == 1
 
 
