@@ -592,6 +592,25 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
     ex["adjoint_batch"] = res4
     log("adjoint batch", res4)
 
+    # Hankel tensor-matrix product (Section 4.2, the HOOI kernel): m=3, n=2^16, R=8, c64
+    g = np.random.Generator(np.random.PCG64(14016238 + 6000))
+    nt, Rt, mt = 1 << 16, 8, 3
+    ht = torch.from_numpy(wl.cn(g, mt * (nt - 1) + 1, 1.0)).to(torch.complex64).to(dev)
+    Ut = torch.from_numpy(wl.cn(g, nt * Rt, 1.0 / nt).reshape(nt, Rt)).to(torch.complex64).to(dev)
+    ms_tm = time_region(torch, lambda: hk.hankel_tensor_matrix(ht, Ut, mt), 3)
+
+    def plain_tm():
+        for j2 in range(Rt):
+            for j3 in range(Rt):
+                hk.hankel_mode_products(ht, [None, Ut[:, j2].contiguous(), Ut[:, j3].contiguous()], [nt] * mt, True,
+                                        False)
+    ms_tmp = time_region(torch, plain_tm, 1, warm=1)
+    ncol = Rt ** (mt - 1)
+    ex["tensor_matrix_c64"] = {"shape": f"m={mt} n={nt} R={Rt}", "columns_per_s": round(ncol / ms_tm * 1000, 1),
+                               "ms": round(ms_tm, 3), "plain_loop_columns_per_s": round(ncol / ms_tmp * 1000, 1)}
+    log("tensor matrix", ex["tensor_matrix_c64"])
+    del ht, Ut
+
     # block batch: 64 BHHB tensors, m=3, 512 blocks of 512, 2048^2 grid, c64
     blk = data["block"]
     Hs = torch.stack([torch.from_numpy(p.h) for p in blk]).to(torch.complex64).to(dev)

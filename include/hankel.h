@@ -150,7 +150,7 @@ typedef struct {
 
 typedef struct hk_plan_s *hk_plan_t;
 
-#define HK_PLAN_PERSISTENT 0x1u /* one persistent launch with an in-kernel task queue          */
+#define HK_PLAN_PERSISTENT 0x1u /* one persistent launch: task queues and grid-wide barriers   */
 #define HK_PLAN_MULTIKERNEL 0x2u /* grouped launches: per phase, one kernel specialised for each
                                    (task kind, transform length) group; no in-kernel waits      */
 #define HK_PLAN_GRAPH 0x4u      /* capture the plan's launches in a hipGraph on first execute */
@@ -161,8 +161,8 @@ typedef struct hk_plan_s *hk_plan_t;
  * that it owns until hk_plan_destroy.  With HK_PLAN_GRAPH it also owns a
  * captured graph.  flags without PERSISTENT pick the grouped launches (the
  * faster schedule on MI355X); PERSISTENT runs the whole batch in one launch
- * whose workgroups pull tasks from a queue and wait (bounded) on per-instance
- * completion counters. */
+ * whose resident workgroups pull each phase's tasks from a queue and meet in
+ * a grid-wide barrier (bounded wait) between phases. */
 hk_status_t hk_plan_create(hk_plan_t *plan, hk_dtype_t dt, const hk_problem_t *probs,
                            int64_t count, unsigned flags);
 hk_status_t hk_plan_workspace_size(hk_plan_t plan, size_t *bytes);
@@ -170,9 +170,17 @@ hk_status_t hk_plan_workspace_size(hk_plan_t plan, size_t *bytes);
  * on `stream` has finished. */
 hk_status_t hk_plan_execute(hk_plan_t plan, void *ws, size_t ws_bytes, hipStream_t stream);
 /* Synchronizes the last execute's stream and returns HK_SUCCESS or
- * HK_ERR_DEVICE_FAULT if the persistent kernel flagged an error (a
- * dependency wait that exceeded its spin bound). */
+ * HK_ERR_DEVICE_FAULT if the persistent kernel flagged an error (a barrier
+ * wait that exceeded its bound: the device could not hold the whole grid at
+ * once, for example while other work occupied it; results are then
+ * unspecified). */
 hk_status_t hk_plan_status(hk_plan_t plan);
+/* Diagnostics: the number of polling iterations (each a short sleep) a
+ * persistent-plan workgroup waits at a grid barrier before it sets the error
+ * word and continues (default 2^22, a fraction of a second).  A tiny bound
+ * exercises the error path of hk_plan_status without any fault.  Not allowed
+ * once the plan is captured in a graph. */
+hk_status_t hk_plan_set_wait_bound(hk_plan_t plan, uint32_t spins);
 hk_status_t hk_plan_destroy(hk_plan_t plan);
 
 /* One-shot convenience: plan (grouped launches), execute with the descriptor
@@ -182,6 +190,23 @@ hk_status_t hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t 
                                               int64_t count, size_t *bytes);
 hk_status_t hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t count,
                                void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* -------------------------------------------------------------------------
+ * Hankel tensor-matrix product (Section 4.2): for the square order-m Hankel
+ * tensor H (generating vector h, m(n-1)+1 elements) and an n x R matrix U
+ * (column-major, device), T = H x_2 U x_3 U ... x_m U with the Section 2.1
+ * mode product, i.e. column (j_2, ..., j_m) of T is the tensor-vector product
+ * H x_2 U[:, j_2] ... x_m U[:, j_m].  out is n x R^(m-1), column-major, column
+ * index j_2 + R j_3 + ... + R^(m-2) j_m.  The columns are symmetric in the j's:
+ * the library computes the nondecreasing tuples (a grouped batch of mode
+ * products) and copies the rest.  R^(m-1) <= 2^20.  The call enqueues its
+ * work on `stream` and waits for it (its descriptor tables live on the host
+ * until then).  Used by HOOI (Algorithm 4.2) for the Hankel tensor-matrix
+ * products that dominate it.
+ * ------------------------------------------------------------------------- */
+hk_status_t hankel_tensor_matrix_workspace_size(hk_dtype_t dt, int m, int64_t n, int64_t R, size_t *bytes);
+hk_status_t hankel_tensor_matrix(hk_dtype_t dt, const void *h, int m, int64_t n, int64_t R, const void *U,
+                                 void *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* -------------------------------------------------------------------------
  * Adjoint of the equal-vector products g = H x^{m-1} (n values) and

@@ -223,6 +223,32 @@ def tvp_backward(m: int, h, x, v=None, phi=None, want_grad_x: bool = True, want_
     return gx, gh
 
 
+def tensor_matrix(m: int, h, U) -> np.ndarray:
+    """Hankel tensor-matrix product T = H x_2 U x_3 U ... x_m U (Section 4.2) of the
+    square order-m Hankel tensor (generating vector h, size n per mode) with the
+    n x R matrix U in every mode but the first, with the Section 2.1 mode product
+    (sum over i_p of H[.., i_p, ..] U[i_p, j_p]).
+
+    Column (j_2, ..., j_m) of T is the tensor-vector product H x_2 U[:, j_2] ...
+    x_m U[:, j_m] (the relation Section 4.2 states), evaluated by the direct oracle.
+    Returns T as an n x R^(m-1) array whose column index is
+    j_2 + R j_3 + ... + R^(m-2) j_m."""
+    U = np.asarray(U, np.complex128)
+    n, R = U.shape
+    h = _c128(h)
+    if len(h) != m * (n - 1) + 1:
+        raise ValueError("h must have m(n-1)+1 entries")
+    out = np.empty((n, R ** (m - 1)), np.complex128)
+    for j in range(R ** (m - 1)):
+        cols, r = [], j
+        for _ in range(m - 1):
+            cols.append(r % R)
+            r //= R
+        vecs = [None] + [U[:, c] for c in cols]
+        out[:, j], _ = tvp(m, [n] * m, h, vecs)
+    return out
+
+
 def problem_tvp(prob, want_y: Optional[bool] = None, want_alpha: Optional[bool] = None):
     """Oracle result for a ``workloads.Problem``."""
     wy = prob.want_y if want_y is None else want_y

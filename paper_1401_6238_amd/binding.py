@@ -272,6 +272,10 @@ class Plan:
     def status(self):
         check(lib().hk_plan_status(self._plan), "hk_plan_status")
 
+    def set_wait_bound(self, spins: int):
+        """Persistent plans: barrier polling iterations before the error path (diagnostics)."""
+        check(lib().hk_plan_set_wait_bound(self._plan, int(spins)), "hk_plan_set_wait_bound")
+
     def close(self):
         if self._plan:
             lib().hk_plan_destroy(self._plan)
@@ -282,6 +286,27 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def hankel_tensor_matrix(h: torch.Tensor, U: torch.Tensor, m: int) -> torch.Tensor:
+    """T = H x_2 U ... x_m U for the square order-m Hankel tensor with generating
+    vector h and an (n, R) matrix U.  Returns T with shape (n, R, ..., R),
+    T[i, j_2, ..., j_m] = (H x_2 U[:, j_2] ... x_m U[:, j_m])[i]."""
+    _dev(h), _dev(U)
+    n, R = U.shape
+    dt = _dtype(h)
+    Ucm = U.t().contiguous()  # column-major n x R: column j contiguous
+    ncols = R ** (m - 1)
+    out = torch.empty((ncols, n), dtype=h.dtype, device=h.device)  # column-major n x R^(m-1)
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_tensor_matrix_workspace_size(dt, m, n, R, ctypes.byref(nb)),
+          "hankel_tensor_matrix_workspace_size")
+    ws, wsb = _workspace(nb.value, h.device)
+    check(lib().hankel_tensor_matrix(dt, _ptr(h), m, n, R, _ptr(Ucm), _ptr(out), _ptr(ws), wsb, _stream(h.device)),
+          "hankel_tensor_matrix")
+    # out rows are columns j = j_2 + R j_3 + ...: as a row-major array its axes are (j_m, ..., j_2, i)
+    T = out.reshape([R] * (m - 1) + [n])
+    return T.permute([m - 1] + list(range(m - 2, -1, -1)))
 
 
 def hankel_tvp_batched(problems):

@@ -414,6 +414,8 @@ hk_status_t hk_plan_status(hk_plan_t plan) { return finish(plan_status(plan)); }
 
 hk_status_t hk_plan_destroy(hk_plan_t plan) { return finish(plan_destroy(plan)); }
 
+hk_status_t hk_plan_set_wait_bound(hk_plan_t plan, uint32_t spins) { return finish(plan_set_wait_bound(plan, spins)); }
+
 hk_status_t hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs, int64_t count, size_t *bytes) {
   if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
   hk_plan_t plan = nullptr;
@@ -435,6 +437,121 @@ hk_status_t hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t
     s = plan_release_after(plan, stream);
   else
     plan_destroy(plan);
+  return finish(s);
+}
+
+// ---------------------------------------------------------------------------
+// Hankel tensor-matrix product T = H x_2 U ... x_m U (square H, the same U in
+// modes 2..m).  Column (j_2, ..., j_m) of T is the mode product with the
+// columns U[:, j_2], ..., U[:, j_m]; it is symmetric in the j's, so only the
+// nondecreasing tuples are computed (one grouped batch of mode products) and
+// the other columns are copies.
+// ---------------------------------------------------------------------------
+struct TmLayout {
+  std::vector<hk_problem_t> probs;      // one per nondecreasing tuple
+  std::vector<int32_t> pairs;           // (dst column, src column) for the others
+};
+
+static Status tm_layout(hk_dtype_t dt, const void *h, int m, int64_t n, int64_t R, const void *U, void *out,
+                        TmLayout *L) {
+  if (m < 2 || m > HK_MAX_ORDER) return fail(HK_ERR_INVALID_VALUE, "order m must be in [2, 8]");
+  if (n < 1 || R < 1) return fail(HK_ERR_INVALID_VALUE, "n and R must be >= 1");
+  int64_t ncols = 1;
+  for (int p = 1; p < m; ++p) {
+    ncols *= R;
+    if (ncols > (1 << 20)) return fail(HK_ERR_SIZE_LIMIT, "R^(m-1) exceeds 2^20 columns");
+  }
+  if (!h || !U || !out) return fail(HK_ERR_NULL_POINTER, "h, U or out is NULL");
+  if (dt < HK_C64 || dt > HK_F64) return fail(HK_ERR_INVALID_VALUE, "unknown dtype");
+  const size_t eb = elem_bytes(dt);
+  std::vector<int64_t> canon_of(ncols, -1);
+  std::vector<int> j(m - 1);
+  for (int64_t c = 0; c < ncols; ++c) {
+    int64_t r = c;
+    for (int p = 0; p < m - 1; ++p) {
+      j[p] = (int)(r % R);
+      r /= R;
+    }
+    std::vector<int> s = j;
+    std::sort(s.begin(), s.end());
+    int64_t cc = 0;
+    for (int p = m - 2; p >= 0; --p) cc = cc * R + s[p];
+    canon_of[c] = cc;
+    if (cc == c) {
+      hk_problem_t q;
+      memset(&q, 0, sizeof(q));
+      q.m = m;
+      for (int p = 0; p < m; ++p) q.dims[p] = n;
+      q.h = h;
+      for (int p = 1; p < m; ++p) q.vectors[p] = (const char *)U + (size_t)j[p - 1] * n * eb;
+      q.y = (char *)out + (size_t)c * n * eb;
+      L->probs.push_back(q);
+    }
+  }
+  for (int64_t c = 0; c < ncols; ++c)
+    if (canon_of[c] != c) {
+      L->pairs.push_back((int32_t)c);
+      L->pairs.push_back((int32_t)canon_of[c]);
+    }
+  if (L->pairs.size() / 2 > 65535) return fail(HK_ERR_SIZE_LIMIT, "too many symmetric columns");
+  return Status();
+}
+
+hk_status_t hankel_tensor_matrix_workspace_size(hk_dtype_t dt, int m, int64_t n, int64_t R, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  TmLayout L;
+  const void *dummy = (const void *)256;
+  Status s = tm_layout(dt, dummy, m, n, R, dummy, (void *)256, &L);
+  if (!s.ok()) return finish(s);
+  hk_plan_t plan = nullptr;
+  s = plan_create(&plan, dt, L.probs.data(), (int64_t)L.probs.size(), 0);
+  if (!s.ok()) return finish(s);
+  size_t pb = 0;
+  s = plan_ws_size(plan, &pb);
+  plan_destroy(plan);
+  if (!s.ok()) return finish(s);
+  *bytes = ((pb + 255) & ~(size_t)255) + L.pairs.size() * sizeof(int32_t) + 256;
+  return finish(Status());
+}
+
+hk_status_t hankel_tensor_matrix(hk_dtype_t dt, const void *h, int m, int64_t n, int64_t R, const void *U,
+                                 void *out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  TmLayout L;
+  Status s = tm_layout(dt, h, m, n, R, U, out, &L);
+  if (!s.ok()) return finish(s);
+  hk_plan_t plan = nullptr;
+  s = plan_create(&plan, dt, L.probs.data(), (int64_t)L.probs.size(), 0);
+  if (!s.ok()) return finish(s);
+  size_t pb = 0;
+  plan_ws_size(plan, &pb);
+  const size_t pairs_off = (pb + 255) & ~(size_t)255;
+  const size_t need = pairs_off + L.pairs.size() * sizeof(int32_t) + 256;
+  if (!ws || ws_bytes < need) {
+    plan_destroy(plan);
+    return finish(fail(HK_ERR_WORKSPACE, "workspace smaller than hankel_tensor_matrix_workspace_size"));
+  }
+  plan_set_oneshot(plan);
+  s = plan_execute(plan, ws, ws_bytes, stream);
+  if (s.ok() && !L.pairs.empty()) {
+    int32_t *dpairs = (int32_t *)((char *)ws + pairs_off);
+    hipError_t e = hipMemcpyAsync(dpairs, L.pairs.data(), L.pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  stream);
+    const bool cplx = is_complex(dt);
+    const bool dbl = dt == HK_C128 || dt == HK_F64;
+    if (e == hipSuccess) {
+      count_launch();
+      e = dbl ? launch_copy_cols_f64(out, dpairs, (int)(L.pairs.size() / 2), n, cplx, stream)
+              : launch_copy_cols_f32(out, dpairs, (int)(L.pairs.size() / 2), n, cplx, stream);
+    }
+    if (e != hipSuccess) s = fail(HK_ERR_HIP, std::string("symmetric completion: ") + hipGetErrorString(e));
+  }
+  // the host tables (plan and pairs) must outlive the copies enqueued above
+  if (s.ok())
+    s = plan_release_after(plan, stream);
+  else {
+    (void)hipStreamSynchronize(stream);
+    plan_destroy(plan);
+  }
   return finish(s);
 }
 

@@ -33,7 +33,7 @@ struct hk_plan_s {
   std::vector<hk::Task> tasks;
   std::vector<int32_t> res_list;
   int32_t phase_end[3] = {0, 0, 0};  // [0, e0): pass A + resident, [e0, e1): pass B, [e1, e2): pass D
-  size_t ctl_bytes = 0;              // BatchCtl + InstCtl[count]
+  size_t ctl_bytes = 0;              // BatchCtl
   size_t tables_bytes = 0;           // descriptor tables (when stored in the workspace)
   size_t inst_bytes = 0;             // instance regions
   bool tables_in_ws = false;
@@ -51,6 +51,7 @@ struct hk_plan_s {
   std::vector<char> host_tables;
   int grid = 1;
   bool persistent = true;
+  uint32_t wait_bound = 1u << 22;  // barrier polling iterations before the error path
   // graph
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -178,7 +179,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
   };
   p->shapes.resize(count);
   p->ptrs.resize(count);
-  p->ctl_bytes = align256(sizeof(BatchCtl)) + align256(sizeof(InstCtl) * (size_t)std::max<int64_t>(count, 1));
+  p->ctl_bytes = align256(sizeof(BatchCtl));
   size_t inst_off = 0;
   struct Inst {
     int64_t idx;
@@ -214,15 +215,14 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
   p->inst_bytes = inst_off;
   std::sort(multi.begin(), multi.end(), [](const Inst &a, const Inst &b) { return a.cost > b.cost; });
   // Phase 1a: pass A of the multipass instances (largest first).
-  std::vector<int32_t> ncola(count, 0), nrowb(count, 0);
+  std::vector<int32_t> nrowb(count, 0);
   for (const Inst &in : multi) {
     const Shape &sh = p->shapes[in.idx];
     const int tw = std::max(1, blk / tps(sh.logC, ec));
     for (int o = 0; o < sh.nops; ++o)
       for (int64_t c0 = 0; c0 < sh.ops[o].ncol_nz; c0 += tw) {
-        Task t = {TASK_COLA, (int32_t)in.idx, o, (int32_t)c0, 0, -1, 0, 0};
+        Task t = {TASK_COLA, (int32_t)in.idx, o, (int32_t)c0, 0};
         p->tasks.push_back(t);
-        ncola[in.idx]++;
       }
   }
   // Phase 1b: resident instances, grouped so that a workgroup's rows share
@@ -235,7 +235,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
     const int rows = std::max(1, blk / tps(sh0.logR, er));
     for (size_t k = 0; k < g.second->size(); k += rows) {
       const int n = (int)std::min<size_t>(rows, g.second->size() - k);
-      Task t = {TASK_RES, (int32_t)p->res_list.size(), n, 0, 0, -1, -1, 0};
+      Task t = {TASK_RES, (int32_t)p->res_list.size(), n, 0, 0};
       for (int j = 0; j < n; ++j) p->res_list.push_back((*g.second)[k + j]);
       p->tasks.push_back(t);
     }
@@ -248,7 +248,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
     const int64_t C = (int64_t)1 << sh.logC;
     const int32_t nb = (int32_t)((C + rows - 1) / rows);
     for (int32_t b = 0; b < nb; ++b) {
-      Task t = {TASK_ROWB, (int32_t)in.idx, (int32_t)(b * rows), b, ncola[in.idx], 0, 1, nb};
+      Task t = {TASK_ROWB, (int32_t)in.idx, (int32_t)(b * rows), b, nb};
       p->tasks.push_back(t);
     }
     nrowb[in.idx] = nb;
@@ -258,7 +258,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
   for (const Inst &in : multi) {
     const Shape &sh = p->shapes[in.idx];
     if (!sh.want_alpha) continue;
-    Task t = {TASK_ALPHA, (int32_t)in.idx, 0, 0, nrowb[in.idx], 1, -1, nrowb[in.idx]};
+    Task t = {TASK_ALPHA, (int32_t)in.idx, 0, 0, nrowb[in.idx]};
     p->tasks.push_back(t);
   }
   for (const Inst &in : multi) {
@@ -267,7 +267,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
     const int tw = std::max(1, blk / tps(sh.logC, ec));
     const int64_t ncols = std::min<int64_t>((int64_t)1 << sh.logR, sh.out_rows);
     for (int64_t c0 = 0; c0 < ncols; c0 += tw) {
-      Task t = {TASK_COLD, (int32_t)in.idx, 0, (int32_t)c0, nrowb[in.idx], 1, -1, 0};
+      Task t = {TASK_COLD, (int32_t)in.idx, 0, (int32_t)c0, 0};
       p->tasks.push_back(t);
     }
   }
@@ -278,8 +278,14 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     ncu = prop.multiProcessorCount;
-  const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
-  p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * std::min(per_cu, 2), p->tasks.size()));
+  // The persistent kernel's phases end in grid-wide barriers, so every one of
+  // its workgroups must be resident at once: the grid is what the occupancy
+  // of the kernel allows on this device (and no more than the largest phase).
+  int per_cu = 1;
+  if ((dbl(dt) ? batch_resident_f64(&per_cu) : batch_resident_f32(&per_cu)) != hipSuccess || per_cu < 1) per_cu = 1;
+  int64_t widest = 1;
+  for (int ph = 0, b = 0; ph < 3; b = p->phase_end[ph++]) widest = std::max<int64_t>(widest, p->phase_end[ph] - b);
+  p->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * per_cu, widest));
   *out = p;
   return Status();
 }
@@ -312,29 +318,20 @@ static Status enqueue(hk_plan_s *p, char *ws, hipStream_t st) {
   A.res_list = (const int32_t *)(tables + p->off_res);
   A.order = (const int32_t *)(tables + p->off_order);
   A.bctl = (BatchCtl *)ws;
-  A.ictl = (InstCtl *)(ws + align256(sizeof(BatchCtl)));
   A.ws_base = ws + p->ctl_bytes + p->tables_bytes;
-  A.spin_limit = 1u << 22;
-  auto launch = [&](const BatchArgs &a, int grid, bool reset) {
-    count_launch();
-    prof_before(st);
-    const hipError_t e = dbl(p->dt) ? launch_batch_f64(a, grid, p->count, reset, st)
-                                    : launch_batch_f32(a, grid, p->count, reset, st);
-    prof_after(PK_BATCH, st);
-    return e;
-  };
+  A.spin_limit = p->wait_bound;
+  for (int ph = 0; ph < 3; ++ph) A.phase_end[ph] = p->phase_end[ph];
   if (p->tasks.empty()) return Status();
   hipError_t e;
   if (p->persistent) {
-    A.begin = 0;
-    A.end = p->phase_end[2];
-    A.use_queue = 1;
-    e = launch(A, p->grid, true);
+    count_launch();
+    prof_before(st);
+    e = dbl(p->dt) ? launch_batch_f64(A, p->grid, st) : launch_batch_f32(A, p->grid, st);
+    prof_after(PK_BATCH, st);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
   } else {
     // one specialised launch per (phase, kind, length) group; the stream
     // orders the phases
-    A.use_queue = 0;
     for (const auto &g : p->launches) {
       A.begin = g.begin;
       A.end = g.begin + g.count;
@@ -417,7 +414,14 @@ Status plan_status(hk_plan_t p) {
   BatchCtl c;
   e = hipMemcpy(&c, p->last_ws, sizeof(c), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "status readback");
-  if (c.error) return fail(HK_ERR_DEVICE_FAULT, "a dependency wait of the persistent kernel exceeded its bound");
+  if (c.error) return fail(HK_ERR_DEVICE_FAULT, "a grid barrier wait of the persistent kernel exceeded its bound");
+  return Status();
+}
+
+Status plan_set_wait_bound(hk_plan_t p, uint32_t spins) {
+  if (!p) return fail(HK_ERR_NULL_POINTER, "plan is NULL");
+  if (p->gexec) return fail(HK_ERR_INVALID_VALUE, "the plan's launches are already captured in a graph");
+  p->wait_bound = spins;
   return Status();
 }
 

@@ -99,21 +99,15 @@ struct Task {
   int32_t inst;          // instance index (RES: first entry in the resident list)
   int32_t a;             // RES: number of instances; COLA: operand; COLD: output; ROWB: first row
   int32_t b;             // COLA/COLD: first column; ROWB: task index within the instance
-  int32_t wait;          // completions of phase `wait_phase` of `inst` required first
-  int32_t wait_phase;    // 0: pass A counter, 1: pass B counter, -1: no wait
-  int32_t signal_phase;  // counter to bump on completion (-1: none)
   int32_t nrowb;         // ROWB / ALPHA: number of row tasks of the instance (scalar partials)
 };
 
-struct InstCtl {  // per-instance counters (persistent schedule), zeroed before each run
-  uint32_t done[2];      // completed pass-A / pass-B tasks
-  uint32_t pad[2];
-};
-
+// Control block of the persistent schedule, zeroed before each run.
 struct BatchCtl {
-  uint32_t next;   // task queue head
-  uint32_t error;  // nonzero: a dependency wait exceeded its bound
-  uint32_t pad[2];
+  uint32_t next[3];    // task queue head of each phase
+  uint32_t arrive[3];  // workgroups that finished each phase (grid barrier)
+  uint32_t error;      // nonzero: a barrier wait exceeded its bound
+  uint32_t pad;
 };
 
 // Arguments of the batched (task-list) kernel.  Ptrs.ws of each instance is
@@ -123,13 +117,12 @@ struct BatchArgs {
   const Shape *shapes;
   const Ptrs *ptrs;
   const int32_t *res_list;
-  InstCtl *ictl;
   BatchCtl *bctl;
   char *ws_base;
-  int32_t begin, end;   // task range of this launch
-  int32_t use_queue;    // 1: persistent workgroups pull tasks and honour dependencies
-  uint32_t spin_limit;  // bound on dependency polling iterations
-  const int32_t *order; // grouped launches: task indices sorted by (phase, kind, length)
+  int32_t begin, end;      // grouped launches: range of `order` of this launch
+  int32_t phase_end[3];    // persistent: tasks [phase_end[p-1], phase_end[p]) form phase p
+  uint32_t spin_limit;     // bound on barrier polling iterations
+  const int32_t *order;    // grouped launches: task indices sorted by (phase, kind, length)
 };
 
 // Grouped launches: one specialised kernel per (task kind, transform length).

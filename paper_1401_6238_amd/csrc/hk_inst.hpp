@@ -286,27 +286,50 @@ hipError_t HK_CAT(launch_group_, HK_SUFFIX)(const BatchArgs &args, int kind, int
   return launch_kernel(fn, dim3((unsigned)ntasks), dim3(BATCH_BLK), kargs, lds, st);
 }
 
-hipError_t HK_CAT(launch_batch_, HK_SUFFIX)(const BatchArgs &args, int grid, int64_t ninst, bool reset,
-                                            hipStream_t st) {
+hipError_t HK_CAT(batch_resident_, HK_SUFFIX)(int *blocks_per_cu) {
   using namespace HK_NS;
-  if (reset) {
-    BatchCtl *b = args.bctl;
-    InstCtl *ic = args.ictl;
-    int64_t n = ninst;
-    void *rargs[] = {&b, &ic, &n};
-    const int64_t blocks = (ninst + 255) / 256 + 1;
-    // not profiled: the event pair belongs to the batch kernel below
-    hipError_t e = hipLaunchKernel((void *)&k_batch_reset, dim3((unsigned)blocks), dim3(256), rargs, 0, st);
-    if (e != hipSuccess) return e;
-  }
   int blk, er, ec;
   size_t lds;
   HK_CAT(batch_geometry_, HK_SUFFIX)(&blk, &er, &ec, &lds);
   hipError_t e = ensure_lds((void *)&k_batch, lds);
   if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)&k_batch, blk, lds);
+}
+
+hipError_t HK_CAT(launch_batch_, HK_SUFFIX)(const BatchArgs &args, int grid, hipStream_t st) {
+  using namespace HK_NS;
+  // zero the control block with a kernel (not a memset node), so that graph
+  // replays start from a clean queue
+  BatchCtl *b = args.bctl;
+  void *rargs[] = {&b};
+  // not profiled: the event pair belongs to the batch kernel below
+  hipError_t e = hipLaunchKernel((void *)&k_batch_reset, dim3(1), dim3(64), rargs, 0, st);
+  if (e != hipSuccess) return e;
+  int blk, er, ec;
+  size_t lds;
+  HK_CAT(batch_geometry_, HK_SUFFIX)(&blk, &er, &ec, &lds);
+  e = ensure_lds((void *)&k_batch, lds);
+  if (e != hipSuccess) return e;
   BatchArgs a = args;
   void *kargs[] = {&a};
   return launch_kernel((void *)&k_batch, dim3((unsigned)grid), dim3(blk), kargs, lds, st);
+}
+
+hipError_t HK_CAT(launch_copy_cols_, HK_SUFFIX)(void *out, const int32_t *pairs, int npairs, int64_t rows,
+                                                bool complex_elems, hipStream_t st) {
+  using namespace HK_NS;
+  if (npairs <= 0) return hipSuccess;
+  if (npairs > 65535) return hipErrorInvalidValue;
+  const unsigned gx = (unsigned)std::min<int64_t>(64, (rows + 255) / 256);
+  int64_t r = rows;
+  if (complex_elems) {
+    cx<T> *o = (cx<T> *)out;
+    void *args[] = {&o, &pairs, &r};
+    return launch_kernel((void *)&k_copy_cols<cx<T>>, dim3(gx, (unsigned)npairs), dim3(256), args, 0, st);
+  }
+  T *o = (T *)out;
+  void *args[] = {&o, &pairs, &r};
+  return launch_kernel((void *)&k_copy_cols<T>, dim3(gx, (unsigned)npairs), dim3(256), args, 0, st);
 }
 
 }  // namespace hk

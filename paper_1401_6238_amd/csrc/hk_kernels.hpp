@@ -143,14 +143,17 @@ namespace hk {
 namespace HK_NS {
 
 // ---------------------------------------------------------------------------
-// Batched task-list kernel.  With use_queue = 1 it is a persistent kernel:
-// each workgroup pulls task indices from a global counter, waits (bounded)
-// until the instance phase it depends on is complete, runs the task and
-// publishes its completion.  Tasks only depend on tasks with smaller
-// indices, and a task index is only handed to a running workgroup, so the
-// oldest unfinished task never waits: the schedule cannot deadlock, whatever
-// the number of resident workgroups.  With use_queue = 0 the same kernel
-// runs one task per workgroup (one launch per phase).
+// Batched task lists.  A plan's tasks form three phases: pass A column tiles
+// and resident instances; pass B row blocks; scalar sums and pass D column
+// tiles.  Tasks of one phase are independent; a phase reads only what
+// earlier phases wrote.  Two schedules run them:
+//  * grouped launches (k_group): per phase, one kernel per (kind, length);
+//    the stream orders the phases;
+//  * one persistent launch (k_batch): resident workgroups pull the tasks of a
+//    phase from a queue and meet in a grid-wide barrier before the next
+//    phase.  The grid never exceeds the workgroups the device can hold at
+//    once, and every barrier wait is bounded: past the bound the error word
+//    is set and the kernel still runs to its end.
 // ---------------------------------------------------------------------------
 enum : int { BATCH_BLK = 512, BATCH_E_ROW = 8, BATCH_E_COL = sizeof(T) == 4 ? 16 : 8 };
 
@@ -241,61 +244,64 @@ __device__ __noinline__ void batch_col(const Task &tk, const Shape &sh, const PV
     default: break;                               \
   }
 
+__device__ __forceinline__ void batch_task(const BatchArgs &A, const Task &tk, cx<T> *smem, int tid) {
+  if (tk.type == TASK_RES) {
+    const Shape &sh0 = A.shapes[A.res_list[tk.inst]];
+    HK_LSWITCH(sh0.logR, batch_res, A, tk, smem, tid)
+  } else {
+    const Shape &sh = A.shapes[tk.inst];
+    const PV P{&A.ptrs[tk.inst], nullptr, 0, A.ws_base};
+    if (tk.type == TASK_ROWB) {
+      HK_LSWITCH(sh.logR, batch_rowb, A, tk, sh, P, smem, tid)
+    } else if (tk.type == TASK_ALPHA) {
+      reduce_partials(sh, P, tk.nrowb, smem);
+    } else {
+      HK_LSWITCH(sh.logC, batch_col, tk, sh, P, smem, tid)
+    }
+  }
+}
+
+// Grid-wide barrier after phase ph: release this workgroup's stores, count
+// the arrival, wait (bounded) for all gridDim.x workgroups, acquire.
+__device__ __forceinline__ void batch_barrier(const BatchArgs &A, int ph, int tid) {
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    atomicAdd(&A.bctl->arrive[ph], 1u);
+    uint32_t spins = 0;
+    while (__hip_atomic_load(&A.bctl->arrive[ph], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > A.spin_limit ||
+          __hip_atomic_load(&A.bctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        atomicOr(&A.bctl->error, 1u);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();  // acquire: observe the other workgroups' stores
+}
+
 __global__ void __launch_bounds__(BATCH_BLK) k_batch(BatchArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *smem = (cx<T> *)smem_raw;
   __shared__ int32_t s_task;
   const int tid = threadIdx.x;
-  for (int iter = 0;; ++iter) {
-    int32_t ti;
-    if (A.use_queue) {
-      if (tid == 0) s_task = A.begin + (int32_t)atomicAdd(&A.bctl->next, 1u);
+  int32_t begin = 0;
+  for (int ph = 0; ph < 3; ++ph) {
+    const int32_t end = A.phase_end[ph];
+    for (;;) {
+      if (tid == 0) s_task = begin + (int32_t)atomicAdd(&A.bctl->next[ph], 1u);
       __syncthreads();
-      ti = s_task;
+      const int32_t ti = s_task;
       __syncthreads();
-    } else {
-      if (iter > 0) break;
-      ti = A.begin + (int32_t)blockIdx.x;
+      if (ti >= end) break;
+      const Task tk = A.tasks[ti];
+      batch_task(A, tk, smem, tid);
+      __syncthreads();  // smem is reused by the next task
     }
-    if (ti >= A.end) break;
-    const Task tk = A.tasks[ti];
-    if (A.use_queue && tk.wait_phase >= 0) {
-      if (tid == 0) {
-        uint32_t spins = 0;
-        while (__hip_atomic_load(&A.ictl[tk.inst].done[tk.wait_phase], __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)tk.wait) {
-          __builtin_amdgcn_s_sleep(2);
-          // Bounded wait: after the limit (or once any wait has failed) the
-          // error word is set and the task runs anyway, so the grid drains.
-          if (++spins > A.spin_limit ||
-              __hip_atomic_load(&A.bctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-            atomicOr(&A.bctl->error, 1u);
-            break;
-          }
-        }
-      }
-      __syncthreads();
-      __threadfence();  // acquire: observe the producer workgroups' stores
-    }
-    if (tk.type == TASK_RES) {
-      const Shape &sh0 = A.shapes[A.res_list[tk.inst]];
-      HK_LSWITCH(sh0.logR, batch_res, A, tk, smem, tid)
-    } else {
-      const Shape &sh = A.shapes[tk.inst];
-      const PV P{&A.ptrs[tk.inst], nullptr, 0, A.ws_base};
-      if (tk.type == TASK_ROWB) {
-        HK_LSWITCH(sh.logR, batch_rowb, A, tk, sh, P, smem, tid)
-      } else if (tk.type == TASK_ALPHA) {
-        reduce_partials(sh, P, tk.nrowb, smem);
-      } else {
-        HK_LSWITCH(sh.logC, batch_col, tk, sh, P, smem, tid)
-      }
-    }
-    if (tk.signal_phase >= 0) {
-      __threadfence();  // release this lane's stores
-      __syncthreads();
-      if (tid == 0) atomicAdd(&A.ictl[tk.inst].done[tk.signal_phase], 1u);
-    }
+    if (ph < 2) batch_barrier(A, ph, tid);
+    begin = end;
   }
 }
 
@@ -325,18 +331,24 @@ __global__ void __launch_bounds__(BATCH_BLK) k_group(BatchArgs A) {
   }
 }
 
-// Zeroes the batch control block and the per-instance counters (a plain
-// kernel rather than a memset node, so that graph replays stay exact).
-__global__ void k_batch_reset(BatchCtl *bctl, InstCtl *ictl, int64_t ninst) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) {
-    bctl->next = 0;
-    bctl->error = 0;
+// out[:, pairs[2k]] = out[:, pairs[2k + 1]] for column-major columns of
+// `rows` elements of type V (symmetric completion of tensor-matrix products).
+template <typename V>
+__global__ void __launch_bounds__(256) k_copy_cols(V *out, const int32_t *pairs, int64_t rows) {
+  const int64_t dst = pairs[2 * blockIdx.y], src = pairs[2 * blockIdx.y + 1];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x)
+    out[dst * rows + i] = out[src * rows + i];
+}
+
+// Zeroes the persistent schedule's control block (a plain kernel rather than
+// a memset node, so that graph replays stay exact).
+__global__ void k_batch_reset(BatchCtl *bctl) {
+  const int i = threadIdx.x;
+  if (i < 3) {
+    bctl->next[i] = 0;
+    bctl->arrive[i] = 0;
   }
-  if (i < ninst) {
-    ictl[i].done[0] = 0;
-    ictl[i].done[1] = 0;
-  }
+  if (i == 0) bctl->error = 0;
 }
 
 }  // namespace HK_NS

@@ -28,7 +28,10 @@ hipError_t launch_kernel(const void *fn, dim3 grid, dim3 block, void **args, siz
   bool limits_##SUFFIX(int logL, int E, KernelLimits *out);                                            \
   hipError_t launch_rows_##SUFFIX(int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh,      \
                                   const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st);   \
-  hipError_t launch_batch_##SUFFIX(const BatchArgs &args, int grid, int64_t ninst, bool reset, hipStream_t st); \
+  hipError_t launch_batch_##SUFFIX(const BatchArgs &args, int grid, hipStream_t st);                  \
+  hipError_t batch_resident_##SUFFIX(int *blocks_per_cu);                                           \
+  hipError_t launch_copy_cols_##SUFFIX(void *out, const int32_t *pairs, int npairs, int64_t rows,     \
+                                       bool complex_elems, hipStream_t st);                          \
   hipError_t launch_alpha_##SUFFIX(const Shape &sh, const Ptrs &p0, const Strides &str, int64_t npart,       \
                                    int64_t count, hipStream_t st);                                     \
   void batch_geometry_##SUFFIX(int *blk, int *e_row, int *e_col, size_t *lds_bytes);                 \

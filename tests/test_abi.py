@@ -167,3 +167,13 @@ def test_tune_db_round_trip(L, tmp_path):
     assert L.hk_tune_load(str(bad).encode(), None) == INVALID
     assert L.hk_tune_load(str(tmp_path / "missing.txt").encode(), None) == INVALID
     assert L.hk_tune_load(None, None) == NULLP
+
+
+def test_tensor_matrix_argument_errors(L):
+    b = ctypes.c_size_t(0)
+    assert L.hankel_tensor_matrix_workspace_size(HK_C64, 1, 8, 2, ctypes.byref(b)) == INVALID
+    assert L.hankel_tensor_matrix_workspace_size(HK_C64, 3, 0, 2, ctypes.byref(b)) == INVALID
+    assert L.hankel_tensor_matrix_workspace_size(HK_C64, 3, 8, 0, ctypes.byref(b)) == INVALID
+    assert L.hankel_tensor_matrix_workspace_size(HK_C64, 5, 8, 64, ctypes.byref(b)) == SIZE  # 64^4 columns
+    assert L.hankel_tensor_matrix_workspace_size(HK_C64, 3, 8, 2, None) == NULLP
+    assert L.hankel_tensor_matrix(HK_C64, None, 3, 8, 2, None, None, None, 0, None) == NULLP

@@ -175,3 +175,27 @@ def test_mixed_batch_subset():
     plan.status()
     check_plan_outputs(probs, outs, dtype)
     plan.close()
+
+
+def test_persistent_barrier_timeout_path():
+    """The bounded wait of the persistent schedule's grid barrier: with a bound
+    of zero polls the kernel takes its error path (sets the error word and
+    runs to its end), hk_plan_status reports it, and a plan with the default
+    bound afterwards is correct again."""
+    import paper_1401_6238_amd as hk
+    from paper_1401_6238_amd import _lib
+    dtype = torch.complex64
+    probs = mixed_problems(33, 40)
+    print_case(test="persistent_barrier_timeout")
+    plan = hk.Plan(plan_inputs(probs, dtype), flags=_lib.HK_PLAN_PERSISTENT)
+    plan.set_wait_bound(0)
+    plan.execute()
+    with pytest.raises(_lib.HankelError) as ei:
+        plan.status()
+    assert ei.value.code == 8  # HK_ERR_DEVICE_FAULT
+    plan.close()
+    plan = hk.Plan(plan_inputs(probs, dtype), flags=_lib.HK_PLAN_PERSISTENT)
+    outs = plan.execute()
+    plan.status()
+    check_plan_outputs(probs, outs, dtype)
+    plan.close()
