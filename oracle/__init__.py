@@ -249,6 +249,36 @@ def tensor_matrix(m: int, h, U) -> np.ndarray:
     return out
 
 
+def hankel_leading_subspace(h, rows: int, rank: int) -> np.ndarray:
+    """R leading left singular vectors of the rows x (len(h) - rows + 1) Hankel
+    matrix of h (the mode-1 unfolding of the Hankel tensor without its redundant
+    columns, Section 4.2), by a dense SVD."""
+    import scipy.linalg
+    h = _c128(h)
+    A = scipy.linalg.hankel(h[:rows], h[rows - 1:])
+    Uf, _, _ = np.linalg.svd(A, full_matrices=False)
+    return Uf[:, :rank]
+
+
+def hooi(m: int, h, rank: int, iters: int, U0=None):
+    """Algorithm 4.2 (HOOI for square Hankel tensors, U_1 = ... = U_m = U) in FP64
+    with dense SVDs: U <- R leading left singular vectors of the Hankel matrix of
+    h; then `iters` times U <- R leading left singular vectors of
+    Unfold_1(H x_2 conj(U) ... x_m conj(U)); core S = H conj(U)^m.
+    Returns (U, S) with S of shape (rank,)*m."""
+    h = _c128(h)
+    n = (len(h) + m - 1) // m
+    U = hankel_leading_subspace(h, n, rank) if U0 is None else np.asarray(U0, np.complex128)
+    for _ in range(iters):
+        M = tensor_matrix(m, h, np.conj(U))
+        Uf, _, _ = np.linalg.svd(M, full_matrices=False)
+        U = Uf[:, :rank]
+    M = tensor_matrix(m, h, np.conj(U))
+    S = (np.conj(U).T @ M).reshape([rank] * m)   # axes (j_1, j_m, ..., j_2)
+    S = np.transpose(S, [0] + list(range(m - 1, 0, -1)))
+    return U, S
+
+
 def problem_tvp(prob, want_y: Optional[bool] = None, want_alpha: Optional[bool] = None):
     """Oracle result for a ``workloads.Problem``."""
     wy = prob.want_y if want_y is None else want_y

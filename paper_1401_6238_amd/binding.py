@@ -39,6 +39,9 @@ def _dev(t: torch.Tensor) -> torch.Tensor:
         raise ValueError("tensors must live on the GPU")
     if not t.is_contiguous():
         raise ValueError("tensors must be contiguous")
+    if t.is_conj() or t.is_neg():
+        # a lazy conjugate / negative view: its memory holds the other values
+        raise ValueError("tensor has a pending conjugation or negation; call .resolve_conj() / .resolve_neg()")
     return t
 
 
@@ -231,6 +234,8 @@ class Plan:
         self._keep = []
         for i, p in enumerate(self.problems):
             vecs = p["vectors"]
+            for t in [p["h"]] + [v for v in vecs if v is not None]:
+                _dev(t)
             ref = next(v for v in vecs if v is not None)
             dtype = ref.dtype if dtype is None else dtype
             if ref.dtype != dtype:
@@ -292,10 +297,12 @@ def hankel_tensor_matrix(h: torch.Tensor, U: torch.Tensor, m: int) -> torch.Tens
     """T = H x_2 U ... x_m U for the square order-m Hankel tensor with generating
     vector h and an (n, R) matrix U.  Returns T with shape (n, R, ..., R),
     T[i, j_2, ..., j_m] = (H x_2 U[:, j_2] ... x_m U[:, j_m])[i]."""
-    _dev(h), _dev(U)
+    _dev(h)
+    if not U.is_cuda:
+        raise ValueError("tensors must live on the GPU")
     n, R = U.shape
     dt = _dtype(h)
-    Ucm = U.t().contiguous()  # column-major n x R: column j contiguous
+    Ucm = U.t().resolve_conj().resolve_neg().contiguous()  # column-major n x R: column j contiguous
     ncols = R ** (m - 1)
     out = torch.empty((ncols, n), dtype=h.dtype, device=h.device)  # column-major n x R^(m-1)
     nb = ctypes.c_size_t(0)
