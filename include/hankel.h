@@ -14,9 +14,14 @@
  *
  * with fft(v)_k = sum_j v_j e^{-2 pi i jk/N}, ifft = (1/N) * conjugate kernel,
  * "~" = zero padding to length N >= d_H, and products taken without complex
- * conjugation (Section 2.1 mode-p product).  The library pads to the next power
- * of two N >= d_H; any N >= d_H gives the same result.  The 2-level block
- * (BHHB) form uses 2D FFTs on a grid of at least
+ * conjugation (Section 2.1 mode-p product).  Any N >= d_H gives the same
+ * result (the paper takes N = d_H, Section 3).  The library takes the smallest
+ * N >= d_H of the form 2^k, 3 * 2^k or 5 * 2^k (N <= 2^24) for which it has
+ * kernels: a length 3 * 2^k or 5 * 2^k transform is computed as a 2D
+ * transform of 3 or 5 sequences of length 2^k through the Chinese-remainder
+ * index map (no twiddles between the factors), which keeps the padding below
+ * 25% of d_H for most lengths instead of up to 100%.  The 2-level block
+ * (BHHB) form uses 2D FFTs of power-of-two sizes on a grid of at least
  * (sum n_p - m + 1) x (sum N_p - m + 1) (Section 3, BHHB procedure).
  *
  * Conventions shared by every entry point
@@ -155,6 +160,8 @@ typedef struct hk_plan_s *hk_plan_t;
                                    (task kind, transform length) group; no in-kernel waits      */
 #define HK_PLAN_GRAPH 0x4u      /* capture the plan's launches in a hipGraph on first execute */
 #define HK_PLAN_AUTOTUNE 0x8u   /* reserved (accepted, no effect)                             */
+#define HK_PLAN_POW2 0x10u      /* power-of-two transform lengths only (no 3 * 2^k, 5 * 2^k);
+                                   implied by PERSISTENT                                        */
 
 /* Creates a plan for `count` problems.  The plan copies the descriptors
  * (pointers included); on first execute it uploads them to a device table
@@ -262,9 +269,10 @@ hk_status_t block_hankel_tvp_strided_batched(hk_dtype_t dt, const void *H, int64
 /* -------------------------------------------------------------------------
  * Schedule control and diagnostics.
  * ------------------------------------------------------------------------- */
-/* Padded FFT length (1D) chosen for a given d_H, and its row x column split
- * (N = n_row * n_col; n_col = 1 means one workgroup holds the whole
- * transform). */
+/* Padded FFT length N (1D) chosen for a given d_H (complex64 data, default
+ * schedule) and the row x column split of each of its power-of-two sequences:
+ * N = odd * n_row * n_col with odd = N / (n_row * n_col) in {1, 3, 5};
+ * n_col = 1 means one workgroup holds the whole transform. */
 hk_status_t hk_fft_layout(int64_t d_h, int64_t *n_fft, int64_t *n_row, int64_t *n_col);
 /* Runs the in-house autotuner for the plain 1D path of one (dtype, m, n)
  * shape on the current device and stores the winner in the process-wide

@@ -20,6 +20,7 @@ HK_PLAN_PERSISTENT = 0x1
 HK_PLAN_MULTIKERNEL = 0x2
 HK_PLAN_GRAPH = 0x4
 HK_PLAN_AUTOTUNE = 0x8
+HK_PLAN_POW2 = 0x10
 
 STATUS_NAMES = {
     0: "HK_SUCCESS", 1: "HK_ERR_INVALID_VALUE", 2: "HK_ERR_NULL_POINTER", 3: "HK_ERR_MISALIGNED",

@@ -39,10 +39,10 @@ static Status prepare(const Problem &p, int64_t batch, Shape *sh, Ptrs *P, Sched
   Status s = layout_for(p, 0, &lay);
   if (!s.ok()) return s;
   Sched sch;
-  const int logN = lay.logR + lay.logC;
-  if (sched_lookup(p.dt, p.prog, p.is_block ? 1 : 0, logN, p.is_block ? lay.logC : -1, batch, &sch)) {
+  const int logM = lay.logR + lay.logC;
+  if (sched_lookup(p.dt, p.prog, p.is_block ? 1 : 0, lay.odd, logM, p.is_block ? lay.logC : -1, batch, &sch)) {
     Layout l2;
-    if (layout_for(p, sch.split, &l2).ok() && sched_valid(p.dt, l2, sch))
+    if (layout_for(p, sch.split, &l2).ok() && l2.odd == lay.odd && sched_valid(p.dt, l2, sch))
       lay = l2;
     else
       sch = default_sched(p.dt, lay, p.prog, batch);
@@ -180,7 +180,7 @@ hk_status_t hk_fft_layout(int64_t d_h, int64_t *n_fft, int64_t *n_row, int64_t *
   Layout lay;
   Status s = layout_for(p, 0, &lay);
   if (!s.ok()) return finish(s);
-  *n_fft = (int64_t)1 << (lay.logR + lay.logC);
+  *n_fft = (int64_t)lay.odd << (lay.logR + lay.logC);
   *n_row = (int64_t)1 << lay.logR;
   *n_col = (int64_t)1 << lay.logC;
   return finish(Status());

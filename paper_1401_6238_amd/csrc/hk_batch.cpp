@@ -43,7 +43,7 @@ struct hk_plan_s {
   // grouped launches: task indices sorted by (phase, kind, length) and the
   // launch list over them
   struct Group {
-    int kind, logL;
+    int kind, logL, odd;
     int32_t begin, count;
   };
   std::vector<int32_t> order;
@@ -87,24 +87,26 @@ static void tables_layout(hk_plan_s *p) {
     memcpy(p->host_tables.data() + p->off_order, p->order.data(), sizeof(int32_t) * p->order.size());
 }
 
-// Sorts each phase's tasks by (kind, transform length) and records one launch
-// per run of equal keys.
+// Sorts each phase's tasks by (kind, transform length, odd factor of the row
+// kernels) and records one launch per run of equal keys.
 static void build_groups(hk_plan_s *p) {
   p->order.clear();
   p->launches.clear();
   int32_t b = 0;
   for (int ph = 0; ph < 3; ++ph) {
     const int32_t e = p->phase_end[ph];
-    std::vector<std::pair<std::pair<int, int>, int32_t>> keyed;
+    std::vector<std::pair<std::tuple<int, int, int>, int32_t>> keyed;
     for (int32_t i = b; i < e; ++i) {
       const Task &t = p->tasks[i];
-      int kind, logL;
+      int kind, logL, odd = 1;  // column kernels take the odd factor at run time
       if (t.type == TASK_RES) {
         kind = GK_RES;
         logL = p->shapes[p->res_list[t.inst]].logR;
+        odd = p->shapes[p->res_list[t.inst]].odd;
       } else if (t.type == TASK_ROWB) {
         kind = GK_ROWB;
         logL = p->shapes[t.inst].logR;
+        odd = p->shapes[t.inst].odd;
       } else if (t.type == TASK_ALPHA) {
         kind = GK_ALPHA;
         logL = 0;
@@ -112,16 +114,20 @@ static void build_groups(hk_plan_s *p) {
         kind = GK_COL;
         logL = p->shapes[t.inst].logC;
       }
-      keyed.push_back({{kind, logL}, i});
+      keyed.push_back({std::make_tuple(kind, logL, odd), i});
     }
     // longest transforms first within a phase
     std::stable_sort(keyed.begin(), keyed.end(), [](const auto &x, const auto &y) {
-      if (x.first.first != y.first.first) return x.first.first < y.first.first;
-      return x.first.second > y.first.second;
+      const int kx = std::get<0>(x.first), ky = std::get<0>(y.first);
+      if (kx != ky) return kx < ky;
+      const int lx = std::get<1>(x.first), ly = std::get<1>(y.first);
+      if (lx != ly) return lx > ly;
+      return std::get<2>(x.first) > std::get<2>(y.first);
     });
     for (size_t k = 0; k < keyed.size(); ++k) {
       if (k == 0 || keyed[k].first != keyed[k - 1].first)
-        p->launches.push_back({keyed[k].first.first, keyed[k].first.second, (int32_t)p->order.size(), 0});
+        p->launches.push_back({std::get<0>(keyed[k].first), std::get<1>(keyed[k].first), std::get<2>(keyed[k].first),
+                               (int32_t)p->order.size(), 0});
       p->order.push_back(keyed[k].second);
       p->launches.back().count++;
     }
@@ -153,7 +159,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
   if (count < 0) return fail(HK_ERR_INVALID_VALUE, "count must be >= 0");
   if (count > 0 && !probs) return fail(HK_ERR_NULL_POINTER, "problems is NULL");
   if (count > (1 << 24)) return fail(HK_ERR_SIZE_LIMIT, "too many problems in one plan");
-  if (flags & ~(unsigned)(HK_PLAN_PERSISTENT | HK_PLAN_MULTIKERNEL | HK_PLAN_GRAPH | HK_PLAN_AUTOTUNE))
+  if (flags & ~(unsigned)(HK_PLAN_PERSISTENT | HK_PLAN_MULTIKERNEL | HK_PLAN_GRAPH | HK_PLAN_AUTOTUNE | HK_PLAN_POW2))
     return fail(HK_ERR_INVALID_VALUE, "unknown plan flags");
   if ((flags & HK_PLAN_PERSISTENT) && (flags & HK_PLAN_MULTIKERNEL))
     return fail(HK_ERR_INVALID_VALUE, "PERSISTENT and MULTIKERNEL are exclusive");
@@ -177,6 +183,32 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
       limits_f32(logL, E, &k);
     return k.tps;
   };
+  // lanes of one row of the batched row kernels (odd-factor rows hold
+  // odd_row_e elements per lane)
+  const int e_odd = dbl(dt) ? odd_row_e_f64() : odd_row_e_f32();
+  auto row_tps = [&](const Shape &sh) {
+    KernelLimits k;
+    if (sh.odd > 1) {
+      row_limits(dt, sh.odd, sh.logR, e_odd, &k);
+      return k.tps;
+    }
+    return tps(sh.logR, er);
+  };
+  // First virtual columns (sequence * R + storage column) of the column tiles
+  // of a transform with `ncols` storage columns per sequence.
+  auto col_tiles = [&](const Shape &sh, int64_t ncols, int tw) {
+    std::vector<int64_t> v;
+    const int64_t R = (int64_t)1 << sh.logR;
+    if (sh.odd == 1 || tw > R) {
+      const int64_t nv = sh.odd == 1 ? ncols : sh.odd * R;
+      for (int64_t c0 = 0; c0 < nv; c0 += tw) v.push_back(c0);
+    } else {
+      for (int q = 0; q < sh.odd; ++q)
+        for (int64_t c0 = 0; c0 < ncols; c0 += tw) v.push_back(q * R + c0);
+    }
+    return v;
+  };
+  const bool allow_odd = !p->persistent && !(flags & HK_PLAN_POW2);
   p->shapes.resize(count);
   p->ptrs.resize(count);
   p->ctl_bytes = align256(sizeof(BatchCtl));
@@ -186,7 +218,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
     double cost;
   };
   std::vector<Inst> multi;
-  std::map<std::tuple<int, int, int, int, int>, std::vector<int32_t>> groups;
+  std::map<std::tuple<int, int, int, int, int, int>, std::vector<int32_t>> groups;
   for (int64_t i = 0; i < count; ++i) {
     Problem pr = problem_of(dt, probs[i]);
     Status s = validate_forward(pr);
@@ -195,19 +227,23 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
       return fail(s.code, "problem " + std::to_string(i) + ": " + s.msg);
     }
     Layout lay;
-    layout_for(pr, 0, &lay);
+    s = layout_for(pr, 0, &lay, allow_odd);
+    if (!s.ok()) {
+      delete p;
+      return fail(s.code, "problem " + std::to_string(i) + ": " + s.msg);
+    }
     Sched sc;
-    if (!lay.resident) sc.rows_per_wg = std::max(1, blk / tps(lay.logR, er));
     Shape sh;
     Ptrs P;
     build_shape(pr, lay, sc, &sh, &P, nullptr);
     if (!lay.resident) {
+      sh.rows_per_wg = std::max(1, blk / row_tps(sh));
       P.ws = (void *)(uintptr_t)inst_off;
       inst_off += align256((size_t)sh.ws_bytes);
-      multi.push_back({i, (double)((int64_t)1 << (sh.logR + sh.logC)) * (sh.nops + 1)});
+      multi.push_back({i, (double)((int64_t)sh.odd << (sh.logR + sh.logC)) * (sh.nops + 1)});
     } else {
       P.ws = nullptr;
-      groups[std::make_tuple(sh.logR, sh.nops, sh.want_y, sh.want_alpha, sh.real_out)].push_back((int32_t)i);
+      groups[std::make_tuple(sh.logR, sh.odd, sh.nops, sh.want_y, sh.want_alpha, sh.real_out)].push_back((int32_t)i);
     }
     p->shapes[i] = sh;
     p->ptrs[i] = P;
@@ -220,7 +256,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
     const Shape &sh = p->shapes[in.idx];
     const int tw = std::max(1, blk / tps(sh.logC, ec));
     for (int o = 0; o < sh.nops; ++o)
-      for (int64_t c0 = 0; c0 < sh.ops[o].ncol_nz; c0 += tw) {
+      for (int64_t c0 : col_tiles(sh, sh.ops[o].ncol_nz, tw)) {
         Task t = {TASK_COLA, (int32_t)in.idx, o, (int32_t)c0, 0};
         p->tasks.push_back(t);
       }
@@ -228,11 +264,12 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
   // Phase 1b: resident instances, grouped so that a workgroup's rows share
   // their control flow; groups of long transforms first.
   std::vector<std::pair<int, std::vector<int32_t> *>> gl;
-  for (auto &kv : groups) gl.push_back({std::get<0>(kv.first) * 16 + std::get<1>(kv.first), &kv.second});
+  for (auto &kv : groups)
+    gl.push_back({(std::get<0>(kv.first) * 8 + std::get<1>(kv.first)) * 16 + std::get<2>(kv.first), &kv.second});
   std::sort(gl.begin(), gl.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
   for (auto &g : gl) {
     const Shape &sh0 = p->shapes[(*g.second)[0]];
-    const int rows = std::max(1, blk / tps(sh0.logR, er));
+    const int rows = std::max(1, blk / row_tps(sh0));
     for (size_t k = 0; k < g.second->size(); k += rows) {
       const int n = (int)std::min<size_t>(rows, g.second->size() - k);
       Task t = {TASK_RES, (int32_t)p->res_list.size(), n, 0, 0};
@@ -244,7 +281,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
   // Phase 2: pass B.
   for (const Inst &in : multi) {
     const Shape &sh = p->shapes[in.idx];
-    const int rows = std::max(1, blk / tps(sh.logR, er));
+    const int rows = std::max(1, blk / row_tps(sh));
     const int64_t C = (int64_t)1 << sh.logC;
     const int32_t nb = (int32_t)((C + rows - 1) / rows);
     for (int32_t b = 0; b < nb; ++b) {
@@ -266,7 +303,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
     if (!sh.want_y) continue;
     const int tw = std::max(1, blk / tps(sh.logC, ec));
     const int64_t ncols = std::min<int64_t>((int64_t)1 << sh.logR, sh.out_rows);
-    for (int64_t c0 = 0; c0 < ncols; c0 += tw) {
+    for (int64_t c0 : col_tiles(sh, ncols, tw)) {
       Task t = {TASK_COLD, (int32_t)in.idx, 0, (int32_t)c0, 0};
       p->tasks.push_back(t);
     }
@@ -337,8 +374,12 @@ static Status enqueue(hk_plan_s *p, char *ws, hipStream_t st) {
       A.end = g.begin + g.count;
       count_launch();
       prof_before(st);
-      e = dbl(p->dt) ? launch_group_f64(A, g.kind, g.logL, g.count, st)
-                     : launch_group_f32(A, g.kind, g.logL, g.count, st);
+      if (g.odd > 1)
+        e = dbl(p->dt) ? launch_group_odd_f64(A, g.odd, g.kind, g.logL, g.count, st)
+                       : launch_group_odd_f32(A, g.odd, g.kind, g.logL, g.count, st);
+      else
+        e = dbl(p->dt) ? launch_group_f64(A, g.kind, g.logL, g.count, st)
+                       : launch_group_f32(A, g.kind, g.logL, g.count, st);
       prof_after(PK_BATCH, st);
       if (e != hipSuccess) return hip_fail(e, "grouped batch launch");
     }
@@ -479,7 +520,8 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
     Layout lay;
     if (p.is_block && sp != 0) continue;
     if (!layout_for(p, sp, &lay).ok()) continue;
-    if (sp != 0 && (lay.resident || (lay.logR == lay0.logR && lay.logC == lay0.logC))) continue;
+    if (sp != 0 && (lay.resident || lay.odd != lay0.odd || (lay.logR == lay0.logR && lay.logC == lay0.logC)))
+      continue;
     layouts.push_back({sp, lay});
   }
   // buffer sizes (workspace does not depend on the schedule)
@@ -596,7 +638,7 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
       if (!s.ok()) break;
       for (int round = 0; round < 2 && s.ok(); ++round) {
         // row-pass parameters
-        for (int er : {8, 16})
+        for (int er : {4, 8, 16})
           for (int rows : {1, 2, 4, 8, 16, 32})
             for (int it : {1, 2, 4}) {
               if (lay.resident && it != 1) continue;
@@ -649,12 +691,13 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   if (e != hipSuccess) return hip_fail(e, "autotune buffers");
   if (!s.ok()) return s;
   if (best >= 1e30) return fail(HK_ERR_NOT_SUPPORTED, "autotune found no schedule");
-  sched_store(dt, p.prog, p.is_block ? 1 : 0, lay0.logR + lay0.logC, p.is_block ? lay0.logC : -1, batch, bestsc);
+  sched_store(dt, p.prog, p.is_block ? 1 : 0, lay0.odd, lay0.logR + lay0.logC, p.is_block ? lay0.logC : -1, batch,
+              bestsc);
   if (verbose)
     fprintf(stderr,
-            "[hk autotune] best of %d: split=%d (R=2^%d C=2^%d) E_row=%d rows=%d iters=%d E_col=%d tw=%d xcd=%d "
-            "%.4f ms\n",
-            ntimed, bestsc.split, bestlay.logR, bestlay.logC, bestsc.E_row, bestsc.rows_per_wg, bestsc.iters,
+            "[hk autotune] best of %d: split=%d (odd=%d R=2^%d C=2^%d) E_row=%d rows=%d iters=%d E_col=%d tw=%d "
+            "xcd=%d %.4f ms\n",
+            ntimed, bestsc.split, bestlay.odd, bestlay.logR, bestlay.logC, bestsc.E_row, bestsc.rows_per_wg, bestsc.iters,
             bestsc.E_col, bestsc.tw, bestsc.xcd, best);
   return Status();
 }

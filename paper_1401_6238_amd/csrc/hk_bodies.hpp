@@ -218,21 +218,39 @@ __device__ __forceinline__ void store_out(void *base, int64_t idx, cx<T> v, int 
     ((cx<T> *)base)[idx] = v;
 }
 
+// Length M = 2^(logR + logC) of one sequence and length N = odd * M of the
+// transform.
+__device__ __forceinline__ int64_t seq_len(const Shape &sh) { return (int64_t)1 << (sh.logR + sh.logC); }
+__device__ __forceinline__ int64_t fft_len(const Shape &sh) { return (int64_t)sh.odd << (sh.logR + sh.logC); }
+
+// Multipass workspace: nbuf buffers of N elements (sequence q of a buffer at
+// q * M), then the row pass's scalar partial sums.
 template <typename T>
 __device__ __forceinline__ cx<T> *ws_buf(const Shape &sh, const PV &P, int b) {
-  const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
-  return (cx<T> *)P.ws() + (int64_t)b * N;
+  return (cx<T> *)P.ws() + (int64_t)b * fft_len(sh);
 }
 
 template <typename T>
 __device__ __forceinline__ cx<T> *ws_partials(const Shape &sh, const PV &P) {
-  const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
-  return (cx<T> *)P.ws() + sh.nbuf * N;
+  return (cx<T> *)P.ws() + sh.nbuf * fft_len(sh);
 }
 
-template <typename T>
-__device__ __forceinline__ uint32_t *ws_counter(const Shape &sh, const PV &P) {
-  return (uint32_t *)(ws_partials<T>(sh, P) + sh.partials);
+// Chinese-remainder map of Z_N = Z_odd x Z_M: element (q, p) of the
+// sequence grid is entry n = p + M tau of the length-N vector, with
+// tau = ((q - p) M^{-1}) mod odd (then n = q mod odd and n = p mod M).
+// tau[s] for the positions p0 + s * step (0 <= p0, step < 2^31); `odd` and
+// `inv` = M^{-1} mod odd, constants where the caller's are.
+template <int EE>
+__device__ __forceinline__ void crt_tau(int (&tau)[EE], int q, uint32_t p0, uint32_t step, int odd, int inv) {
+  const int pm = (int)(p0 % (uint32_t)odd);
+  int t0 = ((q - pm + odd) * inv) % odd;
+  const int d = (int)((step % (uint32_t)odd) * (uint32_t)inv % (uint32_t)odd);
+#pragma unroll
+  for (int s = 0; s < EE; ++s) {
+    tau[s] = t0;
+    t0 -= d;
+    t0 += t0 < 0 ? odd : 0;
+  }
 }
 
 // Tree sum over the lanes [seg*S, seg*S + S) of the workgroup (S a power of
@@ -252,13 +270,15 @@ __device__ __forceinline__ cx<T> segment_sum(cx<T> v, cx<T> *red, int tid, int S
 }
 
 // ---------------------------------------------------------------------------
-// Row body: one sequence of length L per row; TPS lanes per row.
+// Row body: one sequence of length L per row; TPS lanes per row.  With ODD > 1
+// a row stands for the same row of the ODD sequences of the Z_odd x Z_M grid,
+// all held by the row's lanes (slot s of sequence q in h[q][s]).
 // resident = true : the row is a whole 1D instance (load inputs with padding,
 //                   store the sliced outputs).
 // resident = false: pass B row `row` of a multipass instance.
 // Returns this lane's contribution to the scalar product (forward program).
 // ---------------------------------------------------------------------------
-template <typename T, int L, int E>
+template <typename T, int L, int E, int ODD = 1>
 struct RowBody {
   using S = FFTShape<L, E>;
   static constexpr int EE = S::EE;
@@ -267,31 +287,58 @@ struct RowBody {
   // A row's TPS lanes are consecutive, so a row of at most 64 lanes lives in
   // one wavefront and its exchanges need no workgroup barrier.
   static constexpr bool WAVE = TPS <= 64;
+  using Seqs = cx<T>[ODD][EE];
 
   static __device__ __forceinline__ void fft(cx<T> (&a)[EE], int t, cx<T> *lds, const StageTw<T, L, E> &tw) {
     fft_seq<T, L, E, WAVE>(a, t, lds, tw);
   }
 
+  // Length-ODD DFT across the sequences, bin by bin (the odd axis of the
+  // transform).
+  static __device__ __forceinline__ void odd_dft(Seqs &h) {
+    if constexpr (ODD > 1) {
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        cx<T> v[ODD];
+#pragma unroll
+        for (int q = 0; q < ODD; ++q) v[q] = h[q][s];
+        dft_odd<T, ODD>(v);
+#pragma unroll
+        for (int q = 0; q < ODD; ++q) h[q][s] = v[q];
+      }
+    }
+  }
+
+  // Vector entries of slots s of sequence q of a resident row: positions
+  // t + s TPS of the length-L sequence, mapped to Z_N.
+  static __device__ __forceinline__ void res_index(int64_t (&idx)[EE], int q, int t) {
+    int tau[EE];
+    if constexpr (ODD > 1) {
+      constexpr int inv = (L % ODD == 1) ? 1 : (ODD == 3 ? 2 : ((L % 5 == 2) ? 3 : ((L % 5 == 3) ? 2 : 4)));
+      crt_tau<EE>(tau, q, (uint32_t)t, (uint32_t)TPS, ODD, inv);
+    }
+#pragma unroll
+    for (int s = 0; s < EE; ++s) idx[s] = t + s * TPS + (ODD > 1 ? (int64_t)L * tau[s] : 0);
+  }
+
   static __device__ __forceinline__ void load(cx<T> (&a)[EE], const Shape &sh, const PV &P, int o,
-                                              int64_t row, bool valid_row, int t, bool resident) {
+                                              int64_t row, bool valid_row, int t, bool resident, int q) {
     const OpDesc &od = sh.ops[o];
     uint32_t off[EE];
     if (resident) {
       // the rows of a workgroup may be different instances: flat loads
       int64_t idx[EE];
       bool ok[EE];
+      res_index(idx, q, t);
 #pragma unroll
-      for (int s = 0; s < EE; ++s) {
-        idx[s] = t + s * TPS;
-        ok[s] = valid_row && idx[s] < od.len;
-      }
+      for (int s = 0; s < EE; ++s) ok[s] = valid_row && idx[s] < od.len;
       gather<T, EE>(a, P.op(o), idx, ok, od.flags);
     } else {
-      // row `row` of the operand's column transform; its columns past
-      // ncol_nz were never written and read as zero
-      const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
-      const auto r = make_buf(ws_buf<T>(sh, P, od.buf), N * (int64_t)sizeof(cx<T>));
-      const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
+      // row `row` of sequence q of the operand's column transform; its
+      // columns past ncol_nz were never written and read as zero
+      const int64_t M = seq_len(sh);
+      const auto r = make_buf(ws_buf<T>(sh, P, od.buf), ODD * M * (int64_t)sizeof(cx<T>));
+      const uint32_t rbase = (uint32_t)((q * M + row * L) * (int64_t)sizeof(cx<T>));
 #pragma unroll
       for (int s = 0; s < EE; ++s) {
         const int i = t + s * TPS;
@@ -301,26 +348,26 @@ struct RowBody {
     }
   }
 
-  // Stores output `which` (0: y / grad_h, 1: grad_x) of this row.
+  // Stores sequence q of output `which` (0: y / grad_h, 1: grad_x) of this row.
   static __device__ __forceinline__ void store(const cx<T> (&a)[EE], const Shape &sh, const PV &P,
                                                int which, int64_t row, bool valid_row, int t,
-                                               bool resident, const cx<T> (&w)[EE]) {
+                                               bool resident, const cx<T> (&w)[EE], int q) {
     if (!valid_row) return;
     if (resident) {
       void *dst = which == 0 ? P.y() : P.out1();
       const int64_t lim = which == 0 ? sh.out_rows : sh.out1_len;
       const bool cj = (sh.prog == PROG_BWD) && which == 1;
+      int64_t idx[EE];
+      res_index(idx, q, t);
 #pragma unroll
-      for (int s = 0; s < EE; ++s) {
-        const int pos = t + s * TPS;
-        if (pos < lim) store_out<T>(dst, pos, cj ? cconj(a[s]) : a[s], sh.real_out);
-      }
+      for (int s = 0; s < EE; ++s)
+        if (idx[s] < lim) store_out<T>(dst, idx[s], cj ? cconj(a[s]) : a[s], sh.real_out);
     } else {
-      const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
-      const auto r = make_buf(ws_buf<T>(sh, P, sh.ops[which].buf), N * (int64_t)sizeof(cx<T>));
-      const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
+      const int64_t M = seq_len(sh);
+      const auto r = make_buf(ws_buf<T>(sh, P, sh.ops[which].buf), ODD * M * (int64_t)sizeof(cx<T>));
+      const uint32_t rbase = (uint32_t)((q * M + row * L) * (int64_t)sizeof(cx<T>));
       if (!sh.is_block) {
-        // four-step twiddles W_N^{pos * row}, pos = t + s TPS (from twiddles())
+        // four-step twiddles W_M^{pos * row}, pos = t + s TPS (from twiddles())
 #pragma unroll
         for (int s = 0; s < EE; ++s)
           BufIO<T>::st(cmul(a[s], w[s]), r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
@@ -331,7 +378,7 @@ struct RowBody {
     }
   }
 
-  // Pass-B rows of a 1D instance: w[s] = W_N^{(t + s TPS) row}, used on the
+  // Pass-B rows of a 1D instance: w[s] = W_M^{(t + s TPS) row}, used on the
   // loaded operands (pass A's twiddle) and on the stored output.
   static __device__ __forceinline__ bool twiddles(cx<T> (&w)[EE], const Shape &sh, int64_t row, int t,
                                                   bool resident, const cx<T> *tw24, const cx<T> *tw4096) {
@@ -346,100 +393,116 @@ struct RowBody {
     }
   }
 
+  // Spectrum of operand o on this row: its ODD sequences loaded (each next
+  // one in flight while the current one is transformed), transformed along
+  // the power-of-two axis, then across the sequences.
+  static __device__ __forceinline__ void spectrum(Seqs &h, const Shape &sh, const PV &P, int o, int64_t row,
+                                                  bool valid_row, int t, cx<T> *lds, bool resident,
+                                                  const StageTw<T, L, E> &stw, const cx<T> (&w)[EE], bool tw_on) {
+    cx<T> nx[EE];
+    load(nx, sh, P, o, row, valid_row, t, resident, 0);
+#pragma unroll
+    for (int q = 0; q < ODD; ++q) {
+#pragma unroll
+      for (int s = 0; s < EE; ++s) h[q][s] = nx[s];
+      if (q + 1 < ODD) load(nx, sh, P, o, row, valid_row, t, resident, q + 1);
+      twiddle_in(h[q], w, tw_on);
+      fft(h[q], t, lds, stw);
+    }
+    odd_dft(h);
+  }
+
+  // Spectral product step of the forward program for operand o with
+  // spectrum h: the generating vector's ifft starts acc, vectors multiply in
+  // with their multiplicity, the scalar operand's spectrum closes alpha.
+  static __device__ __forceinline__ void combine_fwd(Seqs &acc, const Seqs &h, const OpDesc &od, T invN,
+                                                     cx<T> &part) {
+    if (od.role == ROLE_H) {
+#pragma unroll
+      for (int q = 0; q < ODD; ++q)
+#pragma unroll
+        for (int s = 0; s < EE; ++s) acc[q][s] = cscale(cconj(h[q][s]), invN);
+    } else {
+      for (int e = 0; e < od.exp; ++e) {
+#pragma unroll
+        for (int q = 0; q < ODD; ++q)
+#pragma unroll
+          for (int s = 0; s < EE; ++s) acc[q][s] = cmul(acc[q][s], h[q][s]);
+      }
+      if (od.flags & OPF_ALPHA) {
+#pragma unroll
+        for (int q = 0; q < ODD; ++q)
+#pragma unroll
+          for (int s = 0; s < EE; ++s) part = cfma(acc[q][s], h[q][s], part);
+      }
+    }
+  }
+
+  // Output transform y = fft(z) of the row (odd axis, then each sequence)
+  // and its store.
+  static __device__ __forceinline__ void output(Seqs &acc, const Shape &sh, const PV &P, int which, int64_t row,
+                                                bool valid_row, int t, cx<T> *lds, bool resident,
+                                                const StageTw<T, L, E> &stw, const cx<T> (&w)[EE]) {
+    odd_dft(acc);
+#pragma unroll
+    for (int q = 0; q < ODD; ++q) {
+      fft(acc[q], t, lds, stw);
+      store(acc[q], sh, P, which, row, valid_row, t, resident, w, q);
+    }
+  }
+
   // Forward program: z = h^ prod_p x^_p^{e_p}; y = fft(z); alpha = sum z x^_1.
   static __device__ __forceinline__ cx<T> run_fwd(const Shape &sh, const PV &P, int64_t row, bool valid_row,
                                                   int t, cx<T> *lds, bool resident, const cx<T> *tw24,
                                                   const cx<T> *tw4096) {
-    const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
-    cx<T> a[EE], nx[EE], acc[EE];
-    cx<T> part = czero<T>();
-#pragma unroll
-    for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
-    load(a, sh, P, 0, row, valid_row, t, resident);
-    StageTw<T, L, E> stw;
-    stw.init(t, tw4096);
-    cx<T> w[EE];
-    const bool tw_on = twiddles(w, sh, row, t, resident, tw24, tw4096);
-    for (int o = 0; o < sh.nops; ++o) {
-      // the next operand's loads are in flight while this one is transformed
-      if (o + 1 < sh.nops) load(nx, sh, P, o + 1, row, valid_row, t, resident);
-      twiddle_in(a, w, tw_on);
-      fft(a, t, lds, stw);
-      const OpDesc &od = sh.ops[o];
-      if (od.role == ROLE_H) {
-#pragma unroll
-        for (int s = 0; s < EE; ++s) acc[s] = cscale(cconj(a[s]), invN);
-      } else {
-        for (int e = 0; e < od.exp; ++e) {
-#pragma unroll
-          for (int s = 0; s < EE; ++s) acc[s] = cmul(acc[s], a[s]);
-        }
-        if (od.flags & OPF_ALPHA) {
-#pragma unroll
-          for (int s = 0; s < EE; ++s) part = cfma(acc[s], a[s], part);
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < EE; ++s) a[s] = nx[s];
-    }
-    if (sh.want_y) {
-      fft(acc, t, lds, stw);
-      store(acc, sh, P, 0, row, valid_row, t, resident, w);
-    }
-    return part;
+    return run_fwd_rows(sh, P, row, 0, 1, valid_row, t, lds, resident, tw24, tw4096);
   }
 
-  // Pass B, forward program, over K rows row0, row0 + rstride, ... handled in
-  // turn by this lane group: while a row's last operand is transformed, the
-  // first operand of the next row is already loading, so the memory traffic
-  // of one row overlaps the arithmetic of the previous one.  Returns the lane's
-  // share of the scalar product over its rows.
+  // Forward program over K rows row0, row0 + rstride, ... handled in turn by
+  // this lane group (K = 1 for resident rows).  The loads run one sequence
+  // ahead of the transforms: while a sequence is transformed the next one
+  // (of this operand, the next operand or the next row's first operand) is
+  // already loading, so the memory traffic of a row overlaps the arithmetic.
+  // Returns the lane's share of the scalar product over its rows.
   static __device__ __forceinline__ cx<T> run_fwd_rows(const Shape &sh, const PV &P, int64_t row0, int rstride,
-                                                       int K, int t, cx<T> *lds, const cx<T> *tw24,
-                                                       const cx<T> *tw4096) {
+                                                       int K, bool valid0, int t, cx<T> *lds, bool resident,
+                                                       const cx<T> *tw24, const cx<T> *tw4096) {
     const int64_t C = (int64_t)1 << sh.logC;
-    const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
-    cx<T> a[EE], nx[EE], acc[EE], w[EE];
+    const T invN = T(1) / T((int64_t)ODD << (sh.logR + sh.logC));
+    cx<T> nx[EE], w[EE];
+    Seqs h, acc;
     cx<T> part = czero<T>();
     int64_t row = row0;
-    bool valid = row < C;
-    load(a, sh, P, 0, row, valid, t, false);
+    bool valid = resident ? valid0 : row < C;
+    load(nx, sh, P, 0, row, valid, t, resident, 0);
     StageTw<T, L, E> stw;
     stw.init(t, tw4096);
     for (int it = 0; it < K; ++it) {
-      const bool tw_on = twiddles(w, sh, row, t, false, tw24, tw4096);
+      const bool tw_on = twiddles(w, sh, row, t, resident, tw24, tw4096);
       const int64_t nrow = row + rstride;
       const bool nvalid = (it + 1 < K) && nrow < C;
 #pragma unroll
-      for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
+      for (int q = 0; q < ODD; ++q)
+#pragma unroll
+        for (int s = 0; s < EE; ++s) acc[q][s] = czero<T>();
       for (int o = 0; o < sh.nops; ++o) {
-        if (o + 1 < sh.nops)
-          load(nx, sh, P, o + 1, row, valid, t, false);
-        else if (it + 1 < K)
-          load(nx, sh, P, 0, nrow, nvalid, t, false);
-        twiddle_in(a, w, tw_on);
-        fft(a, t, lds, stw);
-        const OpDesc &od = sh.ops[o];
-        if (od.role == ROLE_H) {
 #pragma unroll
-          for (int s = 0; s < EE; ++s) acc[s] = cscale(cconj(a[s]), invN);
-        } else {
-          for (int e = 0; e < od.exp; ++e) {
+        for (int q = 0; q < ODD; ++q) {
 #pragma unroll
-            for (int s = 0; s < EE; ++s) acc[s] = cmul(acc[s], a[s]);
-          }
-          if (od.flags & OPF_ALPHA) {
-#pragma unroll
-            for (int s = 0; s < EE; ++s) part = cfma(acc[s], a[s], part);
-          }
+          for (int s = 0; s < EE; ++s) h[q][s] = nx[s];
+          if (q + 1 < ODD)
+            load(nx, sh, P, o, row, valid, t, resident, q + 1);
+          else if (o + 1 < sh.nops)
+            load(nx, sh, P, o + 1, row, valid, t, resident, 0);
+          else if (it + 1 < K)
+            load(nx, sh, P, 0, nrow, nvalid, t, resident, 0);
+          twiddle_in(h[q], w, tw_on);
+          fft(h[q], t, lds, stw);
         }
-#pragma unroll
-        for (int s = 0; s < EE; ++s) a[s] = nx[s];
+        odd_dft(h);
+        combine_fwd(acc, h, sh.ops[o], invN, part);
       }
-      if (sh.want_y) {
-        fft(acc, t, lds, stw);
-        store(acc, sh, P, 0, row, valid, t, false, w);
-      }
+      if (sh.want_y) output(acc, sh, P, 0, row, valid, t, lds, resident, stw, w);
       row = nrow;
       valid = nvalid;
     }
@@ -452,56 +515,47 @@ struct RowBody {
   static __device__ __forceinline__ void run_bwd(const Shape &sh, const PV &P, int64_t row, bool valid_row,
                                                  int t, cx<T> *lds, bool resident, const cx<T> *tw24,
                                                  const cx<T> *tw4096) {
-    const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
-    cx<T> a[EE], gq[EE];
+    const T invN = T(1) / T((int64_t)ODD << (sh.logR + sh.logC));
+    // Two spectra are live at a time: a (X's, then the grad_h spectrum, then
+    // H's) and gq (V's, then the grad_x factor), updated in place.
+    Seqs a, gq;
     cx<T> phc = czero<T>();  // conj(phi)
     if (P.phi()) phc = cconj(*(const cx<T> *)P.phi());
     const T m1 = T(sh.m - 1), m0 = T(sh.m);
     StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
     cx<T> w[EE];
-    bool tw_on;
-    {
-      cx<T> xs[EE], p1[EE], vs[EE];
-      load(xs, sh, P, 0, row, valid_row, t, resident);
-      stw.init(t, tw4096);
-      tw_on = twiddles(w, sh, row, t, resident, tw24, tw4096);
-      twiddle_in(xs, w, tw_on);
-      fft(xs, t, lds, stw);
+    const bool tw_on = twiddles(w, sh, row, t, resident, tw24, tw4096);
+    spectrum(a, sh, P, 0, row, valid_row, t, lds, resident, stw, w, tw_on);
+    const bool has_v = sh.nops > 1 && sh.ops[1].role == ROLE_V;
+    if (has_v) {
+      spectrum(gq, sh, P, 1, row, valid_row, t, lds, resident, stw, w, tw_on);
+    } else {
 #pragma unroll
-      for (int s = 0; s < EE; ++s) p1[s] = mk(T(1), T(0));
-      for (int e = 0; e < sh.m - 2; ++e) {
+      for (int q = 0; q < ODD; ++q)
 #pragma unroll
-        for (int s = 0; s < EE; ++s) p1[s] = cmul(p1[s], xs[s]);
-      }
-      const bool has_v = sh.nops > 1 && sh.ops[1].role == ROLE_V;
-      if (has_v) {
-        load(vs, sh, P, 1, row, valid_row, t, resident);
-        twiddle_in(vs, w, tw_on);
-        fft(vs, t, lds, stw);
-      } else {
+        for (int s = 0; s < EE; ++s) gq[q][s] = czero<T>();
+    }
 #pragma unroll
-        for (int s = 0; s < EE; ++s) vs[s] = czero<T>();
-      }
+    for (int q = 0; q < ODD; ++q)
 #pragma unroll
       for (int s = 0; s < EE; ++s) {
+        const cx<T> x = a[q][s], v = gq[q][s];
+        cx<T> p1 = mk(T(1), T(0));  // x^{m-2}
+        for (int e = 0; e < sh.m - 2; ++e) p1 = cmul(p1, x);
         // grad_x spectrum factor: x^{m-2} ((m-1) V + m conj(phi) x)
-        gq[s] = cmul(p1[s], cadd(cscale(vs[s], m1), cscale(cmul(phc, xs[s]), m0)));
+        gq[q][s] = cmul(p1, cadd(cscale(v, m1), cscale(cmul(phc, x), m0)));
         // grad_h spectrum: conj(x^{m-1} (V + conj(phi) x)) / N, transformed forward
-        a[s] = cscale(cconj(cmul(cmul(p1[s], xs[s]), cfma(phc, xs[s], vs[s]))), invN);
+        a[q][s] = cscale(cconj(cmul(cmul(p1, x), cfma(phc, x, v))), invN);
       }
-    }
-    if (sh.want_y) {
-      fft(a, t, lds, stw);
-      store(a, sh, P, 0, row, valid_row, t, resident, w);
-    }
+    if (sh.want_y) output(a, sh, P, 0, row, valid_row, t, lds, resident, stw, w);
     if (sh.want_out1) {
-      load(a, sh, P, sh.nops - 1, row, valid_row, t, resident);  // H
-      twiddle_in(a, w, tw_on);
-      fft(a, t, lds, stw);
+      spectrum(a, sh, P, sh.nops - 1, row, valid_row, t, lds, resident, stw, w, tw_on);  // H
 #pragma unroll
-      for (int s = 0; s < EE; ++s) a[s] = cmul(cscale(cconj(a[s]), invN), gq[s]);
-      fft(a, t, lds, stw);
-      store(a, sh, P, 1, row, valid_row, t, resident, w);
+      for (int q = 0; q < ODD; ++q)
+#pragma unroll
+        for (int s = 0; s < EE; ++s) a[q][s] = cmul(cscale(cconj(a[q][s]), invN), gq[q][s]);
+      output(a, sh, P, 1, row, valid_row, t, lds, resident, stw, w);
     }
   }
 };
@@ -509,7 +563,10 @@ struct RowBody {
 // ---------------------------------------------------------------------------
 // Column body: TW columns of length L (one sequence each), TPS lanes per
 // column, lane l -> column l % TW, position-lane l / TW (so that a wave
-// reads TW contiguous elements of several rows at once).
+// reads TW contiguous elements of several rows at once).  Columns are
+// numbered across the ODD sequences of a transform ("virtual" column
+// v = q R + c: storage column c of sequence q); a job transforms the first
+// job.ncols storage columns of every sequence.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int E>
 struct ColBody {
@@ -517,26 +574,45 @@ struct ColBody {
   static constexpr int EE = S::EE;
   static constexpr int TPS = S::TPS;
 
-  static __device__ __forceinline__ void run(const Shape &sh, const PV &P, const ColJob &job, int64_t c0,
+  // Byte offsets of the lane's slots in a length-N vector: positions
+  // p_s = c + R (t + s TPS) of sequence q, mapped to Z_N.
+  static __device__ __forceinline__ void vec_offsets(uint32_t (&off)[EE], const Shape &sh, int q, int64_t c,
+                                                     int64_t R, int t, int es) {
+    if (sh.odd > 1) {
+      int tau[EE];
+      crt_tau<EE>(tau, q, (uint32_t)(c + R * t), (uint32_t)(R * TPS), sh.odd, sh.odd_inv);
+      const int64_t M = seq_len(sh);
+#pragma unroll
+      for (int s = 0; s < EE; ++s) off[s] = (uint32_t)((c + R * (t + s * TPS) + M * tau[s]) * es);
+    } else {
+#pragma unroll
+      for (int s = 0; s < EE; ++s) off[s] = (uint32_t)((c + R * (t + s * TPS)) * es);
+    }
+  }
+
+  static __device__ __forceinline__ void run(const Shape &sh, const PV &P, const ColJob &job, int64_t v0,
                                              int TW, int tid, cx<T> *lds, const cx<T> *tw24,
                                              const cx<T> *tw4096) {
     const int cw = tid % TW;
     const int t = tid / TW;
-    const int64_t c = c0 + cw;
-    const bool cvalid = c < job.ncols;
+    const int64_t v = v0 + cw;
+    const int q = sh.odd > 1 ? (int)(v >> sh.logR) : 0;
     const int64_t R = (int64_t)1 << sh.logR;
+    const int64_t c = sh.odd > 1 ? (v & (R - 1)) : v;
+    const bool cvalid = c < job.ncols && q < sh.odd;
     cx<T> a[EE];
     uint32_t off[EE];
     constexpr int CB = (int)sizeof(cx<T>);
-    const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+    const int64_t M = seq_len(sh);
+    const int64_t N = fft_len(sh);
     if (job.kind == COL_A) {
       const OpDesc &od = sh.ops[job.op];
       const int es = elem_size<T>(od.flags);
       if (!sh.is_block) {
-        // element c + R k of the padded operand; past its end reads zero
+        // entry c + R k of the padded operand (sequence q of it); past its
+        // end reads zero
         const auto r = make_buf(P.op(job.op), od.len * es);
-#pragma unroll
-        for (int s = 0; s < EE; ++s) off[s] = (uint32_t)((c + R * (t + s * TPS)) * es);
+        vec_offsets(off, sh, q, c, R, t, es);
         bgather<T, EE>(a, r, off, od.flags);
       } else {
         // generating matrix (len rows x cols columns, column-major): row c,
@@ -551,7 +627,7 @@ struct ColBody {
     } else {
       const auto r = make_buf(ws_buf<T>(sh, P, job.buf), N * CB);
 #pragma unroll
-      for (int s = 0; s < EE; ++s) off[s] = (uint32_t)((c + R * (t + s * TPS)) * CB);
+      for (int s = 0; s < EE; ++s) off[s] = (uint32_t)((q * M + c + R * (t + s * TPS)) * CB);
       bgather<T, EE>(a, r, off, 0);
     }
     StageTw<T, L, E> stw;
@@ -562,30 +638,33 @@ struct ColBody {
     // a row segment of the tile is TW elements: whole lines stream out
     // (non-temporal), narrower ones merge in L2
     if (TW * CB >= 128)
-      store_tile<ST_NT>(a, sh, P, job, c, R, t, N);
+      store_tile<ST_NT>(a, sh, P, job, q, c, R, t);
     else
-      store_tile<ST_DEFAULT>(a, sh, P, job, c, R, t, N);
+      store_tile<ST_DEFAULT>(a, sh, P, job, q, c, R, t);
   }
 
   template <int POL>
   static __device__ __forceinline__ void store_tile(const cx<T> (&a)[EE], const Shape &sh, const PV &P,
-                                                    const ColJob &job, int64_t c, int64_t R, int t, int64_t N) {
+                                                    const ColJob &job, int q, int64_t c, int64_t R, int t) {
     constexpr int CB = (int)sizeof(cx<T>);
     if (job.kind == COL_A) {
-      const auto r = make_buf(ws_buf<T>(sh, P, job.buf), N * CB);
+      const int64_t M = seq_len(sh);
+      const auto r = make_buf(ws_buf<T>(sh, P, job.buf), fft_len(sh) * CB);
 #pragma unroll
-      for (int s = 0; s < EE; ++s) BufIO<T>::template st<POL>(a[s], r, off_ws(c, R, t + s * TPS));
+      for (int s = 0; s < EE; ++s)
+        BufIO<T>::template st<POL>(a[s], r, (uint32_t)((q * M + c + R * (t + s * TPS)) * CB));
     } else {
       void *dst = job.op == 0 ? P.y() : P.out1();
       const int es = sh.real_out ? (int)sizeof(T) : CB;
       if (!sh.is_block) {
-        // the slice [0, lim) is the resource: later positions are dropped
+        // the slice [0, lim) is the resource: later entries are dropped
         const int64_t lim = job.op == 0 ? sh.out_rows : sh.out1_len;
         const auto r = make_buf(dst, lim * es);
+        uint32_t off[EE];
+        vec_offsets(off, sh, q, c, R, t, es);
 #pragma unroll
         for (int s = 0; s < EE; ++s)
-          bstore<T, POL>(r, (uint32_t)((c + R * (t + s * TPS)) * es), job.conj_out ? cconj(a[s]) : a[s],
-                         sh.real_out);
+          bstore<T, POL>(r, off[s], job.conj_out ? cconj(a[s]) : a[s], sh.real_out);
       } else if (c < sh.out_rows) {
         // out_rows x out_cols corner, column-major; columns past out_cols fall
         // past the end of the resource
@@ -596,10 +675,6 @@ struct ColBody {
                          sh.real_out);
       }
     }
-  }
-
-  static __device__ __forceinline__ uint32_t off_ws(int64_t c, int64_t R, int k) {
-    return (uint32_t)((c + R * k) * (int64_t)sizeof(cx<T>));
   }
 };
 

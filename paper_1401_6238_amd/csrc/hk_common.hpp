@@ -1,9 +1,17 @@
 // Descriptors shared by the host planner and the device kernels.
 //
 // A product (1D Hankel or BHHB, forward or adjoint) is described by a Shape
-// (sizes, operand roles, FFT layout) plus per-instance pointers (Ptrs).  All
-// transforms are powers of two.  Data live on a 2D "storage grid" of
-// 2^logC rows of 2^logR contiguous elements:
+// (sizes, operand roles, FFT layout) plus per-instance pointers (Ptrs).  The
+// 1D transform length is N = odd * M with odd in {1, 3, 5} and M a power of
+// two.  For odd > 1 the cyclic group Z_N is handled as Z_odd x Z_M through
+// the Chinese-remainder map n -> (n mod odd, n mod M) (Good-Thomas prime
+// factor mapping, no twiddles between the two factors): the operands become
+// `odd` sequences of length M, each transformed by the power-of-two passes
+// below, and a length-odd DFT across the sequences, done in registers where
+// a lane holds the same bins of all of them, completes the transform.  The
+// products only need the transforms to diagonalize cyclic convolution, which
+// holds for any group isomorphic to Z_N.  Each sequence of length M lives on
+// a 2D "storage grid" of 2^logC rows of 2^logR contiguous elements:
 //   * 1D, one workgroup per transform ("resident"): logC = 0, the row is the
 //     whole padded vector of length N = 2^logR.
 //   * 1D, multipass: N = 2^logR * 2^logC, element n at n1 + R n2 with
@@ -58,6 +66,8 @@ struct Shape {
   int32_t real_out;    // store only the real part
   int32_t rows_per_wg; // multipass row pass: rows per workgroup (side by side)
   int32_t row_iters;   // multipass row pass: rows each lane group handles in turn
+  int32_t odd;         // odd factor of the 1D transform length (1, 3 or 5; 1 for BHHB)
+  int32_t odd_inv;     // M^{-1} mod odd (0 when odd == 1)
   int64_t out_rows;    // output slice: 1D length / BHHB rows n_1; adjoint grad_h length
   int64_t out_cols;    // BHHB columns N_1 (1 for 1D)
   int64_t out1_len;    // adjoint grad_x length
@@ -87,7 +97,7 @@ struct ColJob {
   int32_t op;
   int32_t buf;
   int32_t conj_out;
-  int64_t ncols;  // storage columns to transform (pruned)
+  int64_t ncols;  // storage columns to transform per sequence (pruned)
   int64_t npart;  // COL_D: pass-B partial sums to reduce into the scalar product (0: none)
 };
 

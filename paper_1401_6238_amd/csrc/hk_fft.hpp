@@ -1,5 +1,6 @@
-// Device building blocks: complex arithmetic, in-register DFTs and a
-// workgroup-level Stockham FFT for power-of-two lengths on gfx950.
+// Device building blocks: complex arithmetic, in-register DFTs (powers of
+// two up to 32, and the odd sizes 3 and 5) and a workgroup-level Stockham FFT
+// for power-of-two lengths on gfx950.
 //
 // Transform convention (the paper's Matlab-type fft, Section 2.1):
 //   X_k = sum_j x_j exp(-2 pi i j k / L).
@@ -128,6 +129,46 @@ __device__ __forceinline__ void dft(cx<T> (&v)[R]) {
     for (int k = 0; k < R; ++k) o[k] = v[bitrevc(k, bits)];
 #pragma unroll
     for (int k = 0; k < R; ++k) v[k] = o[k];
+  }
+}
+
+// In-register forward DFT of odd size Q in {1, 3, 5}, natural order:
+// X_k = sum_a v_a exp(-2 pi i a k / Q).  Written from the definition with the
+// symmetric pairs v_a +- v_{Q-a}, so that each output needs one real
+// constant per pair (Winograd-style short DFTs).
+template <typename T, int Q>
+__device__ __forceinline__ void dft_odd(cx<T> (&v)[Q]) {
+  static_assert(Q == 1 || Q == 3 || Q == 5, "odd factor");
+  if constexpr (Q == 3) {
+    const T c = T(0.866025403784438646763723170753);  // sin(2 pi / 3)
+    const cx<T> s = cadd(v[1], v[2]);
+    const cx<T> d = csub(v[1], v[2]);
+    const cx<T> m = mk(v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y);
+    // -i sin(2 pi / 3) d
+    const cx<T> r = mk(c * d.y, -c * d.x);
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+  } else if constexpr (Q == 5) {
+    const T c1 = T(0.309016994374947424102293417183);   // cos(2 pi / 5)
+    const T c2 = T(-0.809016994374947424102293417183);  // cos(4 pi / 5)
+    const T s1 = T(0.951056516295153572116439333379);   // sin(2 pi / 5)
+    const T s2 = T(0.587785252292473129168705954639);   // sin(4 pi / 5)
+    const cx<T> a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    const cx<T> a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    // real-weighted sums of the pairs
+    const cx<T> m1 = mk(v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y);
+    const cx<T> m2 = mk(v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y);
+    // odd parts: u1 = s1 b1 + s2 b2, u2 = s2 b1 - s1 b2; outputs take -i u
+    const cx<T> u1 = mk(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y);
+    const cx<T> u2 = mk(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y);
+    const cx<T> r1 = mk(u1.y, -u1.x);
+    const cx<T> r2 = mk(u2.y, -u2.x);
+    v[0] = mk(v[0].x + a1.x + a2.x, v[0].y + a1.y + a2.y);
+    v[1] = cadd(m1, r1);
+    v[4] = csub(m1, r1);
+    v[2] = cadd(m2, r2);
+    v[3] = csub(m2, r2);
   }
 }
 

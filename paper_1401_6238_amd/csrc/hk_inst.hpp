@@ -82,6 +82,7 @@ static KernelLimits lim_of() {
   k.seq_lds = S::ROW_SEQ;
   k.lds_raw = S::LDS;
   k.elem_bytes = (int)sizeof(cx<T>);
+  k.row_maxt = ROW_MAXT;
   return k;
 }
 

@@ -26,11 +26,11 @@ struct ColJobs {
   int32_t xcd;  // 1: XCD-local tile numbering (xcd_local_tile)
 };
 
-// Rows of length L: resident instances (blockIdx.x * rows + rw) or pass-B
-// rows of instance blockIdx.y.
-template <int L, int E, int MAXT, int PROG>
+// Rows of length L (ODD sequences each): resident instances
+// (blockIdx.x * rows + rw) or pass-B rows of instance blockIdx.y.
+template <int L, int E, int MAXT, int PROG, int ODD = 1>
 __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, int64_t count) {
-  using RB = RowBody<T, L, E>;
+  using RB = RowBody<T, L, E, ODD>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *smem = (cx<T> *)smem_raw;
   const int tid = threadIdx.x;
@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
       }
       return;
     }
-    const cx<T> part = RB::run_fwd_rows(sh, P, row0, rows, K, t, lds, g_tw24, g_tw4096);
+    const cx<T> part = RB::run_fwd_rows(sh, P, row0, rows, K, true, t, lds, false, g_tw24, g_tw4096);
     if (sh.want_alpha) {
       // One partial sum per workgroup; the next kernel in the stream (pass D
       // or the reduction kernel) adds them in index order.  No cross-workgroup
@@ -89,12 +89,14 @@ __device__ __forceinline__ void reduce_partials(const Shape &sh, const PV &P, in
   if (tid == 0) store_out<T>(P.alpha(), 0, tot, sh.real_out);
 }
 
+#ifndef HK_ROWS_ONLY
 // Scalar-only products: sums the pass-B partials (grid.x = instances).
 __global__ void __launch_bounds__(256) k_alpha(Shape sh, Ptrs p0, Strides str, int64_t count) {
   __shared__ cx<T> red[256];
   const PV P{&p0, &str, (int64_t)blockIdx.x, nullptr};
   reduce_partials(sh, P, count, red);
 }
+#endif
 
 // Workgroups are dealt to the eight XCDs round-robin by linear id.  The
 // column passes renumber them so that each XCD runs one contiguous eighth of
@@ -125,15 +127,23 @@ __global__ void __launch_bounds__(MAXT) k_cols(Shape sh, Ptrs p0, Strides str, C
   const Tile3 b = jobs.xcd ? xcd_local_tile() : Tile3{blockIdx.x, blockIdx.y, blockIdx.z};
   const ColJob &job = jobs.j[b.y];
   const int TW = blockDim.x / CB::TPS;
-  const int64_t c0 = (int64_t)b.x * TW;
+  const int64_t v0 = (int64_t)b.x * TW;  // first virtual column of the tile
   const PV P{&p0, &str, (int64_t)b.z, nullptr};
   if (job.kind == COL_D && job.npart > 0 && b.x == 0 && b.y == 0) {
     // the scalar product rides on the first pass-D workgroup
     reduce_partials(sh, P, job.npart, smem);
     __syncthreads();
   }
-  if (c0 >= job.ncols) return;
-  CB::run(sh, P, job, c0, TW, threadIdx.x, smem, g_tw24, g_tw4096);
+  if (sh.odd > 1) {
+    // tiles over the odd * R virtual columns; a tile inside one sequence
+    // whose storage columns are all pruned has nothing to do
+    const int64_t R = (int64_t)1 << sh.logR;
+    if (v0 >= (int64_t)sh.odd * R) return;
+    if (TW <= R && (v0 & (R - 1)) >= job.ncols) return;
+  } else if (v0 >= job.ncols) {
+    return;
+  }
+  CB::run(sh, P, job, v0, TW, threadIdx.x, smem, g_tw24, g_tw4096);
 }
 
 }  // namespace HK_NS
@@ -147,19 +157,26 @@ namespace HK_NS {
 // and resident instances; pass B row blocks; scalar sums and pass D column
 // tiles.  Tasks of one phase are independent; a phase reads only what
 // earlier phases wrote.  Two schedules run them:
-//  * grouped launches (k_group): per phase, one kernel per (kind, length);
-//    the stream orders the phases;
-//  * one persistent launch (k_batch): resident workgroups pull the tasks of a
-//    phase from a queue and meet in a grid-wide barrier before the next
-//    phase.  The grid never exceeds the workgroups the device can hold at
-//    once, and every barrier wait is bounded: past the bound the error word
-//    is set and the kernel still runs to its end.
+//  * grouped launches (k_group): per phase, one kernel per (kind, length,
+//    odd factor); the stream orders the phases;
+//  * one persistent launch (k_batch, power-of-two lengths only): resident
+//    workgroups pull the tasks of a phase from a queue and meet in a
+//    grid-wide barrier before the next phase.  The grid never exceeds the
+//    workgroups the device can hold at once, and every barrier wait is
+//    bounded: past the bound the error word is set and the kernel still
+//    runs to its end.
 // ---------------------------------------------------------------------------
 enum : int { BATCH_BLK = 512, BATCH_E_ROW = 8, BATCH_E_COL = sizeof(T) == 4 ? 16 : 8 };
+// Elements per lane of the batched row bodies: a lane of an odd-factor row
+// holds ODD sequences, so it takes 4 to stay within registers.
+template <int ODD>
+struct BatchRowE {
+  static constexpr int value = ODD > 1 ? 4 : BATCH_E_ROW;
+};
 
-template <int L>
+template <int L, int ODD = 1>
 __device__ __forceinline__ void batch_res_body(const BatchArgs &A, const Task &tk, cx<T> *smem, int tid) {
-  using RB = RowBody<T, L, BATCH_E_ROW>;
+  using RB = RowBody<T, L, BatchRowE<ODD>::value, ODD>;
   const int rw = tid / RB::TPS;
   const int t = tid % RB::TPS;
   const bool valid = rw < tk.a;
@@ -173,10 +190,10 @@ __device__ __forceinline__ void batch_res_body(const BatchArgs &A, const Task &t
   }
 }
 
-template <int L>
+template <int L, int ODD = 1>
 __device__ __forceinline__ void batch_rowb_body(const BatchArgs &A, const Task &tk, const Shape &sh, const PV &P,
                                                 cx<T> *smem, int tid) {
-  using RB = RowBody<T, L, BATCH_E_ROW>;
+  using RB = RowBody<T, L, BatchRowE<ODD>::value, ODD>;
   const int rw = tid / RB::TPS;
   const int t = tid % RB::TPS;
   const int64_t row = (int64_t)tk.a + rw;
@@ -210,6 +227,7 @@ __device__ __forceinline__ void batch_col_body(const Task &tk, const Shape &sh, 
   CB::run(sh, P, job, tk.b, TW, tid, smem, g_tw24, g_tw4096);  // LDS sized by batch_geometry
 }
 
+#ifndef HK_ROWS_ONLY
 // The persistent kernel calls the bodies out of line, so that its register
 // allocation is the largest body's rather than the sum over the switch.
 template <int L>
@@ -304,13 +322,14 @@ __global__ void __launch_bounds__(BATCH_BLK) k_batch(BatchArgs A) {
     begin = end;
   }
 }
+#endif  // HK_ROWS_ONLY
 
-// Grouped launches: the tasks of one phase that share a kind and a transform
-// length L run in one launch of a kernel specialised for them (one task per
-// workgroup, A.order[A.begin + blockIdx.x]), so that each gets the registers
-// and LDS of its own length instead of the largest one's.  Phases are
+// Grouped launches: the tasks of one phase that share a kind, a transform
+// length L and an odd factor run in one launch of a kernel specialised for
+// them (one task per workgroup, A.order[A.begin + blockIdx.x]), so that each
+// gets the registers and LDS of its own length instead of the largest one's.  Phases are
 // ordered by the stream; no counters or waits are involved.
-template <int L, int KIND>
+template <int L, int KIND, int ODD = 1>
 __global__ void __launch_bounds__(BATCH_BLK) k_group(BatchArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *smem = (cx<T> *)smem_raw;
@@ -318,12 +337,12 @@ __global__ void __launch_bounds__(BATCH_BLK) k_group(BatchArgs A) {
   const int32_t ti = A.order[A.begin + (int32_t)blockIdx.x];
   const Task tk = A.tasks[ti];
   if (KIND == GK_RES) {
-    batch_res_body<L>(A, tk, smem, tid);
+    batch_res_body<L, ODD>(A, tk, smem, tid);
   } else {
     const Shape &sh = A.shapes[tk.inst];
     const PV P{&A.ptrs[tk.inst], nullptr, 0, A.ws_base};
     if (KIND == GK_ROWB)
-      batch_rowb_body<L>(A, tk, sh, P, smem, tid);
+      batch_rowb_body<L, ODD>(A, tk, sh, P, smem, tid);
     else if (KIND == GK_COL)
       batch_col_body<L>(tk, sh, P, smem, tid);
     else
@@ -340,6 +359,7 @@ __global__ void __launch_bounds__(256) k_copy_cols(V *out, const int32_t *pairs,
     out[dst * rows + i] = out[src * rows + i];
 }
 
+#ifndef HK_ROWS_ONLY
 // Zeroes the persistent schedule's control block (a plain kernel rather than
 // a memset node, so that graph replays stay exact).
 __global__ void k_batch_reset(BatchCtl *bctl) {
@@ -350,6 +370,7 @@ __global__ void k_batch_reset(BatchCtl *bctl) {
   }
   if (i == 0) bctl->error = 0;
 }
+#endif
 
 }  // namespace HK_NS
 }  // namespace hk

@@ -1,5 +1,7 @@
 // Host-side interface between the C-ABI layer and the per-precision kernel
-// translation units (hk_f32.hip, hk_f64.hip).
+// translation units (hk_f32.hip, hk_f64.hip: power-of-two lengths and all
+// column kernels; hk_f32_odd.hip, hk_f64_odd.hip: rows of lengths 3 * 2^k and
+// 5 * 2^k).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -15,6 +17,7 @@ struct KernelLimits {
   int seq_lds;     // LDS elements per row sequence
   int lds_raw;     // LDS elements one sequence's exchanges need (0: no exchange)
   int elem_bytes;  // bytes per complex element
+  int row_maxt;    // most lanes of a plain row-kernel workgroup
 };
 
 // Every kernel launch goes through here.  While per-kernel profiling is on,
@@ -42,5 +45,18 @@ hipError_t launch_kernel(const void *fn, dim3 grid, dim3 block, void **args, siz
 
 HK_DECLARE_LAUNCHERS(f32)
 HK_DECLARE_LAUNCHERS(f64)
+
+#define HK_DECLARE_ODD_LAUNCHERS(SUFFIX)                                                                  \
+  hipError_t init_tables_odd_##SUFFIX(const double *tw4096_interleaved, const double *tw24_interleaved);  \
+  bool limits_odd_##SUFFIX(int odd, int logL, int E, KernelLimits *out);                                \
+  int odd_row_e_##SUFFIX();                                                                             \
+  bool odd_bwd_ok_##SUFFIX(int odd);                                                                    \
+  hipError_t launch_rows_odd_##SUFFIX(int odd, int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh, \
+                                      const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st);   \
+  hipError_t launch_group_odd_##SUFFIX(const BatchArgs &args, int odd, int kind, int logL, int ntasks,     \
+                                       hipStream_t st);
+
+HK_DECLARE_ODD_LAUNCHERS(f32)
+HK_DECLARE_ODD_LAUNCHERS(f64)
 
 }  // namespace hk

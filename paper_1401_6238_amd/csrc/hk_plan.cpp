@@ -100,23 +100,66 @@ Status validate_backward(const Problem &p) {
 // ---------------------------------------------------------------------------
 // Layout
 // ---------------------------------------------------------------------------
-Status layout_for(const Problem &p, int split, Layout *out) {
+bool row_limits(hk_dtype_t dt, int odd, int logL, int E, KernelLimits *k) {
+  if (odd == 1) return is_double(dt) ? limits_f64(logL, E, k) : limits_f32(logL, E, k);
+  return is_double(dt) ? limits_odd_f64(odd, logL, E, k) : limits_odd_f32(odd, logL, E, k);
+}
+
+static int odd_row_e(hk_dtype_t dt) { return is_double(dt) ? odd_row_e_f64() : odd_row_e_f32(); }
+
+// Longest row (log2) the row kernels of odd factor `odd` handle in this
+// precision and program (-1: none).
+static int odd_max_logl(hk_dtype_t dt, int odd, int prog) {
+  if (prog == PROG_BWD && !(is_double(dt) ? odd_bwd_ok_f64(odd) : odd_bwd_ok_f32(odd))) return -1;
+  KernelLimits k;
+  int best = -1;
+  for (int l = 0; l <= MAX_LOGL; ++l)
+    if (row_limits(dt, odd, l, odd_row_e(dt), &k)) best = l;
+  return best;
+}
+
+// Split of a power-of-two sequence of length 2^logM into rows of 2^logR and
+// columns of 2^logC: logR = ceil(logM / 2) + split, clamped so that rows are
+// at most 2^maxR and columns at most 2^MAX_LOGL.
+static bool split_of(int logM, int split, int maxR, int *logR, int *logC) {
+  int r = (logM + 1) / 2 + split;
+  r = std::max<int>(logM - MAX_LOGL, std::min<int>(maxR, r));
+  if (r < 0 || r > maxR || logM - r > MAX_LOGL || logM - r < 0) return false;
+  *logR = r;
+  *logC = logM - r;
+  return true;
+}
+
+Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd) {
   Layout lay;
   if (!p.is_block) {
     int64_t dh = 1 - p.m;
     for (int q = 0; q < p.m; ++q) dh += p.dims[q];
-    const int logN = ceil_log2(dh);
-    if (logN > HK_MAX_FFT_LOG2) return fail(HK_ERR_SIZE_LIMIT, "padded length exceeds 2^24");
-    if (logN <= RES_MAX_LOG) {
-      lay.resident = true;
-      lay.logR = logN;
-      lay.logC = 0;
-    } else {
-      int logR = (logN + 1) / 2 + split;
-      logR = std::max<int>(logN - MAX_LOGL, std::min<int>(MAX_LOGL, logR));
-      lay.logR = logR;
-      lay.logC = logN - logR;
+    if (ceil_log2(dh) > HK_MAX_FFT_LOG2) return fail(HK_ERR_SIZE_LIMIT, "padded length exceeds 2^24");
+    // The smallest N = odd * 2^logM >= d_H among the lengths with kernels.
+    int64_t bestN = -1;
+    for (int odd : {1, 3, 5}) {
+      const int omax = odd == 1 ? MAX_LOGL : (allow_odd ? odd_max_logl(p.dt, odd, p.prog) : -1);
+      if (omax < 0) continue;
+      int logM = 0;
+      while (((int64_t)odd << logM) < dh) ++logM;
+      const int64_t N = (int64_t)odd << logM;
+      if (N > ((int64_t)1 << HK_MAX_FFT_LOG2)) continue;
+      if (bestN >= 0 && N >= bestN) continue;
+      Layout c;
+      c.odd = odd;
+      const int res_max = odd == 1 ? RES_MAX_LOG : omax;
+      if (logM <= res_max) {
+        c.resident = true;
+        c.logR = logM;
+        c.logC = 0;
+      } else if (!split_of(logM, split, omax, &c.logR, &c.logC)) {
+        continue;
+      }
+      lay = c;
+      bestN = N;
     }
+    if (bestN < 0) return fail(HK_ERR_SIZE_LIMIT, "no transform length with kernels for this d_H");
   } else {
     int64_t rows = 1 - p.m, cols = 1 - p.m;
     for (int q = 0; q < p.m; ++q) {
@@ -148,6 +191,13 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
   sh.logR = lay.logR;
   sh.logC = lay.logC;
   sh.resident = lay.resident ? 1 : 0;
+  sh.odd = lay.odd;
+  sh.odd_inv = 0;
+  if (lay.odd > 1) {
+    const int mr = (int)((((int64_t)1) << (lay.logR + lay.logC)) % lay.odd);
+    for (int v = 1; v < lay.odd; ++v)
+      if ((mr * v) % lay.odd == 1) sh.odd_inv = v;
+  }
   sh.real_out = is_complex(p.dt) ? 0 : 1;
   const int real_flag = is_complex(p.dt) ? 0 : OPF_REAL;
   const int64_t R = (int64_t)1 << lay.logR;
@@ -235,7 +285,8 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
     sh.nbuf = sh.nops;
     sh.partials = (int64_t)1 << MAX_LOGL;
     const size_t eb = cplx_bytes(p.dt);
-    const size_t bytes = (size_t)sh.nbuf * ((size_t)1 << (lay.logR + lay.logC)) * eb + (size_t)sh.partials * eb + 16;
+    const size_t bytes =
+        (size_t)sh.nbuf * ((size_t)lay.odd << (lay.logR + lay.logC)) * eb + (size_t)sh.partials * eb;
     sh.ws_bytes = (int64_t)((bytes + 255) & ~(size_t)255);
   }
   *shp = sh;
@@ -254,8 +305,8 @@ static bool lim(hk_dtype_t dt, int logL, int E, KernelLimits *k) {
 
 bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
   KernelLimits kr, kc;
-  if (!lim(dt, lay.logR, sc.E_row, &kr)) return false;
-  if (sc.rows_per_wg < 1 || sc.rows_per_wg * kr.tps > ROW_MAXT) return false;
+  if (!row_limits(dt, lay.odd, lay.logR, sc.E_row, &kr)) return false;
+  if (sc.rows_per_wg < 1 || sc.rows_per_wg * kr.tps > kr.row_maxt) return false;
   const size_t row_lds = std::max((size_t)sc.rows_per_wg * kr.seq_lds, (size_t)sc.rows_per_wg * kr.tps) * kr.elem_bytes;
   if (row_lds > 160 * 1024) return false;
   if (sc.iters != 1 && (lay.resident || (sc.iters != 2 && sc.iters != 4))) return false;
@@ -270,20 +321,20 @@ bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
 Sched default_sched(hk_dtype_t dt, const Layout &lay, int prog, int64_t batch) {
   Sched sc;
   const bool dbl = is_double(dt);
-  sc.E_row = 8;
+  sc.E_row = lay.odd > 1 ? odd_row_e(dt) : 8;
   sc.E_col = dbl ? 8 : 16;
   KernelLimits kr, kc;
-  lim(dt, lay.logR, sc.E_row, &kr);
-  if (kr.tps > ROW_MAXT) {  // 4096-point rows need 16 elements per lane
+  row_limits(dt, lay.odd, lay.logR, sc.E_row, &kr);
+  if (lay.odd == 1 && kr.tps > ROW_MAXT) {  // 4096-point rows need 16 elements per lane
     sc.E_row = 16;
     lim(dt, lay.logR, sc.E_row, &kr);
   }
   if (lay.resident) {
     // One instance per row; pack rows up to 256 lanes when batched.
-    const int max_rows = std::max(1, ROW_MAXT / kr.tps);
+    const int max_rows = std::max(1, std::min((int)ROW_MAXT, kr.row_maxt) / kr.tps);
     sc.rows_per_wg = (int)std::max<int64_t>(1, std::min<int64_t>(max_rows, batch));
   } else {
-    sc.rows_per_wg = std::max(1, std::min(ROW_MAXT / kr.tps, 1 << lay.logC));
+    sc.rows_per_wg = std::max(1, std::min(std::min((int)ROW_MAXT, kr.row_maxt) / kr.tps, 1 << lay.logC));
     lim(dt, lay.logC, sc.E_col, &kc);
     const int want_tw = dbl ? 8 : 16;  // 128-byte row segments
     int tw = std::max(1, std::min(want_tw, COL_MAXT / kc.tps));
@@ -382,8 +433,13 @@ static hipError_t rows(hk_dtype_t dt, int logL, int E, int rpw, dim3 g, const Sh
                        const Strides &str, int64_t cnt, hipStream_t st) {
   count_launch();
   prof_before(st);
-  const hipError_t e = is_double(dt) ? launch_rows_f64(logL, E, rpw, g, sh, p0, str, cnt, st)
-                                     : launch_rows_f32(logL, E, rpw, g, sh, p0, str, cnt, st);
+  hipError_t e;
+  if (sh.odd > 1)
+    e = is_double(dt) ? launch_rows_odd_f64(sh.odd, logL, E, rpw, g, sh, p0, str, cnt, st)
+                      : launch_rows_odd_f32(sh.odd, logL, E, rpw, g, sh, p0, str, cnt, st);
+  else
+    e = is_double(dt) ? launch_rows_f64(logL, E, rpw, g, sh, p0, str, cnt, st)
+                      : launch_rows_f32(logL, E, rpw, g, sh, p0, str, cnt, st);
   prof_after(sh.resident ? PK_RESIDENT : PK_PASS_B, st);
   return e;
 }
@@ -427,7 +483,9 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
     ja[o].ncols = sh.ops[o].ncol_nz;
     max_cols = std::max(max_cols, ja[o].ncols);
   }
-  dim3 ga((unsigned)((max_cols + sc.tw - 1) / sc.tw), (unsigned)sh.nops, (unsigned)count);
+  // tiles over the storage columns of every sequence (virtual columns)
+  const int64_t vcols_a = sh.odd > 1 ? sh.odd * R : max_cols;
+  dim3 ga((unsigned)((vcols_a + sc.tw - 1) / sc.tw), (unsigned)sh.nops, (unsigned)count);
   e = cols(dt, sh.logC, sc.E_col, sc.tw, sc.xcd, ga, sh, p0, str, ja, sh.nops, st);
   if (e != hipSuccess) return hip_fail(e, "pass A launch");
   // Pass B: row transforms, spectral product, row transform of the output.
@@ -462,7 +520,8 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
     ++nd;
   }
   if (nd > 0) {
-    dim3 gd((unsigned)((dcols + sc.tw - 1) / sc.tw), (unsigned)nd, (unsigned)count);
+    const int64_t vcols_d = sh.odd > 1 ? sh.odd * R : dcols;
+    dim3 gd((unsigned)((vcols_d + sc.tw - 1) / sc.tw), (unsigned)nd, (unsigned)count);
     e = cols(dt, sh.logC, sc.E_col, sc.tw, sc.xcd, gd, sh, p0, str, jd, nd, st);
     if (e != hipSuccess) return hip_fail(e, "pass D launch");
   } else if (npart > 0) {
@@ -526,6 +585,8 @@ Status ensure_device() {
   twiddle_tables(a, b);
   e = init_tables_f32(a.data(), b.data());
   if (e == hipSuccess) e = init_tables_f64(a.data(), b.data());
+  if (e == hipSuccess) e = init_tables_odd_f32(a.data(), b.data());
+  if (e == hipSuccess) e = init_tables_odd_f64(a.data(), b.data());
   if (e != hipSuccess) return hip_fail(e, "twiddle table upload");
   state[dev] = 1;
   return Status();
@@ -534,30 +595,34 @@ Status ensure_device() {
 // ---------------------------------------------------------------------------
 // Schedule cache
 // ---------------------------------------------------------------------------
-using SchedKey = std::tuple<int, int, int, int, int, int>;
+using SchedKey = std::tuple<int, int, int, int, int, int, int>;
 static std::mutex g_sched_mu;
 static std::map<SchedKey, Sched> g_sched;
 
 static int batch_class(int64_t b) { return b <= 1 ? 0 : (b < 16 ? 1 : 2); }
 
-bool sched_lookup(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint, int64_t batch, Sched *sc) {
+bool sched_lookup(hk_dtype_t dt, int prog, int is_block, int odd, int logM, int logC_hint, int64_t batch,
+                  Sched *sc) {
   std::lock_guard<std::mutex> lk(g_sched_mu);
-  auto it = g_sched.find(SchedKey((int)dt, prog, is_block, logN, logC_hint, batch_class(batch)));
+  auto it = g_sched.find(SchedKey((int)dt, prog, is_block, odd, logM, logC_hint, batch_class(batch)));
   if (it == g_sched.end()) return false;
   *sc = it->second;
   return true;
 }
 
-void sched_store(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint, int64_t batch, const Sched &sc) {
+void sched_store(hk_dtype_t dt, int prog, int is_block, int odd, int logM, int logC_hint, int64_t batch,
+                 const Sched &sc) {
   std::lock_guard<std::mutex> lk(g_sched_mu);
-  g_sched[SchedKey((int)dt, prog, is_block, logN, logC_hint, batch_class(batch))] = sc;
+  g_sched[SchedKey((int)dt, prog, is_block, odd, logM, logC_hint, batch_class(batch))] = sc;
 }
 
 // Text database, one schedule per line:
-//   dtype prog is_block logN logC_hint batch_class : E_row rows_per_wg E_col tw split xcd iters
-// (xcd and iters may be omitted: 0 and 1).  '#' starts a comment line.
+//   dtype prog is_block odd logM logC_hint batch_class : E_row rows_per_wg E_col tw split xcd iters
+// (logM = log2 of the power-of-two factor of the transform length; xcd and
+// iters may be omitted: 0 and 1).  Lines with six key fields (no odd factor)
+// are read as odd = 1.  '#' starts a comment line.
 static const char *kDbHeader =
-    "# hankel schedule database v3: dt prog blk logN logC bclass : E_row rows E_col tw split xcd iters\n";
+    "# hankel schedule database v4: dt prog blk odd logM logC bclass : E_row rows E_col tw split xcd iters\n";
 
 Status sched_save(const char *path) {
   if (!path) return fail(HK_ERR_NULL_POINTER, "path is NULL");
@@ -568,9 +633,9 @@ Status sched_save(const char *path) {
   for (const auto &kv : g_sched) {
     const SchedKey &k = kv.first;
     const Sched &s = kv.second;
-    fprintf(f, "%d %d %d %d %d %d : %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
-            std::get<3>(k), std::get<4>(k), std::get<5>(k), s.E_row, s.rows_per_wg, s.E_col, s.tw, s.split, s.xcd,
-            s.iters);
+    fprintf(f, "%d %d %d %d %d %d %d : %d %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+            std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), s.E_row, s.rows_per_wg, s.E_col, s.tw,
+            s.split, s.xcd, s.iters);
   }
   const bool ok = fclose(f) == 0;
   return ok ? Status() : fail(HK_ERR_INVALID_VALUE, std::string("error writing ") + path);
@@ -587,16 +652,34 @@ Status sched_load(const char *path, int *loaded) {
   while (fgets(line, sizeof(line), f)) {
     ++lineno;
     if (line[0] == '#' || line[0] == '\n') continue;
-    int k[6], v[7] = {0, 0, 0, 0, 0, 0, 1};
-    const int got = sscanf(line, "%d %d %d %d %d %d : %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4],
-                           &k[5], &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6]);
-    if (got < 11 || got > 13) {
+    char *colon = strchr(line, ':');
+    int k[7] = {0, 0, 0, 1, 0, 0, 0}, v[7] = {0, 0, 0, 0, 0, 0, 1};
+    int nk = -1, nv = -1;
+    if (colon) {
+      *colon = 0;
+      int t[8];
+      nk = sscanf(line, "%d %d %d %d %d %d %d %d", &t[0], &t[1], &t[2], &t[3], &t[4], &t[5], &t[6], &t[7]);
+      if (nk == 7) {
+        for (int i = 0; i < 7; ++i) k[i] = t[i];
+      } else if (nk == 6) {  // no odd factor: power-of-two length
+        k[0] = t[0];
+        k[1] = t[1];
+        k[2] = t[2];
+        k[3] = 1;
+        k[4] = t[3];
+        k[5] = t[4];
+        k[6] = t[5];
+      }
+      int extra = 0;
+      nv = sscanf(colon + 1, "%d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &extra);
+    }
+    if ((nk != 6 && nk != 7) || nv < 5 || nv > 7) {
       st = fail(HK_ERR_INVALID_VALUE, std::string(path) + ": malformed line " + std::to_string(lineno));
       break;
     }
     const bool key_ok = k[0] >= HK_C64 && k[0] <= HK_F64 && (k[1] == PROG_FWD || k[1] == PROG_BWD) &&
-                        (k[2] == 0 || k[2] == 1) && k[3] >= 0 && k[3] <= HK_MAX_FFT_LOG2 && k[4] >= -1 &&
-                        k[4] <= HK_MAX_FFT_LOG2 && k[5] >= 0 && k[5] <= 2;
+                        (k[2] == 0 || k[2] == 1) && (k[3] == 1 || k[3] == 3 || k[3] == 5) && k[4] >= 0 &&
+                        k[4] <= HK_MAX_FFT_LOG2 && k[5] >= -1 && k[5] <= HK_MAX_FFT_LOG2 && k[6] >= 0 && k[6] <= 2;
     Sched s;
     s.E_row = v[0];
     s.rows_per_wg = v[1];
@@ -606,14 +689,14 @@ Status sched_load(const char *path, int *loaded) {
     s.xcd = v[5];
     s.iters = v[6];
     // entries are re-checked against the kernel limits when used (sched_valid)
-    const bool val_ok = (s.E_row == 8 || s.E_row == 16) && (s.E_col == 8 || s.E_col == 16) && s.rows_per_wg >= 1 &&
-                        s.rows_per_wg <= 64 && s.tw >= 1 && s.tw <= 64 && s.split >= -4 && s.split <= 4 &&
-                        (s.xcd == 0 || s.xcd == 1) && (s.iters == 1 || s.iters == 2 || s.iters == 4);
+    const bool val_ok = (s.E_row == 4 || s.E_row == 8 || s.E_row == 16) && (s.E_col == 8 || s.E_col == 16) &&
+                        s.rows_per_wg >= 1 && s.rows_per_wg <= 64 && s.tw >= 1 && s.tw <= 64 && s.split >= -4 &&
+                        s.split <= 4 && (s.xcd == 0 || s.xcd == 1) && (s.iters == 1 || s.iters == 2 || s.iters == 4);
     if (!key_ok || !val_ok) {
       st = fail(HK_ERR_INVALID_VALUE, std::string(path) + ": value out of range on line " + std::to_string(lineno));
       break;
     }
-    add[SchedKey(k[0], k[1], k[2], k[3], k[4], k[5])] = s;
+    add[SchedKey(k[0], k[1], k[2], k[3], k[4], k[5], k[6])] = s;
   }
   fclose(f);
   if (!st.ok()) return st;

@@ -59,6 +59,7 @@ struct Sched {
 
 struct Layout {
   bool resident = false;
+  int odd = 1;  // 1D: transform length odd * 2^(logR + logC)
   int logR = 0, logC = 0;
 };
 
@@ -71,8 +72,12 @@ int ceil_log2(int64_t v);
 Status validate_forward(const Problem &p);
 Status validate_backward(const Problem &p);
 
-// Shape construction.  `layout` decides resident vs multipass and the split.
-Status layout_for(const Problem &p, int split, Layout *out);
+// Shape construction.  `layout` decides the transform length (the smallest
+// 2^k, 3 * 2^k or 5 * 2^k >= d_H with kernels; powers of two only when
+// allow_odd is false), resident vs multipass and the split.
+Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd = true);
+// Row-kernel limits of a layout's row length (odd factor aware).
+bool row_limits(hk_dtype_t dt, int odd, int logL, int E, KernelLimits *k);
 Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *sh, Ptrs *ptrs,
                    int op_src[MAXOPS]);
 
@@ -93,8 +98,10 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
 Status ensure_device();
 
 // Schedule cache (autotuner).
-bool sched_lookup(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint, int64_t batch, Sched *sc);
-void sched_store(hk_dtype_t dt, int prog, int is_block, int logN, int logC_hint, int64_t batch, const Sched &sc);
+bool sched_lookup(hk_dtype_t dt, int prog, int is_block, int odd, int logM, int logC_hint, int64_t batch,
+                  Sched *sc);
+void sched_store(hk_dtype_t dt, int prog, int is_block, int odd, int logM, int logC_hint, int64_t batch,
+                 const Sched &sc);
 Status sched_save(const char *path);
 Status sched_load(const char *path, int *loaded);
 

@@ -43,7 +43,9 @@ def ws(L, dt, m, n):
 def test_workspace_sizes(L):
     assert ws(L, HK_C64, 3, 64) == (OK, 0)          # resident: no workspace
     rc, b = ws(L, HK_C64, 4, 1 << 18)               # N = 2^20, two buffers
-    assert rc == OK and b == ((2 * (1 << 20) * 8 + 4096 * 8 + 16 + 255) // 256) * 256
+    assert rc == OK and b == ((2 * (1 << 20) * 8 + 4096 * 8 + 255) // 256) * 256
+    rc, b3 = ws(L, HK_C64, 3, 65536)                # d_H = 196606 -> N = 3 * 2^16
+    assert rc == OK and b3 == ((2 * 3 * (1 << 16) * 8 + 4096 * 8 + 255) // 256) * 256
     rc, b128 = ws(L, HK_C128, 4, 1 << 18)
     assert rc == OK and b128 > b
 
@@ -116,13 +118,40 @@ def test_plan_argument_errors(L):
     assert L.hk_plan_create(None, HK_C64, None, 0, 1) == NULLP
 
 
-def test_fft_layout(L):
+def fft_layout(L, d):
     a, r, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    assert L.hk_fft_layout(1048573, ctypes.byref(a), ctypes.byref(r), ctypes.byref(c)) == OK
-    assert (a.value, r.value * c.value) == (1 << 20, 1 << 20)
-    assert L.hk_fft_layout(190, ctypes.byref(a), ctypes.byref(r), ctypes.byref(c)) == OK
-    assert (a.value, r.value, c.value) == (256, 256, 1)   # one workgroup holds it
-    assert L.hk_fft_layout(0, ctypes.byref(a), ctypes.byref(r), ctypes.byref(c)) == INVALID
+    assert L.hk_fft_layout(d, ctypes.byref(a), ctypes.byref(r), ctypes.byref(c)) == OK
+    return a.value, r.value, c.value
+
+
+def smooth_lengths(d):
+    """Every length 2^k, 3 * 2^k, 5 * 2^k that is >= d (brute force)."""
+    out = []
+    for odd in (1, 3, 5):
+        k = 0
+        while odd << k < d:
+            k += 1
+        out.append(odd << k)
+    return out
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6, 7, 190, 193, 1100, 1537, 4097, 5000, 6145, 12000, 40961,
+                               196606, 786433, 1048573, (1 << 24) - 5])
+def test_fft_layout(L, d):
+    n, r, c = fft_layout(L, d)
+    assert n >= d and n == min(smooth_lengths(d))    # the smallest 2^k, 3 * 2^k, 5 * 2^k >= d_H
+    assert n % (r * c) == 0 and n // (r * c) in (1, 3, 5)
+    assert r & (r - 1) == 0 and c & (c - 1) == 0
+
+
+def test_fft_layout_cases(L):
+    assert fft_layout(L, 1048573)[0] == 1 << 20       # the large single product stays a power of two
+    assert fft_layout(L, 190) == (192, 64, 1)        # 3 sequences of 64, one workgroup holds it
+    assert fft_layout(L, 1100) == (1280, 256, 1)     # 5 sequences of 256
+    n, r, c = fft_layout(L, 12000)                   # 3 * 4096: multipass sequences
+    assert n == 12288 and r * c == 4096 and c > 1
+    a, r_, c_ = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    assert L.hk_fft_layout(0, ctypes.byref(a), ctypes.byref(r_), ctypes.byref(c_)) == INVALID
 
 
 def test_status_strings(L):
@@ -150,13 +179,18 @@ def test_tune_db_round_trip(L, tmp_path):
     out = tmp_path / "out.txt"
     assert L.hk_tune_save(str(out).encode()) == OK
     lines = [ln for ln in out.read_text().splitlines() if not ln.startswith("#")]
-    assert "1 1 0 23 -1 2 : 16 2 8 4 -1 1 1" in lines
-    assert "0 0 0 23 -1 0 : 8 1 16 8 0 0 1" in lines
+    # lines without the odd factor are power-of-two lengths (odd = 1)
+    assert "1 1 0 1 23 -1 2 : 16 2 8 4 -1 1 1" in lines
+    assert "0 0 0 1 23 -1 0 : 8 1 16 8 0 0 1" in lines
     seven = tmp_path / "seven.txt"
-    seven.write_text("0 0 0 22 -1 0 : 8 2 16 8 0 1 4\n")
+    seven.write_text("0 0 0 22 -1 0 : 8 2 16 8 0 1 4\n0 0 0 3 16 -1 0 : 4 1 16 8 0 1 2\n")
     assert L.hk_tune_load(str(seven).encode(), None) == OK
     assert L.hk_tune_save(str(out).encode()) == OK
-    assert "0 0 0 22 -1 0 : 8 2 16 8 0 1 4" in out.read_text()
+    assert "0 0 0 1 22 -1 0 : 8 2 16 8 0 1 4" in out.read_text()
+    assert "0 0 0 3 16 -1 0 : 4 1 16 8 0 1 2" in out.read_text()
+    bad_odd = tmp_path / "odd.txt"
+    bad_odd.write_text("0 0 0 7 16 -1 0 : 4 1 16 8 0 1 2\n")  # no factor-7 kernels
+    assert L.hk_tune_load(str(bad_odd).encode(), None) == INVALID
     three = tmp_path / "three.txt"
     three.write_text("0 0 0 20 -1 0 : 8 1 16 8 0 0 3\n")  # 3 rows in turn is not offered
     assert L.hk_tune_load(str(three).encode(), None) == INVALID
