@@ -541,11 +541,16 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
             vecs = [None] + [torch.from_numpy(v).to(torch.complex64).to(dev) for v in p.vectors[1:]]
         items.append({"m": p.m, "dims": p.dims, "h": h, "vectors": vecs})
     res = {}
-    for name, flags in (("persistent", _lib.HK_PLAN_PERSISTENT), ("grouped", _lib.HK_PLAN_MULTIKERNEL)):
+    # grouped: lengths 2^k, 3 * 2^k, 5 * 2^k; grouped_pow2 and persistent: powers of two only.
+    # workspace_MB is the plan's workspace, which holds N elements per operand of every
+    # multipass instance: it tracks the padded lengths the passes stream.
+    for name, flags in (("persistent", _lib.HK_PLAN_PERSISTENT), ("grouped", _lib.HK_PLAN_MULTIKERNEL),
+                        ("grouped_pow2", _lib.HK_PLAN_MULTIKERNEL | _lib.HK_PLAN_POW2)):
         plan = hk.Plan(items, flags=flags)
         ms = time_region(torch, plan.execute, 10)
         plan.status()
-        res[name] = {"TVP_s": round(len(items) / ms * 1000, 1), "ms_per_batch": round(ms, 3)}
+        res[name] = {"TVP_s": round(len(items) / ms * 1000, 1), "ms_per_batch": round(ms, 3),
+                     "workspace_MB": round(plan.ws_bytes / 2**20, 1)}
         plan.close()
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):

@@ -43,12 +43,17 @@ struct hk_plan_s {
   // grouped launches: task indices sorted by (phase, kind, length) and the
   // launch list over them
   struct Group {
-    int kind, logL, odd;
+    int kind, logL, odd, phase;
     int32_t begin, count;
   };
   std::vector<int32_t> order;
   std::vector<Group> launches;
   std::vector<char> host_tables;
+  // grouped launches of one phase are independent: they are spread over the
+  // caller's stream and these (created on first use, default priority),
+  // forked from and joined back into the caller's stream by events
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> fork_ev, join_ev;
   int grid = 1;
   bool persistent = true;
   uint32_t wait_bound = 1u << 22;  // barrier polling iterations before the error path
@@ -98,7 +103,7 @@ static void build_groups(hk_plan_s *p) {
     std::vector<std::pair<std::tuple<int, int, int>, int32_t>> keyed;
     for (int32_t i = b; i < e; ++i) {
       const Task &t = p->tasks[i];
-      int kind, logL, odd = 1;  // column kernels take the odd factor at run time
+      int kind, logL, odd = 1;
       if (t.type == TASK_RES) {
         kind = GK_RES;
         logL = p->shapes[p->res_list[t.inst]].logR;
@@ -113,6 +118,7 @@ static void build_groups(hk_plan_s *p) {
       } else {
         kind = GK_COL;
         logL = p->shapes[t.inst].logC;
+        odd = p->shapes[t.inst].odd;
       }
       keyed.push_back({std::make_tuple(kind, logL, odd), i});
     }
@@ -127,7 +133,7 @@ static void build_groups(hk_plan_s *p) {
     for (size_t k = 0; k < keyed.size(); ++k) {
       if (k == 0 || keyed[k].first != keyed[k - 1].first)
         p->launches.push_back({std::get<0>(keyed[k].first), std::get<1>(keyed[k].first), std::get<2>(keyed[k].first),
-                               (int32_t)p->order.size(), 0});
+                               ph, (int32_t)p->order.size(), 0});
       p->order.push_back(keyed[k].second);
       p->launches.back().count++;
     }
@@ -345,6 +351,39 @@ static Status upload_tables(hk_plan_s *p) {
   return Status();
 }
 
+// Streams a grouped plan spreads each phase's launches over (the caller's
+// stream included); four matches the hardware queues a process gets by default.
+constexpr int kGroupStreams = 4;
+
+static Status ensure_streams(hk_plan_s *p, int nstreams) {
+  while ((int)p->aux.size() < nstreams - 1) {
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "plan stream creation");
+    p->aux.push_back(s);
+  }
+  const size_t nfork = 3, njoin = 3 * (size_t)(nstreams - 1);
+  while (p->fork_ev.size() < nfork || p->join_ev.size() < njoin) {
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "plan event creation");
+    if (p->fork_ev.size() < nfork)
+      p->fork_ev.push_back(ev);
+    else
+      p->join_ev.push_back(ev);
+  }
+  return Status();
+}
+
+static void release_streams(hk_plan_s *p) {
+  for (hipStream_t s : p->aux) (void)hipStreamDestroy(s);
+  for (hipEvent_t ev : p->fork_ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : p->join_ev) (void)hipEventDestroy(ev);
+  p->aux.clear();
+  p->fork_ev.clear();
+  p->join_ev.clear();
+}
+
 static Status enqueue(hk_plan_s *p, char *ws, hipStream_t st) {
   char *tables = p->tables_in_ws ? ws + p->ctl_bytes : p->d_tables;
   BatchArgs A;
@@ -367,21 +406,59 @@ static Status enqueue(hk_plan_s *p, char *ws, hipStream_t st) {
     prof_after(PK_BATCH, st);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
   } else {
-    // one specialised launch per (phase, kind, length) group; the stream
-    // orders the phases
+    // one specialised launch per (phase, kind, length, odd factor) group; the
+    // launches of a phase go round-robin (longest transforms first) over up
+    // to kGroupStreams streams, and the phase's end joins them again
+    int per_phase[3] = {0, 0, 0};
+    for (const auto &g : p->launches) per_phase[g.phase]++;
+    const int S = std::min(kGroupStreams, std::max(std::max(per_phase[0], per_phase[1]), per_phase[2]));
+    if (S > 1) {
+      Status ss = ensure_streams(p, S);
+      if (!ss.ok()) return ss;
+    }
+    int cur_phase = -1, k = 0, used = 1;
+    auto join = [&](int ph) -> hipError_t {
+      for (int i = 0; i + 1 < used; ++i) {
+        hipEvent_t ev = p->join_ev[(size_t)ph * (S - 1) + i];
+        hipError_t e2 = hipEventRecord(ev, p->aux[i]);
+        if (e2 == hipSuccess) e2 = hipStreamWaitEvent(st, ev, 0);
+        if (e2 != hipSuccess) return e2;
+      }
+      return hipSuccess;
+    };
     for (const auto &g : p->launches) {
+      if (g.phase != cur_phase) {
+        if (cur_phase >= 0 && S > 1) {
+          e = join(cur_phase);
+          if (e != hipSuccess) return hip_fail(e, "phase join");
+        }
+        cur_phase = g.phase;
+        k = 0;
+        used = S > 1 ? std::min(S, per_phase[g.phase]) : 1;
+        if (used > 1) {
+          e = hipEventRecord(p->fork_ev[g.phase], st);
+          for (int i = 0; e == hipSuccess && i + 1 < used; ++i) e = hipStreamWaitEvent(p->aux[i], p->fork_ev[g.phase], 0);
+          if (e != hipSuccess) return hip_fail(e, "phase fork");
+        }
+      }
+      hipStream_t gs = (k % used == 0) ? st : p->aux[k % used - 1];
+      ++k;
       A.begin = g.begin;
       A.end = g.begin + g.count;
       count_launch();
-      prof_before(st);
-      if (g.odd > 1)
-        e = dbl(p->dt) ? launch_group_odd_f64(A, g.odd, g.kind, g.logL, g.count, st)
-                       : launch_group_odd_f32(A, g.odd, g.kind, g.logL, g.count, st);
+      prof_before(gs);
+      if (g.odd > 1 && g.kind != GK_COL)
+        e = dbl(p->dt) ? launch_group_odd_f64(A, g.odd, g.kind, g.logL, g.count, gs)
+                       : launch_group_odd_f32(A, g.odd, g.kind, g.logL, g.count, gs);
       else
-        e = dbl(p->dt) ? launch_group_f64(A, g.kind, g.logL, g.count, st)
-                       : launch_group_f32(A, g.kind, g.logL, g.count, st);
-      prof_after(PK_BATCH, st);
+        e = dbl(p->dt) ? launch_group_f64(A, g.kind, g.logL, g.odd, g.count, gs)
+                       : launch_group_f32(A, g.kind, g.logL, g.odd, g.count, gs);
+      prof_after(PK_BATCH, gs);
       if (e != hipSuccess) return hip_fail(e, "grouped batch launch");
+    }
+    if (cur_phase >= 0 && S > 1) {
+      e = join(cur_phase);
+      if (e != hipSuccess) return hip_fail(e, "phase join");
     }
   }
   return Status();
@@ -470,10 +547,9 @@ Status plan_destroy(hk_plan_t p) {
   if (!p) return Status();
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
-  if (p->d_tables) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(p->d_tables);
-  }
+  if (p->d_tables || !p->aux.empty()) (void)hipDeviceSynchronize();
+  if (p->d_tables) (void)hipFree(p->d_tables);
+  release_streams(p);
   delete p;
   return Status();
 }
@@ -488,6 +564,7 @@ Status plan_release_after(hk_plan_t p, hipStream_t st) {
   // The descriptor tables were copied into the caller's workspace from the
   // plan's host buffer; wait for the stream before that buffer goes away.
   hipError_t e = hipStreamSynchronize(st);
+  release_streams(p);
   delete p;
   if (e != hipSuccess) return hip_fail(e, "stream synchronize");
   return Status();

@@ -224,10 +224,13 @@ __device__ __forceinline__ int64_t seq_len(const Shape &sh) { return (int64_t)1 
 __device__ __forceinline__ int64_t fft_len(const Shape &sh) { return (int64_t)sh.odd << (sh.logR + sh.logC); }
 
 // Multipass workspace: nbuf buffers of N elements (sequence q of a buffer at
-// q * M), then the row pass's scalar partial sums.
-template <typename T>
+// q * M), then the row pass's scalar partial sums.  ODDF: the shape may have
+// an odd factor; the power-of-two bodies leave it out, so that their hot
+// loops issue no extra scalar loads (whose waits also wait for LDS).
+template <typename T, bool ODDF = false>
 __device__ __forceinline__ cx<T> *ws_buf(const Shape &sh, const PV &P, int b) {
-  return (cx<T> *)P.ws() + (int64_t)b * fft_len(sh);
+  if constexpr (ODDF) return (cx<T> *)P.ws() + (int64_t)b * fft_len(sh);
+  return (cx<T> *)P.ws() + ((int64_t)b << (sh.logR + sh.logC));
 }
 
 template <typename T>
@@ -321,24 +324,27 @@ struct RowBody {
     for (int s = 0; s < EE; ++s) idx[s] = t + s * TPS + (ODD > 1 ? (int64_t)L * tau[s] : 0);
   }
 
+  // Power-of-two rows (ODD == 1): one sequence per row.
   static __device__ __forceinline__ void load(cx<T> (&a)[EE], const Shape &sh, const PV &P, int o,
-                                              int64_t row, bool valid_row, int t, bool resident, int q) {
+                                              int64_t row, bool valid_row, int t, bool resident) {
     const OpDesc &od = sh.ops[o];
     uint32_t off[EE];
     if (resident) {
       // the rows of a workgroup may be different instances: flat loads
       int64_t idx[EE];
       bool ok[EE];
-      res_index(idx, q, t);
 #pragma unroll
-      for (int s = 0; s < EE; ++s) ok[s] = valid_row && idx[s] < od.len;
+      for (int s = 0; s < EE; ++s) {
+        idx[s] = t + s * TPS;
+        ok[s] = valid_row && idx[s] < od.len;
+      }
       gather<T, EE>(a, P.op(o), idx, ok, od.flags);
     } else {
-      // row `row` of sequence q of the operand's column transform; its
-      // columns past ncol_nz were never written and read as zero
-      const int64_t M = seq_len(sh);
-      const auto r = make_buf(ws_buf<T>(sh, P, od.buf), ODD * M * (int64_t)sizeof(cx<T>));
-      const uint32_t rbase = (uint32_t)((q * M + row * L) * (int64_t)sizeof(cx<T>));
+      // row `row` of the operand's column transform; its columns past
+      // ncol_nz were never written and read as zero
+      const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+      const auto r = make_buf(ws_buf<T>(sh, P, od.buf), N * (int64_t)sizeof(cx<T>));
+      const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
 #pragma unroll
       for (int s = 0; s < EE; ++s) {
         const int i = t + s * TPS;
@@ -348,26 +354,26 @@ struct RowBody {
     }
   }
 
-  // Stores sequence q of output `which` (0: y / grad_h, 1: grad_x) of this row.
+  // Stores output `which` (0: y / grad_h, 1: grad_x) of this row.
   static __device__ __forceinline__ void store(const cx<T> (&a)[EE], const Shape &sh, const PV &P,
                                                int which, int64_t row, bool valid_row, int t,
-                                               bool resident, const cx<T> (&w)[EE], int q) {
+                                               bool resident, const cx<T> (&w)[EE]) {
     if (!valid_row) return;
     if (resident) {
       void *dst = which == 0 ? P.y() : P.out1();
       const int64_t lim = which == 0 ? sh.out_rows : sh.out1_len;
       const bool cj = (sh.prog == PROG_BWD) && which == 1;
-      int64_t idx[EE];
-      res_index(idx, q, t);
 #pragma unroll
-      for (int s = 0; s < EE; ++s)
-        if (idx[s] < lim) store_out<T>(dst, idx[s], cj ? cconj(a[s]) : a[s], sh.real_out);
+      for (int s = 0; s < EE; ++s) {
+        const int pos = t + s * TPS;
+        if (pos < lim) store_out<T>(dst, pos, cj ? cconj(a[s]) : a[s], sh.real_out);
+      }
     } else {
-      const int64_t M = seq_len(sh);
-      const auto r = make_buf(ws_buf<T>(sh, P, sh.ops[which].buf), ODD * M * (int64_t)sizeof(cx<T>));
-      const uint32_t rbase = (uint32_t)((q * M + row * L) * (int64_t)sizeof(cx<T>));
+      const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+      const auto r = make_buf(ws_buf<T>(sh, P, sh.ops[which].buf), N * (int64_t)sizeof(cx<T>));
+      const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
       if (!sh.is_block) {
-        // four-step twiddles W_M^{pos * row}, pos = t + s TPS (from twiddles())
+        // four-step twiddles W_N^{pos * row}, pos = t + s TPS (from twiddles())
 #pragma unroll
         for (int s = 0; s < EE; ++s)
           BufIO<T>::st(cmul(a[s], w[s]), r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
@@ -378,7 +384,7 @@ struct RowBody {
     }
   }
 
-  // Pass-B rows of a 1D instance: w[s] = W_M^{(t + s TPS) row}, used on the
+  // Pass-B rows of a 1D instance: w[s] = W_N^{(t + s TPS) row}, used on the
   // loaded operands (pass A's twiddle) and on the stored output.
   static __device__ __forceinline__ bool twiddles(cx<T> (&w)[EE], const Shape &sh, int64_t row, int t,
                                                   bool resident, const cx<T> *tw24, const cx<T> *tw4096) {
@@ -393,6 +399,236 @@ struct RowBody {
     }
   }
 
+  // Forward program: z = h^ prod_p x^_p^{e_p}; y = fft(z); alpha = sum z x^_1.
+  static __device__ __forceinline__ cx<T> run_fwd(const Shape &sh, const PV &P, int64_t row, bool valid_row,
+                                                  int t, cx<T> *lds, bool resident, const cx<T> *tw24,
+                                                  const cx<T> *tw4096) {
+    if constexpr (ODD > 1) {
+      return run_fwd_odd(sh, P, row, 0, 1, valid_row, t, lds, resident, tw24, tw4096);
+    } else {
+    const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
+    cx<T> a[EE], nx[EE], acc[EE];
+    cx<T> part = czero<T>();
+#pragma unroll
+    for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
+    load(a, sh, P, 0, row, valid_row, t, resident);
+    StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
+    cx<T> w[EE];
+    const bool tw_on = twiddles(w, sh, row, t, resident, tw24, tw4096);
+    for (int o = 0; o < sh.nops; ++o) {
+      // the next operand's loads are in flight while this one is transformed
+      if (o + 1 < sh.nops) load(nx, sh, P, o + 1, row, valid_row, t, resident);
+      twiddle_in(a, w, tw_on);
+      fft(a, t, lds, stw);
+      const OpDesc &od = sh.ops[o];
+      if (od.role == ROLE_H) {
+#pragma unroll
+        for (int s = 0; s < EE; ++s) acc[s] = cscale(cconj(a[s]), invN);
+      } else {
+        for (int e = 0; e < od.exp; ++e) {
+#pragma unroll
+          for (int s = 0; s < EE; ++s) acc[s] = cmul(acc[s], a[s]);
+        }
+        if (od.flags & OPF_ALPHA) {
+#pragma unroll
+          for (int s = 0; s < EE; ++s) part = cfma(acc[s], a[s], part);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < EE; ++s) a[s] = nx[s];
+    }
+    if (sh.want_y) {
+      fft(acc, t, lds, stw);
+      store(acc, sh, P, 0, row, valid_row, t, resident, w);
+    }
+    return part;
+    }
+  }
+
+  // Pass B, forward program, over K rows row0, row0 + rstride, ... handled in
+  // turn by this lane group: while a row's last operand is transformed, the
+  // first operand of the next row is already loading, so the memory traffic
+  // of one row overlaps the arithmetic of the previous one.  Returns the lane's
+  // share of the scalar product over its rows.
+  static __device__ __forceinline__ cx<T> run_fwd_rows(const Shape &sh, const PV &P, int64_t row0, int rstride,
+                                                       int K, int t, cx<T> *lds, const cx<T> *tw24,
+                                                       const cx<T> *tw4096) {
+    if constexpr (ODD > 1) {
+      return run_fwd_odd(sh, P, row0, rstride, K, true, t, lds, false, tw24, tw4096);
+    } else {
+    const int64_t C = (int64_t)1 << sh.logC;
+    const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
+    cx<T> a[EE], nx[EE], acc[EE], w[EE];
+    cx<T> part = czero<T>();
+    int64_t row = row0;
+    bool valid = row < C;
+    load(a, sh, P, 0, row, valid, t, false);
+    StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
+    for (int it = 0; it < K; ++it) {
+      const bool tw_on = twiddles(w, sh, row, t, false, tw24, tw4096);
+      const int64_t nrow = row + rstride;
+      const bool nvalid = (it + 1 < K) && nrow < C;
+#pragma unroll
+      for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
+      for (int o = 0; o < sh.nops; ++o) {
+        if (o + 1 < sh.nops)
+          load(nx, sh, P, o + 1, row, valid, t, false);
+        else if (it + 1 < K)
+          load(nx, sh, P, 0, nrow, nvalid, t, false);
+        twiddle_in(a, w, tw_on);
+        fft(a, t, lds, stw);
+        const OpDesc &od = sh.ops[o];
+        if (od.role == ROLE_H) {
+#pragma unroll
+          for (int s = 0; s < EE; ++s) acc[s] = cscale(cconj(a[s]), invN);
+        } else {
+          for (int e = 0; e < od.exp; ++e) {
+#pragma unroll
+            for (int s = 0; s < EE; ++s) acc[s] = cmul(acc[s], a[s]);
+          }
+          if (od.flags & OPF_ALPHA) {
+#pragma unroll
+            for (int s = 0; s < EE; ++s) part = cfma(acc[s], a[s], part);
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < EE; ++s) a[s] = nx[s];
+      }
+      if (sh.want_y) {
+        fft(acc, t, lds, stw);
+        store(acc, sh, P, 0, row, valid, t, false, w);
+      }
+      row = nrow;
+      valid = nvalid;
+    }
+    return part;
+    }
+  }
+
+  // Adjoint of g = H x^{m-1}, f = H x^m (equal vectors).  Operands in order:
+  // X, then optionally V (cotangent of g, conjugated on load), then H when
+  // grad_x is requested.
+  static __device__ __forceinline__ void run_bwd(const Shape &sh, const PV &P, int64_t row, bool valid_row,
+                                                 int t, cx<T> *lds, bool resident, const cx<T> *tw24,
+                                                 const cx<T> *tw4096) {
+    if constexpr (ODD > 1) {
+      run_bwd_odd(sh, P, row, valid_row, t, lds, resident, tw24, tw4096);
+      return;
+    }
+    const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
+    cx<T> a[EE], gq[EE];
+    cx<T> phc = czero<T>();  // conj(phi)
+    if (P.phi()) phc = cconj(*(const cx<T> *)P.phi());
+    const T m1 = T(sh.m - 1), m0 = T(sh.m);
+    StageTw<T, L, E> stw;
+    cx<T> w[EE];
+    bool tw_on;
+    {
+      cx<T> xs[EE], p1[EE], vs[EE];
+      load(xs, sh, P, 0, row, valid_row, t, resident);
+      stw.init(t, tw4096);
+      tw_on = twiddles(w, sh, row, t, resident, tw24, tw4096);
+      twiddle_in(xs, w, tw_on);
+      fft(xs, t, lds, stw);
+#pragma unroll
+      for (int s = 0; s < EE; ++s) p1[s] = mk(T(1), T(0));
+      for (int e = 0; e < sh.m - 2; ++e) {
+#pragma unroll
+        for (int s = 0; s < EE; ++s) p1[s] = cmul(p1[s], xs[s]);
+      }
+      const bool has_v = sh.nops > 1 && sh.ops[1].role == ROLE_V;
+      if (has_v) {
+        load(vs, sh, P, 1, row, valid_row, t, resident);
+        twiddle_in(vs, w, tw_on);
+        fft(vs, t, lds, stw);
+      } else {
+#pragma unroll
+        for (int s = 0; s < EE; ++s) vs[s] = czero<T>();
+      }
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        // grad_x spectrum factor: x^{m-2} ((m-1) V + m conj(phi) x)
+        gq[s] = cmul(p1[s], cadd(cscale(vs[s], m1), cscale(cmul(phc, xs[s]), m0)));
+        // grad_h spectrum: conj(x^{m-1} (V + conj(phi) x)) / N, transformed forward
+        a[s] = cscale(cconj(cmul(cmul(p1[s], xs[s]), cfma(phc, xs[s], vs[s]))), invN);
+      }
+    }
+    if (sh.want_y) {
+      fft(a, t, lds, stw);
+      store(a, sh, P, 0, row, valid_row, t, resident, w);
+    }
+    if (sh.want_out1) {
+      load(a, sh, P, sh.nops - 1, row, valid_row, t, resident);  // H
+      twiddle_in(a, w, tw_on);
+      fft(a, t, lds, stw);
+#pragma unroll
+      for (int s = 0; s < EE; ++s) a[s] = cmul(cscale(cconj(a[s]), invN), gq[s]);
+      fft(a, t, lds, stw);
+      store(a, sh, P, 1, row, valid_row, t, resident, w);
+    }
+  }
+
+  // ---- Odd-factor rows (ODD > 1): the same row of ODD sequences. ----
+
+  static __device__ __forceinline__ void load_seq(cx<T> (&a)[EE], const Shape &sh, const PV &P, int o,
+                                                  int64_t row, bool valid_row, int t, bool resident, int q) {
+    const OpDesc &od = sh.ops[o];
+    uint32_t off[EE];
+    if (resident) {
+      // the rows of a workgroup may be different instances: flat loads
+      int64_t idx[EE];
+      bool ok[EE];
+      res_index(idx, q, t);
+#pragma unroll
+      for (int s = 0; s < EE; ++s) ok[s] = valid_row && idx[s] < od.len;
+      gather<T, EE>(a, P.op(o), idx, ok, od.flags);
+    } else {
+      // row `row` of sequence q of the operand's column transform; its
+      // columns past ncol_nz were never written and read as zero
+      const int64_t M = seq_len(sh);
+      const auto r = make_buf(ws_buf<T, true>(sh, P, od.buf), ODD * M * (int64_t)sizeof(cx<T>));
+      const uint32_t rbase = (uint32_t)((q * M + row * L) * (int64_t)sizeof(cx<T>));
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        const int i = t + s * TPS;
+        off[s] = (valid_row && i < od.ncol_nz) ? rbase + (uint32_t)(i * (int)sizeof(cx<T>)) : OOB_OFF;
+      }
+      bgather<T, EE>(a, r, off, 0);
+    }
+  }
+
+  // Stores sequence q of output `which` (0: y / grad_h, 1: grad_x) of this row.
+  static __device__ __forceinline__ void store_seq(const cx<T> (&a)[EE], const Shape &sh, const PV &P,
+                                                   int which, int64_t row, bool valid_row, int t,
+                                                   bool resident, const cx<T> (&w)[EE], int q) {
+    if (!valid_row) return;
+    if (resident) {
+      void *dst = which == 0 ? P.y() : P.out1();
+      const int64_t lim = which == 0 ? sh.out_rows : sh.out1_len;
+      const bool cj = (sh.prog == PROG_BWD) && which == 1;
+      int64_t idx[EE];
+      res_index(idx, q, t);
+#pragma unroll
+      for (int s = 0; s < EE; ++s)
+        if (idx[s] < lim) store_out<T>(dst, idx[s], cj ? cconj(a[s]) : a[s], sh.real_out);
+    } else {
+      const int64_t M = seq_len(sh);
+      const auto r = make_buf(ws_buf<T, true>(sh, P, sh.ops[which].buf), ODD * M * (int64_t)sizeof(cx<T>));
+      const uint32_t rbase = (uint32_t)((q * M + row * L) * (int64_t)sizeof(cx<T>));
+      if (!sh.is_block) {
+        // four-step twiddles W_M^{pos * row}, pos = t + s TPS (from twiddles())
+#pragma unroll
+        for (int s = 0; s < EE; ++s)
+          BufIO<T>::st(cmul(a[s], w[s]), r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
+      } else {
+#pragma unroll
+        for (int s = 0; s < EE; ++s) BufIO<T>::st(a[s], r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
+      }
+    }
+  }
+
   // Spectrum of operand o on this row: its ODD sequences loaded (each next
   // one in flight while the current one is transformed), transformed along
   // the power-of-two axis, then across the sequences.
@@ -400,12 +636,12 @@ struct RowBody {
                                                   bool valid_row, int t, cx<T> *lds, bool resident,
                                                   const StageTw<T, L, E> &stw, const cx<T> (&w)[EE], bool tw_on) {
     cx<T> nx[EE];
-    load(nx, sh, P, o, row, valid_row, t, resident, 0);
+    load_seq(nx, sh, P, o, row, valid_row, t, resident, 0);
 #pragma unroll
     for (int q = 0; q < ODD; ++q) {
 #pragma unroll
       for (int s = 0; s < EE; ++s) h[q][s] = nx[s];
-      if (q + 1 < ODD) load(nx, sh, P, o, row, valid_row, t, resident, q + 1);
+      if (q + 1 < ODD) load_seq(nx, sh, P, o, row, valid_row, t, resident, q + 1);
       twiddle_in(h[q], w, tw_on);
       fft(h[q], t, lds, stw);
     }
@@ -447,25 +683,18 @@ struct RowBody {
 #pragma unroll
     for (int q = 0; q < ODD; ++q) {
       fft(acc[q], t, lds, stw);
-      store(acc[q], sh, P, which, row, valid_row, t, resident, w, q);
+      store_seq(acc[q], sh, P, which, row, valid_row, t, resident, w, q);
     }
   }
 
-  // Forward program: z = h^ prod_p x^_p^{e_p}; y = fft(z); alpha = sum z x^_1.
-  static __device__ __forceinline__ cx<T> run_fwd(const Shape &sh, const PV &P, int64_t row, bool valid_row,
-                                                  int t, cx<T> *lds, bool resident, const cx<T> *tw24,
-                                                  const cx<T> *tw4096) {
-    return run_fwd_rows(sh, P, row, 0, 1, valid_row, t, lds, resident, tw24, tw4096);
-  }
-
-  // Forward program over K rows row0, row0 + rstride, ... handled in turn by
-  // this lane group (K = 1 for resident rows).  The loads run one sequence
+  // Forward program of odd-factor rows over K rows row0, row0 + rstride, ...
+  // handled in turn by this lane group (K = 1 for resident rows).  The loads run one sequence
   // ahead of the transforms: while a sequence is transformed the next one
   // (of this operand, the next operand or the next row's first operand) is
   // already loading, so the memory traffic of a row overlaps the arithmetic.
   // Returns the lane's share of the scalar product over its rows.
-  static __device__ __forceinline__ cx<T> run_fwd_rows(const Shape &sh, const PV &P, int64_t row0, int rstride,
-                                                       int K, bool valid0, int t, cx<T> *lds, bool resident,
+  static __device__ __forceinline__ cx<T> run_fwd_odd(const Shape &sh, const PV &P, int64_t row0, int rstride,
+                                                      int K, bool valid0, int t, cx<T> *lds, bool resident,
                                                        const cx<T> *tw24, const cx<T> *tw4096) {
     const int64_t C = (int64_t)1 << sh.logC;
     const T invN = T(1) / T((int64_t)ODD << (sh.logR + sh.logC));
@@ -474,7 +703,7 @@ struct RowBody {
     cx<T> part = czero<T>();
     int64_t row = row0;
     bool valid = resident ? valid0 : row < C;
-    load(nx, sh, P, 0, row, valid, t, resident, 0);
+    load_seq(nx, sh, P, 0, row, valid, t, resident, 0);
     StageTw<T, L, E> stw;
     stw.init(t, tw4096);
     for (int it = 0; it < K; ++it) {
@@ -491,11 +720,11 @@ struct RowBody {
 #pragma unroll
           for (int s = 0; s < EE; ++s) h[q][s] = nx[s];
           if (q + 1 < ODD)
-            load(nx, sh, P, o, row, valid, t, resident, q + 1);
+            load_seq(nx, sh, P, o, row, valid, t, resident, q + 1);
           else if (o + 1 < sh.nops)
-            load(nx, sh, P, o + 1, row, valid, t, resident, 0);
+            load_seq(nx, sh, P, o + 1, row, valid, t, resident, 0);
           else if (it + 1 < K)
-            load(nx, sh, P, 0, nrow, nvalid, t, resident, 0);
+            load_seq(nx, sh, P, 0, nrow, nvalid, t, resident, 0);
           twiddle_in(h[q], w, tw_on);
           fft(h[q], t, lds, stw);
         }
@@ -509,10 +738,8 @@ struct RowBody {
     return part;
   }
 
-  // Adjoint of g = H x^{m-1}, f = H x^m (equal vectors).  Operands in order:
-  // X, then optionally V (cotangent of g, conjugated on load), then H when
-  // grad_x is requested.
-  static __device__ __forceinline__ void run_bwd(const Shape &sh, const PV &P, int64_t row, bool valid_row,
+  // Adjoint of odd-factor rows (see run_bwd).
+  static __device__ __forceinline__ void run_bwd_odd(const Shape &sh, const PV &P, int64_t row, bool valid_row,
                                                  int t, cx<T> *lds, bool resident, const cx<T> *tw24,
                                                  const cx<T> *tw4096) {
     const T invN = T(1) / T((int64_t)ODD << (sh.logR + sh.logC));
@@ -590,8 +817,95 @@ struct ColBody {
     }
   }
 
-  static __device__ __forceinline__ void run(const Shape &sh, const PV &P, const ColJob &job, int64_t v0,
+  // Power-of-two transforms (odd == 1).
+  static __device__ __forceinline__ void run(const Shape &sh, const PV &P, const ColJob &job, int64_t c0,
                                              int TW, int tid, cx<T> *lds, const cx<T> *tw24,
+                                             const cx<T> *tw4096) {
+    const int cw = tid % TW;
+    const int t = tid / TW;
+    const int64_t c = c0 + cw;
+    const bool cvalid = c < job.ncols;
+    const int64_t R = (int64_t)1 << sh.logR;
+    cx<T> a[EE];
+    uint32_t off[EE];
+    constexpr int CB = (int)sizeof(cx<T>);
+    const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+    if (job.kind == COL_A) {
+      const OpDesc &od = sh.ops[job.op];
+      const int es = elem_size<T>(od.flags);
+      if (!sh.is_block) {
+        // element c + R k of the padded operand; past its end reads zero
+        const auto r = make_buf(P.op(job.op), od.len * es);
+#pragma unroll
+        for (int s = 0; s < EE; ++s) off[s] = (uint32_t)((c + R * (t + s * TPS)) * es);
+        bgather<T, EE>(a, r, off, od.flags);
+      } else {
+        // generating matrix (len rows x cols columns, column-major): row c,
+        // column k; rows past len are zero padding (k past cols falls past
+        // the end of the resource)
+        const auto r = make_buf(P.op(job.op), od.len * od.cols * es);
+        const bool crow = c < od.len;
+#pragma unroll
+        for (int s = 0; s < EE; ++s) off[s] = crow ? (uint32_t)((c + od.len * (t + s * TPS)) * es) : OOB_OFF;
+        bgather<T, EE>(a, r, off, od.flags);
+      }
+    } else {
+      const auto r = make_buf(ws_buf<T>(sh, P, job.buf), N * CB);
+#pragma unroll
+      for (int s = 0; s < EE; ++s) off[s] = (uint32_t)((c + R * (t + s * TPS)) * CB);
+      bgather<T, EE>(a, r, off, 0);
+    }
+    StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
+    // TW interleaved columns: element i of column cw at lds[(sw(i) << log2 TW) + cw]
+    fft_seq<T, L, E>(a, t, lds + cw, stw, __builtin_ctz((unsigned)TW));
+    if (!cvalid) return;
+    // a row segment of the tile is TW elements: whole lines stream out
+    // (non-temporal), narrower ones merge in L2
+    if (TW * CB >= 128)
+      store_tile<ST_NT>(a, sh, P, job, c, R, t, N);
+    else
+      store_tile<ST_DEFAULT>(a, sh, P, job, c, R, t, N);
+  }
+
+  template <int POL>
+  static __device__ __forceinline__ void store_tile(const cx<T> (&a)[EE], const Shape &sh, const PV &P,
+                                                    const ColJob &job, int64_t c, int64_t R, int t, int64_t N) {
+    constexpr int CB = (int)sizeof(cx<T>);
+    if (job.kind == COL_A) {
+      const auto r = make_buf(ws_buf<T>(sh, P, job.buf), N * CB);
+#pragma unroll
+      for (int s = 0; s < EE; ++s) BufIO<T>::template st<POL>(a[s], r, off_ws(c, R, t + s * TPS));
+    } else {
+      void *dst = job.op == 0 ? P.y() : P.out1();
+      const int es = sh.real_out ? (int)sizeof(T) : CB;
+      if (!sh.is_block) {
+        // the slice [0, lim) is the resource: later positions are dropped
+        const int64_t lim = job.op == 0 ? sh.out_rows : sh.out1_len;
+        const auto r = make_buf(dst, lim * es);
+#pragma unroll
+        for (int s = 0; s < EE; ++s)
+          bstore<T, POL>(r, (uint32_t)((c + R * (t + s * TPS)) * es), job.conj_out ? cconj(a[s]) : a[s],
+                         sh.real_out);
+      } else if (c < sh.out_rows) {
+        // out_rows x out_cols corner, column-major; columns past out_cols fall
+        // past the end of the resource
+        const auto r = make_buf(dst, sh.out_rows * sh.out_cols * es);
+#pragma unroll
+        for (int s = 0; s < EE; ++s)
+          bstore<T, POL>(r, (uint32_t)((c + sh.out_rows * (t + s * TPS)) * es), job.conj_out ? cconj(a[s]) : a[s],
+                         sh.real_out);
+      }
+    }
+  }
+
+  static __device__ __forceinline__ uint32_t off_ws(int64_t c, int64_t R, int k) {
+    return (uint32_t)((c + R * k) * (int64_t)sizeof(cx<T>));
+  }
+
+  // Odd-factor transforms: virtual column v0 + lane column of the odd * R.
+  static __device__ __forceinline__ void run_odd(const Shape &sh, const PV &P, const ColJob &job, int64_t v0,
+                                                 int TW, int tid, cx<T> *lds, const cx<T> *tw24,
                                              const cx<T> *tw4096) {
     const int cw = tid % TW;
     const int t = tid / TW;
@@ -625,7 +939,7 @@ struct ColBody {
         bgather<T, EE>(a, r, off, od.flags);
       }
     } else {
-      const auto r = make_buf(ws_buf<T>(sh, P, job.buf), N * CB);
+      const auto r = make_buf(ws_buf<T, true>(sh, P, job.buf), N * CB);
 #pragma unroll
       for (int s = 0; s < EE; ++s) off[s] = (uint32_t)((q * M + c + R * (t + s * TPS)) * CB);
       bgather<T, EE>(a, r, off, 0);
@@ -638,18 +952,18 @@ struct ColBody {
     // a row segment of the tile is TW elements: whole lines stream out
     // (non-temporal), narrower ones merge in L2
     if (TW * CB >= 128)
-      store_tile<ST_NT>(a, sh, P, job, q, c, R, t);
+      store_tile_odd<ST_NT>(a, sh, P, job, q, c, R, t);
     else
-      store_tile<ST_DEFAULT>(a, sh, P, job, q, c, R, t);
+      store_tile_odd<ST_DEFAULT>(a, sh, P, job, q, c, R, t);
   }
 
   template <int POL>
-  static __device__ __forceinline__ void store_tile(const cx<T> (&a)[EE], const Shape &sh, const PV &P,
-                                                    const ColJob &job, int q, int64_t c, int64_t R, int t) {
+  static __device__ __forceinline__ void store_tile_odd(const cx<T> (&a)[EE], const Shape &sh, const PV &P,
+                                                        const ColJob &job, int q, int64_t c, int64_t R, int t) {
     constexpr int CB = (int)sizeof(cx<T>);
     if (job.kind == COL_A) {
       const int64_t M = seq_len(sh);
-      const auto r = make_buf(ws_buf<T>(sh, P, job.buf), fft_len(sh) * CB);
+      const auto r = make_buf(ws_buf<T, true>(sh, P, job.buf), fft_len(sh) * CB);
 #pragma unroll
       for (int s = 0; s < EE; ++s)
         BufIO<T>::template st<POL>(a[s], r, (uint32_t)((q * M + c + R * (t + s * TPS)) * CB));

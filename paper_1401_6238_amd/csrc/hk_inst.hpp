@@ -18,8 +18,8 @@ static void *row_fn(int prog) {
   return prog == PROG_BWD ? (void *)&k_rows<L, E, ROW_MAXT, PROG_BWD> : (void *)&k_rows<L, E, ROW_MAXT, PROG_FWD>;
 }
 template <int L, int E>
-static void *col_fn() {
-  return (void *)&k_cols<L, E, COL_MAXT>;
+static void *col_fn(bool oddc) {
+  return oddc ? (void *)&k_cols<L, E, COL_MAXT, true> : (void *)&k_cols<L, E, COL_MAXT, false>;
 }
 
 template <int E>
@@ -42,21 +42,21 @@ static void *pick_row(int logL, int prog) {
   return nullptr;
 }
 template <int E>
-static void *pick_col(int logL) {
+static void *pick_col(int logL, bool oddc) {
   switch (logL) {
-    case 0: return col_fn<1, E>();
-    case 1: return col_fn<2, E>();
-    case 2: return col_fn<4, E>();
-    case 3: return col_fn<8, E>();
-    case 4: return col_fn<16, E>();
-    case 5: return col_fn<32, E>();
-    case 6: return col_fn<64, E>();
-    case 7: return col_fn<128, E>();
-    case 8: return col_fn<256, E>();
-    case 9: return col_fn<512, E>();
-    case 10: return col_fn<1024, E>();
-    case 11: return col_fn<2048, E>();
-    case 12: return col_fn<4096, E>();
+    case 0: return col_fn<1, E>(oddc);
+    case 1: return col_fn<2, E>(oddc);
+    case 2: return col_fn<4, E>(oddc);
+    case 3: return col_fn<8, E>(oddc);
+    case 4: return col_fn<16, E>(oddc);
+    case 5: return col_fn<32, E>(oddc);
+    case 6: return col_fn<64, E>(oddc);
+    case 7: return col_fn<128, E>(oddc);
+    case 8: return col_fn<256, E>(oddc);
+    case 9: return col_fn<512, E>(oddc);
+    case 10: return col_fn<1024, E>(oddc);
+    case 11: return col_fn<2048, E>(oddc);
+    case 12: return col_fn<4096, E>(oddc);
   }
   return nullptr;
 }
@@ -67,10 +67,10 @@ static void *row_kernel(int logL, int E, int prog) {
   if (E == 16) return pick_row<16>(logL, prog);
   return nullptr;
 }
-static void *col_kernel(int logL, int E) {
+static void *col_kernel(int logL, int E, bool oddc) {
   if (logL < 0 || logL > MAX_LOGL) return nullptr;
-  if (E == 8) return pick_col<8>(logL);
-  if (E == 16) return pick_col<16>(logL);
+  if (E == 8) return pick_col<8>(logL, oddc);
+  if (E == 16) return pick_col<16>(logL, oddc);
   return nullptr;
 }
 
@@ -105,31 +105,33 @@ static KernelLimits lim_pick(int logL) {
   }
 }
 
+// Column tasks of odd-factor transforms run in the ODD = 3 variant of the
+// column group kernel (their odd factor is read from the shape).
 template <int L>
-static void *group_fn(int kind) {
+static void *group_fn(int kind, bool oddc) {
   switch (kind) {
-    case GK_RES: return (void *)&k_group<L, GK_RES>;
-    case GK_ROWB: return (void *)&k_group<L, GK_ROWB>;
-    case GK_COL: return (void *)&k_group<L, GK_COL>;
+    case GK_RES: return oddc ? nullptr : (void *)&k_group<L, GK_RES>;
+    case GK_ROWB: return oddc ? nullptr : (void *)&k_group<L, GK_ROWB>;
+    case GK_COL: return oddc ? (void *)&k_group<L, GK_COL, 3> : (void *)&k_group<L, GK_COL>;
   }
   return nullptr;
 }
-static void *group_kernel(int kind, int logL) {
+static void *group_kernel(int kind, int logL, bool oddc) {
   if (kind == GK_ALPHA) return (void *)&k_group<1, GK_ALPHA>;
   switch (logL) {
-    case 0: return group_fn<1>(kind);
-    case 1: return group_fn<2>(kind);
-    case 2: return group_fn<4>(kind);
-    case 3: return group_fn<8>(kind);
-    case 4: return group_fn<16>(kind);
-    case 5: return group_fn<32>(kind);
-    case 6: return group_fn<64>(kind);
-    case 7: return group_fn<128>(kind);
-    case 8: return group_fn<256>(kind);
-    case 9: return group_fn<512>(kind);
-    case 10: return group_fn<1024>(kind);
-    case 11: return group_fn<2048>(kind);
-    case 12: return group_fn<4096>(kind);
+    case 0: return group_fn<1>(kind, oddc);
+    case 1: return group_fn<2>(kind, oddc);
+    case 2: return group_fn<4>(kind, oddc);
+    case 3: return group_fn<8>(kind, oddc);
+    case 4: return group_fn<16>(kind, oddc);
+    case 5: return group_fn<32>(kind, oddc);
+    case 6: return group_fn<64>(kind, oddc);
+    case 7: return group_fn<128>(kind, oddc);
+    case 8: return group_fn<256>(kind, oddc);
+    case 9: return group_fn<512>(kind, oddc);
+    case 10: return group_fn<1024>(kind, oddc);
+    case 11: return group_fn<2048>(kind, oddc);
+    case 12: return group_fn<4096>(kind, oddc);
   }
   return nullptr;
 }
@@ -202,7 +204,7 @@ hipError_t HK_CAT(launch_cols_, HK_SUFFIX)(int logL, int E, int tw, int xcd, dim
                                            const Ptrs &p0, const Strides &str, const ColJob *jobs, int njobs,
                                            hipStream_t st) {
   using namespace HK_NS;
-  void *fn = col_kernel(logL, E);
+  void *fn = col_kernel(logL, E, sh.odd > 1);
   KernelLimits k;
   if (!fn || !HK_CAT(limits_, HK_SUFFIX)(logL, E, &k)) return hipErrorInvalidValue;
   const int threads = tw * k.tps;
@@ -273,11 +275,12 @@ static size_t group_lds_elems(int kind, int logL) {
   return mx;
 }
 
-hipError_t HK_CAT(launch_group_, HK_SUFFIX)(const BatchArgs &args, int kind, int logL, int ntasks, hipStream_t st) {
+hipError_t HK_CAT(launch_group_, HK_SUFFIX)(const BatchArgs &args, int kind, int logL, int odd, int ntasks,
+                                            hipStream_t st) {
   using namespace HK_NS;
   if (ntasks <= 0) return hipSuccess;
   if (logL < 0 || logL > MAX_LOGL) return hipErrorInvalidValue;
-  void *fn = group_kernel(kind, logL);
+  void *fn = group_kernel(kind, logL, odd > 1);
   if (!fn) return hipErrorInvalidValue;
   const size_t lds = group_lds_elems(kind, logL) * sizeof(cx<T>);
   hipError_t e = ensure_lds(fn, lds);

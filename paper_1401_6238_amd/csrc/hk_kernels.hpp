@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
       }
       return;
     }
-    const cx<T> part = RB::run_fwd_rows(sh, P, row0, rows, K, true, t, lds, false, g_tw24, g_tw4096);
+    const cx<T> part = RB::run_fwd_rows(sh, P, row0, rows, K, t, lds, g_tw24, g_tw4096);
     if (sh.want_alpha) {
       // One partial sum per workgroup; the next kernel in the stream (pass D
       // or the reduction kernel) adds them in index order.  No cross-workgroup
@@ -119,7 +119,8 @@ __device__ __forceinline__ Tile3 xcd_local_tile() {
   return Tile3{xcd * per + j % per, slice % gy, slice / gy};
 }
 
-template <int L, int E, int MAXT>
+// ODDC: transforms of odd factor 3 or 5 (tiles over virtual columns).
+template <int L, int E, int MAXT, bool ODDC = false>
 __global__ void __launch_bounds__(MAXT) k_cols(Shape sh, Ptrs p0, Strides str, ColJobs jobs) {
   using CB = ColBody<T, L, E>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -134,16 +135,17 @@ __global__ void __launch_bounds__(MAXT) k_cols(Shape sh, Ptrs p0, Strides str, C
     reduce_partials(sh, P, job.npart, smem);
     __syncthreads();
   }
-  if (sh.odd > 1) {
+  if constexpr (ODDC) {
     // tiles over the odd * R virtual columns; a tile inside one sequence
     // whose storage columns are all pruned has nothing to do
     const int64_t R = (int64_t)1 << sh.logR;
     if (v0 >= (int64_t)sh.odd * R) return;
     if (TW <= R && (v0 & (R - 1)) >= job.ncols) return;
-  } else if (v0 >= job.ncols) {
-    return;
+    CB::run_odd(sh, P, job, v0, TW, threadIdx.x, smem, g_tw24, g_tw4096);
+  } else {
+    if (v0 >= job.ncols) return;
+    CB::run(sh, P, job, v0, TW, threadIdx.x, smem, g_tw24, g_tw4096);
   }
-  CB::run(sh, P, job, v0, TW, threadIdx.x, smem, g_tw24, g_tw4096);
 }
 
 }  // namespace HK_NS
@@ -205,7 +207,7 @@ __device__ __forceinline__ void batch_rowb_body(const BatchArgs &A, const Task &
   }
 }
 
-template <int L>
+template <int L, bool ODDC = false>
 __device__ __forceinline__ void batch_col_body(const Task &tk, const Shape &sh, const PV &P, cx<T> *smem, int tid) {
   using CB = ColBody<T, L, BATCH_E_COL>;
   constexpr int TW = BATCH_BLK / CB::TPS;
@@ -224,7 +226,11 @@ __device__ __forceinline__ void batch_col_body(const Task &tk, const Shape &sh, 
     const int64_t lim = tk.a == 0 ? sh.out_rows : sh.out1_len;
     job.ncols = min(((int64_t)1 << sh.logR), lim);
   }
-  CB::run(sh, P, job, tk.b, TW, tid, smem, g_tw24, g_tw4096);  // LDS sized by batch_geometry
+  // LDS sized by batch_geometry
+  if constexpr (ODDC)
+    CB::run_odd(sh, P, job, tk.b, TW, tid, smem, g_tw24, g_tw4096);
+  else
+    CB::run(sh, P, job, tk.b, TW, tid, smem, g_tw24, g_tw4096);
 }
 
 #ifndef HK_ROWS_ONLY
@@ -336,15 +342,15 @@ __global__ void __launch_bounds__(BATCH_BLK) k_group(BatchArgs A) {
   const int tid = threadIdx.x;
   const int32_t ti = A.order[A.begin + (int32_t)blockIdx.x];
   const Task tk = A.tasks[ti];
-  if (KIND == GK_RES) {
+  if constexpr (KIND == GK_RES) {
     batch_res_body<L, ODD>(A, tk, smem, tid);
   } else {
     const Shape &sh = A.shapes[tk.inst];
     const PV P{&A.ptrs[tk.inst], nullptr, 0, A.ws_base};
-    if (KIND == GK_ROWB)
+    if constexpr (KIND == GK_ROWB)
       batch_rowb_body<L, ODD>(A, tk, sh, P, smem, tid);
-    else if (KIND == GK_COL)
-      batch_col_body<L>(tk, sh, P, smem, tid);
+    else if constexpr (KIND == GK_COL)
+      batch_col_body<L, (ODD > 1)>(tk, sh, P, smem, tid);
     else
       reduce_partials(sh, P, tk.nrowb, smem);
   }

@@ -38,7 +38,8 @@ hipError_t launch_kernel(const void *fn, dim3 grid, dim3 block, void **args, siz
   hipError_t launch_alpha_##SUFFIX(const Shape &sh, const Ptrs &p0, const Strides &str, int64_t npart,       \
                                    int64_t count, hipStream_t st);                                     \
   void batch_geometry_##SUFFIX(int *blk, int *e_row, int *e_col, size_t *lds_bytes);                 \
-  hipError_t launch_group_##SUFFIX(const BatchArgs &args, int kind, int logL, int ntasks, hipStream_t st); \
+  hipError_t launch_group_##SUFFIX(const BatchArgs &args, int kind, int logL, int odd, int ntasks,      \
+                                   hipStream_t st);                                                 \
   hipError_t launch_cols_##SUFFIX(int logL, int E, int tw, int xcd, dim3 grid, const Shape &sh,         \
                                   const Ptrs &p0, const Strides &str, const ColJob *jobs, int njobs,    \
                                   hipStream_t st);

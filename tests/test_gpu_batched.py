@@ -134,16 +134,21 @@ def test_plan_matches_plain_path():
     plan.close()
 
 
-def test_plan_graph_replays():
-    """Graph replays with eager work in between; every replay checked."""
+@pytest.mark.parametrize("mode", ["persistent", "grouped"])
+def test_plan_graph_replays(mode):
+    """Graph replays with eager work in between; every replay checked.  The
+    grouped plan's graph holds its launches on several streams (forked and
+    joined per phase)."""
     import paper_1401_6238_amd as hk
     from paper_1401_6238_amd import _lib
     dtype = torch.complex64
+    print_case(test="plan_graph_replays", mode=mode)
     probs = mixed_problems(33, 30)
     items = plan_inputs(probs, dtype)
     s = torch.cuda.Stream()
+    base = _lib.HK_PLAN_PERSISTENT if mode == "persistent" else _lib.HK_PLAN_MULTIKERNEL
     with torch.cuda.stream(s):
-        plan = hk.Plan(items, flags=_lib.HK_PLAN_PERSISTENT | _lib.HK_PLAN_GRAPH)
+        plan = hk.Plan(items, flags=base | _lib.HK_PLAN_GRAPH)
         for rep in range(3):
             for y, a in plan.outputs:
                 if y is not None:
