@@ -40,9 +40,9 @@ static Status prepare(const Problem &p, int64_t batch, Shape *sh, Ptrs *P, Sched
   if (!s.ok()) return s;
   Sched sch;
   const int logM = lay.logR + lay.logC;
-  if (sched_lookup(p.dt, p.prog, p.is_block ? 1 : 0, lay.odd, logM, p.is_block ? lay.logC : -1, batch, &sch)) {
+  if (sched_lookup(p.dt, p.prog, p.is_block ? 1 : 0, lay.lclass(), logM, p.is_block ? lay.logC : -1, batch, &sch)) {
     Layout l2;
-    if (layout_for(p, sch.split, &l2).ok() && l2.odd == lay.odd && sched_valid(p.dt, l2, sch))
+    if (layout_for(p, sch.split, &l2).ok() && l2.lclass() == lay.lclass() && sched_valid(p.dt, l2, sch))
       lay = l2;
     else
       sch = default_sched(p.dt, lay, p.prog, batch);

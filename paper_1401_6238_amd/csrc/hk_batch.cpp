@@ -106,8 +106,9 @@ static void build_groups(hk_plan_s *p) {
       int kind, logL, odd = 1;
       if (t.type == TASK_RES) {
         kind = GK_RES;
-        logL = p->shapes[p->res_list[t.inst]].logR;
-        odd = p->shapes[p->res_list[t.inst]].odd;
+        const Shape &rs = p->shapes[p->res_list[t.inst]];
+        logL = rs.logR;
+        odd = rs.r2c ? 2 : rs.odd;  // 2: real-input rows
       } else if (t.type == TASK_ROWB) {
         kind = GK_ROWB;
         logL = p->shapes[t.inst].logR;
@@ -194,6 +195,13 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
   const int e_odd = dbl(dt) ? odd_row_e_f64() : odd_row_e_f32();
   auto row_tps = [&](const Shape &sh) {
     KernelLimits k;
+    if (sh.r2c) {
+      if (dbl(dt))
+        limits_r2c_f64(sh.logR, r2c_row_e_f64(), &k);
+      else
+        limits_r2c_f32(sh.logR, r2c_row_e_f32(), &k);
+      return k.tps;
+    }
     if (sh.odd > 1) {
       row_limits(dt, sh.odd, sh.logR, e_odd, &k);
       return k.tps;
@@ -249,7 +257,8 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
       multi.push_back({i, (double)((int64_t)sh.odd << (sh.logR + sh.logC)) * (sh.nops + 1)});
     } else {
       P.ws = nullptr;
-      groups[std::make_tuple(sh.logR, sh.odd, sh.nops, sh.want_y, sh.want_alpha, sh.real_out)].push_back((int32_t)i);
+      groups[std::make_tuple(sh.logR, sh.r2c ? 2 : sh.odd, sh.nops, sh.want_y, sh.want_alpha, sh.real_out)].push_back(
+          (int32_t)i);
     }
     p->shapes[i] = sh;
     p->ptrs[i] = P;
@@ -447,7 +456,9 @@ static Status enqueue(hk_plan_s *p, char *ws, hipStream_t st) {
       A.end = g.begin + g.count;
       count_launch();
       prof_before(gs);
-      if (g.odd > 1 && g.kind != GK_COL)
+      if (g.odd == 2 && g.kind == GK_RES)
+        e = dbl(p->dt) ? launch_group_r2c_f64(A, g.logL, g.count, gs) : launch_group_r2c_f32(A, g.logL, g.count, gs);
+      else if (g.odd > 1 && g.kind != GK_COL)
         e = dbl(p->dt) ? launch_group_odd_f64(A, g.odd, g.kind, g.logL, g.count, gs)
                        : launch_group_odd_f32(A, g.odd, g.kind, g.logL, g.count, gs);
       else
@@ -768,8 +779,8 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   if (e != hipSuccess) return hip_fail(e, "autotune buffers");
   if (!s.ok()) return s;
   if (best >= 1e30) return fail(HK_ERR_NOT_SUPPORTED, "autotune found no schedule");
-  sched_store(dt, p.prog, p.is_block ? 1 : 0, lay0.odd, lay0.logR + lay0.logC, p.is_block ? lay0.logC : -1, batch,
-              bestsc);
+  sched_store(dt, p.prog, p.is_block ? 1 : 0, lay0.lclass(), lay0.logR + lay0.logC, p.is_block ? lay0.logC : -1,
+              batch, bestsc);
   if (verbose)
     fprintf(stderr,
             "[hk autotune] best of %d: split=%d (odd=%d R=2^%d C=2^%d) E_row=%d rows=%d iters=%d E_col=%d tw=%d "

@@ -788,6 +788,130 @@ struct RowBody {
 };
 
 // ---------------------------------------------------------------------------
+// Real-input rows (forward program, resident): the zero-padded real vectors of
+// length N = 2L are read as L complex pairs z_j = v_{2j} + i v_{2j+1}, so one
+// length-L transform Z per operand gives its length-N real transform
+//   V_k = (Z_k + conj Z_{L-k}) / 2 - i W_N^k (Z_k - conj Z_{L-k}) / 2,  k < L,
+//   V_L = Re Z_0 - Im Z_0,
+// the other half being conj(V_{N-k}) (Hermitian).  The spectral product runs
+// on bins 0..L.  Its transform y = fft(z^) is real and comes out packed,
+// y_{2j} + i y_{2j+1} = FFT_L(Q)_j with
+//   Q_k = (z^_k + conj z^_{L-k}) + i W_N^k (z^_k - conj z^_{L-k}),
+// and alpha = t_0 + t_L + 2 Re sum_{0<k<L} t_k over the half spectrum.  The
+// mirror bins L - k sit on other lanes; they pass through the row's LDS.
+// Published method: the half-length complex FFT for real data (two real
+// sequences packed into one complex transform, then split by symmetry).
+// ---------------------------------------------------------------------------
+template <typename T, int L, int E>
+struct RealRowBody {
+  using S = FFTShape<L, E>;
+  static constexpr int EE = S::EE;
+  static constexpr int TPS = S::TPS;
+  static constexpr int SEQ_LDS = S::ROW_SEQ > L ? S::ROW_SEQ : L;
+  static constexpr bool WAVE = TPS <= 64;
+
+  // z_j for the lane's slots j = t + s TPS, real entries past `len` zero
+  static __device__ __forceinline__ void load(cx<T> (&a)[EE], const void *src, int64_t len, bool valid, int t) {
+    const T *p = (const T *)src;
+    T re[EE], im[EE];
+#pragma unroll
+    for (int s = 0; s < EE; ++s) {
+      const int64_t j2 = 2 * (int64_t)(t + s * TPS);
+      const bool ok0 = valid && j2 < len, ok1 = valid && j2 + 1 < len;
+      re[s] = p[ok0 ? j2 : 0];
+      im[s] = p[ok1 ? j2 + 1 : 0];
+      re[s] = ok0 ? re[s] : T(0);
+      im[s] = ok1 ? im[s] : T(0);
+    }
+#pragma unroll
+    for (int s = 0; s < EE; ++s) a[s] = mk(re[s], im[s]);
+  }
+
+  // m[s] = a at the mirror bin (L - j) mod L of the lane's slot j
+  static __device__ __forceinline__ void mirror(cx<T> (&m)[EE], const cx<T> (&a)[EE], int t, cx<T> *lds) {
+    seq_sync<WAVE>();
+#pragma unroll
+    for (int s = 0; s < EE; ++s) lds[t + s * TPS] = a[s];
+    seq_sync<WAVE>();
+#pragma unroll
+    for (int s = 0; s < EE; ++s) m[s] = lds[(L - (t + s * TPS)) & (L - 1)];
+  }
+
+  static __device__ __forceinline__ cx<T> run_fwd(const Shape &sh, const PV &P, bool valid, int t, cx<T> *lds,
+                                                  const cx<T> *tw24, const cx<T> *tw4096) {
+    constexpr int LOGN = S::LOGL + 1;
+    const T invN = T(1) / T(2 * L);
+    cx<T> a[EE], nx[EE], acc[EE], w[EE], m[EE];
+    cx<T> accn = czero<T>();  // bin L (real for real inputs)
+    T part = T(0);
+    slot_twiddles<T, EE>(w, 1, t, TPS, LOGN, tw24, tw4096);  // W_N^j
+    StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
+    load(a, P.op(0), sh.ops[0].len, valid, t);
+#pragma unroll
+    for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
+    for (int o = 0; o < sh.nops; ++o) {
+      if (o + 1 < sh.nops) load(nx, P.op(o + 1), sh.ops[o + 1].len, valid, t);
+      fft_seq<T, L, E, WAVE>(a, t, lds, stw);
+      mirror(m, a, t, lds);
+      const T vn = a[0].x - a[0].y;  // V_L (meaningful on the lane with slot j = 0)
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        const cx<T> zm = cconj(m[s]);
+        const cx<T> sp = cadd(a[s], zm), df = csub(a[s], zm);
+        // (sp - i w df) / 2
+        const cx<T> wd = cmul(w[s], df);
+        a[s] = mk(T(0.5) * (sp.x + wd.y), T(0.5) * (sp.y - wd.x));
+      }
+      const OpDesc &od = sh.ops[o];
+      if (od.role == ROLE_H) {
+#pragma unroll
+        for (int s = 0; s < EE; ++s) acc[s] = cscale(cconj(a[s]), invN);
+        accn = mk(vn * invN, T(0));
+      } else {
+        for (int e = 0; e < od.exp; ++e) {
+#pragma unroll
+          for (int s = 0; s < EE; ++s) acc[s] = cmul(acc[s], a[s]);
+          accn.x *= vn;
+        }
+        if (od.flags & OPF_ALPHA) {
+#pragma unroll
+          for (int s = 0; s < EE; ++s) {
+            const T tre = acc[s].x * a[s].x - acc[s].y * a[s].y;  // Re(acc V)
+            part += (t + s * TPS == 0) ? tre : T(2) * tre;
+          }
+          if (t == 0) part += accn.x * vn;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < EE; ++s) a[s] = nx[s];
+    }
+    if (sh.want_y) {
+      mirror(m, acc, t, lds);
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        const cx<T> zm = cconj((t + s * TPS == 0) ? accn : m[s]);
+        const cx<T> sp = cadd(acc[s], zm), df = csub(acc[s], zm);
+        const cx<T> wd = cmul(w[s], df);
+        acc[s] = mk(sp.x - wd.y, sp.y + wd.x);  // sp + i w df
+      }
+      fft_seq<T, L, E, WAVE>(acc, t, lds, stw);
+      if (valid) {
+        T *dst = (T *)P.y();
+        const int64_t lim = sh.out_rows;
+#pragma unroll
+        for (int s = 0; s < EE; ++s) {
+          const int64_t j2 = 2 * (int64_t)(t + s * TPS);
+          if (j2 < lim) dst[j2] = acc[s].x;
+          if (j2 + 1 < lim) dst[j2 + 1] = acc[s].y;
+        }
+      }
+    }
+    return mk(part, T(0));
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Column body: TW columns of length L (one sequence each), TPS lanes per
 // column, lane l -> column l % TW, position-lane l / TW (so that a wave
 // reads TW contiguous elements of several rows at once).  Columns are

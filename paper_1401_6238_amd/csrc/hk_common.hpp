@@ -68,6 +68,9 @@ struct Shape {
   int32_t row_iters;   // multipass row pass: rows each lane group handles in turn
   int32_t odd;         // odd factor of the 1D transform length (1, 3 or 5; 1 for BHHB)
   int32_t odd_inv;     // M^{-1} mod odd (0 when odd == 1)
+  int32_t r2c;         // real inputs, resident: length-N real transforms as length-N/2
+                       // complex ones (logR = log2(N/2)); forward program only
+  int32_t pad0;
   int64_t out_rows;    // output slice: 1D length / BHHB rows n_1; adjoint grad_h length
   int64_t out_cols;    // BHHB columns N_1 (1 for 1D)
   int64_t out1_len;    // adjoint grad_x length

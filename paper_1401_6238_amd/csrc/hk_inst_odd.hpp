@@ -12,6 +12,7 @@
 #pragma once
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -129,6 +130,40 @@ static KernelLimits lim_pick(int logL) {
   }
 }
 
+// Real-input resident rows: R2C_E elements per lane, up to 512 lanes (rows up
+// to 4096 in float, 2048 in double).
+constexpr int R2C_MAXT = 512;
+template <int L>
+static KernelLimits lim_r2c() {
+  using RB = RealRowBody<T, L, R2C_E>;
+  KernelLimits k;
+  k.tps = RB::TPS;
+  k.seq_lds = RB::SEQ_LDS;
+  k.lds_raw = RB::SEQ_LDS;
+  k.elem_bytes = (int)sizeof(cx<T>);
+  k.row_maxt = R2C_MAXT;
+  return k;
+}
+#define HK_R2C_CASES(X) X(0, 1) X(1, 2) X(2, 4) X(3, 8) X(4, 16) X(5, 32) X(6, 64) X(7, 128) X(8, 256) \
+  X(9, 512) X(10, 1024) X(11, 2048) X(12, 4096)
+static bool r2c_pick(int logL, KernelLimits *k, void **row, void **group) {
+  if ((1 << logL) / R2C_E > R2C_MAXT) return false;  // a row must fit one workgroup
+  switch (logL) {
+#define HK_R2C_CASE(lg, L)                                        \
+  case lg:                                                        \
+    if constexpr (L / R2C_E <= R2C_MAXT) {                        \
+      *k = lim_r2c<L>();                                          \
+      *row = (void *)&k_rows_r2c<L, R2C_E, R2C_MAXT>;             \
+      *group = (void *)&k_group_r2c<L>;                           \
+      return true;                                                \
+    }                                                             \
+    return false;
+    HK_R2C_CASES(HK_R2C_CASE)
+#undef HK_R2C_CASE
+  }
+  return false;
+}
+
 static std::mutex g_attr_mu;
 
 static hipError_t ensure_lds(void *fn, size_t bytes) {
@@ -171,6 +206,8 @@ bool HK_CAT(limits_odd_, HK_SUFFIX)(int odd, int logL, int E, KernelLimits *out)
 
 int HK_CAT(odd_row_e_, HK_SUFFIX)() { return HK_NS::ODD_E; }
 
+int HK_CAT(r2c_row_e_, HK_SUFFIX)() { return HK_NS::R2C_E; }
+
 bool HK_CAT(odd_bwd_ok_, HK_SUFFIX)(int odd) { return HK_NS::has_bwd(odd); }
 
 hipError_t HK_CAT(launch_rows_odd_, HK_SUFFIX)(int odd, int logL, int E, int rows_per_wg, dim3 grid,
@@ -193,6 +230,47 @@ hipError_t HK_CAT(launch_rows_odd_, HK_SUFFIX)(int odd, int logL, int E, int row
   int64_t cnt = count;
   void *args[] = {&shc, &pc, &sc, &cnt};
   return launch_kernel(fn, grid, dim3(threads), args, lds, st);
+}
+
+bool HK_CAT(limits_r2c_, HK_SUFFIX)(int logL, int E, KernelLimits *out) {
+  using namespace HK_NS;
+  void *r, *g;
+  if (E != R2C_E) return false;
+  return r2c_pick(logL, out, &r, &g);
+}
+
+hipError_t HK_CAT(launch_rows_r2c_, HK_SUFFIX)(int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh,
+                                               const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st) {
+  using namespace HK_NS;
+  KernelLimits k;
+  void *fn = nullptr, *g = nullptr;
+  if (E != R2C_E || !sh.r2c || !r2c_pick(logL, &k, &fn, &g)) return hipErrorInvalidValue;
+  const int threads = rows_per_wg * k.tps;
+  if (threads < 1 || threads > R2C_MAXT) return hipErrorInvalidValue;
+  size_t lds = (size_t)rows_per_wg * k.seq_lds * sizeof(cx<T>);
+  lds = std::max(lds, (size_t)threads * sizeof(cx<T>));
+  hipError_t e = ensure_lds(fn, lds);
+  if (e != hipSuccess) return e;
+  Shape shc = sh;
+  Ptrs pc = p0;
+  Strides sc = str;
+  int64_t cnt = count;
+  void *args[] = {&shc, &pc, &sc, &cnt};
+  return launch_kernel(fn, grid, dim3(threads), args, lds, st);
+}
+
+hipError_t HK_CAT(launch_group_r2c_, HK_SUFFIX)(const BatchArgs &args, int logL, int ntasks, hipStream_t st) {
+  using namespace HK_NS;
+  if (ntasks <= 0) return hipSuccess;
+  KernelLimits k;
+  void *r = nullptr, *fn = nullptr;
+  if (!r2c_pick(logL, &k, &r, &fn) || k.tps > BATCH_BLK) return hipErrorInvalidValue;
+  const size_t lds = std::max((size_t)BATCH_BLK, (size_t)(BATCH_BLK / k.tps) * k.seq_lds) * sizeof(cx<T>);
+  hipError_t e = ensure_lds(fn, lds);
+  if (e != hipSuccess) return e;
+  BatchArgs a = args;
+  void *kargs[] = {&a};
+  return launch_kernel(fn, dim3((unsigned)ntasks), dim3(BATCH_BLK), kargs, lds, st);
 }
 
 hipError_t HK_CAT(launch_group_odd_, HK_SUFFIX)(const BatchArgs &args, int odd, int kind, int logL, int ntasks,

@@ -76,6 +76,26 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
   }
 }
 
+// Real-input resident rows (RealRowBody): instance blockIdx.x * rows + rw.
+template <int L, int E, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_rows_r2c(Shape sh, Ptrs p0, Strides str, int64_t count) {
+  using RB = RealRowBody<T, L, E>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *smem = (cx<T> *)smem_raw;
+  const int tid = threadIdx.x;
+  const int rw = tid / RB::TPS;
+  const int t = tid % RB::TPS;
+  const int rows = blockDim.x / RB::TPS;
+  const int64_t inst = (int64_t)blockIdx.x * rows + rw;
+  const bool valid = inst < count;
+  const PV P{&p0, &str, valid ? inst : 0, nullptr};
+  const cx<T> part = RB::run_fwd(sh, P, valid, t, smem + rw * RB::SEQ_LDS, g_tw24, g_tw4096);
+  if (sh.want_alpha) {
+    const cx<T> tot = segment_sum(part, smem, tid, RB::TPS);
+    if (valid && t == 0) store_out<T>(P.alpha(), 0, tot, sh.real_out);
+  }
+}
+
 // Deterministic sum of the pass-B partial sums of one instance (count
 // partials, fixed tree order) by one workgroup; lane 0 stores the scalar
 // product.  `red` holds at least blockDim.x elements.
@@ -353,6 +373,29 @@ __global__ void __launch_bounds__(BATCH_BLK) k_group(BatchArgs A) {
       batch_col_body<L, (ODD > 1)>(tk, sh, P, smem, tid);
     else
       reduce_partials(sh, P, tk.nrowb, smem);
+  }
+}
+
+// Grouped real-input resident rows: task = up to BATCH_BLK / TPS instances.
+// Elements per lane: 8 in float, 4 in double (8 would spill).
+enum : int { R2C_E = sizeof(T) == 4 ? 8 : 4 };
+template <int L>
+__global__ void __launch_bounds__(BATCH_BLK) k_group_r2c(BatchArgs A) {
+  using RB = RealRowBody<T, L, R2C_E>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *smem = (cx<T> *)smem_raw;
+  const int tid = threadIdx.x;
+  const Task tk = A.tasks[A.order[A.begin + (int32_t)blockIdx.x]];
+  const int rw = tid / RB::TPS;
+  const int t = tid % RB::TPS;
+  const bool valid = rw < tk.a;
+  const int32_t inst = A.res_list[tk.inst + (valid ? rw : 0)];
+  const Shape &sh = A.shapes[inst];
+  const PV P{&A.ptrs[inst], nullptr, 0, nullptr};
+  const cx<T> part = RB::run_fwd(sh, P, valid, t, smem + rw * RB::SEQ_LDS, g_tw24, g_tw4096);
+  if (sh.want_alpha) {
+    const cx<T> tot = segment_sum(part, smem, tid, RB::TPS);
+    if (valid && t == 0) store_out<T>(P.alpha(), 0, tot, sh.real_out);
   }
 }
 

@@ -55,7 +55,12 @@ HK_DECLARE_LAUNCHERS(f64)
   hipError_t launch_rows_odd_##SUFFIX(int odd, int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh, \
                                       const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st);   \
   hipError_t launch_group_odd_##SUFFIX(const BatchArgs &args, int odd, int kind, int logL, int ntasks,     \
-                                       hipStream_t st);
+                                       hipStream_t st);                                                  \
+  bool limits_r2c_##SUFFIX(int logL, int E, KernelLimits *out);                                         \
+  int r2c_row_e_##SUFFIX();                                                                             \
+  hipError_t launch_rows_r2c_##SUFFIX(int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh,       \
+                                      const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st);   \
+  hipError_t launch_group_r2c_##SUFFIX(const BatchArgs &args, int logL, int ntasks, hipStream_t st);
 
 HK_DECLARE_ODD_LAUNCHERS(f32)
 HK_DECLARE_ODD_LAUNCHERS(f64)

@@ -107,6 +107,17 @@ bool row_limits(hk_dtype_t dt, int odd, int logL, int E, KernelLimits *k) {
 
 static int odd_row_e(hk_dtype_t dt) { return is_double(dt) ? odd_row_e_f64() : odd_row_e_f32(); }
 
+// Real-input rows: elements per lane and limits.
+static int r2c_row_e(hk_dtype_t dt) { return is_double(dt) ? r2c_row_e_f64() : r2c_row_e_f32(); }
+static bool r2c_limits(hk_dtype_t dt, int logL, int E, KernelLimits *k) {
+  return is_double(dt) ? limits_r2c_f64(logL, E, k) : limits_r2c_f32(logL, E, k);
+}
+
+bool layout_row_limits(hk_dtype_t dt, const Layout &lay, int E, KernelLimits *k) {
+  if (lay.r2c) return r2c_limits(dt, lay.logR, E, k);
+  return row_limits(dt, lay.odd, lay.logR, E, k);
+}
+
 // Longest row (log2) the row kernels of odd factor `odd` handle in this
 // precision and program (-1: none).
 static int odd_max_logl(hk_dtype_t dt, int odd, int prog) {
@@ -136,6 +147,20 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd) {
     int64_t dh = 1 - p.m;
     for (int q = 0; q < p.m; ++q) dh += p.dims[q];
     if (ceil_log2(dh) > HK_MAX_FFT_LOG2) return fail(HK_ERR_SIZE_LIMIT, "padded length exceeds 2^24");
+    // Real forward products that fit one workgroup: a length-N real transform
+    // (N = 2^k >= max(d_H, 2)) as a length-N/2 complex one.
+    if (allow_odd && p.prog == PROG_FWD && !is_complex(p.dt)) {
+      const int logN = std::max(1, ceil_log2(dh));
+      KernelLimits k;
+      if (r2c_limits(p.dt, logN - 1, r2c_row_e(p.dt), &k)) {
+        lay.r2c = true;
+        lay.resident = true;
+        lay.logR = logN - 1;
+        lay.logC = 0;
+        *out = lay;
+        return Status();
+      }
+    }
     // The smallest N = odd * 2^logM >= d_H among the lengths with kernels.
     int64_t bestN = -1;
     for (int odd : {1, 3, 5}) {
@@ -191,6 +216,7 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
   sh.logR = lay.logR;
   sh.logC = lay.logC;
   sh.resident = lay.resident ? 1 : 0;
+  sh.r2c = lay.r2c ? 1 : 0;
   sh.odd = lay.odd;
   sh.odd_inv = 0;
   if (lay.odd > 1) {
@@ -305,12 +331,13 @@ static bool lim(hk_dtype_t dt, int logL, int E, KernelLimits *k) {
 
 bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
   KernelLimits kr, kc;
-  if (!row_limits(dt, lay.odd, lay.logR, sc.E_row, &kr)) return false;
+  if (!layout_row_limits(dt, lay, sc.E_row, &kr)) return false;
   if (sc.rows_per_wg < 1 || sc.rows_per_wg * kr.tps > kr.row_maxt) return false;
   const size_t row_lds = std::max((size_t)sc.rows_per_wg * kr.seq_lds, (size_t)sc.rows_per_wg * kr.tps) * kr.elem_bytes;
   if (row_lds > 160 * 1024) return false;
   if (sc.iters != 1 && (lay.resident || (sc.iters != 2 && sc.iters != 4))) return false;
   if (!lay.resident) {
+    if (sc.E_col != 8 && sc.E_col != 16) return false;  // the column kernels built
     if (!lim(dt, lay.logC, sc.E_col, &kc)) return false;
     if (sc.tw < 1 || sc.tw * kc.tps > COL_MAXT) return false;
     if ((size_t)sc.tw * kc.lds_raw * kc.elem_bytes > 160 * 1024) return false;
@@ -321,11 +348,11 @@ bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
 Sched default_sched(hk_dtype_t dt, const Layout &lay, int prog, int64_t batch) {
   Sched sc;
   const bool dbl = is_double(dt);
-  sc.E_row = lay.odd > 1 ? odd_row_e(dt) : 8;
+  sc.E_row = lay.r2c ? r2c_row_e(dt) : (lay.odd > 1 ? odd_row_e(dt) : 8);
   sc.E_col = dbl ? 8 : 16;
   KernelLimits kr, kc;
-  row_limits(dt, lay.odd, lay.logR, sc.E_row, &kr);
-  if (lay.odd == 1 && kr.tps > ROW_MAXT) {  // 4096-point rows need 16 elements per lane
+  layout_row_limits(dt, lay, sc.E_row, &kr);
+  if (lay.odd == 1 && !lay.r2c && kr.tps > ROW_MAXT) {  // 4096-point rows need 16 elements per lane
     sc.E_row = 16;
     lim(dt, lay.logR, sc.E_row, &kr);
   }
@@ -434,7 +461,10 @@ static hipError_t rows(hk_dtype_t dt, int logL, int E, int rpw, dim3 g, const Sh
   count_launch();
   prof_before(st);
   hipError_t e;
-  if (sh.odd > 1)
+  if (sh.r2c)
+    e = is_double(dt) ? launch_rows_r2c_f64(logL, E, rpw, g, sh, p0, str, cnt, st)
+                      : launch_rows_r2c_f32(logL, E, rpw, g, sh, p0, str, cnt, st);
+  else if (sh.odd > 1)
     e = is_double(dt) ? launch_rows_odd_f64(sh.odd, logL, E, rpw, g, sh, p0, str, cnt, st)
                       : launch_rows_odd_f32(sh.odd, logL, E, rpw, g, sh, p0, str, cnt, st);
   else
@@ -617,9 +647,10 @@ void sched_store(hk_dtype_t dt, int prog, int is_block, int odd, int logM, int l
 }
 
 // Text database, one schedule per line:
-//   dtype prog is_block odd logM logC_hint batch_class : E_row rows_per_wg E_col tw split xcd iters
-// (logM = log2 of the power-of-two factor of the transform length; xcd and
-// iters may be omitted: 0 and 1).  Lines with six key fields (no odd factor)
+//   dtype prog is_block lclass logM logC_hint batch_class : E_row rows_per_wg E_col tw split xcd iters
+// (lclass = the odd factor 1, 3 or 5 of the transform length, or 2 for real
+// inputs transformed at half length; logM = log2 of its power-of-two part;
+// xcd and iters may be omitted: 0 and 1).  Lines with six key fields (no odd factor)
 // are read as odd = 1.  '#' starts a comment line.
 static const char *kDbHeader =
     "# hankel schedule database v4: dt prog blk odd logM logC bclass : E_row rows E_col tw split xcd iters\n";
@@ -678,7 +709,7 @@ Status sched_load(const char *path, int *loaded) {
       break;
     }
     const bool key_ok = k[0] >= HK_C64 && k[0] <= HK_F64 && (k[1] == PROG_FWD || k[1] == PROG_BWD) &&
-                        (k[2] == 0 || k[2] == 1) && (k[3] == 1 || k[3] == 3 || k[3] == 5) && k[4] >= 0 &&
+                        (k[2] == 0 || k[2] == 1) && (k[3] == 1 || k[3] == 2 || k[3] == 3 || k[3] == 5) && k[4] >= 0 &&
                         k[4] <= HK_MAX_FFT_LOG2 && k[5] >= -1 && k[5] <= HK_MAX_FFT_LOG2 && k[6] >= 0 && k[6] <= 2;
     Sched s;
     s.E_row = v[0];

@@ -59,8 +59,11 @@ struct Sched {
 
 struct Layout {
   bool resident = false;
-  int odd = 1;  // 1D: transform length odd * 2^(logR + logC)
+  int odd = 1;       // 1D: transform length odd * 2^(logR + logC)
+  bool r2c = false;  // real inputs, resident: length 2^(logR + 1) real transforms
   int logR = 0, logC = 0;
+  // length class of the schedule key: 1, 3, 5 = odd factor, 2 = real inputs
+  int lclass() const { return r2c ? 2 : odd; }
 };
 
 bool is_complex(hk_dtype_t dt);
@@ -73,9 +76,13 @@ Status validate_forward(const Problem &p);
 Status validate_backward(const Problem &p);
 
 // Shape construction.  `layout` decides the transform length (the smallest
-// 2^k, 3 * 2^k or 5 * 2^k >= d_H with kernels; powers of two only when
-// allow_odd is false), resident vs multipass and the split.
+// 2^k, 3 * 2^k or 5 * 2^k >= d_H with kernels; for real forward products
+// with N <= 8192 a length-N real transform done as a length-N/2 complex one;
+// powers of two only when allow_odd is false), resident vs multipass and the
+// split.
 Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd = true);
+// Kernel limits of a layout's rows (odd factor and real-input aware).
+bool layout_row_limits(hk_dtype_t dt, const Layout &lay, int E, KernelLimits *k);
 // Row-kernel limits of a layout's row length (odd factor aware).
 bool row_limits(hk_dtype_t dt, int odd, int logL, int E, KernelLimits *k);
 Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *sh, Ptrs *ptrs,
