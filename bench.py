@@ -569,6 +569,31 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
     log("mixed batch", res)
     del items
 
+    # real inputs: 4096 float problems (m in {3,4,5}, equal vectors, n log-uniform with
+    # d_H <= 8192, uniform[-1,1] entries as in the small real case), y and alpha; the
+    # real-input rows (length-N real transforms at half length) against the same plan
+    # restricted to power-of-two complex transforms
+    g = np.random.Generator(np.random.PCG64(14016238 + 7000))
+    ritems = []
+    for i in range(4096):
+        mr = int(g.integers(3, 6))
+        nmax = (8192 - 1) // mr + 1
+        nr = int(np.exp(g.uniform(np.log(64), np.log(nmax))))
+        hr = torch.from_numpy(g.uniform(-1, 1, mr * (nr - 1) + 1)).to(torch.float32).to(dev)
+        xr = torch.from_numpy(g.uniform(-1, 1, nr)).to(torch.float32).to(dev)
+        ritems.append({"m": mr, "dims": [nr] * mr, "h": hr, "vectors": [xr] * mr, "want_alpha": True})
+    resr = {}
+    for name, flags in (("real_rows", _lib.HK_PLAN_MULTIKERNEL),
+                        ("complex_pow2", _lib.HK_PLAN_MULTIKERNEL | _lib.HK_PLAN_POW2)):
+        plan = hk.Plan(ritems, flags=flags)
+        ms = time_region(torch, plan.execute, 10)
+        plan.status()
+        resr[name] = {"TVP_s": round(len(ritems) / ms * 1000, 1), "ms_per_batch": round(ms, 3)}
+        plan.close()
+    ex["real_batch_f32"] = resr
+    log("real batch", resr)
+    del ritems
+
     # adjoint batch: 256 instances, m=4, n=2^16: forward (g, f) and adjoint, c64 and c128
     adj = data["adjoint"]
     res4 = {}

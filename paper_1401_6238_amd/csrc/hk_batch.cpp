@@ -112,14 +112,14 @@ static void build_groups(hk_plan_s *p) {
       } else if (t.type == TASK_ROWB) {
         kind = GK_ROWB;
         logL = p->shapes[t.inst].logR;
-        odd = p->shapes[t.inst].odd;
+        odd = p->shapes[t.inst].r2c ? 2 : p->shapes[t.inst].odd;  // 2: real-input row pairs
       } else if (t.type == TASK_ALPHA) {
         kind = GK_ALPHA;
         logL = 0;
       } else {
         kind = GK_COL;
         logL = p->shapes[t.inst].logC;
-        odd = p->shapes[t.inst].odd;
+        odd = p->shapes[t.inst].r2c ? 2 : p->shapes[t.inst].odd;  // 2: real arrays as pairs
       }
       keyed.push_back({std::make_tuple(kind, logL, odd), i});
     }
@@ -195,11 +195,18 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
   const int e_odd = dbl(dt) ? odd_row_e_f64() : odd_row_e_f32();
   auto row_tps = [&](const Shape &sh) {
     KernelLimits k;
-    if (sh.r2c) {
+    if (sh.r2c && sh.resident) {
       if (dbl(dt))
         limits_r2c_f64(sh.logR, r2c_row_e_f64(), &k);
       else
         limits_r2c_f32(sh.logR, r2c_row_e_f32(), &k);
+      return k.tps;
+    }
+    if (sh.r2c) {  // row pairs
+      if (dbl(dt))
+        limits_r2cp_f64(sh.logR, 4, &k);
+      else
+        limits_r2cp_f32(sh.logR, 4, &k);
       return k.tps;
     }
     if (sh.odd > 1) {
@@ -298,7 +305,8 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
     const Shape &sh = p->shapes[in.idx];
     const int rows = std::max(1, blk / row_tps(sh));
     const int64_t C = (int64_t)1 << sh.logC;
-    const int32_t nb = (int32_t)((C + rows - 1) / rows);
+    const int64_t brows = sh.r2c ? C / 2 : C;  // real inputs: mirrored row pairs
+    const int32_t nb = (int32_t)((brows + rows - 1) / rows);
     for (int32_t b = 0; b < nb; ++b) {
       Task t = {TASK_ROWB, (int32_t)in.idx, (int32_t)(b * rows), b, nb};
       p->tasks.push_back(t);
@@ -317,7 +325,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
     const Shape &sh = p->shapes[in.idx];
     if (!sh.want_y) continue;
     const int tw = std::max(1, blk / tps(sh.logC, ec));
-    const int64_t ncols = std::min<int64_t>((int64_t)1 << sh.logR, sh.out_rows);
+    const int64_t ncols = std::min<int64_t>((int64_t)1 << sh.logR, sh.r2c ? (sh.out_rows + 1) / 2 : sh.out_rows);
     for (int64_t c0 : col_tiles(sh, ncols, tw)) {
       Task t = {TASK_COLD, (int32_t)in.idx, 0, (int32_t)c0, 0};
       p->tasks.push_back(t);
@@ -458,6 +466,9 @@ static Status enqueue(hk_plan_s *p, char *ws, hipStream_t st) {
       prof_before(gs);
       if (g.odd == 2 && g.kind == GK_RES)
         e = dbl(p->dt) ? launch_group_r2c_f64(A, g.logL, g.count, gs) : launch_group_r2c_f32(A, g.logL, g.count, gs);
+      else if (g.odd == 2 && g.kind == GK_ROWB)
+        e = dbl(p->dt) ? launch_group_r2cp_f64(A, g.logL, g.count, gs)
+                       : launch_group_r2cp_f32(A, g.logL, g.count, gs);
       else if (g.odd > 1 && g.kind != GK_COL)
         e = dbl(p->dt) ? launch_group_odd_f64(A, g.odd, g.kind, g.logL, g.count, gs)
                        : launch_group_odd_f32(A, g.odd, g.kind, g.logL, g.count, gs);

@@ -1114,6 +1114,202 @@ struct ColBody {
       }
     }
   }
+
+  // Real-input transforms of length 2 * 2^(logR + logC): operands and output
+  // are real arrays read and written as complex pairs (entry e = c + R k of
+  // the complex view is real entries 2e and 2e + 1, each range-checked on its
+  // own, so padding and the slice need no compares).
+  static __device__ __forceinline__ void run_r2c(const Shape &sh, const PV &P, const ColJob &job, int64_t c0,
+                                                 int TW, int tid, cx<T> *lds, const cx<T> *tw24,
+                                                 const cx<T> *tw4096) {
+    const int cw = tid % TW;
+    const int t = tid / TW;
+    const int64_t c = c0 + cw;
+    const bool cvalid = c < job.ncols;
+    const int64_t R = (int64_t)1 << sh.logR;
+    const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+    constexpr int CB = (int)sizeof(cx<T>), TB = (int)sizeof(T);
+    cx<T> a[EE];
+    if (job.kind == COL_A) {
+      const auto r = make_buf(P.op(job.op), sh.ops[job.op].len * TB);
+      T re[EE], im[EE];
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        const uint32_t off = (uint32_t)(2 * (c + R * (t + s * TPS)) * TB);
+        re[s] = BufIO<T>::ld1(r, off);
+        im[s] = BufIO<T>::ld1(r, off + TB);
+      }
+#pragma unroll
+      for (int s = 0; s < EE; ++s) a[s] = mk(re[s], im[s]);
+    } else {
+      const auto r = make_buf(ws_buf<T>(sh, P, job.buf), N * CB);
+      uint32_t off[EE];
+#pragma unroll
+      for (int s = 0; s < EE; ++s) off[s] = (uint32_t)((c + R * (t + s * TPS)) * CB);
+      bgather<T, EE>(a, r, off, 0);
+    }
+    StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
+    fft_seq<T, L, E>(a, t, lds + cw, stw, __builtin_ctz((unsigned)TW));
+    if (!cvalid) return;
+    if (job.kind == COL_A) {
+      const auto r = make_buf(ws_buf<T>(sh, P, job.buf), N * CB);
+#pragma unroll
+      for (int s = 0; s < EE; ++s) BufIO<T>::template st<ST_DEFAULT>(a[s], r, off_ws(c, R, t + s * TPS));
+    } else {
+      const auto r = make_buf(job.op == 0 ? P.y() : P.out1(), sh.out_rows * TB);
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        const uint32_t off = (uint32_t)(2 * (c + R * (t + s * TPS)) * TB);
+        BufIO<T>::template st1<ST_DEFAULT>(a[s].x, r, off);
+        BufIO<T>::template st1<ST_DEFAULT>(a[s].y, r, off + TB);
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Pass B of multipass real-input transforms (complex length N' = R C, real
+// length N = 2 N').  Bin k of row r sits at position k1 with k = r + C k1; its
+// mirror N' - k is in row C - r at position R - 1 - k1, and for rows 0 and
+// C / 2 in the same row at positions -k1 mod R and R - 1 - k1.  A lane group
+// therefore takes the row pair (p, C - p), or (0, C / 2) for p = 0, so that
+// the real transform's split and the output's packing (see RealRowBody) find
+// every mirror bin among its two rows (through LDS).
+// ---------------------------------------------------------------------------
+template <typename T, int L, int E>
+struct RealPairRowBody {
+  using S = FFTShape<L, E>;
+  using RB = RowBody<T, L, E, 1>;
+  static constexpr int EE = S::EE;
+  static constexpr int TPS = S::TPS;
+  static constexpr int SEQ_LDS = S::ROW_SEQ > 2 * L ? S::ROW_SEQ : 2 * L;
+  static constexpr bool WAVE = TPS <= 64;
+
+  // W_N^{r + C (t + s TPS)}, N = 2 R C
+  static __device__ __forceinline__ void split_tw(cx<T> (&w)[EE], const Shape &sh, int64_t r, int t,
+                                                  const cx<T> *tw24, const cx<T> *tw4096) {
+    const int logN = sh.logR + sh.logC + 1;
+    slot_twiddles<T, EE>(w, (int64_t)1 << sh.logC, t, TPS, logN, tw24, tw4096);
+    const cx<T> wr = twiddle_big<T>(r, logN, tw24, tw4096);
+#pragma unroll
+    for (int s = 0; s < EE; ++s) w[s] = cmul(w[s], wr);
+  }
+
+  static __device__ __forceinline__ void mirror(cx<T> (&ma)[EE], cx<T> (&mb)[EE], const cx<T> (&a)[EE],
+                                                const cx<T> (&b)[EE], bool self, int t, cx<T> *lds) {
+    cx<T> *la = lds, *lb = lds + L;
+    seq_sync<WAVE>();
+#pragma unroll
+    for (int s = 0; s < EE; ++s) {
+      la[t + s * TPS] = a[s];
+      lb[t + s * TPS] = b[s];
+    }
+    seq_sync<WAVE>();
+#pragma unroll
+    for (int s = 0; s < EE; ++s) {
+      const int k1 = t + s * TPS;
+      const int rev = L - 1 - k1;
+      ma[s] = (self ? la : lb)[self ? ((L - k1) & (L - 1)) : rev];
+      mb[s] = (self ? lb : la)[rev];
+    }
+  }
+
+  // V = (Z + conj Zm) / 2 - i w (Z - conj Zm) / 2
+  static __device__ __forceinline__ void split(cx<T> (&a)[EE], const cx<T> (&m)[EE], const cx<T> (&w)[EE]) {
+#pragma unroll
+    for (int s = 0; s < EE; ++s) {
+      const cx<T> zm = cconj(m[s]);
+      const cx<T> sp = cadd(a[s], zm), df = csub(a[s], zm);
+      const cx<T> wd = cmul(w[s], df);
+      a[s] = mk(T(0.5) * (sp.x + wd.y), T(0.5) * (sp.y - wd.x));
+    }
+  }
+  // Q = (z + conj zm) + i w (z - conj zm)
+  static __device__ __forceinline__ void pack(cx<T> (&a)[EE], const cx<T> (&m)[EE], const cx<T> (&w)[EE]) {
+#pragma unroll
+    for (int s = 0; s < EE; ++s) {
+      const cx<T> zm = cconj(m[s]);
+      const cx<T> sp = cadd(a[s], zm), df = csub(a[s], zm);
+      const cx<T> wd = cmul(w[s], df);
+      a[s] = mk(sp.x - wd.y, sp.y + wd.x);
+    }
+  }
+
+  // Forward program on row pair p; returns the lane's share of alpha.
+  static __device__ __forceinline__ cx<T> run_fwd(const Shape &sh, const PV &P, int64_t p, bool valid, int t,
+                                                  cx<T> *lds, const cx<T> *tw24, const cx<T> *tw4096) {
+    const int64_t C = (int64_t)1 << sh.logC;
+    const bool self = p == 0;
+    const int64_t ra = p, rb = self ? C / 2 : C - p;
+    const T invN = T(1) / T((int64_t)2 << (sh.logR + sh.logC));
+    cx<T> a[EE], b[EE], ma[EE], mb[EE], accA[EE], accB[EE], w4a[EE], w4b[EE], wua[EE], wub[EE];
+    cx<T> accn = czero<T>();
+    T part = T(0);
+    RB::twiddles(w4a, sh, ra, t, false, tw24, tw4096);
+    RB::twiddles(w4b, sh, rb, t, false, tw24, tw4096);
+    split_tw(wua, sh, ra, t, tw24, tw4096);
+    split_tw(wub, sh, rb, t, tw24, tw4096);
+    StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
+#pragma unroll
+    for (int s = 0; s < EE; ++s) {
+      accA[s] = czero<T>();
+      accB[s] = czero<T>();
+    }
+    const bool lane0 = self && t == 0;  // holds bin 0 (row 0, position 0) and the bin N'
+    for (int o = 0; o < sh.nops; ++o) {
+      RB::load(a, sh, P, o, ra, valid, t, false);
+      RB::load(b, sh, P, o, rb, valid, t, false);
+      RB::twiddle_in(a, w4a, true);
+      RB::twiddle_in(b, w4b, true);
+      RB::fft(a, t, lds, stw);
+      RB::fft(b, t, lds, stw);
+      const T vn = a[0].x - a[0].y;  // bin N' (on lane0)
+      mirror(ma, mb, a, b, self, t, lds);
+      split(a, ma, wua);
+      split(b, mb, wub);
+      const OpDesc &od = sh.ops[o];
+      if (od.role == ROLE_H) {
+#pragma unroll
+        for (int s = 0; s < EE; ++s) {
+          accA[s] = cscale(cconj(a[s]), invN);
+          accB[s] = cscale(cconj(b[s]), invN);
+        }
+        accn = mk(vn * invN, T(0));
+      } else {
+        for (int e = 0; e < od.exp; ++e) {
+#pragma unroll
+          for (int s = 0; s < EE; ++s) {
+            accA[s] = cmul(accA[s], a[s]);
+            accB[s] = cmul(accB[s], b[s]);
+          }
+          accn.x *= vn;
+        }
+        if (od.flags & OPF_ALPHA) {
+#pragma unroll
+          for (int s = 0; s < EE; ++s) {
+            const T ta = accA[s].x * a[s].x - accA[s].y * a[s].y;
+            const T tb = accB[s].x * b[s].x - accB[s].y * b[s].y;
+            part += (lane0 && s == 0) ? ta : T(2) * ta;  // bin 0 counts once
+            part += T(2) * tb;
+          }
+          if (lane0) part += accn.x * vn;
+        }
+      }
+    }
+    if (sh.want_y) {
+      mirror(ma, mb, accA, accB, self, t, lds);
+      if (lane0) ma[0] = accn;  // the mirror of bin 0 is bin N'
+      pack(accA, ma, wua);
+      pack(accB, mb, wub);
+      RB::fft(accA, t, lds, stw);
+      RB::store(accA, sh, P, 0, ra, valid, t, false, w4a);
+      RB::fft(accB, t, lds, stw);
+      RB::store(accB, sh, P, 0, rb, valid, t, false, w4b);
+    }
+    return mk(part, T(0));
+  }
 };
 
 }  // namespace hk

@@ -18,8 +18,10 @@ static void *row_fn(int prog) {
   return prog == PROG_BWD ? (void *)&k_rows<L, E, ROW_MAXT, PROG_BWD> : (void *)&k_rows<L, E, ROW_MAXT, PROG_FWD>;
 }
 template <int L, int E>
-static void *col_fn(bool oddc) {
-  return oddc ? (void *)&k_cols<L, E, COL_MAXT, true> : (void *)&k_cols<L, E, COL_MAXT, false>;
+static void *col_fn(int var) {
+  if (var == CV_ODD) return (void *)&k_cols<L, E, COL_MAXT, CV_ODD>;
+  if (var == CV_R2C) return (void *)&k_cols<L, E, COL_MAXT, CV_R2C>;
+  return (void *)&k_cols<L, E, COL_MAXT, CV_POW2>;
 }
 
 template <int E>
@@ -42,21 +44,21 @@ static void *pick_row(int logL, int prog) {
   return nullptr;
 }
 template <int E>
-static void *pick_col(int logL, bool oddc) {
+static void *pick_col(int logL, int var) {
   switch (logL) {
-    case 0: return col_fn<1, E>(oddc);
-    case 1: return col_fn<2, E>(oddc);
-    case 2: return col_fn<4, E>(oddc);
-    case 3: return col_fn<8, E>(oddc);
-    case 4: return col_fn<16, E>(oddc);
-    case 5: return col_fn<32, E>(oddc);
-    case 6: return col_fn<64, E>(oddc);
-    case 7: return col_fn<128, E>(oddc);
-    case 8: return col_fn<256, E>(oddc);
-    case 9: return col_fn<512, E>(oddc);
-    case 10: return col_fn<1024, E>(oddc);
-    case 11: return col_fn<2048, E>(oddc);
-    case 12: return col_fn<4096, E>(oddc);
+    case 0: return col_fn<1, E>(var);
+    case 1: return col_fn<2, E>(var);
+    case 2: return col_fn<4, E>(var);
+    case 3: return col_fn<8, E>(var);
+    case 4: return col_fn<16, E>(var);
+    case 5: return col_fn<32, E>(var);
+    case 6: return col_fn<64, E>(var);
+    case 7: return col_fn<128, E>(var);
+    case 8: return col_fn<256, E>(var);
+    case 9: return col_fn<512, E>(var);
+    case 10: return col_fn<1024, E>(var);
+    case 11: return col_fn<2048, E>(var);
+    case 12: return col_fn<4096, E>(var);
   }
   return nullptr;
 }
@@ -67,10 +69,10 @@ static void *row_kernel(int logL, int E, int prog) {
   if (E == 16) return pick_row<16>(logL, prog);
   return nullptr;
 }
-static void *col_kernel(int logL, int E, bool oddc) {
+static void *col_kernel(int logL, int E, int var) {
   if (logL < 0 || logL > MAX_LOGL) return nullptr;
-  if (E == 8) return pick_col<8>(logL, oddc);
-  if (E == 16) return pick_col<16>(logL, oddc);
+  if (E == 8) return pick_col<8>(logL, var);
+  if (E == 16) return pick_col<16>(logL, var);
   return nullptr;
 }
 
@@ -106,32 +108,36 @@ static KernelLimits lim_pick(int logL) {
 }
 
 // Column tasks of odd-factor transforms run in the ODD = 3 variant of the
-// column group kernel (their odd factor is read from the shape).
+// column group kernel (their odd factor is read from the shape), those of
+// real-input transforms in the ODD = 2 one.
 template <int L>
-static void *group_fn(int kind, bool oddc) {
+static void *group_fn(int kind, int var) {
   switch (kind) {
-    case GK_RES: return oddc ? nullptr : (void *)&k_group<L, GK_RES>;
-    case GK_ROWB: return oddc ? nullptr : (void *)&k_group<L, GK_ROWB>;
-    case GK_COL: return oddc ? (void *)&k_group<L, GK_COL, 3> : (void *)&k_group<L, GK_COL>;
+    case GK_RES: return var != CV_POW2 ? nullptr : (void *)&k_group<L, GK_RES>;
+    case GK_ROWB: return var != CV_POW2 ? nullptr : (void *)&k_group<L, GK_ROWB>;
+    case GK_COL:
+      if (var == CV_ODD) return (void *)&k_group<L, GK_COL, 3>;
+      if (var == CV_R2C) return (void *)&k_group<L, GK_COL, 2>;
+      return (void *)&k_group<L, GK_COL>;
   }
   return nullptr;
 }
-static void *group_kernel(int kind, int logL, bool oddc) {
+static void *group_kernel(int kind, int logL, int var) {
   if (kind == GK_ALPHA) return (void *)&k_group<1, GK_ALPHA>;
   switch (logL) {
-    case 0: return group_fn<1>(kind, oddc);
-    case 1: return group_fn<2>(kind, oddc);
-    case 2: return group_fn<4>(kind, oddc);
-    case 3: return group_fn<8>(kind, oddc);
-    case 4: return group_fn<16>(kind, oddc);
-    case 5: return group_fn<32>(kind, oddc);
-    case 6: return group_fn<64>(kind, oddc);
-    case 7: return group_fn<128>(kind, oddc);
-    case 8: return group_fn<256>(kind, oddc);
-    case 9: return group_fn<512>(kind, oddc);
-    case 10: return group_fn<1024>(kind, oddc);
-    case 11: return group_fn<2048>(kind, oddc);
-    case 12: return group_fn<4096>(kind, oddc);
+    case 0: return group_fn<1>(kind, var);
+    case 1: return group_fn<2>(kind, var);
+    case 2: return group_fn<4>(kind, var);
+    case 3: return group_fn<8>(kind, var);
+    case 4: return group_fn<16>(kind, var);
+    case 5: return group_fn<32>(kind, var);
+    case 6: return group_fn<64>(kind, var);
+    case 7: return group_fn<128>(kind, var);
+    case 8: return group_fn<256>(kind, var);
+    case 9: return group_fn<512>(kind, var);
+    case 10: return group_fn<1024>(kind, var);
+    case 11: return group_fn<2048>(kind, var);
+    case 12: return group_fn<4096>(kind, var);
   }
   return nullptr;
 }
@@ -204,7 +210,7 @@ hipError_t HK_CAT(launch_cols_, HK_SUFFIX)(int logL, int E, int tw, int xcd, dim
                                            const Ptrs &p0, const Strides &str, const ColJob *jobs, int njobs,
                                            hipStream_t st) {
   using namespace HK_NS;
-  void *fn = col_kernel(logL, E, sh.odd > 1);
+  void *fn = col_kernel(logL, E, sh.r2c ? CV_R2C : (sh.odd > 1 ? CV_ODD : CV_POW2));
   KernelLimits k;
   if (!fn || !HK_CAT(limits_, HK_SUFFIX)(logL, E, &k)) return hipErrorInvalidValue;
   const int threads = tw * k.tps;
@@ -280,7 +286,7 @@ hipError_t HK_CAT(launch_group_, HK_SUFFIX)(const BatchArgs &args, int kind, int
   using namespace HK_NS;
   if (ntasks <= 0) return hipSuccess;
   if (logL < 0 || logL > MAX_LOGL) return hipErrorInvalidValue;
-  void *fn = group_kernel(kind, logL, odd > 1);
+  void *fn = group_kernel(kind, logL, odd == 2 ? CV_R2C : (odd > 1 ? CV_ODD : CV_POW2));
   if (!fn) return hipErrorInvalidValue;
   const size_t lds = group_lds_elems(kind, logL) * sizeof(cx<T>);
   hipError_t e = ensure_lds(fn, lds);

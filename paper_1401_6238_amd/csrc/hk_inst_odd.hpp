@@ -164,6 +164,37 @@ static bool r2c_pick(int logL, KernelLimits *k, void **row, void **group) {
   return false;
 }
 
+// Pass-B row pairs of multipass real-input transforms: R2C_PAIR_E elements
+// per lane, up to 512 lanes (rows up to 2048).
+template <int L>
+static KernelLimits lim_r2cp() {
+  using PB = RealPairRowBody<T, L, R2C_PAIR_E>;
+  KernelLimits k;
+  k.tps = PB::TPS;
+  k.seq_lds = PB::SEQ_LDS;
+  k.lds_raw = PB::SEQ_LDS;
+  k.elem_bytes = (int)sizeof(cx<T>);
+  k.row_maxt = R2C_MAXT;
+  return k;
+}
+static bool r2cp_pick(int logL, KernelLimits *k, void **row, void **group) {
+  if (logL > 11) return false;
+  switch (logL) {
+#define HK_R2CP_CASE(lg, L)                                          \
+  case lg:                                                           \
+    if constexpr (L <= 2048) {                                       \
+      *k = lim_r2cp<L>();                                            \
+      *row = (void *)&k_rows_r2c_pairs<L, R2C_PAIR_E, R2C_MAXT>;     \
+      *group = (void *)&k_group_r2c_pairs<L>;                        \
+      return true;                                                   \
+    }                                                                \
+    return false;
+    HK_R2C_CASES(HK_R2CP_CASE)
+#undef HK_R2CP_CASE
+  }
+  return false;
+}
+
 static std::mutex g_attr_mu;
 
 static hipError_t ensure_lds(void *fn, size_t bytes) {
@@ -265,6 +296,47 @@ hipError_t HK_CAT(launch_group_r2c_, HK_SUFFIX)(const BatchArgs &args, int logL,
   KernelLimits k;
   void *r = nullptr, *fn = nullptr;
   if (!r2c_pick(logL, &k, &r, &fn) || k.tps > BATCH_BLK) return hipErrorInvalidValue;
+  const size_t lds = std::max((size_t)BATCH_BLK, (size_t)(BATCH_BLK / k.tps) * k.seq_lds) * sizeof(cx<T>);
+  hipError_t e = ensure_lds(fn, lds);
+  if (e != hipSuccess) return e;
+  BatchArgs a = args;
+  void *kargs[] = {&a};
+  return launch_kernel(fn, dim3((unsigned)ntasks), dim3(BATCH_BLK), kargs, lds, st);
+}
+
+bool HK_CAT(limits_r2cp_, HK_SUFFIX)(int logL, int E, KernelLimits *out) {
+  using namespace HK_NS;
+  void *r, *g;
+  if (E != R2C_PAIR_E) return false;
+  return r2cp_pick(logL, out, &r, &g);
+}
+
+hipError_t HK_CAT(launch_rows_r2cp_, HK_SUFFIX)(int logL, int E, int groups_per_wg, dim3 grid, const Shape &sh,
+                                                const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st) {
+  using namespace HK_NS;
+  KernelLimits k;
+  void *fn = nullptr, *g = nullptr;
+  if (E != R2C_PAIR_E || !sh.r2c || sh.resident || !r2cp_pick(logL, &k, &fn, &g)) return hipErrorInvalidValue;
+  const int threads = groups_per_wg * k.tps;
+  if (threads < 1 || threads > R2C_MAXT) return hipErrorInvalidValue;
+  size_t lds = (size_t)groups_per_wg * k.seq_lds * sizeof(cx<T>);
+  lds = std::max(lds, (size_t)threads * sizeof(cx<T>));
+  hipError_t e = ensure_lds(fn, lds);
+  if (e != hipSuccess) return e;
+  Shape shc = sh;
+  Ptrs pc = p0;
+  Strides sc = str;
+  int64_t cnt = count;
+  void *args[] = {&shc, &pc, &sc, &cnt};
+  return launch_kernel(fn, grid, dim3(threads), args, lds, st);
+}
+
+hipError_t HK_CAT(launch_group_r2cp_, HK_SUFFIX)(const BatchArgs &args, int logL, int ntasks, hipStream_t st) {
+  using namespace HK_NS;
+  if (ntasks <= 0) return hipSuccess;
+  KernelLimits k;
+  void *r = nullptr, *fn = nullptr;
+  if (!r2cp_pick(logL, &k, &r, &fn) || k.tps > BATCH_BLK) return hipErrorInvalidValue;
   const size_t lds = std::max((size_t)BATCH_BLK, (size_t)(BATCH_BLK / k.tps) * k.seq_lds) * sizeof(cx<T>);
   hipError_t e = ensure_lds(fn, lds);
   if (e != hipSuccess) return e;

@@ -96,6 +96,28 @@ __global__ void __launch_bounds__(MAXT) k_rows_r2c(Shape sh, Ptrs p0, Strides st
   }
 }
 
+// Pass B of multipass real-input transforms (RealPairRowBody): row pairs
+// blockIdx.x * groups + rw of instance blockIdx.y.
+template <int L, int E, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_rows_r2c_pairs(Shape sh, Ptrs p0, Strides str, int64_t count) {
+  using PB = RealPairRowBody<T, L, E>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *smem = (cx<T> *)smem_raw;
+  const int tid = threadIdx.x;
+  const int rw = tid / PB::TPS;
+  const int t = tid % PB::TPS;
+  const int groups = blockDim.x / PB::TPS;
+  const PV P{&p0, &str, (int64_t)blockIdx.y, nullptr};
+  const int64_t npairs = ((int64_t)1 << sh.logC) / 2;
+  const int64_t pi = (int64_t)blockIdx.x * groups + rw;
+  const bool valid = pi < npairs;
+  const cx<T> part = PB::run_fwd(sh, P, valid ? pi : 0, valid, t, smem + rw * PB::SEQ_LDS, g_tw24, g_tw4096);
+  if (sh.want_alpha) {
+    const cx<T> tot = segment_sum(part, smem, tid, (int)blockDim.x);
+    if (tid == 0) ws_partials<T>(sh, P)[blockIdx.x] = tot;
+  }
+}
+
 // Deterministic sum of the pass-B partial sums of one instance (count
 // partials, fixed tree order) by one workgroup; lane 0 stores the scalar
 // product.  `red` holds at least blockDim.x elements.
@@ -139,8 +161,10 @@ __device__ __forceinline__ Tile3 xcd_local_tile() {
   return Tile3{xcd * per + j % per, slice % gy, slice / gy};
 }
 
-// ODDC: transforms of odd factor 3 or 5 (tiles over virtual columns).
-template <int L, int E, int MAXT, bool ODDC = false>
+// Column-kernel variants: power-of-two complex transforms, odd factor 3 or 5
+// (tiles over virtual columns), real inputs (real arrays as complex pairs).
+enum ColVar : int { CV_POW2 = 0, CV_ODD = 1, CV_R2C = 2 };
+template <int L, int E, int MAXT, int VAR = CV_POW2>
 __global__ void __launch_bounds__(MAXT) k_cols(Shape sh, Ptrs p0, Strides str, ColJobs jobs) {
   using CB = ColBody<T, L, E>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -155,13 +179,16 @@ __global__ void __launch_bounds__(MAXT) k_cols(Shape sh, Ptrs p0, Strides str, C
     reduce_partials(sh, P, job.npart, smem);
     __syncthreads();
   }
-  if constexpr (ODDC) {
+  if constexpr (VAR == CV_ODD) {
     // tiles over the odd * R virtual columns; a tile inside one sequence
     // whose storage columns are all pruned has nothing to do
     const int64_t R = (int64_t)1 << sh.logR;
     if (v0 >= (int64_t)sh.odd * R) return;
     if (TW <= R && (v0 & (R - 1)) >= job.ncols) return;
     CB::run_odd(sh, P, job, v0, TW, threadIdx.x, smem, g_tw24, g_tw4096);
+  } else if constexpr (VAR == CV_R2C) {
+    if (v0 >= job.ncols) return;
+    CB::run_r2c(sh, P, job, v0, TW, threadIdx.x, smem, g_tw24, g_tw4096);
   } else {
     if (v0 >= job.ncols) return;
     CB::run(sh, P, job, v0, TW, threadIdx.x, smem, g_tw24, g_tw4096);
@@ -227,7 +254,7 @@ __device__ __forceinline__ void batch_rowb_body(const BatchArgs &A, const Task &
   }
 }
 
-template <int L, bool ODDC = false>
+template <int L, int VAR = CV_POW2>
 __device__ __forceinline__ void batch_col_body(const Task &tk, const Shape &sh, const PV &P, cx<T> *smem, int tid) {
   using CB = ColBody<T, L, BATCH_E_COL>;
   constexpr int TW = BATCH_BLK / CB::TPS;
@@ -244,11 +271,14 @@ __device__ __forceinline__ void batch_col_body(const Task &tk, const Shape &sh, 
     job.buf = sh.ops[tk.a].buf;
     job.conj_out = (sh.prog == PROG_BWD && tk.a == 1) ? 1 : 0;
     const int64_t lim = tk.a == 0 ? sh.out_rows : sh.out1_len;
-    job.ncols = min(((int64_t)1 << sh.logR), lim);
+    // real outputs of a real-input transform are stored in pairs
+    job.ncols = min(((int64_t)1 << sh.logR), VAR == CV_R2C ? (lim + 1) / 2 : lim);
   }
   // LDS sized by batch_geometry
-  if constexpr (ODDC)
+  if constexpr (VAR == CV_ODD)
     CB::run_odd(sh, P, job, tk.b, TW, tid, smem, g_tw24, g_tw4096);
+  else if constexpr (VAR == CV_R2C)
+    CB::run_r2c(sh, P, job, tk.b, TW, tid, smem, g_tw24, g_tw4096);
   else
     CB::run(sh, P, job, tk.b, TW, tid, smem, g_tw24, g_tw4096);
 }
@@ -370,7 +400,7 @@ __global__ void __launch_bounds__(BATCH_BLK) k_group(BatchArgs A) {
     if constexpr (KIND == GK_ROWB)
       batch_rowb_body<L, ODD>(A, tk, sh, P, smem, tid);
     else if constexpr (KIND == GK_COL)
-      batch_col_body<L, (ODD > 1)>(tk, sh, P, smem, tid);
+      batch_col_body<L, ODD == 2 ? CV_R2C : (ODD > 1 ? CV_ODD : CV_POW2)>(tk, sh, P, smem, tid);
     else
       reduce_partials(sh, P, tk.nrowb, smem);
   }
@@ -378,7 +408,7 @@ __global__ void __launch_bounds__(BATCH_BLK) k_group(BatchArgs A) {
 
 // Grouped real-input resident rows: task = up to BATCH_BLK / TPS instances.
 // Elements per lane: 8 in float, 4 in double (8 would spill).
-enum : int { R2C_E = sizeof(T) == 4 ? 8 : 4 };
+enum : int { R2C_E = sizeof(T) == 4 ? 8 : 4, R2C_PAIR_E = 4 };
 template <int L>
 __global__ void __launch_bounds__(BATCH_BLK) k_group_r2c(BatchArgs A) {
   using RB = RealRowBody<T, L, R2C_E>;
@@ -396,6 +426,27 @@ __global__ void __launch_bounds__(BATCH_BLK) k_group_r2c(BatchArgs A) {
   if (sh.want_alpha) {
     const cx<T> tot = segment_sum(part, smem, tid, RB::TPS);
     if (valid && t == 0) store_out<T>(P.alpha(), 0, tot, sh.real_out);
+  }
+}
+
+// Grouped pass-B row pairs of real-input transforms: task = pairs tk.a, ...
+template <int L>
+__global__ void __launch_bounds__(BATCH_BLK) k_group_r2c_pairs(BatchArgs A) {
+  using PB = RealPairRowBody<T, L, R2C_PAIR_E>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *smem = (cx<T> *)smem_raw;
+  const int tid = threadIdx.x;
+  const Task tk = A.tasks[A.order[A.begin + (int32_t)blockIdx.x]];
+  const Shape &sh = A.shapes[tk.inst];
+  const PV P{&A.ptrs[tk.inst], nullptr, 0, A.ws_base};
+  const int rw = tid / PB::TPS;
+  const int t = tid % PB::TPS;
+  const int64_t pi = (int64_t)tk.a + rw;
+  const bool valid = pi < ((int64_t)1 << sh.logC) / 2;
+  const cx<T> part = PB::run_fwd(sh, P, valid ? pi : 0, valid, t, smem + rw * PB::SEQ_LDS, g_tw24, g_tw4096);
+  if (sh.want_alpha) {  // partial sum of this task; a TASK_ALPHA adds them up
+    const cx<T> tot = segment_sum(part, smem, tid, BATCH_BLK);
+    if (tid == 0) ws_partials<T>(sh, P)[tk.b] = tot;
   }
 }
 

@@ -60,7 +60,11 @@ HK_DECLARE_LAUNCHERS(f64)
   int r2c_row_e_##SUFFIX();                                                                             \
   hipError_t launch_rows_r2c_##SUFFIX(int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh,       \
                                       const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st);   \
-  hipError_t launch_group_r2c_##SUFFIX(const BatchArgs &args, int logL, int ntasks, hipStream_t st);
+  hipError_t launch_group_r2c_##SUFFIX(const BatchArgs &args, int logL, int ntasks, hipStream_t st);       \
+  bool limits_r2cp_##SUFFIX(int logL, int E, KernelLimits *out);                                        \
+  hipError_t launch_rows_r2cp_##SUFFIX(int logL, int E, int groups_per_wg, dim3 grid, const Shape &sh,    \
+                                       const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st);  \
+  hipError_t launch_group_r2cp_##SUFFIX(const BatchArgs &args, int logL, int ntasks, hipStream_t st);
 
 HK_DECLARE_ODD_LAUNCHERS(f32)
 HK_DECLARE_ODD_LAUNCHERS(f64)

@@ -113,8 +113,14 @@ static bool r2c_limits(hk_dtype_t dt, int logL, int E, KernelLimits *k) {
   return is_double(dt) ? limits_r2c_f64(logL, E, k) : limits_r2c_f32(logL, E, k);
 }
 
+// Pass-B row pairs of multipass real-input transforms: 4 elements per lane.
+constexpr int R2CP_E_ROW = 4;
+static bool r2cp_limits(hk_dtype_t dt, int logL, int E, KernelLimits *k) {
+  return is_double(dt) ? limits_r2cp_f64(logL, E, k) : limits_r2cp_f32(logL, E, k);
+}
+
 bool layout_row_limits(hk_dtype_t dt, const Layout &lay, int E, KernelLimits *k) {
-  if (lay.r2c) return r2c_limits(dt, lay.logR, E, k);
+  if (lay.r2c) return lay.resident ? r2c_limits(dt, lay.logR, E, k) : r2cp_limits(dt, lay.logR, E, k);
   return row_limits(dt, lay.odd, lay.logR, E, k);
 }
 
@@ -147,8 +153,9 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd) {
     int64_t dh = 1 - p.m;
     for (int q = 0; q < p.m; ++q) dh += p.dims[q];
     if (ceil_log2(dh) > HK_MAX_FFT_LOG2) return fail(HK_ERR_SIZE_LIMIT, "padded length exceeds 2^24");
-    // Real forward products that fit one workgroup: a length-N real transform
-    // (N = 2^k >= max(d_H, 2)) as a length-N/2 complex one.
+    // Real forward products: a length-N real transform (N = 2^k >= max(d_H, 2))
+    // as a length-N/2 complex one, in one workgroup or in three passes whose
+    // row pass takes mirrored row pairs.
     if (allow_odd && p.prog == PROG_FWD && !is_complex(p.dt)) {
       const int logN = std::max(1, ceil_log2(dh));
       KernelLimits k;
@@ -158,6 +165,16 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd) {
         lay.logR = logN - 1;
         lay.logC = 0;
         *out = lay;
+        return Status();
+      }
+      int maxR = -1;
+      for (int l = 0; l <= MAX_LOGL; ++l)
+        if (r2cp_limits(p.dt, l, R2CP_E_ROW, &k)) maxR = l;
+      Layout c;
+      if (maxR >= 0 && split_of(logN - 1, split, maxR, &c.logR, &c.logC) && c.logC >= 1) {
+        c.r2c = true;
+        c.resident = false;
+        *out = c;
         return Status();
       }
     }
@@ -240,7 +257,8 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
     od.len = len;
     od.cols = cols;
     od.buf = sh.nops;
-    od.ncol_nz = std::min<int64_t>(R, len);
+    // storage columns that may be nonzero (real inputs: pairs of entries)
+    od.ncol_nz = std::min<int64_t>(R, lay.r2c ? (len + 1) / 2 : len);
     P.op[sh.nops] = ptr;
     if (op_src) op_src[sh.nops] = src;
     ++sh.nops;
@@ -335,7 +353,7 @@ bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
   if (sc.rows_per_wg < 1 || sc.rows_per_wg * kr.tps > kr.row_maxt) return false;
   const size_t row_lds = std::max((size_t)sc.rows_per_wg * kr.seq_lds, (size_t)sc.rows_per_wg * kr.tps) * kr.elem_bytes;
   if (row_lds > 160 * 1024) return false;
-  if (sc.iters != 1 && (lay.resident || (sc.iters != 2 && sc.iters != 4))) return false;
+  if (sc.iters != 1 && (lay.resident || lay.r2c || (sc.iters != 2 && sc.iters != 4))) return false;
   if (!lay.resident) {
     if (sc.E_col != 8 && sc.E_col != 16) return false;  // the column kernels built
     if (!lim(dt, lay.logC, sc.E_col, &kc)) return false;
@@ -348,7 +366,7 @@ bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
 Sched default_sched(hk_dtype_t dt, const Layout &lay, int prog, int64_t batch) {
   Sched sc;
   const bool dbl = is_double(dt);
-  sc.E_row = lay.r2c ? r2c_row_e(dt) : (lay.odd > 1 ? odd_row_e(dt) : 8);
+  sc.E_row = lay.r2c ? (lay.resident ? r2c_row_e(dt) : R2CP_E_ROW) : (lay.odd > 1 ? odd_row_e(dt) : 8);
   sc.E_col = dbl ? 8 : 16;
   KernelLimits kr, kc;
   layout_row_limits(dt, lay, sc.E_row, &kr);
@@ -461,9 +479,12 @@ static hipError_t rows(hk_dtype_t dt, int logL, int E, int rpw, dim3 g, const Sh
   count_launch();
   prof_before(st);
   hipError_t e;
-  if (sh.r2c)
+  if (sh.r2c && sh.resident)
     e = is_double(dt) ? launch_rows_r2c_f64(logL, E, rpw, g, sh, p0, str, cnt, st)
                       : launch_rows_r2c_f32(logL, E, rpw, g, sh, p0, str, cnt, st);
+  else if (sh.r2c)
+    e = is_double(dt) ? launch_rows_r2cp_f64(logL, E, rpw, g, sh, p0, str, cnt, st)
+                      : launch_rows_r2cp_f32(logL, E, rpw, g, sh, p0, str, cnt, st);
   else if (sh.odd > 1)
     e = is_double(dt) ? launch_rows_odd_f64(sh.odd, logL, E, rpw, g, sh, p0, str, cnt, st)
                       : launch_rows_odd_f32(sh.odd, logL, E, rpw, g, sh, p0, str, cnt, st);
@@ -518,14 +539,16 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
   dim3 ga((unsigned)((vcols_a + sc.tw - 1) / sc.tw), (unsigned)sh.nops, (unsigned)count);
   e = cols(dt, sh.logC, sc.E_col, sc.tw, sc.xcd, ga, sh, p0, str, ja, sh.nops, st);
   if (e != hipSuccess) return hip_fail(e, "pass A launch");
-  // Pass B: row transforms, spectral product, row transform of the output.
-  const int64_t rows_wg = (int64_t)sc.rows_per_wg * sc.iters;  // rows per workgroup
-  dim3 gb((unsigned)((C + rows_wg - 1) / rows_wg), (unsigned)count);
+  // Pass B: row transforms, spectral product, row transform of the output
+  // (real inputs: C / 2 mirrored row pairs).
+  const int64_t rows_wg = (int64_t)sc.rows_per_wg * sc.iters;  // rows (pairs) per workgroup
+  const int64_t brows = sh.r2c ? C / 2 : C;
+  dim3 gb((unsigned)((brows + rows_wg - 1) / rows_wg), (unsigned)count);
   e = rows(dt, sh.logR, sc.E_row, sc.rows_per_wg, gb, sh, p0, str, count, st);
   if (e != hipSuccess) return hip_fail(e, "pass B launch");
   // Pass D: column transforms of the outputs and the slice; its first
   // workgroup also sums pass B's scalar partials.
-  const int64_t npart = (sh.prog == PROG_FWD && sh.want_alpha) ? (C + rows_wg - 1) / rows_wg : 0;
+  const int64_t npart = (sh.prog == PROG_FWD && sh.want_alpha) ? (brows + rows_wg - 1) / rows_wg : 0;
   ColJob jd[2];
   memset(jd, 0, sizeof(jd));
   int nd = 0;
@@ -536,7 +559,8 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
     jd[nd].buf = sh.ops[0].buf;
     jd[nd].conj_out = 0;
     jd[nd].npart = npart;
-    jd[nd].ncols = std::min<int64_t>(R, sh.out_rows);
+    // real outputs of real-input transforms are stored in pairs
+    jd[nd].ncols = std::min<int64_t>(R, sh.r2c ? (sh.out_rows + 1) / 2 : sh.out_rows);
     dcols = std::max(dcols, jd[nd].ncols);
     ++nd;
   }

@@ -1,9 +1,10 @@
 """GPU parity of the real-input forward path against the CPU oracle.  Real
-forward products whose padded length N fits one workgroup (N <= 8192 in
-float, 4096 in double) transform each real vector as N/2 complex pairs
-(length-N/2 complex FFT, then the split into the real transform's half
-spectrum by conjugate symmetry), multiply on bins 0..N/2 and return the real
-result packed in pairs.  These cases cover the degenerate lengths (N = 2, 4),
+forward products transform each real vector of padded length N as N/2
+complex pairs (length-N/2 complex FFT, then the split into the real
+transform's half spectrum by conjugate symmetry), multiply on bins 0..N/2 and
+return the real result packed in pairs: in one workgroup up to N = 8192
+(float) / 4096 (double), in three passes beyond (the row pass on mirrored row
+pairs).  These cases cover the degenerate lengths (N = 2, 4),
 odd and even d_H and output lengths, every row length, equal and distinct
 vectors, the scalar product (a half-spectrum sum), strided batches and
 grouped plans (also against the complex path of a power-of-two-only plan).
@@ -63,6 +64,39 @@ def test_strided_batched(dtype, m, n, B):
 
 
 @pytest.mark.parametrize("dtype", REAL)
+@pytest.mark.parametrize("m,n", [(3, 2800), (3, 4000), (4, 5000), (5, 3000), (2, 40000), (3, 30000), (8, 2000)])
+def test_multipass_equal(dtype, m, n):
+    print_case(test="real_multipass_equal", dtype=dtype, m=m, n=n)
+    prob = wl.random_problem(9900 + 7 * m + n, m, [n] * m, True, complex_=False, want_alpha=True)
+    check(prob, dtype)
+
+
+@pytest.mark.parametrize("dtype", REAL)
+@pytest.mark.parametrize("dims", [[5000, 3000, 4001], [20000, 9999], [3001, 2000, 2500, 1800]])
+def test_multipass_distinct(dtype, dims):
+    m = len(dims)
+    print_case(test="real_multipass_distinct", dtype=dtype, dims=dims)
+    prob = wl.random_problem(9950 + sum(dims), m, dims, False, complex_=False, want_alpha=True)
+    check(prob, dtype)
+
+
+@pytest.mark.parametrize("dtype", REAL)
+def test_multipass_strided(dtype):
+    import paper_1401_6238_amd as hk
+    m, n, B = 3, 5000, 3
+    print_case(test="real_multipass_strided", dtype=dtype)
+    probs = [wl.random_problem(9990 + b, m, [n] * m, True, complex_=False, want_alpha=True) for b in range(B)]
+    H = torch.stack([to_dev(p.h, dtype) for p in probs])
+    X = torch.stack([to_dev(p.vectors[1], dtype) for p in probs])
+    y, a = hk.hankel_tvp_strided_batched(H, X, m, True, True)
+    torch.cuda.synchronize()
+    for b, p in enumerate(probs):
+        yo, ao = oracle_problem(p, dtype)
+        assert rel(host(y[b]), yo) <= TOL[dtype]
+        assert abs(complex(host(a[b:b + 1])[0]) - ao) <= 10 * TOL[dtype] * abs(ao)
+
+
+@pytest.mark.parametrize("dtype", REAL)
 def test_plan(dtype):
     """A grouped plan of real problems of many sizes (real rows, and the
     complex path beyond one workgroup) against the oracle, and against the
@@ -74,7 +108,7 @@ def test_plan(dtype):
     probs = []
     for i in range(40):
         m = int(g.integers(2, 6))
-        n = int(np.exp(g.uniform(np.log(2), np.log(4000))))
+        n = int(np.exp(g.uniform(np.log(2), np.log(12000))))
         eq = bool(g.integers(0, 2))
         dims = [n] * m if eq else [max(1, int(n * g.uniform(0.3, 1.0))) for _ in range(m)]
         probs.append(wl.random_problem(9800 + i, m, dims, eq, complex_=False, want_alpha=bool(g.integers(0, 2))))
