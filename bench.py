@@ -528,6 +528,30 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
         ex["large_single_c128"] = {"TVP_s": round(1000 / ms, 1), "ms": round(ms, 4)}
         del hs, xs
         log("c128", ex["large_single_c128"])
+        # the same shape on real data (float, uniform[-1,1] entries): real-input transforms
+        # (length 2^20 real done as 2^19 complex) against the complex path on the same values
+        gr = np.random.Generator(np.random.PCG64(14016238 + 8000))
+        hr = [torch.from_numpy(gr.uniform(-1, 1, DH)).to(torch.float32).to(dev) for _ in range(P)]
+        xr = [torch.from_numpy(gr.uniform(-1, 1, NVEC) / NVEC).to(torch.float32).to(dev) for _ in range(P)]
+        it = [0]
+
+        def one_real():
+            k = it[0] % P
+            it[0] += 1
+            hk.hankel_tvp(hr[k], xr[k], M, True, True)
+        ms_r = time_region(torch, one_real, 50)
+        hc = [v.to(torch.complex64) for v in hr]
+        xc = [v.to(torch.complex64) for v in xr]
+
+        def one_cplx():
+            k = it[0] % P
+            it[0] += 1
+            hk.hankel_tvp(hc[k], xc[k], M, True, True)
+        ms_c = time_region(torch, one_cplx, 50)
+        ex["large_single_real_f32"] = {"real_TVP_s": round(1000 / ms_r, 1), "real_ms": round(ms_r, 4),
+                                       "complex_path_TVP_s": round(1000 / ms_c, 1), "complex_path_ms": round(ms_c, 4)}
+        del hr, xr, hc, xc
+        log("large real", ex["large_single_real_f32"])
 
     # mixed batch: 4096 instances, one persistent launch vs per-pass launches vs plain loop
     mixed = data["mixed"]

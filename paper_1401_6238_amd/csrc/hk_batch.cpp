@@ -204,9 +204,9 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
     }
     if (sh.r2c) {  // row pairs
       if (dbl(dt))
-        limits_r2cp_f64(sh.logR, 4, &k);
+        limits_r2cp_f64(sh.logR, r2c_row_e_f64(), &k);
       else
-        limits_r2cp_f32(sh.logR, 4, &k);
+        limits_r2cp_f32(sh.logR, r2c_row_e_f32(), &k);
       return k.tps;
     }
     if (sh.odd > 1) {

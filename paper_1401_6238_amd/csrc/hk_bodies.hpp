@@ -1172,18 +1172,18 @@ struct ColBody {
 // Pass B of multipass real-input transforms (complex length N' = R C, real
 // length N = 2 N').  Bin k of row r sits at position k1 with k = r + C k1; its
 // mirror N' - k is in row C - r at position R - 1 - k1, and for rows 0 and
-// C / 2 in the same row at positions -k1 mod R and R - 1 - k1.  A lane group
-// therefore takes the row pair (p, C - p), or (0, C / 2) for p = 0, so that
-// the real transform's split and the output's packing (see RealRowBody) find
-// every mirror bin among its two rows (through LDS).
+// C / 2 in the same row at positions -k1 mod R and R - 1 - k1.  Two lane
+// groups of one workgroup take the row pair (p, C - p), or (0, C / 2) for
+// p = 0, one row each, and find every mirror bin of the real transform's split
+// and of the output's packing (see RealRowBody) in the pair's LDS.
 // ---------------------------------------------------------------------------
 template <typename T, int L, int E>
 struct RealPairRowBody {
   using S = FFTShape<L, E>;
   using RB = RowBody<T, L, E, 1>;
   static constexpr int EE = S::EE;
-  static constexpr int TPS = S::TPS;
-  static constexpr int SEQ_LDS = S::ROW_SEQ > 2 * L ? S::ROW_SEQ : 2 * L;
+  static constexpr int TPS = S::TPS;  // lanes per row; a pair takes 2 TPS
+  static constexpr int SEQ_LDS = S::ROW_SEQ > L ? S::ROW_SEQ : L;  // per row; a pair takes 2 SEQ_LDS
   static constexpr bool WAVE = TPS <= 64;
 
   // W_N^{r + C (t + s TPS)}, N = 2 R C
@@ -1196,117 +1196,93 @@ struct RealPairRowBody {
     for (int s = 0; s < EE; ++s) w[s] = cmul(w[s], wr);
   }
 
-  static __device__ __forceinline__ void mirror(cx<T> (&ma)[EE], cx<T> (&mb)[EE], const cx<T> (&a)[EE],
-                                                const cx<T> (&b)[EE], bool self, int t, cx<T> *lds) {
-    cx<T> *la = lds, *lb = lds + L;
-    seq_sync<WAVE>();
+  // m[s] = the mirror of this row's slot s: from the partner row at R - 1 - k1,
+  // or, for the rows 0 and C / 2 (self), from this row.  The barriers span the
+  // workgroup: the partner row is another lane group, and the next transform
+  // writes this row's LDS only after the partner has read it.
+  static __device__ __forceinline__ void mirror(cx<T> (&m)[EE], const cx<T> (&a)[EE], bool self, int g, int t,
+                                                cx<T> *mine, const cx<T> *partner) {
+    __syncthreads();
 #pragma unroll
-    for (int s = 0; s < EE; ++s) {
-      la[t + s * TPS] = a[s];
-      lb[t + s * TPS] = b[s];
-    }
-    seq_sync<WAVE>();
+    for (int s = 0; s < EE; ++s) mine[t + s * TPS] = a[s];
+    __syncthreads();
 #pragma unroll
     for (int s = 0; s < EE; ++s) {
       const int k1 = t + s * TPS;
       const int rev = L - 1 - k1;
-      ma[s] = (self ? la : lb)[self ? ((L - k1) & (L - 1)) : rev];
-      mb[s] = (self ? lb : la)[rev];
+      m[s] = (self ? (const cx<T> *)mine : partner)[(self && g == 0) ? ((L - k1) & (L - 1)) : rev];
     }
+    __syncthreads();
   }
 
-  // V = (Z + conj Zm) / 2 - i w (Z - conj Zm) / 2
-  static __device__ __forceinline__ void split(cx<T> (&a)[EE], const cx<T> (&m)[EE], const cx<T> (&w)[EE]) {
-#pragma unroll
-    for (int s = 0; s < EE; ++s) {
-      const cx<T> zm = cconj(m[s]);
-      const cx<T> sp = cadd(a[s], zm), df = csub(a[s], zm);
-      const cx<T> wd = cmul(w[s], df);
-      a[s] = mk(T(0.5) * (sp.x + wd.y), T(0.5) * (sp.y - wd.x));
-    }
-  }
-  // Q = (z + conj zm) + i w (z - conj zm)
-  static __device__ __forceinline__ void pack(cx<T> (&a)[EE], const cx<T> (&m)[EE], const cx<T> (&w)[EE]) {
-#pragma unroll
-    for (int s = 0; s < EE; ++s) {
-      const cx<T> zm = cconj(m[s]);
-      const cx<T> sp = cadd(a[s], zm), df = csub(a[s], zm);
-      const cx<T> wd = cmul(w[s], df);
-      a[s] = mk(sp.x - wd.y, sp.y + wd.x);
-    }
-  }
-
-  // Forward program on row pair p; returns the lane's share of alpha.
-  static __device__ __forceinline__ cx<T> run_fwd(const Shape &sh, const PV &P, int64_t p, bool valid, int t,
-                                                  cx<T> *lds, const cx<T> *tw24, const cx<T> *tw4096) {
+  // Forward program on row g of pair p; returns the lane's share of alpha.
+  static __device__ __forceinline__ cx<T> run_fwd(const Shape &sh, const PV &P, int64_t p, int g, bool valid, int t,
+                                                  cx<T> *lds_pair, const cx<T> *tw24, const cx<T> *tw4096) {
     const int64_t C = (int64_t)1 << sh.logC;
     const bool self = p == 0;
-    const int64_t ra = p, rb = self ? C / 2 : C - p;
+    const int64_t r = g == 0 ? p : (self ? C / 2 : C - p);
+    cx<T> *mine = lds_pair + g * SEQ_LDS;
+    const cx<T> *partner = lds_pair + (1 - g) * SEQ_LDS;
     const T invN = T(1) / T((int64_t)2 << (sh.logR + sh.logC));
-    cx<T> a[EE], b[EE], ma[EE], mb[EE], accA[EE], accB[EE], w4a[EE], w4b[EE], wua[EE], wub[EE];
+    const bool lane0 = self && g == 0 && t == 0;  // holds bin 0 (row 0, position 0) and the bin N'
+    cx<T> a[EE], nx[EE], m[EE], acc[EE], w4[EE], wu[EE];
     cx<T> accn = czero<T>();
     T part = T(0);
-    RB::twiddles(w4a, sh, ra, t, false, tw24, tw4096);
-    RB::twiddles(w4b, sh, rb, t, false, tw24, tw4096);
-    split_tw(wua, sh, ra, t, tw24, tw4096);
-    split_tw(wub, sh, rb, t, tw24, tw4096);
+    RB::twiddles(w4, sh, r, t, false, tw24, tw4096);
+    split_tw(wu, sh, r, t, tw24, tw4096);
     StageTw<T, L, E> stw;
     stw.init(t, tw4096);
 #pragma unroll
-    for (int s = 0; s < EE; ++s) {
-      accA[s] = czero<T>();
-      accB[s] = czero<T>();
-    }
-    const bool lane0 = self && t == 0;  // holds bin 0 (row 0, position 0) and the bin N'
+    for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
+    RB::load(a, sh, P, 0, r, valid, t, false);
     for (int o = 0; o < sh.nops; ++o) {
-      RB::load(a, sh, P, o, ra, valid, t, false);
-      RB::load(b, sh, P, o, rb, valid, t, false);
-      RB::twiddle_in(a, w4a, true);
-      RB::twiddle_in(b, w4b, true);
-      RB::fft(a, t, lds, stw);
-      RB::fft(b, t, lds, stw);
+      if (o + 1 < sh.nops) RB::load(nx, sh, P, o + 1, r, valid, t, false);
+      RB::twiddle_in(a, w4, true);
+      RB::fft(a, t, mine, stw);
       const T vn = a[0].x - a[0].y;  // bin N' (on lane0)
-      mirror(ma, mb, a, b, self, t, lds);
-      split(a, ma, wua);
-      split(b, mb, wub);
+      mirror(m, a, self, g, t, mine, partner);
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {  // V = (Z + conj Zm) / 2 - i w (Z - conj Zm) / 2
+        const cx<T> zm = cconj(m[s]);
+        const cx<T> sp = cadd(a[s], zm), df = csub(a[s], zm);
+        const cx<T> wd = cmul(wu[s], df);
+        a[s] = mk(T(0.5) * (sp.x + wd.y), T(0.5) * (sp.y - wd.x));
+      }
       const OpDesc &od = sh.ops[o];
       if (od.role == ROLE_H) {
 #pragma unroll
-        for (int s = 0; s < EE; ++s) {
-          accA[s] = cscale(cconj(a[s]), invN);
-          accB[s] = cscale(cconj(b[s]), invN);
-        }
+        for (int s = 0; s < EE; ++s) acc[s] = cscale(cconj(a[s]), invN);
         accn = mk(vn * invN, T(0));
       } else {
         for (int e = 0; e < od.exp; ++e) {
 #pragma unroll
-          for (int s = 0; s < EE; ++s) {
-            accA[s] = cmul(accA[s], a[s]);
-            accB[s] = cmul(accB[s], b[s]);
-          }
+          for (int s = 0; s < EE; ++s) acc[s] = cmul(acc[s], a[s]);
           accn.x *= vn;
         }
         if (od.flags & OPF_ALPHA) {
 #pragma unroll
           for (int s = 0; s < EE; ++s) {
-            const T ta = accA[s].x * a[s].x - accA[s].y * a[s].y;
-            const T tb = accB[s].x * b[s].x - accB[s].y * b[s].y;
-            part += (lane0 && s == 0) ? ta : T(2) * ta;  // bin 0 counts once
-            part += T(2) * tb;
+            const T tr = acc[s].x * a[s].x - acc[s].y * a[s].y;
+            part += (lane0 && s == 0) ? tr : T(2) * tr;  // bin 0 counts once
           }
           if (lane0) part += accn.x * vn;
         }
       }
+#pragma unroll
+      for (int s = 0; s < EE; ++s) a[s] = nx[s];
     }
     if (sh.want_y) {
-      mirror(ma, mb, accA, accB, self, t, lds);
-      if (lane0) ma[0] = accn;  // the mirror of bin 0 is bin N'
-      pack(accA, ma, wua);
-      pack(accB, mb, wub);
-      RB::fft(accA, t, lds, stw);
-      RB::store(accA, sh, P, 0, ra, valid, t, false, w4a);
-      RB::fft(accB, t, lds, stw);
-      RB::store(accB, sh, P, 0, rb, valid, t, false, w4b);
+      mirror(m, acc, self, g, t, mine, partner);
+      if (lane0) m[0] = accn;  // the mirror of bin 0 is bin N'
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {  // Q = (z + conj zm) + i w (z - conj zm)
+        const cx<T> zm = cconj(m[s]);
+        const cx<T> sp = cadd(acc[s], zm), df = csub(acc[s], zm);
+        const cx<T> wd = cmul(wu[s], df);
+        acc[s] = mk(sp.x - wd.y, sp.y + wd.x);
+      }
+      RB::fft(acc, t, mine, stw);
+      RB::store(acc, sh, P, 0, r, valid, t, false, w4);
     }
     return mk(part, T(0));
   }

@@ -164,27 +164,28 @@ static bool r2c_pick(int logL, KernelLimits *k, void **row, void **group) {
   return false;
 }
 
-// Pass-B row pairs of multipass real-input transforms: R2C_PAIR_E elements
-// per lane, up to 512 lanes (rows up to 2048).
+// Pass-B row pairs of multipass real-input transforms: R2C_E elements per
+// lane, a row per lane group, two lane groups per pair (limits are per pair:
+// tps = lanes of a pair, seq_lds = its LDS), at most 512 lanes per pair.
 template <int L>
 static KernelLimits lim_r2cp() {
-  using PB = RealPairRowBody<T, L, R2C_PAIR_E>;
+  using PB = RealPairRowBody<T, L, R2C_E>;
   KernelLimits k;
-  k.tps = PB::TPS;
-  k.seq_lds = PB::SEQ_LDS;
-  k.lds_raw = PB::SEQ_LDS;
+  k.tps = 2 * PB::TPS;
+  k.seq_lds = 2 * PB::SEQ_LDS;
+  k.lds_raw = 2 * PB::SEQ_LDS;
   k.elem_bytes = (int)sizeof(cx<T>);
   k.row_maxt = R2C_MAXT;
   return k;
 }
 static bool r2cp_pick(int logL, KernelLimits *k, void **row, void **group) {
-  if (logL > 11) return false;
+  if (2 * ((1 << logL) / R2C_E) > R2C_MAXT) return false;
   switch (logL) {
 #define HK_R2CP_CASE(lg, L)                                          \
   case lg:                                                           \
-    if constexpr (L <= 2048) {                                       \
+    if constexpr (2 * (L / R2C_E) <= R2C_MAXT) {                     \
       *k = lim_r2cp<L>();                                            \
-      *row = (void *)&k_rows_r2c_pairs<L, R2C_PAIR_E, R2C_MAXT>;     \
+      *row = (void *)&k_rows_r2c_pairs<L, R2C_E, R2C_MAXT>;          \
       *group = (void *)&k_group_r2c_pairs<L>;                        \
       return true;                                                   \
     }                                                                \
@@ -307,7 +308,7 @@ hipError_t HK_CAT(launch_group_r2c_, HK_SUFFIX)(const BatchArgs &args, int logL,
 bool HK_CAT(limits_r2cp_, HK_SUFFIX)(int logL, int E, KernelLimits *out) {
   using namespace HK_NS;
   void *r, *g;
-  if (E != R2C_PAIR_E) return false;
+  if (E != R2C_E) return false;
   return r2cp_pick(logL, out, &r, &g);
 }
 
@@ -316,7 +317,7 @@ hipError_t HK_CAT(launch_rows_r2cp_, HK_SUFFIX)(int logL, int E, int groups_per_
   using namespace HK_NS;
   KernelLimits k;
   void *fn = nullptr, *g = nullptr;
-  if (E != R2C_PAIR_E || !sh.r2c || sh.resident || !r2cp_pick(logL, &k, &fn, &g)) return hipErrorInvalidValue;
+  if (E != R2C_E || !sh.r2c || sh.resident || !r2cp_pick(logL, &k, &fn, &g)) return hipErrorInvalidValue;
   const int threads = groups_per_wg * k.tps;
   if (threads < 1 || threads > R2C_MAXT) return hipErrorInvalidValue;
   size_t lds = (size_t)groups_per_wg * k.seq_lds * sizeof(cx<T>);

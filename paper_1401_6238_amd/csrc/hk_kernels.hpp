@@ -97,21 +97,23 @@ __global__ void __launch_bounds__(MAXT) k_rows_r2c(Shape sh, Ptrs p0, Strides st
 }
 
 // Pass B of multipass real-input transforms (RealPairRowBody): row pairs
-// blockIdx.x * groups + rw of instance blockIdx.y.
+// blockIdx.x * pairs + pw of instance blockIdx.y, two lane groups each.
 template <int L, int E, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_rows_r2c_pairs(Shape sh, Ptrs p0, Strides str, int64_t count) {
   using PB = RealPairRowBody<T, L, E>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *smem = (cx<T> *)smem_raw;
   const int tid = threadIdx.x;
-  const int rw = tid / PB::TPS;
+  const int grp = tid / PB::TPS;
   const int t = tid % PB::TPS;
-  const int groups = blockDim.x / PB::TPS;
+  const int pw = grp >> 1, g = grp & 1;
+  const int pairs = blockDim.x / (2 * PB::TPS);
   const PV P{&p0, &str, (int64_t)blockIdx.y, nullptr};
   const int64_t npairs = ((int64_t)1 << sh.logC) / 2;
-  const int64_t pi = (int64_t)blockIdx.x * groups + rw;
+  const int64_t pi = (int64_t)blockIdx.x * pairs + pw;
   const bool valid = pi < npairs;
-  const cx<T> part = PB::run_fwd(sh, P, valid ? pi : 0, valid, t, smem + rw * PB::SEQ_LDS, g_tw24, g_tw4096);
+  const cx<T> part =
+      PB::run_fwd(sh, P, valid ? pi : 0, g, valid, t, smem + pw * 2 * PB::SEQ_LDS, g_tw24, g_tw4096);
   if (sh.want_alpha) {
     const cx<T> tot = segment_sum(part, smem, tid, (int)blockDim.x);
     if (tid == 0) ws_partials<T>(sh, P)[blockIdx.x] = tot;
@@ -408,7 +410,7 @@ __global__ void __launch_bounds__(BATCH_BLK) k_group(BatchArgs A) {
 
 // Grouped real-input resident rows: task = up to BATCH_BLK / TPS instances.
 // Elements per lane: 8 in float, 4 in double (8 would spill).
-enum : int { R2C_E = sizeof(T) == 4 ? 8 : 4, R2C_PAIR_E = 4 };
+enum : int { R2C_E = sizeof(T) == 4 ? 8 : 4 };
 template <int L>
 __global__ void __launch_bounds__(BATCH_BLK) k_group_r2c(BatchArgs A) {
   using RB = RealRowBody<T, L, R2C_E>;
@@ -429,21 +431,23 @@ __global__ void __launch_bounds__(BATCH_BLK) k_group_r2c(BatchArgs A) {
   }
 }
 
-// Grouped pass-B row pairs of real-input transforms: task = pairs tk.a, ...
+// Grouped pass-B row pairs of real-input transforms: pairs tk.a, tk.a + 1, ...
 template <int L>
 __global__ void __launch_bounds__(BATCH_BLK) k_group_r2c_pairs(BatchArgs A) {
-  using PB = RealPairRowBody<T, L, R2C_PAIR_E>;
+  using PB = RealPairRowBody<T, L, R2C_E>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *smem = (cx<T> *)smem_raw;
   const int tid = threadIdx.x;
   const Task tk = A.tasks[A.order[A.begin + (int32_t)blockIdx.x]];
   const Shape &sh = A.shapes[tk.inst];
   const PV P{&A.ptrs[tk.inst], nullptr, 0, A.ws_base};
-  const int rw = tid / PB::TPS;
+  const int grp = tid / PB::TPS;
   const int t = tid % PB::TPS;
-  const int64_t pi = (int64_t)tk.a + rw;
+  const int pw = grp >> 1, g = grp & 1;
+  const int64_t pi = (int64_t)tk.a + pw;
   const bool valid = pi < ((int64_t)1 << sh.logC) / 2;
-  const cx<T> part = PB::run_fwd(sh, P, valid ? pi : 0, valid, t, smem + rw * PB::SEQ_LDS, g_tw24, g_tw4096);
+  const cx<T> part =
+      PB::run_fwd(sh, P, valid ? pi : 0, g, valid, t, smem + pw * 2 * PB::SEQ_LDS, g_tw24, g_tw4096);
   if (sh.want_alpha) {  // partial sum of this task; a TASK_ALPHA adds them up
     const cx<T> tot = segment_sum(part, smem, tid, BATCH_BLK);
     if (tid == 0) ws_partials<T>(sh, P)[tk.b] = tot;

@@ -113,8 +113,8 @@ static bool r2c_limits(hk_dtype_t dt, int logL, int E, KernelLimits *k) {
   return is_double(dt) ? limits_r2c_f64(logL, E, k) : limits_r2c_f32(logL, E, k);
 }
 
-// Pass-B row pairs of multipass real-input transforms: 4 elements per lane.
-constexpr int R2CP_E_ROW = 4;
+// Pass-B row pairs of multipass real-input transforms: as many elements per
+// lane as the resident real-input rows.
 static bool r2cp_limits(hk_dtype_t dt, int logL, int E, KernelLimits *k) {
   return is_double(dt) ? limits_r2cp_f64(logL, E, k) : limits_r2cp_f32(logL, E, k);
 }
@@ -169,7 +169,7 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd) {
       }
       int maxR = -1;
       for (int l = 0; l <= MAX_LOGL; ++l)
-        if (r2cp_limits(p.dt, l, R2CP_E_ROW, &k)) maxR = l;
+        if (r2cp_limits(p.dt, l, r2c_row_e(p.dt), &k)) maxR = l;
       Layout c;
       if (maxR >= 0 && split_of(logN - 1, split, maxR, &c.logR, &c.logC) && c.logC >= 1) {
         c.r2c = true;
@@ -366,7 +366,7 @@ bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
 Sched default_sched(hk_dtype_t dt, const Layout &lay, int prog, int64_t batch) {
   Sched sc;
   const bool dbl = is_double(dt);
-  sc.E_row = lay.r2c ? (lay.resident ? r2c_row_e(dt) : R2CP_E_ROW) : (lay.odd > 1 ? odd_row_e(dt) : 8);
+  sc.E_row = lay.r2c ? r2c_row_e(dt) : (lay.odd > 1 ? odd_row_e(dt) : 8);
   sc.E_col = dbl ? 8 : 16;
   KernelLimits kr, kc;
   layout_row_limits(dt, lay, sc.E_row, &kr);
