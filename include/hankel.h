@@ -28,9 +28,13 @@
  * ---------------------------------------
  *  - Data pointers are DEVICE pointers owned by the caller.  Arrays are
  *    contiguous (stride 1).  Complex dtypes are interleaved (re, im) pairs;
- *    real dtypes (HK_F32, HK_F64) mean real inputs and real outputs (the
- *    imaginary part of the complex result, pure rounding noise for real data,
- *    is dropped).  Each pointer must be aligned to its element size.
+ *    real dtypes (HK_F32, HK_F64) mean real inputs and real outputs.  Real
+ *    forward products (1D) transform each real vector of padded length N as
+ *    N/2 complex pairs and split the result by conjugate symmetry, so they
+ *    move and transform half the data of a complex product (power-of-two N;
+ *    the adjoint of real data, persistent plans and HK_PLAN_POW2 plans take
+ *    the complex path and drop the imaginary part, rounding noise for real
+ *    data).  Each pointer must be aligned to its element size.
  *  - Arrays of vector pointers ("vectors") are HOST arrays of device pointers.
  *  - Calls are asynchronous and stream-ordered on `stream` (NULL = default
  *    stream).  Outputs are fully overwritten; outputs must not alias inputs.
@@ -160,8 +164,8 @@ typedef struct hk_plan_s *hk_plan_t;
                                    (task kind, transform length) group; no in-kernel waits      */
 #define HK_PLAN_GRAPH 0x4u      /* capture the plan's launches in a hipGraph on first execute */
 #define HK_PLAN_AUTOTUNE 0x8u   /* reserved (accepted, no effect)                             */
-#define HK_PLAN_POW2 0x10u      /* power-of-two transform lengths only (no 3 * 2^k, 5 * 2^k);
-                                   implied by PERSISTENT                                        */
+#define HK_PLAN_POW2 0x10u      /* power-of-two complex transforms only (no 3 * 2^k, 5 * 2^k,
+                                   no half-length real transforms); implied by PERSISTENT      */
 
 /* Creates a plan for `count` problems.  The plan copies the descriptors
  * (pointers included); on first execute it uploads them to a device table
