@@ -203,6 +203,38 @@ hk_status_t hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t
                                void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* -------------------------------------------------------------------------
+ * Level-k block Hankel tensor, 1 <= k <= 4 (Section 2.2: a block Hankel tensor
+ * whose blocks are level-(k-1) block Hankel tensors; k = 2 is the BHHB tensor
+ * of block_hankel_tvp, k = 1 the Hankel tensor of hankel_mode_products).  The
+ * tensor is fixed by its generating tensor G of order k (Section 2.2) and the
+ * sizes of its modes at every level:
+ *   dims    : HOST array of k*m sizes, dims[t*m + p] = size of mode p at level
+ *             t (t = 0 the innermost level, the entries of the Hankel blocks);
+ *   G       : d_0 x ... x d_{k-1}, d_t = dims[t*m] + ... + dims[t*m+m-1] - m + 1,
+ *             column-major (entry (i_0, ..., i_{k-1}) at i_0 + d_0 (i_1 + d_1 (...)));
+ *             prod_t d_t <= 2^24;
+ *   vectors : HOST array of m device pointers, vectors[p] = vec(X_p), X_p of size
+ *             dims[p] x dims[m+p] x ..., column-major like G (vectors[0] only
+ *             for alpha);
+ *   y       : if non-NULL, vec(Y) of size dims[0] x dims[m] x ... x dims[(k-1)m]:
+ *             Y = H x_2 vec(X_2) ... x_m vec(X_m) (mode 1 free);
+ *   alpha   : if non-NULL, H x_1 vec(X_1) ... x_m vec(X_m).
+ * The paper computes these with k-dimensional FFTs on the padded grid.  This
+ * call embeds each X_p at the strides of G's column-major layout, where the
+ * index sums of a product never carry from one level into the next, so the
+ * product equals a 1D Hankel product with generating vector G and the embedded
+ * vectors, read back at the same strides (same result, one 1D transform of
+ * length >= prod d_t).  Workspace: block_hankel_tvp_levels_workspace_size with
+ * the same sizes, vectors and requested outputs (the vector pointers only
+ * decide which modes share one embedding). */
+hk_status_t block_hankel_tvp_levels_workspace_size(hk_dtype_t dt, int m, int k, const int64_t *dims,
+                                                   const void *const *vectors, int want_y, int want_alpha,
+                                                   size_t *bytes);
+hk_status_t block_hankel_tvp_levels(hk_dtype_t dt, const void *G, int m, int k, const int64_t *dims,
+                                    const void *const *vectors, void *y, void *alpha, void *ws,
+                                    size_t ws_bytes, hipStream_t stream);
+
+/* -------------------------------------------------------------------------
  * Hankel tensor-matrix product (Section 4.2): for the square order-m Hankel
  * tensor H (generating vector h, m(n-1)+1 elements) and an n x R matrix U
  * (column-major, device), T = H x_2 U x_3 U ... x_m U with the Section 2.1

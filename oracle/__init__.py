@@ -180,6 +180,49 @@ def block_tvp(m: int, dims, block_dims, H, vectors, want_y: bool = True, want_al
     return y, (None if alpha is None else complex(alpha[0]))
 
 
+def block_levels_tvp(m: int, dims, G, vectors, want_y: bool = True, want_alpha: bool = False):
+    """Level-k block Hankel product (Section 2.2: a block Hankel tensor whose
+    blocks are level-(k-1) block Hankel tensors), k = len(dims), in plain
+    numpy FP64 with direct sums.
+
+    dims[t][p] is the size of mode p at level t (t = 0 innermost); G is the
+    generating tensor of size d_0 x ... x d_{k-1}, d_t = sum_p dims[t][p] - m + 1
+    (flat column-major, or an array of that shape); vectors[p] = vec(X_p),
+    column-major.  The entry of the level-k tensor at the multi-indices
+    (i_1, ..., i_m) is G[i_1 + ... + i_m] (sums taken level by level), so,
+    gathering terms by their index sum, W = X_2 * ... * X_m (k-dimensional
+    linear convolutions) and Y[i] = sum_a G[i + a] W[a]; alpha = sum_s G[s]
+    (X_1 * W)[s].  Returns (vec(Y) or None, alpha or None).
+    """
+    k = len(dims)
+    d = [sum(int(v) for v in dims[t]) - m + 1 for t in range(k)]
+    G = np.asarray(G, np.complex128).reshape(d, order="F")
+    X = [None if v is None else np.asarray(v, np.complex128).reshape([int(dims[t][p]) for t in range(k)], order="F")
+         for p, v in enumerate(vectors)]
+
+    def conv(A, B):
+        out = np.zeros([a + b - 1 for a, b in zip(A.shape, B.shape)], np.complex128)
+        for idx in np.ndindex(*B.shape):
+            out[tuple(slice(i, i + n) for i, n in zip(idx, A.shape))] += A * B[idx]
+        return out
+
+    W = X[1]
+    for p in range(2, m):
+        W = conv(W, X[p])
+    y = None
+    if want_y:
+        n1 = [int(dims[t][0]) for t in range(k)]
+        Y = np.zeros(n1, np.complex128)
+        for idx in np.ndindex(*W.shape):
+            Y += W[idx] * G[tuple(slice(i, i + n) for i, n in zip(idx, n1))]
+        y = Y.reshape(-1, order="F")
+    alpha = None
+    if want_alpha:
+        V = conv(X[0], W)
+        alpha = complex(np.sum(G[tuple(slice(0, n) for n in V.shape)] * V))
+    return y, alpha
+
+
 def block_tvp_sampled(m: int, dims, block_dims, H, vectors, idx, want_alpha: bool = False):
     """BHHB product at flat output indices idx (column-major in the n_1 x N_1 result)."""
     dims, H, vecs = _prep(m, dims, H, vectors, want_alpha)

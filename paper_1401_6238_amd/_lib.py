@@ -59,6 +59,8 @@ _SIGS = {
     "hankel_mode_products": [_I, _P, _I, _PI64, _P, _P, _P, _P, _SZ, _P],
     "block_hankel_tvp_workspace_size": [_I, _I, _PI64, _PI64, _P, _I, _I, _PSZ],
     "block_hankel_tvp": [_I, _P, _I, _PI64, _PI64, _P, _P, _P, _P, _SZ, _P],
+    "block_hankel_tvp_levels_workspace_size": [_I, _I, _I, _PI64, _P, _I, _I, _PSZ],
+    "block_hankel_tvp_levels": [_I, _P, _I, _I, _PI64, _P, _P, _P, _P, _SZ, _P],
     "hk_plan_create": [ctypes.POINTER(_P), _I, _P, _I64, ctypes.c_uint],
     "hk_plan_workspace_size": [_P, _PSZ],
     "hk_plan_execute": [_P, _P, _SZ, _P],

@@ -144,6 +144,38 @@ def block_hankel_tvp(H: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]],
     return y, (None if alpha is None else alpha[0])
 
 
+def block_hankel_tvp_levels(G: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]], dims,
+                            want_y: bool = True, want_alpha: bool = False):
+    """Level-k block Hankel tensor (k = len(dims)): G is the column-major
+    generating tensor (flat), dims[t][p] the size of mode p at level t
+    (t = 0 innermost), vectors[p] = vec(X_p) column-major.  Returns (y, alpha)
+    with y = vec(Y), Y of size dims[0][0] x dims[1][0] x ..."""
+    m = len(vectors)
+    k = len(dims)
+    ref = next(v for v in vectors if v is not None)
+    _dev(G)
+    for v in vectors:
+        if v is not None:
+            _dev(v)
+    _same_device(G, *vectors)
+    dt = _dtype(ref)
+    flat = [int(dims[t][p]) for t in range(k) for p in range(m)]
+    ny = 1
+    for t in range(k):
+        ny *= int(dims[t][0])
+    y = torch.empty(ny, dtype=ref.dtype, device=ref.device) if want_y else None
+    alpha = torch.empty(1, dtype=ref.dtype, device=ref.device) if want_alpha else None
+    da = _i64arr(flat)
+    va = _vecarr(vectors)
+    nb = ctypes.c_size_t(0)
+    check(lib().block_hankel_tvp_levels_workspace_size(dt, m, k, da, va, int(want_y), int(want_alpha),
+                                                       ctypes.byref(nb)), "block_hankel_tvp_levels_workspace_size")
+    ws, wsb = _workspace(nb.value, ref.device)
+    check(lib().block_hankel_tvp_levels(dt, _ptr(G), m, k, da, va, _ptr(y), _ptr(alpha), _ptr(ws), wsb,
+                                        _stream(ref.device)), "block_hankel_tvp_levels")
+    return y, (None if alpha is None else alpha[0])
+
+
 def hankel_tvp_backward(h: torch.Tensor, x: torch.Tensor, m: int, grad_y: Optional[torch.Tensor],
                         grad_alpha: Optional[torch.Tensor], want_grad_x: bool = True, want_grad_h: bool = True):
     """J^H [grad_y; grad_alpha] for g = H x^{m-1}, f = H x^m.  Returns (grad_x, grad_h)."""

@@ -23,6 +23,8 @@ static hk_status_t finish(const Status &s) {
   return s.code;
 }
 
+static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
 static Status check_ws(size_t need, const void *ws, size_t ws_bytes) {
   if (need == 0) return Status();
   if (!ws) return fail(HK_ERR_WORKSPACE, "workspace pointer is NULL but " + std::to_string(need) + " bytes are needed");
@@ -146,6 +148,109 @@ static Problem bwd_problem(hk_dtype_t dt, const void *h, int m, int64_t n, const
   return p;
 }
 
+// ---------------------------------------------------------------------------
+// Level-k block Hankel tensors (Section 2.2: block Hankel tensors whose blocks
+// are level-(k-1) block Hankel tensors; k = 2 is the BHHB tensor).  With the
+// generating tensor G stored column-major, its entry (i_0, ..., i_{k-1}) sits
+// at sum_t i_t S_t, S_t = d_0 ... d_{t-1}.  Each X_p is embedded at the same
+// strides; along level t the indices of a product add up to at most d_t - 1,
+// so no sum carries into the next level, and the level-k product is exactly
+// the 1D Hankel product with generating vector G (prod_t d_t entries, which is
+// sum_p L_p - m + 1) and the embedded vectors (L_p = 1 + sum_t (n_p^(t) - 1)
+// S_t entries), whose output is read back at the same strides (a Kronecker
+// substitution).  One 1D transform of length >= prod_t d_t takes the place of
+// the k-dimensional one of the paper's procedure (the multi-dimensional FFT
+// on the grid prod_t 2^ceil(log2 d_t)), with the same result.
+// ---------------------------------------------------------------------------
+struct LevelsRun {
+  int k = 0, m = 0;
+  int64_t S[HK_MAX_LEVELS] = {0};
+  int64_t L[HK_MAX_ORDER] = {0};
+  int src[HK_MAX_ORDER] = {0};     // first mode with the same vector (pointer and sizes)
+  bool need[HK_MAX_ORDER] = {false};
+  size_t off_vec[HK_MAX_ORDER] = {0}, off_y = 0, ws1d = 0, total = 0;
+  Problem p1;                     // the 1D problem, with workspace placeholders
+};
+
+static Status levels_setup(hk_dtype_t dt, const void *G, int m, int k, const int64_t *dims,
+                           const void *const *vectors, bool want_y, bool want_alpha, LevelsRun *r) {
+  if (m < 2 || m > HK_MAX_ORDER) return fail(HK_ERR_INVALID_VALUE, "order m must be in [2, 8]");
+  if (k < 1 || k > HK_MAX_LEVELS) return fail(HK_ERR_INVALID_VALUE, "levels k must be in [1, 4]");
+  if (!dims) return fail(HK_ERR_NULL_POINTER, "dims is NULL");
+  if (!vectors) return fail(HK_ERR_NULL_POINTER, "vectors is NULL");
+  if (!want_y && !want_alpha) return fail(HK_ERR_NULL_POINTER, "neither y nor alpha requested");
+  if (dt < HK_C64 || dt > HK_F64) return fail(HK_ERR_INVALID_VALUE, "unknown dtype");
+  for (int i = 0; i < k * m; ++i)
+    if (dims[i] < 1) return fail(HK_ERR_INVALID_VALUE, "every size must be >= 1");
+  r->k = k;
+  r->m = m;
+  int64_t prod = 1;
+  for (int t = 0; t < k; ++t) {
+    int64_t d = 1 - m;
+    for (int p = 0; p < m; ++p) {
+      if (dims[t * m + p] > ((int64_t)1 << HK_MAX_FFT_LOG2)) return fail(HK_ERR_SIZE_LIMIT, "size too large");
+      d += dims[t * m + p];
+    }
+    r->S[t] = prod;
+    if (d > ((int64_t)1 << HK_MAX_FFT_LOG2) || prod > (((int64_t)1 << HK_MAX_FFT_LOG2) / d))
+      return fail(HK_ERR_SIZE_LIMIT, "generating tensor exceeds 2^24 entries");
+    prod *= d;
+  }
+  for (int p = 0; p < m; ++p) {
+    r->L[p] = 1;
+    for (int t = 0; t < k; ++t) r->L[p] += (dims[t * m + p] - 1) * r->S[t];
+    r->need[p] = p > 0 || want_alpha;
+    if (r->need[p] && !vectors[p])
+      return fail(HK_ERR_NULL_POINTER, "vector " + std::to_string(p + 1) + " is NULL");
+    r->src[p] = p;
+    for (int q = 0; q < p; ++q) {
+      if (!r->need[q] || vectors[q] != vectors[p]) continue;
+      bool same = true;
+      for (int t = 0; t < k; ++t) same = same && dims[t * m + q] == dims[t * m + p];
+      if (same) {
+        r->src[p] = r->src[q];
+        break;
+      }
+    }
+  }
+  // the 1D problem; placeholders stand for the workspace pointers
+  Problem &q = r->p1;
+  q = Problem();
+  q.dt = dt;
+  q.prog = PROG_FWD;
+  q.m = m;
+  q.h = G ? G : (const void *)256;
+  for (int p = 0; p < m; ++p) {
+    q.dims[p] = r->L[p];
+    q.vec[p] = r->need[p] ? (const void *)(uintptr_t)(256 * (1 + r->src[p])) : nullptr;
+  }
+  q.y = want_y ? (void *)256 : nullptr;
+  q.alpha = want_alpha ? (void *)256 : nullptr;
+  Status s = validate_forward(q);
+  if (!s.ok()) return s;
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  s = prepare(q, 1, &sh, &P, &sc);
+  if (!s.ok()) return s;
+  const size_t es = elem_bytes(dt);
+  size_t off = (instance_ws_bytes(sh, dt) + 255) & ~(size_t)255;
+  r->ws1d = off;
+  if (k > 1) {
+    for (int p = 0; p < m; ++p) {
+      if (!r->need[p] || r->src[p] != p) continue;
+      r->off_vec[p] = off;
+      off += ((size_t)r->L[p] * es + 255) & ~(size_t)255;
+    }
+    if (want_y) {
+      r->off_y = off;
+      off += ((size_t)r->L[0] * es + 255) & ~(size_t)255;
+    }
+  }
+  r->total = off;
+  return Status();
+}
+
 extern "C" {
 
 int hk_version(void) { return 10000; }
@@ -246,6 +351,93 @@ hk_status_t block_hankel_tvp(hk_dtype_t dt, const void *H, int m, const int64_t 
   s = validate_forward(p);
   if (!s.ok()) return finish(s);
   return finish(run_one(p, ws, ws_bytes, stream));
+}
+
+hk_status_t block_hankel_tvp_levels_workspace_size(hk_dtype_t dt, int m, int k, const int64_t *dims,
+                                                   const void *const *vectors, int want_y, int want_alpha,
+                                                   size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  LevelsRun r;
+  Status s = levels_setup(dt, nullptr, m, k, dims, vectors, want_y != 0, want_alpha != 0, &r);
+  if (!s.ok()) return finish(s);
+  *bytes = r.total;
+  return finish(Status());
+}
+
+hk_status_t block_hankel_tvp_levels(hk_dtype_t dt, const void *G, int m, int k, const int64_t *dims,
+                                    const void *const *vectors, void *y, void *alpha, void *ws, size_t ws_bytes,
+                                    hipStream_t stream) {
+  if (!G) return finish(fail(HK_ERR_NULL_POINTER, "generating tensor is NULL"));
+  LevelsRun r;
+  Status s = levels_setup(dt, G, m, k, dims, vectors, y != nullptr, alpha != nullptr, &r);
+  if (!s.ok()) return finish(s);
+  const size_t es = elem_bytes(dt);
+  if (!aligned(G, es) || (y && !aligned(y, es)) || (alpha && !aligned(alpha, es)))
+    return finish(fail(HK_ERR_MISALIGNED, "pointer not aligned to the element size"));
+  for (int p = 0; p < m; ++p)
+    if (r.need[p] && !aligned(vectors[p], es))
+      return finish(fail(HK_ERR_MISALIGNED, "vector not aligned to the element size"));
+  s = check_ws(r.total, ws, ws_bytes);
+  if (!s.ok()) return finish(s);
+  s = ensure_device();
+  if (!s.ok()) return finish(s);
+  char *w = (char *)ws;
+  Problem q = r.p1;
+  q.h = G;
+  q.alpha = alpha;
+  // embed the distinct vectors (k = 1: the vectors themselves)
+  for (int p = 0; p < m; ++p) {
+    if (!r.need[p]) continue;
+    if (k == 1) {
+      q.vec[p] = vectors[p];
+      continue;
+    }
+    if (r.src[p] == p) {
+      Levels lv;
+      memset(&lv, 0, sizeof(lv));
+      lv.k = k;
+      int64_t cnt = 1;
+      for (int t = 0; t < k; ++t) {
+        lv.ext[t] = dims[t * m + p];
+        lv.stride[t] = r.S[t];
+        cnt *= lv.ext[t];
+      }
+      count_launch();
+      hipError_t e = launch_levels_fill(w + r.off_vec[p], r.L[p], (int)es, stream);
+      if (e == hipSuccess) {
+        count_launch();
+        e = launch_levels_copy(const_cast<void *>(vectors[p]), w + r.off_vec[p], lv, cnt, 0, (int)es, stream);
+      }
+      if (e != hipSuccess) return finish(fail(HK_ERR_HIP, std::string("level embedding: ") + hipGetErrorString(e)));
+    }
+    q.vec[p] = w + r.off_vec[r.src[p]];
+  }
+  q.y = y ? (k == 1 ? y : (void *)(w + r.off_y)) : nullptr;
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  s = prepare(q, 1, &sh, &P, &sc);
+  if (!s.ok()) return finish(s);
+  P.ws = ws;
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  s = launch_shape(dt, sh, sc, P, str, 1, stream);
+  if (!s.ok()) return finish(s);
+  if (y && k > 1) {
+    Levels lv;
+    memset(&lv, 0, sizeof(lv));
+    lv.k = k;
+    int64_t cnt = 1;
+    for (int t = 0; t < k; ++t) {
+      lv.ext[t] = dims[t * m];
+      lv.stride[t] = r.S[t];
+      cnt *= lv.ext[t];
+    }
+    count_launch();
+    hipError_t e = launch_levels_copy(y, w + r.off_y, lv, cnt, 1, (int)es, stream);
+    if (e != hipSuccess) return finish(fail(HK_ERR_HIP, std::string("level extraction: ") + hipGetErrorString(e)));
+  }
+  return finish(Status());
 }
 
 hk_status_t hankel_tvp_backward_workspace_size(hk_dtype_t dt, int m, int64_t n, size_t *bytes) {

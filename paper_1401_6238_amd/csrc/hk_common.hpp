@@ -138,6 +138,17 @@ struct BatchArgs {
   const int32_t *order;    // grouped launches: task indices sorted by (phase, kind, length)
 };
 
+// Level-k block Hankel products: a compact k-dimensional array (extents
+// ext[0..k), column-major) and its embedding at strides stride[0..k) in a 1D
+// vector (entry (i_0, ..., i_{k-1}) at sum_t i_t stride[t]).
+enum : int { HK_MAX_LEVELS = 4 };
+struct Levels {
+  int32_t k;
+  int32_t pad;
+  int64_t ext[HK_MAX_LEVELS];
+  int64_t stride[HK_MAX_LEVELS];
+};
+
 // Grouped launches: one specialised kernel per (task kind, transform length).
 enum GroupKind : int { GK_RES = 0, GK_ROWB = 1, GK_COL = 2, GK_ALPHA = 3 };
 

@@ -47,6 +47,13 @@ hipError_t launch_kernel(const void *fn, dim3 grid, dim3 block, void **args, siz
 HK_DECLARE_LAUNCHERS(f32)
 HK_DECLARE_LAUNCHERS(f64)
 
+// Level-k block Hankel products (hk_levels.hip): zero fill of n elements of
+// es bytes, and the strided embedding (dir 0) / extraction (dir 1) of a
+// compact array of `total` elements.
+hipError_t launch_levels_fill(void *p, int64_t n, int es, hipStream_t st);
+hipError_t launch_levels_copy(void *compact, void *emb, const Levels &lv, int64_t total, int dir, int es,
+                              hipStream_t st);
+
 #define HK_DECLARE_ODD_LAUNCHERS(SUFFIX)                                                                  \
   hipError_t init_tables_odd_##SUFFIX(const double *tw4096_interleaved, const double *tw24_interleaved);  \
   bool limits_odd_##SUFFIX(int odd, int logL, int E, KernelLimits *out);                                \

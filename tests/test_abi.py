@@ -211,3 +211,25 @@ def test_tensor_matrix_argument_errors(L):
     assert L.hankel_tensor_matrix_workspace_size(HK_C64, 5, 8, 64, ctypes.byref(b)) == SIZE  # 64^4 columns
     assert L.hankel_tensor_matrix_workspace_size(HK_C64, 3, 8, 2, None) == NULLP
     assert L.hankel_tensor_matrix(HK_C64, None, 3, 8, 2, None, None, None, 0, None) == NULLP
+
+
+def test_levels_argument_errors(L):
+    b = ctypes.c_size_t(0)
+    dims = (ctypes.c_int64 * 6)(4, 3, 2, 5, 2, 3)
+    vec = (ctypes.c_void_p * 3)(256, 256, 256)
+    f = L.block_hankel_tvp_levels_workspace_size
+    assert f(HK_C64, 3, 2, dims, vec, 1, 1, ctypes.byref(b)) == OK and b.value > 0
+    assert f(HK_C64, 3, 0, dims, vec, 1, 1, ctypes.byref(b)) == INVALID        # k outside [1, 4]
+    assert f(HK_C64, 3, 5, dims, vec, 1, 1, ctypes.byref(b)) == INVALID
+    assert f(HK_C64, 1, 2, dims, vec, 1, 1, ctypes.byref(b)) == INVALID        # m outside [2, 8]
+    assert f(HK_C64, 3, 2, None, vec, 1, 1, ctypes.byref(b)) == NULLP
+    assert f(HK_C64, 3, 2, dims, None, 1, 1, ctypes.byref(b)) == NULLP
+    assert f(HK_C64, 3, 2, dims, vec, 0, 0, ctypes.byref(b)) == NULLP          # nothing requested
+    big = (ctypes.c_int64 * 6)(3000, 3000, 3000, 3000, 3000, 3000)             # 8998^2 > 2^24 entries
+    assert f(HK_C64, 3, 2, big, vec, 1, 1, ctypes.byref(b)) == SIZE
+    zero = (ctypes.c_int64 * 6)(4, 0, 2, 5, 2, 3)
+    assert f(HK_C64, 3, 2, zero, vec, 1, 1, ctypes.byref(b)) == INVALID
+    # the workspace holds the embedded vectors: two distinct ones when mode 1 is not needed
+    vec2 = (ctypes.c_void_p * 3)(None, 256, 256)
+    b2 = ctypes.c_size_t(0)
+    assert f(HK_C64, 3, 2, dims, vec2, 1, 0, ctypes.byref(b2)) == OK and b2.value < b.value
