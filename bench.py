@@ -700,6 +700,27 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
     ms5p = time_region(torch, plain5, 1, warm=1)
     ex["block_batch_c64"] = {"batched_TVP_s": round(64 / ms5 * 1000, 2), "plain_loop_TVP_s": round(64 / ms5p * 1000, 2)}
     log("block batch", ex["block_batch_c64"])
+
+    # level-k products: the same BHHB tensors through the level-k call (one 1D transform of
+    # length >= 1534^2, here 3 * 2^20) against the native 2D passes on the 2048^2 grid, one
+    # tensor at a time; and a level-3 tensor (m = 3, 64 x 64 x 16 per mode, generating tensor
+    # 190 x 190 x 46, CN(0,1) entries)
+    def plain_levels():
+        for b in range(Hs.shape[0]):
+            hk.block_hankel_tvp_levels(Hs[b], [Xs[b]] * 3, [[512] * 3, [512] * 3], True, True)
+    ms_lv = time_region(torch, plain_levels, 1, warm=1)
+    g3 = np.random.Generator(np.random.PCG64(14016238 + 9000))
+    dims3 = [[64] * 3, [64] * 3, [16] * 3]
+    n_g3 = 190 * 190 * 46
+    G3 = torch.from_numpy(wl.cn(g3, n_g3, 1.0)).to(torch.complex64).to(dev)
+    X3 = torch.from_numpy(wl.cn(g3, 64 * 64 * 16, 1.0)).to(torch.complex64).to(dev)
+    ms_3 = time_region(torch, lambda: hk.block_hankel_tvp_levels(G3, [X3] * 3, dims3, True, True), 20)
+    ex["block_levels_c64"] = {"level2_via_1d_TVP_s": round(64 / ms_lv * 1000, 2),
+                              "level2_native_2d_TVP_s": round(64 / ms5p * 1000, 2),
+                              "level3_shape": "m=3, 64x64x16 per mode, generating tensor 190x190x46",
+                              "level3_TVP_s": round(1000 / ms_3, 1), "level3_ms": round(ms_3, 4)}
+    log("block levels", ex["block_levels_c64"])
+    del G3, X3
     return ex
 
 
