@@ -194,9 +194,30 @@ def classify_passes(names):
     return out
 
 
+def headline_tile_width(dtype):
+    """Column-tile width of the large single product's schedule in the shipped
+    schedule database (the schedule the profiled run used)."""
+    key = f"{0 if dtype == 'c64' else 1} 0 0 1 20 -1 0"
+    path = os.path.join(ROOT, "paper_1401_6238_amd", "tune_db.txt")
+    with open(path) as f:
+        for line in f:
+            if line.startswith(key + " :"):
+                return int(line.split(":")[1].split()[3])
+    return 16 if dtype == "c64" else 8  # the default schedule
+
+
 def summarize_counters(fetch_dir, write_dir, dtype, calib_mib, command):
-    """Per-pass FETCH_SIZE / WRITE_SIZE (KiB per dispatch) scaled by the same
-    counters read on a plain device copy of calib_mib MiB."""
+    """Per-pass FETCH_SIZE / WRITE_SIZE (KiB per dispatch), as HBM bytes.
+
+    On this pool the 128-byte read-request counter (TCC_BUBBLE) stays at zero,
+    so FETCH_SIZE counts every read request as 64 bytes: a plain device copy,
+    whose requests are 128-byte lines, reads half its bytes.  A pass's fetched
+    bytes are therefore its request count times its request size, which is the
+    width of the contiguous segments it reads, capped at one 128-byte line:
+    whole lines for the row pass, TW complex elements for the column passes
+    (TW from the schedule).  The copy of calib_mib MiB, run in the same
+    process, checks the 128-byte case; WRITE_SIZE is scaled by the copy the
+    same way."""
     res = {}
     for tag, d, ctr in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = [r for r in _read_csv(d, "counter_collection.csv") if r["Counter_Name"] == ctr]
@@ -224,6 +245,11 @@ def summarize_counters(fetch_dir, write_dir, dtype, calib_mib, command):
                     "n": {k: len(v) for k, v in acc.items()}}
     esz = 8 if dtype == "c64" else 16
     alg = {"pass_a": (DH + NVEC + 2 * NFFT) * esz, "pass_b": 3 * NFFT * esz, "pass_d": (NFFT + NVEC) * esz}
+    tw = headline_tile_width(dtype)
+    col_req = max(32, min(128, tw * esz))
+    req = {"pass_a": col_req, "pass_b": 128, "pass_d": col_req}
+    # the copy's factor belongs to 128-byte requests; other sizes scale with it
+    ffac = {k: res["fetch"]["factor"] * req[k] / 128.0 for k in req}
     lines = [
         f"# HBM traffic per launch, large single product (order 4, n=2^18, d_H=1048573, N=2^20), {dtype}",
         "# from two rocprofv3 --pmc runs of the same command (FETCH_SIZE, then WRITE_SIZE):",
@@ -231,16 +257,21 @@ def summarize_counters(fetch_dir, write_dir, dtype, calib_mib, command):
         f"# counter calibration: a plain device copy of {calib_mib} MiB (8 dispatches in the same run);",
         f"#   FETCH_SIZE read {res['fetch']['copy_kib']:.1f} KiB per copy -> factor {res['fetch']['factor']:.4f}",
         f"#   WRITE_SIZE read {res['write']['copy_kib']:.1f} KiB per copy -> factor {res['write']['factor']:.4f}",
-        "# traffic_bytes = (FETCH_SIZE * fetch factor + WRITE_SIZE * write factor) * 1024, mean over dispatches;",
+        "# FETCH_SIZE counts each read request as 64 bytes here (the 128-byte request counter",
+        "# TCC_BUBBLE reads zero; TCC_EA0_RDREQ of the copy = bytes / 128): fetched bytes = FETCH_SIZE",
+        "# scaled by request size / 64, the request size being the width of the contiguous segments",
+        f"# a pass reads, capped at 128 B: rows 128 B; column tiles of TW = {tw} elements {col_req} B",
+        "# traffic_bytes = fetched bytes + WRITE_SIZE * write factor * 1024, mean over dispatches;",
         "# alg_bytes = the algorithmic bytes of the pass (reads + writes the pass needs at minimum)",
         f"source_sha256: {kernel_source_hash()}",
         f"fetch_factor: {res['fetch']['factor']:.6f}",
         f"write_factor: {res['write']['factor']:.6f}",
+        f"column_request_bytes: {col_req}",
     ]
     for k in ("pass_a", "pass_b", "pass_d"):
         if k not in res["fetch"]["kib"] or k not in res["write"]["kib"]:
             continue
-        fb = res["fetch"]["kib"][k] * res["fetch"]["factor"] * 1024
+        fb = res["fetch"]["kib"][k] * ffac[k] * 1024
         wb = res["write"]["kib"][k] * res["write"]["factor"] * 1024
         lines.append(f"{k}: fetch_bytes={int(fb)} write_bytes={int(wb)} traffic_bytes={int(fb + wb)} "
                      f"alg_bytes={alg[k]} ratio={(fb + wb) / alg[k]:.3f} dispatches={res['fetch']['n'][k]}")
