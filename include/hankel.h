@@ -305,8 +305,25 @@ hk_status_t block_hankel_tvp_strided_batched(hk_dtype_t dt, const void *H, int64
 /* -------------------------------------------------------------------------
  * Schedule control and diagnostics.
  * ------------------------------------------------------------------------- */
-/* Padded FFT length N (1D) chosen for a given d_H (complex64 data, default
- * schedule) and the row x column split of each of its power-of-two sequences:
+/* Process-wide choice of transform lengths for the calls and plans created
+ * afterwards.  HK_LENGTHS_SMALLEST takes the smallest length with kernels
+ * (2^k, 3 * 2^k, 5 * 2^k); HK_LENGTHS_AUTO (default) does so when the call's
+ * work is large enough to fill the device (instances * the power-of-two
+ * length >= 2^18: a plan's instances, a strided batch's count) and takes the
+ * power of two otherwise, where the odd lengths' longer per-lane sequences
+ * would cost latency; HK_LENGTHS_POW2 takes power-of-two complex transforms
+ * only.  Real forward products use their half-length transform under AUTO
+ * and SMALLEST.  Workspace sizes depend on the policy: query them under the
+ * policy the call runs with.  Not synchronized with calls running on other
+ * host threads. */
+#define HK_LENGTHS_AUTO 0
+#define HK_LENGTHS_POW2 1
+#define HK_LENGTHS_SMALLEST 2
+hk_status_t hk_set_fft_lengths(int policy);
+int hk_get_fft_lengths(void);
+/* Padded FFT length N (1D) chosen for a single product with a given d_H
+ * (complex64 data, current length policy, default schedule) and the row x
+ * column split of each of its power-of-two sequences:
  * N = odd * n_row * n_col with odd = N / (n_row * n_col) in {1, 3, 5};
  * n_col = 1 means one workgroup holds the whole transform. */
 hk_status_t hk_fft_layout(int64_t d_h, int64_t *n_fft, int64_t *n_row, int64_t *n_col);

@@ -79,6 +79,8 @@ _SIGS = {
     "block_hankel_tvp_strided_batched": [_I, _P, _I64, _I, _PI64, _PI64, _P, _I64, _P, _I64, _P, _I64, _P,
                                          _SZ, _P],
     "hk_fft_layout": [_I64, _PI64, _PI64, _PI64],
+    "hk_set_fft_lengths": [_I],
+    "hk_get_fft_lengths": [],
     "hk_autotune_tvp": [_I, _I, _I64, _I],
     "hk_autotune": [_I, _I, _I, _I64, _PI64, _PI64, _I64, _I],
     "hk_tune_save": [ctypes.c_char_p],

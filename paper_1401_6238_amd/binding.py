@@ -359,6 +359,23 @@ def hankel_tvp_batched(problems):
     return out
 
 
+_LENGTHS = {"auto": 0, "pow2": 1, "smallest": 2}
+
+
+def hk_set_fft_lengths(policy: str):
+    """Process-wide transform lengths for later calls and plans: "auto"
+    (default: the smallest of 2^k, 3 * 2^k, 5 * 2^k when instances * the
+    power-of-two length >= 2^18, else the power of two), "smallest" or
+    "pow2"."""
+    if policy not in _LENGTHS:
+        raise ValueError("policy must be 'auto', 'smallest' or 'pow2'")
+    check(lib().hk_set_fft_lengths(_LENGTHS[policy]), "hk_set_fft_lengths")
+
+
+def hk_get_fft_lengths() -> str:
+    return {v: k for k, v in _LENGTHS.items()}[lib().hk_get_fft_lengths()]
+
+
 def hk_fft_layout(d_h: int):
     a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     check(lib().hk_fft_layout(d_h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "hk_fft_layout")

@@ -38,13 +38,13 @@ static Status check_ws(size_t need, const void *ws, size_t ws_bytes) {
 // Picks the schedule (autotuned if cached, else the default) and builds the shape.
 static Status prepare(const Problem &p, int64_t batch, Shape *sh, Ptrs *P, Sched *sc) {
   Layout lay;
-  Status s = layout_for(p, 0, &lay);
+  Status s = layout_for(p, 0, &lay, true, batch);
   if (!s.ok()) return s;
   Sched sch;
   const int logM = lay.logR + lay.logC;
   if (sched_lookup(p.dt, p.prog, p.is_block ? 1 : 0, lay.lclass(), logM, p.is_block ? lay.logC : -1, batch, &sch)) {
     Layout l2;
-    if (layout_for(p, sch.split, &l2).ok() && l2.lclass() == lay.lclass() && sched_valid(p.dt, l2, sch))
+    if (layout_for(p, sch.split, &l2, true, batch).ok() && l2.lclass() == lay.lclass() && sched_valid(p.dt, l2, sch))
       lay = l2;
     else
       sch = default_sched(p.dt, lay, p.prog, batch);
@@ -274,6 +274,15 @@ const char *hk_status_string(hk_status_t s) {
 const char *hk_last_error(void) { return tl_err.c_str(); }
 
 int hk_last_launch_count(void) { return tl_last_launches; }
+
+hk_status_t hk_set_fft_lengths(int policy) {
+  if (policy != HK_LENGTHS_AUTO && policy != HK_LENGTHS_SMALLEST && policy != HK_LENGTHS_POW2)
+    return finish(fail(HK_ERR_INVALID_VALUE, "unknown length policy"));
+  set_length_policy(policy);
+  return finish(Status());
+}
+
+int hk_get_fft_lengths(void) { return length_policy(); }
 
 hk_status_t hk_fft_layout(int64_t d_h, int64_t *n_fft, int64_t *n_row, int64_t *n_col) {
   if (!n_fft || !n_row || !n_col) return finish(fail(HK_ERR_NULL_POINTER, "output pointer is NULL"));

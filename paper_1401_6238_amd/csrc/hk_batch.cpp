@@ -248,7 +248,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
       return fail(s.code, "problem " + std::to_string(i) + ": " + s.msg);
     }
     Layout lay;
-    s = layout_for(pr, 0, &lay, allow_odd);
+    s = layout_for(pr, 0, &lay, allow_odd, count);
     if (!s.ok()) {
       delete p;
       return fail(s.code, "problem " + std::to_string(i) + ": " + s.msg);
@@ -611,14 +611,14 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   Problem p = proto;
   const hk_dtype_t dt = p.dt;
   Layout lay0;
-  s = layout_for(p, 0, &lay0);
+  s = layout_for(p, 0, &lay0, true, batch);
   if (!s.ok()) return s;
   // layouts to search
   std::vector<std::pair<int, Layout>> layouts;
   for (int sp : {0, -1, 1, -2, 2}) {
     Layout lay;
     if (p.is_block && sp != 0) continue;
-    if (!layout_for(p, sp, &lay).ok()) continue;
+    if (!layout_for(p, sp, &lay, true, batch).ok()) continue;
     if (sp != 0 && (lay.resident || lay.odd != lay0.odd || (lay.logR == lay0.logR && lay.logC == lay0.logC)))
       continue;
     layouts.push_back({sp, lay});

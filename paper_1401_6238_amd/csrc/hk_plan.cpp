@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -147,7 +148,28 @@ static bool split_of(int logM, int split, int maxR, int *logR, int *logC) {
   return true;
 }
 
-Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd) {
+// Process-wide transform-length policy (hk_set_fft_lengths).  Odd-factor
+// lengths save bytes but give each lane group `odd` sequences in turn: they
+// pay off where there is enough work to fill the device (measured: single
+// products gain from N ~ 2^18 on, batches of many small ones do), and cost
+// latency below.  HK_LENGTHS_AUTO therefore takes them when batch * (the
+// power-of-two length) >= 2^18; real inputs take their half-length transform
+// under every policy but HK_LENGTHS_POW2.
+static std::atomic<int> g_length_policy{HK_LENGTHS_AUTO};
+void set_length_policy(int policy) { g_length_policy.store(policy); }
+int length_policy() { return g_length_policy.load(); }
+constexpr int64_t kOddWorkMin = (int64_t)1 << 18;
+
+Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int64_t batch) {
+  const int policy = g_length_policy.load();
+  const bool allow_r2c = allow_odd && policy != HK_LENGTHS_POW2;
+  if (policy == HK_LENGTHS_POW2) allow_odd = false;
+  if (allow_odd && policy == HK_LENGTHS_AUTO && !p.is_block) {
+    int64_t dh = 1 - p.m;
+    for (int q = 0; q < p.m; ++q) dh += p.dims[q];
+    const int64_t n2 = (int64_t)1 << std::max(0, ceil_log2(dh));
+    if (std::max<int64_t>(1, batch) * n2 < kOddWorkMin) allow_odd = false;
+  }
   Layout lay;
   if (!p.is_block) {
     int64_t dh = 1 - p.m;
@@ -156,7 +178,7 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd) {
     // Real forward products: a length-N real transform (N = 2^k >= max(d_H, 2))
     // as a length-N/2 complex one, in one workgroup or in three passes whose
     // row pass takes mirrored row pairs.
-    if (allow_odd && p.prog == PROG_FWD && !is_complex(p.dt)) {
+    if (allow_r2c && p.prog == PROG_FWD && !is_complex(p.dt)) {
       const int logN = std::max(1, ceil_log2(dh));
       KernelLimits k;
       if (r2c_limits(p.dt, logN - 1, r2c_row_e(p.dt), &k)) {

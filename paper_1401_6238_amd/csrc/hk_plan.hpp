@@ -80,7 +80,10 @@ Status validate_backward(const Problem &p);
 // with N <= 8192 a length-N real transform done as a length-N/2 complex one;
 // powers of two only when allow_odd is false), resident vs multipass and the
 // split.
-Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd = true);
+Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd = true, int64_t batch = 1);
+// Process-wide transform-length policy (see hk_set_fft_lengths).
+void set_length_policy(int policy);
+int length_policy();
 // Kernel limits of a layout's rows (odd factor and real-input aware).
 bool layout_row_limits(hk_dtype_t dt, const Layout &lay, int E, KernelLimits *k);
 // Row-kernel limits of a layout's row length (odd factor aware).

@@ -135,16 +135,24 @@ def smooth_lengths(d):
     return out
 
 
+@pytest.fixture
+def smallest(L):
+    """Transform lengths: always the smallest with kernels (restored to auto)."""
+    assert L.hk_set_fft_lengths(2) == OK
+    yield
+    assert L.hk_set_fft_lengths(0) == OK
+
+
 @pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6, 7, 190, 193, 1100, 1537, 4097, 5000, 6145, 12000, 40961,
                                196606, 786433, 1048573, (1 << 24) - 5])
-def test_fft_layout(L, d):
+def test_fft_layout(L, smallest, d):
     n, r, c = fft_layout(L, d)
     assert n >= d and n == min(smooth_lengths(d))    # the smallest 2^k, 3 * 2^k, 5 * 2^k >= d_H
     assert n % (r * c) == 0 and n // (r * c) in (1, 3, 5)
     assert r & (r - 1) == 0 and c & (c - 1) == 0
 
 
-def test_fft_layout_cases(L):
+def test_fft_layout_cases(L, smallest):
     assert fft_layout(L, 1048573)[0] == 1 << 20       # the large single product stays a power of two
     assert fft_layout(L, 190) == (192, 64, 1)        # 3 sequences of 64, one workgroup holds it
     assert fft_layout(L, 1100) == (1280, 256, 1)     # 5 sequences of 256
@@ -233,3 +241,17 @@ def test_levels_argument_errors(L):
     vec2 = (ctypes.c_void_p * 3)(None, 256, 256)
     b2 = ctypes.c_size_t(0)
     assert f(HK_C64, 3, 2, dims, vec2, 1, 0, ctypes.byref(b2)) == OK and b2.value < b.value
+
+
+def test_length_policies(L):
+    """auto: odd-factor lengths once the power-of-two length reaches 2^18 (one
+    product); pow2: never; smallest: always; unknown policies rejected."""
+    assert L.hk_get_fft_lengths() == 0
+    assert fft_layout(L, 190)[0] == 256 and fft_layout(L, 12000)[0] == 16384
+    assert fft_layout(L, 196606)[0] == 3 << 16 and fft_layout(L, 1100000)[0] == 5 << 18
+    assert L.hk_set_fft_lengths(1) == OK
+    assert fft_layout(L, 196606)[0] == 1 << 18
+    assert L.hk_set_fft_lengths(2) == OK
+    assert fft_layout(L, 190)[0] == 192
+    assert L.hk_set_fft_lengths(7) == INVALID
+    assert L.hk_set_fft_lengths(0) == OK and L.hk_get_fft_lengths() == 0

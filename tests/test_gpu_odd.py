@@ -21,6 +21,16 @@ from test_gpu_batched import check_plan_outputs, mixed_problems, plan_inputs  # 
 from test_gpu_parity import check  # noqa: E402
 
 
+@pytest.fixture(autouse=True, scope="module")
+def smallest_lengths():
+    """These tests pin the odd-factor kernels, so every call here takes the
+    smallest length (the default policy takes them for large work only)."""
+    import paper_1401_6238_amd as hk
+    hk.hk_set_fft_lengths("smallest")
+    yield
+    hk.hk_set_fft_lengths("auto")
+
+
 def layout(d):
     """(odd factor, multipass) of the complex64 layout of d_H = d."""
     import paper_1401_6238_amd as hk
