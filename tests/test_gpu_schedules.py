@@ -95,3 +95,54 @@ def test_adjoint_schedules(tmp_path, dtype):
         torch.cuda.synchronize()
         assert rel(host(gx), gxo) <= TOL[dtype], sched
         assert rel(host(gh), gho) <= TOL[dtype], sched
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_odd_length_schedules(tmp_path, dtype):
+    """The 3-pass path on N = 3 * 2^12 under a sweep of schedules (row split,
+    rows per workgroup, rows in turn, column tiles, XCD numbering)."""
+    import paper_1401_6238_amd as hk
+    m, n = 3, 4096  # d_H = 12286, N = 3 * 4096
+    hk.hk_set_fft_lengths("smallest")
+    try:
+        prob = wl.random_problem(4343, m, [n] * m, True, want_alpha=True)
+        h, x = to_dev(prob.h, dtype), to_dev(prob.vectors[1], dtype)
+        yo, ao = oracle.tvp(m, [n] * m, seen(prob.h, dtype), [seen(prob.vectors[1], dtype)] * m, True, True)
+        key = (DT_CODE[dtype], 0, 0, 3, 12, -1, 0)
+        for sched in [(4, 1, 8, 8, 0, 0, 1), (4, 2, 16, 4, -1, 1, 2), (4, 1, 16, 16, 1, 0, 4), (4, 4, 8, 1, 0, 1, 1),
+                      (4, 1, 8, 16, -1, 0, 2)]:
+            print_case(test="odd_schedules", dtype=dtype, sched=sched)
+            install(tmp_path, key, sched)
+            y, a = hk.hankel_tvp(h, x, m, True, True)
+            torch.cuda.synchronize()
+            assert rel(host(y), yo) <= TOL[dtype], sched
+            assert abs(complex(host(a.reshape(1))[0]) - ao) <= 10 * TOL[dtype] * abs(ao), sched
+    finally:
+        hk.hk_set_fft_lengths("auto")
+
+
+def test_autotuned_odd_and_real_shapes():
+    """The autotuner on an odd-length strided batch and on a 3-pass real-input
+    product; the tuned schedules give the oracle's results."""
+    import paper_1401_6238_amd as hk
+    dtype = torch.complex64
+    m, n, B = 3, 4096, 16  # 16 x 2^14 >= 2^18: the default policy takes N = 3 * 2^12
+    print_case(test="autotune_odd_real")
+    hk.hk_autotune(dtype, "forward", m, n, batch=B)
+    probs = [wl.random_problem(4400 + b, m, [n] * m, True, want_alpha=True) for b in range(B)]
+    H = torch.stack([to_dev(p.h, dtype) for p in probs])
+    X = torch.stack([to_dev(p.vectors[1], dtype) for p in probs])
+    y, a = hk.hankel_tvp_strided_batched(H, X, m, True, True)
+    torch.cuda.synchronize()
+    for b, p in enumerate(probs[:3]):
+        yo, ao = oracle.tvp(m, [n] * m, seen(p.h, dtype), [seen(p.vectors[1], dtype)] * m, True, True)
+        assert rel(host(y[b]), yo) <= TOL[dtype]
+    rdt = torch.float32
+    m, n = 3, 5000  # real N = 16384: three passes on mirrored row pairs
+    hk.hk_autotune(rdt, "forward", m, n)
+    p = wl.random_problem(4500, m, [n] * m, True, complex_=False, want_alpha=True)
+    y, a = hk.hankel_tvp(to_dev(p.h, rdt), to_dev(p.vectors[1], rdt), m, True, True)
+    torch.cuda.synchronize()
+    yo, ao = oracle.tvp(m, [n] * m, seen(p.h, rdt), [seen(p.vectors[1], rdt)] * m, True, True)
+    assert rel(host(y), yo) <= TOL[rdt]
+    assert abs(complex(host(a.reshape(1))[0]) - ao) <= 10 * TOL[rdt] * abs(ao)
