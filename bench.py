@@ -313,8 +313,8 @@ def summarize_trace(trace_dir, command):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=2048)
+    ap.add_argument("--warmup", type=int, default=1024)
     ap.add_argument("--dtype", default="c64", choices=["c64", "c128"])
     ap.add_argument("--pool", type=int, default=32)
     ap.add_argument("--no-extras", action="store_true")
@@ -395,34 +395,48 @@ def main():
         if rc:
             _lib.check(rc, "hankel_tvp")
 
-    for i in range(args.warmup):
+    # Warm-up: W steps, the first (up to one pass over the pool) launched
+    # directly, the rest as graph replays.  The GPU clock ramps up over the
+    # first ~10 ms of work after idle; the default W covers ~30 ms.
+    n_eager = min(args.warmup, P)
+    for i in range(n_eager):
         step(i, sp)
     torch.cuda.synchronize()
-    graph = None
+    steps = args.steps
+    graph = graph_rem = None
     if not args.no_graph:
         # The library's launches for one pass over the pool are captured once
         # in a HIP graph and replayed: no per-launch host work in the timed
-        # region.  Each replay runs P independent products in sequence.
-        graph = torch.cuda.CUDAGraph()
-        cap = torch.cuda.Stream()
-        with torch.cuda.graph(graph, stream=cap):
-            csp = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
-            for k in range(P):
-                step(k, csp)
-        torch.cuda.synchronize()
-        graph.replay()
-        torch.cuda.synchronize()
-        reps = max(1, (args.steps + P - 1) // P)
-        steps = reps * P
+        # region.  Each replay runs P independent products in sequence; a
+        # second graph of the first K mod P products completes exactly K steps.
+        def capture(count):
+            gr = torch.cuda.CUDAGraph()
+            cap = torch.cuda.Stream()
+            with torch.cuda.graph(gr, stream=cap):
+                csp = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+                for k in range(count):
+                    step(k, csp)
+            torch.cuda.synchronize()
+            return gr
+        graph = capture(P)
+        if steps % P:
+            graph_rem = capture(steps % P)
+        for _ in range((args.warmup - n_eager) // P):
+            graph.replay()
+        for i in range((args.warmup - n_eager) % P):
+            step(i, sp)
     else:
-        steps = args.steps
+        for i in range(n_eager, args.warmup):
+            step(i, sp)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
     e0.record(stream)
     if graph is not None:
-        for _ in range(reps):
+        for _ in range(steps // P):
             graph.replay()
+        if graph_rem is not None:
+            graph_rem.replay()
     else:
         for i in range(steps):
             step(i, sp)
@@ -440,7 +454,7 @@ def main():
     # run back to back, as in the timed region, not host launch latency.
     torch.cuda._sleep(int(args.profile_delay_cycles))
     hk.hk_profile_start()
-    for i in range(steps):
+    for i in range(min(steps, 512)):
         step(i, sp)
     prof = hk.hk_profile_stop()
     torch.cuda.synchronize()
@@ -505,10 +519,21 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def time_region(torch, fn, reps, warm=2):
+def time_region(torch, fn, reps, warm=2, warm_ms=50.0, min_ms=20.0):
+    """Mean milliseconds per call of fn.  Warm-up: at least `warm` calls and
+    about `warm_ms` of work (the GPU clock ramps up over the first ~10 ms after
+    idle); the timed window holds at least `reps` calls and about `min_ms`."""
+    t0 = time.perf_counter()
     for _ in range(warm):
         fn()
     torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) * 1e3 / max(1, warm)
+    left = warm_ms - (time.perf_counter() - t0) * 1e3
+    if left > 0:
+        for _ in range(min(10000, int(left / max(per, 1e-3)) + 1)):
+            fn()
+        torch.cuda.synchronize()
+    reps = max(reps, min(10000, int(min_ms / max(per, 1e-3)) + 1))
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)

@@ -213,6 +213,8 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
       row_limits(dt, sh.odd, sh.logR, e_odd, &k);
       return k.tps;
     }
+    // grouped pass-B rows take 4 elements per lane up to 2048 points
+    if (!sh.resident && !p->persistent && sh.logR <= 11) return tps(sh.logR, 4);
     return tps(sh.logR, er);
   };
   // First virtual columns (sequence * R + storage column) of the column tiles
@@ -600,8 +602,9 @@ Status plan_release_after(hk_plan_t p, hipStream_t st) {
 // other fixed, twice.  Every candidate is timed on scratch buffers: inputs
 // distinct per instance (zero-filled), and for single products a pool of
 // input sets larger than the 256 MB last-level cache that successive launches
-// cycle through, so that inputs come from HBM as in use.  The winner is
-// cached under the key the call path looks up (dtype, program, 1D/BHHB, N,
+// cycle through, so that inputs come from HBM as in use.  A playoff of the
+// fastest candidates (interleaved repeated timings, median) picks the winner,
+// which is cached under the key the call path looks up (dtype, program, 1D/BHHB, N,
 // batch class).
 // ---------------------------------------------------------------------------
 Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
@@ -728,13 +731,20 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
   double best = 1e30;
   Sched bestsc;
   Layout bestlay;
+  struct Cand {
+    double t;
+    int li;  // index into layouts
+    Sched sc;
+  };
+  std::vector<Cand> seen;
   if (e == hipSuccess) {
-    for (const auto &sl : layouts) {
-      const Layout &lay = sl.second;
+    for (int li = 0; li < (int)layouts.size(); ++li) {
+      const Layout &lay = layouts[li].second;
       Sched cur = default_sched(dt, lay, p.prog, batch);
-      cur.split = sl.first;
+      cur.split = layouts[li].first;
       double tcur = time_sched(lay, cur);
       if (!s.ok()) break;
+      if (tcur < 1e30) seen.push_back({tcur, li, cur});
       for (int round = 0; round < 2 && s.ok(); ++round) {
         // row-pass parameters
         for (int er : {4, 8, 16})
@@ -748,6 +758,7 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
               if (c.E_row == cur.E_row && c.rows_per_wg == cur.rows_per_wg && c.iters == cur.iters) continue;
               const double tc = time_sched(lay, c);
               if (!s.ok()) break;
+              if (tc < 1e30) seen.push_back({tc, li, c});
               if (tc < tcur) {
                 tcur = tc;
                 cur = c;
@@ -765,6 +776,7 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
               if (c.E_col == cur.E_col && c.tw == cur.tw && c.xcd == cur.xcd) continue;
               const double tc = time_sched(lay, c);
               if (!s.ok()) break;
+              if (tc < 1e30) seen.push_back({tc, li, c});
               if (tc < tcur) {
                 tcur = tc;
                 cur = c;
@@ -775,6 +787,57 @@ Status autotune_problem(const Problem &proto, int64_t batch, bool verbose) {
         best = tcur;
         bestsc = cur;
         bestlay = lay;
+      }
+    }
+  }
+  // Playoff.  One timing of a candidate varies by a few percent from run to
+  // run, enough to crown a schedule that is no faster than the one it
+  // replaces.  The fastest few candidates, the default schedule and the
+  // schedule already cached under this key are timed again in interleaved
+  // rounds; the lowest median wins.
+  if (e == hipSuccess && s.ok() && !seen.empty()) {
+    std::stable_sort(seen.begin(), seen.end(), [](const Cand &a, const Cand &b) { return a.t < b.t; });
+    std::vector<Cand> fin;
+    auto same = [](const Sched &a, const Sched &b) {
+      return a.E_row == b.E_row && a.rows_per_wg == b.rows_per_wg && a.E_col == b.E_col && a.tw == b.tw &&
+             a.split == b.split && a.xcd == b.xcd && a.iters == b.iters;
+    };
+    auto add = [&](int li, const Sched &c) {
+      for (const Cand &f : fin)
+        if (f.li == li && same(f.sc, c)) return;
+      fin.push_back({0.0, li, c});
+    };
+    for (size_t i = 0; i < seen.size() && fin.size() < 4; ++i) add(seen[i].li, seen[i].sc);
+    for (int li = 0; li < (int)layouts.size(); ++li)
+      if (layouts[li].first == 0) {
+        Sched d = default_sched(dt, layouts[li].second, p.prog, batch);
+        d.split = 0;
+        add(li, d);
+      }
+    Sched inc;
+    if (sched_lookup(dt, p.prog, p.is_block ? 1 : 0, lay0.lclass(), lay0.logR + lay0.logC, p.is_block ? lay0.logC : -1,
+                     batch, &inc))
+      for (int li = 0; li < (int)layouts.size(); ++li)
+        if (layouts[li].first == inc.split) add(li, inc);
+    constexpr int kRounds = 5;
+    std::vector<std::vector<double>> ts(fin.size());
+    for (int r = 0; r < kRounds && s.ok(); ++r)
+      for (size_t i = 0; i < fin.size() && s.ok(); ++i)
+        ts[i].push_back(time_sched(layouts[fin[i].li].second, fin[i].sc));
+    if (s.ok()) {
+      best = 1e30;
+      for (size_t i = 0; i < fin.size(); ++i) {
+        std::sort(ts[i].begin(), ts[i].end());
+        const double med = ts[i][kRounds / 2];
+        if (verbose)
+          fprintf(stderr, "[hk autotune] playoff split=%d E_row=%d rows=%d iters=%d E_col=%d tw=%d xcd=%d : median %.4f ms\n",
+                  fin[i].sc.split, fin[i].sc.E_row, fin[i].sc.rows_per_wg, fin[i].sc.iters, fin[i].sc.E_col,
+                  fin[i].sc.tw, fin[i].sc.xcd, med);
+        if (med < best) {
+          best = med;
+          bestsc = fin[i].sc;
+          bestlay = layouts[fin[i].li].second;
+        }
       }
     }
   }

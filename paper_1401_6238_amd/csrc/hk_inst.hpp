@@ -13,9 +13,16 @@
 namespace hk {
 namespace HK_NS {
 
+// Rows of 4 elements per lane take up to 512 lanes: fewer registers, more
+// waves per SIMD, more LDS exchanges (the autotuner picks them where that
+// pays, e.g. in batches); 8 and 16 elements per lane take up to ROW_MAXT.
+constexpr int ROW_MAXT_E4 = 512;
+constexpr int row_maxt(int E) { return E == 4 ? ROW_MAXT_E4 : ROW_MAXT; }
+
 template <int L, int E>
 static void *row_fn(int prog) {
-  return prog == PROG_BWD ? (void *)&k_rows<L, E, ROW_MAXT, PROG_BWD> : (void *)&k_rows<L, E, ROW_MAXT, PROG_FWD>;
+  return prog == PROG_BWD ? (void *)&k_rows<L, E, row_maxt(E), PROG_BWD>
+                          : (void *)&k_rows<L, E, row_maxt(E), PROG_FWD>;
 }
 template <int L, int E>
 static void *col_fn(int var) {
@@ -65,6 +72,7 @@ static void *pick_col(int logL, int var) {
 
 static void *row_kernel(int logL, int E, int prog) {
   if (logL < 0 || logL > MAX_LOGL) return nullptr;
+  if (E == 4) return logL <= 11 ? pick_row<4>(logL, prog) : nullptr;
   if (E == 8) return pick_row<8>(logL, prog);
   if (E == 16) return pick_row<16>(logL, prog);
   return nullptr;
@@ -84,7 +92,7 @@ static KernelLimits lim_of() {
   k.seq_lds = S::ROW_SEQ;
   k.lds_raw = S::LDS;
   k.elem_bytes = (int)sizeof(cx<T>);
-  k.row_maxt = ROW_MAXT;
+  k.row_maxt = row_maxt(E);
   return k;
 }
 
@@ -179,7 +187,8 @@ hipError_t HK_CAT(init_tables_, HK_SUFFIX)(const double *tw4096, const double *t
 bool HK_CAT(limits_, HK_SUFFIX)(int logL, int E, KernelLimits *out) {
   using namespace HK_NS;
   if (logL < 0 || logL > MAX_LOGL) return false;
-  if (E == 8) *out = lim_pick<8>(logL);
+  if (E == 4 && logL <= 11) *out = lim_pick<4>(logL);
+  else if (E == 8) *out = lim_pick<8>(logL);
   else if (E == 16) *out = lim_pick<16>(logL);
   else return false;
   return true;
@@ -192,7 +201,7 @@ hipError_t HK_CAT(launch_rows_, HK_SUFFIX)(int logL, int E, int rows_per_wg, dim
   KernelLimits k;
   if (!fn || !HK_CAT(limits_, HK_SUFFIX)(logL, E, &k)) return hipErrorInvalidValue;
   const int threads = rows_per_wg * k.tps;
-  if (threads < 1 || threads > ROW_MAXT) return hipErrorInvalidValue;
+  if (threads < 1 || threads > k.row_maxt) return hipErrorInvalidValue;
   size_t lds = (size_t)rows_per_wg * k.seq_lds * sizeof(cx<T>);
   const size_t red = (size_t)threads * sizeof(cx<T>);
   if (lds < red) lds = red;
@@ -268,7 +277,7 @@ static size_t group_lds_elems(int kind, int logL) {
   size_t mx = (size_t)BATCH_BLK;
   if (kind == GK_RES || kind == GK_ROWB) {
     KernelLimits kr;
-    HK_CAT(limits_, HK_SUFFIX)(logL, BATCH_E_ROW, &kr);
+    HK_CAT(limits_, HK_SUFFIX)(logL, kind == GK_ROWB && logL <= 11 ? 4 : BATCH_E_ROW, &kr);
     if (kr.tps <= BATCH_BLK) mx = std::max(mx, (size_t)(BATCH_BLK / kr.tps) * kr.seq_lds);
   } else if (kind == GK_COL) {
     KernelLimits kc;
