@@ -565,6 +565,68 @@ def cpu_fft_method(h, x, m, reps=3):
     return {"TVP_s": round(1.0 / t, 2), "ms": round(t * 1e3, 2), "cores": workers, "kind": "scipy.fft c128"}
 
 
+def independent_products(data, hk, _lib, L, torch, dev):
+    """Throughput of independent large products (the headline shape, c64) with
+    several in flight.  One product runs each pass as a single generation of
+    workgroups and leaves the GPU latency-bound; products on S streams (each
+    with its own workspace, each stream replaying a captured graph of P/S
+    products four times between joins) or
+    one strided batched call over the pool overlap their passes.  Each product
+    is computed exactly as in the headline step."""
+    P = len(data["large"])
+    hs = [torch.from_numpy(d[0]).to(dev) for d in data["large"]]
+    xs = [torch.from_numpy(d[1]).to(dev) for d in data["large"]]
+    ys = [torch.empty(NVEC, dtype=torch.complex64, device=dev) for _ in range(P)]
+    als = torch.empty(P, dtype=torch.complex64, device=dev)
+    nb = ctypes.c_size_t(0)
+    _lib.check(L.hankel_tvp_workspace_size(_lib.HK_C64, M, NVEC, ctypes.byref(nb)), "ws")
+    res = {}
+    for S in (1, 2, 3, 4):
+        per = P // S
+        wss = [torch.empty(nb.value, dtype=torch.uint8, device=dev) for _ in range(S)]
+
+        def step(k, sp, w):
+            _lib.check(L.hankel_tvp(_lib.HK_C64, ctypes.c_void_p(hs[k].data_ptr()), M, NVEC,
+                                    ctypes.c_void_p(xs[k].data_ptr()), ctypes.c_void_p(ys[k].data_ptr()),
+                                    ctypes.c_void_p(als.data_ptr() + 8 * k), ctypes.c_void_p(wss[w].data_ptr()),
+                                    ctypes.c_size_t(nb.value), sp), "hankel_tvp")
+        graphs = []
+        for i in range(S):
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr, stream=torch.cuda.Stream()):
+                csp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+                for k in range(i * per, (i + 1) * per):
+                    step(k, csp, i)
+            torch.cuda.synchronize()
+            graphs.append(gr)
+        streams = [torch.cuda.Stream() for _ in range(S)]
+
+        def run():
+            main = torch.cuda.current_stream()
+            ev = torch.cuda.Event()
+            ev.record(main)
+            for st in streams:
+                st.wait_event(ev)
+            for _ in range(4):
+                for gi, st in enumerate(streams):
+                    with torch.cuda.stream(st):
+                        graphs[gi].replay()
+            for st in streams:
+                e = torch.cuda.Event()
+                e.record(st)
+                main.wait_event(e)
+        ms = time_region(torch, run, 8) / (4 * per * S)
+        res[f"streams_{S}"] = {"TVP_s": round(1000 / ms, 1), "us_per_product": round(ms * 1e3, 2)}
+        del graphs, wss
+    H = torch.stack(hs)
+    X = torch.stack(xs)
+    del hs, xs, ys
+    ms = time_region(torch, lambda: hk.hankel_tvp_strided_batched(H, X, M, True, True), 5) / P
+    res[f"strided_batch_{P}"] = {"TVP_s": round(1000 / ms, 1), "us_per_product": round(ms * 1e3, 2)}
+    del H, X
+    return res
+
+
 def run_extras(args, data, hk, _lib, L, torch, dev):
     ex = {}
     ex["large_single_cpu_fft_method"] = cpu_fft_method(data["large"][0][2], data["large"][0][3], M)
@@ -608,6 +670,8 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
                                        "complex_path_TVP_s": round(1000 / ms_c, 1), "complex_path_ms": round(ms_c, 4)}
         del hr, xr, hc, xc
         log("large real", ex["large_single_real_f32"])
+        ex["large_single_throughput_c64"] = independent_products(data, hk, _lib, L, torch, dev)
+        log("independent large products", ex["large_single_throughput_c64"])
 
     # mixed batch: 4096 instances, one persistent launch vs per-pass launches vs plain loop
     mixed = data["mixed"]
