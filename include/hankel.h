@@ -113,6 +113,50 @@ hk_status_t hankel_mode_products(hk_dtype_t dt, const void *h, int m, const int6
                                  size_t ws_bytes, hipStream_t stream);
 
 /* -------------------------------------------------------------------------
+ * Spectral form (Section 3: the products are pointwise products of the
+ * spectra h^ = ifft(pad_N h) and x^_p = fft(pad_N x_p) on one transform length
+ * N >= d_H, followed by one transform).  A spectrum computed once serves every
+ * product that shares its operand: a fixed h met by many vectors (power
+ * iterations, HOOI), a vector met by many h.  Complex dtypes (HK_C64,
+ * HK_C128) and d_H = sum(dims) - m + 1 above 4096; other shapes return
+ * HK_ERR_NOT_SUPPORTED.
+ *
+ * Layout: N is the power of two >= d_H; R = 2^ceil(log2(N) / 2) and C = N / R.
+ * A spectrum is N elements of the dtype; element r R + c (r < C, c < R) holds
+ * bin r + C c.  The layout depends only on dt and d_H, so spectra of separate
+ * calls combine whenever their shapes have the same d_H.
+ *
+ * hankel_spectrum_layout: *n_fft = N, *row_len = R for the shape (m, dims).
+ * hankel_spectrum: which = -1: src = h (d_H elements), spec receives h^
+ *   (including the 1/N of the inverse transform); which = p in [0, m):
+ *   src = x_p (dims[p] elements), spec receives x^_p.  spec must not overlap
+ *   src or ws.  Workspace: hankel_spectrum_workspace_size.
+ * hankel_mode_products_spectral: h_spec = h^ (from hankel_spectrum with
+ *   which = -1 on the same shape).  Mode p's operand is specs[p] (a spectrum)
+ *   when specs is non-NULL and specs[p] is non-NULL, else vectors[p] (the
+ *   vector itself); vectors and specs may each be NULL.  Mode 0 is read only
+ *   when alpha is requested.  y and alpha as in hankel_mode_products; equal
+ *   operands (same pointer, length and kind) are used once, as a power.
+ *   Workspace: hankel_mode_products_spectral_workspace_size, with the same
+ *   vectors/specs pointers (they decide which operands are merged).
+ * Errors as for hankel_mode_products.
+ * ------------------------------------------------------------------------- */
+hk_status_t hankel_spectrum_layout(hk_dtype_t dt, int m, const int64_t *dims, int64_t *n_fft,
+                                   int64_t *row_len);
+hk_status_t hankel_spectrum_workspace_size(hk_dtype_t dt, int m, const int64_t *dims, int which,
+                                           size_t *bytes);
+hk_status_t hankel_spectrum(hk_dtype_t dt, int m, const int64_t *dims, int which, const void *src,
+                            void *spec, void *ws, size_t ws_bytes, hipStream_t stream);
+hk_status_t hankel_mode_products_spectral_workspace_size(hk_dtype_t dt, int m, const int64_t *dims,
+                                                         const void *const *vectors,
+                                                         const void *const *specs, int want_y,
+                                                         int want_alpha, size_t *bytes);
+hk_status_t hankel_mode_products_spectral(hk_dtype_t dt, const void *h_spec, int m,
+                                          const int64_t *dims, const void *const *vectors,
+                                          const void *const *specs, void *y, void *alpha,
+                                          void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* -------------------------------------------------------------------------
  * 2-level block Hankel tensor with Hankel blocks (BHHB; Section 2.2
  * generating matrix, Section 3 BHHB procedure).  Mode p has N_p blocks of
  * size n_p; the tensor entry at in-block indices (i_p) and block indices
@@ -241,8 +285,11 @@ hk_status_t block_hankel_tvp_levels(hk_dtype_t dt, const void *G, int m, int k, 
  * mode product, i.e. column (j_2, ..., j_m) of T is the tensor-vector product
  * H x_2 U[:, j_2] ... x_m U[:, j_m].  out is n x R^(m-1), column-major, column
  * index j_2 + R j_3 + ... + R^(m-2) j_m.  The columns are symmetric in the j's:
- * the library computes the nondecreasing tuples (a grouped batch of mode
- * products) and copies the rest.  R^(m-1) <= 2^20.  The call enqueues its
+ * the library computes the nondecreasing tuples and copies the rest.  For
+ * complex dtypes with d_H > 4096 and (tuples x N) >= 2^21 it transforms h and
+ * each column of U once (the spectral form above) and forms every tuple as a
+ * product of those spectra followed by one transform; otherwise each tuple is
+ * a mode product of a grouped batch.  R^(m-1) <= 2^20.  The call enqueues its
  * work on `stream` and waits for it (its descriptor tables live on the host
  * until then).  Used by HOOI (Algorithm 4.2) for the Hankel tensor-matrix
  * products that dominate it.

@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (OpenMP, -O2).  Returns the library path."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp]
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -52,10 +52,11 @@ def _lib():
         lib.hko_block_tvp_i64.argtypes = [ctypes.c_int, P, P, P, P, P, P]
         lib.hko_block_tvp_sampled.argtypes = [ctypes.c_int, P, P, P, P, P, I64, P, P]
         lib.hko_tvp_backward.argtypes = [ctypes.c_int, I64, P, P, P, P, P, P]
+        lib.hko_dft_sampled.argtypes = [ctypes.c_int, P, I64, I64, P, I64, P]
         lib.hko_max_threads.argtypes = []
         for f in (lib.hko_conv_range, lib.hko_conv, lib.hko_corr, lib.hko_tvp, lib.hko_tvp_sampled,
                   lib.hko_tvp_i64, lib.hko_block_tvp, lib.hko_block_tvp_i64, lib.hko_block_tvp_sampled,
-                  lib.hko_tvp_backward,
+                  lib.hko_tvp_backward, lib.hko_dft_sampled,
                   lib.hko_max_threads):
             f.restype = ctypes.c_int
         _lib_handle = lib
@@ -264,6 +265,18 @@ def tvp_backward(m: int, h, x, v=None, phi=None, want_grad_x: bool = True, want_
     _check(_lib().hko_tvp_backward(m, n, _ptr(h), _ptr(x), _ptr(v), _ptr(ph), _ptr(gx), _ptr(gh)),
            "tvp_backward")
     return gx, gh
+
+
+def spectrum(a, N: int, idx=None, inverse: bool = False) -> np.ndarray:
+    """Section 3 spectra as plain DFT sums (no FFT): fft(pad_N a) at the bins
+    idx (all N bins when idx is None), or with inverse=True ifft(pad_N a)
+    = (1/N) sum_s a_s e^{+2 pi i j s / N}, the h^ of the fast procedures."""
+    a = _c128(a)
+    idx = np.arange(N, dtype=np.int64) if idx is None else np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(len(idx), np.complex128)
+    _check(_lib().hko_dft_sampled(1 if inverse else -1, _ptr(a), len(a), int(N), _ptr(idx), len(idx), _ptr(out)),
+           "dft")
+    return out
 
 
 def tensor_matrix(m: int, h, U) -> np.ndarray:

@@ -33,6 +33,11 @@
  *   grad_h[s] = sum_i conj(w_{s-i}) v_i + phi conj(u_s)        (w = x^{*(m-1)}, u = x^{*m})
  *   grad_x[l] = (m-1) conj( sum_k h_{l+k} c_k ) + m phi conj(g_l)   (c = conj(v) * x^{*(m-2)})
  *
+ * Spectra: the fast procedures of Section 3 multiply h^ = ifft(pad_N h) and
+ * x^ = fft(pad_N x).  hko_dft_sampled evaluates these two transforms at listed
+ * bins as plain DFT sums (a sum over the samples per bin, with the phase
+ * index j s reduced mod N exactly in integers); it is not an FFT.
+ *
  * Arithmetic: FP64 (complex as interleaved re/im pairs).  Long sums are
  * accumulated in consecutive blocks of 256 terms whose partial sums are then
  * added in order, which keeps the rounding error of sums of ~10^6 terms well
@@ -43,6 +48,7 @@
  * is always summed in the same order, so results do not depend on the thread
  * count.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -512,4 +518,39 @@ int hko_tvp_backward(int m, int64_t n, const hkc *h, const hkc *x, const hkc *v,
     }
     free(w); free(w2); free(dims); free(vecs);
     return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spectra of the Section 3 procedures, as DFT sums at the bins idx[]:       */
+/*   sign = -1:  out_i = sum_{s<len} a_s e^{-2 pi i j s / N}          (fft)   */
+/*   sign = +1:  out_i = (1/N) sum_{s<len} a_s e^{+2 pi i j s / N}    (ifft)  */
+/* with j = idx[i] mod N; a is zero-padded from len to N samples.            */
+/* ------------------------------------------------------------------------ */
+int hko_dft_sampled(int sign, const hkc *a, int64_t len, int64_t N, const int64_t *idx, int64_t nidx, hkc *out) {
+    if (N < 1 || len < 0 || len > N || (sign != 1 && sign != -1) || nidx < 0) return -1;
+    hkc *w = (hkc *)malloc(sizeof(hkc) * (size_t)N);
+    if (!w) return -2;
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int64_t k = 0; k < N; ++k) {
+        const long double t = two_pi * ((long double)k / (long double)N);
+        w[k].re = (double)cosl(t);
+        w[k].im = (double)(sign * sinl(t));
+    }
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < nidx; ++i) {
+        const int64_t j = ((idx[i] % N) + N) % N;
+        hkc total = { 0.0, 0.0 }, part = { 0.0, 0.0 };
+        int cnt = 0;
+        int64_t k = 0;  /* j s mod N */
+        for (int64_t s = 0; s < len; ++s) {
+            part = cadd(part, cmul(a[s], w[k]));
+            if (++cnt == BLOCK) { total = cadd(total, part); part.re = part.im = 0.0; cnt = 0; }
+            k += j;
+            if (k >= N) k -= N;
+        }
+        total = cadd(total, part);
+        out[i] = sign > 0 ? cscale(total, 1.0 / (double)N) : total;
+    }
+    free(w);
+    return 0;
 }

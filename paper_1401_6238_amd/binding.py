@@ -122,6 +122,58 @@ def hankel_mode_products(h: torch.Tensor, vectors: Sequence[Optional[torch.Tenso
     return y, (None if alpha is None else alpha[0])
 
 
+def hankel_spectrum_layout(dtype: torch.dtype, m: int, dims: Sequence[int]) -> Tuple[int, int]:
+    """(N, R) of the spectra of shape (m, dims): element r*R + c of a spectrum
+    holds bin r + (N/R)*c of the length-N transform."""
+    n_fft, row = ctypes.c_int64(0), ctypes.c_int64(0)
+    check(lib().hankel_spectrum_layout(_DT[dtype], m, _i64arr(dims), ctypes.byref(n_fft), ctypes.byref(row)),
+          "hankel_spectrum_layout")
+    return n_fft.value, row.value
+
+
+def hankel_spectrum(src: torch.Tensor, m: int, dims: Sequence[int], which: int = -1) -> torch.Tensor:
+    """Spectrum of h (which = -1: h^ = ifft(pad_N h)) or of the vector of mode
+    `which` (x^ = fft(pad_N x)), in the library's row order (N elements)."""
+    _dev(src)
+    dt = _dtype(src)
+    n_fft, _ = hankel_spectrum_layout(src.dtype, m, dims)
+    spec = torch.empty(n_fft, dtype=src.dtype, device=src.device)
+    d = _i64arr(dims)
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_spectrum_workspace_size(dt, m, d, which, ctypes.byref(nb)), "hankel_spectrum_workspace_size")
+    ws, wsb = _workspace(nb.value, src.device)
+    check(lib().hankel_spectrum(dt, m, d, which, _ptr(src), _ptr(spec), _ptr(ws), wsb, _stream(src.device)),
+          "hankel_spectrum")
+    return spec
+
+
+def hankel_mode_products_spectral(h_spec: torch.Tensor, m: int, dims: Sequence[int],
+                                  vectors: Optional[Sequence[Optional[torch.Tensor]]] = None,
+                                  specs: Optional[Sequence[Optional[torch.Tensor]]] = None,
+                                  want_y: bool = True, want_alpha: bool = False):
+    """Mode products from h^ (hankel_spectrum(h, m, dims)); mode p's operand is
+    specs[p] (a spectrum) if given, else vectors[p].  Returns (y, alpha)."""
+    _dev(h_spec)
+    ts = [t for t in list(vectors or []) + list(specs or []) if t is not None]
+    for t in ts:
+        _dev(t)
+    _same_device(h_spec, *ts)
+    dt = _dtype(h_spec)
+    y = torch.empty(int(dims[0]), dtype=h_spec.dtype, device=h_spec.device) if want_y else None
+    alpha = torch.empty(1, dtype=h_spec.dtype, device=h_spec.device) if want_alpha else None
+    d = _i64arr(dims)
+    va = _vecarr(list(vectors)) if vectors is not None else None
+    sa = _vecarr(list(specs)) if specs is not None else None
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_mode_products_spectral_workspace_size(dt, m, d, va, sa, int(want_y), int(want_alpha),
+                                                             ctypes.byref(nb)),
+          "hankel_mode_products_spectral_workspace_size")
+    ws, wsb = _workspace(nb.value, h_spec.device)
+    check(lib().hankel_mode_products_spectral(dt, _ptr(h_spec), m, d, va, sa, _ptr(y), _ptr(alpha), _ptr(ws), wsb,
+                                              _stream(h_spec.device)), "hankel_mode_products_spectral")
+    return y, (None if alpha is None else alpha[0])
+
+
 def block_hankel_tvp(H: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]], inner_dims: Sequence[int],
                      block_dims: Sequence[int], want_y: bool = True, want_alpha: bool = False):
     """BHHB tensor: H is the column-major generating matrix (flat); vectors are vec(X_p)."""

@@ -339,6 +339,211 @@ hk_status_t hankel_mode_products(hk_dtype_t dt, const void *h, int m, const int6
   return finish(run_one(p, ws, ws_bytes, stream));
 }
 
+// ---------------------------------------------------------------------------
+// Spectral form.  The fast product is a pointwise product of spectra,
+// h^ = ifft(pad_N h) and x^_p = fft(pad_N x_p) on one transform length N
+// (Section 3, the procedures for the mode products and the scalar).  A
+// spectrum computed once serves every product that shares the operand.
+// Spectra use the power-of-two three-pass layout with the balanced split
+// (row length R = 2^ceil(log2(N) / 2), C = N / R rows), so that spectra made by
+// separate calls combine; element r R + c holds bin r + C c.
+// ---------------------------------------------------------------------------
+static Status spectral_problem(hk_dtype_t dt, int m, const int64_t *dims, Problem *out) {
+  if (dt != HK_C64 && dt != HK_C128) return fail(HK_ERR_NOT_SUPPORTED, "spectra are implemented for complex dtypes");
+  if (m < 2 || m > HK_MAX_ORDER) return fail(HK_ERR_INVALID_VALUE, "order m must be in [2, 8]");
+  if (!dims) return fail(HK_ERR_NULL_POINTER, "dims is NULL");
+  Problem p;
+  p.dt = dt;
+  p.prog = PROG_FWD;
+  p.m = m;
+  for (int q = 0; q < m; ++q) {
+    if (dims[q] < 1) return fail(HK_ERR_INVALID_VALUE, "every dimension must be >= 1");
+    if (dims[q] > ((int64_t)1 << 40)) return fail(HK_ERR_SIZE_LIMIT, "dimension too large");
+    p.dims[q] = dims[q];
+  }
+  *out = p;
+  return Status();
+}
+
+static Status spectral_setup(const Problem &p, Layout *lay, Sched *sc) {
+  Status s = layout_for(p, 0, lay, /*allow_odd=*/false, 1);
+  if (!s.ok()) return s;
+  if (lay->resident || lay->odd != 1 || lay->r2c)
+    return fail(HK_ERR_NOT_SUPPORTED, "spectra need the three-pass layout: d_H above 4096");
+  Sched sch;
+  const int logM = lay->logR + lay->logC;
+  if (sched_lookup(p.dt, PROG_FWD, 0, lay->lclass(), logM, -1, 1, &sch) && sch.split == 0 &&
+      sched_valid(p.dt, *lay, sch))
+    *sc = sch;
+  else
+    *sc = default_sched(p.dt, *lay, PROG_FWD, 1);
+  if (!sched_valid(p.dt, *lay, *sc)) return fail(HK_ERR_NOT_SUPPORTED, "no valid schedule for this shape");
+  return Status();
+}
+
+// The spectrum program: the column pass of one operand (h for which = -1,
+// the vector of mode `which` otherwise), its row transform stored to `spec`
+// in row order, no product.
+static Status spectrum_prepare(hk_dtype_t dt, int m, const int64_t *dims, int which, const void *src, void *spec,
+                               Shape *sh, Ptrs *P, Sched *sc) {
+  Problem p;
+  Status s = spectral_problem(dt, m, dims, &p);
+  if (!s.ok()) return s;
+  if (which < -1 || which >= m) return fail(HK_ERR_INVALID_VALUE, "which must be -1 (h) or a mode in [0, m)");
+  Layout lay;
+  s = spectral_setup(p, &lay, sc);
+  if (!s.ok()) return s;
+  const void *dummy = (const void *)256;
+  p.h = dummy;
+  for (int q = 0; q < m; ++q) p.vec[q] = dummy;
+  p.y = (void *)256;
+  Shape b;
+  Ptrs bp;
+  s = build_shape(p, lay, *sc, &b, &bp, nullptr);
+  if (!s.ok()) return s;
+  OpDesc od = b.ops[0];  // h: conjugated on load, conjugated and scaled by 1/N after the row transform
+  if (which >= 0) {
+    od.role = ROLE_X;
+    od.exp = 0;
+    od.flags = 0;
+    od.len = dims[which];
+    od.cols = 1;
+    od.ncol_nz = std::min<int64_t>((int64_t)1 << lay.logR, dims[which]);
+  }
+  od.flags |= OPF_STORE_SPEC;
+  od.buf = 0;
+  b.ops[0] = od;
+  b.nops = 1;
+  b.want_y = 0;
+  b.want_alpha = 0;
+  b.nbuf = 1;
+  const size_t eb = cplx_bytes(dt);
+  b.ws_bytes = (int64_t)(((((size_t)1 << (lay.logR + lay.logC)) + (size_t)b.partials) * eb + 255) & ~(size_t)255);
+  memset(&bp, 0, sizeof(bp));
+  bp.op[0] = src;
+  bp.y = spec;
+  *sh = b;
+  *P = bp;
+  return Status();
+}
+
+hk_status_t hankel_spectrum_layout(hk_dtype_t dt, int m, const int64_t *dims, int64_t *n_fft, int64_t *row_len) {
+  if (!n_fft || !row_len) return finish(fail(HK_ERR_NULL_POINTER, "n_fft or row_len is NULL"));
+  Problem p;
+  Status s = spectral_problem(dt, m, dims, &p);
+  if (!s.ok()) return finish(s);
+  Layout lay;
+  Sched sc;
+  s = spectral_setup(p, &lay, &sc);
+  if (!s.ok()) return finish(s);
+  *n_fft = (int64_t)1 << (lay.logR + lay.logC);
+  *row_len = (int64_t)1 << lay.logR;
+  return finish(Status());
+}
+
+hk_status_t hankel_spectrum_workspace_size(hk_dtype_t dt, int m, const int64_t *dims, int which, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  Status s = spectrum_prepare(dt, m, dims, which, nullptr, nullptr, &sh, &P, &sc);
+  if (!s.ok()) return finish(s);
+  *bytes = instance_ws_bytes(sh, dt);
+  return finish(Status());
+}
+
+hk_status_t hankel_spectrum(hk_dtype_t dt, int m, const int64_t *dims, int which, const void *src, void *spec,
+                            void *ws, size_t ws_bytes, hipStream_t stream) {
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  Status s = spectrum_prepare(dt, m, dims, which, src, spec, &sh, &P, &sc);
+  if (!s.ok()) return finish(s);
+  if (!src || !spec) return finish(fail(HK_ERR_NULL_POINTER, "src or spec is NULL"));
+  const size_t a = elem_bytes(dt);
+  if (!aligned(src, a) || !aligned(spec, a)) return finish(fail(HK_ERR_MISALIGNED, "pointer not aligned to the element size"));
+  s = check_ws(instance_ws_bytes(sh, dt), ws, ws_bytes);
+  if (!s.ok()) return finish(s);
+  s = ensure_device();
+  if (!s.ok()) return finish(s);
+  P.ws = ws;
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  return finish(launch_shape(dt, sh, sc, P, str, 1, stream));
+}
+
+// Mode products with h given by its spectrum and each vector by itself or by
+// its spectrum (specs[q] non-NULL).
+static Status spectral_products_problem(hk_dtype_t dt, const void *h_spec, int m, const int64_t *dims,
+                                        const void *const *vectors, const void *const *specs, void *y, void *alpha,
+                                        Problem *out) {
+  Problem p;
+  Status s = spectral_problem(dt, m, dims, &p);
+  if (!s.ok()) return s;
+  p.h = h_spec;
+  p.h_spec = true;
+  for (int q = 0; q < m; ++q) {
+    if (q == 0 && !alpha) continue;
+    if (specs && specs[q]) {
+      p.vec[q] = specs[q];
+      p.spec_mask |= 1u << q;
+    } else if (vectors) {
+      p.vec[q] = vectors[q];
+    }
+  }
+  p.y = y;
+  p.alpha = alpha;
+  s = validate_forward(p);
+  if (!s.ok()) return s;
+  *out = p;
+  return Status();
+}
+
+static Status spectral_products_prepare(const Problem &p, Shape *sh, Ptrs *P, Sched *sc) {
+  Layout lay;
+  Status s = spectral_setup(p, &lay, sc);
+  if (!s.ok()) return s;
+  return build_shape(p, lay, *sc, sh, P, nullptr);
+}
+
+hk_status_t hankel_mode_products_spectral_workspace_size(hk_dtype_t dt, int m, const int64_t *dims,
+                                                         const void *const *vectors, const void *const *specs,
+                                                         int want_y, int want_alpha, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  Problem p;
+  Status s = spectral_products_problem(dt, (const void *)256, m, dims, vectors, specs,
+                                       want_y ? (void *)256 : nullptr, want_alpha ? (void *)256 : nullptr, &p);
+  if (!s.ok()) return finish(s);
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  s = spectral_products_prepare(p, &sh, &P, &sc);
+  if (!s.ok()) return finish(s);
+  *bytes = instance_ws_bytes(sh, dt);
+  return finish(Status());
+}
+
+hk_status_t hankel_mode_products_spectral(hk_dtype_t dt, const void *h_spec, int m, const int64_t *dims,
+                                          const void *const *vectors, const void *const *specs, void *y,
+                                          void *alpha, void *ws, size_t ws_bytes, hipStream_t stream) {
+  Problem p;
+  Status s = spectral_products_problem(dt, h_spec, m, dims, vectors, specs, y, alpha, &p);
+  if (!s.ok()) return finish(s);
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  s = spectral_products_prepare(p, &sh, &P, &sc);
+  if (!s.ok()) return finish(s);
+  s = check_ws(instance_ws_bytes(sh, dt), ws, ws_bytes);
+  if (!s.ok()) return finish(s);
+  s = ensure_device();
+  if (!s.ok()) return finish(s);
+  P.ws = ws;
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  return finish(launch_shape(dt, sh, sc, P, str, 1, stream));
+}
+
 hk_status_t block_hankel_tvp_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims, const int64_t *block_dims,
                                             const void *const *vectors, int want_y, int want_alpha, size_t *bytes) {
   if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
@@ -698,12 +903,210 @@ static Status tm_layout(hk_dtype_t dt, const void *h, int m, int64_t n, int64_t 
   return Status();
 }
 
+// Tensor-matrix product from spectra (complex dtypes, three-pass layouts):
+// h^ once, the R columns of U once, then for every nondecreasing tuple the
+// product of its spectra and one output transform (the grouped batch of mode
+// products transforms h and the tuple's columns again for every column of T).
+// All tuples run in one strided launch per pass: operand t of tuple k is the
+// spectrum of U[:, s_{t-1}(k)], looked up in a per-operand pointer table, and
+// the outputs go to a staging area from which one gather fills every column
+// of T (the symmetric ones included).
+// Workspace: [h^ | U^ (R spectra) | B instances | staging (K columns) |
+//             pointer tables ((m-1) K) | gather pairs (2 R^(m-1))].
+struct TmSpectral {
+  Layout lay;
+  Sched sc;
+  int64_t N = 0, K = 0, ncols = 0;
+  int64_t batch = 0;    // instances per launch
+  size_t inst_ws = 0;   // bytes per instance
+  size_t off_u = 0, off_inst = 0, off_stage = 0, off_tab = 0, off_pairs = 0, bytes = 0;
+  std::vector<int32_t> digits;  // K x (m-1) nondecreasing digits, tuple-major
+  std::vector<int32_t> pairs;   // (column of T, tuple) for every column
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static bool tm_spectral_plan(hk_dtype_t dt, int m, int64_t n, int64_t R, TmSpectral *T) {
+  if (dt != HK_C64 && dt != HK_C128) return false;
+  if (R < 1 || m < 2 || m > HK_MAX_ORDER) return false;
+  int64_t dims[HK_MAX_ORDER];
+  for (int q = 0; q < m; ++q) dims[q] = n;
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  if (!spectrum_prepare(dt, m, dims, -1, nullptr, nullptr, &sh, &P, &sc).ok()) return false;
+  Problem p;
+  if (!spectral_problem(dt, m, dims, &p).ok() || !spectral_setup(p, &T->lay, &T->sc).ok()) return false;
+  T->N = (int64_t)1 << (T->lay.logR + T->lay.logC);
+  // the product program (all operands spectra) needs one buffer, as the
+  // spectrum program does
+  T->inst_ws = instance_ws_bytes(sh, dt);
+  int64_t ncols = 1;
+  for (int q = 1; q < m; ++q) ncols *= R;
+  if (ncols > (1 << 20)) return false;
+  T->ncols = ncols;
+  // tuples: the columns whose digits (least significant first) are nondecreasing
+  const int d = m - 1;
+  std::vector<int32_t> tuple_of(ncols, -1), j(d);
+  T->digits.clear();
+  for (int64_t c = 0; c < ncols; ++c) {
+    int64_t r = c;
+    bool sorted = true;
+    for (int q = 0; q < d; ++q) {
+      j[q] = (int32_t)(r % R);
+      r /= R;
+      if (q > 0 && j[q] < j[q - 1]) sorted = false;
+    }
+    if (sorted) {
+      tuple_of[c] = (int32_t)(T->digits.size() / d);
+      T->digits.insert(T->digits.end(), j.begin(), j.end());
+    }
+  }
+  T->K = (int64_t)(T->digits.size() / d);
+  // Below about 2^21 spectral elements of products the launches, not the
+  // transforms, set the time, and the grouped batch (fewer launches) is
+  // as fast or faster.
+  if (T->K * T->N < ((int64_t)1 << 21)) return false;
+  T->pairs.resize(2 * ncols);
+  for (int64_t c = 0; c < ncols; ++c) {
+    int64_t r = c;
+    for (int q = 0; q < d; ++q) {
+      j[q] = (int32_t)(r % R);
+      r /= R;
+    }
+    std::sort(j.begin(), j.end());
+    int64_t cc = 0;
+    for (int q = d - 1; q >= 0; --q) cc = cc * R + j[q];
+    T->pairs[2 * c] = (int32_t)c;
+    T->pairs[2 * c + 1] = tuple_of[cc];
+  }
+  const size_t eb = elem_bytes(dt);
+  T->batch = std::max<int64_t>(1, std::min<int64_t>({T->K, (int64_t)(((size_t)256 << 20) / T->inst_ws), 65535}));
+  T->off_u = align256((size_t)T->N * eb);
+  T->off_inst = T->off_u + align256((size_t)R * (size_t)T->N * eb);
+  T->off_stage = T->off_inst + (size_t)T->batch * T->inst_ws;
+  T->off_tab = T->off_stage + align256((size_t)T->K * (size_t)n * eb);
+  T->off_pairs = T->off_tab + align256((size_t)d * (size_t)T->K * sizeof(void *));
+  T->bytes = T->off_pairs + align256((size_t)T->pairs.size() * sizeof(int32_t));
+  return T->bytes <= ((size_t)8 << 30);
+}
+
+static Status tm_spectral_run(const TmSpectral &T, hk_dtype_t dt, const void *h, int m, int64_t n, int64_t R,
+                              const void *U, void *out, char *ws, hipStream_t st) {
+  const size_t eb = elem_bytes(dt);
+  const int64_t N = T.N, K = T.K;
+  const int d = m - 1;
+  char *hspec = ws, *uspec = ws + T.off_u, *inst = ws + T.off_inst, *stage = ws + T.off_stage;
+  const void **tab = (const void **)(ws + T.off_tab);
+  int32_t *dpairs = (int32_t *)(ws + T.off_pairs);
+  int64_t dims[HK_MAX_ORDER];
+  for (int q = 0; q < m; ++q) dims[q] = n;
+  // tables: operand t of tuple k -> spectrum of U[:, digit t-1 of k]
+  std::vector<const void *> htab((size_t)d * K);
+  for (int t = 0; t < d; ++t)
+    for (int64_t k = 0; k < K; ++k) htab[(size_t)t * K + k] = uspec + (size_t)T.digits[(size_t)k * d + t] * N * eb;
+  hipError_t e = hipMemcpyAsync(tab, htab.data(), htab.size() * sizeof(void *), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dpairs, T.pairs.data(), T.pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail(HK_ERR_HIP, std::string("tensor-matrix tables: ") + hipGetErrorString(e));
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  Strides str;
+  // h^
+  Status s = spectrum_prepare(dt, m, dims, -1, h, hspec, &sh, &P, &sc);
+  if (s.ok()) {
+    P.ws = inst;
+    memset(&str, 0, sizeof(str));
+    s = launch_shape(dt, sh, sc, P, str, 1, st);
+  }
+  // the spectra of the columns of U
+  if (s.ok()) s = spectrum_prepare(dt, m, dims, 1, U, uspec, &sh, &P, &sc);
+  if (s.ok()) {
+    str.op[0] = n * (int64_t)eb;
+    str.y = N * (int64_t)eb;
+    str.ws = (int64_t)T.inst_ws;
+    for (int64_t c0 = 0; c0 < R && s.ok(); c0 += T.batch) {
+      Ptrs Pc = P;
+      Pc.op[0] = (const char *)U + (size_t)c0 * n * eb;
+      Pc.y = uspec + (size_t)c0 * N * eb;
+      Pc.ws = inst;
+      s = launch_shape(dt, sh, sc, Pc, str, std::min(T.batch, R - c0), st);
+    }
+  }
+  // every tuple: h^ times the m - 1 spectra of its digits (not merged, so
+  // that all tuples share one shape), the output transform, to the staging
+  if (s.ok()) {
+    Problem q;
+    q.dt = dt;
+    q.prog = PROG_FWD;
+    q.m = m;
+    for (int t = 0; t < m; ++t) q.dims[t] = n;
+    q.h = hspec;
+    q.h_spec = true;
+    for (int t = 1; t < m; ++t) {
+      q.vec[t] = (const void *)(uintptr_t)(256 * t);  // distinct placeholders: one operand per mode
+      q.spec_mask |= 1u << t;
+    }
+    q.y = stage;
+    int op_src[MAXOPS];
+    s = build_shape(q, T.lay, T.sc, &sh, &P, op_src);
+    if (s.ok() && sh.nops != m) s = fail(HK_ERR_NOT_SUPPORTED, "tensor-matrix operand layout");
+    for (int64_t k0 = 0; k0 < K && s.ok(); k0 += T.batch) {
+      Ptrs Pk = P;
+      memset(&str, 0, sizeof(str));
+      for (int o = 1; o < sh.nops; ++o) {
+        Pk.op[o] = tab + (size_t)(op_src[o] - 1) * K + k0;
+        str.op[o] = OP_TABLE;
+      }
+      Pk.y = stage + (size_t)k0 * n * eb;
+      str.y = n * (int64_t)eb;
+      Pk.ws = inst;
+      str.ws = (int64_t)T.inst_ws;
+      s = launch_shape(dt, sh, T.sc, Pk, str, std::min(T.batch, K - k0), st);
+    }
+  }
+  if (s.ok()) {
+    count_launch();
+    const bool dbl = dt == HK_C128;
+    e = dbl ? launch_copy_cols_f64(out, stage, dpairs, T.ncols, n, true, st)
+            : launch_copy_cols_f32(out, stage, dpairs, T.ncols, n, true, st);
+    if (e != hipSuccess) s = fail(HK_ERR_HIP, std::string("tensor-matrix gather: ") + hipGetErrorString(e));
+  }
+  // the host copies of the tables must outlive the transfers enqueued above
+  e = hipStreamSynchronize(st);
+  if (s.ok() && e != hipSuccess) s = fail(HK_ERR_HIP, std::string("stream synchronize: ") + hipGetErrorString(e));
+  return s;
+}
+
+// The columns of T that are not nondecreasing tuples: copies of their
+// canonical column (the pair table goes to the workspace first).
+static Status tm_copy_pairs(hk_dtype_t dt, const TmLayout &L, int64_t n, void *out, char *dst, hipStream_t stream) {
+  int32_t *dpairs = (int32_t *)dst;
+  hipError_t e =
+      hipMemcpyAsync(dpairs, L.pairs.data(), L.pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+  const bool cplx = is_complex(dt);
+  const bool dbl = dt == HK_C128 || dt == HK_F64;
+  if (e == hipSuccess) {
+    count_launch();
+    e = dbl ? launch_copy_cols_f64(out, out, dpairs, (int64_t)(L.pairs.size() / 2), n, cplx, stream)
+            : launch_copy_cols_f32(out, out, dpairs, (int64_t)(L.pairs.size() / 2), n, cplx, stream);
+  }
+  if (e != hipSuccess) return fail(HK_ERR_HIP, std::string("symmetric completion: ") + hipGetErrorString(e));
+  return Status();
+}
+
 hk_status_t hankel_tensor_matrix_workspace_size(hk_dtype_t dt, int m, int64_t n, int64_t R, size_t *bytes) {
   if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
   TmLayout L;
   const void *dummy = (const void *)256;
   Status s = tm_layout(dt, dummy, m, n, R, dummy, (void *)256, &L);
   if (!s.ok()) return finish(s);
+  TmSpectral T;
+  if (tm_spectral_plan(dt, m, n, R, &T)) {
+    *bytes = T.bytes;
+    return finish(Status());
+  }
   hk_plan_t plan = nullptr;
   s = plan_create(&plan, dt, L.probs.data(), (int64_t)L.probs.size(), 0);
   if (!s.ok()) return finish(s);
@@ -720,6 +1123,19 @@ hk_status_t hankel_tensor_matrix(hk_dtype_t dt, const void *h, int m, int64_t n,
   TmLayout L;
   Status s = tm_layout(dt, h, m, n, R, U, out, &L);
   if (!s.ok()) return finish(s);
+  TmSpectral T;
+  if (tm_spectral_plan(dt, m, n, R, &T)) {
+    const size_t need = T.bytes;
+    if (!ws || ws_bytes < need)
+      return finish(fail(HK_ERR_WORKSPACE, "workspace smaller than hankel_tensor_matrix_workspace_size"));
+    if (((uintptr_t)ws) % 256 != 0) return finish(fail(HK_ERR_MISALIGNED, "workspace must be 256-byte aligned"));
+    const size_t a = elem_bytes(dt);
+    if (!aligned(h, a) || !aligned(U, a) || !aligned(out, a))
+      return finish(fail(HK_ERR_MISALIGNED, "pointer not aligned to the element size"));
+    s = ensure_device();
+    if (!s.ok()) return finish(s);
+    return finish(tm_spectral_run(T, dt, h, m, n, R, U, out, (char *)ws, stream));
+  }
   hk_plan_t plan = nullptr;
   s = plan_create(&plan, dt, L.probs.data(), (int64_t)L.probs.size(), 0);
   if (!s.ok()) return finish(s);
@@ -733,19 +1149,7 @@ hk_status_t hankel_tensor_matrix(hk_dtype_t dt, const void *h, int m, int64_t n,
   }
   plan_set_oneshot(plan);
   s = plan_execute(plan, ws, ws_bytes, stream);
-  if (s.ok() && !L.pairs.empty()) {
-    int32_t *dpairs = (int32_t *)((char *)ws + pairs_off);
-    hipError_t e = hipMemcpyAsync(dpairs, L.pairs.data(), L.pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                                  stream);
-    const bool cplx = is_complex(dt);
-    const bool dbl = dt == HK_C128 || dt == HK_F64;
-    if (e == hipSuccess) {
-      count_launch();
-      e = dbl ? launch_copy_cols_f64(out, dpairs, (int)(L.pairs.size() / 2), n, cplx, stream)
-              : launch_copy_cols_f32(out, dpairs, (int)(L.pairs.size() / 2), n, cplx, stream);
-    }
-    if (e != hipSuccess) s = fail(HK_ERR_HIP, std::string("symmetric completion: ") + hipGetErrorString(e));
-  }
+  if (s.ok() && !L.pairs.empty()) s = tm_copy_pairs(dt, L, n, out, (char *)ws + pairs_off, stream);
   // the host tables (plan and pairs) must outlive the copies enqueued above
   if (s.ok())
     s = plan_release_after(plan, stream);

@@ -324,7 +324,9 @@ struct RowBody {
     for (int s = 0; s < EE; ++s) idx[s] = t + s * TPS + (ODD > 1 ? (int64_t)L * tau[s] : 0);
   }
 
-  // Power-of-two rows (ODD == 1): one sequence per row.
+  // Power-of-two rows (ODD == 1): one sequence per row.  SPEC: the row
+  // kernel variant for shapes with stored spectra (OPF_SPEC operands).
+  template <bool SPEC = false>
   static __device__ __forceinline__ void load(cx<T> (&a)[EE], const Shape &sh, const PV &P, int o,
                                               int64_t row, bool valid_row, int t, bool resident) {
     const OpDesc &od = sh.ops[o];
@@ -341,17 +343,44 @@ struct RowBody {
       gather<T, EE>(a, P.op(o), idx, ok, od.flags);
     } else {
       // row `row` of the operand's column transform; its columns past
-      // ncol_nz were never written and read as zero
+      // ncol_nz were never written and read as zero.  A stored spectrum
+      // (OPF_SPEC) is read whole from the operand pointer.
       const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
-      const auto r = make_buf(ws_buf<T>(sh, P, od.buf), N * (int64_t)sizeof(cx<T>));
       const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
+      if constexpr (SPEC) {
+        const bool spec = (od.flags & OPF_SPEC) != 0;
+        const void *src = (const void *)ws_buf<T>(sh, P, od.buf);
+        if (spec) src = (P.st && P.st->op[o] == OP_TABLE) ? ((const void *const *)P.b->op[o])[P.i] : P.op(o);
+        const auto r = make_buf(src, N * (int64_t)sizeof(cx<T>));
+        const int64_t ncol = spec ? (int64_t)L : od.ncol_nz;
 #pragma unroll
-      for (int s = 0; s < EE; ++s) {
-        const int i = t + s * TPS;
-        off[s] = (valid_row && i < od.ncol_nz) ? rbase + (uint32_t)(i * (int)sizeof(cx<T>)) : OOB_OFF;
+        for (int s = 0; s < EE; ++s) {
+          const int i = t + s * TPS;
+          off[s] = (valid_row && i < ncol) ? rbase + (uint32_t)(i * (int)sizeof(cx<T>)) : OOB_OFF;
+        }
+        bgather<T, EE>(a, r, off, 0);
+      } else {
+        const auto r = make_buf(ws_buf<T>(sh, P, od.buf), N * (int64_t)sizeof(cx<T>));
+#pragma unroll
+        for (int s = 0; s < EE; ++s) {
+          const int i = t + s * TPS;
+          off[s] = (valid_row && i < od.ncol_nz) ? rbase + (uint32_t)(i * (int)sizeof(cx<T>)) : OOB_OFF;
+        }
+        bgather<T, EE>(a, r, off, 0);
       }
-      bgather<T, EE>(a, r, off, 0);
     }
+  }
+
+  // Spectrum row `row` (natural order within the row) to y: element k_c of
+  // row k_r is bin k_r + C k_c of the length-N transform.
+  static __device__ __forceinline__ void store_spec(const cx<T> (&a)[EE], const Shape &sh, const PV &P, int64_t row,
+                                                    bool valid_row, int t) {
+    if (!valid_row) return;
+    const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+    const auto r = make_buf(P.y(), N * (int64_t)sizeof(cx<T>));
+    const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
+#pragma unroll
+    for (int s = 0; s < EE; ++s) BufIO<T>::st(a[s], r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
   }
 
   // Stores output `which` (0: y / grad_h, 1: grad_x) of this row.
@@ -451,6 +480,9 @@ struct RowBody {
   // first operand of the next row is already loading, so the memory traffic
   // of one row overlaps the arithmetic of the previous one.  Returns the lane's
   // share of the scalar product over its rows.
+  // SPEC: operands may be stored spectra (OPF_SPEC: no twiddle, transform or
+  // conjugation) and the spectrum of an operand may be stored (OPF_STORE_SPEC).
+  template <bool SPEC = false>
   static __device__ __forceinline__ cx<T> run_fwd_rows(const Shape &sh, const PV &P, int64_t row0, int rstride,
                                                        int K, int t, cx<T> *lds, const cx<T> *tw24,
                                                        const cx<T> *tw4096) {
@@ -463,7 +495,7 @@ struct RowBody {
     cx<T> part = czero<T>();
     int64_t row = row0;
     bool valid = row < C;
-    load(a, sh, P, 0, row, valid, t, false);
+    load<SPEC>(a, sh, P, 0, row, valid, t, false);
     StageTw<T, L, E> stw;
     stw.init(t, tw4096);
     for (int it = 0; it < K; ++it) {
@@ -474,12 +506,39 @@ struct RowBody {
       for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
       for (int o = 0; o < sh.nops; ++o) {
         if (o + 1 < sh.nops)
-          load(nx, sh, P, o + 1, row, valid, t, false);
+          load<SPEC>(nx, sh, P, o + 1, row, valid, t, false);
         else if (it + 1 < K)
-          load(nx, sh, P, 0, nrow, nvalid, t, false);
+          load<SPEC>(nx, sh, P, 0, nrow, nvalid, t, false);
+        const OpDesc &od = sh.ops[o];
+        if constexpr (SPEC) {
+          const bool spec = (od.flags & OPF_SPEC) != 0;
+          if (!spec) {
+            twiddle_in(a, w, tw_on);
+            fft(a, t, lds, stw);
+          }
+          if (od.role == ROLE_H) {
+            if (spec) {
+#pragma unroll
+              for (int s = 0; s < EE; ++s) acc[s] = a[s];
+            } else {
+#pragma unroll
+              for (int s = 0; s < EE; ++s) acc[s] = cscale(cconj(a[s]), invN);
+            }
+            if (od.flags & OPF_STORE_SPEC) store_spec(acc, sh, P, row, valid, t);
+          } else {
+            if (od.flags & OPF_STORE_SPEC) store_spec(a, sh, P, row, valid, t);
+            for (int e = 0; e < od.exp; ++e) {
+#pragma unroll
+              for (int s = 0; s < EE; ++s) acc[s] = cmul(acc[s], a[s]);
+            }
+            if (od.flags & OPF_ALPHA) {
+#pragma unroll
+              for (int s = 0; s < EE; ++s) part = cfma(acc[s], a[s], part);
+            }
+          }
+        } else {
         twiddle_in(a, w, tw_on);
         fft(a, t, lds, stw);
-        const OpDesc &od = sh.ops[o];
         if (od.role == ROLE_H) {
 #pragma unroll
           for (int s = 0; s < EE; ++s) acc[s] = cscale(cconj(a[s]), invN);
@@ -492,6 +551,7 @@ struct RowBody {
 #pragma unroll
             for (int s = 0; s < EE; ++s) part = cfma(acc[s], a[s], part);
           }
+        }
         }
 #pragma unroll
         for (int s = 0; s < EE; ++s) a[s] = nx[s];

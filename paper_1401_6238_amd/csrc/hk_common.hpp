@@ -36,9 +36,16 @@ enum OpFlag : int32_t {
   OPF_CONJ = 1,   // load conj(x)
   OPF_REAL = 2,   // source array is real
   OPF_ALPHA = 4,  // spectrum multiplies into the scalar product (x_1)
+  // Multipass, power-of-two 1D rows only:
+  OPF_SPEC = 8,         // the operand pointer holds the operand's spectrum in row order
+                        // (no column pass; the row pass loads it as transformed)
+  OPF_STORE_SPEC = 16,  // the row pass stores this operand's spectrum, in row order, to y
 };
 
 enum Prog : int32_t { PROG_FWD = 0, PROG_BWD = 1 };
+// Row-kernel variant (never a Shape's prog): the forward program built with
+// stored-spectrum operands (OPF_SPEC, OPF_STORE_SPEC) enabled.
+enum : int32_t { PROG_FWD_SPEC = 2 };
 
 enum ColKind : int32_t { COL_A = 0, COL_D = 1 };
 
@@ -80,6 +87,13 @@ struct Shape {
   OpDesc ops[MAXOPS];
 };
 
+// True when a shape's row pass needs the PROG_FWD_SPEC kernels.
+inline bool shape_has_spec(const Shape &sh) {
+  for (int o = 0; o < sh.nops; ++o)
+    if (sh.ops[o].flags & (OPF_SPEC | OPF_STORE_SPEC)) return true;
+  return false;
+}
+
 struct Ptrs {
   const void *op[MAXOPS];
   void *y;           // forward vector output / adjoint grad_h
@@ -90,6 +104,10 @@ struct Ptrs {
 };
 
 // Byte strides between consecutive instances of a strided batch (0 = shared).
+// op[o] == OP_TABLE: the base pointer of operand o is a device array of
+// per-instance pointers (stored-spectrum operands of the PROG_FWD_SPEC row
+// kernels only).
+constexpr int64_t OP_TABLE = INT64_MIN;
 struct Strides {
   int64_t op[MAXOPS];
   int64_t y, alpha, out1, phi, ws;

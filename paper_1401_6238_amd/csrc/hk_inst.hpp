@@ -21,8 +21,13 @@ constexpr int row_maxt(int E) { return E == 4 ? ROW_MAXT_E4 : ROW_MAXT; }
 
 template <int L, int E>
 static void *row_fn(int prog) {
-  return prog == PROG_BWD ? (void *)&k_rows<L, E, row_maxt(E), PROG_BWD>
-                          : (void *)&k_rows<L, E, row_maxt(E), PROG_FWD>;
+  if (prog == PROG_BWD) return (void *)&k_rows<L, E, row_maxt(E), PROG_BWD>;
+  if (prog == PROG_FWD_SPEC) {
+    // spectra exist for the three-pass layouts only, whose rows have >= 2^7 points
+    if constexpr (L >= 128) return (void *)&k_rows<L, E, row_maxt(E), PROG_FWD_SPEC>;
+    return nullptr;
+  }
+  return (void *)&k_rows<L, E, row_maxt(E), PROG_FWD>;
 }
 template <int L, int E>
 static void *col_fn(int var) {
@@ -197,7 +202,8 @@ bool HK_CAT(limits_, HK_SUFFIX)(int logL, int E, KernelLimits *out) {
 hipError_t HK_CAT(launch_rows_, HK_SUFFIX)(int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh,
                                            const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st) {
   using namespace HK_NS;
-  void *fn = row_kernel(logL, E, sh.prog);
+  const int prog = (sh.prog == PROG_FWD && !sh.resident && shape_has_spec(sh)) ? (int)PROG_FWD_SPEC : sh.prog;
+  void *fn = row_kernel(logL, E, prog);
   KernelLimits k;
   if (!fn || !HK_CAT(limits_, HK_SUFFIX)(logL, E, &k)) return hipErrorInvalidValue;
   const int threads = rows_per_wg * k.tps;
@@ -334,21 +340,29 @@ hipError_t HK_CAT(launch_batch_, HK_SUFFIX)(const BatchArgs &args, int grid, hip
   return launch_kernel((void *)&k_batch, dim3((unsigned)grid), dim3(blk), kargs, lds, st);
 }
 
-hipError_t HK_CAT(launch_copy_cols_, HK_SUFFIX)(void *out, const int32_t *pairs, int npairs, int64_t rows,
-                                                bool complex_elems, hipStream_t st) {
+hipError_t HK_CAT(launch_copy_cols_, HK_SUFFIX)(void *out, const void *src, const int32_t *pairs, int64_t npairs,
+                                                int64_t rows, bool complex_elems, hipStream_t st) {
   using namespace HK_NS;
-  if (npairs <= 0) return hipSuccess;
-  if (npairs > 65535) return hipErrorInvalidValue;
   const unsigned gx = (unsigned)std::min<int64_t>(64, (rows + 255) / 256);
   int64_t r = rows;
-  if (complex_elems) {
-    cx<T> *o = (cx<T> *)out;
-    void *args[] = {&o, &pairs, &r};
-    return launch_kernel((void *)&k_copy_cols<cx<T>>, dim3(gx, (unsigned)npairs), dim3(256), args, 0, st);
+  for (int64_t p0 = 0; p0 < npairs; p0 += 65535) {
+    const unsigned gy = (unsigned)std::min<int64_t>(65535, npairs - p0);
+    const int32_t *pp = pairs + 2 * p0;
+    hipError_t e;
+    if (complex_elems) {
+      cx<T> *o = (cx<T> *)out;
+      const cx<T> *s = (const cx<T> *)src;
+      void *args[] = {&o, &s, &pp, &r};
+      e = launch_kernel((void *)&k_copy_cols<cx<T>>, dim3(gx, gy), dim3(256), args, 0, st);
+    } else {
+      T *o = (T *)out;
+      const T *s = (const T *)src;
+      void *args[] = {&o, &s, &pp, &r};
+      e = launch_kernel((void *)&k_copy_cols<T>, dim3(gx, gy), dim3(256), args, 0, st);
+    }
+    if (e != hipSuccess) return e;
   }
-  T *o = (T *)out;
-  void *args[] = {&o, &pairs, &r};
-  return launch_kernel((void *)&k_copy_cols<T>, dim3(gx, (unsigned)npairs), dim3(256), args, 0, st);
+  return hipSuccess;
 }
 
 }  // namespace hk

@@ -65,7 +65,8 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
       }
       return;
     }
-    const cx<T> part = RB::run_fwd_rows(sh, P, row0, rows, K, t, lds, g_tw24, g_tw4096);
+    const cx<T> part =
+        RB::template run_fwd_rows<PROG == PROG_FWD_SPEC>(sh, P, row0, rows, K, t, lds, g_tw24, g_tw4096);
     if (sh.want_alpha) {
       // One partial sum per workgroup; the next kernel in the stream (pass D
       // or the reduction kernel) adds them in index order.  No cross-workgroup
@@ -461,13 +462,14 @@ __global__ void __launch_bounds__(BATCH_BLK) k_group_r2c_pairs(BatchArgs A) {
   }
 }
 
-// out[:, pairs[2k]] = out[:, pairs[2k + 1]] for column-major columns of
-// `rows` elements of type V (symmetric completion of tensor-matrix products).
+// out[:, pairs[2k]] = src[:, pairs[2k + 1]] for column-major columns of
+// `rows` elements of type V (tensor-matrix products: the symmetric
+// completion, src = out, and the gather from the spectral path's staging).
 template <typename V>
-__global__ void __launch_bounds__(256) k_copy_cols(V *out, const int32_t *pairs, int64_t rows) {
-  const int64_t dst = pairs[2 * blockIdx.y], src = pairs[2 * blockIdx.y + 1];
+__global__ void __launch_bounds__(256) k_copy_cols(V *out, const V *src, const int32_t *pairs, int64_t rows) {
+  const int64_t d = pairs[2 * blockIdx.y], s = pairs[2 * blockIdx.y + 1];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x)
-    out[dst * rows + i] = out[src * rows + i];
+    out[d * rows + i] = src[s * rows + i];
 }
 
 #ifndef HK_ROWS_ONLY

@@ -33,8 +33,9 @@ hipError_t launch_kernel(const void *fn, dim3 grid, dim3 block, void **args, siz
                                   const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st);   \
   hipError_t launch_batch_##SUFFIX(const BatchArgs &args, int grid, hipStream_t st);                  \
   hipError_t batch_resident_##SUFFIX(int *blocks_per_cu);                                           \
-  hipError_t launch_copy_cols_##SUFFIX(void *out, const int32_t *pairs, int npairs, int64_t rows,     \
-                                       bool complex_elems, hipStream_t st);                          \
+  hipError_t launch_copy_cols_##SUFFIX(void *out, const void *src, const int32_t *pairs,            \
+                                       int64_t npairs, int64_t rows, bool complex_elems,             \
+                                       hipStream_t st);                                              \
   hipError_t launch_alpha_##SUFFIX(const Shape &sh, const Ptrs &p0, const Strides &str, int64_t npart,       \
                                    int64_t count, hipStream_t st);                                     \
   void batch_geometry_##SUFFIX(int *blk, int *e_row, int *e_col, size_t *lds_bytes);                 \

@@ -288,40 +288,43 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
   if (p.prog == PROG_FWD) {
     sh.want_y = p.y ? 1 : 0;
     sh.want_alpha = p.alpha ? 1 : 0;
-    add_op(ROLE_H, 1, OPF_CONJ | real_flag, p.is_block ? hrows : hrows, p.is_block ? hcols : 1, p.h, -1);
-    // Group identical vectors of modes 2..m (same pointer and shape).
+    add_op(ROLE_H, 1, p.h_spec ? OPF_SPEC : (OPF_CONJ | real_flag), p.is_block ? hrows : hrows,
+           p.is_block ? hcols : 1, p.h, -1);
+    // Group identical vectors of modes 2..m (same pointer, shape and kind).
     struct G {
       const void *ptr;
       int64_t n, nb;
       int exp;
       int src;
+      bool spec;
     };
+    auto is_spec = [&](int q) { return ((p.spec_mask >> q) & 1u) != 0; };
     std::vector<G> groups;
     for (int q = 1; q < p.m; ++q) {
       bool found = false;
       for (auto &g : groups)
-        if (g.ptr == p.vec[q] && g.n == p.dims[q] && g.nb == (p.is_block ? p.bdims[q] : 1)) {
+        if (g.ptr == p.vec[q] && g.n == p.dims[q] && g.nb == (p.is_block ? p.bdims[q] : 1) && g.spec == is_spec(q)) {
           g.exp++;
           found = true;
           break;
         }
-      if (!found) groups.push_back({p.vec[q], p.dims[q], p.is_block ? p.bdims[q] : 1, 1, q});
+      if (!found) groups.push_back({p.vec[q], p.dims[q], p.is_block ? p.bdims[q] : 1, 1, q, is_spec(q)});
     }
     int alpha_group = -1;
     if (p.alpha) {
       for (size_t i = 0; i < groups.size(); ++i)
         if (groups[i].ptr == p.vec[0] && groups[i].n == p.dims[0] &&
-            groups[i].nb == (p.is_block ? p.bdims[0] : 1))
+            groups[i].nb == (p.is_block ? p.bdims[0] : 1) && groups[i].spec == is_spec(0))
           alpha_group = (int)i;
       if (alpha_group < 0) {
-        groups.push_back({p.vec[0], p.dims[0], p.is_block ? p.bdims[0] : 1, 0, 0});
+        groups.push_back({p.vec[0], p.dims[0], p.is_block ? p.bdims[0] : 1, 0, 0, is_spec(0)});
         alpha_group = (int)groups.size() - 1;
       }
       std::swap(groups[alpha_group], groups.back());  // scalar operand is processed last
       alpha_group = (int)groups.size() - 1;
     }
     for (size_t i = 0; i < groups.size(); ++i) {
-      const int flags = real_flag | ((int)i == alpha_group ? OPF_ALPHA : 0);
+      const int flags = real_flag | ((int)i == alpha_group ? OPF_ALPHA : 0) | (groups[i].spec ? OPF_SPEC : 0);
       add_op(ROLE_X, groups[i].exp, flags, groups[i].n, groups[i].nb, groups[i].ptr, groups[i].src);
     }
     sh.out_rows = p.dims[0];
@@ -349,6 +352,17 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
     sh.rows_per_wg = sc.rows_per_wg;
     sh.row_iters = sc.iters;
     sh.nbuf = sh.nops;
+    if (p.h_spec || p.spec_mask) {
+      // Spectrum operands need no buffer: the others take buffers 0, 1, ...;
+      // the output row goes to buffer 0 (operand 0's), in place of a row the
+      // row pass has already read, or to a buffer of its own.
+      int nb = 0;
+      for (int o = 0; o < sh.nops; ++o)
+        if (!(sh.ops[o].flags & OPF_SPEC)) sh.ops[o].buf = nb++;
+      for (int o = 0; o < sh.nops; ++o)
+        if (sh.ops[o].flags & OPF_SPEC) sh.ops[o].buf = 0;
+      sh.nbuf = std::max(1, nb);
+    }
     sh.partials = (int64_t)1 << MAX_LOGL;
     const size_t eb = cplx_bytes(p.dt);
     const size_t bytes =
@@ -544,23 +558,28 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
   }
   const int64_t R = (int64_t)1 << sh.logR;
   const int64_t C = (int64_t)1 << sh.logC;
-  // Pass A: column transforms of every operand.
+  // Pass A: column transforms of every operand not given as a spectrum.
   ColJob ja[MAXOPS];
   memset(ja, 0, sizeof(ja));
   int64_t max_cols = 0;
+  int na = 0;
   for (int o = 0; o < sh.nops; ++o) {
-    ja[o].kind = COL_A;
-    ja[o].op = o;
-    ja[o].buf = sh.ops[o].buf;
-    ja[o].conj_out = 0;
-    ja[o].ncols = sh.ops[o].ncol_nz;
-    max_cols = std::max(max_cols, ja[o].ncols);
+    if (sh.ops[o].flags & OPF_SPEC) continue;
+    ja[na].kind = COL_A;
+    ja[na].op = o;
+    ja[na].buf = sh.ops[o].buf;
+    ja[na].conj_out = 0;
+    ja[na].ncols = sh.ops[o].ncol_nz;
+    max_cols = std::max(max_cols, ja[na].ncols);
+    ++na;
   }
-  // tiles over the storage columns of every sequence (virtual columns)
-  const int64_t vcols_a = sh.odd > 1 ? sh.odd * R : max_cols;
-  dim3 ga((unsigned)((vcols_a + sc.tw - 1) / sc.tw), (unsigned)sh.nops, (unsigned)count);
-  e = cols(dt, sh.logC, sc.E_col, sc.tw, sc.xcd, ga, sh, p0, str, ja, sh.nops, st);
-  if (e != hipSuccess) return hip_fail(e, "pass A launch");
+  if (na > 0) {
+    // tiles over the storage columns of every sequence (virtual columns)
+    const int64_t vcols_a = sh.odd > 1 ? sh.odd * R : max_cols;
+    dim3 ga((unsigned)((vcols_a + sc.tw - 1) / sc.tw), (unsigned)na, (unsigned)count);
+    e = cols(dt, sh.logC, sc.E_col, sc.tw, sc.xcd, ga, sh, p0, str, ja, na, st);
+    if (e != hipSuccess) return hip_fail(e, "pass A launch");
+  }
   // Pass B: row transforms, spectral product, row transform of the output
   // (real inputs: C / 2 mirrored row pairs).
   const int64_t rows_wg = (int64_t)sc.rows_per_wg * sc.iters;  // rows (pairs) per workgroup

@@ -36,6 +36,10 @@ struct Problem {
   int64_t bdims[HK_MAX_ORDER] = {0};
   const void *h = nullptr;
   const void *vec[HK_MAX_ORDER] = {nullptr};  // forward: vec[0] only for alpha
+  // forward, multipass power-of-two 1D layouts: h / vec[q] (bit q) point to
+  // spectra in row order instead of the vectors themselves
+  bool h_spec = false;
+  uint32_t spec_mask = 0;
   void *y = nullptr;
   void *alpha = nullptr;
   // adjoint (equal vectors): vec[1] = x

@@ -255,3 +255,45 @@ def test_length_policies(L):
     assert fft_layout(L, 190)[0] == 192
     assert L.hk_set_fft_lengths(7) == INVALID
     assert L.hk_set_fft_lengths(0) == OK and L.hk_get_fft_lengths() == 0
+
+
+def test_spectral_layout_and_errors(L):
+    """The spectral entry points check their arguments on the host."""
+    def lay(dt, m, dims):
+        n_fft, row = ctypes.c_int64(0), ctypes.c_int64(0)
+        d = (ctypes.c_int64 * m)(*dims)
+        rc = L.hankel_spectrum_layout(dt, m, d, ctypes.byref(n_fft), ctypes.byref(row))
+        return rc, n_fft.value, row.value
+    # d_H = 4*(2^18 - 1) + 1 -> N = 2^20, rows of 2^10; d_H = 8998 -> 2^14, rows of 2^7
+    assert lay(HK_C64, 4, [1 << 18] * 4) == (OK, 1 << 20, 1 << 10)
+    assert lay(HK_C128, 3, [3000] * 3) == (OK, 1 << 14, 1 << 7)
+    assert lay(HK_C64, 4, [8192] * 4) == (OK, 1 << 15, 1 << 8)
+    assert lay(HK_C64, 3, [30] * 3)[0] == NOTSUP      # resident size
+    assert lay(HK_F32, 3, [3000] * 3)[0] == NOTSUP    # real dtype
+    assert lay(HK_C64, 1, [3000])[0] == INVALID
+    assert lay(HK_C64, 3, [3000, 0, 5])[0] == INVALID
+    d = (ctypes.c_int64 * 3)(3000, 3000, 3000)
+    b = ctypes.c_size_t(0)
+    assert L.hankel_spectrum_workspace_size(HK_C64, 3, d, 3, ctypes.byref(b)) == INVALID
+    assert L.hankel_spectrum_workspace_size(HK_C64, 3, d, -2, ctypes.byref(b)) == INVALID
+    assert L.hankel_spectrum_workspace_size(HK_C64, 3, d, -1, ctypes.byref(b)) == OK
+    assert b.value >= (1 << 14) * 8
+    assert L.hankel_spectrum(HK_C64, 3, d, -1, None, ctypes.c_void_p(256), ctypes.c_void_p(256), b.value,
+                             None) == NULLP
+    assert L.hankel_spectrum(HK_C64, 3, d, -1, ctypes.c_void_p(260), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                             b.value, None) == MISALIGNED
+    # products: h spectrum missing, a vector missing, too small a workspace
+    v = (ctypes.c_void_p * 3)(256, 512, 768)
+    assert L.hankel_mode_products_spectral_workspace_size(HK_C64, 3, d, v, None, 1, 0, ctypes.byref(b)) == OK
+    need = b.value
+    assert L.hankel_mode_products_spectral(HK_C64, None, 3, d, v, None, ctypes.c_void_p(256), None,
+                                           ctypes.c_void_p(256), need, None) == NULLP
+    v0 = (ctypes.c_void_p * 3)(256, None, 768)
+    assert L.hankel_mode_products_spectral(HK_C64, ctypes.c_void_p(256), 3, d, v0, None, ctypes.c_void_p(256), None,
+                                           ctypes.c_void_p(256), need, None) == NULLP
+    assert L.hankel_mode_products_spectral(HK_C64, ctypes.c_void_p(256), 3, d, v, None, ctypes.c_void_p(256), None,
+                                           ctypes.c_void_p(256), need - 1, None) == WORKSPACE
+    # every operand a spectrum: one output buffer and the partial sums only
+    s = (ctypes.c_void_p * 3)(1024, 1280, 1536)
+    assert L.hankel_mode_products_spectral_workspace_size(HK_C64, 3, d, None, s, 1, 1, ctypes.byref(b)) == OK
+    assert b.value < need

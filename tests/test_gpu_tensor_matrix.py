@@ -35,3 +35,35 @@ def test_tensor_matrix(m, n, R, dtype):
     if m >= 3 and R >= 2:
         t = host(T)
         assert np.array_equal(t[:, 0, 1], t[:, 1, 0]) if m == 3 else True
+
+
+@pytest.mark.parametrize("m,n,R,dtype", [
+    (3, 4096, 16, torch.complex64), (3, 4096, 16, torch.complex128), (2, 32768, 32, torch.complex64),
+    (4, 2048, 11, torch.complex64),
+])
+def test_tensor_matrix_spectral(m, n, R, dtype):
+    """Shapes past the spectral threshold (tuples x transform length >= 2^21):
+    h^ and the spectra of the columns of U are made once, every nondecreasing
+    tuple is one product of spectra, and a gather fills all columns.  Sampled
+    rows of every canonical column against the oracle's direct sums; every
+    other column a bit-exact copy of its canonical column."""
+    import itertools
+
+    import paper_1401_6238_amd as hk
+    print_case(test="tensor_matrix_spectral", m=m, n=n, R=R, dtype=dtype)
+    g = np.random.Generator(np.random.PCG64(950 + 10 * m + R))
+    h = g.normal(size=m * (n - 1) + 1) + 1j * g.normal(size=m * (n - 1) + 1)
+    U = (g.normal(size=(n, R)) + 1j * g.normal(size=(n, R))) / np.sqrt(n)
+    T = hk.hankel_tensor_matrix(to_dev(h, dtype), to_dev(U.reshape(-1), dtype).reshape(n, R), m)
+    torch.cuda.synchronize()
+    # the spectral path: two spectrum programs, one product program, the gather
+    assert hk.hk_last_launch_count() == 7
+    t = host(T)
+    hs, Us = seen(h, dtype), seen(U.reshape(-1), dtype).reshape(n, R)
+    idx = np.unique(np.concatenate([np.arange(8), np.arange(n - 8, n), g.integers(0, n, 48)]))
+    for tup in itertools.combinations_with_replacement(range(R), m - 1):
+        col = t[(slice(None),) + tup]
+        ref, _ = oracle.tvp_sampled(m, [n] * m, hs, [None] + [Us[:, j] for j in tup], idx)
+        assert rel(col[idx], ref) <= TOL[dtype], tup
+    for tup in itertools.product(range(R), repeat=m - 1):
+        assert np.array_equal(t[(slice(None),) + tup], t[(slice(None),) + tuple(sorted(tup))])
