@@ -121,7 +121,8 @@ hk_status_t hankel_mode_products(hk_dtype_t dt, const void *h, int m, const int6
  * HK_C128) and d_H = sum(dims) - m + 1 above 4096; other shapes return
  * HK_ERR_NOT_SUPPORTED.
  *
- * Layout: N is the power of two >= d_H; R = 2^ceil(log2(N) / 2) and C = N / R.
+ * Layout: N is the power of two >= d_H; R = 2^(ceil(log2(N) / 2) + 1) for
+ * N >= 2^16 (at most 2^12), else R = 2^ceil(log2(N) / 2); C = N / R.
  * A spectrum is N elements of the dtype; element r R + c (r < C, c < R) holds
  * bin r + C c.  The layout depends only on dt and d_H, so spectra of separate
  * calls combine whenever their shapes have the same d_H.

@@ -344,9 +344,11 @@ hk_status_t hankel_mode_products(hk_dtype_t dt, const void *h, int m, const int6
 // h^ = ifft(pad_N h) and x^_p = fft(pad_N x_p) on one transform length N
 // (Section 3, the procedures for the mode products and the scalar).  A
 // spectrum computed once serves every product that shares the operand.
-// Spectra use the power-of-two three-pass layout with the balanced split
-// (row length R = 2^ceil(log2(N) / 2), C = N / R rows), so that spectra made by
-// separate calls combine; element r R + c holds bin r + C c.
+// Spectra use the power-of-two three-pass layout with a fixed split (row
+// length R = 2^(ceil(log2(N) / 2) + 1) from N = 2^16 on, the split the tuned
+// schedules of large transforms use, else 2^ceil(log2(N) / 2); C = N / R
+// rows), so that spectra made by separate calls combine; element r R + c
+// holds bin r + C c.
 // ---------------------------------------------------------------------------
 static Status spectral_problem(hk_dtype_t dt, int m, const int64_t *dims, Problem *out) {
   if (dt != HK_C64 && dt != HK_C128) return fail(HK_ERR_NOT_SUPPORTED, "spectra are implemented for complex dtypes");
@@ -366,17 +368,24 @@ static Status spectral_problem(hk_dtype_t dt, int m, const int64_t *dims, Proble
 }
 
 static Status spectral_setup(const Problem &p, Layout *lay, Sched *sc) {
-  Status s = layout_for(p, 0, lay, /*allow_odd=*/false, 1);
+  int64_t dh = 1 - p.m;
+  for (int q = 0; q < p.m; ++q) dh += p.dims[q];
+  int logN = 0;
+  while (((int64_t)1 << logN) < dh) ++logN;
+  const int split = logN >= 16 ? 1 : 0;
+  Status s = layout_for(p, split, lay, /*allow_odd=*/false, 1);
   if (!s.ok()) return s;
   if (lay->resident || lay->odd != 1 || lay->r2c)
     return fail(HK_ERR_NOT_SUPPORTED, "spectra need the three-pass layout: d_H above 4096");
   Sched sch;
   const int logM = lay->logR + lay->logC;
-  if (sched_lookup(p.dt, PROG_FWD, 0, lay->lclass(), logM, -1, 1, &sch) && sch.split == 0 &&
+  if (sched_lookup(p.dt, PROG_FWD, 0, lay->lclass(), logM, -1, 1, &sch) && sch.split == split &&
       sched_valid(p.dt, *lay, sch))
     *sc = sch;
-  else
+  else {
     *sc = default_sched(p.dt, *lay, PROG_FWD, 1);
+    sc->split = split;
+  }
   if (!sched_valid(p.dt, *lay, *sc)) return fail(HK_ERR_NOT_SUPPORTED, "no valid schedule for this shape");
   return Status();
 }

@@ -264,8 +264,10 @@ def test_spectral_layout_and_errors(L):
         d = (ctypes.c_int64 * m)(*dims)
         rc = L.hankel_spectrum_layout(dt, m, d, ctypes.byref(n_fft), ctypes.byref(row))
         return rc, n_fft.value, row.value
-    # d_H = 4*(2^18 - 1) + 1 -> N = 2^20, rows of 2^10; d_H = 8998 -> 2^14, rows of 2^7
-    assert lay(HK_C64, 4, [1 << 18] * 4) == (OK, 1 << 20, 1 << 10)
+    # rows of 2^(ceil(log2 N / 2) + 1) from N = 2^16 on (at most 2^12), else 2^ceil(log2 N / 2)
+    assert lay(HK_C64, 4, [1 << 18] * 4) == (OK, 1 << 20, 1 << 11)
+    assert lay(HK_C64, 2, [1 << 23] * 2) == (OK, 1 << 24, 1 << 12)
+    assert lay(HK_C64, 3, [1 << 15] * 3) == (OK, 1 << 17, 1 << 10)
     assert lay(HK_C128, 3, [3000] * 3) == (OK, 1 << 14, 1 << 7)
     assert lay(HK_C64, 4, [8192] * 4) == (OK, 1 << 15, 1 << 8)
     assert lay(HK_C64, 3, [30] * 3)[0] == NOTSUP      # resident size
