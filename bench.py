@@ -522,7 +522,8 @@ def main():
 def time_region(torch, fn, reps, warm=2, warm_ms=50.0, min_ms=20.0):
     """Mean milliseconds per call of fn.  Warm-up: at least `warm` calls and
     about `warm_ms` of work (the GPU clock ramps up over the first ~10 ms after
-    idle); the timed window holds at least `reps` calls and about `min_ms`."""
+    idle); three timed windows of at least `reps` calls and about `min_ms`
+    each, the median reported."""
     t0 = time.perf_counter()
     for _ in range(warm):
         fn()
@@ -535,13 +536,16 @@ def time_region(torch, fn, reps, warm=2, warm_ms=50.0, min_ms=20.0):
         torch.cuda.synchronize()
     reps = max(reps, min(10000, int(min_ms / max(per, 1e-3)) + 1))
     s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s)
-    for _ in range(reps):
-        fn()
-    e1.record(s)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
+    ts = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / reps)
+    return sorted(ts)[1]
 
 
 def cpu_fft_method(h, x, m, reps=3):
