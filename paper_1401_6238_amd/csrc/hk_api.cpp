@@ -908,7 +908,6 @@ static Status tm_layout(hk_dtype_t dt, const void *h, int m, int64_t n, int64_t 
       L->pairs.push_back((int32_t)c);
       L->pairs.push_back((int32_t)canon_of[c]);
     }
-  if (L->pairs.size() / 2 > 65535) return fail(HK_ERR_SIZE_LIMIT, "too many symmetric columns");
   return Status();
 }
 

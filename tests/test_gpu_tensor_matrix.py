@@ -67,3 +67,26 @@ def test_tensor_matrix_spectral(m, n, R, dtype):
         assert rel(col[idx], ref) <= TOL[dtype], tup
     for tup in itertools.product(range(R), repeat=m - 1):
         assert np.array_equal(t[(slice(None),) + tup], t[(slice(None),) + tuple(sorted(tup))])
+
+
+def test_tensor_matrix_spectral_many_columns():
+    """R^(m-1) = 65536 columns and 32896 tuples (m = 3, R = 256): the product
+    launches and the gather run in several chunks.  Sampled tuples against the
+    oracle; sampled columns bit-exact copies of their canonical columns."""
+    import paper_1401_6238_amd as hk
+    m, n, R, dtype = 3, 3000, 256, torch.complex64
+    print_case(test="tensor_matrix_many_columns", m=m, n=n, R=R)
+    g = np.random.Generator(np.random.PCG64(977))
+    h = g.normal(size=m * (n - 1) + 1) + 1j * g.normal(size=m * (n - 1) + 1)
+    U = (g.normal(size=(n, R)) + 1j * g.normal(size=(n, R))) / np.sqrt(n)
+    T = hk.hankel_tensor_matrix(to_dev(h, dtype), to_dev(U.reshape(-1), dtype).reshape(n, R), m)
+    torch.cuda.synchronize()
+    assert hk.hk_last_launch_count() > 7
+    hs, Us = seen(h, dtype), seen(U.reshape(-1), dtype).reshape(n, R)
+    idx = np.unique(np.concatenate([np.arange(8), np.arange(n - 8, n), g.integers(0, n, 32)]))
+    pairs = [(0, 0), (0, 255), (255, 255), (17, 200), (128, 129)] + [tuple(sorted(g.integers(0, R, 2))) for _ in range(10)]
+    for a, b in pairs:
+        col = host(T[:, a, b])
+        ref, _ = oracle.tvp_sampled(m, [n] * m, hs, [None, Us[:, a], Us[:, b]], idx)
+        assert rel(col[idx], ref) <= TOL[dtype], (a, b)
+        assert np.array_equal(col, host(T[:, b, a]))
