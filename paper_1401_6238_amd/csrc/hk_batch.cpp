@@ -213,6 +213,8 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
       row_limits(dt, sh.odd, sh.logR, e_odd, &k);
       return k.tps;
     }
+    // grouped pass-B rows take 4 elements per lane up to 2048 points
+    if (!sh.resident && !p->persistent && sh.logR <= 11) return tps(sh.logR, 4);
     return tps(sh.logR, er);
   };
   // First virtual columns (sequence * R + storage column) of the column tiles

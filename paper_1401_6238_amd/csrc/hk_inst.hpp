@@ -283,7 +283,7 @@ static size_t group_lds_elems(int kind, int logL) {
   size_t mx = (size_t)BATCH_BLK;
   if (kind == GK_RES || kind == GK_ROWB) {
     KernelLimits kr;
-    HK_CAT(limits_, HK_SUFFIX)(logL, BATCH_E_ROW, &kr);
+    HK_CAT(limits_, HK_SUFFIX)(logL, kind == GK_ROWB && logL <= 11 ? 4 : BATCH_E_ROW, &kr);
     if (kr.tps <= BATCH_BLK) mx = std::max(mx, (size_t)(BATCH_BLK / kr.tps) * kr.seq_lds);
   } else if (kind == GK_COL) {
     KernelLimits kc;

@@ -225,6 +225,13 @@ template <int ODD>
 struct BatchRowE {
   static constexpr int value = ODD > 1 ? 4 : BATCH_E_ROW;
 };
+// Elements per lane of the grouped pass-B rows: 4 up to 2048 points (fewer
+// registers, more waves per SIMD; pass B of large batches is latency-bound at
+// two waves), 8 beyond.  The persistent kernel keeps BATCH_E_ROW.
+template <int L, int ODD>
+struct GroupRowbE {
+  static constexpr int value = (ODD > 1 || L <= 2048) ? 4 : BATCH_E_ROW;
+};
 
 
 template <int L, int ODD = 1>
@@ -402,7 +409,7 @@ __global__ void __launch_bounds__(BATCH_BLK) k_group(BatchArgs A) {
     const Shape &sh = A.shapes[tk.inst];
     const PV P{&A.ptrs[tk.inst], nullptr, 0, A.ws_base};
     if constexpr (KIND == GK_ROWB)
-      batch_rowb_body<L, ODD>(A, tk, sh, P, smem, tid);
+      batch_rowb_body<L, ODD, GroupRowbE<L, ODD>::value>(A, tk, sh, P, smem, tid);
     else if constexpr (KIND == GK_COL)
       batch_col_body<L, ODD == 2 ? CV_R2C : (ODD > 1 ? CV_ODD : CV_POW2)>(tk, sh, P, smem, tid);
     else
