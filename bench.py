@@ -673,6 +673,47 @@ def warm_products(data, hk, _lib, L, torch, dev):
     return res
 
 
+def shared_h_batch(data, hk, _lib, L, torch, dev):
+    """256 vectors against one h (the adjoint-batch shape: m = 4, n = 2^16,
+    N = 2^18, c64), y and alpha for each: the strided batch that transforms h
+    again for every instance (h stride 0) against one stored h^ shared by the
+    batch (hankel_tvp_spectral_strided_batched)."""
+    adj = data["adjoint"]
+    h = torch.from_numpy(adj[0]["h"]).to(torch.complex64).to(dev)
+    X = torch.stack([torch.from_numpy(d["x"]) for d in adj]).to(torch.complex64).to(dev)
+    B, n = X.shape
+    Y = torch.empty_like(X)
+    A = torch.empty(B, dtype=torch.complex64, device=dev)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    P = ctypes.c_void_p
+    nb = ctypes.c_size_t(0)
+    _lib.check(L.hankel_tvp_strided_batched_workspace_size(_lib.HK_C64, 4, n, B, ctypes.byref(nb)), "ws")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+
+    def cold():
+        _lib.check(L.hankel_tvp_strided_batched(_lib.HK_C64, P(h.data_ptr()), 0, 4, n, P(X.data_ptr()), n,
+                                                P(Y.data_ptr()), n, P(A.data_ptr()), B, P(ws.data_ptr()),
+                                                ctypes.c_size_t(nb.value), st), "hankel_tvp_strided_batched")
+    ms_c = time_region(torch, cold, 5)
+    hs = hk.hankel_spectrum(h, 4, [n] * 4, -1)
+    nw = ctypes.c_size_t(0)
+    _lib.check(L.hankel_tvp_spectral_strided_batched_workspace_size(_lib.HK_C64, 4, n, B, ctypes.byref(nw)), "ws")
+    wsw = torch.empty(nw.value, dtype=torch.uint8, device=dev)
+
+    def warm():
+        _lib.check(L.hankel_tvp_spectral_strided_batched(_lib.HK_C64, P(hs.data_ptr()), 4, n, P(X.data_ptr()), n,
+                                                         P(Y.data_ptr()), n, P(A.data_ptr()), B, P(wsw.data_ptr()),
+                                                         ctypes.c_size_t(nw.value), st),
+                   "hankel_tvp_spectral_strided_batched")
+    ms_w = time_region(torch, warm, 5)
+    NB = 1 << 18
+    dh = 4 * (n - 1) + 1
+    return {"h_transformed_per_instance": {"TVP_s": round(B / ms_c * 1000, 1), "ms": round(ms_c, 3),
+                                           "alg_GB_s": round((dh + 2 * n + 6 * NB) * 8 * B / (ms_c * 1e-3) / 1e9, 1)},
+            "stored_h_spectrum": {"TVP_s": round(B / ms_w * 1000, 1), "ms": round(ms_w, 3),
+                                  "alg_GB_s": round((2 * n + 5 * NB) * 8 * B / (ms_w * 1e-3) / 1e9, 1)}}
+
+
 def run_extras(args, data, hk, _lib, L, torch, dev):
     ex = {}
     ex["large_single_cpu_fft_method"] = cpu_fft_method(data["large"][0][2], data["large"][0][3], M)
@@ -818,6 +859,8 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
         del H, X, V, PHI
     ex["adjoint_batch"] = res4
     log("adjoint batch", res4)
+    ex["shared_h_batch_c64"] = shared_h_batch(data, hk, _lib, L, torch, dev)
+    log("256 vectors, one h", ex["shared_h_batch_c64"])
 
     # Hankel tensor-matrix product (Section 4.2, the HOOI kernel): m=3, n=2^16, R=8, c64
     g = np.random.Generator(np.random.PCG64(14016238 + 6000))

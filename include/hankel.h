@@ -156,6 +156,18 @@ hk_status_t hankel_mode_products_spectral(hk_dtype_t dt, const void *h_spec, int
                                           const int64_t *dims, const void *const *vectors,
                                           const void *const *specs, void *y, void *alpha,
                                           void *ws, size_t ws_bytes, hipStream_t stream);
+/* Strided batch of equal-vector products (square shape (m, n)) that share one
+ * stored h^ (hankel_spectrum with which = -1 on dims = {n, ..., n}): instance b
+ * uses x + b*x_stride and writes y + b*y_stride (H x^{m-1}) and alpha + b
+ * (H x^m); y or alpha may be NULL.  One launch per pass covers the batch; the
+ * h^ it reads is shared by all instances.  Rules as for the spectral form. */
+hk_status_t hankel_tvp_spectral_strided_batched_workspace_size(hk_dtype_t dt, int m, int64_t n,
+                                                               int64_t batch, size_t *bytes);
+hk_status_t hankel_tvp_spectral_strided_batched(hk_dtype_t dt, const void *h_spec, int m,
+                                                int64_t n, const void *x, int64_t x_stride,
+                                                void *y, int64_t y_stride, void *alpha,
+                                                int64_t batch, void *ws, size_t ws_bytes,
+                                                hipStream_t stream);
 
 /* -------------------------------------------------------------------------
  * 2-level block Hankel tensor with Hankel blocks (BHHB; Section 2.2

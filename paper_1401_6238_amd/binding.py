@@ -174,6 +174,26 @@ def hankel_mode_products_spectral(h_spec: torch.Tensor, m: int, dims: Sequence[i
     return y, (None if alpha is None else alpha[0])
 
 
+def hankel_tvp_spectral_strided_batched(h_spec: torch.Tensor, X: torch.Tensor, m: int, want_y: bool = True,
+                                        want_alpha: bool = False):
+    """Batch of equal-vector products H x_b^{m-1}, H x_b^m (X is (B, n)) sharing
+    one stored h^ = hankel_spectrum(h, m, [n] * m).  Returns (Y (B, n), alpha (B))."""
+    _dev(h_spec), _dev(X)
+    _same_device(h_spec, X)
+    B, n = X.shape
+    dt = _dtype(X)
+    Y = torch.empty(B, n, dtype=X.dtype, device=X.device) if want_y else None
+    alpha = torch.empty(B, dtype=X.dtype, device=X.device) if want_alpha else None
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_tvp_spectral_strided_batched_workspace_size(dt, m, n, B, ctypes.byref(nb)),
+          "hankel_tvp_spectral_strided_batched_workspace_size")
+    ws, wsb = _workspace(nb.value, X.device)
+    check(lib().hankel_tvp_spectral_strided_batched(dt, _ptr(h_spec), m, n, _ptr(X), n, _ptr(Y), n, _ptr(alpha), B,
+                                                    _ptr(ws), wsb, _stream(X.device)),
+          "hankel_tvp_spectral_strided_batched")
+    return Y, alpha
+
+
 def block_hankel_tvp(H: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]], inner_dims: Sequence[int],
                      block_dims: Sequence[int], want_y: bool = True, want_alpha: bool = False):
     """BHHB tensor: H is the column-major generating matrix (flat); vectors are vec(X_p)."""

@@ -367,7 +367,7 @@ static Status spectral_problem(hk_dtype_t dt, int m, const int64_t *dims, Proble
   return Status();
 }
 
-static Status spectral_setup(const Problem &p, Layout *lay, Sched *sc) {
+static Status spectral_setup(const Problem &p, Layout *lay, Sched *sc, int64_t batch = 1) {
   int64_t dh = 1 - p.m;
   for (int q = 0; q < p.m; ++q) dh += p.dims[q];
   int logN = 0;
@@ -379,11 +379,11 @@ static Status spectral_setup(const Problem &p, Layout *lay, Sched *sc) {
     return fail(HK_ERR_NOT_SUPPORTED, "spectra need the three-pass layout: d_H above 4096");
   Sched sch;
   const int logM = lay->logR + lay->logC;
-  if (sched_lookup(p.dt, PROG_FWD, 0, lay->lclass(), logM, -1, 1, &sch) && sch.split == split &&
+  if (sched_lookup(p.dt, PROG_FWD, 0, lay->lclass(), logM, -1, batch, &sch) && sch.split == split &&
       sched_valid(p.dt, *lay, sch))
     *sc = sch;
   else {
-    *sc = default_sched(p.dt, *lay, PROG_FWD, 1);
+    *sc = default_sched(p.dt, *lay, PROG_FWD, batch);
     sc->split = split;
   }
   if (!sched_valid(p.dt, *lay, *sc)) return fail(HK_ERR_NOT_SUPPORTED, "no valid schedule for this shape");
@@ -508,9 +508,9 @@ static Status spectral_products_problem(hk_dtype_t dt, const void *h_spec, int m
   return Status();
 }
 
-static Status spectral_products_prepare(const Problem &p, Shape *sh, Ptrs *P, Sched *sc) {
+static Status spectral_products_prepare(const Problem &p, Shape *sh, Ptrs *P, Sched *sc, int64_t batch = 1) {
   Layout lay;
-  Status s = spectral_setup(p, &lay, sc);
+  Status s = spectral_setup(p, &lay, sc, batch);
   if (!s.ok()) return s;
   return build_shape(p, lay, *sc, sh, P, nullptr);
 }
@@ -551,6 +551,67 @@ hk_status_t hankel_mode_products_spectral(hk_dtype_t dt, const void *h_spec, int
   Strides str;
   memset(&str, 0, sizeof(str));
   return finish(launch_shape(dt, sh, sc, P, str, 1, stream));
+}
+
+// Strided batch of equal-vector products sharing one stored h^: operand 0 is
+// the spectrum (stride 0), operand 1 the vector x (one transform, power m - 1).
+static Status spectral_batch_problem(hk_dtype_t dt, const void *h_spec, int m, int64_t n, const void *x, void *y,
+                                     void *alpha, Problem *p) {
+  if (m < 2 || m > HK_MAX_ORDER) return fail(HK_ERR_INVALID_VALUE, "order m must be in [2, 8]");
+  int64_t dims[HK_MAX_ORDER];
+  const void *vecs[HK_MAX_ORDER];
+  for (int q = 0; q < m; ++q) {
+    dims[q] = n;
+    vecs[q] = x;
+  }
+  return spectral_products_problem(dt, h_spec, m, dims, vecs, nullptr, y, alpha, p);
+}
+
+hk_status_t hankel_tvp_spectral_strided_batched_workspace_size(hk_dtype_t dt, int m, int64_t n, int64_t batch,
+                                                               size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  if (batch < 0) return finish(fail(HK_ERR_INVALID_VALUE, "batch must be >= 0"));
+  Problem p;
+  Status s = spectral_batch_problem(dt, (const void *)256, m, n, (const void *)256, (void *)256, (void *)256, &p);
+  if (!s.ok()) return finish(s);
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  s = spectral_products_prepare(p, &sh, &P, &sc, std::max<int64_t>(1, batch));
+  if (!s.ok()) return finish(s);
+  *bytes = instance_ws_bytes(sh, dt) * (size_t)batch;
+  return finish(Status());
+}
+
+hk_status_t hankel_tvp_spectral_strided_batched(hk_dtype_t dt, const void *h_spec, int m, int64_t n, const void *x,
+                                                int64_t x_stride, void *y, int64_t y_stride, void *alpha,
+                                                int64_t batch, void *ws, size_t ws_bytes, hipStream_t stream) {
+  if (batch < 0) return finish(fail(HK_ERR_INVALID_VALUE, "batch must be >= 0"));
+  Problem p;
+  Status s = spectral_batch_problem(dt, h_spec, m, n, x, y, alpha, &p);
+  if (!s.ok()) return finish(s);
+  if (batch == 0) return finish(Status());
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  s = spectral_products_prepare(p, &sh, &P, &sc, batch);
+  if (!s.ok()) return finish(s);
+  const size_t per = instance_ws_bytes(sh, dt);
+  s = check_ws(per * (size_t)batch, ws, ws_bytes);
+  if (!s.ok()) return finish(s);
+  s = ensure_device();
+  if (!s.ok()) return finish(s);
+  if (sh.nops != 2 || !(sh.ops[0].flags & OPF_SPEC))
+    return finish(fail(HK_ERR_NOT_SUPPORTED, "unexpected operand layout"));
+  const int64_t eb = (int64_t)elem_bytes(dt);
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  str.op[1] = x_stride * eb;  // operand 0, the stored h^, is shared
+  str.y = y_stride * eb;
+  str.alpha = eb;
+  str.ws = (int64_t)per;
+  P.ws = ws;
+  return finish(launch_shape(dt, sh, sc, P, str, batch, stream));
 }
 
 hk_status_t block_hankel_tvp_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims, const int64_t *block_dims,

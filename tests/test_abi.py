@@ -299,3 +299,19 @@ def test_spectral_layout_and_errors(L):
     s = (ctypes.c_void_p * 3)(1024, 1280, 1536)
     assert L.hankel_mode_products_spectral_workspace_size(HK_C64, 3, d, None, s, 1, 1, ctypes.byref(b)) == OK
     assert b.value < need
+
+
+def test_spectral_batch_argument_errors(L):
+    b = ctypes.c_size_t(0)
+    assert L.hankel_tvp_spectral_strided_batched_workspace_size(HK_C64, 4, 1 << 14, 8, ctypes.byref(b)) == OK
+    one = ctypes.c_size_t(0)
+    assert L.hankel_tvp_spectral_strided_batched_workspace_size(HK_C64, 4, 1 << 14, 1, ctypes.byref(one)) == OK
+    assert b.value == 8 * one.value
+    assert L.hankel_tvp_spectral_strided_batched_workspace_size(HK_C64, 4, 1 << 14, -1, ctypes.byref(b)) == INVALID
+    assert L.hankel_tvp_spectral_strided_batched_workspace_size(HK_F32, 4, 1 << 14, 8, ctypes.byref(b)) == NOTSUP
+    assert L.hankel_tvp_spectral_strided_batched_workspace_size(HK_C64, 3, 100, 8, ctypes.byref(b)) == NOTSUP
+    P = ctypes.c_void_p
+    assert L.hankel_tvp_spectral_strided_batched(HK_C64, None, 4, 1 << 14, P(256), 1 << 14, P(256), 1 << 14, None, 8,
+                                                 P(256), 8 * one.value, None) == NULLP
+    assert L.hankel_tvp_spectral_strided_batched(HK_C64, P(256), 4, 1 << 14, P(256), 1 << 14, P(256), 1 << 14, None, 8,
+                                                 P(256), 8 * one.value - 1, None) == WORKSPACE

@@ -117,3 +117,28 @@ def test_warm_products(dtype):
         yo, ao = oracle.tvp_sampled(m, dims, seen(h, dtype), [xo] * m, idx, want_alpha=True)
         assert rel(host(y)[idx], yo) <= TOL[dtype]
         assert abs(complex(a) - ao) / abs(ao) <= 10 * TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", CDTYPES)
+@pytest.mark.parametrize("m,n", [(3, 8000), (4, 1 << 14)])
+def test_spectral_strided_batch(dtype, m, n):
+    """One stored h^ shared by a strided batch of 5 vectors: every instance's
+    scalar and sampled outputs against the oracle."""
+    import paper_1401_6238_amd as hk
+    print_case(test="spectral_strided_batch", dtype=dtype, m=m, n=n)
+    g = np.random.default_rng(21 + m)
+    B = 5
+    h = draw(g, m * (n - 1) + 1)
+    X = np.stack([draw(g, n, 1.0 / n) for _ in range(B)])
+    hs = hk.hankel_spectrum(to_dev(h, dtype), m, [n] * m, -1)
+    Xd = to_dev(X.reshape(-1), dtype).reshape(B, n)
+    Y, A = hk.hankel_tvp_spectral_strided_batched(hs, Xd, m, True, True)
+    torch.cuda.synchronize()
+    Y, A = host(Y), host(A)
+    idx = np.unique(np.concatenate([np.arange(8), np.arange(n - 8, n), g.integers(0, n, 32)]))
+    ho = seen(h, dtype)
+    for b in range(B):
+        xo = seen(X[b], dtype)
+        yo, ao = oracle.tvp_sampled(m, [n] * m, ho, [xo] * m, idx, want_alpha=True)
+        assert rel(Y[b][idx], yo) <= TOL[dtype], b
+        assert abs(A[b] - ao) / abs(ao) <= 10 * TOL[dtype], b
