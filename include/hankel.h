@@ -230,7 +230,12 @@ typedef struct hk_plan_s *hk_plan_t;
  * captured graph.  flags without PERSISTENT pick the grouped launches (the
  * faster schedule on MI355X); PERSISTENT runs the whole batch in one launch
  * whose resident workgroups pull each phase's tasks from a queue and meet in
- * a grid-wide barrier (bounded wait) between phases. */
+ * a grid-wide barrier (bounded wait) between phases.  Grouped launches spread
+ * a phase's groups over the caller's stream and three streams of the plan;
+ * the process's streams share its few hardware queues, so the eager plan's
+ * time varies with the streams the process created before it (by up to ~15 %
+ * on one mixed batch), while a graph plan (HK_PLAN_GRAPH, on a non-default
+ * stream) replays with the same time whatever they are. */
 hk_status_t hk_plan_create(hk_plan_t *plan, hk_dtype_t dt, const hk_problem_t *probs,
                            int64_t count, unsigned flags);
 hk_status_t hk_plan_workspace_size(hk_plan_t plan, size_t *bytes);
