@@ -854,8 +854,17 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
                 hk.hankel_tvp(H[b], X[b], 4, True, True)
         ms_p = time_region(torch, plain_fwd, 2, warm=1)
         key = "c64" if tdt == torch.complex64 else "c128"
+        # pass-model bytes per instance (N = 2^18): forward d_H + 2n + 6N (pass A reads h
+        # and x and writes two N-element buffers, B reads two and writes one, D reads one
+        # and writes n); adjoint 2 d_H + 3n + 10N (three operands in, grad_h and grad_x out)
+        nn, NN, es = X.shape[1], 1 << 18, (8 if tdt == torch.complex64 else 16)
+        dh = 4 * (nn - 1) + 1
+        fwd_b = (dh + 2 * nn + 6 * NN) * es * B
+        bwd_b = (2 * dh + 3 * nn + 10 * NN) * es * B
         res4[key] = {"fwd_batched_TVP_s": round(B / ms_f * 1000, 1), "bwd_batched_per_s": round(B / ms_b * 1000, 1),
-                     "fwd_plain_loop_TVP_s": round(B / ms_p * 1000, 1), "bwd_over_fwd_time": round(ms_b / ms_f, 3)}
+                     "fwd_plain_loop_TVP_s": round(B / ms_p * 1000, 1), "bwd_over_fwd_time": round(ms_b / ms_f, 3),
+                     "fwd_pass_model_GB_s": round(fwd_b / (ms_f * 1e-3) / 1e9, 1),
+                     "bwd_pass_model_GB_s": round(bwd_b / (ms_b * 1e-3) / 1e9, 1)}
         del H, X, V, PHI
     ex["adjoint_batch"] = res4
     log("adjoint batch", res4)
