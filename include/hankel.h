@@ -117,14 +117,15 @@ hk_status_t hankel_mode_products(hk_dtype_t dt, const void *h, int m, const int6
  * spectra h^ = ifft(pad_N h) and x^_p = fft(pad_N x_p) on one transform length
  * N >= d_H, followed by one transform).  A spectrum computed once serves every
  * product that shares its operand: a fixed h met by many vectors (power
- * iterations, HOOI), a vector met by many h.  Complex dtypes (HK_C64,
- * HK_C128) and d_H = sum(dims) - m + 1 above 4096; other shapes return
- * HK_ERR_NOT_SUPPORTED.
+ * iterations, HOOI), a vector met by many h.  d_H = sum(dims) - m + 1 must
+ * be above 4096 (smaller shapes return HK_ERR_NOT_SUPPORTED).  Every dtype:
+ * a spectrum is N complex values of the dtype's precision (complex64 for
+ * HK_F32, complex128 for HK_F64 and HK_C128); real inputs are transformed as
+ * complex data with zero imaginary parts and real outputs keep the real part.
  *
  * Layout: N is the power of two >= d_H; R = 2^(ceil(log2(N) / 2) + 1) for
  * N >= 2^16 (at most 2^12), else R = 2^ceil(log2(N) / 2); C = N / R.
- * A spectrum is N elements of the dtype; element r R + c (r < C, c < R) holds
- * bin r + C c.  The layout depends only on dt and d_H, so spectra of separate
+ * Element r R + c (r < C, c < R) of a spectrum holds bin r + C c.  The layout depends only on dt and d_H, so spectra of separate
  * calls combine whenever their shapes have the same d_H.
  *
  * hankel_spectrum_layout: *n_fft = N, *row_len = R for the shape (m, dims).
@@ -303,8 +304,8 @@ hk_status_t block_hankel_tvp_levels(hk_dtype_t dt, const void *G, int m, int k, 
  * mode product, i.e. column (j_2, ..., j_m) of T is the tensor-vector product
  * H x_2 U[:, j_2] ... x_m U[:, j_m].  out is n x R^(m-1), column-major, column
  * index j_2 + R j_3 + ... + R^(m-2) j_m.  The columns are symmetric in the j's:
- * the library computes the nondecreasing tuples and copies the rest.  For
- * complex dtypes with d_H > 4096 and (tuples x N) >= 2^21 it transforms h and
+ * the library computes the nondecreasing tuples and copies the rest.  With
+ * d_H > 4096 and (tuples x N) >= 2^21 it transforms h and
  * each column of U once (the spectral form above) and forms every tuple as a
  * product of those spectra followed by one transform; otherwise each tuple is
  * a mode product of a grouped batch.  R^(m-1) <= 2^20.  The call enqueues its

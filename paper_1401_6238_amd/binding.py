@@ -137,7 +137,8 @@ def hankel_spectrum(src: torch.Tensor, m: int, dims: Sequence[int], which: int =
     _dev(src)
     dt = _dtype(src)
     n_fft, _ = hankel_spectrum_layout(src.dtype, m, dims)
-    spec = torch.empty(n_fft, dtype=src.dtype, device=src.device)
+    cdt = {torch.float32: torch.complex64, torch.float64: torch.complex128}.get(src.dtype, src.dtype)
+    spec = torch.empty(n_fft, dtype=cdt, device=src.device)
     d = _i64arr(dims)
     nb = ctypes.c_size_t(0)
     check(lib().hankel_spectrum_workspace_size(dt, m, d, which, ctypes.byref(nb)), "hankel_spectrum_workspace_size")
@@ -150,17 +151,23 @@ def hankel_spectrum(src: torch.Tensor, m: int, dims: Sequence[int], which: int =
 def hankel_mode_products_spectral(h_spec: torch.Tensor, m: int, dims: Sequence[int],
                                   vectors: Optional[Sequence[Optional[torch.Tensor]]] = None,
                                   specs: Optional[Sequence[Optional[torch.Tensor]]] = None,
-                                  want_y: bool = True, want_alpha: bool = False):
+                                  want_y: bool = True, want_alpha: bool = False,
+                                  dtype: Optional[torch.dtype] = None):
     """Mode products from h^ (hankel_spectrum(h, m, dims)); mode p's operand is
-    specs[p] (a spectrum) if given, else vectors[p].  Returns (y, alpha)."""
+    specs[p] (a spectrum) if given, else vectors[p].  dtype: the problem's
+    dtype (default: that of the plain vectors, else the spectra's complex
+    dtype); real problems return real y and alpha.  Returns (y, alpha)."""
     _dev(h_spec)
     ts = [t for t in list(vectors or []) + list(specs or []) if t is not None]
     for t in ts:
         _dev(t)
     _same_device(h_spec, *ts)
-    dt = _dtype(h_spec)
-    y = torch.empty(int(dims[0]), dtype=h_spec.dtype, device=h_spec.device) if want_y else None
-    alpha = torch.empty(1, dtype=h_spec.dtype, device=h_spec.device) if want_alpha else None
+    if dtype is None:
+        plain = [v for v in (vectors or []) if v is not None]
+        dtype = plain[0].dtype if plain else h_spec.dtype
+    dt = _DT[dtype]
+    y = torch.empty(int(dims[0]), dtype=dtype, device=h_spec.device) if want_y else None
+    alpha = torch.empty(1, dtype=dtype, device=h_spec.device) if want_alpha else None
     d = _i64arr(dims)
     va = _vecarr(list(vectors)) if vectors is not None else None
     sa = _vecarr(list(specs)) if specs is not None else None

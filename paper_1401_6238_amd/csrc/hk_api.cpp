@@ -351,7 +351,7 @@ hk_status_t hankel_mode_products(hk_dtype_t dt, const void *h, int m, const int6
 // holds bin r + C c.
 // ---------------------------------------------------------------------------
 static Status spectral_problem(hk_dtype_t dt, int m, const int64_t *dims, Problem *out) {
-  if (dt != HK_C64 && dt != HK_C128) return fail(HK_ERR_NOT_SUPPORTED, "spectra are implemented for complex dtypes");
+  if (dt < HK_C64 || dt > HK_F64) return fail(HK_ERR_INVALID_VALUE, "unknown dtype");
   if (m < 2 || m > HK_MAX_ORDER) return fail(HK_ERR_INVALID_VALUE, "order m must be in [2, 8]");
   if (!dims) return fail(HK_ERR_NULL_POINTER, "dims is NULL");
   Problem p;
@@ -414,7 +414,7 @@ static Status spectrum_prepare(hk_dtype_t dt, int m, const int64_t *dims, int wh
   if (which >= 0) {
     od.role = ROLE_X;
     od.exp = 0;
-    od.flags = 0;
+    od.flags = is_complex(dt) ? 0 : OPF_REAL;
     od.len = dims[which];
     od.cols = 1;
     od.ncol_nz = std::min<int64_t>((int64_t)1 << lay.logR, dims[which]);
@@ -469,8 +469,8 @@ hk_status_t hankel_spectrum(hk_dtype_t dt, int m, const int64_t *dims, int which
   Status s = spectrum_prepare(dt, m, dims, which, src, spec, &sh, &P, &sc);
   if (!s.ok()) return finish(s);
   if (!src || !spec) return finish(fail(HK_ERR_NULL_POINTER, "src or spec is NULL"));
-  const size_t a = elem_bytes(dt);
-  if (!aligned(src, a) || !aligned(spec, a)) return finish(fail(HK_ERR_MISALIGNED, "pointer not aligned to the element size"));
+  if (!aligned(src, elem_bytes(dt)) || !aligned(spec, cplx_bytes(dt)))
+    return finish(fail(HK_ERR_MISALIGNED, "pointer not aligned to the element size"));
   s = check_ws(instance_ws_bytes(sh, dt), ws, ws_bytes);
   if (!s.ok()) return finish(s);
   s = ensure_device();
@@ -996,7 +996,6 @@ struct TmSpectral {
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static bool tm_spectral_plan(hk_dtype_t dt, int m, int64_t n, int64_t R, TmSpectral *T) {
-  if (dt != HK_C64 && dt != HK_C128) return false;
   if (R < 1 || m < 2 || m > HK_MAX_ORDER) return false;
   int64_t dims[HK_MAX_ORDER];
   for (int q = 0; q < m; ++q) dims[q] = n;
@@ -1049,10 +1048,10 @@ static bool tm_spectral_plan(hk_dtype_t dt, int m, int64_t n, int64_t R, TmSpect
     T->pairs[2 * c] = (int32_t)c;
     T->pairs[2 * c + 1] = tuple_of[cc];
   }
-  const size_t eb = elem_bytes(dt);
+  const size_t eb = elem_bytes(dt), cb = cplx_bytes(dt);
   T->batch = std::max<int64_t>(1, std::min<int64_t>({T->K, (int64_t)(((size_t)256 << 20) / T->inst_ws), 65535}));
-  T->off_u = align256((size_t)T->N * eb);
-  T->off_inst = T->off_u + align256((size_t)R * (size_t)T->N * eb);
+  T->off_u = align256((size_t)T->N * cb);
+  T->off_inst = T->off_u + align256((size_t)R * (size_t)T->N * cb);
   T->off_stage = T->off_inst + (size_t)T->batch * T->inst_ws;
   T->off_tab = T->off_stage + align256((size_t)T->K * (size_t)n * eb);
   T->off_pairs = T->off_tab + align256((size_t)d * (size_t)T->K * sizeof(void *));
@@ -1062,7 +1061,7 @@ static bool tm_spectral_plan(hk_dtype_t dt, int m, int64_t n, int64_t R, TmSpect
 
 static Status tm_spectral_run(const TmSpectral &T, hk_dtype_t dt, const void *h, int m, int64_t n, int64_t R,
                               const void *U, void *out, char *ws, hipStream_t st) {
-  const size_t eb = elem_bytes(dt);
+  const size_t eb = elem_bytes(dt), cb = cplx_bytes(dt);  // vectors and outputs / spectra
   const int64_t N = T.N, K = T.K;
   const int d = m - 1;
   char *hspec = ws, *uspec = ws + T.off_u, *inst = ws + T.off_inst, *stage = ws + T.off_stage;
@@ -1073,7 +1072,7 @@ static Status tm_spectral_run(const TmSpectral &T, hk_dtype_t dt, const void *h,
   // tables: operand t of tuple k -> spectrum of U[:, digit t-1 of k]
   std::vector<const void *> htab((size_t)d * K);
   for (int t = 0; t < d; ++t)
-    for (int64_t k = 0; k < K; ++k) htab[(size_t)t * K + k] = uspec + (size_t)T.digits[(size_t)k * d + t] * N * eb;
+    for (int64_t k = 0; k < K; ++k) htab[(size_t)t * K + k] = uspec + (size_t)T.digits[(size_t)k * d + t] * N * cb;
   hipError_t e = hipMemcpyAsync(tab, htab.data(), htab.size() * sizeof(void *), hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(dpairs, T.pairs.data(), T.pairs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
@@ -1093,12 +1092,12 @@ static Status tm_spectral_run(const TmSpectral &T, hk_dtype_t dt, const void *h,
   if (s.ok()) s = spectrum_prepare(dt, m, dims, 1, U, uspec, &sh, &P, &sc);
   if (s.ok()) {
     str.op[0] = n * (int64_t)eb;
-    str.y = N * (int64_t)eb;
+    str.y = N * (int64_t)cb;
     str.ws = (int64_t)T.inst_ws;
     for (int64_t c0 = 0; c0 < R && s.ok(); c0 += T.batch) {
       Ptrs Pc = P;
       Pc.op[0] = (const char *)U + (size_t)c0 * n * eb;
-      Pc.y = uspec + (size_t)c0 * N * eb;
+      Pc.y = uspec + (size_t)c0 * N * cb;
       Pc.ws = inst;
       s = launch_shape(dt, sh, sc, Pc, str, std::min(T.batch, R - c0), st);
     }
@@ -1137,9 +1136,9 @@ static Status tm_spectral_run(const TmSpectral &T, hk_dtype_t dt, const void *h,
   }
   if (s.ok()) {
     count_launch();
-    const bool dbl = dt == HK_C128;
-    e = dbl ? launch_copy_cols_f64(out, stage, dpairs, T.ncols, n, true, st)
-            : launch_copy_cols_f32(out, stage, dpairs, T.ncols, n, true, st);
+    const bool dbl = dt == HK_C128 || dt == HK_F64;
+    e = dbl ? launch_copy_cols_f64(out, stage, dpairs, T.ncols, n, is_complex(dt), st)
+            : launch_copy_cols_f32(out, stage, dpairs, T.ncols, n, is_complex(dt), st);
     if (e != hipSuccess) s = fail(HK_ERR_HIP, std::string("tensor-matrix gather: ") + hipGetErrorString(e));
   }
   // the host copies of the tables must outlive the transfers enqueued above

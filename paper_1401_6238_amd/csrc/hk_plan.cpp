@@ -324,7 +324,8 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
       alpha_group = (int)groups.size() - 1;
     }
     for (size_t i = 0; i < groups.size(); ++i) {
-      const int flags = real_flag | ((int)i == alpha_group ? OPF_ALPHA : 0) | (groups[i].spec ? OPF_SPEC : 0);
+      // a stored spectrum is complex whatever the dtype
+      const int flags = (groups[i].spec ? OPF_SPEC : real_flag) | ((int)i == alpha_group ? OPF_ALPHA : 0);
       add_op(ROLE_X, groups[i].exp, flags, groups[i].n, groups[i].nb, groups[i].ptr, groups[i].src);
     }
     sh.out_rows = p.dims[0];

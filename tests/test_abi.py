@@ -271,7 +271,8 @@ def test_spectral_layout_and_errors(L):
     assert lay(HK_C128, 3, [3000] * 3) == (OK, 1 << 14, 1 << 7)
     assert lay(HK_C64, 4, [8192] * 4) == (OK, 1 << 15, 1 << 8)
     assert lay(HK_C64, 3, [30] * 3)[0] == NOTSUP      # resident size
-    assert lay(HK_F32, 3, [3000] * 3)[0] == NOTSUP    # real dtype
+    assert lay(HK_F32, 3, [3000] * 3) == (OK, 1 << 14, 1 << 7)    # real dtypes: the complex layout
+    assert lay(9, 3, [3000] * 3)[0] == INVALID
     assert lay(HK_C64, 1, [3000])[0] == INVALID
     assert lay(HK_C64, 3, [3000, 0, 5])[0] == INVALID
     d = (ctypes.c_int64 * 3)(3000, 3000, 3000)
@@ -308,7 +309,7 @@ def test_spectral_batch_argument_errors(L):
     assert L.hankel_tvp_spectral_strided_batched_workspace_size(HK_C64, 4, 1 << 14, 1, ctypes.byref(one)) == OK
     assert b.value == 8 * one.value
     assert L.hankel_tvp_spectral_strided_batched_workspace_size(HK_C64, 4, 1 << 14, -1, ctypes.byref(b)) == INVALID
-    assert L.hankel_tvp_spectral_strided_batched_workspace_size(HK_F32, 4, 1 << 14, 8, ctypes.byref(b)) == NOTSUP
+    assert L.hankel_tvp_spectral_strided_batched_workspace_size(HK_F64, 4, 1 << 14, 8, ctypes.byref(b)) == OK
     assert L.hankel_tvp_spectral_strided_batched_workspace_size(HK_C64, 3, 100, 8, ctypes.byref(b)) == NOTSUP
     P = ctypes.c_void_p
     assert L.hankel_tvp_spectral_strided_batched(HK_C64, None, 4, 1 << 14, P(256), 1 << 14, P(256), 1 << 14, None, 8,

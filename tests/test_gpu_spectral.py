@@ -18,9 +18,12 @@ pytestmark = pytest.mark.gpu
 from gpu_util import TOL, host, print_case, rel, seen, to_dev  # noqa: E402
 
 CDTYPES = [torch.complex64, torch.complex128]
+DTYPES = CDTYPES + [torch.float32, torch.float64]
 
 
-def draw(g, n, scale=1.0):
+def draw(g, n, scale=1.0, real=False):
+    if real:
+        return g.uniform(-1, 1, n) * scale
     return (g.standard_normal(n) + 1j * g.standard_normal(n)) * scale
 
 
@@ -31,20 +34,23 @@ def bins_of_layout(N, R):
     return (e // R) + C * (e % R)
 
 
-@pytest.mark.parametrize("dtype", CDTYPES)
+@pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("m,n", [(3, 3000), (4, 8192), (4, 16384)])
 def test_spectra_match_dft(dtype, m, n):
+    """Real dtypes: the spectra of real data, complex values of the same precision."""
     import paper_1401_6238_amd as hk
     print_case(test="spectra", dtype=dtype, m=m, n=n)
     g = np.random.default_rng(100 + m)
     dims = [n] * m
     dh = m * (n - 1) + 1
-    h, x = draw(g, dh), draw(g, n, 1.0 / n)
+    real = not dtype.is_complex
+    h, x = draw(g, dh, real=real), draw(g, n, 1.0 / n, real=real)
     N, R = hk.hankel_spectrum_layout(dtype, m, dims)
     assert N >= dh and N & (N - 1) == 0 and N // 2 < dh
     sh = hk.hankel_spectrum(to_dev(h, dtype), m, dims, -1)
     sx = hk.hankel_spectrum(to_dev(x, dtype), m, dims, 2)
     torch.cuda.synchronize()
+    assert sh.is_complex() and sh.numel() == N
     # a sample of elements that covers whole rows at both ends and scattered ones
     sel = np.unique(np.concatenate([np.arange(2 * R), np.arange(N - 2 * R, N),
                                     np.random.default_rng(7).integers(0, N, 2048)]))
@@ -142,3 +148,37 @@ def test_spectral_strided_batch(dtype, m, n):
         yo, ao = oracle.tvp_sampled(m, [n] * m, ho, [xo] * m, idx, want_alpha=True)
         assert rel(Y[b][idx], yo) <= TOL[dtype], b
         assert abs(A[b] - ao) / abs(ao) <= 10 * TOL[dtype], b
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_real_products_from_spectra(dtype):
+    """Real h and vectors: products from h^ and one stored vector spectrum are
+    real, against the oracle; the warm strided batch on real data too."""
+    import paper_1401_6238_amd as hk
+    print_case(test="real_spectral_products", dtype=dtype)
+    g = np.random.default_rng(31)
+    m, dims = 3, [2500, 3100, 1800]
+    h = draw(g, sum(dims) - m + 1, real=True)
+    xs = [draw(g, n, real=True) for n in dims]
+    xd = [to_dev(v, dtype) for v in xs]
+    hs = hk.hankel_spectrum(to_dev(h, dtype), m, dims, -1)
+    specs = [None, hk.hankel_spectrum(xd[1], m, dims, 1), None]
+    y, a = hk.hankel_mode_products_spectral(hs, m, dims, xd, specs, True, True)
+    torch.cuda.synchronize()
+    assert y.dtype == dtype and not torch.is_complex(a)
+    yo, ao = oracle.tvp(m, dims, seen(h, dtype), [seen(v, dtype) for v in xs], True, True)
+    assert rel(host(y), yo) <= TOL[dtype]
+    assert abs(float(a) - ao.real) / abs(ao) <= 10 * TOL[dtype]
+    # warm strided batch, m = 4, n = 2^13
+    m, n, B = 4, 1 << 13, 3
+    h = draw(g, m * (n - 1) + 1, real=True)
+    X = np.stack([draw(g, n, real=True) for _ in range(B)])
+    hs = hk.hankel_spectrum(to_dev(h, dtype), m, [n] * m, -1)
+    Y, A = hk.hankel_tvp_spectral_strided_batched(hs, to_dev(X.reshape(-1), dtype).reshape(B, n), m, True, True)
+    torch.cuda.synchronize()
+    assert Y.dtype == dtype
+    idx = np.unique(np.concatenate([np.arange(8), np.arange(n - 8, n), g.integers(0, n, 32)]))
+    for b in range(B):
+        yo, ao = oracle.tvp_sampled(m, [n] * m, seen(h, dtype), [seen(X[b], dtype)] * m, idx, want_alpha=True)
+        assert rel(host(Y[b])[idx], yo) <= TOL[dtype], b
+        assert abs(float(A[b]) - ao.real) / abs(ao) <= 10 * TOL[dtype], b

@@ -39,7 +39,7 @@ def test_tensor_matrix(m, n, R, dtype):
 
 @pytest.mark.parametrize("m,n,R,dtype", [
     (3, 4096, 16, torch.complex64), (3, 4096, 16, torch.complex128), (2, 32768, 32, torch.complex64),
-    (4, 2048, 11, torch.complex64),
+    (4, 2048, 11, torch.complex64), (3, 4096, 16, torch.float32), (3, 4096, 16, torch.float64),
 ])
 def test_tensor_matrix_spectral(m, n, R, dtype):
     """Shapes past the spectral threshold (tuples x transform length >= 2^21):
