@@ -58,6 +58,35 @@ def test_large_single_golden(dtype):
     assert ea <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_large_single_warm_golden(dtype):
+    """The same product with h^ stored once (hankel_spectrum) and reused: a
+    single warm product and a strided batch of two, against the oracle's
+    sampled outputs and scalar."""
+    import paper_1401_6238_amd as hk
+    g = golden("large_single")
+    tag = "c128" if dtype == torch.complex128 else "c64"
+    print_case(test="large_warm_golden", dtype=tag)
+    p = wl.large_single(0)
+    same_inputs(g["large_fp_h"], p.h)
+    same_inputs(g["large_fp_x"], p.vectors[1])
+    n = p.dims[0]
+    x = to_dev(p.vectors[1], dtype)
+    hs = hk.hankel_spectrum(to_dev(p.h, dtype), 4, [n] * 4, -1)
+    y, a = hk.hankel_mode_products_spectral(hs, 4, [n] * 4, [x] * 4, None, True, True)
+    Y, A = hk.hankel_tvp_spectral_strided_batched(hs, torch.stack([x, x]), 4, True, True)
+    torch.cuda.synchronize()
+    idx = g["large_idx"]
+    ao = complex(g[f"large_{tag}_alpha"][0])
+    for yy, aa in ((host(y), complex(host(a.reshape(1))[0])), (host(Y[0]), complex(host(A[0:1])[0])),
+                   (host(Y[1]), complex(host(A[1:2])[0]))):
+        e = rel(yy[idx], g[f"large_{tag}_y"])
+        ea = abs(aa - ao) / abs(ao)
+        print(f"large warm {tag}: y rel err {e:.3e}, alpha rel err {ea:.3e}")
+        assert e <= TOL[dtype]
+        assert ea <= TOL[dtype]
+
+
 def test_large_single_vandermonde_all_outputs():
     """Noise-free twin of the large single-product input: every output against the closed form.
 
