@@ -129,8 +129,14 @@ def test_plan_matches_plain_path():
             y2, a2 = hk.block_hankel_tvp(it["h"], it["vectors"], p.dims, p.block_dims, p.want_y, p.want_alpha)
         else:
             y2, a2 = hk.hankel_mode_products(it["h"], it["vectors"], p.dims, p.want_y, p.want_alpha)
+        # the plan and the plain path, each against the oracle
+        yo, ao = oracle_problem(p, dtype)
         if p.want_y:
-            assert rel(host(y), host(y2)) <= 1e-5
+            assert rel(host(y), yo) <= TOL[dtype]
+            assert rel(host(y2), yo) <= TOL[dtype]
+        if p.want_alpha:
+            for aa in (a, a2):
+                assert abs(complex(host(aa.reshape(1))[0]) - ao) <= 10 * TOL[dtype] * max(abs(ao), 1e-300)
     plan.close()
 
 
