@@ -307,6 +307,23 @@ def summarize_trace(trace_dir, command):
     return "\n".join(lines) + "\n"
 
 
+def summarize_stats(trace_dir, command, title, top=40):
+    """The rocprofv3 --stats table alone (kernels by total time), for a traced
+    run of any workload mix."""
+    stats = _read_csv(trace_dir, "kernel_stats.csv")
+    stats.sort(key=lambda r: -float(r["Percentage"]))
+    lines = [f"# {title}", f"#   {command}", "",
+             f"## per-kernel statistics (rocprofv3 --stats, the {top} kernels with the most total time)",
+             "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
+    for r in stats[:top]:
+        nm = r["Name"]
+        short = nm if len(nm) < 120 else nm[:117] + "..."
+        lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['Percentage']):.1f} |")
+    return "\n".join(lines) + "\n"
+
+
 # ---------------------------------------------------------------------------
 # GPU measurements
 # ---------------------------------------------------------------------------
@@ -329,13 +346,17 @@ def main():
                     help="length of the delay kernel queued before the profiled pass")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 4))
     ap.add_argument("--summarize-trace", metavar="DIR", help="write profiles/ summary of a rocprofv3 kernel trace")
+    ap.add_argument("--summarize-stats", metavar="DIR", help="write the per-kernel table of any rocprofv3 trace")
+    ap.add_argument("--title", default="rocprofv3 kernel statistics", help="title line of --summarize-stats")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the per-pass HBM traffic summary from two rocprofv3 --pmc runs")
     ap.add_argument("--profiled-command", default="", help="command line recorded in the summaries")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
-    if args.summarize_trace or args.summarize_counters:
-        if args.summarize_trace:
+    if args.summarize_trace or args.summarize_counters or args.summarize_stats:
+        if args.summarize_stats:
+            txt = summarize_stats(args.summarize_stats, args.profiled_command, args.title)
+        elif args.summarize_trace:
             txt = summarize_trace(args.summarize_trace, args.profiled_command)
         else:
             txt = summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.dtype,
