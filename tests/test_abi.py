@@ -316,3 +316,20 @@ def test_spectral_batch_argument_errors(L):
                                                  P(256), 8 * one.value, None) == NULLP
     assert L.hankel_tvp_spectral_strided_batched(HK_C64, P(256), 4, 1 << 14, P(256), 1 << 14, P(256), 1 << 14, None, 8,
                                                  P(256), 8 * one.value - 1, None) == WORKSPACE
+
+
+def test_spectral_layout_ignores_length_policy(L):
+    """Stored spectra keep the power-of-two layout under every length policy
+    (d_H = 196606 would take 3 * 2^16 under 'smallest'), so spectra made under
+    different policies still combine."""
+    def lay(m, dims):
+        n_fft, row = ctypes.c_int64(0), ctypes.c_int64(0)
+        d = (ctypes.c_int64 * m)(*dims)
+        assert L.hankel_spectrum_layout(HK_C64, m, d, ctypes.byref(n_fft), ctypes.byref(row)) == OK
+        return n_fft.value, row.value
+    try:
+        for policy in (0, 1, 2):
+            assert L.hk_set_fft_lengths(policy) == OK
+            assert lay(3, [65536] * 3) == (1 << 18, 1 << 10)
+    finally:
+        assert L.hk_set_fft_lengths(0) == OK
