@@ -87,6 +87,34 @@ def test_large_single_warm_golden(dtype):
         assert ea <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_shared_h_batch_golden(dtype):
+    """A strided batch of 16 vectors sharing one stored h^ at the adjoint-batch
+    shape (m = 4, n = 2^16, N = 2^18; the batch schedule of that shape, rows in
+    turn): every instance is instance 0 of that workload, against the oracle's
+    sampled forward outputs and scalar, and all 16 bit for bit alike."""
+    import paper_1401_6238_amd as hk
+    g = golden("adjoint_batch")
+    tag = "c128" if dtype == torch.complex128 else "c64"
+    print_case(test="shared_h_batch", dtype=tag)
+    d = wl.adjoint_instance(0)
+    same_inputs(g["adjoint_0_fp_h"], d["h"])
+    n = d["n"]
+    hs = hk.hankel_spectrum(to_dev(d["h"], dtype), 4, [n] * 4, -1)
+    x = to_dev(d["x"], dtype)
+    Y, A = hk.hankel_tvp_spectral_strided_batched(hs, x.expand(16, n).contiguous(), 4, True, True)
+    torch.cuda.synchronize()
+    idx = g["adjoint_0_idx_x"]
+    fo = complex(g[f"adjoint_0_{tag}_f"][0])
+    y0 = host(Y[0])
+    e = rel(y0[idx], g[f"adjoint_0_{tag}_g"])
+    ea = abs(complex(host(A[0:1])[0]) - fo) / abs(fo)
+    print(f"shared-h batch {tag}: y rel err {e:.3e}, alpha rel err {ea:.3e}")
+    assert e <= TOL[dtype] and ea <= TOL[dtype]
+    for b in range(1, 16):
+        assert np.array_equal(host(Y[b]), y0)
+
+
 def test_large_single_vandermonde_all_outputs():
     """Noise-free twin of the large single-product input: every output against the closed form.
 
