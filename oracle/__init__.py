@@ -53,10 +53,11 @@ def _lib():
         lib.hko_block_tvp_sampled.argtypes = [ctypes.c_int, P, P, P, P, P, I64, P, P]
         lib.hko_tvp_backward.argtypes = [ctypes.c_int, I64, P, P, P, P, P, P]
         lib.hko_dft_sampled.argtypes = [ctypes.c_int, P, I64, I64, P, I64, P]
+        lib.hko_tvp_comp.argtypes = [ctypes.c_int, P, P, P, P, P]
         lib.hko_max_threads.argtypes = []
         for f in (lib.hko_conv_range, lib.hko_conv, lib.hko_corr, lib.hko_tvp, lib.hko_tvp_sampled,
                   lib.hko_tvp_i64, lib.hko_block_tvp, lib.hko_block_tvp_i64, lib.hko_block_tvp_sampled,
-                  lib.hko_tvp_backward, lib.hko_dft_sampled,
+                  lib.hko_tvp_backward, lib.hko_dft_sampled, lib.hko_tvp_comp,
                   lib.hko_max_threads):
             f.restype = ctypes.c_int
         _lib_handle = lib
@@ -123,13 +124,16 @@ def _prep(m, dims, h, vectors, need_first):
     return dims, h, vecs
 
 
-def tvp(m: int, dims, h, vectors, want_y: bool = True, want_alpha: bool = False):
-    """Returns (y, alpha): y = H x_2 ... x_m (length dims[0]), alpha = H x_1 ... x_m."""
+def tvp(m: int, dims, h, vectors, want_y: bool = True, want_alpha: bool = False, compensated: bool = False):
+    """Returns (y, alpha): y = H x_2 ... x_m (length dims[0]), alpha = H x_1 ... x_m.
+    compensated=True: every sum by the Dot2 algorithm (twice the working
+    precision), to measure the rounding error of the default blocked sums."""
     dims, h, vecs = _prep(m, dims, h, vectors, want_alpha)
     y = np.empty(int(dims[0]), np.complex128) if want_y else None
     alpha = np.zeros(1, np.complex128) if want_alpha else None
     keep = _vec_ptrs(vecs)
-    _check(_lib().hko_tvp(m, _ptr(dims), _ptr(h), keep, _ptr(y), _ptr(alpha)), "tvp")
+    fn = _lib().hko_tvp_comp if compensated else _lib().hko_tvp
+    _check(fn(m, _ptr(dims), _ptr(h), keep, _ptr(y), _ptr(alpha)), "tvp")
     return y, (None if alpha is None else complex(alpha[0]))
 
 
