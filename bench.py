@@ -105,18 +105,31 @@ def cpu_baseline(x):
     # stage of the oracle (the repeated convolutions and the final correlation
     # with h) runs the same blocked multiply-add loop, so the MAC rate of this
     # slice, divided by the MACs of a whole product, gives products per second.
-    half = min(n - 1, 15000 * max(1, threads))
-    k0, k1 = n - half, n + half
-    macs = sum(min(k, n - 1) - max(0, k - (n - 1)) + 1 for k in range(k0, k1))
-    t0 = time.perf_counter()
-    oracle.conv(x, x, k0, k1)
-    dt = time.perf_counter() - t0
-    rate = macs / dt
     total = oracle_macs_per_product(n, M)
-    return {"value": rate / total, "unit": "TVP/s", "cores": threads, "kind": "oracle",
+
+    def rate(half, reps):
+        k0, k1 = n - half, n + half
+        macs = sum(min(k, n - 1) - max(0, k - (n - 1)) + 1 for k in range(k0, k1))
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.conv(x, x, k0, k1)
+            ts.append(time.perf_counter() - t0)
+        dt = sorted(ts)[len(ts) // 2]
+        return macs / dt, (k0, k1, macs, dt)
+    # all threads: median of 3 runs; one thread: one run of a slice 1/threads as long
+    r_all, (k0, k1, macs, dt) = rate(min(n - 1, 15000 * max(1, threads)), 3)
+    prev = oracle.set_threads(1)
+    try:
+        r_one, (_, _, macs1, dt1) = rate(min(n - 1, 15000), 1)
+    finally:
+        oracle.set_threads(prev)
+    return {"value": r_all / total, "unit": "TVP/s", "cores": threads, "kind": "oracle",
+            "value_1_thread": r_one / total,
             "sample": (f"direct FP64 oracle: outputs [{k0},{k1}) of x*x for one n=2^18 instance "
-                       f"({macs:.3e} complex MACs in {dt:.1f}s), scaled by the {total:.3e} MACs "
-                       f"the oracle needs for one product (y and alpha)")}
+                       f"({macs:.3e} complex MACs, median of 3 runs {dt:.1f}s), scaled by the {total:.3e} MACs "
+                       f"the oracle needs for one product (y and alpha); one thread: {macs1:.3e} MACs "
+                       f"in {dt1:.1f}s")}
 
 
 # ---------------------------------------------------------------------------

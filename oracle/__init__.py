@@ -55,10 +55,11 @@ def _lib():
         lib.hko_dft_sampled.argtypes = [ctypes.c_int, P, I64, I64, P, I64, P]
         lib.hko_tvp_comp.argtypes = [ctypes.c_int, P, P, P, P, P]
         lib.hko_max_threads.argtypes = []
+        lib.hko_set_threads.argtypes = [ctypes.c_int]
         for f in (lib.hko_conv_range, lib.hko_conv, lib.hko_corr, lib.hko_tvp, lib.hko_tvp_sampled,
                   lib.hko_tvp_i64, lib.hko_block_tvp, lib.hko_block_tvp_i64, lib.hko_block_tvp_sampled,
                   lib.hko_tvp_backward, lib.hko_dft_sampled, lib.hko_tvp_comp,
-                  lib.hko_max_threads):
+                  lib.hko_max_threads, lib.hko_set_threads):
             f.restype = ctypes.c_int
         _lib_handle = lib
     return _lib_handle
@@ -66,6 +67,11 @@ def _lib():
 
 def max_threads() -> int:
     return int(_lib().hko_max_threads())
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops from now on; returns the previous count."""
+    return int(_lib().hko_set_threads(int(n)))
 
 
 def _c128(a) -> np.ndarray:

@@ -91,6 +91,15 @@ int hko_max_threads(void) {
 #endif
 }
 
+/* Threads of the following parallel loops (n >= 1); returns the previous count. */
+int hko_set_threads(int n) {
+    const int prev = hko_max_threads();
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#endif
+    return prev;
+}
+
 /* ------------------------------------------------------------------------ */
 /* 1D linear convolution: out_k = sum_j a_j b_{k-j}, for k in [k0, k1).      */
 /* ------------------------------------------------------------------------ */
