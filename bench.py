@@ -582,13 +582,16 @@ def time_region(torch, fn, reps, warm=2, warm_ms=50.0, min_ms=20.0):
     return sorted(ts)[1]
 
 
-def cpu_fft_method(h, x, m, reps=3):
-    """The paper's fast procedure on the host CPU (scipy.fft, FP64, all cores):
-    a cross-check of what the method costs on a CPU, not the oracle."""
+def cpu_fft_method(h, x, m, reps=3, single=False):
+    """The paper's fast procedure on the host CPU (scipy.fft, FP64 or with
+    single=True FP32, the process's CPU share): a cross-check of what the
+    method costs on a CPU, not the oracle."""
     import scipy.fft as sf
+    if single:
+        h, x = np.asarray(h, np.complex64), np.asarray(x, np.complex64)
     n, dh = len(x), len(h)
     N = 1 << (dh - 1).bit_length()
-    workers = os.cpu_count() or 1
+    workers = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
     ts = []
     for _ in range(reps):
         t0 = time.perf_counter()
@@ -600,7 +603,8 @@ def cpu_fft_method(h, x, m, reps=3):
         ts.append(time.perf_counter() - t0)
         del y, a
     t = float(np.median(ts))
-    return {"TVP_s": round(1.0 / t, 2), "ms": round(t * 1e3, 2), "cores": workers, "kind": "scipy.fft c128"}
+    return {"TVP_s": round(1.0 / t, 2), "ms": round(t * 1e3, 2), "cores": workers,
+            "kind": "scipy.fft " + ("c64" if single else "c128")}
 
 
 def independent_products(data, hk, _lib, L, torch, dev):
@@ -751,7 +755,8 @@ def shared_h_batch(data, hk, _lib, L, torch, dev):
 def run_extras(args, data, hk, _lib, L, torch, dev):
     ex = {}
     ex["large_single_cpu_fft_method"] = cpu_fft_method(data["large"][0][2], data["large"][0][3], M)
-    log("cpu fft method", ex["large_single_cpu_fft_method"])
+    ex["large_single_cpu_fft_method_fp32"] = cpu_fft_method(data["large"][0][2], data["large"][0][3], M, single=True)
+    log("cpu fft method", ex["large_single_cpu_fft_method"], ex["large_single_cpu_fft_method_fp32"])
     # the large single product in complex128 (same inputs, FP64 arithmetic)
     if args.dtype == "c64":
         P = 16
