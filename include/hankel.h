@@ -125,8 +125,10 @@ hk_status_t hankel_mode_products(hk_dtype_t dt, const void *h, int m, const int6
  *
  * Layout: N is the power of two >= d_H; R = 2^(ceil(log2(N) / 2) + 1) for
  * N >= 2^16 (at most 2^12), else R = 2^ceil(log2(N) / 2); C = N / R.
- * Element r R + c (r < C, c < R) of a spectrum holds bin r + C c.  The layout depends only on dt and d_H, so spectra of separate
- * calls combine whenever their shapes have the same d_H.
+ * Element r R + c (r < C, c < R) of a spectrum holds bin r + C c.  The
+ * layout depends only on d_H (not on hk_set_fft_lengths), so spectra of
+ * separate calls combine whenever their shapes have the same d_H.  spec
+ * pointers are aligned to the complex element (8 or 16 bytes).
  *
  * hankel_spectrum_layout: *n_fft = N, *row_len = R for the shape (m, dims).
  * hankel_spectrum: which = -1: src = h (d_H elements), spec receives h^
