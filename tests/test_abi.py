@@ -333,3 +333,10 @@ def test_spectral_layout_ignores_length_policy(L):
             assert lay(3, [65536] * 3) == (1 << 18, 1 << 10)
     finally:
         assert L.hk_set_fft_lengths(0) == OK
+
+
+def test_spectral_batch_of_zero(L):
+    """An empty strided spectral batch succeeds on the host without the device."""
+    P = ctypes.c_void_p
+    assert L.hankel_tvp_spectral_strided_batched(HK_C64, P(256), 4, 1 << 14, P(256), 1 << 14, P(256), 1 << 14, None, 0,
+                                                 None, 0, None) == OK

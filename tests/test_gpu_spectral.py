@@ -182,3 +182,25 @@ def test_real_products_from_spectra(dtype):
         yo, ao = oracle.tvp_sampled(m, [n] * m, seen(h, dtype), [seen(X[b], dtype)] * m, idx, want_alpha=True)
         assert rel(host(Y[b])[idx], yo) <= TOL[dtype], b
         assert abs(float(A[b]) - ao.real) / abs(ao) <= 10 * TOL[dtype], b
+
+
+@pytest.mark.parametrize("want", ["y", "alpha"])
+def test_spectral_single_output(want):
+    """Only y or only alpha requested from stored spectra."""
+    import paper_1401_6238_amd as hk
+    dtype = torch.complex128
+    print_case(test="spectral_single_output", want=want)
+    g = np.random.default_rng(41)
+    m, dims = 3, [3000, 2600, 2200]
+    h = draw(g, sum(dims) - m + 1)
+    xs = [draw(g, n, 1.0 / n) for n in dims]
+    xd = [to_dev(v, dtype) for v in xs]
+    hs = hk.hankel_spectrum(to_dev(h, dtype), m, dims, -1)
+    specs = [hk.hankel_spectrum(xd[p], m, dims, p) for p in range(m)]
+    y, a = hk.hankel_mode_products_spectral(hs, m, dims, None, specs, want == "y", want == "alpha")
+    torch.cuda.synchronize()
+    yo, ao = oracle.tvp(m, dims, seen(h, dtype), [seen(v, dtype) for v in xs], True, True)
+    if want == "y":
+        assert a is None and rel(host(y), yo) <= TOL[dtype]
+    else:
+        assert y is None and abs(complex(a) - ao) / abs(ao) <= 10 * TOL[dtype]
