@@ -335,6 +335,15 @@ hk_status_t hankel_tensor_matrix(hk_dtype_t dt, const void *h, int m, int64_t n,
  * Complex dtypes only.
  * ------------------------------------------------------------------------- */
 hk_status_t hankel_tvp_backward_workspace_size(hk_dtype_t dt, int m, int64_t n, size_t *bytes);
+/* The same adjoint with x given by its stored spectrum x_spec (hankel_spectrum
+ * on the shape (m, {n, ..., n}), any mode): the forward's x^ kept for the
+ * backward, so x is not transformed again.  Complex dtypes and the rules of
+ * the spectral form (d_H > 4096). */
+hk_status_t hankel_tvp_backward_spectral_workspace_size(hk_dtype_t dt, int m, int64_t n, size_t *bytes);
+hk_status_t hankel_tvp_backward_spectral(hk_dtype_t dt, const void *h, int m, int64_t n,
+                                         const void *x_spec, const void *grad_y,
+                                         const void *grad_alpha, void *grad_x, void *grad_h,
+                                         void *ws, size_t ws_bytes, hipStream_t stream);
 hk_status_t hankel_tvp_backward(hk_dtype_t dt, const void *h, int m, int64_t n, const void *x,
                                 const void *grad_y, const void *grad_alpha, void *grad_x,
                                 void *grad_h, void *ws, size_t ws_bytes, hipStream_t stream);

@@ -63,6 +63,8 @@ _SIGS = {
     "hankel_mode_products_spectral_workspace_size": [_I, _I, _PI64, _P, _P, _I, _I, _PSZ],
     "hankel_mode_products_spectral": [_I, _P, _I, _PI64, _P, _P, _P, _P, _P, _SZ, _P],
     "hankel_tvp_spectral_strided_batched_workspace_size": [_I, _I, _I64, _I64, _PSZ],
+    "hankel_tvp_backward_spectral_workspace_size": [_I, _I, _I64, _PSZ],
+    "hankel_tvp_backward_spectral": [_I, _P, _I, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P],
     "hankel_tvp_spectral_strided_batched": [_I, _P, _I, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _SZ, _P],
     "block_hankel_tvp_workspace_size": [_I, _I, _PI64, _PI64, _P, _I, _I, _PSZ],
     "block_hankel_tvp": [_I, _P, _I, _PI64, _PI64, _P, _P, _P, _P, _SZ, _P],

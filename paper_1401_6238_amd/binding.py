@@ -273,6 +273,26 @@ def hankel_tvp_backward(h: torch.Tensor, x: torch.Tensor, m: int, grad_y: Option
     return gx, gh
 
 
+def hankel_tvp_backward_spectral(h: torch.Tensor, x_spec: torch.Tensor, m: int, n: int,
+                                 grad_y: Optional[torch.Tensor], grad_alpha: Optional[torch.Tensor],
+                                 want_grad_x: bool = True, want_grad_h: bool = True):
+    """hankel_tvp_backward with x given by its stored spectrum
+    (hankel_spectrum(x, m, [n] * m, 1)).  Returns (grad_x, grad_h)."""
+    _dev(h), _dev(x_spec)
+    dt = _dtype(h)
+    gx = torch.empty(n, dtype=h.dtype, device=h.device) if want_grad_x else None
+    gh = torch.empty(h.numel(), dtype=h.dtype, device=h.device) if want_grad_h else None
+    ga = None if grad_alpha is None else grad_alpha.reshape(1).contiguous()
+    gy = None if grad_y is None else grad_y.contiguous()
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_tvp_backward_spectral_workspace_size(dt, m, n, ctypes.byref(nb)),
+          "hankel_tvp_backward_spectral_workspace_size")
+    ws, wsb = _workspace(nb.value, h.device)
+    check(lib().hankel_tvp_backward_spectral(dt, _ptr(h), m, n, _ptr(x_spec), _ptr(gy), _ptr(ga), _ptr(gx), _ptr(gh),
+                                             _ptr(ws), wsb, _stream(h.device)), "hankel_tvp_backward_spectral")
+    return gx, gh
+
+
 def hankel_tvp_strided_batched(h: torch.Tensor, x: torch.Tensor, m: int, want_y: bool = True,
                                want_alpha: bool = False):
     """Batch of equal-vector products: h (B, d_H), x (B, n).  Returns (y (B, n), alpha (B,))."""

@@ -379,11 +379,11 @@ static Status spectral_setup(const Problem &p, Layout *lay, Sched *sc, int64_t b
     return fail(HK_ERR_NOT_SUPPORTED, "spectra need the three-pass layout: d_H above 4096");
   Sched sch;
   const int logM = lay->logR + lay->logC;
-  if (sched_lookup(p.dt, PROG_FWD, 0, lay->lclass(), logM, -1, batch, &sch) && sch.split == split &&
+  if (sched_lookup(p.dt, p.prog, 0, lay->lclass(), logM, -1, batch, &sch) && sch.split == split &&
       sched_valid(p.dt, *lay, sch))
     *sc = sch;
   else {
-    *sc = default_sched(p.dt, *lay, PROG_FWD, batch);
+    *sc = default_sched(p.dt, *lay, p.prog, batch);
     sc->split = split;
   }
   if (!sched_valid(p.dt, *lay, *sc)) return fail(HK_ERR_NOT_SUPPORTED, "no valid schedule for this shape");
@@ -612,6 +612,53 @@ hk_status_t hankel_tvp_spectral_strided_batched(hk_dtype_t dt, const void *h_spe
   str.ws = (int64_t)per;
   P.ws = ws;
   return finish(launch_shape(dt, sh, sc, P, str, batch, stream));
+}
+
+// Adjoint of the equal-vector products with x given by its stored spectrum
+// (the forward's x^, from hankel_spectrum on the same shape): the column
+// pass of x and its row transform are skipped.
+static Status backward_spectral_prepare(const Problem &p, Shape *sh, Ptrs *P, Sched *sc) {
+  Status s = validate_backward(p);
+  if (!s.ok()) return s;
+  Layout lay;
+  s = spectral_setup(p, &lay, sc);
+  if (!s.ok()) return s;
+  return build_shape(p, lay, *sc, sh, P, nullptr);
+}
+
+hk_status_t hankel_tvp_backward_spectral_workspace_size(hk_dtype_t dt, int m, int64_t n, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  Problem p = bwd_problem(dt, (const void *)256, m, n, (const void *)256, (const void *)256, (const void *)256,
+                          (void *)256, (void *)256);
+  p.spec_mask = 2u;
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  Status s = backward_spectral_prepare(p, &sh, &P, &sc);
+  if (!s.ok()) return finish(s);
+  *bytes = instance_ws_bytes(sh, dt);
+  return finish(Status());
+}
+
+hk_status_t hankel_tvp_backward_spectral(hk_dtype_t dt, const void *h, int m, int64_t n, const void *x_spec,
+                                         const void *grad_y, const void *grad_alpha, void *grad_x, void *grad_h,
+                                         void *ws, size_t ws_bytes, hipStream_t stream) {
+  Problem p = bwd_problem(dt, h, m, n, x_spec, grad_y, grad_alpha, grad_x, grad_h);
+  p.spec_mask = 2u;
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  Status s = backward_spectral_prepare(p, &sh, &P, &sc);
+  if (!s.ok()) return finish(s);
+  if (!(sh.ops[0].flags & OPF_SPEC)) return finish(fail(HK_ERR_NOT_SUPPORTED, "unexpected operand layout"));
+  s = check_ws(instance_ws_bytes(sh, dt), ws, ws_bytes);
+  if (!s.ok()) return finish(s);
+  s = ensure_device();
+  if (!s.ok()) return finish(s);
+  P.ws = ws;
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  return finish(launch_shape(dt, sh, sc, P, str, 1, stream));
 }
 
 hk_status_t block_hankel_tvp_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims, const int64_t *block_dims,

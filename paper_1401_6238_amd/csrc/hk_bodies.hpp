@@ -570,6 +570,9 @@ struct RowBody {
   // Adjoint of g = H x^{m-1}, f = H x^m (equal vectors).  Operands in order:
   // X, then optionally V (cotangent of g, conjugated on load), then H when
   // grad_x is requested.
+  // SPEC: x (operand 0) may be a stored spectrum (OPF_SPEC): loaded as
+  // transformed, no twiddle or transform.
+  template <bool SPEC = false>
   static __device__ __forceinline__ void run_bwd(const Shape &sh, const PV &P, int64_t row, bool valid_row,
                                                  int t, cx<T> *lds, bool resident, const cx<T> *tw24,
                                                  const cx<T> *tw4096) {
@@ -587,11 +590,18 @@ struct RowBody {
     bool tw_on;
     {
       cx<T> xs[EE], p1[EE], vs[EE];
-      load(xs, sh, P, 0, row, valid_row, t, resident);
+      load<SPEC>(xs, sh, P, 0, row, valid_row, t, resident);
       stw.init(t, tw4096);
       tw_on = twiddles(w, sh, row, t, resident, tw24, tw4096);
-      twiddle_in(xs, w, tw_on);
-      fft(xs, t, lds, stw);
+      if constexpr (SPEC) {
+        if (!(sh.ops[0].flags & OPF_SPEC)) {
+          twiddle_in(xs, w, tw_on);
+          fft(xs, t, lds, stw);
+        }
+      } else {
+        twiddle_in(xs, w, tw_on);
+        fft(xs, t, lds, stw);
+      }
 #pragma unroll
       for (int s = 0; s < EE; ++s) p1[s] = mk(T(1), T(0));
       for (int e = 0; e < sh.m - 2; ++e) {

@@ -43,9 +43,9 @@ enum OpFlag : int32_t {
 };
 
 enum Prog : int32_t { PROG_FWD = 0, PROG_BWD = 1 };
-// Row-kernel variant (never a Shape's prog): the forward program built with
-// stored-spectrum operands (OPF_SPEC, OPF_STORE_SPEC) enabled.
-enum : int32_t { PROG_FWD_SPEC = 2 };
+// Row-kernel variants (never a Shape's prog): the forward and adjoint
+// programs built with stored-spectrum operands (OPF_SPEC, OPF_STORE_SPEC).
+enum : int32_t { PROG_FWD_SPEC = 2, PROG_BWD_SPEC = 3 };
 
 enum ColKind : int32_t { COL_A = 0, COL_D = 1 };
 

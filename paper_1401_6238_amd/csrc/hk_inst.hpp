@@ -22,9 +22,12 @@ constexpr int row_maxt(int E) { return E == 4 ? ROW_MAXT_E4 : ROW_MAXT; }
 template <int L, int E>
 static void *row_fn(int prog) {
   if (prog == PROG_BWD) return (void *)&k_rows<L, E, row_maxt(E), PROG_BWD>;
-  if (prog == PROG_FWD_SPEC) {
+  if (prog == PROG_FWD_SPEC || prog == PROG_BWD_SPEC) {
     // spectra exist for the three-pass layouts only, whose rows have >= 2^7 points
-    if constexpr (L >= 128) return (void *)&k_rows<L, E, row_maxt(E), PROG_FWD_SPEC>;
+    if constexpr (L >= 128) {
+      if (prog == PROG_FWD_SPEC) return (void *)&k_rows<L, E, row_maxt(E), PROG_FWD_SPEC>;
+      return (void *)&k_rows<L, E, row_maxt(E), PROG_BWD_SPEC>;
+    }
     return nullptr;
   }
   return (void *)&k_rows<L, E, row_maxt(E), PROG_FWD>;
@@ -202,7 +205,8 @@ bool HK_CAT(limits_, HK_SUFFIX)(int logL, int E, KernelLimits *out) {
 hipError_t HK_CAT(launch_rows_, HK_SUFFIX)(int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh,
                                            const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st) {
   using namespace HK_NS;
-  const int prog = (sh.prog == PROG_FWD && !sh.resident && shape_has_spec(sh)) ? (int)PROG_FWD_SPEC : sh.prog;
+  const bool spec = !sh.resident && shape_has_spec(sh);
+  const int prog = !spec ? sh.prog : (sh.prog == PROG_FWD ? (int)PROG_FWD_SPEC : (int)PROG_BWD_SPEC);
   void *fn = row_kernel(logL, E, prog);
   KernelLimits k;
   if (!fn || !HK_CAT(limits_, HK_SUFFIX)(logL, E, &k)) return hipErrorInvalidValue;

@@ -43,8 +43,8 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
     const int64_t inst = (int64_t)blockIdx.x * rows + rw;
     const bool valid = inst < count;
     const PV P{&p0, &str, valid ? inst : 0, nullptr};
-    if (PROG == PROG_BWD) {
-      RB::run_bwd(sh, P, 0, valid, t, lds, true, g_tw24, g_tw4096);
+    if (PROG == PROG_BWD || PROG == PROG_BWD_SPEC) {
+      RB::template run_bwd<PROG == PROG_BWD_SPEC>(sh, P, 0, valid, t, lds, true, g_tw24, g_tw4096);
       return;
     }
     const cx<T> part = RB::run_fwd(sh, P, 0, valid, t, lds, true, g_tw24, g_tw4096);
@@ -58,10 +58,11 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
     // rows of this workgroup: (blockIdx.x * K + it) * rows + rw, it < K
     const int K = sh.row_iters > 1 ? sh.row_iters : 1;
     const int64_t row0 = (int64_t)blockIdx.x * K * rows + rw;
-    if (PROG == PROG_BWD) {
+    if (PROG == PROG_BWD || PROG == PROG_BWD_SPEC) {
       for (int it = 0; it < K; ++it) {
         const int64_t row = row0 + (int64_t)it * rows;
-        RB::run_bwd(sh, P, row, row < ((int64_t)1 << sh.logC), t, lds, false, g_tw24, g_tw4096);
+        RB::template run_bwd<PROG == PROG_BWD_SPEC>(sh, P, row, row < ((int64_t)1 << sh.logC), t, lds, false,
+                                                     g_tw24, g_tw4096);
       }
       return;
     }

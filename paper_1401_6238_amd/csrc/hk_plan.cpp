@@ -337,7 +337,8 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
     const int64_t n = p.dims[0];
     sh.want_y = p.gh ? 1 : 0;
     sh.want_out1 = p.gx ? 1 : 0;
-    add_op(ROLE_X, 0, 0, n, 1, p.vec[1], 1);
+    // x may be given by its stored spectrum (spec_mask bit 1)
+    add_op(ROLE_X, 0, (p.spec_mask & 2u) ? OPF_SPEC : 0, n, 1, p.vec[1], 1);
     if (p.v) add_op(ROLE_V, 0, OPF_CONJ, n, 1, p.v, -2);
     if (p.gx) add_op(ROLE_H, 1, OPF_CONJ, hrows, 1, p.h, -1);
     sh.out_rows = hrows;  // grad_h length d_H
@@ -353,7 +354,9 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
     sh.rows_per_wg = sc.rows_per_wg;
     sh.row_iters = sc.iters;
     sh.nbuf = sh.nops;
-    if (p.h_spec || p.spec_mask) {
+    // (adjoint shapes keep one buffer per operand: grad_h and grad_x leave the
+    // row pass in the buffers of operands 0 and 1)
+    if (p.prog == PROG_FWD && (p.h_spec || p.spec_mask)) {
       // Spectrum operands need no buffer: the others take buffers 0, 1, ...;
       // the output row goes to buffer 0 (operand 0's), in place of a row the
       // row pass has already read, or to a buffer of its own.

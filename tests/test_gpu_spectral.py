@@ -204,3 +204,4 @@ def test_spectral_single_output(want):
         assert a is None and rel(host(y), yo) <= TOL[dtype]
     else:
         assert y is None and abs(complex(a) - ao) / abs(ao) <= 10 * TOL[dtype]
+
