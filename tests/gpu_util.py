@@ -42,6 +42,16 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def check_alpha(a, ao, dtype, what="", tol=None):
+    """Scalar alpha = H x_1 ... x_m against the oracle: |a - ao| / |ao| within the
+    same relative tolerance as the vector products."""
+    tol = TOL[dtype] if tol is None else tol
+    a, ao = complex(a), complex(ao)
+    e = abs(a - ao) / max(abs(ao), 1e-300)
+    assert e <= tol, f"alpha rel err {e:.3e} > {tol:g} {what}"
+    return e
+
+
 def print_case(**kw):
     print("CASE " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
 

@@ -16,7 +16,7 @@ from paper_1401_6238_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-from gpu_util import TOL, host, print_case, rel, to_dev  # noqa: E402
+from gpu_util import TOL, check_alpha, host, print_case, rel, to_dev  # noqa: E402
 
 GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 

@@ -12,7 +12,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-from gpu_util import TOL, host, print_case, rel, seen, to_dev  # noqa: E402
+from gpu_util import TOL, check_alpha, host, print_case, rel, seen, to_dev  # noqa: E402
 
 DTYPES = [torch.complex64, torch.complex128, torch.float32, torch.float64]
 
@@ -66,7 +66,7 @@ def test_levels_vs_oracle(dtype, m, dims, equal):
     y, a = run(G, xs, dims, dtype, equal)
     yo, ao = oracle.block_levels_tvp(m, dims, seen(G, dtype), [seen(x, dtype) for x in xs], True, True)
     assert rel(y, yo) <= TOL[dtype]
-    assert abs(a - ao) <= 10 * TOL[dtype] * max(abs(ao), 1e-300)
+    check_alpha(a, ao, dtype)
 
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
@@ -82,7 +82,7 @@ def test_level2_matches_native_bhhb(dtype):
     yo, ao = oracle.block_tvp(m, dims[0], dims[1], seen(G, dtype), [seen(x, dtype) for x in xs], True, True)
     for yy, aa in ((y, a), (host(yb), complex(host(ab.reshape(1))[0]))):
         assert rel(yy, yo) <= TOL[dtype]
-        assert abs(aa - ao) <= 10 * TOL[dtype] * abs(ao)
+        check_alpha(aa, ao, dtype)
 
 
 def test_level1_matches_mode_products():
@@ -97,4 +97,4 @@ def test_level1_matches_mode_products():
     yo, ao = oracle.tvp(m, dims[0], seen(G, dtype), [seen(x, dtype) for x in xs], True, True)
     for yy, aa in ((y, a), (host(y1), complex(host(a1.reshape(1))[0]))):
         assert rel(yy, yo) <= TOL[dtype]
-        assert abs(aa - ao) <= 10 * TOL[dtype] * abs(ao)
+        check_alpha(aa, ao, dtype)

@@ -16,7 +16,7 @@ from paper_1401_6238_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-from gpu_util import TOL, host, oracle_problem, print_case, rel, seen, to_dev  # noqa: E402
+from gpu_util import TOL, check_alpha, host, oracle_problem, print_case, rel, seen, to_dev  # noqa: E402
 from test_gpu_batched import check_plan_outputs, mixed_problems, plan_inputs  # noqa: E402
 from test_gpu_parity import check  # noqa: E402
 
@@ -99,7 +99,7 @@ def test_strided_batched(dtype, m, n, B):
     for b, p in enumerate(probs):
         yo, ao = oracle_problem(p, dtype)
         assert rel(host(y[b]), yo) <= TOL[dtype]
-        assert abs(complex(host(a[b:b + 1])[0]) - ao) <= 10 * TOL[dtype] * abs(ao)
+        check_alpha(complex(host(a[b:b + 1])[0]), ao, dtype)
 
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])

@@ -13,7 +13,7 @@ from paper_1401_6238_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-from gpu_util import TOL, host, oracle_problem, print_case, rel, seen, to_dev  # noqa: E402
+from gpu_util import TOL, check_alpha, host, oracle_problem, print_case, rel, seen, to_dev  # noqa: E402
 
 DTYPES = [torch.complex128, torch.complex64]
 
@@ -40,8 +40,7 @@ def check(prob, dtype, tol=None):
         e = rel(y, yo)
         assert e <= tol, f"y rel err {e:.3e} > {tol}"
     if prob.want_alpha:
-        e = abs(a - ao) / max(abs(ao), 1e-300)
-        assert e <= tol * 10, f"alpha rel err {e:.3e}"
+        check_alpha(a, ao, dtype, tol=tol)
 
 
 def test_small_real_f64():

@@ -16,7 +16,7 @@ from paper_1401_6238_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-from gpu_util import TOL, host, print_case, rel, seen, to_dev  # noqa: E402
+from gpu_util import TOL, check_alpha, host, print_case, rel, seen, to_dev  # noqa: E402
 
 DT_CODE = {torch.complex64: 0, torch.complex128: 1}
 
@@ -50,7 +50,7 @@ def test_plain_multipass_schedules(tmp_path, dtype):
         y, a = hk.hankel_tvp(h, x, m, True, True)
         torch.cuda.synchronize()
         assert rel(host(y), yo) <= TOL[dtype], sched
-        assert abs(complex(host(a.reshape(1))[0]) - ao) <= 10 * TOL[dtype] * abs(ao), sched
+        check_alpha(complex(host(a.reshape(1))[0]), ao, dtype, sched)
 
 
 def test_block_schedules(tmp_path):
@@ -71,7 +71,7 @@ def test_block_schedules(tmp_path):
         y, a = hk.block_hankel_tvp(H, vecs, dims, bdims, True, True)
         torch.cuda.synchronize()
         assert rel(host(y), yo) <= TOL[dtype], sched
-        assert abs(complex(host(a.reshape(1))[0]) - ao) <= 10 * TOL[dtype] * abs(ao), sched
+        check_alpha(complex(host(a.reshape(1))[0]), ao, dtype, sched)
 
 
 @pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
@@ -116,7 +116,7 @@ def test_odd_length_schedules(tmp_path, dtype):
             y, a = hk.hankel_tvp(h, x, m, True, True)
             torch.cuda.synchronize()
             assert rel(host(y), yo) <= TOL[dtype], sched
-            assert abs(complex(host(a.reshape(1))[0]) - ao) <= 10 * TOL[dtype] * abs(ao), sched
+            check_alpha(complex(host(a.reshape(1))[0]), ao, dtype, sched)
     finally:
         hk.hk_set_fft_lengths("auto")
 
@@ -145,4 +145,4 @@ def test_autotuned_odd_and_real_shapes():
     torch.cuda.synchronize()
     yo, ao = oracle.tvp(m, [n] * m, seen(p.h, rdt), [seen(p.vectors[1], rdt)] * m, True, True)
     assert rel(host(y), yo) <= TOL[rdt]
-    assert abs(complex(host(a.reshape(1))[0]) - ao) <= 10 * TOL[rdt] * abs(ao)
+    check_alpha(complex(host(a.reshape(1))[0]), ao, rdt)
