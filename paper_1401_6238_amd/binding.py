@@ -45,6 +45,38 @@ def _dev(t: torch.Tensor) -> torch.Tensor:
     return t
 
 
+def _arg(t: torch.Tensor, name: str, numel: Optional[int] = None, dtype: Optional[torch.dtype] = None,
+         device=None) -> torch.Tensor:
+    """One tensor argument: on the GPU, contiguous, no pending conjugation, and
+    (where given) the element count, dtype and device the call implies, so that
+    no kernel reads or writes past the tensor's memory."""
+    _dev(t)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if numel is not None and t.numel() != int(numel):
+        raise ValueError(f"{name} has {t.numel()} elements, expected {int(numel)}")
+    return t
+
+
+def _cotangent(t: Optional[torch.Tensor], name: str, numel: int, dtype: torch.dtype, device):
+    """A cotangent handed over by autograd may be a lazy conjugate or negative
+    view (its memory holds the other values): materialize it, then check it."""
+    if t is None:
+        return None
+    t = t.resolve_conj().resolve_neg().contiguous()
+    return _arg(t, name, numel, dtype, device)
+
+
+def _spec_dtype(dtype: torch.dtype) -> torch.dtype:
+    return {torch.float32: torch.complex64, torch.float64: torch.complex128}.get(dtype, dtype)
+
+
+def _hlen(m: int, dims: Sequence[int]) -> int:
+    return sum(int(d) for d in dims) - int(m) + 1
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -75,11 +107,9 @@ def _same_device(*ts):
 
 def hankel_tvp(h: torch.Tensor, x: torch.Tensor, m: int, want_y: bool = True, want_alpha: bool = False):
     """Square Hankel tensor, equal vectors: (H x^{m-1}, H x^m).  Returns (y, alpha)."""
-    _dev(h), _dev(x)
-    _same_device(h, x)
-    if h.dtype != x.dtype:
-        raise TypeError("h and x must share a dtype")
+    _dev(x)
     n = x.numel()
+    _arg(h, "h", m * (n - 1) + 1, x.dtype, x.device)
     dt = _dtype(x)
     y = torch.empty(n, dtype=x.dtype, device=x.device) if want_y else None
     alpha = torch.empty(1, dtype=x.dtype, device=x.device) if want_alpha else None
@@ -103,11 +133,15 @@ def hankel_mode_products(h: torch.Tensor, vectors: Sequence[Optional[torch.Tenso
             raise ValueError("dims[0] is needed when vectors[0] is None")
         dims = [v.numel() for v in vectors]
     ref = next(v for v in vectors if v is not None)
-    _dev(h)
-    for v in vectors:
+    _dev(ref)
+    if len(dims) != m:
+        raise ValueError("dims must have one entry per vector")
+    _arg(h, "h", _hlen(m, dims), ref.dtype, ref.device)
+    for p, v in enumerate(vectors):
         if v is not None:
-            _dev(v)
-    _same_device(h, *vectors)
+            _arg(v, f"vectors[{p}]", dims[p], ref.dtype, ref.device)
+        elif p > 0 or want_alpha:
+            raise ValueError(f"vectors[{p}] is needed")
     dt = _dtype(ref)
     y = torch.empty(int(dims[0]), dtype=ref.dtype, device=ref.device) if want_y else None
     alpha = torch.empty(1, dtype=ref.dtype, device=ref.device) if want_alpha else None
@@ -136,8 +170,11 @@ def hankel_spectrum(src: torch.Tensor, m: int, dims: Sequence[int], which: int =
     `which` (x^ = fft(pad_N x)), in the library's row order (N elements)."""
     _dev(src)
     dt = _dtype(src)
+    if len(dims) != m or not -1 <= which < m:
+        raise ValueError("dims must have m entries and which must be in [-1, m)")
+    _arg(src, "src", _hlen(m, dims) if which < 0 else dims[which])
     n_fft, _ = hankel_spectrum_layout(src.dtype, m, dims)
-    cdt = {torch.float32: torch.complex64, torch.float64: torch.complex128}.get(src.dtype, src.dtype)
+    cdt = _spec_dtype(src.dtype)
     spec = torch.empty(n_fft, dtype=cdt, device=src.device)
     d = _i64arr(dims)
     nb = ctypes.c_size_t(0)
@@ -158,14 +195,24 @@ def hankel_mode_products_spectral(h_spec: torch.Tensor, m: int, dims: Sequence[i
     dtype (default: that of the plain vectors, else the spectra's complex
     dtype); real problems return real y and alpha.  Returns (y, alpha)."""
     _dev(h_spec)
-    ts = [t for t in list(vectors or []) + list(specs or []) if t is not None]
-    for t in ts:
-        _dev(t)
-    _same_device(h_spec, *ts)
     if dtype is None:
         plain = [v for v in (vectors or []) if v is not None]
         dtype = plain[0].dtype if plain else h_spec.dtype
     dt = _DT[dtype]
+    if len(dims) != m:
+        raise ValueError("dims must have m entries")
+    n_fft, _ = hankel_spectrum_layout(dtype, m, dims)
+    sdt = _spec_dtype(dtype)
+    _arg(h_spec, "h_spec", n_fft, sdt)
+    for p in range(m):
+        sp = specs[p] if specs is not None and p < len(specs) else None
+        v = vectors[p] if vectors is not None and p < len(vectors) else None
+        if sp is not None:
+            _arg(sp, f"specs[{p}]", n_fft, sdt, h_spec.device)
+        elif v is not None:
+            _arg(v, f"vectors[{p}]", dims[p], dtype, h_spec.device)
+        elif p > 0 or want_alpha:
+            raise ValueError(f"mode {p} needs a vector or a spectrum")
     y = torch.empty(int(dims[0]), dtype=dtype, device=h_spec.device) if want_y else None
     alpha = torch.empty(1, dtype=dtype, device=h_spec.device) if want_alpha else None
     d = _i64arr(dims)
@@ -185,10 +232,11 @@ def hankel_tvp_spectral_strided_batched(h_spec: torch.Tensor, X: torch.Tensor, m
                                         want_alpha: bool = False):
     """Batch of equal-vector products H x_b^{m-1}, H x_b^m (X is (B, n)) sharing
     one stored h^ = hankel_spectrum(h, m, [n] * m).  Returns (Y (B, n), alpha (B))."""
-    _dev(h_spec), _dev(X)
-    _same_device(h_spec, X)
+    _dev(X)
     B, n = X.shape
     dt = _dtype(X)
+    n_fft, _ = hankel_spectrum_layout(X.dtype, m, [n] * m)
+    _arg(h_spec, "h_spec", n_fft, _spec_dtype(X.dtype), X.device)
     Y = torch.empty(B, n, dtype=X.dtype, device=X.device) if want_y else None
     alpha = torch.empty(B, dtype=X.dtype, device=X.device) if want_alpha else None
     nb = ctypes.c_size_t(0)
@@ -206,8 +254,15 @@ def block_hankel_tvp(H: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]],
     """BHHB tensor: H is the column-major generating matrix (flat); vectors are vec(X_p)."""
     m = len(vectors)
     ref = next(v for v in vectors if v is not None)
-    _dev(H)
-    _same_device(H, *vectors)
+    _dev(ref)
+    if len(inner_dims) != m or len(block_dims) != m:
+        raise ValueError("inner_dims and block_dims must have one entry per vector")
+    _arg(H, "H", _hlen(m, inner_dims) * _hlen(m, block_dims), ref.dtype, ref.device)
+    for p, v in enumerate(vectors):
+        if v is not None:
+            _arg(v, f"vectors[{p}]", int(inner_dims[p]) * int(block_dims[p]), ref.dtype, ref.device)
+        elif p > 0 or want_alpha:
+            raise ValueError(f"vectors[{p}] is needed")
     dt = _dtype(ref)
     ny = int(inner_dims[0]) * int(block_dims[0])
     y = torch.empty(ny, dtype=ref.dtype, device=ref.device) if want_y else None
@@ -232,11 +287,21 @@ def block_hankel_tvp_levels(G: torch.Tensor, vectors: Sequence[Optional[torch.Te
     m = len(vectors)
     k = len(dims)
     ref = next(v for v in vectors if v is not None)
-    _dev(G)
-    for v in vectors:
+    _dev(ref)
+    if any(len(dims[t]) != m for t in range(k)):
+        raise ValueError("dims[t] must have one entry per vector")
+    glen = 1
+    for t in range(k):
+        glen *= _hlen(m, dims[t])
+    _arg(G, "G", glen, ref.dtype, ref.device)
+    for p, v in enumerate(vectors):
         if v is not None:
-            _dev(v)
-    _same_device(G, *vectors)
+            vlen = 1
+            for t in range(k):
+                vlen *= int(dims[t][p])
+            _arg(v, f"vectors[{p}]", vlen, ref.dtype, ref.device)
+        elif p > 0 or want_alpha:
+            raise ValueError(f"vectors[{p}] is needed")
     dt = _dtype(ref)
     flat = [int(dims[t][p]) for t in range(k) for p in range(m)]
     ny = 1
@@ -258,13 +323,14 @@ def block_hankel_tvp_levels(G: torch.Tensor, vectors: Sequence[Optional[torch.Te
 def hankel_tvp_backward(h: torch.Tensor, x: torch.Tensor, m: int, grad_y: Optional[torch.Tensor],
                         grad_alpha: Optional[torch.Tensor], want_grad_x: bool = True, want_grad_h: bool = True):
     """J^H [grad_y; grad_alpha] for g = H x^{m-1}, f = H x^m.  Returns (grad_x, grad_h)."""
-    _dev(h), _dev(x)
+    _dev(x)
     n = x.numel()
     dt = _dtype(x)
+    _arg(h, "h", m * (n - 1) + 1, x.dtype, x.device)
     gx = torch.empty(n, dtype=x.dtype, device=x.device) if want_grad_x else None
     gh = torch.empty(h.numel(), dtype=x.dtype, device=x.device) if want_grad_h else None
-    ga = None if grad_alpha is None else grad_alpha.reshape(1).contiguous()
-    gy = None if grad_y is None else grad_y.contiguous()
+    ga = _cotangent(grad_alpha, "grad_alpha", 1, x.dtype, x.device)
+    gy = _cotangent(grad_y, "grad_y", n, x.dtype, x.device)
     nb = ctypes.c_size_t(0)
     check(lib().hankel_tvp_backward_workspace_size(dt, m, n, ctypes.byref(nb)), "hankel_tvp_backward_workspace_size")
     ws, wsb = _workspace(nb.value, x.device)
@@ -278,12 +344,15 @@ def hankel_tvp_backward_spectral(h: torch.Tensor, x_spec: torch.Tensor, m: int, 
                                  want_grad_x: bool = True, want_grad_h: bool = True):
     """hankel_tvp_backward with x given by its stored spectrum
     (hankel_spectrum(x, m, [n] * m, 1)).  Returns (grad_x, grad_h)."""
-    _dev(h), _dev(x_spec)
+    _dev(h)
     dt = _dtype(h)
+    _arg(h, "h", m * (n - 1) + 1)
+    n_fft, _ = hankel_spectrum_layout(h.dtype, m, [n] * m)
+    _arg(x_spec, "x_spec", n_fft, _spec_dtype(h.dtype), h.device)
     gx = torch.empty(n, dtype=h.dtype, device=h.device) if want_grad_x else None
     gh = torch.empty(h.numel(), dtype=h.dtype, device=h.device) if want_grad_h else None
-    ga = None if grad_alpha is None else grad_alpha.reshape(1).contiguous()
-    gy = None if grad_y is None else grad_y.contiguous()
+    ga = _cotangent(grad_alpha, "grad_alpha", 1, h.dtype, h.device)
+    gy = _cotangent(grad_y, "grad_y", n, h.dtype, h.device)
     nb = ctypes.c_size_t(0)
     check(lib().hankel_tvp_backward_spectral_workspace_size(dt, m, n, ctypes.byref(nb)),
           "hankel_tvp_backward_spectral_workspace_size")
@@ -296,9 +365,12 @@ def hankel_tvp_backward_spectral(h: torch.Tensor, x_spec: torch.Tensor, m: int, 
 def hankel_tvp_strided_batched(h: torch.Tensor, x: torch.Tensor, m: int, want_y: bool = True,
                                want_alpha: bool = False):
     """Batch of equal-vector products: h (B, d_H), x (B, n).  Returns (y (B, n), alpha (B,))."""
-    _dev(h), _dev(x)
+    _dev(x)
     B, n = x.shape
     dt = _dtype(x)
+    _arg(h, "h", B * (m * (n - 1) + 1), x.dtype, x.device)
+    if h.dim() != 2:
+        raise ValueError("h must be (B, d_H)")
     y = torch.empty(B, n, dtype=x.dtype, device=x.device) if want_y else None
     alpha = torch.empty(B, dtype=x.dtype, device=x.device) if want_alpha else None
     nb = ctypes.c_size_t(0)
@@ -313,13 +385,18 @@ def hankel_tvp_strided_batched(h: torch.Tensor, x: torch.Tensor, m: int, want_y:
 def hankel_tvp_backward_strided_batched(h: torch.Tensor, x: torch.Tensor, m: int, grad_y: Optional[torch.Tensor],
                                         grad_alpha: Optional[torch.Tensor], want_grad_x: bool = True,
                                         want_grad_h: bool = True):
-    _dev(h), _dev(x)
+    """J^H of a strided batch: h (B, d_H), x (B, n), grad_y (B, n), grad_alpha (B,).
+    Returns (grad_x (B, n), grad_h (B, d_H))."""
+    _dev(x)
     B, n = x.shape
     dt = _dtype(x)
+    _arg(h, "h", B * (m * (n - 1) + 1), x.dtype, x.device)
+    if h.dim() != 2:
+        raise ValueError("h must be (B, d_H)")
     gx = torch.empty(B, n, dtype=x.dtype, device=x.device) if want_grad_x else None
     gh = torch.empty(B, h.shape[1], dtype=x.dtype, device=x.device) if want_grad_h else None
-    gy = None if grad_y is None else grad_y.contiguous()
-    ga = None if grad_alpha is None else grad_alpha.contiguous()
+    gy = _cotangent(grad_y, "grad_y", B * n, x.dtype, x.device)
+    ga = _cotangent(grad_alpha, "grad_alpha", B, x.dtype, x.device)
     nb = ctypes.c_size_t(0)
     check(lib().hankel_tvp_backward_strided_batched_workspace_size(dt, m, n, B, ctypes.byref(nb)),
           "hankel_tvp_backward_strided_batched_workspace_size")
@@ -333,9 +410,14 @@ def hankel_tvp_backward_strided_batched(h: torch.Tensor, x: torch.Tensor, m: int
 def block_hankel_tvp_strided_batched(H: torch.Tensor, x: torch.Tensor, m: int, inner: int, blocks: int,
                                      want_y: bool = True, want_alpha: bool = False):
     """Batch of equal-vector BHHB products: H (B, rows*cols) column-major, x (B, inner*blocks)."""
-    _dev(H), _dev(x)
+    _dev(x)
     B = x.shape[0]
     dt = _dtype(x)
+    if x.dim() != 2 or x.shape[1] != inner * blocks:
+        raise ValueError("x must be (B, inner * blocks)")
+    _arg(H, "H", B * (m * (inner - 1) + 1) * (m * (blocks - 1) + 1), x.dtype, x.device)
+    if H.dim() != 2:
+        raise ValueError("H must be (B, rows * cols)")
     ny = inner * blocks
     y = torch.empty(B, ny, dtype=x.dtype, device=x.device) if want_y else None
     alpha = torch.empty(B, dtype=x.dtype, device=x.device) if want_alpha else None
@@ -365,9 +447,8 @@ class Plan:
         self._keep = []
         for i, p in enumerate(self.problems):
             vecs = p["vectors"]
-            for t in [p["h"]] + [v for v in vecs if v is not None]:
-                _dev(t)
             ref = next(v for v in vecs if v is not None)
+            _dev(ref)
             dtype = ref.dtype if dtype is None else dtype
             if ref.dtype != dtype:
                 raise TypeError("all problems of a plan share one dtype")
@@ -376,6 +457,16 @@ class Plan:
             bd = p.get("block_dims")
             want_y = p.get("want_y", True)
             want_a = p.get("want_alpha", False)
+            if len(vecs) != m or len(dims) != m or (bd is not None and len(bd) != m):
+                raise ValueError(f"problem {i}: vectors, dims and block_dims need m entries")
+            hlen = _hlen(m, dims) * (_hlen(m, bd) if bd is not None else 1)
+            _arg(p["h"], f"problem {i} h", hlen, dtype, ref.device)
+            for k, v in enumerate(vecs):
+                if v is not None:
+                    _arg(v, f"problem {i} vectors[{k}]", int(dims[k]) * (int(bd[k]) if bd is not None else 1),
+                         dtype, ref.device)
+                elif k > 0 or want_a:
+                    raise ValueError(f"problem {i}: vectors[{k}] is needed")
             ny = int(dims[0]) * (int(bd[0]) if bd is not None else 1)
             y = torch.empty(ny, dtype=dtype, device=ref.device) if want_y else None
             a = torch.empty(1, dtype=dtype, device=ref.device) if want_a else None
@@ -428,10 +519,12 @@ def hankel_tensor_matrix(h: torch.Tensor, U: torch.Tensor, m: int) -> torch.Tens
     """T = H x_2 U ... x_m U for the square order-m Hankel tensor with generating
     vector h and an (n, R) matrix U.  Returns T with shape (n, R, ..., R),
     T[i, j_2, ..., j_m] = (H x_2 U[:, j_2] ... x_m U[:, j_m])[i]."""
-    _dev(h)
+    if U.dim() != 2 or U.dtype != h.dtype or U.device != h.device:
+        raise ValueError("U must be an (n, R) matrix of h's dtype on h's device")
+    n, R = U.shape
+    _arg(h, "h", m * (n - 1) + 1)
     if not U.is_cuda:
         raise ValueError("tensors must live on the GPU")
-    n, R = U.shape
     dt = _dtype(h)
     Ucm = U.t().resolve_conj().resolve_neg().contiguous()  # column-major n x R: column j contiguous
     ncols = R ** (m - 1)

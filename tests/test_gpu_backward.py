@@ -145,3 +145,27 @@ def test_backward_finite_differences_gpu():
             d[s] = eps * unit
             fd = (loss(h + d, x) - loss(h - d, x)) / (2 * eps)
             assert abs(fd - part(gh[s])) <= 1e-7 * max(1.0, abs(gh[s]))
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_autograd_conjugated_loss(batched):
+    """Loss Re(sum conj(g) w) + Re(conj(f) psi): autograd hands the backward
+    cotangents that can be lazy conjugate views; the gradients must still be
+    J^H applied to (w, psi), the oracle's gradients."""
+    import paper_1401_6238_amd as hk
+    m, n, B = 3, 2000, (2 if batched else 1)
+    dt = torch.complex128
+    data = [inputs(60 + b, m, n) for b in range(B)]
+    H = torch.stack([to_dev(d[0], dt) for d in data]).requires_grad_(True)
+    X = torch.stack([to_dev(d[1], dt) for d in data]).requires_grad_(True)
+    W = torch.stack([to_dev(d[2], dt) for d in data])
+    psi = to_dev(np.array([d[3] for d in data]), dt)
+    hh, xx = (H, X) if batched else (H[0], X[0])
+    g, f = hk.hankel_tvp_autograd(hh, xx, m)
+    ww, pp = (W, psi) if batched else (W[0], psi[0])
+    loss = (g.conj() * ww).real.sum() + (f.conj() * pp).real.sum()
+    gH, gX = torch.autograd.grad(loss, [H, X])
+    for b, (h, x, w, ps) in enumerate(data):
+        ox, oh = oracle.tvp_backward(m, h, x, w, ps)
+        assert rel(host(gX[b]), ox) <= TOL[dt]
+        assert rel(host(gH[b]), oh) <= TOL[dt]
