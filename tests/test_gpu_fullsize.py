@@ -6,7 +6,9 @@ Expected values come from the CPU oracle through tests/golden/make_golden.py
 from closed forms that hold at any size (Vandermonde generating vectors,
 Section 4.1 / 4.3), which check every output.
 """
+import functools
 import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -180,23 +182,42 @@ def test_mixed_batch_all_instances(flags):
     assert worst <= TOL[dtype]
 
 
+@functools.lru_cache(maxsize=None)
+def _instances(kind, count):
+    make = wl.adjoint_instance if kind == "adjoint" else wl.block_instance
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        return tuple(ex.map(make, range(count)))
+
+
+def _scalar_invariant(x, y, f, dtype):
+    """alpha = x_1^T (H x_2 ... x_m) (Section 3): the scalar equals the vector
+    product dotted with the first vector, at any size.  Both sides come from the
+    GPU: with ||dy|| <= tol ||y|| and |df| <= tol |f| <= tol ||x|| ||y||
+    (Cauchy-Schwarz), |f - x^T y| <= 2 tol ||x|| ||y||."""
+    x = np.asarray(x, np.complex128)
+    y = np.asarray(y, np.complex128)
+    ref = complex(np.dot(x, y))
+    bound = 2 * TOL[dtype] * np.linalg.norm(x) * np.linalg.norm(y)
+    assert abs(complex(f) - ref) <= bound, (complex(f), ref, bound)
+
+
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 def test_adjoint_batch_forward_and_adjoint(dtype):
-    """Batch of 256 (m=4, n=2^16): forward g, f and gradients of sampled instances."""
+    """Batch of 256 distinct instances (m=4, n=2^16), as the benchmark times it:
+    forward g, f and the gradients of twelve instances against the oracle's
+    sampled values, the scalar of every instance against x^T g."""
     import paper_1401_6238_amd as hk
     g = golden("adjoint_batch")
     tag = "c128" if dtype == torch.complex128 else "c64"
     print_case(test="adjoint_batch", dtype=tag)
     insts = [int(i) for i in g["adjoint_instances"]]
-    data = {i: wl.adjoint_instance(i) for i in insts}
+    data = _instances("adjoint", 256)
     for i in insts:
         same_inputs(g[f"adjoint_{i}_fp_h"], data[i]["h"])
-    # the 252 other slots repeat instance 0: their results must equal slot 0 bit for bit
-    order = [i if i in data else 0 for i in range(256)]
-    H = torch.stack([to_dev(data[i]["h"], dtype) for i in order])
-    X = torch.stack([to_dev(data[i]["x"], dtype) for i in order])
-    V = torch.stack([to_dev(data[i]["v"], dtype) for i in order])
-    PHI = to_dev(np.array([data[i]["phi"] for i in order]), dtype)
+    H = torch.stack([to_dev(d["h"], dtype) for d in data])
+    X = torch.stack([to_dev(d["x"], dtype) for d in data])
+    V = torch.stack([to_dev(d["v"], dtype) for d in data])
+    PHI = to_dev(np.array([d["phi"] for d in data]), dtype)
     gy, f = hk.hankel_tvp_strided_batched(H, X, 4, True, True)
     gx, gh = hk.hankel_tvp_backward_strided_batched(H, X, 4, V, PHI)
     torch.cuda.synchronize()
@@ -204,39 +225,38 @@ def test_adjoint_batch_forward_and_adjoint(dtype):
     for i in insts:
         ix, ih = g[f"adjoint_{i}_idx_x"], g[f"adjoint_{i}_idx_h"]
         assert rel(host(gy[i])[ix], g[f"adjoint_{i}_{tag}_g"]) <= tol
-        fo = complex(g[f"adjoint_{i}_{tag}_f"][0])
-        assert abs(complex(host(f[i:i + 1])[0]) - fo) <= tol * abs(fo)
+        check_alpha(complex(host(f[i:i + 1])[0]), complex(g[f"adjoint_{i}_{tag}_f"][0]), dtype, i)
         assert rel(host(gx[i])[ix], g[f"adjoint_{i}_{tag}_gx"]) <= tol
         assert rel(host(gh[i])[ih], g[f"adjoint_{i}_{tag}_gh"]) <= tol
-    ref = host(gx[0])
-    for b in (2, 77, 200):
-        assert np.array_equal(host(gx[b]), ref)
-        assert np.array_equal(host(gy[b]), host(gy[0]))
+    Xh, Gh, Fh = host(X), host(gy), host(f)
+    for b in range(256):
+        _scalar_invariant(Xh[b], Gh[b], Fh[b], dtype)
 
 
 def test_block_batch():
-    """64 BHHB tensors (m=3, 512 blocks of 512, 2048^2 grid), sampled outputs of tensors 0 and 63."""
+    """64 distinct BHHB tensors (m=3, 512 blocks of 512, 2048^2 grid): sampled
+    outputs of six tensors against the oracle, the scalar of every tensor
+    against vec(X)^T vec(Y)."""
     import paper_1401_6238_amd as hk
     g = golden("block_batch")
     print_case(test="block_batch")
     dtype = torch.complex64
     insts = [int(i) for i in g["block_instances"]]
-    data = {i: wl.block_instance(i) for i in insts}
+    data = _instances("block", 64)
     for i in insts:
         same_inputs(g[f"block_{i}_fp_h"], data[i].h)
-    order = [i if i in data else 0 for i in range(64)]
-    Hs = torch.stack([to_dev(data[i].h, dtype) for i in order])
-    Xs = torch.stack([to_dev(data[i].vectors[1], dtype) for i in order])
+    Hs = torch.stack([to_dev(d.h, dtype) for d in data])
+    Xs = torch.stack([to_dev(d.vectors[1], dtype) for d in data])
     y, a = hk.block_hankel_tvp_strided_batched(Hs, Xs, 3, 512, 512, True, True)
     torch.cuda.synchronize()
     for i in insts:
         e = rel(host(y[i])[g[f"block_{i}_idx"]], g[f"block_{i}_y"])
-        ao = complex(g[f"block_{i}_alpha"][0])
-        ea = abs(complex(host(a[i:i + 1])[0]) - ao) / abs(ao)
-        print(f"block tensor {i}: y {e:.3e} alpha {ea:.3e}")
-        assert e <= TOL[dtype] and ea <= TOL[dtype]
-    for b in (1, 30):
-        assert np.array_equal(host(y[b]), host(y[0]))
+        print(f"block tensor {i}: y {e:.3e}")
+        assert e <= TOL[dtype]
+        check_alpha(complex(host(a[i:i + 1])[0]), complex(g[f"block_{i}_alpha"][0]), dtype, i)
+    Xh, Yh, Ah = host(Xs), host(y), host(a)
+    for b in range(64):
+        _scalar_invariant(Xh[b], Yh[b], Ah[b], dtype)
 
 
 def test_block_level2_closed_form():

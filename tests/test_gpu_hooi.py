@@ -10,7 +10,7 @@ from paper_1401_6238_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-from gpu_util import host, print_case, seen, to_dev  # noqa: E402
+from gpu_util import TOL, host, print_case, rel, seen, to_dev  # noqa: E402
 
 PTOL = {torch.complex128: 1e-9, torch.complex64: 2e-3}
 
@@ -43,5 +43,8 @@ def test_hooi_matches_oracle(dtype, m, n, R):
     Ug, Sg, hist = hooi.hooi(hd, m, R, iters=3, U0=to_dev(U0o.reshape(-1), dtype).reshape(n, R))
     torch.cuda.synchronize()
     assert proj_dist(host(Ug), Uo) <= PTOL[dtype]
-    assert abs(np.linalg.norm(host(Sg)) - np.linalg.norm(So)) <= 10 * PTOL[dtype] * np.linalg.norm(So)
+    # the core S = H conj(U)^m element by element: the oracle's core of the GPU's
+    # own U (the subspace agrees above; its basis is only fixed up to a rotation)
+    _, So_g = oracle.hooi(m, hs, R, iters=0, U0=host(Ug))
+    assert rel(host(Sg), So_g) <= TOL[dtype]
     assert len(hist) == 3

@@ -25,14 +25,16 @@ from test_gpu_parity import check  # noqa: E402
 REAL = [torch.float32, torch.float64]
 
 
-@pytest.mark.parametrize("dtype", REAL)
-@pytest.mark.parametrize("m,n", [(2, 1), (2, 2), (3, 2), (2, 3), (3, 3), (4, 4), (3, 7), (2, 64), (3, 64), (5, 33),
-                                 (3, 100), (4, 300), (3, 683), (2, 2048), (3, 1366), (4, 1365), (5, 1024),
-                                 (3, 2731), (8, 500)])
+EQUAL_SHAPES = [(2, 1), (2, 2), (3, 2), (2, 3), (3, 3), (4, 4), (3, 7), (2, 64), (3, 64), (5, 33),
+                (3, 100), (4, 300), (3, 683), (2, 2048), (3, 1366), (4, 1365), (5, 1024), (3, 2731), (8, 500)]
+# resident real rows hold N <= 8192 (float) and N <= 4096 (double); the double
+# shapes beyond that run three passes, which test_multipass_equal covers
+EQUAL_CASES = [(dt, m, n) for dt in REAL for (m, n) in EQUAL_SHAPES
+               if not (dt == torch.float64 and m * (n - 1) + 1 > 4096)]
+
+
+@pytest.mark.parametrize("dtype,m,n", EQUAL_CASES)
 def test_equal(dtype, m, n):
-    d = m * (n - 1) + 1
-    if dtype == torch.float64 and d > 4096:
-        pytest.skip("double real rows hold N <= 4096; larger ones take the complex path (covered elsewhere)")
     print_case(test="real_equal", dtype=dtype, m=m, n=n)
     prob = wl.random_problem(9500 + 7 * m + n, m, [n] * m, True, complex_=False, want_alpha=True)
     check(prob, dtype)
