@@ -95,6 +95,28 @@ hk_status_t hankel_tvp(hk_dtype_t dt, const void *h, int m, int64_t n, const voi
                        void *y, void *alpha, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* -------------------------------------------------------------------------
+ * hankel_tvp without a workspace argument and without device allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results and kernels as hankel_tvp; the workspace is a static device array
+ * of HK_NOALLOC_SCRATCH_BYTES per device, held by every device the library
+ * runs on until the process ends.
+ *  - Products whose workspace (hankel_tvp_workspace_size) exceeds
+ *    HK_NOALLOC_SCRATCH_BYTES are rejected with HK_ERR_WORKSPACE before
+ *    anything is enqueued.  40 MiB covers, e.g., m = 4, n = 2^18 (N = 2^20)
+ *    in HK_C64 and HK_C128.
+ *  - The first call on a device looks up that device's copy of the array and
+ *    uploads the twiddle tables (host-synchronous, once); make it outside
+ *    graph capture.  Later calls enqueue kernels only.
+ *  - All calls on one device share its array: calls that overlap in time on
+ *    one device (different streams or threads without ordering) race and give
+ *    unspecified results.  Calls on one stream are ordered and safe.
+ * ------------------------------------------------------------------------- */
+#define HK_NOALLOC_SCRATCH_BYTES ((size_t)40 << 20)
+hk_status_t hankel_tvp_noalloc(hk_dtype_t dt, const void *h, int m, int64_t n, const void *x,
+                               void *y, void *alpha, hipStream_t stream);
+
+/* -------------------------------------------------------------------------
  * General Hankel tensor n_1 x ... x n_m, distinct vectors (Section 3, the two
  * product types y = H x_2 ... x_m and alpha = H x_1 ... x_m).
  *   dims    : host array of m sizes n_p >= 1

@@ -55,6 +55,7 @@ _PI64 = ctypes.POINTER(ctypes.c_int64)
 _SIGS = {
     "hankel_tvp_workspace_size": [_I, _I, _I64, _PSZ],
     "hankel_tvp": [_I, _P, _I, _I64, _P, _P, _P, _P, _SZ, _P],
+    "hankel_tvp_noalloc": [_I, _P, _I, _I64, _P, _P, _P, _P],
     "hankel_mode_products_workspace_size": [_I, _I, _PI64, _P, _I, _I, _PSZ],
     "hankel_mode_products": [_I, _P, _I, _PI64, _P, _P, _P, _P, _SZ, _P],
     "hankel_spectrum_layout": [_I, _I, _PI64, _PI64, _PI64],

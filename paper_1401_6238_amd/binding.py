@@ -121,6 +121,20 @@ def hankel_tvp(h: torch.Tensor, x: torch.Tensor, m: int, want_y: bool = True, wa
     return y, (None if alpha is None else alpha[0])
 
 
+def hankel_tvp_noalloc(h: torch.Tensor, x: torch.Tensor, m: int, want_y: bool = True, want_alpha: bool = False):
+    """hankel_tvp with the library's static device workspace (no workspace
+    tensor is allocated; the outputs are the caller's only new tensors)."""
+    _dev(x)
+    n = x.numel()
+    _arg(h, "h", m * (n - 1) + 1, x.dtype, x.device)
+    dt = _dtype(x)
+    y = torch.empty(n, dtype=x.dtype, device=x.device) if want_y else None
+    alpha = torch.empty(1, dtype=x.dtype, device=x.device) if want_alpha else None
+    check(lib().hankel_tvp_noalloc(dt, _ptr(h), m, n, _ptr(x), _ptr(y), _ptr(alpha), _stream(x.device)),
+          "hankel_tvp_noalloc")
+    return y, (None if alpha is None else alpha[0])
+
+
 def hankel_mode_products(h: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]], dims: Sequence[int] = None,
                          want_y: bool = True, want_alpha: bool = False):
     """General Hankel tensor: y = H x_2 ... x_m, alpha = H x_1 ... x_m.

@@ -23,6 +23,10 @@ static hk_status_t finish(const Status &s) {
   return s.code;
 }
 
+namespace hk {
+hk_status_t api_finish(const Status &s) { return finish(s); }
+}  // namespace hk
+
 static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 static Status check_ws(size_t need, const void *ws, size_t ws_bytes) {
