@@ -510,6 +510,9 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
                 "per_kernel": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                                for k, v in per_kernel.items()}}
+    # parity of what is timed: instance 0's outputs (last written by the profiled
+    # launches above) against the oracle's sampled values
+    parity = golden_error(ys[0].cpu().to(torch.complex128).numpy(), complex(als[0].cpu()), args.dtype)
     compulsory = (DH + 2 * NVEC) * esz
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "TVP/s", "n_gpus": 1,
@@ -522,6 +525,7 @@ def main():
                    "m": M, "n": NVEC, "fft_len": NFFT, "pool": P, "hip_graph": graph is not None},
         "roofline": roofline,
         "compulsory_GB_s": round(compulsory / (ms * 1e-3) / 1e9, 1),
+        "parity_vs_oracle": parity,
     }
 
     traffic = load_traffic(args.dtype)
@@ -580,6 +584,43 @@ def time_region(torch, fn, reps, warm=2, warm_ms=50.0, min_ms=20.0):
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1) / reps)
     return sorted(ts)[1]
+
+
+def roof(alg_bytes, ms, kernel):
+    """Roofline entry: algorithmic bytes of one timed unit over its time, against
+    the 8 TB/s HBM peak."""
+    gbs = alg_bytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "alg_bytes": int(alg_bytes), "ms": round(ms, 5), "achieved_GB_s": round(gbs, 1),
+            "peak_GB_s": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4), "kernel": kernel}
+
+
+def golden_error(y, alpha, dtype):
+    """Relative 2-norm error of the timed product's y (at the sampled indices) and
+    |d alpha| / |alpha| against the oracle's values for instance 0
+    (tests/golden/large_single_oracle.npz, written from the CPU oracle only)."""
+    path = os.path.join(ROOT, "tests", "golden", "large_single_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    idx = g["large_idx"]
+    yo, ao = g[f"large_{dtype}_y"], complex(g[f"large_{dtype}_alpha"][0])
+    yv = np.asarray(y, np.complex128)[idx]
+    return {"y_rel_err": float(np.linalg.norm(yv - yo) / np.linalg.norm(yo)),
+            "alpha_rel_err": float(abs(complex(alpha) - ao) / abs(ao)), "sampled_outputs": int(len(idx)),
+            "tolerance": 1e-4 if dtype == "c64" else 1e-12}
+
+
+def copy_ceiling(torch, dev):
+    """Device-to-device copies: 1 GiB (the practical HBM streaming rate) and
+    8 MiB (a one-launch transfer of a pass's size, launch overhead included)."""
+    res = {}
+    for name, nbytes in (("copy_1GiB", 1 << 30), ("copy_8MiB", 8 << 20)):
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        ms = time_region(torch, lambda: dst.copy_(src), 5)
+        res[name] = {"ms": round(ms, 5), "GB_s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+        del src, dst
+    return res
 
 
 def cpu_fft_method(h, x, m, reps=3, single=False):
@@ -752,6 +793,35 @@ def shared_h_batch(data, hk, _lib, L, torch, dev):
                                   "alg_GB_s": round((2 * n + 5 * NB) * 8 * B / (ms_w * 1e-3) / 1e9, 1)}}
 
 
+def small_real_products(hk, torch, dev):
+    """The small real workload (m = 3, n = 64, d_H = 190, float64; y = H x^2 and
+    alpha = H x^3): one product per launch (a graph of 64 products replayed, each a
+    single resident workgroup: launch-bound) and a strided batch of 65536 instances
+    (one launch; bytes h + x + y + alpha per instance)."""
+    p = wl.small_real()
+    h = torch.from_numpy(p.h).to(dev)
+    x = torch.from_numpy(p.vectors[1]).to(dev)
+    hk.hankel_tvp(h, x, 3, True, True)
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr, stream=torch.cuda.Stream()):
+        for _ in range(64):
+            hk.hankel_tvp(h, x, 3, True, True)
+    torch.cuda.synchronize()
+    ms1 = time_region(torch, gr.replay, 4) / 64
+    B = 65536
+    g = np.random.Generator(np.random.PCG64(14016238 + 1000 + 1))
+    H = torch.from_numpy(g.uniform(-1, 1, (B, 190))).to(dev)
+    X = torch.from_numpy(g.uniform(-1, 1, (B, 64))).to(dev)
+    msb = time_region(torch, lambda: hk.hankel_tvp_strided_batched(H, X, 3, True, True), 5)
+    per = (190 + 64 + 64 + 1) * 8
+    res = {"single": {"TVP_s": round(1000 / ms1, 1), "us_per_product": round(ms1 * 1e3, 2)},
+           "strided_batch_65536": {"TVP_s": round(B / msb * 1000, 1), "ms": round(msb, 4),
+                                   "roofline": roof(per * B, msb, "k_rows resident (N = 256)")}}
+    del gr, H, X
+    return res
+
+
 def run_extras(args, data, hk, _lib, L, torch, dev):
     ex = {}
     ex["large_single_cpu_fft_method"] = cpu_fft_method(data["large"][0][2], data["large"][0][3], M)
@@ -770,6 +840,17 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
             hk.hankel_tvp(hs[k], xs[k], M, True, True)
         ms = time_region(torch, one, 50)
         ex["large_single_c128"] = {"TVP_s": round(1000 / ms, 1), "ms": round(ms, 4)}
+        torch.cuda._sleep(int(args.profile_delay_cycles))
+        hk.hk_profile_start()
+        for _ in range(64):
+            one()
+        prof = hk.hk_profile_stop()
+        nb128 = {"pass_a": (DH + NVEC + 2 * NFFT) * 16, "pass_b": 3 * NFFT * 16, "pass_d": (NFFT + NVEC) * 16}
+        per = {k: roof(nb128[k], prof[k][0] / prof[k][1], k) for k in nb128 if prof[k][1]}
+        dom = max(per, key=lambda k: prof[k][0])
+        ex["large_single_c128"]["roofline"] = dict(per[dom], per_kernel=per)
+        y0, a0 = hk.hankel_tvp(hs[0], xs[0], M, True, True)
+        ex["large_single_c128"]["parity_vs_oracle"] = golden_error(y0.cpu().numpy(), complex(a0.cpu()), "c128")
         del hs, xs
         log("c128", ex["large_single_c128"])
         # the same shape on real data (float, uniform[-1,1] entries): real-input transforms
@@ -801,6 +882,11 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
         ex["large_single_warm_c64"] = warm_products(data, hk, _lib, L, torch, dev)
         log("warm large products (h spectrum cached)", ex["large_single_warm_c64"])
 
+    ex["copy_ceiling"] = copy_ceiling(torch, dev)
+    log("copy ceiling", ex["copy_ceiling"])
+    ex["small_real_f64"] = small_real_products(hk, torch, dev)
+    log("small real (m=3, n=64, f64)", ex["small_real_f64"])
+
     # mixed batch: 4096 instances, one persistent launch vs per-pass launches vs plain loop
     mixed = data["mixed"]
     items = []
@@ -822,7 +908,8 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
         ms = time_region(torch, plan.execute, 10)
         plan.status()
         res[name] = {"TVP_s": round(len(items) / ms * 1000, 1), "ms_per_batch": round(ms, 3),
-                     "workspace_MB": round(plan.ws_bytes / 2**20, 1)}
+                     "workspace_MB": round(plan.ws_bytes / 2**20, 1),
+                     "roofline": roof(plan.pass_bytes(), ms, "k_batch" if name == "persistent" else "k_group")}
         plan.close()
     # graph plans (launches captured once, replayed): the grouped plan's four
     # streams then no longer depend on how the process's streams share the
@@ -834,8 +921,10 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
             plan = hk.Plan(items, flags=flags)
             ms = time_region(torch, plan.execute, 10)
             plan.status()
+            res[name] = {"TVP_s": round(len(items) / ms * 1000, 1), "ms_per_batch": round(ms, 3),
+                         "roofline": roof(plan.pass_bytes(), ms,
+                                          "k_batch" if name.startswith("persistent") else "k_group")}
             plan.close()
-            res[name] = {"TVP_s": round(len(items) / ms * 1000, 1), "ms_per_batch": round(ms, 3)}
 
     def plain_loop():
         for it_ in items:
@@ -895,15 +984,17 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
         key = "c64" if tdt == torch.complex64 else "c128"
         # pass-model bytes per instance (N = 2^18): forward d_H + 2n + 6N (pass A reads h
         # and x and writes two N-element buffers, B reads two and writes one, D reads one
-        # and writes n); adjoint 2 d_H + 3n + 10N (three operands in, grad_h and grad_x out)
+        # and writes n, plus alpha); adjoint 2 d_H + 3n + 10N (x, v, h in: pass A reads
+        # x, v and h and writes three buffers, B reads three and writes grad_h's and
+        # grad_x's row transforms, D reads both and writes grad_h and grad_x)
         nn, NN, es = X.shape[1], 1 << 18, (8 if tdt == torch.complex64 else 16)
         dh = 4 * (nn - 1) + 1
         fwd_b = (dh + 2 * nn + 6 * NN) * es * B
         bwd_b = (2 * dh + 3 * nn + 10 * NN) * es * B
         res4[key] = {"fwd_batched_TVP_s": round(B / ms_f * 1000, 1), "bwd_batched_per_s": round(B / ms_b * 1000, 1),
                      "fwd_plain_loop_TVP_s": round(B / ms_p * 1000, 1), "bwd_over_fwd_time": round(ms_b / ms_f, 3),
-                     "fwd_pass_model_GB_s": round(fwd_b / (ms_f * 1e-3) / 1e9, 1),
-                     "bwd_pass_model_GB_s": round(bwd_b / (ms_b * 1e-3) / 1e9, 1)}
+                     "fwd_roofline": roof(fwd_b, ms_f, "k_cols / k_rows (strided batch)"),
+                     "bwd_roofline": roof(bwd_b, ms_b, "k_cols / k_rows<PROG_BWD> (strided batch)")}
         del H, X, V, PHI
     ex["adjoint_batch"] = res4
     log("adjoint batch", res4)
@@ -962,7 +1053,14 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
         for b in range(Hs.shape[0]):
             hk.block_hankel_tvp(Hs[b], [Xs[b]] * 3, [512] * 3, [512] * 3, True, True)
     ms5p = time_region(torch, plain5, 1, warm=1)
-    ex["block_batch_c64"] = {"batched_TVP_s": round(64 / ms5 * 1000, 2), "plain_loop_TVP_s": round(64 / ms5p * 1000, 2)}
+    # pass model per tensor (grid 2048 x 2048, c64): pass A reads H (1534^2) and X (512^2)
+    # and writes 1534 + 512 storage columns of 2048; pass B reads them and writes the 512
+    # output columns pass D reads; pass D reads those and writes Y (512^2) and alpha
+    G, hr, nx = 2048, 1534, 512
+    blk_bytes = 8 * ((hr * hr + nx * nx + (hr + nx) * G) + ((hr + nx) * G + nx * G) + (nx * G + nx * nx + 1))
+    ex["block_batch_c64"] = {"batched_TVP_s": round(64 / ms5 * 1000, 2), "plain_loop_TVP_s": round(64 / ms5p * 1000, 2),
+                             "us_per_tensor": round(ms5 * 1e3 / 64, 2), "pass_model_MB_per_tensor": round(blk_bytes / 1e6, 1),
+                             "roofline": roof(64 * blk_bytes, ms5, "k_cols / k_rows (BHHB strided batch)")}
     log("block batch", ex["block_batch_c64"])
 
     # level-k products: the same BHHB tensors through the level-k call (one 1D transform of

@@ -279,6 +279,14 @@ hk_status_t hk_plan_status(hk_plan_t plan);
  * exercises the error path of hk_plan_status without any fault.  Not allowed
  * once the plan is captured in a graph. */
 hk_status_t hk_plan_set_wait_bound(hk_plan_t plan, uint32_t spins);
+/* Diagnostics (measurement): the bytes one hk_plan_execute reads and writes
+ * in HBM under the pass model of its kernels, summed over the instances.
+ * Resident instances (one workgroup per product) count their inputs and
+ * outputs once; three-pass instances count pass A (each operand read, the
+ * storage columns that can be nonzero written), pass B (those columns read,
+ * the output columns the last pass reads written) and pass D (those read
+ * back, the output slice written).  Host-only; *bytes receives the total. */
+hk_status_t hk_plan_pass_bytes(hk_plan_t plan, int64_t *bytes);
 hk_status_t hk_plan_destroy(hk_plan_t plan);
 
 /* One-shot convenience: plan (grouped launches), execute with the descriptor

@@ -513,6 +513,12 @@ class Plan:
     def status(self):
         check(lib().hk_plan_status(self._plan), "hk_plan_status")
 
+    def pass_bytes(self) -> int:
+        """Bytes one execute reads and writes under the pass model of its kernels."""
+        b = ctypes.c_int64(0)
+        check(lib().hk_plan_pass_bytes(self._plan, ctypes.byref(b)), "hk_plan_pass_bytes")
+        return int(b.value)
+
     def set_wait_bound(self, spins: int):
         """Persistent plans: barrier polling iterations before the error path (diagnostics)."""
         check(lib().hk_plan_set_wait_bound(self._plan, int(spins)), "hk_plan_set_wait_bound")

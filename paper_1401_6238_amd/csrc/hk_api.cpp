@@ -943,6 +943,8 @@ hk_status_t hk_plan_destroy(hk_plan_t plan) { return finish(plan_destroy(plan));
 
 hk_status_t hk_plan_set_wait_bound(hk_plan_t plan, uint32_t spins) { return finish(plan_set_wait_bound(plan, spins)); }
 
+hk_status_t hk_plan_pass_bytes(hk_plan_t plan, int64_t *bytes) { return finish(plan_pass_bytes(plan, bytes)); }
+
 hk_status_t hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs, int64_t count, size_t *bytes) {
   if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
   hk_plan_t plan = nullptr;

@@ -567,6 +567,15 @@ Status plan_set_wait_bound(hk_plan_t p, uint32_t spins) {
   return Status();
 }
 
+Status plan_pass_bytes(hk_plan_t p, int64_t *bytes) {
+  if (!p) return fail(HK_ERR_NULL_POINTER, "plan is NULL");
+  if (!bytes) return fail(HK_ERR_NULL_POINTER, "bytes is NULL");
+  int64_t tot = 0;
+  for (const Shape &sh : p->shapes) tot += pass_model_bytes(sh, p->dt);
+  *bytes = tot;
+  return Status();
+}
+
 Status plan_destroy(hk_plan_t p) {
   if (!p) return Status();
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);

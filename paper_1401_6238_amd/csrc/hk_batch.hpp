@@ -11,6 +11,7 @@ Status plan_execute(hk_plan_t plan, void *ws, size_t ws_bytes, hipStream_t st);
 Status plan_status(hk_plan_t plan);
 Status plan_destroy(hk_plan_t plan);
 Status plan_set_wait_bound(hk_plan_t plan, uint32_t spins);
+Status plan_pass_bytes(hk_plan_t plan, int64_t *bytes);
 // One-shot execution keeps the descriptor tables in the caller's workspace
 // (no plan-owned device memory).
 Status plan_set_oneshot(hk_plan_t plan);

@@ -238,6 +238,18 @@ __device__ __forceinline__ cx<T> *ws_partials(const Shape &sh, const PV &P) {
   return (cx<T> *)P.ws() + sh.nbuf * fft_len(sh);
 }
 
+// Storage columns of output `which` (0: y / grad_h, 1: grad_x) that the
+// output's column pass reads: the slice keeps positions < out_rows
+// (< out1_len), and position p sits in storage column p mod R, so columns at
+// or past that length (and past R) are never read.  Real outputs of
+// real-input transforms are stored in pairs.  The row pass stores only these
+// columns of its output rows.
+__device__ __forceinline__ int64_t out_cols_read(const Shape &sh, int which) {
+  const int64_t R = (int64_t)1 << sh.logR;
+  const int64_t len = which == 0 ? (sh.r2c ? (sh.out_rows + 1) / 2 : sh.out_rows) : sh.out1_len;
+  return len < R ? len : R;
+}
+
 // Chinese-remainder map of Z_N = Z_odd x Z_M: element (q, p) of the
 // sequence grid is entry n = p + M tau of the length-N vector, with
 // tau = ((q - p) M^{-1}) mod odd (then n = q mod odd and n = p mod M).
@@ -401,14 +413,21 @@ struct RowBody {
       const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
       const auto r = make_buf(ws_buf<T>(sh, P, sh.ops[which].buf), N * (int64_t)sizeof(cx<T>));
       const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
+      // columns the output's column pass never reads are not stored
+      const int keep = (int)out_cols_read(sh, which);
+      uint32_t off[EE];
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        const int pos = t + s * TPS;
+        off[s] = pos < keep ? rbase + (uint32_t)(pos * (int)sizeof(cx<T>)) : OOB_OFF;
+      }
       if (!sh.is_block) {
         // four-step twiddles W_N^{pos * row}, pos = t + s TPS (from twiddles())
 #pragma unroll
-        for (int s = 0; s < EE; ++s)
-          BufIO<T>::st(cmul(a[s], w[s]), r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
+        for (int s = 0; s < EE; ++s) BufIO<T>::st(cmul(a[s], w[s]), r, off[s]);
       } else {
 #pragma unroll
-        for (int s = 0; s < EE; ++s) BufIO<T>::st(a[s], r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
+        for (int s = 0; s < EE; ++s) BufIO<T>::st(a[s], r, off[s]);
       }
     }
   }
@@ -687,14 +706,21 @@ struct RowBody {
       const int64_t M = seq_len(sh);
       const auto r = make_buf(ws_buf<T, true>(sh, P, sh.ops[which].buf), ODD * M * (int64_t)sizeof(cx<T>));
       const uint32_t rbase = (uint32_t)((q * M + row * L) * (int64_t)sizeof(cx<T>));
+      // columns the output's column pass never reads are not stored
+      const int keep = (int)out_cols_read(sh, which);
+      uint32_t off[EE];
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        const int pos = t + s * TPS;
+        off[s] = pos < keep ? rbase + (uint32_t)(pos * (int)sizeof(cx<T>)) : OOB_OFF;
+      }
       if (!sh.is_block) {
         // four-step twiddles W_M^{pos * row}, pos = t + s TPS (from twiddles())
 #pragma unroll
-        for (int s = 0; s < EE; ++s)
-          BufIO<T>::st(cmul(a[s], w[s]), r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
+        for (int s = 0; s < EE; ++s) BufIO<T>::st(cmul(a[s], w[s]), r, off[s]);
       } else {
 #pragma unroll
-        for (int s = 0; s < EE; ++s) BufIO<T>::st(a[s], r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));
+        for (int s = 0; s < EE; ++s) BufIO<T>::st(a[s], r, off[s]);
       }
     }
   }

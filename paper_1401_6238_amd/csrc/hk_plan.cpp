@@ -380,6 +380,41 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
 
 size_t instance_ws_bytes(const Shape &sh, hk_dtype_t) { return sh.resident ? 0 : (size_t)sh.ws_bytes; }
 
+// Bytes the passes of one instance read and write as built: pass A reads each
+// operand and writes the storage columns that can be nonzero; pass B reads
+// those columns and writes the output columns the last pass reads; pass D
+// reads them back and writes the slice.  Resident instances move their
+// inputs and outputs once.
+int64_t pass_model_bytes(const Shape &sh, hk_dtype_t dt) {
+  const int64_t s = (int64_t)cplx_bytes(dt);
+  const int64_t es_out = sh.real_out ? s / 2 : s;
+  int64_t in = 0;
+  for (int o = 0; o < sh.nops; ++o) {
+    const OpDesc &od = sh.ops[o];
+    if (!(od.flags & OPF_SPEC)) in += od.len * od.cols * ((od.flags & OPF_REAL) ? s / 2 : s);
+  }
+  int64_t out = 0;
+  if (sh.want_y) out += sh.out_rows * sh.out_cols * es_out;
+  if (sh.want_alpha) out += es_out;
+  if (sh.prog == PROG_BWD && sh.want_out1) out += sh.out1_len * es_out;
+  if (sh.resident) return in + out;
+  const int64_t R = (int64_t)1 << sh.logR, C = (int64_t)1 << sh.logC, seq = (int64_t)sh.odd * C;
+  int64_t a_write = 0, b_read = 0;
+  for (int o = 0; o < sh.nops; ++o) {
+    const OpDesc &od = sh.ops[o];
+    if (od.flags & OPF_SPEC) {
+      b_read += R * seq * s;
+    } else {
+      a_write += od.ncol_nz * seq * s;
+      b_read += od.ncol_nz * seq * s;
+    }
+  }
+  int64_t b_write = 0;
+  if (sh.want_y) b_write += std::min<int64_t>(R, sh.r2c ? (sh.out_rows + 1) / 2 : sh.out_rows) * seq * s;
+  if (sh.prog == PROG_BWD && sh.want_out1) b_write += std::min<int64_t>(R, sh.out1_len) * seq * s;
+  return (in + a_write) + (b_read + b_write) + (b_write + out);
+}
+
 // ---------------------------------------------------------------------------
 // Schedules
 // ---------------------------------------------------------------------------

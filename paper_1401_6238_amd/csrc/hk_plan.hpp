@@ -102,6 +102,8 @@ bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc);
 
 // Workspace bytes per instance for a shape (0 for resident).
 size_t instance_ws_bytes(const Shape &sh, hk_dtype_t dt);
+// Bytes one instance's passes read and write (the pass model; diagnostics).
+int64_t pass_model_bytes(const Shape &sh, hk_dtype_t dt);
 
 // Plain path: enqueue the product(s) of one shape; instance i uses the
 // pointers p0 + i * str (byte strides).
