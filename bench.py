@@ -976,6 +976,12 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
             log(f"adjoint batch autotune ({tdt}) took {time.time() - t0:.1f}s")
         ms_f = time_region(torch, lambda: hk.hankel_tvp_strided_batched(H, X, 4, True, True), 5)
         ms_b = time_region(torch, lambda: hk.hankel_tvp_backward_strided_batched(H, X, 4, V, PHI), 5)
+        # the autograd pair: a forward that keeps x^ and an adjoint that reads it
+        ms_fs = time_region(torch, lambda: hk.hankel_tvp_save_spectrum(H, X, 4, True, True), 5)
+        _, _, XS = hk.hankel_tvp_save_spectrum(H, X, 4, True, True)
+        ms_bs = time_region(torch, lambda: hk.hankel_tvp_backward_spectral_strided_batched(H, XS, 4, X.shape[1], V,
+                                                                                          PHI), 5)
+        del XS
 
         def plain_fwd():
             for b in range(B):
@@ -994,7 +1000,15 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
         res4[key] = {"fwd_batched_TVP_s": round(B / ms_f * 1000, 1), "bwd_batched_per_s": round(B / ms_b * 1000, 1),
                      "fwd_plain_loop_TVP_s": round(B / ms_p * 1000, 1), "bwd_over_fwd_time": round(ms_b / ms_f, 3),
                      "fwd_roofline": roof(fwd_b, ms_f, "k_cols / k_rows (strided batch)"),
-                     "bwd_roofline": roof(bwd_b, ms_b, "k_cols / k_rows<PROG_BWD> (strided batch)")}
+                     "bwd_roofline": roof(bwd_b, ms_b, "k_cols / k_rows<PROG_BWD> (strided batch)"),
+                     # forward storing x^ (+N writes) and the adjoint reading it (x's column pass
+                     # and row transform skipped: 2 d_H + 2n + 9N)
+                     "autograd_pair": {"fwd_save_spectrum_ms": round(ms_fs, 4), "bwd_from_spectrum_ms": round(ms_bs, 4),
+                                       "bwd_over_fwd_time": round(ms_bs / ms_fs, 3),
+                                       "bwd_over_plain_fwd_time": round(ms_bs / ms_f, 3),
+                                       "fwd_roofline": roof(fwd_b + NN * es * B, ms_fs, "k_rows<PROG_FWD_SPEC>"),
+                                       "bwd_roofline": roof((2 * dh + 2 * nn + 9 * NN) * es * B, ms_bs,
+                                                            "k_rows<PROG_BWD_SPEC>")}}
         del H, X, V, PHI
     ex["adjoint_batch"] = res4
     log("adjoint batch", res4)

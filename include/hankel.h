@@ -378,6 +378,32 @@ hk_status_t hankel_tvp_backward(hk_dtype_t dt, const void *h, int m, int64_t n, 
                                 const void *grad_y, const void *grad_alpha, void *grad_x,
                                 void *grad_h, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Forward products that keep x^ for the adjoint: the strided batch of
+ * hankel_tvp_strided_batched (instance b: h + b*h_stride, x + b*x_stride,
+ * y + b*y_stride, alpha + b; y or alpha may be NULL) that also writes each
+ * instance's x^ = fft(pad_N x), in the row order of hankel_spectrum, to
+ * x_spec + b*spec_stride (complex elements of x's precision; spec_stride >= N,
+ * N from hankel_spectrum_layout).  The row pass stores x^ right after
+ * transforming x, so the saved spectrum costs N element writes and no extra
+ * transform.  Complex dtypes, d_H > 4096 (the spectral layout, power-of-two N). */
+hk_status_t hankel_tvp_save_spectrum_workspace_size(hk_dtype_t dt, int m, int64_t n, int64_t batch,
+                                                    size_t *bytes);
+hk_status_t hankel_tvp_save_spectrum(hk_dtype_t dt, const void *h, int64_t h_stride, int m, int64_t n,
+                                     const void *x, int64_t x_stride, void *y, int64_t y_stride,
+                                     void *alpha, void *x_spec, int64_t spec_stride, int64_t batch,
+                                     void *ws, size_t ws_bytes, hipStream_t stream);
+/* Strided batch of hankel_tvp_backward_spectral: instance b reads h + b*h_stride,
+ * x_spec + b*spec_stride (as stored by hankel_tvp_save_spectrum),
+ * grad_y + b*gy_stride, grad_alpha + b, and writes grad_x + b*gx_stride,
+ * grad_h + b*gh_stride (NULL pointers as in hankel_tvp_backward). */
+hk_status_t hankel_tvp_backward_spectral_strided_batched_workspace_size(hk_dtype_t dt, int m, int64_t n,
+                                                                        int64_t batch, size_t *bytes);
+hk_status_t hankel_tvp_backward_spectral_strided_batched(
+    hk_dtype_t dt, const void *h, int64_t h_stride, int m, int64_t n, const void *x_spec,
+    int64_t spec_stride, const void *grad_y, int64_t gy_stride, const void *grad_alpha,
+    void *grad_x, int64_t gx_stride, void *grad_h, int64_t gh_stride, int64_t batch, void *ws,
+    size_t ws_bytes, hipStream_t stream);
+
 /* Strided batch of equal-vector products of one shape (m, n): instance b uses
  * h + b*h_stride, x + b*x_stride, y + b*y_stride, alpha + b (elements).
  * y or alpha may be NULL.  One launch per pass covers the whole batch. */

@@ -376,6 +376,66 @@ def hankel_tvp_backward_spectral(h: torch.Tensor, x_spec: torch.Tensor, m: int, 
     return gx, gh
 
 
+def hankel_tvp_save_spectrum(h: torch.Tensor, x: torch.Tensor, m: int, want_y: bool = True,
+                             want_alpha: bool = False):
+    """Equal-vector products that also return x^ for the adjoint: h (d_H) and x
+    (n) for one product, or h (B, d_H) and x (B, n) for a batch.  Returns
+    (y, alpha, x_spec) with x_spec (N) or (B, N) in the row order of
+    hankel_spectrum."""
+    _dev(x)
+    single = x.dim() == 1
+    X = x.reshape(1, -1) if single else x
+    B, n = X.shape
+    dt = _dtype(x)
+    d_h = m * (n - 1) + 1
+    _arg(h, "h", B * d_h, x.dtype, x.device)
+    if not single and h.dim() != 2:
+        raise ValueError("h must be (B, d_H)")
+    n_fft, _ = hankel_spectrum_layout(x.dtype, m, [n] * m)
+    y = torch.empty(B, n, dtype=x.dtype, device=x.device) if want_y else None
+    alpha = torch.empty(B, dtype=x.dtype, device=x.device) if want_alpha else None
+    spec = torch.empty(B, n_fft, dtype=_spec_dtype(x.dtype), device=x.device)
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_tvp_save_spectrum_workspace_size(dt, m, n, B, ctypes.byref(nb)),
+          "hankel_tvp_save_spectrum_workspace_size")
+    ws, wsb = _workspace(nb.value, x.device)
+    check(lib().hankel_tvp_save_spectrum(dt, _ptr(h), d_h, m, n, _ptr(X), n, _ptr(y), n, _ptr(alpha), _ptr(spec),
+                                         n_fft, B, _ptr(ws), wsb, _stream(x.device)), "hankel_tvp_save_spectrum")
+    if single:
+        return (None if y is None else y[0]), (None if alpha is None else alpha[0]), spec[0]
+    return y, alpha, spec
+
+
+def hankel_tvp_backward_spectral_strided_batched(h: torch.Tensor, x_spec: torch.Tensor, m: int, n: int,
+                                                 grad_y: Optional[torch.Tensor], grad_alpha: Optional[torch.Tensor],
+                                                 want_grad_x: bool = True, want_grad_h: bool = True):
+    """J^H of a strided batch with x given by its stored spectra: h (B, d_H),
+    x_spec (B, N) from hankel_tvp_save_spectrum, grad_y (B, n), grad_alpha (B,).
+    Returns (grad_x (B, n), grad_h (B, d_H))."""
+    _dev(h)
+    if h.dim() != 2:
+        raise ValueError("h must be (B, d_H)")
+    B = h.shape[0]
+    dt = _dtype(h)
+    d_h = m * (n - 1) + 1
+    _arg(h, "h", B * d_h)
+    n_fft, _ = hankel_spectrum_layout(h.dtype, m, [n] * m)
+    _arg(x_spec, "x_spec", B * n_fft, _spec_dtype(h.dtype), h.device)
+    gx = torch.empty(B, n, dtype=h.dtype, device=h.device) if want_grad_x else None
+    gh = torch.empty(B, d_h, dtype=h.dtype, device=h.device) if want_grad_h else None
+    ga = _cotangent(grad_alpha, "grad_alpha", B, h.dtype, h.device)
+    gy = _cotangent(grad_y, "grad_y", B * n, h.dtype, h.device)
+    nb = ctypes.c_size_t(0)
+    check(lib().hankel_tvp_backward_spectral_strided_batched_workspace_size(dt, m, n, B, ctypes.byref(nb)),
+          "hankel_tvp_backward_spectral_strided_batched_workspace_size")
+    ws, wsb = _workspace(nb.value, h.device)
+    check(lib().hankel_tvp_backward_spectral_strided_batched(dt, _ptr(h), d_h, m, n, _ptr(x_spec), n_fft, _ptr(gy), n,
+                                                             _ptr(ga), _ptr(gx), n, _ptr(gh), d_h, B, _ptr(ws), wsb,
+                                                             _stream(h.device)),
+          "hankel_tvp_backward_spectral_strided_batched")
+    return gx, gh
+
+
 def hankel_tvp_strided_batched(h: torch.Tensor, x: torch.Tensor, m: int, want_y: bool = True,
                                want_alpha: bool = False):
     """Batch of equal-vector products: h (B, d_H), x (B, n).  Returns (y (B, n), alpha (B,))."""

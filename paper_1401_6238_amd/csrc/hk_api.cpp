@@ -383,8 +383,14 @@ static Status spectral_setup(const Problem &p, Layout *lay, Sched *sc, int64_t b
     return fail(HK_ERR_NOT_SUPPORTED, "spectra need the three-pass layout: d_H above 4096");
   Sched sch;
   const int logM = lay->logR + lay->logC;
-  if (sched_lookup(p.dt, p.prog, 0, lay->lclass(), logM, -1, batch, &sch) && sch.split == split &&
-      sched_valid(p.dt, *lay, sch))
+  // the cached schedule of this shape, moved to the spectral split when it was
+  // tuned for another (its row and column parameters still fit the batch)
+  bool have = sched_lookup(p.dt, p.prog, 0, lay->lclass(), logM, -1, batch, &sch);
+  if (have) {
+    sch.split = split;
+    have = sched_valid(p.dt, *lay, sch);
+  }
+  if (have)
     *sc = sch;
   else {
     *sc = default_sched(p.dt, *lay, p.prog, batch);
@@ -434,7 +440,7 @@ static Status spectrum_prepare(hk_dtype_t dt, int m, const int64_t *dims, int wh
   b.ws_bytes = (int64_t)(((((size_t)1 << (lay.logR + lay.logC)) + (size_t)b.partials) * eb + 255) & ~(size_t)255);
   memset(&bp, 0, sizeof(bp));
   bp.op[0] = src;
-  bp.y = spec;
+  bp.out1 = spec;
   *sh = b;
   *P = bp;
   return Status();
@@ -621,11 +627,11 @@ hk_status_t hankel_tvp_spectral_strided_batched(hk_dtype_t dt, const void *h_spe
 // Adjoint of the equal-vector products with x given by its stored spectrum
 // (the forward's x^, from hankel_spectrum on the same shape): the column
 // pass of x and its row transform are skipped.
-static Status backward_spectral_prepare(const Problem &p, Shape *sh, Ptrs *P, Sched *sc) {
+static Status backward_spectral_prepare(const Problem &p, Shape *sh, Ptrs *P, Sched *sc, int64_t batch = 1) {
   Status s = validate_backward(p);
   if (!s.ok()) return s;
   Layout lay;
-  s = spectral_setup(p, &lay, sc);
+  s = spectral_setup(p, &lay, sc, batch);
   if (!s.ok()) return s;
   return build_shape(p, lay, *sc, sh, P, nullptr);
 }
@@ -663,6 +669,132 @@ hk_status_t hankel_tvp_backward_spectral(hk_dtype_t dt, const void *h, int m, in
   Strides str;
   memset(&str, 0, sizeof(str));
   return finish(launch_shape(dt, sh, sc, P, str, 1, stream));
+}
+
+// Forward equal-vector products that also store x^ = fft(pad_N x) in the row
+// order of hankel_spectrum (the shape's spectral layout), to be reused by the
+// adjoint (hankel_tvp_backward_spectral*): the row pass writes the spectrum
+// row of x right after transforming it.
+static Status save_spectrum_prepare(const Problem &p, int64_t batch, Shape *sh, Ptrs *P, Sched *sc) {
+  Status s = validate_forward(p);
+  if (!s.ok()) return s;
+  if (!is_complex(p.dt)) return fail(HK_ERR_NOT_SUPPORTED, "stored spectra for the adjoint need a complex dtype");
+  Layout lay;
+  s = spectral_setup(p, &lay, sc, batch);
+  if (!s.ok()) return s;
+  s = build_shape(p, lay, *sc, sh, P, nullptr);
+  if (!s.ok()) return s;
+  int nx = 0;
+  for (int o = 0; o < sh->nops; ++o)
+    if (sh->ops[o].role == ROLE_X) {
+      sh->ops[o].flags |= OPF_STORE_SPEC;
+      ++nx;
+    }
+  if (nx != 1 || sh->ops[0].role != ROLE_H) return fail(HK_ERR_NOT_SUPPORTED, "unexpected operand layout");
+  return Status();
+}
+
+hk_status_t hankel_tvp_save_spectrum_workspace_size(hk_dtype_t dt, int m, int64_t n, int64_t batch, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  if (batch < 0) return finish(fail(HK_ERR_INVALID_VALUE, "batch must be >= 0"));
+  Problem p = tvp_problem(dt, (const void *)256, m, n, (const void *)256, (void *)256, (void *)256);
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  Status s = save_spectrum_prepare(p, std::max<int64_t>(1, batch), &sh, &P, &sc);
+  if (!s.ok()) return finish(s);
+  *bytes = instance_ws_bytes(sh, dt) * (size_t)batch;
+  return finish(Status());
+}
+
+hk_status_t hankel_tvp_save_spectrum(hk_dtype_t dt, const void *h, int64_t h_stride, int m, int64_t n, const void *x,
+                                     int64_t x_stride, void *y, int64_t y_stride, void *alpha, void *x_spec,
+                                     int64_t spec_stride, int64_t batch, void *ws, size_t ws_bytes,
+                                     hipStream_t stream) {
+  if (batch < 0) return finish(fail(HK_ERR_INVALID_VALUE, "batch must be >= 0"));
+  if (!x_spec) return finish(fail(HK_ERR_NULL_POINTER, "x_spec is NULL"));
+  if (!aligned(x_spec, cplx_bytes(dt))) return finish(fail(HK_ERR_MISALIGNED, "x_spec not aligned to its element size"));
+  Problem p = tvp_problem(dt, h, m, n, x, y, alpha);
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  Status s = save_spectrum_prepare(p, std::max<int64_t>(1, batch), &sh, &P, &sc);
+  if (!s.ok()) return finish(s);
+  const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+  if (batch > 1 && spec_stride < N) return finish(fail(HK_ERR_INVALID_VALUE, "spec_stride is below the spectrum length"));
+  if (batch == 0) return finish(Status());
+  const size_t per = instance_ws_bytes(sh, dt);
+  s = check_ws(per * (size_t)batch, ws, ws_bytes);
+  if (!s.ok()) return finish(s);
+  s = ensure_device();
+  if (!s.ok()) return finish(s);
+  const int64_t eb = (int64_t)elem_bytes(dt);
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  str.op[0] = h_stride * eb;  // operands: H, X
+  str.op[1] = x_stride * eb;
+  str.y = y_stride * eb;
+  str.alpha = eb;
+  str.out1 = spec_stride * (int64_t)cplx_bytes(dt);
+  str.ws = (int64_t)per;
+  P.out1 = x_spec;
+  P.ws = ws;
+  return finish(launch_shape(dt, sh, sc, P, str, batch, stream));
+}
+
+hk_status_t hankel_tvp_backward_spectral_strided_batched_workspace_size(hk_dtype_t dt, int m, int64_t n, int64_t batch,
+                                                                        size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  if (batch < 0) return finish(fail(HK_ERR_INVALID_VALUE, "batch must be >= 0"));
+  Problem p = bwd_problem(dt, (const void *)256, m, n, (const void *)256, (const void *)256, (const void *)256,
+                          (void *)256, (void *)256);
+  p.spec_mask = 2u;
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  Status s = backward_spectral_prepare(p, &sh, &P, &sc, std::max<int64_t>(1, batch));
+  if (!s.ok()) return finish(s);
+  *bytes = instance_ws_bytes(sh, dt) * (size_t)batch;
+  return finish(Status());
+}
+
+hk_status_t hankel_tvp_backward_spectral_strided_batched(hk_dtype_t dt, const void *h, int64_t h_stride, int m,
+                                                         int64_t n, const void *x_spec, int64_t spec_stride,
+                                                         const void *grad_y, int64_t gy_stride, const void *grad_alpha,
+                                                         void *grad_x, int64_t gx_stride, void *grad_h,
+                                                         int64_t gh_stride, int64_t batch, void *ws, size_t ws_bytes,
+                                                         hipStream_t stream) {
+  if (batch < 0) return finish(fail(HK_ERR_INVALID_VALUE, "batch must be >= 0"));
+  Problem p = bwd_problem(dt, h, m, n, x_spec, grad_y, grad_alpha, grad_x, grad_h);
+  p.spec_mask = 2u;
+  Shape sh;
+  Ptrs P;
+  Sched sc;
+  Status s = backward_spectral_prepare(p, &sh, &P, &sc, std::max<int64_t>(1, batch));
+  if (!s.ok()) return finish(s);
+  if (!(sh.ops[0].flags & OPF_SPEC)) return finish(fail(HK_ERR_NOT_SUPPORTED, "unexpected operand layout"));
+  const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+  if (batch > 1 && spec_stride < N) return finish(fail(HK_ERR_INVALID_VALUE, "spec_stride is below the spectrum length"));
+  if (batch == 0) return finish(Status());
+  const size_t per = instance_ws_bytes(sh, dt);
+  s = check_ws(per * (size_t)batch, ws, ws_bytes);
+  if (!s.ok()) return finish(s);
+  s = ensure_device();
+  if (!s.ok()) return finish(s);
+  const int64_t eb = (int64_t)elem_bytes(dt);
+  // operand order of the adjoint shape: X (stored spectrum), [V], [H]
+  Strides str;
+  memset(&str, 0, sizeof(str));
+  int o = 0;
+  str.op[o++] = spec_stride * (int64_t)cplx_bytes(dt);
+  if (grad_y) str.op[o++] = gy_stride * eb;
+  if (grad_x) str.op[o++] = h_stride * eb;
+  str.y = gh_stride * eb;
+  str.out1 = gx_stride * eb;
+  str.phi = eb;
+  str.ws = (int64_t)per;
+  P.ws = ws;
+  return finish(launch_shape(dt, sh, sc, P, str, batch, stream));
 }
 
 hk_status_t block_hankel_tvp_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims, const int64_t *block_dims,
@@ -1145,12 +1277,12 @@ static Status tm_spectral_run(const TmSpectral &T, hk_dtype_t dt, const void *h,
   if (s.ok()) s = spectrum_prepare(dt, m, dims, 1, U, uspec, &sh, &P, &sc);
   if (s.ok()) {
     str.op[0] = n * (int64_t)eb;
-    str.y = N * (int64_t)cb;
+    str.out1 = N * (int64_t)cb;
     str.ws = (int64_t)T.inst_ws;
     for (int64_t c0 = 0; c0 < R && s.ok(); c0 += T.batch) {
       Ptrs Pc = P;
       Pc.op[0] = (const char *)U + (size_t)c0 * n * eb;
-      Pc.y = uspec + (size_t)c0 * N * cb;
+      Pc.out1 = uspec + (size_t)c0 * N * cb;
       Pc.ws = inst;
       s = launch_shape(dt, sh, sc, Pc, str, std::min(T.batch, R - c0), st);
     }

@@ -383,13 +383,13 @@ struct RowBody {
     }
   }
 
-  // Spectrum row `row` (natural order within the row) to y: element k_c of
-  // row k_r is bin k_r + C k_c of the length-N transform.
+  // Spectrum row `row` (natural order within the row) to out1: element k_c
+  // of row k_r is bin k_r + C k_c of the length-N transform.
   static __device__ __forceinline__ void store_spec(const cx<T> (&a)[EE], const Shape &sh, const PV &P, int64_t row,
                                                     bool valid_row, int t) {
     if (!valid_row) return;
     const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
-    const auto r = make_buf(P.y(), N * (int64_t)sizeof(cx<T>));
+    const auto r = make_buf(P.out1(), N * (int64_t)sizeof(cx<T>));
     const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
 #pragma unroll
     for (int s = 0; s < EE; ++s) BufIO<T>::st(a[s], r, rbase + (uint32_t)((t + s * TPS) * (int)sizeof(cx<T>)));

@@ -39,7 +39,7 @@ enum OpFlag : int32_t {
   // Multipass, power-of-two 1D rows only:
   OPF_SPEC = 8,         // the operand pointer holds the operand's spectrum in row order
                         // (no column pass; the row pass loads it as transformed)
-  OPF_STORE_SPEC = 16,  // the row pass stores this operand's spectrum, in row order, to y
+  OPF_STORE_SPEC = 16,  // the row pass stores this operand's spectrum, in row order, to out1
 };
 
 enum Prog : int32_t { PROG_FWD = 0, PROG_BWD = 1 };

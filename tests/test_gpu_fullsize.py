@@ -233,6 +233,33 @@ def test_adjoint_batch_forward_and_adjoint(dtype):
         _scalar_invariant(Xh[b], Gh[b], Fh[b], dtype)
 
 
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_adjoint_batch_autograd(dtype):
+    """The batch of 256 (m=4, n=2^16) through the autograd Function, whose
+    forward keeps x^ and whose backward reuses it: g, f and the gradients of
+    the twelve sampled instances against the oracle's values."""
+    import paper_1401_6238_amd as hk
+    g = golden("adjoint_batch")
+    tag = "c128" if dtype == torch.complex128 else "c64"
+    print_case(test="adjoint_batch_autograd", dtype=tag)
+    insts = [int(i) for i in g["adjoint_instances"]]
+    data = _instances("adjoint", 256)
+    H = torch.stack([to_dev(d["h"], dtype) for d in data]).requires_grad_(True)
+    X = torch.stack([to_dev(d["x"], dtype) for d in data]).requires_grad_(True)
+    V = torch.stack([to_dev(d["v"], dtype) for d in data])
+    PHI = to_dev(np.array([d["phi"] for d in data]), dtype)
+    gy, f = hk.hankel_tvp_autograd(H, X, 4)
+    gH, gX = torch.autograd.grad([gy, f], [H, X], [V, PHI])
+    torch.cuda.synchronize()
+    tol = TOL[dtype]
+    for i in insts:
+        ix, ih = g[f"adjoint_{i}_idx_x"], g[f"adjoint_{i}_idx_h"]
+        assert rel(host(gy[i].detach())[ix], g[f"adjoint_{i}_{tag}_g"]) <= tol
+        check_alpha(complex(host(f[i:i + 1].detach())[0]), complex(g[f"adjoint_{i}_{tag}_f"][0]), dtype, i)
+        assert rel(host(gX[i])[ix], g[f"adjoint_{i}_{tag}_gx"]) <= tol
+        assert rel(host(gH[i])[ih], g[f"adjoint_{i}_{tag}_gh"]) <= tol
+
+
 def test_block_batch():
     """64 distinct BHHB tensors (m=3, 512 blocks of 512, 2048^2 grid): sampled
     outputs of six tensors against the oracle, the scalar of every tensor
