@@ -52,13 +52,16 @@ def _lib():
         lib.hko_block_tvp_i64.argtypes = [ctypes.c_int, P, P, P, P, P, P]
         lib.hko_block_tvp_sampled.argtypes = [ctypes.c_int, P, P, P, P, P, I64, P, P]
         lib.hko_tvp_backward.argtypes = [ctypes.c_int, I64, P, P, P, P, P, P]
+        lib.hko_mode_backward.argtypes = [ctypes.c_int, P, P, P, P, P, P, P]
+        lib.hko_block_backward.argtypes = [ctypes.c_int, P, P, P, P, P, P, P, P]
         lib.hko_dft_sampled.argtypes = [ctypes.c_int, P, I64, I64, P, I64, P]
         lib.hko_tvp_comp.argtypes = [ctypes.c_int, P, P, P, P, P]
         lib.hko_max_threads.argtypes = []
         lib.hko_set_threads.argtypes = [ctypes.c_int]
         for f in (lib.hko_conv_range, lib.hko_conv, lib.hko_corr, lib.hko_tvp, lib.hko_tvp_sampled,
                   lib.hko_tvp_i64, lib.hko_block_tvp, lib.hko_block_tvp_i64, lib.hko_block_tvp_sampled,
-                  lib.hko_tvp_backward, lib.hko_dft_sampled, lib.hko_tvp_comp,
+                  lib.hko_tvp_backward, lib.hko_mode_backward, lib.hko_block_backward, lib.hko_dft_sampled,
+                  lib.hko_tvp_comp,
                   lib.hko_max_threads, lib.hko_set_threads):
             f.restype = ctypes.c_int
         _lib_handle = lib
@@ -275,6 +278,46 @@ def tvp_backward(m: int, h, x, v=None, phi=None, want_grad_x: bool = True, want_
     _check(_lib().hko_tvp_backward(m, n, _ptr(h), _ptr(x), _ptr(v), _ptr(ph), _ptr(gx), _ptr(gh)),
            "tvp_backward")
     return gx, gh
+
+
+def mode_backward(m: int, dims, h, vectors, v=None, phi=None, want=None, want_grad_h: bool = True):
+    """J^H of y = H x_2 ... x_m (cotangent v) and alpha = H x_1 ... x_m (cotangent
+    phi) with distinct vectors (hko_mode_backward).  vectors[0] is needed only
+    with phi.  want[p] selects grad_{x_p} (default: all).  Returns
+    (list of grad_{x_p} or None, grad_h or None)."""
+    dims = np.ascontiguousarray(np.asarray(dims, np.int64))
+    h = _c128(h)
+    vecs = [None if a is None else _c128(a) for a in vectors]
+    want = [True] * m if want is None else list(want)
+    v = None if v is None else _c128(v)
+    ph = None if phi is None else np.array([phi], np.complex128)
+    gv = [np.empty(int(dims[p]), np.complex128) if want[p] else None for p in range(m)]
+    gh = np.empty(len(h), np.complex128) if want_grad_h else None
+    keep = _vec_ptrs(vecs)
+    gkeep = _vec_ptrs(gv)
+    _check(_lib().hko_mode_backward(m, _ptr(dims), _ptr(h), keep, _ptr(v), _ptr(ph), gkeep, _ptr(gh)),
+           "mode_backward")
+    return gv, gh
+
+
+def block_backward(m: int, dims, block_dims, H, vectors, v=None, phi=None, want=None, want_grad_h: bool = True):
+    """J^H of the BHHB product y = H x_2 ... x_m (vec(Y), cotangent v of n_1 N_1
+    values) and alpha = H x_1 ... x_m (cotangent phi), distinct vectors
+    (hko_block_backward).  Returns (list of grad vec(X_p) or None, grad vec(H) or None)."""
+    dims = np.ascontiguousarray(np.asarray(dims, np.int64))
+    bd = np.ascontiguousarray(np.asarray(block_dims, np.int64))
+    H = _c128(H)
+    vecs = [None if a is None else _c128(a) for a in vectors]
+    want = [True] * m if want is None else list(want)
+    v = None if v is None else _c128(v)
+    ph = None if phi is None else np.array([phi], np.complex128)
+    gv = [np.empty(int(dims[p] * bd[p]), np.complex128) if want[p] else None for p in range(m)]
+    gh = np.empty(len(H), np.complex128) if want_grad_h else None
+    keep = _vec_ptrs(vecs)
+    gkeep = _vec_ptrs(gv)
+    _check(_lib().hko_block_backward(m, _ptr(dims), _ptr(bd), _ptr(H), keep, _ptr(v), _ptr(ph), gkeep, _ptr(gh)),
+           "block_backward")
+    return gv, gh
 
 
 def spectrum(a, N: int, idx=None, inverse: bool = False) -> np.ndarray:

@@ -536,6 +536,191 @@ int hko_tvp_backward(int m, int64_t n, const hkc *h, const hkc *x, const hkc *v,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Gradients of the general products with distinct vectors (the paper does   */
+/* not differentiate; complex autograd's convention, J^H applied to the      */
+/* cotangents of these holomorphic maps):                                    */
+/*   y = H x_2 ... x_m (cotangent v, dims[0] values),                        */
+/*   alpha = H x_1 x_2 ... x_m (cotangent phi).                              */
+/* y is linear in each x_p; its coefficient of x_p[l] multiplied by conj(v)  */
+/* and summed over the free index is the mode-p-free product with conj(v)    */
+/* in mode 1, and alpha's is the same with x_1 in mode 1.  With             */
+/* c = conj(v) + conj(phi) x_1 (both linear in mode 1):                      */
+/*   grad_{x_p}[l] = conj( sum_k h_{l+k} (c * x_q, q != 1, p)_k ),  p >= 2   */
+/*   grad_{x_1}[l] = phi conj( sum_k h_{l+k} (x_2 * ... * x_m)_k )          */
+/*   grad_h[s]     = conj( (c * x_2 * ... * x_m)_s ),   s < d_H              */
+/* (* = linear convolution).  v or phi may be NULL (zero cotangent); x_1 is  */
+/* read only with phi; grad_vectors[p] or grad_h may be NULL.                */
+/* ------------------------------------------------------------------------ */
+static hkc *cotangent_mode1(int64_t n1, const hkc *v, const hkc *phi, const hkc *x1) {
+    hkc *c = (hkc *)malloc(sizeof(hkc) * (size_t)n1);
+    if (!c) return NULL;
+    for (int64_t i = 0; i < n1; ++i) {
+        hkc t = { 0.0, 0.0 };
+        if (v) t = cconj(v[i]);
+        if (phi) t = cadd(t, cmul(cconj(*phi), x1[i]));
+        c[i] = t;
+    }
+    return c;
+}
+
+int hko_mode_backward(int m, const int64_t *dims, const hkc *h, const hkc *const *vectors, const hkc *v,
+                      const hkc *phi, hkc *const *grad_vectors, hkc *grad_h) {
+    if (check_dims(m, dims)) return -1;
+    if (phi && !vectors[0]) return -1;
+    int64_t dh = 1 - m;
+    for (int p = 0; p < m; ++p) dh += dims[p];
+    hkc *c = cotangent_mode1(dims[0], v, phi, vectors[0]);
+    const hkc **vecs = (const hkc **)malloc(sizeof(hkc *) * (size_t)m);
+    int64_t *d2 = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    if (!c || !vecs || !d2) { free(c); free(vecs); free(d2); return -2; }
+    int rc = 0;
+    if (grad_h) {
+        /* c * x_2 * ... * x_m, length d_H */
+        vecs[0] = c;
+        d2[0] = dims[0];
+        for (int q = 1; q < m; ++q) { vecs[q] = vectors[q]; d2[q] = dims[q]; }
+        int64_t lu = 0;
+        hkc *u = conv_chain(0, m, d2, vecs, &lu);
+        if (!u) rc = -2;
+        else {
+            for (int64_t s = 0; s < dh; ++s) grad_h[s] = cconj(u[s]);
+            free(u);
+        }
+    }
+    for (int p = 1; p < m && rc == 0; ++p) {
+        if (!grad_vectors[p]) continue;
+        /* c and the vectors of the modes other than 1 and p */
+        int k = 0;
+        vecs[k] = c;
+        d2[k++] = dims[0];
+        for (int q = 1; q < m; ++q)
+            if (q != p) { vecs[k] = vectors[q]; d2[k++] = dims[q]; }
+        int64_t lw = 0;
+        hkc *w = conv_chain(0, k, d2, vecs, &lw); /* length d_H - n_p + 1 */
+        if (!w) { rc = -2; break; }
+        rc = hko_corr(h, dh, w, lw, dims[p], grad_vectors[p]);
+        for (int64_t l = 0; l < dims[p] && rc == 0; ++l) grad_vectors[p][l] = cconj(grad_vectors[p][l]);
+        free(w);
+    }
+    if (rc == 0 && grad_vectors[0]) {
+        if (!phi) {
+            for (int64_t l = 0; l < dims[0]; ++l) { grad_vectors[0][l].re = 0.0; grad_vectors[0][l].im = 0.0; }
+        } else {
+            int64_t lw = 0;
+            hkc *w = conv_chain(1, m, dims, vectors, &lw); /* x_2 * ... * x_m */
+            if (!w) rc = -2;
+            else {
+                rc = hko_corr(h, dh, w, lw, dims[0], grad_vectors[0]);
+                for (int64_t l = 0; l < dims[0] && rc == 0; ++l)
+                    grad_vectors[0][l] = cmul(*phi, cconj(grad_vectors[0][l]));
+                free(w);
+            }
+        }
+    }
+    free(c); free(vecs); free(d2);
+    return rc;
+}
+
+/* The same for the BHHB product (Section 3's 2-level form; matrices        */
+/* column-major, X_p is n_p x N_p, H is (sum n - m + 1) x (sum N - m + 1)):  */
+/* 2D linear convolutions and Y-style 2D correlations with H in place of    */
+/* the 1D ones:                                                              */
+/*   grad_{X_p}[i,j] = conj( sum_{k,l} H[i+k, j+l] (C (*) X_q, q != 1, p)[k,l] ), */
+/*   grad_{X_1}[i,j] = phi conj( Y[i,j] ),  grad_H = conj( C (*) X_2 (*) ... (*) X_m ), */
+/* C = conj(V) + conj(phi) X_1.                                              */
+static hkc *conv2_chain(int k, const hkc *const *mats, const int64_t *rows, const int64_t *cols,
+                        int64_t *r_out, int64_t *c_out) {
+    int64_t wr = 1, wc = 1;
+    hkc *w = (hkc *)malloc(sizeof(hkc));
+    if (!w) return NULL;
+    w[0].re = 1.0; w[0].im = 0.0;
+    for (int p = 0; p < k; ++p) {
+        hkc *nw = conv2(w, wr, wc, mats[p], rows[p], cols[p]);
+        free(w);
+        if (!nw) return NULL;
+        w = nw;
+        wr += rows[p] - 1;
+        wc += cols[p] - 1;
+    }
+    *r_out = wr;
+    *c_out = wc;
+    return w;
+}
+
+/* out[i + outr*j] = conj( sum_{k,l} H[(i+k) + hr (j+l)] W[k + wr l] ) for i < outr, j < outc. */
+static void corr2_conj(const hkc *H, int64_t hr, const hkc *W, int64_t wr, int64_t wc, int64_t outr,
+                       int64_t outc, hkc *out) {
+#pragma omp parallel for collapse(2) schedule(dynamic, 16)
+    for (int64_t j = 0; j < outc; ++j)
+        for (int64_t i = 0; i < outr; ++i) {
+            hkc total = { 0.0, 0.0 }, part = { 0.0, 0.0 };
+            int cnt = 0;
+            for (int64_t l = 0; l < wc; ++l)
+                for (int64_t k = 0; k < wr; ++k) {
+                    part = cadd(part, cmul(H[(i + k) + hr * (j + l)], W[k + wr * l]));
+                    if (++cnt == BLOCK) { total = cadd(total, part); part.re = part.im = 0.0; cnt = 0; }
+                }
+            out[i + outr * j] = cconj(cadd(total, part));
+        }
+}
+
+int hko_block_backward(int m, const int64_t *n, const int64_t *nblk, const hkc *H, const hkc *const *vectors,
+                       const hkc *v, const hkc *phi, hkc *const *grad_vectors, hkc *grad_H) {
+    if (check_dims(m, n) || check_dims(m, nblk)) return -1;
+    if (phi && !vectors[0]) return -1;
+    int64_t hr = 1 - m, hc = 1 - m;
+    for (int p = 0; p < m; ++p) { hr += n[p]; hc += nblk[p]; }
+    hkc *c = cotangent_mode1(n[0] * nblk[0], v, phi, vectors[0]);
+    const hkc **mats = (const hkc **)malloc(sizeof(hkc *) * (size_t)m);
+    int64_t *rr = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    int64_t *cc = (int64_t *)malloc(sizeof(int64_t) * (size_t)m);
+    if (!c || !mats || !rr || !cc) { free(c); free(mats); free(rr); free(cc); return -2; }
+    int rc = 0;
+    if (grad_H) {
+        mats[0] = c; rr[0] = n[0]; cc[0] = nblk[0];
+        for (int q = 1; q < m; ++q) { mats[q] = vectors[q]; rr[q] = n[q]; cc[q] = nblk[q]; }
+        int64_t ur = 0, uc = 0;
+        hkc *u = conv2_chain(m, mats, rr, cc, &ur, &uc); /* hr x hc */
+        if (!u) rc = -2;
+        else {
+            for (int64_t s = 0; s < hr * hc; ++s) grad_H[s] = cconj(u[s]);
+            free(u);
+        }
+    }
+    for (int p = 1; p < m && rc == 0; ++p) {
+        if (!grad_vectors[p]) continue;
+        int k = 0;
+        mats[k] = c; rr[k] = n[0]; cc[k++] = nblk[0];
+        for (int q = 1; q < m; ++q)
+            if (q != p) { mats[k] = vectors[q]; rr[k] = n[q]; cc[k++] = nblk[q]; }
+        int64_t wr = 0, wc = 0;
+        hkc *w = conv2_chain(k, mats, rr, cc, &wr, &wc);
+        if (!w) { rc = -2; break; }
+        corr2_conj(H, hr, w, wr, wc, n[p], nblk[p], grad_vectors[p]);
+        free(w);
+    }
+    if (rc == 0 && grad_vectors[0]) {
+        const int64_t len = n[0] * nblk[0];
+        if (!phi) {
+            for (int64_t s = 0; s < len; ++s) { grad_vectors[0][s].re = 0.0; grad_vectors[0][s].im = 0.0; }
+        } else {
+            int k = 0;
+            for (int q = 1; q < m; ++q) { mats[k] = vectors[q]; rr[k] = n[q]; cc[k++] = nblk[q]; }
+            int64_t wr = 0, wc = 0;
+            hkc *w = conv2_chain(k, mats, rr, cc, &wr, &wc);
+            if (!w) rc = -2;
+            else {
+                corr2_conj(H, hr, w, wr, wc, n[0], nblk[0], grad_vectors[0]);
+                for (int64_t s = 0; s < len; ++s) grad_vectors[0][s] = cmul(*phi, grad_vectors[0][s]);
+                free(w);
+            }
+        }
+    }
+    free(c); free(mats); free(rr); free(cc);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Spectra of the Section 3 procedures, as DFT sums at the bins idx[]:       */
 /*   sign = -1:  out_i = sum_{s<len} a_s e^{-2 pi i j s / N}          (fft)   */
 /*   sign = +1:  out_i = (1/N) sum_{s<len} a_s e^{+2 pi i j s / N}    (ifft)  */
