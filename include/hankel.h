@@ -404,6 +404,46 @@ hk_status_t hankel_tvp_backward_spectral_strided_batched(
     void *grad_x, int64_t gx_stride, void *grad_h, int64_t gh_stride, int64_t batch, void *ws,
     size_t ws_bytes, hipStream_t stream);
 
+/* -------------------------------------------------------------------------
+ * Adjoint of the products with distinct vectors: the general Hankel tensor
+ * (hankel_mode_products: y = H x_2 ... x_m, alpha = H x_1 ... x_m) and the
+ * BHHB tensor (block_hankel_tvp, vectors vec(X_p), y = vec(Y)).  The paper
+ * does not differentiate; as for hankel_tvp_backward the gradients are J^H
+ * applied to the cotangents v (of y) and phi (of alpha).  With
+ * c = conj(v) + conj(phi) x_1:
+ *   grad_h     = conj( c * x_2 * ... * x_m )            (d_H values; BHHB: 2D, the H grid)
+ *   grad_{x_p} = conj( H x_1 c x_q (q != 1, p) )         (mode p free, dims[p] values), p >= 2
+ *   grad_{x_1} = phi conj( H x_2 ... x_m )               (zero when grad_alpha is NULL)
+ * (* = linear convolution; 2D for BHHB; Section 2.1 mode products).  Each
+ * is computed by the forward kernels on the power-of-two complex grid
+ * (spectral correlations / convolutions), one after the other on `stream`.
+ *   vectors      : host array of m device pointers; vectors[0] (x_1) is read
+ *                  only when grad_alpha is given
+ *   grad_y       : cotangent of y (dims[0] values; BHHB n_1 N_1) or NULL
+ *   grad_alpha   : cotangent of alpha (1 value, device) or NULL
+ *   grad_vectors : host array of m device pointers, grad_vectors[p] receives
+ *                  grad_{x_p} (NULL = not requested)
+ *   grad_h       : receives grad_h (NULL = not requested)
+ * Workspace: *_workspace_size with the mask of requested grad_vectors (bit p)
+ * and want_grad_h.  Complex dtypes only.
+ * ------------------------------------------------------------------------- */
+hk_status_t hankel_mode_products_backward_workspace_size(hk_dtype_t dt, int m, const int64_t *dims,
+                                                         int grad_vectors_mask, int want_grad_h,
+                                                         size_t *bytes);
+hk_status_t hankel_mode_products_backward(hk_dtype_t dt, const void *h, int m, const int64_t *dims,
+                                          const void *const *vectors, const void *grad_y,
+                                          const void *grad_alpha, void *const *grad_vectors,
+                                          void *grad_h, void *ws, size_t ws_bytes,
+                                          hipStream_t stream);
+hk_status_t block_hankel_tvp_backward_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims,
+                                                     const int64_t *block_dims, int grad_vectors_mask,
+                                                     int want_grad_h, size_t *bytes);
+hk_status_t block_hankel_tvp_backward(hk_dtype_t dt, const void *H, int m, const int64_t *inner_dims,
+                                      const int64_t *block_dims, const void *const *vectors,
+                                      const void *grad_y, const void *grad_alpha,
+                                      void *const *grad_vectors, void *grad_H, void *ws,
+                                      size_t ws_bytes, hipStream_t stream);
+
 /* Strided batch of equal-vector products of one shape (m, n): instance b uses
  * h + b*h_stride, x + b*x_stride, y + b*y_stride, alpha + b (elements).
  * y or alpha may be NULL.  One launch per pass covers the whole batch. */

@@ -12,7 +12,8 @@ from __future__ import annotations
 
 import torch
 
-from .binding import (hankel_tvp, hankel_tvp_backward, hankel_tvp_backward_spectral,
+from .binding import (block_hankel_tvp, block_hankel_tvp_backward, hankel_mode_products,
+                      hankel_mode_products_backward, hankel_tvp, hankel_tvp_backward, hankel_tvp_backward_spectral,
                       hankel_tvp_backward_spectral_strided_batched, hankel_tvp_backward_strided_batched,
                       hankel_tvp_save_spectrum, hankel_tvp_strided_batched)
 
@@ -68,3 +69,59 @@ class HankelTVPFunction(torch.autograd.Function):
 def hankel_tvp_autograd(h: torch.Tensor, x: torch.Tensor, m: int):
     """Differentiable (H x^{m-1}, H x^m)."""
     return HankelTVPFunction.apply(h, x, m)
+
+
+class HankelModeProductsFunction(torch.autograd.Function):
+    """(h, x_1, ..., x_m) -> (y, alpha) = (H x_2 ... x_m, H x_1 ... x_m) for the
+    general Hankel tensor of size dims (distinct vectors); the backward is the
+    library's distinct-vector adjoint."""
+
+    @staticmethod
+    def forward(ctx, h, dims, *xs):
+        ctx.dims = list(dims)
+        y, a = hankel_mode_products(h, list(xs), ctx.dims, True, True)
+        ctx.save_for_backward(h, *xs)
+        return y, a
+
+    @staticmethod
+    def backward(ctx, grad_y, grad_alpha):
+        h, *xs = ctx.saved_tensors
+        want = list(ctx.needs_input_grad[2:])
+        want_h = ctx.needs_input_grad[0]
+        if not (want_h or any(want)):
+            return (None, None) + (None,) * len(xs)
+        gv, gh = hankel_mode_products_backward(h, xs, ctx.dims, grad_y, grad_alpha, want, want_h)
+        return (gh, None) + tuple(gv)
+
+
+class BlockHankelTVPFunction(torch.autograd.Function):
+    """(H, vec(X_1), ..., vec(X_m)) -> (vec(Y), alpha) for the BHHB tensor with
+    blocks of size inner_dims and block counts block_dims (distinct vectors)."""
+
+    @staticmethod
+    def forward(ctx, H, inner_dims, block_dims, *xs):
+        ctx.inner, ctx.blocks = list(inner_dims), list(block_dims)
+        y, a = block_hankel_tvp(H, list(xs), ctx.inner, ctx.blocks, True, True)
+        ctx.save_for_backward(H, *xs)
+        return y, a
+
+    @staticmethod
+    def backward(ctx, grad_y, grad_alpha):
+        H, *xs = ctx.saved_tensors
+        want = list(ctx.needs_input_grad[3:])
+        want_h = ctx.needs_input_grad[0]
+        if not (want_h or any(want)):
+            return (None, None, None) + (None,) * len(xs)
+        gv, gh = block_hankel_tvp_backward(H, xs, ctx.inner, ctx.blocks, grad_y, grad_alpha, want, want_h)
+        return (gh, None, None) + tuple(gv)
+
+
+def hankel_mode_products_autograd(h: torch.Tensor, vectors, dims=None):
+    """Differentiable (H x_2 ... x_m, H x_1 ... x_m) with distinct vectors."""
+    dims = [v.numel() for v in vectors] if dims is None else list(dims)
+    return HankelModeProductsFunction.apply(h, dims, *vectors)
+
+
+def block_hankel_tvp_autograd(H: torch.Tensor, vectors, inner_dims, block_dims):
+    """Differentiable BHHB products (vec(Y), alpha) with distinct vectors."""
+    return BlockHankelTVPFunction.apply(H, list(inner_dims), list(block_dims), *vectors)

@@ -292,6 +292,67 @@ def block_hankel_tvp(H: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]],
     return y, (None if alpha is None else alpha[0])
 
 
+def _adjoint_distinct(block: bool, h: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]], inner_dims,
+                      block_dims, grad_y, grad_alpha, want, want_grad_h: bool):
+    m = len(vectors)
+    ref = next(v for v in vectors if v is not None)
+    _dev(ref)
+    dt = _dtype(ref)
+    if len(inner_dims) != m or (block and len(block_dims) != m):
+        raise ValueError("dims must have one entry per vector")
+    lens = [int(inner_dims[p]) * (int(block_dims[p]) if block else 1) for p in range(m)]
+    hlen = _hlen(m, inner_dims) * (_hlen(m, block_dims) if block else 1)
+    _arg(h, "H" if block else "h", hlen, ref.dtype, ref.device)
+    for p, v in enumerate(vectors):
+        if v is not None:
+            _arg(v, f"vectors[{p}]", lens[p], ref.dtype, ref.device)
+        elif p > 0 or grad_alpha is not None:
+            raise ValueError(f"vectors[{p}] is needed")
+    want = [True] * m if want is None else list(want)
+    gy = _cotangent(grad_y, "grad_y", lens[0], ref.dtype, ref.device)
+    ga = _cotangent(grad_alpha, "grad_alpha", 1, ref.dtype, ref.device)
+    gv = [torch.empty(lens[p], dtype=ref.dtype, device=ref.device) if want[p] else None for p in range(m)]
+    gh = torch.empty(hlen, dtype=ref.dtype, device=ref.device) if want_grad_h else None
+    mask = sum(1 << p for p in range(m) if want[p])
+    di = _i64arr(inner_dims)
+    nb = ctypes.c_size_t(0)
+    if block:
+        db = _i64arr(block_dims)
+        check(lib().block_hankel_tvp_backward_workspace_size(dt, m, di, db, mask, int(want_grad_h), ctypes.byref(nb)),
+              "block_hankel_tvp_backward_workspace_size")
+    else:
+        check(lib().hankel_mode_products_backward_workspace_size(dt, m, di, mask, int(want_grad_h), ctypes.byref(nb)),
+              "hankel_mode_products_backward_workspace_size")
+    ws, wsb = _workspace(nb.value, ref.device)
+    va, ga_arr = _vecarr(vectors), _vecarr(gv)
+    if block:
+        check(lib().block_hankel_tvp_backward(dt, _ptr(h), m, di, db, va, _ptr(gy), _ptr(ga), ga_arr, _ptr(gh),
+                                              _ptr(ws), wsb, _stream(ref.device)), "block_hankel_tvp_backward")
+    else:
+        check(lib().hankel_mode_products_backward(dt, _ptr(h), m, di, va, _ptr(gy), _ptr(ga), ga_arr, _ptr(gh),
+                                                  _ptr(ws), wsb, _stream(ref.device)), "hankel_mode_products_backward")
+    return gv, gh
+
+
+def hankel_mode_products_backward(h: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]], dims: Sequence[int],
+                                  grad_y: Optional[torch.Tensor], grad_alpha: Optional[torch.Tensor],
+                                  want: Optional[Sequence[bool]] = None, want_grad_h: bool = True):
+    """J^H of y = H x_2 ... x_m and alpha = H x_1 ... x_m (distinct vectors)
+    applied to the cotangents grad_y (dims[0]) and grad_alpha (scalar).
+    vectors[0] may be None when grad_alpha is None.  Returns (list of
+    grad_{x_p} (None where want[p] is False), grad_h)."""
+    return _adjoint_distinct(False, h, vectors, dims, None, grad_y, grad_alpha, want, want_grad_h)
+
+
+def block_hankel_tvp_backward(H: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]], inner_dims: Sequence[int],
+                              block_dims: Sequence[int], grad_y: Optional[torch.Tensor],
+                              grad_alpha: Optional[torch.Tensor], want: Optional[Sequence[bool]] = None,
+                              want_grad_h: bool = True):
+    """J^H of the BHHB products (vectors vec(X_p), y = vec(Y)) applied to
+    grad_y (n_1 N_1) and grad_alpha.  Returns (list of grad vec(X_p), grad vec(H))."""
+    return _adjoint_distinct(True, H, vectors, inner_dims, block_dims, grad_y, grad_alpha, want, want_grad_h)
+
+
 def block_hankel_tvp_levels(G: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]], dims,
                             want_y: bool = True, want_alpha: bool = False):
     """Level-k block Hankel tensor (k = len(dims)): G is the column-major

@@ -16,7 +16,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhankel.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["hk_f32.hip", "hk_f64.hip", "hk_f32_odd.hip", "hk_f64_odd.hip", "hk_levels.hip", "hk_noalloc.hip"]
+HIP_SOURCES = ["hk_f32.hip", "hk_f64.hip", "hk_f32_odd.hip", "hk_f64_odd.hip", "hk_levels.hip", "hk_noalloc.hip", "hk_adjoint.hip"]
 HOST_SOURCES = ["hk_plan.cpp", "hk_batch.cpp", "hk_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

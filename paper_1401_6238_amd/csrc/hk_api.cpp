@@ -28,6 +28,7 @@ hk_status_t api_finish(const Status &s) { return finish(s); }
 }  // namespace hk
 
 static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static Status check_ws(size_t need, const void *ws, size_t ws_bytes) {
   if (need == 0) return Status();
@@ -797,6 +798,202 @@ hk_status_t hankel_tvp_backward_spectral_strided_batched(hk_dtype_t dt, const vo
   return finish(launch_shape(dt, sh, sc, P, str, batch, stream));
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of the products with distinct vectors, 1D and BHHB (complex
+// autograd's J^H applied to the cotangents v of y and phi of alpha).  Every
+// gradient is linear in the cotangent of mode 1, c = conj(v) + conj(phi) x_1:
+//   grad_h     = conj(c * x_2 * ... * x_m)            (convolution program)
+//   grad_{x_p} = conj(H x_1 c x_q (q != 1, p))         (mode p free, p >= 2)
+//   grad_{x_1} = phi conj(H x_2 ... x_m) = conj(H x_2 (conj(phi) x_2) x_3 ... x_m)
+// Each is one product of the forward kernels on power-of-two complex
+// layouts (conjugated output, or the generating-vector-free convolution),
+// run in turn on the stream; they share one workspace after the two
+// cotangent vectors.
+// ---------------------------------------------------------------------------
+static Status adjoint_distinct(hk_dtype_t dt, bool is_block, const void *h, int m, const int64_t *dims,
+                               const int64_t *bdims, const void *const *vectors, const void *grad_y,
+                               const void *grad_alpha, void *const *grad_vectors, void *grad_h, void *ws,
+                               size_t ws_bytes, size_t *ws_need, hipStream_t st) {
+  if (!dims || !vectors || !grad_vectors || (is_block && !bdims))
+    return fail(HK_ERR_NULL_POINTER, "dims, block_dims, vectors or grad_vectors is NULL");
+  if (m < 2 || m > HK_MAX_ORDER) return fail(HK_ERR_INVALID_VALUE, "order m must be in [2, 8]");
+  if (!is_complex(dt)) return fail(HK_ERR_NOT_SUPPORTED, "the adjoint is implemented for complex dtypes");
+  const bool sizing = ws_need != nullptr;
+  bool any = grad_h != nullptr;
+  for (int q = 0; q < m; ++q) any = any || grad_vectors[q] != nullptr;
+  if (!any) return fail(HK_ERR_NULL_POINTER, "no gradient requested");
+  if (grad_alpha && !vectors[0]) return fail(HK_ERR_NULL_POINTER, "grad_alpha given but vector 1 is NULL");
+  const size_t eb = elem_bytes(dt);
+  int64_t len[HK_MAX_ORDER];
+  for (int q = 0; q < m; ++q) {
+    if (dims[q] < 1 || (is_block && bdims[q] < 1)) return fail(HK_ERR_INVALID_VALUE, "every dimension must be >= 1");
+    len[q] = dims[q] * (is_block ? bdims[q] : 1);
+  }
+  const void *ptrs[] = {h, grad_y, grad_alpha, grad_h};
+  for (const void *q : ptrs)
+    if (q && !aligned(q, eb)) return fail(HK_ERR_MISALIGNED, "pointer not aligned to the element size");
+  for (int q = 0; q < m; ++q)
+    if ((vectors[q] && !aligned(vectors[q], eb)) || (grad_vectors[q] && !aligned(grad_vectors[q], eb)))
+      return fail(HK_ERR_MISALIGNED, "vector not aligned to the element size");
+  // workspace: c (len[0]), d = conj(phi) x_2 (len[1]), then the products' workspace
+  const size_t off_d = align256(len[0] * cplx_bytes(dt));
+  const size_t off_p = off_d + align256(len[1] * cplx_bytes(dt));
+  char *base = (char *)ws;
+  // sizing: distinct placeholder addresses, so that no operands merge (an
+  // upper bound on the workspace of any call whose vectors may coincide)
+  auto dummy_of = [](int q) { return (const void *)(uintptr_t)(256 * (q + 3)); };
+  const void *c = sizing ? (const void *)256 : (const void *)base;
+  const void *d = sizing ? (const void *)512 : (const void *)(base + off_d);
+  void *pws = sizing ? nullptr : (void *)(base + off_p);
+  const size_t pws_bytes = ws_bytes > off_p ? ws_bytes - off_p : 0;
+  // the sub-products
+  std::vector<Problem> subs;
+  auto sub = [&](const int64_t *order, const void *const *vecs, void *y, bool conv) {
+    Problem q;
+    q.dt = dt;
+    q.prog = PROG_FWD;
+    q.is_block = is_block;
+    q.m = m;
+    for (int t = 0; t < m; ++t) {
+      q.dims[t] = dims[order[t]];
+      q.bdims[t] = is_block ? bdims[order[t]] : 0;
+      q.vec[t] = vecs[t];
+    }
+    q.h = conv ? nullptr : h;
+    q.y = y;
+    q.conv = conv;
+    q.conj_y = !conv;
+    subs.push_back(q);
+  };
+  int64_t order[HK_MAX_ORDER];
+  const void *vecs[HK_MAX_ORDER];
+  if (grad_h) {
+    for (int t = 0; t < m; ++t) {
+      order[t] = t;
+      vecs[t] = t == 0 ? c : (sizing ? dummy_of(t) : vectors[t]);
+    }
+    sub(order, vecs, sizing ? (void *)256 : grad_h, true);
+  }
+  for (int p = 1; p < m; ++p) {
+    if (!grad_vectors[p]) continue;
+    // mode p free, c in the next mode, the other vectors after it
+    int k = 0;
+    order[k] = p;
+    vecs[k++] = nullptr;
+    order[k] = 0;
+    vecs[k++] = c;
+    for (int q = 1; q < m; ++q)
+      if (q != p) {
+        order[k] = q;
+        vecs[k++] = sizing ? dummy_of(q) : vectors[q];
+      }
+    sub(order, vecs, sizing ? (void *)256 : grad_vectors[p], false);
+  }
+  const bool x1_product = grad_vectors[0] && grad_alpha;
+  if (x1_product) {
+    for (int t = 0; t < m; ++t) {
+      order[t] = t;
+      vecs[t] = t == 0 ? nullptr : (t == 1 ? d : (sizing ? dummy_of(t) : vectors[t]));
+    }
+    sub(order, vecs, sizing ? (void *)256 : grad_vectors[0], false);
+  }
+  for (Problem &q : subs) {
+    if (!sizing && !q.conv && !q.h) return fail(HK_ERR_NULL_POINTER, "generating vector/matrix is NULL");
+    if (sizing && !q.conv) q.h = (const void *)256;
+    Status s = validate_forward(q);
+    if (!s.ok()) return s;
+  }
+  size_t need_p = 0;
+  for (const Problem &q : subs) {
+    Shape sh;
+    Ptrs P;
+    Sched sc;
+    Status s = prepare(q, 1, &sh, &P, &sc);
+    if (!s.ok()) return s;
+    need_p = std::max(need_p, instance_ws_bytes(sh, dt));
+  }
+  const size_t need = off_p + need_p;
+  if (sizing) {
+    *ws_need = need;
+    return Status();
+  }
+  Status s = check_ws(need, ws, ws_bytes);
+  if (!s.ok()) return s;
+  s = ensure_device();
+  if (!s.ok()) return s;
+  const bool dbl = dt == HK_C128;
+  hipError_t e = hipSuccess;
+  const bool need_c = grad_h || [&] {
+    for (int p = 1; p < m; ++p)
+      if (grad_vectors[p]) return true;
+    return false;
+  }();
+  if (need_c) {
+    count_launch();
+    e = launch_mode1_cotangent(dbl, (void *)c, grad_y, grad_alpha, vectors[0], len[0], st);
+  }
+  if (e == hipSuccess && x1_product) {
+    count_launch();
+    e = launch_mode1_cotangent(dbl, (void *)d, nullptr, grad_alpha, vectors[1], len[1], st);
+  }
+  if (e == hipSuccess && grad_vectors[0] && !grad_alpha) {
+    // x_1 enters alpha only: with no cotangent for alpha its gradient is zero
+    count_launch();
+    e = launch_mode1_cotangent(dbl, grad_vectors[0], nullptr, nullptr, nullptr, len[0], st);
+  }
+  if (e != hipSuccess) return fail(HK_ERR_HIP, std::string("cotangent kernel launch: ") + hipGetErrorString(e));
+  for (const Problem &q : subs) {
+    s = run_one(q, pws, pws_bytes, st);
+    if (!s.ok()) return s;
+  }
+  return Status();
+}
+
+hk_status_t hankel_mode_products_backward_workspace_size(hk_dtype_t dt, int m, const int64_t *dims,
+                                                         int grad_vectors_mask, int want_grad_h, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  void *gv[HK_MAX_ORDER] = {nullptr};
+  const void *vv[HK_MAX_ORDER];
+  for (int q = 0; q < HK_MAX_ORDER; ++q) {
+    gv[q] = ((grad_vectors_mask >> q) & 1) ? (void *)256 : nullptr;
+    vv[q] = (const void *)256;
+  }
+  return finish(adjoint_distinct(dt, false, (const void *)256, m, dims, nullptr, vv, (const void *)256,
+                                 (const void *)256, gv, want_grad_h ? (void *)256 : nullptr, nullptr, 0, bytes,
+                                 nullptr));
+}
+
+hk_status_t hankel_mode_products_backward(hk_dtype_t dt, const void *h, int m, const int64_t *dims,
+                                          const void *const *vectors, const void *grad_y, const void *grad_alpha,
+                                          void *const *grad_vectors, void *grad_h, void *ws, size_t ws_bytes,
+                                          hipStream_t stream) {
+  return finish(adjoint_distinct(dt, false, h, m, dims, nullptr, vectors, grad_y, grad_alpha, grad_vectors, grad_h,
+                                 ws, ws_bytes, nullptr, stream));
+}
+
+hk_status_t block_hankel_tvp_backward_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims,
+                                                     const int64_t *block_dims, int grad_vectors_mask,
+                                                     int want_grad_h, size_t *bytes) {
+  if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
+  void *gv[HK_MAX_ORDER] = {nullptr};
+  const void *vv[HK_MAX_ORDER];
+  for (int q = 0; q < HK_MAX_ORDER; ++q) {
+    gv[q] = ((grad_vectors_mask >> q) & 1) ? (void *)256 : nullptr;
+    vv[q] = (const void *)256;
+  }
+  return finish(adjoint_distinct(dt, true, (const void *)256, m, inner_dims, block_dims, vv, (const void *)256,
+                                 (const void *)256, gv, want_grad_h ? (void *)256 : nullptr, nullptr, 0, bytes,
+                                 nullptr));
+}
+
+hk_status_t block_hankel_tvp_backward(hk_dtype_t dt, const void *H, int m, const int64_t *inner_dims,
+                                      const int64_t *block_dims, const void *const *vectors, const void *grad_y,
+                                      const void *grad_alpha, void *const *grad_vectors, void *grad_H, void *ws,
+                                      size_t ws_bytes, hipStream_t stream) {
+  return finish(adjoint_distinct(dt, true, H, m, inner_dims, block_dims, vectors, grad_y, grad_alpha, grad_vectors,
+                                 grad_H, ws, ws_bytes, nullptr, stream));
+}
+
 hk_status_t block_hankel_tvp_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims, const int64_t *block_dims,
                                             const void *const *vectors, int want_y, int want_alpha, size_t *bytes) {
   if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
@@ -1177,8 +1374,6 @@ struct TmSpectral {
   std::vector<int32_t> digits;  // K x (m-1) nondecreasing digits, tuple-major
   std::vector<int32_t> pairs;   // (column of T, tuple) for every column
 };
-
-static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static bool tm_spectral_plan(hk_dtype_t dt, int m, int64_t n, int64_t R, TmSpectral *T) {
   if (R < 1 || m < 2 || m > HK_MAX_ORDER) return false;

@@ -403,7 +403,7 @@ struct RowBody {
     if (resident) {
       void *dst = which == 0 ? P.y() : P.out1();
       const int64_t lim = which == 0 ? sh.out_rows : sh.out1_len;
-      const bool cj = (sh.prog == PROG_BWD) && which == 1;
+      const bool cj = which == 1 ? sh.prog == PROG_BWD : (sh.fwd_flags & SHF_CONJ_Y) != 0;
 #pragma unroll
       for (int s = 0; s < EE; ++s) {
         const int pos = t + s * TPS;
@@ -455,10 +455,11 @@ struct RowBody {
       return run_fwd_odd(sh, P, row, 0, 1, valid_row, t, lds, resident, tw24, tw4096);
     } else {
     const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
+    const bool conv = (sh.fwd_flags & SHF_CONV) != 0;
     cx<T> a[EE], nx[EE], acc[EE];
     cx<T> part = czero<T>();
 #pragma unroll
-    for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
+    for (int s = 0; s < EE; ++s) acc[s] = mk(conv ? T(1) : T(0), T(0));
     load(a, sh, P, 0, row, valid_row, t, resident);
     StageTw<T, L, E> stw;
     stw.init(t, tw4096);
@@ -487,6 +488,10 @@ struct RowBody {
       for (int s = 0; s < EE; ++s) a[s] = nx[s];
     }
     if (sh.want_y) {
+      if (conv) {
+#pragma unroll
+        for (int s = 0; s < EE; ++s) acc[s] = cscale(cconj(acc[s]), invN);
+      }
       fft(acc, t, lds, stw);
       store(acc, sh, P, 0, row, valid_row, t, resident, w);
     }
@@ -510,6 +515,7 @@ struct RowBody {
     } else {
     const int64_t C = (int64_t)1 << sh.logC;
     const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
+    const bool conv = (sh.fwd_flags & SHF_CONV) != 0;
     cx<T> a[EE], nx[EE], acc[EE], w[EE];
     cx<T> part = czero<T>();
     int64_t row = row0;
@@ -522,7 +528,7 @@ struct RowBody {
       const int64_t nrow = row + rstride;
       const bool nvalid = (it + 1 < K) && nrow < C;
 #pragma unroll
-      for (int s = 0; s < EE; ++s) acc[s] = czero<T>();
+      for (int s = 0; s < EE; ++s) acc[s] = mk(conv ? T(1) : T(0), T(0));
       for (int o = 0; o < sh.nops; ++o) {
         if (o + 1 < sh.nops)
           load<SPEC>(nx, sh, P, o + 1, row, valid, t, false);
@@ -576,6 +582,10 @@ struct RowBody {
         for (int s = 0; s < EE; ++s) a[s] = nx[s];
       }
       if (sh.want_y) {
+        if (conv) {
+#pragma unroll
+          for (int s = 0; s < EE; ++s) acc[s] = cscale(cconj(acc[s]), invN);
+        }
         fft(acc, t, lds, stw);
         store(acc, sh, P, 0, row, valid, t, false, w);
       }

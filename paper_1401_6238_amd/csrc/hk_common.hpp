@@ -43,6 +43,16 @@ enum OpFlag : int32_t {
 };
 
 enum Prog : int32_t { PROG_FWD = 0, PROG_BWD = 1 };
+
+// Forward-program variants used by the adjoint of the distinct-vector and
+// BHHB products (power-of-two complex layouts only):
+enum ShapeFlag : int32_t {
+  // no generating vector: the operands' spectra multiply from one, and the
+  // output is fft(conj(z) / N) = conj(ifft(z)), i.e. the conjugate of the
+  // operands' linear convolution (sliced to out_rows x out_cols)
+  SHF_CONV = 1,
+  SHF_CONJ_Y = 2,  // the vector output is stored conjugated
+};
 // Row-kernel variants (never a Shape's prog): the forward and adjoint
 // programs built with stored-spectrum operands (OPF_SPEC, OPF_STORE_SPEC).
 enum : int32_t { PROG_FWD_SPEC = 2, PROG_BWD_SPEC = 3 };
@@ -77,7 +87,7 @@ struct Shape {
   int32_t odd_inv;     // M^{-1} mod odd (0 when odd == 1)
   int32_t r2c;         // real inputs, resident: length-N real transforms as length-N/2
                        // complex ones (logR = log2(N/2)); forward program only
-  int32_t pad0;
+  int32_t fwd_flags;   // forward program variants (ShapeFlag bits)
   int64_t out_rows;    // output slice: 1D length / BHHB rows n_1; adjoint grad_h length
   int64_t out_cols;    // BHHB columns N_1 (1 for 1D)
   int64_t out1_len;    // adjoint grad_x length

@@ -55,6 +55,12 @@ hipError_t launch_levels_fill(void *p, int64_t n, int es, hipStream_t st);
 hipError_t launch_levels_copy(void *compact, void *emb, const Levels &lv, int64_t total, int dir, int es,
                               hipStream_t st);
 
+// Adjoint of the distinct-vector and BHHB products (hk_adjoint.hip):
+// out[i] = (v ? conj(v[i]) : 0) + (phi ? conj(*phi) x[i] : 0), i < n complex
+// elements of float (dbl = false) or double precision.
+hipError_t launch_mode1_cotangent(bool dbl, void *out, const void *v, const void *phi, const void *x, int64_t n,
+                                  hipStream_t st);
+
 #define HK_DECLARE_ODD_LAUNCHERS(SUFFIX)                                                                  \
   hipError_t init_tables_odd_##SUFFIX(const double *tw4096_interleaved, const double *tw24_interleaved);  \
   bool limits_odd_##SUFFIX(int odd, int logL, int E, KernelLimits *out);                                \

@@ -71,12 +71,19 @@ Status validate_forward(const Problem &p) {
   Status s = check_common(p);
   if (!s.ok()) return s;
   if (!p.y && !p.alpha) return fail(HK_ERR_NULL_POINTER, "neither y nor alpha requested");
-  if (!p.h) return fail(HK_ERR_NULL_POINTER, "generating vector/matrix is NULL");
+  if ((p.conv || p.conj_y) && !is_complex(p.dt))
+    return fail(HK_ERR_NOT_SUPPORTED, "the adjoint is implemented for complex dtypes");
+  if (p.conv) {
+    if (!p.y || p.alpha) return fail(HK_ERR_INVALID_VALUE, "the convolution program has a vector output only");
+    if (!p.vec[0]) return fail(HK_ERR_NULL_POINTER, "vector 1 is NULL");
+  } else if (!p.h) {
+    return fail(HK_ERR_NULL_POINTER, "generating vector/matrix is NULL");
+  }
   for (int q = 1; q < p.m; ++q)
     if (!p.vec[q]) return fail(HK_ERR_NULL_POINTER, "vector " + std::to_string(q + 1) + " is NULL");
   if (p.alpha && !p.vec[0]) return fail(HK_ERR_NULL_POINTER, "alpha requested but vector 1 is NULL");
   const size_t a = elem_bytes(p.dt);
-  if (!aligned(p.h, a) || (p.y && !aligned(p.y, a)) || (p.alpha && !aligned(p.alpha, a)))
+  if ((p.h && !aligned(p.h, a)) || (p.y && !aligned(p.y, a)) || (p.alpha && !aligned(p.alpha, a)))
     return fail(HK_ERR_MISALIGNED, "pointer not aligned to the element size");
   for (int q = 0; q < p.m; ++q)
     if (p.vec[q] && !aligned(p.vec[q], a)) return fail(HK_ERR_MISALIGNED, "vector not aligned to the element size");
@@ -162,6 +169,8 @@ constexpr int64_t kOddWorkMin = (int64_t)1 << 18;
 
 Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int64_t batch) {
   const int policy = g_length_policy.load();
+  // the adjoint's forward variants run on power-of-two complex layouts
+  if (p.conv || p.conj_y) allow_odd = false;
   const bool allow_r2c = allow_odd && policy != HK_LENGTHS_POW2;
   if (policy == HK_LENGTHS_POW2) allow_odd = false;
   if (allow_odd && policy == HK_LENGTHS_AUTO && !p.is_block) {
@@ -285,9 +294,35 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
     if (op_src) op_src[sh.nops] = src;
     ++sh.nops;
   };
-  if (p.prog == PROG_FWD) {
+  if (p.prog == PROG_FWD && p.conv) {
+    // conj(x_1 * ... * x_m) on the generating grid: every vector an operand
+    // (identical ones merged into powers), no generating vector, no scalar
+    sh.want_y = 1;
+    sh.fwd_flags = SHF_CONV;
+    struct G {
+      const void *ptr;
+      int64_t n, nb;
+      int exp, src;
+    };
+    std::vector<G> groups;
+    for (int q = 0; q < p.m; ++q) {
+      bool found = false;
+      for (auto &g : groups)
+        if (g.ptr == p.vec[q] && g.n == p.dims[q] && g.nb == (p.is_block ? p.bdims[q] : 1)) {
+          g.exp++;
+          found = true;
+          break;
+        }
+      if (!found) groups.push_back({p.vec[q], p.dims[q], p.is_block ? p.bdims[q] : 1, 1, q});
+    }
+    for (const G &g : groups) add_op(ROLE_X, g.exp, 0, g.n, g.nb, g.ptr, g.src);
+    sh.out_rows = hrows;
+    sh.out_cols = p.is_block ? hcols : 1;
+    P.y = p.y;
+  } else if (p.prog == PROG_FWD) {
     sh.want_y = p.y ? 1 : 0;
     sh.want_alpha = p.alpha ? 1 : 0;
+    sh.fwd_flags = p.conj_y ? SHF_CONJ_Y : 0;
     add_op(ROLE_H, 1, p.h_spec ? OPF_SPEC : (OPF_CONJ | real_flag), p.is_block ? hrows : hrows,
            p.is_block ? hcols : 1, p.h, -1);
     // Group identical vectors of modes 2..m (same pointer, shape and kind).
@@ -637,7 +672,7 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
     jd[nd].kind = COL_D;
     jd[nd].op = 0;
     jd[nd].buf = sh.ops[0].buf;
-    jd[nd].conj_out = 0;
+    jd[nd].conj_out = (sh.prog == PROG_FWD && (sh.fwd_flags & SHF_CONJ_Y)) ? 1 : 0;
     jd[nd].npart = npart;
     // real outputs of real-input transforms are stored in pairs
     jd[nd].ncols = std::min<int64_t>(R, sh.r2c ? (sh.out_rows + 1) / 2 : sh.out_rows);

@@ -47,6 +47,11 @@ struct Problem {
   const void *phi = nullptr;
   void *gx = nullptr;
   void *gh = nullptr;
+  // forward variants (power-of-two complex layouts): conv = no generating
+  // vector, output conj(x_1 * ... * x_m) over the generating grid; conj_y =
+  // the vector output stored conjugated
+  bool conv = false;
+  bool conj_y = false;
 };
 
 // Launch parameters of one shape.
