@@ -903,13 +903,17 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
     # workspace_MB is the plan's workspace, which holds N elements per operand of every
     # multipass instance: it tracks the padded lengths the passes stream.
     for name, flags in (("persistent", _lib.HK_PLAN_PERSISTENT), ("grouped", _lib.HK_PLAN_MULTIKERNEL),
-                        ("grouped_pow2", _lib.HK_PLAN_MULTIKERNEL | _lib.HK_PLAN_POW2)):
+                        ("grouped_pow2", _lib.HK_PLAN_MULTIKERNEL | _lib.HK_PLAN_POW2),
+                        ("grouped_autotune", _lib.HK_PLAN_MULTIKERNEL | _lib.HK_PLAN_AUTOTUNE)):
         plan = hk.Plan(items, flags=flags)
         ms = time_region(torch, plan.execute, 10)
         plan.status()
         res[name] = {"TVP_s": round(len(items) / ms * 1000, 1), "ms_per_batch": round(ms, 3),
                      "workspace_MB": round(plan.ws_bytes / 2**20, 1),
                      "roofline": roof(plan.pass_bytes(), ms, "k_batch" if name == "persistent" else "k_group")}
+        if name == "grouped_autotune":
+            t0, t1, mask = plan.tune_times()
+            res[name]["tuner"] = {"default_ms": round(t0, 4), "kept_ms": round(t1, 4), "pow2_buckets": hex(mask)}
         plan.close()
     # graph plans (launches captured once, replayed): the grouped plan's four
     # streams then no longer depend on how the process's streams share the
@@ -917,7 +921,9 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         for name, flags in (("persistent_graph", _lib.HK_PLAN_PERSISTENT | _lib.HK_PLAN_GRAPH),
-                            ("grouped_graph", _lib.HK_PLAN_MULTIKERNEL | _lib.HK_PLAN_GRAPH)):
+                            ("grouped_graph", _lib.HK_PLAN_MULTIKERNEL | _lib.HK_PLAN_GRAPH),
+                            ("grouped_autotune_graph", _lib.HK_PLAN_MULTIKERNEL | _lib.HK_PLAN_GRAPH |
+                             _lib.HK_PLAN_AUTOTUNE)):
             plan = hk.Plan(items, flags=flags)
             ms = time_region(torch, plan.execute, 10)
             plan.status()

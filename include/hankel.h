@@ -245,7 +245,11 @@ typedef struct hk_plan_s *hk_plan_t;
 #define HK_PLAN_MULTIKERNEL 0x2u /* grouped launches: per phase, one kernel specialised for each
                                    (task kind, transform length) group; no in-kernel waits      */
 #define HK_PLAN_GRAPH 0x4u      /* capture the plan's launches in a hipGraph on first execute */
-#define HK_PLAN_AUTOTUNE 0x8u   /* reserved (accepted, no effect)                             */
+#define HK_PLAN_AUTOTUNE 0x8u   /* grouped plans: at the first execute, choose per length
+                                   bucket (log2 of the power-of-two length >= d_H) between
+                                   the odd-factor and the power-of-two transform lengths by
+                                   timing the whole plan (coordinate descent, longest bucket
+                                   first); the workspace size covers every candidate       */
 #define HK_PLAN_POW2 0x10u      /* power-of-two complex transforms only (no 3 * 2^k, 5 * 2^k,
                                    no half-length real transforms); implied by PERSISTENT      */
 
@@ -287,6 +291,11 @@ hk_status_t hk_plan_set_wait_bound(hk_plan_t plan, uint32_t spins);
  * the output columns the last pass reads written) and pass D (those read
  * back, the output slice written).  Host-only; *bytes receives the total. */
 hk_status_t hk_plan_pass_bytes(hk_plan_t plan, int64_t *bytes);
+/* Diagnostics: the times (ms per execute) the HK_PLAN_AUTOTUNE tuner measured
+ * for the default plan and for the plan it kept, and the mask of length
+ * buckets it moved to powers of two (bit b: power-of-two length 2^b); zeros
+ * before the first execute or without the flag.  Any pointer may be NULL. */
+hk_status_t hk_plan_tune_times(hk_plan_t plan, double *ms_default, double *ms_tuned, uint32_t *pow2_buckets);
 hk_status_t hk_plan_destroy(hk_plan_t plan);
 
 /* One-shot convenience: plan (grouped launches), execute with the descriptor

@@ -107,6 +107,8 @@ _SIGS = {
     "hankel_tensor_matrix": [_I, _P, _I, _I64, _I64, _P, _P, _P, ctypes.c_size_t, _P],
     "hk_plan_set_wait_bound": [ctypes.c_void_p, ctypes.c_uint32],
     "hk_plan_pass_bytes": [ctypes.c_void_p, _PI64],
+    "hk_plan_tune_times": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_uint32)],
     "hk_tune_load": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)],
     "hk_last_launch_count": [],
     "hk_profile_start": [],

@@ -640,6 +640,14 @@ class Plan:
         check(lib().hk_plan_pass_bytes(self._plan, ctypes.byref(b)), "hk_plan_pass_bytes")
         return int(b.value)
 
+    def tune_times(self):
+        """HK_PLAN_AUTOTUNE: (ms per execute of the default plan, of the kept plan,
+        mask of length buckets moved to powers of two); zeros before the first execute."""
+        a, b, mask = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_uint32(0)
+        check(lib().hk_plan_tune_times(self._plan, ctypes.byref(a), ctypes.byref(b), ctypes.byref(mask)),
+              "hk_plan_tune_times")
+        return a.value, b.value, int(mask.value)
+
     def set_wait_bound(self, spins: int):
         """Persistent plans: barrier polling iterations before the error path (diagnostics)."""
         check(lib().hk_plan_set_wait_bound(self._plan, int(spins)), "hk_plan_set_wait_bound")

@@ -1274,6 +1274,10 @@ hk_status_t hk_plan_set_wait_bound(hk_plan_t plan, uint32_t spins) { return fini
 
 hk_status_t hk_plan_pass_bytes(hk_plan_t plan, int64_t *bytes) { return finish(plan_pass_bytes(plan, bytes)); }
 
+hk_status_t hk_plan_tune_times(hk_plan_t plan, double *ms_default, double *ms_tuned, uint32_t *pow2_buckets) {
+  return finish(plan_tune_times(plan, ms_default, ms_tuned, pow2_buckets));
+}
+
 hk_status_t hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs, int64_t count, size_t *bytes) {
   if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));
   hk_plan_t plan = nullptr;

@@ -65,6 +65,14 @@ struct hk_plan_s {
   // status
   hipStream_t last_stream = nullptr;
   void *last_ws = nullptr;
+  // HK_PLAN_AUTOTUNE: the problems (to rebuild the plan), the length buckets
+  // (log2 of the power-of-two length >= d_H) forced to powers of two, the
+  // workspace every candidate fits in, and whether the first execute has tuned
+  std::vector<hk_problem_t> probs;
+  uint32_t pow2_buckets = 0;
+  size_t tune_ws_bytes = 0;
+  bool tuned = false;
+  double tune_ms_default = 0.0, tune_ms_best = 0.0;
 };
 
 namespace hk {
@@ -160,7 +168,38 @@ static Problem problem_of(hk_dtype_t dt, const hk_problem_t &q) {
   return p;
 }
 
+// log2 of the power-of-two transform length of a 1D problem (its length bucket).
+static int length_bucket(const Problem &pr) {
+  int64_t dh = 1 - pr.m;
+  for (int q = 0; q < pr.m; ++q) dh += pr.dims[q];
+  return ceil_log2(dh);
+}
+
+static Status plan_build(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int64_t count, unsigned flags,
+                         uint32_t pow2_buckets);
+
 Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int64_t count, unsigned flags) {
+  Status s = plan_build(out, dt, probs, count, flags, 0);
+  if (!s.ok() || !(flags & HK_PLAN_AUTOTUNE) || (flags & HK_PLAN_PERSISTENT)) return s;
+  // the tuner may force any length bucket to powers of two: the workspace
+  // must hold the plan with all of them forced
+  hk_plan_s *p = *out;
+  hk_plan_t all = nullptr;
+  s = plan_build(&all, dt, probs, count, flags, ~0u);
+  if (!s.ok()) {
+    delete p;
+    *out = nullptr;
+    return s;
+  }
+  p->tune_ws_bytes = std::max(p->ctl_bytes + p->tables_bytes + p->inst_bytes,
+                              all->ctl_bytes + all->tables_bytes + all->inst_bytes);
+  delete all;
+  p->probs.assign(probs, probs + count);
+  return Status();
+}
+
+static Status plan_build(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int64_t count, unsigned flags,
+                         uint32_t pow2_buckets) {
   if (!out) return fail(HK_ERR_NULL_POINTER, "plan pointer is NULL");
   *out = nullptr;
   if (count < 0) return fail(HK_ERR_INVALID_VALUE, "count must be >= 0");
@@ -176,6 +215,7 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
   p->flags = flags;
   p->count = count;
   p->persistent = (flags & HK_PLAN_PERSISTENT) != 0;
+  p->pow2_buckets = pow2_buckets;
   int blk, er, ec;
   size_t lds;
   if (dbl(dt))
@@ -250,7 +290,8 @@ Status plan_create(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *probs, int
       return fail(s.code, "problem " + std::to_string(i) + ": " + s.msg);
     }
     Layout lay;
-    s = layout_for(pr, 0, &lay, allow_odd, count);
+    const bool forced = !pr.is_block && ((pow2_buckets >> std::min(31, length_bucket(pr))) & 1u);
+    s = layout_for(pr, 0, &lay, allow_odd && !forced, count);
     if (!s.ok()) {
       delete p;
       return fail(s.code, "problem " + std::to_string(i) + ": " + s.msg);
@@ -357,7 +398,7 @@ Status plan_ws_size(hk_plan_t p, size_t *bytes) {
   if (!bytes) return fail(HK_ERR_NULL_POINTER, "bytes is NULL");
   // Room for the descriptor tables is always reserved so that one-shot
   // execution can keep them in the workspace.
-  *bytes = p->ctl_bytes + p->tables_bytes + p->inst_bytes;
+  *bytes = std::max(p->ctl_bytes + p->tables_bytes + p->inst_bytes, p->tune_ws_bytes);
   return Status();
 }
 
@@ -488,6 +529,8 @@ static Status enqueue(hk_plan_s *p, char *ws, hipStream_t st) {
   return Status();
 }
 
+static Status tune_plan(hk_plan_s *p, char *ws, hipStream_t st);
+
 Status plan_execute(hk_plan_t p, void *ws, size_t ws_bytes, hipStream_t st) {
   if (!p) return fail(HK_ERR_NULL_POINTER, "plan is NULL");
   Status s = ensure_device();
@@ -497,6 +540,10 @@ Status plan_execute(hk_plan_t p, void *ws, size_t ws_bytes, hipStream_t st) {
   if (!ws) return fail(HK_ERR_WORKSPACE, "workspace is NULL");
   if (ws_bytes < need) return fail(HK_ERR_WORKSPACE, "workspace smaller than hk_plan_workspace_size");
   if ((uintptr_t)ws % 256) return fail(HK_ERR_MISALIGNED, "workspace must be 256-byte aligned");
+  if ((p->flags & HK_PLAN_AUTOTUNE) && !p->persistent && !p->tuned && !p->tables_in_ws) {
+    s = tune_plan(p, (char *)ws, st);
+    if (!s.ok()) return s;
+  }
   p->last_stream = st;
   p->last_ws = ws;
   if (p->tables_in_ws) {
@@ -545,6 +592,107 @@ Status plan_execute(hk_plan_t p, void *ws, size_t ws_bytes, hipStream_t st) {
     return Status();
   }
   return enqueue(p, (char *)ws, st);
+}
+
+// HK_PLAN_AUTOTUNE, at the first execute: a coordinate descent over the
+// length buckets whose instances take odd-factor lengths (3 * 2^k, 5 * 2^k),
+// longest first: each is tried at powers of two and kept there when the whole
+// plan runs faster.  Odd lengths move fewer bytes but give each lane group
+// several sequences in turn, and which wins depends on the length and on how
+// much work the plan has of that length.  Every candidate is timed on the
+// caller's stream and workspace (its outputs are rewritten by the execute
+// that follows); the best plan replaces this one's contents.
+static Status time_plan(hk_plan_s *q, char *ws, hipStream_t st, double *ms) {
+  Status s = upload_tables(q);
+  if (!s.ok()) return s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  std::vector<float> t;
+  for (int w = 0; w < 2 && s.ok(); ++w) s = enqueue(q, ws, st);  // warm-up
+  for (int r = 0; r < 5 && s.ok() && e == hipSuccess; ++r) {
+    e = hipEventRecord(e0, st);
+    for (int k = 0; k < 3 && s.ok() && e == hipSuccess; ++k) s = enqueue(q, ws, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float v = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&v, e0, e1);
+    t.push_back(v / 3.0f);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (!s.ok()) return s;
+  if (e != hipSuccess) return hip_fail(e, "plan timing");
+  std::sort(t.begin(), t.end());
+  *ms = t[t.size() / 2];
+  return Status();
+}
+
+static Status tune_plan(hk_plan_s *p, char *ws, hipStream_t st) {
+  p->tuned = true;
+  // buckets with odd-factor lengths in the default plan
+  std::vector<int> buckets;
+  for (int64_t i = 0; i < p->count; ++i) {
+    const Shape &sh = p->shapes[i];
+    if (sh.is_block || sh.odd == 1) continue;
+    const int b = length_bucket(problem_of(p->dt, p->probs[i]));
+    if (b < 32 && std::find(buckets.begin(), buckets.end(), b) == buckets.end()) buckets.push_back(b);
+  }
+  std::sort(buckets.rbegin(), buckets.rend());
+  double best = 0.0;
+  Status s = time_plan(p, ws, st, &best);
+  if (!s.ok()) return s;
+  p->tune_ms_default = best;
+  uint32_t best_mask = p->pow2_buckets;
+  hk_plan_t best_plan = nullptr;
+  for (int b : buckets) {
+    hk_plan_t q = nullptr;
+    s = plan_build(&q, p->dt, p->probs.data(), p->count, p->flags, best_mask | (1u << b));
+    if (!s.ok()) break;
+    double t = 0.0;
+    s = time_plan(q, ws, st, &t);
+    if (!s.ok()) {
+      plan_destroy(q);
+      break;
+    }
+    if (t < 0.97 * best) {  // eager timings of one plan vary by a few percent
+      best = t;
+      best_mask |= 1u << b;
+      if (best_plan) plan_destroy(best_plan);
+      best_plan = q;
+    } else {
+      plan_destroy(q);
+    }
+  }
+  if (!s.ok()) {
+    if (best_plan) plan_destroy(best_plan);
+    return s;
+  }
+  p->tune_ms_best = best;
+  if (best_plan) {
+    // take the winner's task lists, tables and streams; the old ones leave
+    // with the temporary plan
+    std::vector<hk_problem_t> probs;
+    probs.swap(p->probs);
+    const size_t tune_ws = p->tune_ws_bytes;
+    const double d0 = p->tune_ms_default;
+    std::swap(*p, *best_plan);
+    p->probs.swap(probs);
+    p->tune_ws_bytes = tune_ws;
+    p->tune_ms_default = d0;
+    p->tune_ms_best = best;
+    p->tuned = true;
+    plan_destroy(best_plan);
+  }
+  return Status();
+}
+
+Status plan_tune_times(hk_plan_t p, double *ms_default, double *ms_tuned, uint32_t *pow2_buckets) {
+  if (!p) return fail(HK_ERR_NULL_POINTER, "plan is NULL");
+  if (ms_default) *ms_default = p->tune_ms_default;
+  if (ms_tuned) *ms_tuned = p->tune_ms_best;
+  if (pow2_buckets) *pow2_buckets = p->pow2_buckets;
+  return Status();
 }
 
 Status plan_status(hk_plan_t p) {

@@ -12,6 +12,7 @@ Status plan_status(hk_plan_t plan);
 Status plan_destroy(hk_plan_t plan);
 Status plan_set_wait_bound(hk_plan_t plan, uint32_t spins);
 Status plan_pass_bytes(hk_plan_t plan, int64_t *bytes);
+Status plan_tune_times(hk_plan_t plan, double *ms_default, double *ms_tuned, uint32_t *pow2_buckets);
 // One-shot execution keeps the descriptor tables in the caller's workspace
 // (no plan-owned device memory).
 Status plan_set_oneshot(hk_plan_t plan);

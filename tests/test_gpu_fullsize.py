@@ -146,9 +146,10 @@ def test_large_single_vandermonde_all_outputs():
     assert ea <= TOL[dtype]
 
 
-@pytest.mark.parametrize("flags", ["persistent", "grouped"])
+@pytest.mark.parametrize("flags", ["persistent", "grouped", "grouped_autotune"])
 def test_mixed_batch_all_instances(flags):
-    """All 4096 mixed instances in one plan, sampled outputs against the oracle."""
+    """All 4096 mixed instances in one plan, sampled outputs against the oracle
+    (autotune: the plan the first execute's tuner keeps, executed twice)."""
     import paper_1401_6238_amd as hk
     from paper_1401_6238_amd import _lib
     g = golden("mixed_batch")
@@ -168,8 +169,15 @@ def test_mixed_batch_all_instances(flags):
     same_inputs(g["mixed_fp_h"][0], probs[0].h)
     same_inputs(g["mixed_fp_h"][4095], probs[4095].h)
     f = _lib.HK_PLAN_PERSISTENT if flags == "persistent" else _lib.HK_PLAN_MULTIKERNEL
+    if flags == "grouped_autotune":
+        f |= _lib.HK_PLAN_AUTOTUNE
     plan = hk.Plan(items, flags=f)
     outs = plan.execute()
+    if flags == "grouped_autotune":
+        t0, t1, mask = plan.tune_times()
+        print(f"autotune: default {t0:.3f} ms, kept {t1:.3f} ms, power-of-two buckets {mask:#x}")
+        assert 0.0 < t1 <= t0
+        outs = plan.execute()
     plan.status()
     off, idx, ys = g["mixed_off"], g["mixed_idx"], g["mixed_y"]
     worst = 0.0
