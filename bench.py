@@ -1073,13 +1073,16 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
         for b in range(Hs.shape[0]):
             hk.block_hankel_tvp(Hs[b], [Xs[b]] * 3, [512] * 3, [512] * 3, True, True)
     ms5p = time_region(torch, plain5, 1, warm=1)
-    # pass model per tensor (grid 2048 x 2048, c64): pass A reads H (1534^2) and X (512^2)
-    # and writes 1534 + 512 storage columns of 2048; pass B reads them and writes the 512
-    # output columns pass D reads; pass D reads those and writes Y (512^2) and alpha
-    G, hr, nx = 2048, 1534, 512
-    blk_bytes = 8 * ((hr * hr + nx * nx + (hr + nx) * G) + ((hr + nx) * G + nx * G) + (nx * G + nx * nx + 1))
+    # pass model per tensor (c64) on the grid the call uses (G_r x G_c: 1536^2 with the
+    # factor 3 on both axes, 2048^2 with powers of two): pass A reads H (1534^2) and X
+    # (512^2) and writes their 1534 + 512 storage columns of G_c; pass B reads them and
+    # writes the 512 output columns pass D reads; pass D reads those, writes Y and alpha
+    gr_, gc_ = hk.block_hankel_tvp_layout(torch.complex64, 3, [512] * 3, [512] * 3, 64)
+    hr, nx = 1534, 512
+    blk_bytes = 8 * ((hr * hr + nx * nx + (hr + nx) * gc_) + ((hr + nx) * gc_ + nx * gc_) + (nx * gc_ + nx * nx + 1))
     ex["block_batch_c64"] = {"batched_TVP_s": round(64 / ms5 * 1000, 2), "plain_loop_TVP_s": round(64 / ms5p * 1000, 2),
-                             "us_per_tensor": round(ms5 * 1e3 / 64, 2), "pass_model_MB_per_tensor": round(blk_bytes / 1e6, 1),
+                             "us_per_tensor": round(ms5 * 1e3 / 64, 2), "grid": [gr_, gc_],
+                             "pass_model_MB_per_tensor": round(blk_bytes / 1e6, 1),
                              "roofline": roof(64 * blk_bytes, ms5, "k_cols / k_rows (BHHB strided batch)")}
     log("block batch", ex["block_batch_c64"])
 

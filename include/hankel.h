@@ -21,8 +21,9 @@
  * transform of 3 or 5 sequences of length 2^k through the Chinese-remainder
  * index map (no twiddles between the factors), which keeps the padding below
  * 25% of d_H for most lengths instead of up to 100%.  The 2-level block
- * (BHHB) form uses 2D FFTs of power-of-two sizes on a grid of at least
- * (sum n_p - m + 1) x (sum N_p - m + 1) (Section 3, BHHB procedure).
+ * (BHHB) form uses 2D FFTs on a grid of at least (sum n_p - m + 1) x
+ * (sum N_p - m + 1) (Section 3, BHHB procedure), each axis 2^k, 3 * 2^k or
+ * 5 * 2^k (block_hankel_tvp_layout).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -208,6 +209,15 @@ hk_status_t hankel_tvp_spectral_strided_batched(hk_dtype_t dt, const void *h_spe
  *                n_1 x N_1 column-major matrix
  *   alpha      : if non-NULL, receives H x_1 ... x_m (needs vectors[0])
  * ------------------------------------------------------------------------- */
+/* The transform grid of a BHHB shape (rows along the in-block index, columns
+ * along the block index) for a call of `batch` instances under the current
+ * length policy: each axis is the smallest of 2^k, 3 * 2^k, 5 * 2^k (complex
+ * dtypes; odd column factors with an odd row factor) >= its extent
+ * (sum n_p - m + 1, sum N_p - m + 1) that has kernels, or the power of two.
+ * An axis of length odd * 2^k is transformed as `odd` sequences of 2^k
+ * through the Chinese-remainder index map.  Host-only. */
+hk_status_t block_hankel_tvp_layout(hk_dtype_t dt, int m, const int64_t *inner_dims, const int64_t *block_dims,
+                                    int64_t batch, int64_t *grid_rows, int64_t *grid_cols);
 hk_status_t block_hankel_tvp_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims,
                                             const int64_t *block_dims, const void *const *vectors,
                                             int want_y, int want_alpha, size_t *bytes);

@@ -68,6 +68,7 @@ _SIGS = {
     "hankel_tvp_backward_spectral": [_I, _P, _I, _I64, _P, _P, _P, _P, _P, _P, _SZ, _P],
     "hankel_tvp_spectral_strided_batched": [_I, _P, _I, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _SZ, _P],
     "block_hankel_tvp_workspace_size": [_I, _I, _PI64, _PI64, _P, _I, _I, _PSZ],
+    "block_hankel_tvp_layout": [_I, _I, _PI64, _PI64, _I64, _PI64, _PI64],
     "block_hankel_tvp": [_I, _P, _I, _PI64, _PI64, _P, _P, _P, _P, _SZ, _P],
     "block_hankel_tvp_levels_workspace_size": [_I, _I, _I, _PI64, _P, _I, _I, _PSZ],
     "block_hankel_tvp_levels": [_I, _P, _I, _I, _PI64, _P, _P, _P, _P, _SZ, _P],

@@ -353,6 +353,15 @@ def block_hankel_tvp_backward(H: torch.Tensor, vectors: Sequence[Optional[torch.
     return _adjoint_distinct(True, H, vectors, inner_dims, block_dims, grad_y, grad_alpha, want, want_grad_h)
 
 
+def block_hankel_tvp_layout(dtype: torch.dtype, m: int, inner_dims: Sequence[int], block_dims: Sequence[int],
+                            batch: int = 1) -> Tuple[int, int]:
+    """(rows, cols) of the transform grid of a BHHB shape (each axis 2^k, 3 * 2^k or 5 * 2^k)."""
+    r, c = ctypes.c_int64(0), ctypes.c_int64(0)
+    check(lib().block_hankel_tvp_layout(_DT[dtype], m, _i64arr(inner_dims), _i64arr(block_dims), int(batch),
+                                        ctypes.byref(r), ctypes.byref(c)), "block_hankel_tvp_layout")
+    return r.value, c.value
+
+
 def block_hankel_tvp_levels(G: torch.Tensor, vectors: Sequence[Optional[torch.Tensor]], dims,
                             want_y: bool = True, want_alpha: bool = False):
     """Level-k block Hankel tensor (k = len(dims)): G is the column-major

@@ -994,6 +994,22 @@ hk_status_t block_hankel_tvp_backward(hk_dtype_t dt, const void *H, int m, const
                                  grad_H, ws, ws_bytes, nullptr, stream));
 }
 
+hk_status_t block_hankel_tvp_layout(hk_dtype_t dt, int m, const int64_t *inner_dims, const int64_t *block_dims,
+                                    int64_t batch, int64_t *grid_rows, int64_t *grid_cols) {
+  if (!grid_rows || !grid_cols) return finish(fail(HK_ERR_NULL_POINTER, "grid_rows or grid_cols is NULL"));
+  const void *vecs[HK_MAX_ORDER];
+  for (int q = 0; q < HK_MAX_ORDER; ++q) vecs[q] = (const void *)256;
+  Problem p;
+  Status s = block_problem(dt, (const void *)256, m, inner_dims, block_dims, vecs, (void *)256, nullptr, &p);
+  if (!s.ok()) return finish(s);
+  Layout lay;
+  s = layout_for(p, 0, &lay, true, std::max<int64_t>(1, batch));
+  if (!s.ok()) return finish(s);
+  *grid_rows = (int64_t)lay.odd << lay.logR;
+  *grid_cols = (int64_t)lay.odd_c << lay.logC;
+  return finish(Status());
+}
+
 hk_status_t block_hankel_tvp_workspace_size(hk_dtype_t dt, int m, const int64_t *inner_dims, const int64_t *block_dims,
                                             const void *const *vectors, int want_y, int want_alpha, size_t *bytes) {
   if (!bytes) return finish(fail(HK_ERR_NULL_POINTER, "bytes is NULL"));

@@ -291,7 +291,8 @@ static Status plan_build(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *prob
     }
     Layout lay;
     const bool forced = !pr.is_block && ((pow2_buckets >> std::min(31, length_bucket(pr))) & 1u);
-    s = layout_for(pr, 0, &lay, allow_odd && !forced, count);
+    // the grouped and persistent kernels run BHHB on power-of-two grids
+    s = layout_for(pr, 0, &lay, allow_odd && !forced && !pr.is_block, count);
     if (!s.ok()) {
       delete p;
       return fail(s.code, "problem " + std::to_string(i) + ": " + s.msg);

@@ -218,10 +218,22 @@ __device__ __forceinline__ void store_out(void *base, int64_t idx, cx<T> v, int 
     ((cx<T> *)base)[idx] = v;
 }
 
-// Length M = 2^(logR + logC) of one sequence and length N = odd * M of the
-// transform.
-__device__ __forceinline__ int64_t seq_len(const Shape &sh) { return (int64_t)1 << (sh.logR + sh.logC); }
-__device__ __forceinline__ int64_t fft_len(const Shape &sh) { return (int64_t)sh.odd << (sh.logR + sh.logC); }
+// Storage of one sequence and of a whole transform.  1D: a sequence has
+// M = 2^(logR + logC) elements and the transform N = odd * M.  BHHB with odd
+// factors: the grid (odd R) x (odd_c C) holds `odd` sequences along the row
+// axis, each of odd_c C rows of R elements (after the column pass, row
+// r = q_c C + k2 is bin k2 of the column transform's power-of-two axis and bin
+// q_c of its odd axis), so M = odd_c R C.
+__device__ __forceinline__ int oddc_of(const Shape &sh) { return sh.odd_c > 1 ? sh.odd_c : 1; }
+__device__ __forceinline__ int64_t seq_len(const Shape &sh) { return (int64_t)oddc_of(sh) << (sh.logR + sh.logC); }
+__device__ __forceinline__ int64_t fft_len(const Shape &sh) { return (int64_t)sh.odd * seq_len(sh); }
+// Rows of the row pass: the storage grid's rows, odd_c C of them for BHHB.
+__device__ __forceinline__ int64_t pass_rows(const Shape &sh) { return (int64_t)oddc_of(sh) << sh.logC; }
+// BHHB grids with an odd row factor keep each workspace row (odd R elements)
+// in natural order of the row index i: the column passes then read and
+// write whole runs of consecutive i (the nonzero and the kept ones exactly),
+// and the row pass gathers sequence q's position c from i = c + R tau.
+__device__ __forceinline__ bool block_natural(const Shape &sh) { return sh.is_block && sh.odd > 1; }
 
 // Multipass workspace: nbuf buffers of N elements (sequence q of a buffer at
 // q * M), then the row pass's scalar partial sums.  ODDF: the shape may have
@@ -245,7 +257,7 @@ __device__ __forceinline__ cx<T> *ws_partials(const Shape &sh, const PV &P) {
 // real-input transforms are stored in pairs.  The row pass stores only these
 // columns of its output rows.
 __device__ __forceinline__ int64_t out_cols_read(const Shape &sh, int which) {
-  const int64_t R = (int64_t)1 << sh.logR;
+  const int64_t R = (int64_t)(sh.is_block && sh.odd > 1 ? sh.odd : 1) << sh.logR;
   const int64_t len = which == 0 ? (sh.r2c ? (sh.out_rows + 1) / 2 : sh.out_rows) : sh.out1_len;
   return len < R ? len : R;
 }
@@ -683,6 +695,20 @@ struct RowBody {
 #pragma unroll
       for (int s = 0; s < EE; ++s) ok[s] = valid_row && idx[s] < od.len;
       gather<T, EE>(a, P.op(o), idx, ok, od.flags);
+    } else if (sh.is_block) {
+      // BHHB: row `row` of the column transform in natural order of i;
+      // sequence q's position c is entry i = c + L tau; entries at or past
+      // ncol_nz (the operand's rows) were never written and read as zero
+      int tau[EE];
+      crt_tau<EE>(tau, q, (uint32_t)t, (uint32_t)TPS, ODD, sh.odd_inv);
+      const auto r = make_buf(ws_buf<T, true>(sh, P, od.buf), fft_len(sh) * (int64_t)sizeof(cx<T>));
+      const uint32_t rbase = (uint32_t)(row * (ODD * L) * (int64_t)sizeof(cx<T>));
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        const int i = t + s * TPS + L * tau[s];
+        off[s] = (valid_row && i < od.ncol_nz) ? rbase + (uint32_t)(i * (int)sizeof(cx<T>)) : OOB_OFF;
+      }
+      bgather<T, EE>(a, r, off, 0);
     } else {
       // row `row` of sequence q of the operand's column transform; its
       // columns past ncol_nz were never written and read as zero
@@ -712,6 +738,19 @@ struct RowBody {
 #pragma unroll
       for (int s = 0; s < EE; ++s)
         if (idx[s] < lim) store_out<T>(dst, idx[s], cj ? cconj(a[s]) : a[s], sh.real_out);
+    } else if (sh.is_block) {
+      // BHHB: natural order of i; only the entries the output's column pass
+      // reads (i < out_rows) are stored
+      int tau[EE];
+      crt_tau<EE>(tau, q, (uint32_t)t, (uint32_t)TPS, ODD, sh.odd_inv);
+      const auto r = make_buf(ws_buf<T, true>(sh, P, sh.ops[which].buf), fft_len(sh) * (int64_t)sizeof(cx<T>));
+      const uint32_t rbase = (uint32_t)(row * (ODD * L) * (int64_t)sizeof(cx<T>));
+      const int keep = (int)out_cols_read(sh, which);
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        const int i = t + s * TPS + L * tau[s];
+        BufIO<T>::template st<ST_DEFAULT>(a[s], r, i < keep ? rbase + (uint32_t)(i * (int)sizeof(cx<T>)) : OOB_OFF);
+      }
     } else {
       const int64_t M = seq_len(sh);
       const auto r = make_buf(ws_buf<T, true>(sh, P, sh.ops[which].buf), ODD * M * (int64_t)sizeof(cx<T>));
@@ -802,8 +841,8 @@ struct RowBody {
   static __device__ __forceinline__ cx<T> run_fwd_odd(const Shape &sh, const PV &P, int64_t row0, int rstride,
                                                       int K, bool valid0, int t, cx<T> *lds, bool resident,
                                                        const cx<T> *tw24, const cx<T> *tw4096) {
-    const int64_t C = (int64_t)1 << sh.logC;
-    const T invN = T(1) / T((int64_t)ODD << (sh.logR + sh.logC));
+    const int64_t C = pass_rows(sh);
+    const T invN = T(1) / T(fft_len(sh));
     cx<T> nx[EE], w[EE];
     Seqs h, acc;
     cx<T> part = czero<T>();
@@ -1217,6 +1256,106 @@ struct ColBody {
         for (int s = 0; s < EE; ++s)
           bstore<T, POL>(r, (uint32_t)((c + sh.out_rows * (t + s * TPS)) * es), job.conj_out ? cconj(a[s]) : a[s],
                          sh.real_out);
+      }
+    }
+  }
+
+  // BHHB grids with odd factors: rows odd * R (row axis i), columns
+  // ODDC * C (column axis j), each axis through its own Chinese-remainder
+  // map (i <-> (i mod odd, i mod R), j <-> (j mod ODDC, j mod C)).  The
+  // workspace keeps i in natural order (the row pass applies the row axis's
+  // map), so a tile is TW consecutive matrix rows i and only rows that can be
+  // nonzero (pass A) or are kept (pass D) are transformed.  The ODDC column
+  // sequences (index q_c) of a row are held side by side in the lane (slot s
+  // of sequence q_c at position t + s TPS), each transformed along the
+  // power-of-two axis, and a length-ODDC DFT across them per bin completes
+  // the column axis (after the power-of-two transforms in the inputs' pass,
+  // before them in the output's: the two factors commute).  Workspace row
+  // r = q_c C + k2 holds bin k2 of the power-of-two axis, bin q_c of the odd one.
+  template <int ODDC>
+  static __device__ __forceinline__ void run_block_odd(const Shape &sh, const PV &P, const ColJob &job, int64_t v0,
+                                                       int TW, int tid, cx<T> *lds, const cx<T> *tw4096) {
+    const int cw = tid % TW;
+    const int t = tid / TW;
+    const int64_t i = v0 + cw;  // matrix row
+    const bool cvalid = i < job.ncols;
+    const int64_t C = (int64_t)1 << sh.logC;
+    const int64_t W = (int64_t)(sh.odd > 1 ? sh.odd : 1) << sh.logR;  // workspace row length
+    constexpr int CB = (int)sizeof(cx<T>);
+    cx<T> a[ODDC][EE];
+    if (job.kind == COL_A) {
+      // generating matrix / vec(X_p): len rows x cols columns, column-major;
+      // columns past cols fall past the end of the resource
+      const OpDesc &od = sh.ops[job.op];
+      const int es = elem_size<T>(od.flags);
+      const auto r = make_buf(P.op(job.op), od.len * od.cols * es);
+#pragma unroll
+      for (int qc = 0; qc < ODDC; ++qc) {
+        int tau[EE];
+        if constexpr (ODDC > 1) crt_tau<EE>(tau, qc, (uint32_t)t, (uint32_t)TPS, ODDC, sh.odd_c_inv);
+        uint32_t off[EE];
+#pragma unroll
+        for (int s = 0; s < EE; ++s) {
+          const int64_t j = t + s * TPS + (ODDC > 1 ? C * tau[s] : 0);
+          off[s] = cvalid ? (uint32_t)((i + od.len * j) * es) : OOB_OFF;
+        }
+        bgather<T, EE>(a[qc], r, off, od.flags);
+      }
+    } else {
+      const auto r = make_buf(ws_buf<T, true>(sh, P, job.buf), fft_len(sh) * CB);
+#pragma unroll
+      for (int qc = 0; qc < ODDC; ++qc) {
+        uint32_t off[EE];
+#pragma unroll
+        for (int s = 0; s < EE; ++s)
+          off[s] = cvalid ? (uint32_t)(((qc * C + t + s * TPS) * W + i) * CB) : OOB_OFF;
+        bgather<T, EE>(a[qc], r, off, 0);
+      }
+    }
+    StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
+    auto odd_axis = [&]() {
+      if constexpr (ODDC > 1) {
+#pragma unroll
+        for (int s = 0; s < EE; ++s) {
+          cx<T> w[ODDC];
+#pragma unroll
+          for (int qc = 0; qc < ODDC; ++qc) w[qc] = a[qc][s];
+          dft_odd<T, ODDC>(w);
+#pragma unroll
+          for (int qc = 0; qc < ODDC; ++qc) a[qc][s] = w[qc];
+        }
+      }
+    };
+    if (job.kind == COL_D) odd_axis();
+    // TW interleaved columns: element k of column cw at lds[(sw(k) << log2 TW) + cw]
+#pragma unroll
+    for (int qc = 0; qc < ODDC; ++qc) fft_seq<T, L, E>(a[qc], t, lds + cw, stw, __builtin_ctz((unsigned)TW));
+    if (job.kind == COL_A) odd_axis();
+    if (!cvalid) return;
+    if (job.kind == COL_A) {
+      const auto r = make_buf(ws_buf<T, true>(sh, P, job.buf), fft_len(sh) * CB);
+#pragma unroll
+      for (int qc = 0; qc < ODDC; ++qc)
+#pragma unroll
+        for (int s = 0; s < EE; ++s)
+          BufIO<T>::template st<ST_DEFAULT>(a[qc][s], r, (uint32_t)(((qc * C + t + s * TPS) * W + i) * CB));
+    } else {
+      // out_rows x out_cols corner of the output grid, column-major; columns
+      // past out_cols fall past the end of the resource
+      void *dst = job.op == 0 ? P.y() : P.out1();
+      const int eo = sh.real_out ? (int)sizeof(T) : CB;
+      const auto r = make_buf(dst, sh.out_rows * sh.out_cols * eo);
+#pragma unroll
+      for (int qc = 0; qc < ODDC; ++qc) {
+        int tau[EE];
+        if constexpr (ODDC > 1) crt_tau<EE>(tau, qc, (uint32_t)t, (uint32_t)TPS, ODDC, sh.odd_c_inv);
+#pragma unroll
+        for (int s = 0; s < EE; ++s) {
+          const int64_t j = t + s * TPS + (ODDC > 1 ? C * tau[s] : 0);
+          bstore<T, ST_DEFAULT>(r, (uint32_t)((i + sh.out_rows * j) * eo), job.conj_out ? cconj(a[qc][s]) : a[qc][s],
+                                sh.real_out);
+        }
       }
     }
   }

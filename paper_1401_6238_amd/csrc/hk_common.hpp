@@ -88,6 +88,9 @@ struct Shape {
   int32_t r2c;         // real inputs, resident: length-N real transforms as length-N/2
                        // complex ones (logR = log2(N/2)); forward program only
   int32_t fwd_flags;   // forward program variants (ShapeFlag bits)
+  int32_t odd_c;       // BHHB: odd factor of the column (block-index) axis, 0 or 1 = none;
+                       // the row axis takes `odd` (see hk_bodies.hpp, BHHB with odd factors)
+  int32_t odd_c_inv;   // BHHB: C^{-1} mod odd_c (C = 2^logC)
   int64_t out_rows;    // output slice: 1D length / BHHB rows n_1; adjoint grad_h length
   int64_t out_cols;    // BHHB columns N_1 (1 for 1D)
   int64_t out1_len;    // adjoint grad_x length

@@ -36,6 +36,15 @@ template <int L, int E>
 static void *col_fn(int var) {
   if (var == CV_ODD) return (void *)&k_cols<L, E, COL_MAXT, CV_ODD>;
   if (var == CV_R2C) return (void *)&k_cols<L, E, COL_MAXT, CV_R2C>;
+  if (var >= CV_BODD1) {
+    // BHHB grids with odd factors: columns of 2^6 .. 2^11 points per sequence
+    if constexpr (L >= 64 && L <= 2048) {
+      if (var == CV_BODD1) return (void *)&k_cols<L, E, COL_MAXT, CV_BODD1>;
+      if (var == CV_BODD3) return (void *)&k_cols<L, E, COL_MAXT, CV_BODD3>;
+      return (void *)&k_cols<L, E, COL_MAXT, CV_BODD5>;
+    }
+    return nullptr;
+  }
   return (void *)&k_cols<L, E, COL_MAXT, CV_POW2>;
 }
 
@@ -229,7 +238,9 @@ hipError_t HK_CAT(launch_cols_, HK_SUFFIX)(int logL, int E, int tw, int xcd, dim
                                            const Ptrs &p0, const Strides &str, const ColJob *jobs, int njobs,
                                            hipStream_t st) {
   using namespace HK_NS;
-  void *fn = col_kernel(logL, E, sh.r2c ? CV_R2C : (sh.odd > 1 ? CV_ODD : CV_POW2));
+  int var = sh.r2c ? CV_R2C : (sh.odd > 1 ? CV_ODD : CV_POW2);
+  if (sh.is_block && (sh.odd > 1 || sh.odd_c > 1)) var = sh.odd_c == 5 ? CV_BODD5 : (sh.odd_c == 3 ? CV_BODD3 : CV_BODD1);
+  void *fn = col_kernel(logL, E, var);
   KernelLimits k;
   if (!fn || !HK_CAT(limits_, HK_SUFFIX)(logL, E, &k)) return hipErrorInvalidValue;
   const int threads = tw * k.tps;

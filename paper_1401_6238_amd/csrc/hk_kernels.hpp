@@ -167,7 +167,10 @@ __device__ __forceinline__ Tile3 xcd_local_tile() {
 
 // Column-kernel variants: power-of-two complex transforms, odd factor 3 or 5
 // (tiles over virtual columns), real inputs (real arrays as complex pairs).
-enum ColVar : int { CV_POW2 = 0, CV_ODD = 1, CV_R2C = 2 };
+enum ColVar : int { CV_POW2 = 0, CV_ODD = 1, CV_R2C = 2, CV_BODD1 = 3, CV_BODD3 = 4, CV_BODD5 = 5 };
+// BHHB grids with odd factors: CV_BODD<k> tiles the row axis's odd * R
+// virtual columns and carries the column axis's odd factor k (1: none).
+constexpr int bodd_factor(int var) { return var == CV_BODD5 ? 5 : (var == CV_BODD3 ? 3 : 1); }
 template <int L, int E, int MAXT, int VAR = CV_POW2>
 __global__ void __launch_bounds__(MAXT) k_cols(Shape sh, Ptrs p0, Strides str, ColJobs jobs) {
   using CB = ColBody<T, L, E>;
@@ -190,6 +193,10 @@ __global__ void __launch_bounds__(MAXT) k_cols(Shape sh, Ptrs p0, Strides str, C
     if (v0 >= (int64_t)sh.odd * R) return;
     if (TW <= R && (v0 & (R - 1)) >= job.ncols) return;
     CB::run_odd(sh, P, job, v0, TW, threadIdx.x, smem, g_tw24, g_tw4096);
+  } else if constexpr (VAR >= CV_BODD1) {
+    // tiles over the matrix rows that can be nonzero (pass A) or are kept (pass D)
+    if (v0 >= job.ncols) return;
+    CB::template run_block_odd<bodd_factor(VAR)>(sh, P, job, v0, TW, threadIdx.x, smem, g_tw4096);
   } else if constexpr (VAR == CV_R2C) {
     if (v0 >= job.ncols) return;
     CB::run_r2c(sh, P, job, v0, TW, threadIdx.x, smem, g_tw24, g_tw4096);

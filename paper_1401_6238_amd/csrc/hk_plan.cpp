@@ -173,10 +173,14 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int6
   if (p.conv || p.conj_y) allow_odd = false;
   const bool allow_r2c = allow_odd && policy != HK_LENGTHS_POW2;
   if (policy == HK_LENGTHS_POW2) allow_odd = false;
-  if (allow_odd && policy == HK_LENGTHS_AUTO && !p.is_block) {
-    int64_t dh = 1 - p.m;
-    for (int q = 0; q < p.m; ++q) dh += p.dims[q];
-    const int64_t n2 = (int64_t)1 << std::max(0, ceil_log2(dh));
+  if (allow_odd && policy == HK_LENGTHS_AUTO) {
+    int64_t dh = 1 - p.m, dc = 1 - p.m;
+    for (int q = 0; q < p.m; ++q) {
+      dh += p.dims[q];
+      dc += p.bdims[q];
+    }
+    int64_t n2 = (int64_t)1 << std::max(0, ceil_log2(dh));
+    if (p.is_block) n2 <<= std::max(0, ceil_log2(dc));
     if (std::max<int64_t>(1, batch) * n2 < kOddWorkMin) allow_odd = false;
   }
   Layout lay;
@@ -244,6 +248,36 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int6
     if (lay.logR > MAX_LOGL || lay.logC > MAX_LOGL)
       return fail(HK_ERR_SIZE_LIMIT, "padded BHHB grid exceeds 4096 along an axis");
     lay.resident = false;
+    if (allow_odd && is_complex(p.dt)) {
+      // each axis takes the smallest of 2^k, 3 * 2^k, 5 * 2^k >= its extent;
+      // an odd row axis needs odd-factor row kernels of its 2^logR points, an
+      // odd column axis column kernels of 2^6 .. 2^11 points per sequence and
+      // an odd row axis (the power-of-two row bodies keep one sequence)
+      auto axis = [&](int64_t ext, int odd, int *logp) {
+        int l = 0;
+        while (((int64_t)odd << l) < ext) ++l;
+        *logp = l;
+        return (int64_t)odd << l;
+      };
+      int64_t best = ((int64_t)1 << lay.logR) << lay.logC;
+      for (int orow : {3, 5}) {
+        int lr = 0;
+        const int64_t nr = axis(rows, orow, &lr);
+        if (lr > odd_max_logl(p.dt, orow, p.prog)) continue;
+        for (int ocol : {1, 3, 5}) {
+          int lc = 0;
+          const int64_t nc = axis(cols, ocol, &lc);
+          if (lc > MAX_LOGL || (ocol > 1 && (lc < 6 || lc > 11))) continue;
+          if (nr * nc < best) {
+            best = nr * nc;
+            lay.odd = orow;
+            lay.odd_c = ocol;
+            lay.logR = lr;
+            lay.logC = lc;
+          }
+        }
+      }
+    }
   }
   *out = lay;
   return Status();
@@ -267,11 +301,17 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
   sh.r2c = lay.r2c ? 1 : 0;
   sh.odd = lay.odd;
   sh.odd_inv = 0;
-  if (lay.odd > 1) {
-    const int mr = (int)((((int64_t)1) << (lay.logR + lay.logC)) % lay.odd);
-    for (int v = 1; v < lay.odd; ++v)
-      if ((mr * v) % lay.odd == 1) sh.odd_inv = v;
-  }
+  // the Chinese-remainder maps need the power-of-two part's inverse modulo
+  // the odd factor: M = R C in 1D, R (rows) and C (columns) for BHHB
+  auto inv_mod = [](int64_t pow2, int odd) {
+    const int r = (int)(pow2 % odd);
+    for (int v = 1; v < odd; ++v)
+      if ((r * v) % odd == 1) return v;
+    return 0;
+  };
+  if (lay.odd > 1) sh.odd_inv = inv_mod((int64_t)1 << (p.is_block ? lay.logR : lay.logR + lay.logC), lay.odd);
+  sh.odd_c = lay.odd_c;
+  sh.odd_c_inv = lay.odd_c > 1 ? inv_mod((int64_t)1 << lay.logC, lay.odd_c) : 0;
   sh.real_out = is_complex(p.dt) ? 0 : 1;
   const int real_flag = is_complex(p.dt) ? 0 : OPF_REAL;
   const int64_t R = (int64_t)1 << lay.logR;
@@ -288,8 +328,10 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
     od.len = len;
     od.cols = cols;
     od.buf = sh.nops;
-    // storage columns that may be nonzero (real inputs: pairs of entries)
-    od.ncol_nz = std::min<int64_t>(R, lay.r2c ? (len + 1) / 2 : len);
+    // storage columns that may be nonzero (real inputs: pairs of entries;
+    // BHHB grids with an odd row factor: rows of the natural-order workspace)
+    const int64_t rw = (p.is_block && lay.odd > 1) ? (int64_t)lay.odd * R : R;
+    od.ncol_nz = std::min<int64_t>(rw, lay.r2c ? (len + 1) / 2 : len);
     P.op[sh.nops] = ptr;
     if (op_src) op_src[sh.nops] = src;
     ++sh.nops;
@@ -405,7 +447,7 @@ Status build_shape(const Problem &p, const Layout &lay, const Sched &sc, Shape *
     sh.partials = (int64_t)1 << MAX_LOGL;
     const size_t eb = cplx_bytes(p.dt);
     const size_t bytes =
-        (size_t)sh.nbuf * ((size_t)lay.odd << (lay.logR + lay.logC)) * eb + (size_t)sh.partials * eb;
+        (size_t)sh.nbuf * ((size_t)lay.odd * lay.odd_c << (lay.logR + lay.logC)) * eb + (size_t)sh.partials * eb;
     sh.ws_bytes = (int64_t)((bytes + 255) & ~(size_t)255);
   }
   *shp = sh;
@@ -433,7 +475,12 @@ int64_t pass_model_bytes(const Shape &sh, hk_dtype_t dt) {
   if (sh.want_alpha) out += es_out;
   if (sh.prog == PROG_BWD && sh.want_out1) out += sh.out1_len * es_out;
   if (sh.resident) return in + out;
-  const int64_t R = (int64_t)1 << sh.logR, C = (int64_t)1 << sh.logC, seq = (int64_t)sh.odd * C;
+  const int64_t C = (int64_t)1 << sh.logC;
+  // columns of one workspace row and rows per column: 1D, `odd` sequences of
+  // R x C; BHHB with an odd row factor, natural rows of odd R over odd_c C
+  const bool nat = sh.is_block && sh.odd > 1;
+  const int64_t R = (int64_t)(nat ? sh.odd : 1) << sh.logR;
+  const int64_t seq = (nat ? (int64_t)(sh.odd_c > 1 ? sh.odd_c : 1) : (int64_t)sh.odd) * C;
   int64_t a_write = 0, b_read = 0;
   for (int o = 0; o < sh.nops; ++o) {
     const OpDesc &od = sh.ops[o];
@@ -477,7 +524,7 @@ Sched default_sched(hk_dtype_t dt, const Layout &lay, int prog, int64_t batch) {
   Sched sc;
   const bool dbl = is_double(dt);
   sc.E_row = lay.r2c ? r2c_row_e(dt) : (lay.odd > 1 ? odd_row_e(dt) : 8);
-  sc.E_col = dbl ? 8 : 16;
+  sc.E_col = (dbl || lay.odd_c > 1) ? 8 : 16;
   KernelLimits kr, kc;
   layout_row_limits(dt, lay, sc.E_row, &kr);
   if (lay.odd == 1 && !lay.r2c && kr.tps > ROW_MAXT) {  // 4096-point rows need 16 elements per lane
@@ -647,9 +694,11 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
     max_cols = std::max(max_cols, ja[na].ncols);
     ++na;
   }
+  // BHHB grids with an odd row factor: the column passes tile the natural rows
+  const bool nat = sh.is_block && sh.odd > 1;
   if (na > 0) {
     // tiles over the storage columns of every sequence (virtual columns)
-    const int64_t vcols_a = sh.odd > 1 ? sh.odd * R : max_cols;
+    const int64_t vcols_a = (sh.odd > 1 && !nat) ? sh.odd * R : max_cols;
     dim3 ga((unsigned)((vcols_a + sc.tw - 1) / sc.tw), (unsigned)na, (unsigned)count);
     e = cols(dt, sh.logC, sc.E_col, sc.tw, sc.xcd, ga, sh, p0, str, ja, na, st);
     if (e != hipSuccess) return hip_fail(e, "pass A launch");
@@ -657,7 +706,7 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
   // Pass B: row transforms, spectral product, row transform of the output
   // (real inputs: C / 2 mirrored row pairs).
   const int64_t rows_wg = (int64_t)sc.rows_per_wg * sc.iters;  // rows (pairs) per workgroup
-  const int64_t brows = sh.r2c ? C / 2 : C;
+  const int64_t brows = sh.r2c ? C / 2 : C * (sh.odd_c > 1 ? sh.odd_c : 1);
   dim3 gb((unsigned)((brows + rows_wg - 1) / rows_wg), (unsigned)count);
   e = rows(dt, sh.logR, sc.E_row, sc.rows_per_wg, gb, sh, p0, str, count, st);
   if (e != hipSuccess) return hip_fail(e, "pass B launch");
@@ -675,7 +724,7 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
     jd[nd].conj_out = (sh.prog == PROG_FWD && (sh.fwd_flags & SHF_CONJ_Y)) ? 1 : 0;
     jd[nd].npart = npart;
     // real outputs of real-input transforms are stored in pairs
-    jd[nd].ncols = std::min<int64_t>(R, sh.r2c ? (sh.out_rows + 1) / 2 : sh.out_rows);
+    jd[nd].ncols = std::min<int64_t>(nat ? sh.odd * R : R, sh.r2c ? (sh.out_rows + 1) / 2 : sh.out_rows);
     dcols = std::max(dcols, jd[nd].ncols);
     ++nd;
   }
@@ -689,7 +738,7 @@ Status launch_shape(hk_dtype_t dt, const Shape &sh, const Sched &sc, const Ptrs 
     ++nd;
   }
   if (nd > 0) {
-    const int64_t vcols_d = sh.odd > 1 ? sh.odd * R : dcols;
+    const int64_t vcols_d = (sh.odd > 1 && !nat) ? sh.odd * R : dcols;
     dim3 gd((unsigned)((vcols_d + sc.tw - 1) / sc.tw), (unsigned)nd, (unsigned)count);
     e = cols(dt, sh.logC, sc.E_col, sc.tw, sc.xcd, gd, sh, p0, str, jd, nd, st);
     if (e != hipSuccess) return hip_fail(e, "pass D launch");
@@ -811,6 +860,13 @@ Status sched_save(const char *path) {
   return ok ? Status() : fail(HK_ERR_INVALID_VALUE, std::string("error writing ") + path);
 }
 
+// Length classes of the schedule key (Layout::lclass): 1, 2 (real), 3, 5,
+// and for BHHB grids the row factor plus 16 times an odd column factor.
+static bool lclass_ok(int c) {
+  const int base = c % 16, col = c / 16;
+  return (base == 1 || base == 2 || base == 3 || base == 5) && (col == 0 || col == 3 || col == 5);
+}
+
 Status sched_load(const char *path, int *loaded) {
   if (!path) return fail(HK_ERR_NULL_POINTER, "path is NULL");
   FILE *f = fopen(path, "r");
@@ -848,7 +904,7 @@ Status sched_load(const char *path, int *loaded) {
       break;
     }
     const bool key_ok = k[0] >= HK_C64 && k[0] <= HK_F64 && (k[1] == PROG_FWD || k[1] == PROG_BWD) &&
-                        (k[2] == 0 || k[2] == 1) && (k[3] == 1 || k[3] == 2 || k[3] == 3 || k[3] == 5) && k[4] >= 0 &&
+                        (k[2] == 0 || k[2] == 1) && lclass_ok(k[3]) && k[4] >= 0 &&
                         k[4] <= HK_MAX_FFT_LOG2 && k[5] >= -1 && k[5] <= HK_MAX_FFT_LOG2 && k[6] >= 0 && k[6] <= 2;
     Sched s;
     s.E_row = v[0];

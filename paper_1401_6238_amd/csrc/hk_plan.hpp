@@ -68,11 +68,14 @@ struct Sched {
 
 struct Layout {
   bool resident = false;
-  int odd = 1;       // 1D: transform length odd * 2^(logR + logC)
+  int odd = 1;       // 1D: transform length odd * 2^(logR + logC); BHHB: rows odd * 2^logR
+  int odd_c = 1;     // BHHB: columns odd_c * 2^logC
   bool r2c = false;  // real inputs, resident: length 2^(logR + 1) real transforms
   int logR = 0, logC = 0;
-  // length class of the schedule key: 1, 3, 5 = odd factor, 2 = real inputs
-  int lclass() const { return r2c ? 2 : odd; }
+  // length class of the schedule key: 1, 3, 5 = odd factor, 2 = real inputs;
+  // BHHB grids add 16 * the column axis's odd factor when it has one
+  int lclass() const { return (r2c ? 2 : odd) + (odd_c > 1 ? 16 * odd_c : 0); }
+  bool block_odd() const { return odd > 1 || odd_c > 1; }
 };
 
 bool is_complex(hk_dtype_t dt);

@@ -1,0 +1,89 @@
+"""GPU parity of BHHB products on grids with odd factors: each axis of the
+padded grid is 2^k, 3 * 2^k or 5 * 2^k, transformed as 3 or 5 power-of-two
+sequences through that axis's Chinese-remainder index map (the row axis in
+the row pass, the column axis in the column passes).  Every case checks the
+grid the planner picks, then compares y = vec(Y) and alpha with the CPU
+oracle's BHHB sums on exactly the inputs the GPU sees (n_p != N_p, distinct
+and equal vectors, single and strided-batched calls).  Tolerances: relative
+2-norm error <= 1e-12 (FP64) / 1e-4 (FP32), alpha at the same bound."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1401_6238_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import TOL, check_alpha, host, print_case, rel, seen, to_dev  # noqa: E402
+
+
+@pytest.fixture(autouse=True, scope="module")
+def smallest_lengths():
+    """Small grids take odd factors only under the 'smallest' length policy."""
+    import paper_1401_6238_amd as hk
+    hk.hk_set_fft_lengths("smallest")
+    yield
+    hk.hk_set_fft_lengths("auto")
+
+
+# (inner dims n_p, block dims N_p, dtype, expected grid)
+CASES = [
+    ((70, 60, 62), (100, 100, 102), torch.complex64, (192, 320)),     # 3 x 64 rows, 5 x 64 columns
+    ((70, 60, 62), (100, 100, 102), torch.complex128, (192, 320)),
+    ((130, 100, 80), (200, 150, 140), torch.complex64, (320, 512)),   # odd rows, power-of-two columns
+    ((50, 41), (90, 70), torch.complex64, (96, 192)),                 # m = 2
+    ((20, 30, 25, 18), (40, 36, 30, 33), torch.complex128, (96, 192)),
+]
+
+
+def grid_of(dims, bdims, dtype):
+    import paper_1401_6238_amd as hk
+    return hk.block_hankel_tvp_layout(dtype, len(dims), dims, bdims, 1)
+
+
+@pytest.mark.parametrize("dims,bdims,dtype,grid", CASES)
+@pytest.mark.parametrize("equal", [False, True])
+def test_block_odd_grid(dims, bdims, dtype, grid, equal):
+    import paper_1401_6238_amd as hk
+    m = len(dims)
+    if equal:
+        dims, bdims = (dims[0],) * m, (bdims[0],) * m
+        grid = grid_of(dims, bdims, dtype)
+    assert grid_of(dims, bdims, dtype) == grid
+    assert grid[0] % 2 or grid[0] & (grid[0] - 1)  # not both axes plain powers of two
+    print_case(test="block_odd", dims=dims, bdims=bdims, dtype=dtype, grid=grid, equal=equal)
+    prob = wl.random_problem(3100 + sum(dims) + sum(bdims), m, list(dims), equal, want_alpha=True,
+                             block_dims=list(bdims))
+    H = to_dev(prob.h, dtype)
+    vecs = [to_dev(v, dtype) for v in prob.vectors]
+    y, a = hk.block_hankel_tvp(H, vecs, list(dims), list(bdims), True, True)
+    torch.cuda.synchronize()
+    hs = seen(prob.h, dtype)
+    vs = [seen(v, dtype) for v in prob.vectors]
+    n_out = dims[0] * bdims[0]
+    idx = np.unique(np.concatenate([np.arange(min(64, n_out)), np.arange(max(0, n_out - 64), n_out),
+                                    np.random.default_rng(5).integers(0, n_out, 128)]))
+    yo, ao = oracle.block_tvp_sampled(m, list(dims), list(bdims), hs, vs, idx, want_alpha=True)
+    assert rel(host(y)[idx], yo) <= TOL[dtype]
+    check_alpha(complex(a), ao, dtype)
+
+
+def test_block_odd_strided_batch():
+    """A strided batch of BHHB tensors on a 5 x 5 odd grid, every instance
+    against the oracle."""
+    import paper_1401_6238_amd as hk
+    dims, bdims, dtype = (70,) * 3, (100,) * 3, torch.complex64
+    grid = hk.block_hankel_tvp_layout(dtype, 3, dims, bdims, 4)
+    assert grid == (320, 320), grid
+    probs = [wl.random_problem(3300 + b, 3, list(dims), True, want_alpha=True, block_dims=list(bdims))
+             for b in range(4)]
+    Hs = torch.stack([to_dev(p.h, dtype) for p in probs])
+    Xs = torch.stack([to_dev(p.vectors[1], dtype) for p in probs])
+    y, a = hk.block_hankel_tvp_strided_batched(Hs, Xs, 3, 70, 100, True, True)
+    torch.cuda.synchronize()
+    for b, p in enumerate(probs):
+        yo, ao = oracle.block_tvp(3, list(dims), list(bdims), seen(p.h, dtype), [seen(p.vectors[1], dtype)] * 3,
+                                  True, True)
+        assert rel(host(y[b]), yo) <= TOL[dtype]
+        check_alpha(complex(host(a[b:b + 1])[0]), ao, dtype, b)
