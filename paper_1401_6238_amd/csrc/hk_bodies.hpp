@@ -296,6 +296,26 @@ __device__ __forceinline__ cx<T> segment_sum(cx<T> v, cx<T> *red, int tid, int S
   return red[tid];
 }
 
+// Sum over the whole workgroup (blockDim.x a multiple of 64), valid in
+// thread 0: each wavefront folds its lanes with cross-lane shuffles (a fixed
+// butterfly order), then thread 0 adds the wavefronts' sums in index order.
+// Bitwise reproducible, two workgroup barriers.
+template <typename T>
+__device__ __forceinline__ cx<T> block_sum(cx<T> v, cx<T> *red, int tid) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    v.x += __shfl_xor(v.x, d, 64);
+    v.y += __shfl_xor(v.y, d, 64);
+  }
+  __syncthreads();  // the transforms' last LDS reads are done
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  cx<T> tot = czero<T>();
+  if (tid == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot = cadd(tot, red[w]);
+  return tot;
+}
+
 // ---------------------------------------------------------------------------
 // Row body: one sequence of length L per row; TPS lanes per row.  With ODD > 1
 // a row stands for the same row of the ODD sequences of the Z_odd x Z_M grid,
@@ -532,7 +552,23 @@ struct RowBody {
     cx<T> part = czero<T>();
     int64_t row = row0;
     bool valid = row < C;
-    load<SPEC>(a, sh, P, 0, row, valid, t, false);
+    // The (row, operand) items in processing order stream through two
+    // register sets: `a` holds the item being transformed and `nx` the next
+    // one, in flight.  The first two loads go out before the twiddle set-up,
+    // whose table reads would otherwise delay the second.
+    int nit = 0, nop = 0;  // the next item to load
+    auto load_item = [&](cx<T>(&dst)[EE]) {
+      if (nit < K) {
+        const int64_t r = row0 + (int64_t)nit * rstride;
+        load<SPEC>(dst, sh, P, nop, r, r < C, t, false);
+      }
+      if (++nop == sh.nops) {
+        nop = 0;
+        ++nit;
+      }
+    };
+    load_item(a);
+    load_item(nx);
     StageTw<T, L, E> stw;
     stw.init(t, tw4096);
     for (int it = 0; it < K; ++it) {
@@ -542,10 +578,6 @@ struct RowBody {
 #pragma unroll
       for (int s = 0; s < EE; ++s) acc[s] = mk(conv ? T(1) : T(0), T(0));
       for (int o = 0; o < sh.nops; ++o) {
-        if (o + 1 < sh.nops)
-          load<SPEC>(nx, sh, P, o + 1, row, valid, t, false);
-        else if (it + 1 < K)
-          load<SPEC>(nx, sh, P, 0, nrow, nvalid, t, false);
         const OpDesc &od = sh.ops[o];
         if constexpr (SPEC) {
           const bool spec = (od.flags & OPF_SPEC) != 0;
@@ -592,6 +624,7 @@ struct RowBody {
         }
 #pragma unroll
         for (int s = 0; s < EE; ++s) a[s] = nx[s];
+        load_item(nx);
       }
       if (sh.want_y) {
         if (conv) {

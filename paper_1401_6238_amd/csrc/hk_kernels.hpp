@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
       // One partial sum per workgroup; the next kernel in the stream (pass D
       // or the reduction kernel) adds them in index order.  No cross-workgroup
       // fence is needed: the kernel boundary makes them visible.
-      const cx<T> tot = segment_sum(part, red, tid, (int)blockDim.x);
+      const cx<T> tot = (blockDim.x & 63) == 0 ? block_sum(part, red, tid) : segment_sum(part, red, tid, (int)blockDim.x);
       if (tid == 0) ws_partials<T>(sh, P)[blockIdx.x] = tot;
     }
   }
