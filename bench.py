@@ -291,6 +291,137 @@ def summarize_counters(fetch_dir, write_dir, dtype, calib_mib, command):
     return "\n".join(lines) + "\n"
 
 
+def _per_dispatch(d, ctr_names):
+    """{dispatch: (kernel name, {counter: value summed over dimensions}, vgprs)} of a --pmc run."""
+    out = {}
+    for r in _read_csv(d, "counter_collection.csv"):
+        if r["Counter_Name"] not in ctr_names:
+            continue
+        k = int(r["Dispatch_Id"])
+        e = out.setdefault(k, [r["Kernel_Name"], {}, int(float(r.get("VGPR_Count", 0) or 0))])
+        e[1][r["Counter_Name"]] = e[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def summarize_sq(dirs, command):
+    """Per-pass SQ counters of the large single product from --pmc runs (each
+    directory one set of counters), per wavefront."""
+    names = {"SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",
+             "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
+             "SQ_INSTS_VMEM_WR", "SQ_INSTS_SALU", "SQ_LDS_BANK_CONFLICT", "GRBM_GUI_ACTIVE"}
+    per_disp = {}  # pass -> counter -> mean per dispatch (over every run that has it)
+    ndisp = {}
+    for d in dirs:
+        disp = _per_dispatch(d, names)
+        order = sorted(disp)
+        kinds = classify_passes([disp[k][0] for k in order])
+        for k, kind in zip(order, kinds):
+            if not kind:
+                continue
+            for c, v in disp[k][1].items():
+                per_disp.setdefault(kind, {}).setdefault(c, []).append(v)
+            ndisp[kind] = max(ndisp.get(kind, 0), 1)
+    lines = ["# SQ counters per wavefront, large single product (order 4, n=2^18, N=2^20), c64",
+             "# from rocprofv3 --pmc runs of the same command (one counter set per run):"]
+    for c in command.split(" ;; "):
+        lines.append(f"#   {c}")
+    lines += ["# SQ_WAVE_CYCLES, SQ_ACTIVE_* and SQ_WAIT_* count per wavefront in units of 4 clocks; VALU busy =",
+              "# SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES (a wave64 VALU instruction occupies its SIMD for 4 clocks)",
+              "", "| pass | waves / dispatch | VALU instr / wave | LDS instr / wave | VMEM rd / wr per wave | "
+              "SALU / wave | wave lifetime (us at 2.4 GHz) | VALU busy | waiting on dependencies | waiting (any) |",
+              "|---|---|---|---|---|---|---|---|---|---|"]
+    for kind in ("pass_a", "pass_b", "pass_d"):
+        if kind not in per_disp:
+            continue
+        m = {c: float(np.mean(v)) for c, v in per_disp[kind].items()}
+        waves = m.get("SQ_WAVES", 0.0)
+        if not waves:
+            continue
+        per = lambda c: m[c] / waves if c in m else None  # noqa: E731
+        wc = per("SQ_WAVE_CYCLES")
+        f0 = lambda v: "" if v is None else f"{v:.0f}"  # noqa: E731
+        pc = lambda c: "" if per(c) is None or not wc else f"{per(c) / wc:.0%}"  # noqa: E731
+        vm = "" if per("SQ_INSTS_VMEM_RD") is None else f"{per('SQ_INSTS_VMEM_RD'):.0f} / {per('SQ_INSTS_VMEM_WR'):.0f}"
+        life = "" if not wc else f"{wc * 4 / 2.4e3:.1f}"
+        lines.append(f"| {kind} | {waves:.0f} | {f0(per('SQ_INSTS_VALU'))} | {f0(per('SQ_INSTS_LDS'))} | {vm} | "
+                     f"{f0(per('SQ_INSTS_SALU'))} | {life} | {pc('SQ_ACTIVE_INST_VALU')} | {pc('SQ_WAIT_INST_ANY')} | "
+                     f"{pc('SQ_WAIT_ANY')} |")
+    return "\n".join(lines) + "\n"
+
+
+def summarize_block_counters(fetch_dir, write_dir, calib_mib, command):
+    """FETCH_SIZE / WRITE_SIZE per pass of the block batch (64 BHHB tensors,
+    c64), per tensor, against the pass model of the grid the call used."""
+    res = {}
+    for tag, d, ctr in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        disp = _per_dispatch(d, {ctr})
+        order = sorted(disp)
+        names = [disp[k][0] for k in order]
+        kinds = classify_passes(names)
+        acc, copies = {}, []
+        for k, kind, name in zip(order, kinds, names):
+            v = disp[k][1].get(ctr, 0.0)
+            if kind:
+                acc.setdefault(kind, []).append(v)
+            elif "copy" in name.lower():
+                copies.append(v)
+        if not copies:
+            raise SystemExit(f"{ctr}: no copy dispatches found for the calibration")
+        res[tag] = {"factor": calib_mib * 1024.0 / float(np.median(copies)),
+                    "kib": {k: float(np.mean(v)) for k, v in acc.items()}, "n": {k: len(v) for k, v in acc.items()}}
+    G, hr, nx, B = 1536, 1534, 512, 64
+    alg = {"pass_a": 8 * (hr * hr + nx * nx + (hr + nx) * G), "pass_b": 8 * ((hr + nx) * G + nx * G),
+           "pass_d": 8 * (nx * G + nx * nx + 1)}
+    # requests: column tiles of 8 complex64 (64 B), rows whole lines (128 B)
+    req = {"pass_a": 64, "pass_b": 128, "pass_d": 64}
+    lines = ["# HBM traffic per tensor, block batch (64 BHHB tensors, m=3, 512 blocks of 512, grid 1536 x 1536), c64",
+             "# from two rocprofv3 --pmc runs of the same command (FETCH_SIZE, then WRITE_SIZE):",
+             f"#   {command}",
+             f"# calibration: a plain device copy of {calib_mib} MiB in the same run: FETCH_SIZE factor "
+             f"{res['fetch']['factor']:.4f}, WRITE_SIZE factor {res['write']['factor']:.4f}",
+             "# FETCH_SIZE counts each read request as 64 bytes on this pool: fetched bytes = FETCH_SIZE scaled by",
+             "# request size / 64 (column tiles 64 B, row-pass reads whole 128-byte lines); per tensor = per dispatch / 64",
+             "# alg = the pass model (reads + writes each pass needs on the 1536^2 grid)",
+             "", "| pass | dispatches | fetched MB / tensor | written MB / tensor | traffic MB | alg MB | ratio |",
+             "|---|---|---|---|---|---|---|"]
+    tt = ta = 0.0
+    for k in ("pass_a", "pass_b", "pass_d"):
+        if k not in res["fetch"]["kib"] or k not in res["write"]["kib"]:
+            continue
+        fb = res["fetch"]["kib"][k] * 1024 * res["fetch"]["factor"] * req[k] / 128.0 / B
+        wb = res["write"]["kib"][k] * 1024 * res["write"]["factor"] / B
+        tt += fb + wb
+        ta += alg[k]
+        lines.append(f"| {k} | {res['fetch']['n'][k]} | {fb / 1e6:.2f} | {wb / 1e6:.2f} | {(fb + wb) / 1e6:.2f} | "
+                     f"{alg[k] / 1e6:.2f} | {(fb + wb) / alg[k]:.3f} |")
+    if ta:
+        lines.append(f"| total | | | | {tt / 1e6:.2f} | {ta / 1e6:.2f} | {tt / ta:.3f} |")
+    return "\n".join(lines) + "\n"
+
+
+def profile_block(steps, calib_mib):
+    """Runs the block batch `steps` times (and the copy calibration) for a
+    rocprofv3 counter or trace run, then exits."""
+    import torch
+    import paper_1401_6238_amd as hk
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        blk = list(ex.map(wl.block_instance, range(64)))
+    dev = torch.device("cuda:0")
+    Hs = torch.stack([torch.from_numpy(p.h) for p in blk]).to(torch.complex64).to(dev)
+    Xs = torch.stack([torch.from_numpy(p.vectors[1]) for p in blk]).to(torch.complex64).to(dev)
+    for _ in range(steps):
+        hk.block_hankel_tvp_strided_batched(Hs, Xs, 3, 512, 512, True, True)
+    torch.cuda.synchronize()
+    if calib_mib:
+        src = torch.empty(calib_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(8):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    log(f"block batch: {steps} calls")
+
+
 def summarize_trace(trace_dir, command):
     """rocprofv3 --kernel-trace --stats summary plus the per-pass split."""
     stats = _read_csv(trace_dir, "kernel_stats.csv")
@@ -363,11 +494,25 @@ def main():
     ap.add_argument("--title", default="rocprofv3 kernel statistics", help="title line of --summarize-stats")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the per-pass HBM traffic summary from two rocprofv3 --pmc runs")
+    ap.add_argument("--summarize-sq", nargs="+", metavar="DIR", help="write the per-pass SQ counter table")
+    ap.add_argument("--summarize-block-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the block batch's per-pass HBM traffic from two rocprofv3 --pmc runs")
+    ap.add_argument("--profile-block", type=int, default=0, metavar="STEPS",
+                    help="run only the block batch STEPS times (for a profiler) and exit")
     ap.add_argument("--profiled-command", default="", help="command line recorded in the summaries")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
-    if args.summarize_trace or args.summarize_counters or args.summarize_stats:
-        if args.summarize_stats:
+    if args.profile_block:
+        profile_block(args.profile_block, args.copy_calib)
+        return
+    if args.summarize_trace or args.summarize_counters or args.summarize_stats or args.summarize_sq or \
+            args.summarize_block_counters:
+        if args.summarize_sq:
+            txt = summarize_sq(args.summarize_sq, args.profiled_command)
+        elif args.summarize_block_counters:
+            txt = summarize_block_counters(args.summarize_block_counters[0], args.summarize_block_counters[1],
+                                           args.copy_calib, args.profiled_command)
+        elif args.summarize_stats:
             txt = summarize_stats(args.summarize_stats, args.profiled_command, args.title)
         elif args.summarize_trace:
             txt = summarize_trace(args.summarize_trace, args.profiled_command)
