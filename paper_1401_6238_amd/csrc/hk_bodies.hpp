@@ -234,6 +234,16 @@ __device__ __forceinline__ int64_t pass_rows(const Shape &sh) { return (int64_t)
 // write whole runs of consecutive i (the nonzero and the kept ones exactly),
 // and the row pass gathers sequence q's position c from i = c + R tau.
 __device__ __forceinline__ bool block_natural(const Shape &sh) { return sh.is_block && sh.odd > 1; }
+// Elements of one workspace buffer and rows of the row pass for the
+// power-of-two row bodies: 1D shapes 2^(logR + logC) and 2^logC; BHHB grids
+// may have an odd column factor (odd_c 2^logC rows of 2^logR).  The 1D branch
+// reads no odd factor, so the 1D hot loops are unchanged.
+__device__ __forceinline__ int64_t pow2_grid_len(const Shape &sh) {
+  return sh.is_block ? seq_len(sh) : ((int64_t)1 << (sh.logR + sh.logC));
+}
+__device__ __forceinline__ int64_t pow2_pass_rows(const Shape &sh) {
+  return sh.is_block ? pass_rows(sh) : ((int64_t)1 << sh.logC);
+}
 
 // Multipass workspace: nbuf buffers of N elements (sequence q of a buffer at
 // q * M), then the row pass's scalar partial sums.  ODDF: the shape may have
@@ -242,6 +252,7 @@ __device__ __forceinline__ bool block_natural(const Shape &sh) { return sh.is_bl
 template <typename T, bool ODDF = false>
 __device__ __forceinline__ cx<T> *ws_buf(const Shape &sh, const PV &P, int b) {
   if constexpr (ODDF) return (cx<T> *)P.ws() + (int64_t)b * fft_len(sh);
+  if (sh.is_block) return (cx<T> *)P.ws() + (int64_t)b * seq_len(sh);
   return (cx<T> *)P.ws() + ((int64_t)b << (sh.logR + sh.logC));
 }
 
@@ -389,7 +400,7 @@ struct RowBody {
       // row `row` of the operand's column transform; its columns past
       // ncol_nz were never written and read as zero.  A stored spectrum
       // (OPF_SPEC) is read whole from the operand pointer.
-      const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+      const int64_t N = pow2_grid_len(sh);
       const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
       if constexpr (SPEC) {
         const bool spec = (od.flags & OPF_SPEC) != 0;
@@ -442,7 +453,7 @@ struct RowBody {
         if (pos < lim) store_out<T>(dst, pos, cj ? cconj(a[s]) : a[s], sh.real_out);
       }
     } else {
-      const int64_t N = (int64_t)1 << (sh.logR + sh.logC);
+      const int64_t N = pow2_grid_len(sh);
       const auto r = make_buf(ws_buf<T>(sh, P, sh.ops[which].buf), N * (int64_t)sizeof(cx<T>));
       const uint32_t rbase = (uint32_t)(row * L * (int64_t)sizeof(cx<T>));
       // columns the output's column pass never reads are not stored
@@ -545,8 +556,8 @@ struct RowBody {
     if constexpr (ODD > 1) {
       return run_fwd_odd(sh, P, row0, rstride, K, true, t, lds, false, tw24, tw4096);
     } else {
-    const int64_t C = (int64_t)1 << sh.logC;
-    const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
+    const int64_t C = pow2_pass_rows(sh);
+    const T invN = T(1) / T(pow2_grid_len(sh));
     const bool conv = (sh.fwd_flags & SHF_CONV) != 0;
     cx<T> a[EE], nx[EE], acc[EE], w[EE];
     cx<T> part = czero<T>();

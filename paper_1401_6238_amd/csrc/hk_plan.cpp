@@ -249,33 +249,49 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int6
       return fail(HK_ERR_SIZE_LIMIT, "padded BHHB grid exceeds 4096 along an axis");
     lay.resident = false;
     if (allow_odd && is_complex(p.dt)) {
-      // each axis takes the smallest of 2^k, 3 * 2^k, 5 * 2^k >= its extent;
-      // an odd row axis needs odd-factor row kernels of its 2^logR points, an
-      // odd column axis column kernels of 2^6 .. 2^11 points per sequence and
-      // an odd row axis (the power-of-two row bodies keep one sequence)
+      // Each axis is the shortest of 2^k, 3 * 2^k and 5 * 2^k with kernels.
+      // The passes' bytes scale with the column axis only (pass A writes,
+      // pass B reads and writes, pass D reads columns of that length; the row
+      // pass loads and stores only a row's nonzero and kept entries); the row
+      // axis sets the row transforms' arithmetic.  An odd column factor needs
+      // column kernels of 2^6 .. 2^11 points per sequence; it combines with
+      // either kind of row.  (Measured on the 64-tensor batch with 512 blocks
+      // of 512: rows of 3 * 512 took 30.1 us per tensor, power-of-two rows of
+      // 2048 over the same columns 34.4 us, so the row axis is not lengthened
+      // to a power of two either.)
       auto axis = [&](int64_t ext, int odd, int *logp) {
         int l = 0;
         while (((int64_t)odd << l) < ext) ++l;
         *logp = l;
         return (int64_t)odd << l;
       };
-      int64_t best = ((int64_t)1 << lay.logR) << lay.logC;
+      int64_t nc_best = (int64_t)1 << lay.logC;
+      for (int ocol : {3, 5}) {
+        int lc = 0;
+        const int64_t nc = axis(cols, ocol, &lc);
+        if (lc < 6 || lc > 11) continue;
+        if (nc < nc_best) {
+          nc_best = nc;
+          lay.odd_c = ocol;
+          lay.logC = lc;
+        }
+      }
+      const int64_t nr_pow2 = (int64_t)1 << lay.logR;
+      int64_t nr_odd = -1;
+      int orow_best = 1, lr_best = lay.logR;
       for (int orow : {3, 5}) {
         int lr = 0;
         const int64_t nr = axis(rows, orow, &lr);
         if (lr > odd_max_logl(p.dt, orow, p.prog)) continue;
-        for (int ocol : {1, 3, 5}) {
-          int lc = 0;
-          const int64_t nc = axis(cols, ocol, &lc);
-          if (lc > MAX_LOGL || (ocol > 1 && (lc < 6 || lc > 11))) continue;
-          if (nr * nc < best) {
-            best = nr * nc;
-            lay.odd = orow;
-            lay.odd_c = ocol;
-            lay.logR = lr;
-            lay.logC = lc;
-          }
+        if (nr_odd < 0 || nr < nr_odd) {
+          nr_odd = nr;
+          orow_best = orow;
+          lr_best = lr;
         }
+      }
+      if (nr_odd > 0 && nr_odd < nr_pow2) {
+        lay.odd = orow_best;
+        lay.logR = lr_best;
       }
     }
   }
@@ -477,8 +493,8 @@ int64_t pass_model_bytes(const Shape &sh, hk_dtype_t dt) {
   if (sh.resident) return in + out;
   const int64_t C = (int64_t)1 << sh.logC;
   // columns of one workspace row and rows per column: 1D, `odd` sequences of
-  // R x C; BHHB with an odd row factor, natural rows of odd R over odd_c C
-  const bool nat = sh.is_block && sh.odd > 1;
+  // R x C; BHHB, natural rows of odd R over odd_c C
+  const bool nat = sh.is_block;
   const int64_t R = (int64_t)(nat ? sh.odd : 1) << sh.logR;
   const int64_t seq = (nat ? (int64_t)(sh.odd_c > 1 ? sh.odd_c : 1) : (int64_t)sh.odd) * C;
   int64_t a_write = 0, b_read = 0;

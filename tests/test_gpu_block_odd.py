@@ -1,7 +1,8 @@
 """GPU parity of BHHB products on grids with odd factors: each axis of the
 padded grid is 2^k, 3 * 2^k or 5 * 2^k, transformed as 3 or 5 power-of-two
 sequences through that axis's Chinese-remainder index map (the row axis in
-the row pass, the column axis in the column passes).  Every case checks the
+the row pass, the column axis in the column passes); odd column axes are
+checked with odd and with power-of-two row axes.  Every case checks the
 grid the planner picks, then compares y = vec(Y) and alpha with the CPU
 oracle's BHHB sums on exactly the inputs the GPU sees (n_p != N_p, distinct
 and equal vectors, single and strided-batched calls).  Tolerances: relative
@@ -34,7 +35,14 @@ CASES = [
     ((130, 100, 80), (200, 150, 140), torch.complex64, (320, 512)),   # odd rows, power-of-two columns
     ((50, 41), (90, 70), torch.complex64, (96, 192)),                 # m = 2
     ((20, 30, 25, 18), (40, 36, 30, 33), torch.complex128, (96, 192)),
+    ((100, 60, 50), (130, 100, 102), torch.complex64, (256, 384)),    # power-of-two rows, 3 x 128 columns
+    ((100, 60, 50), (130, 100, 102), torch.complex128, (256, 384)),
+    ((100, 60, 50), (100, 100, 102), torch.complex64, (256, 320)),    # power-of-two rows, 5 x 64 columns
 ]
+
+
+def _pow2(v):
+    return v & (v - 1) == 0
 
 
 def grid_of(dims, bdims, dtype):
@@ -51,7 +59,7 @@ def test_block_odd_grid(dims, bdims, dtype, grid, equal):
         dims, bdims = (dims[0],) * m, (bdims[0],) * m
         grid = grid_of(dims, bdims, dtype)
     assert grid_of(dims, bdims, dtype) == grid
-    assert grid[0] % 2 or grid[0] & (grid[0] - 1)  # not both axes plain powers of two
+    assert not (_pow2(grid[0]) and _pow2(grid[1]))  # not both axes plain powers of two
     print_case(test="block_odd", dims=dims, bdims=bdims, dtype=dtype, grid=grid, equal=equal)
     prob = wl.random_problem(3100 + sum(dims) + sum(bdims), m, list(dims), equal, want_alpha=True,
                              block_dims=list(bdims))
@@ -69,18 +77,20 @@ def test_block_odd_grid(dims, bdims, dtype, grid, equal):
     check_alpha(complex(a), ao, dtype)
 
 
-def test_block_odd_strided_batch():
-    """A strided batch of BHHB tensors on a 5 x 5 odd grid, every instance
-    against the oracle."""
+@pytest.mark.parametrize("n,grid", [(70, (256, 320)), (60, (192, 320))])
+def test_block_odd_strided_batch(n, grid):
+    """A strided batch of BHHB tensors on a grid with 5 x 64 columns (rows a
+    power of two, or 3 x 64), every instance against the oracle."""
     import paper_1401_6238_amd as hk
-    dims, bdims, dtype = (70,) * 3, (100,) * 3, torch.complex64
-    grid = hk.block_hankel_tvp_layout(dtype, 3, dims, bdims, 4)
-    assert grid == (320, 320), grid
+    dims, bdims, dtype = (n,) * 3, (100,) * 3, torch.complex64
+    got = hk.block_hankel_tvp_layout(dtype, 3, dims, bdims, 4)
+    assert got == grid, got
+    print_case(test="block_odd_strided", n=n, grid=grid)
     probs = [wl.random_problem(3300 + b, 3, list(dims), True, want_alpha=True, block_dims=list(bdims))
              for b in range(4)]
     Hs = torch.stack([to_dev(p.h, dtype) for p in probs])
     Xs = torch.stack([to_dev(p.vectors[1], dtype) for p in probs])
-    y, a = hk.block_hankel_tvp_strided_batched(Hs, Xs, 3, 70, 100, True, True)
+    y, a = hk.block_hankel_tvp_strided_batched(Hs, Xs, 3, n, 100, True, True)
     torch.cuda.synchronize()
     for b, p in enumerate(probs):
         yo, ao = oracle.block_tvp(3, list(dims), list(bdims), seen(p.h, dtype), [seen(p.vectors[1], dtype)] * 3,
