@@ -399,19 +399,54 @@ def summarize_block_counters(fetch_dir, write_dir, calib_mib, command):
     return "\n".join(lines) + "\n"
 
 
-def profile_block(steps, calib_mib):
-    """Runs the block batch `steps` times (and the copy calibration) for a
-    rocprofv3 counter or trace run, then exits."""
+def profile_workload(name, steps, calib_mib, workers):
+    """Runs one workload of the benchmark `steps` times (and the copy
+    calibration) for a rocprofv3 trace or counter run, then exits:
+    block   64 BHHB tensors (m=3, 512 blocks of 512), one strided batched call;
+    mixed   the 4096-instance mixed batch through the grouped plan (c64);
+    adjoint the 256-instance batch (m=4, n=2^16, c64): strided batched forward,
+            adjoint, forward keeping x^ and the adjoint reading it."""
+    import multiprocessing as mp
     import torch
     import paper_1401_6238_amd as hk
-    from concurrent.futures import ThreadPoolExecutor
-    with ThreadPoolExecutor(max_workers=16) as ex:
-        blk = list(ex.map(wl.block_instance, range(64)))
+    from paper_1401_6238_amd import _lib
+    gen, count = {"block": (_gen_block, 64), "mixed": (_gen_mixed, 4096), "adjoint": (_gen_adjoint, 256)}[name]
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        data = list(ex.map(gen, range(count), chunksize=8))
     dev = torch.device("cuda:0")
-    Hs = torch.stack([torch.from_numpy(p.h) for p in blk]).to(torch.complex64).to(dev)
-    Xs = torch.stack([torch.from_numpy(p.vectors[1]) for p in blk]).to(torch.complex64).to(dev)
-    for _ in range(steps):
-        hk.block_hankel_tvp_strided_batched(Hs, Xs, 3, 512, 512, True, True)
+    if name == "block":
+        Hs = torch.stack([torch.from_numpy(p.h) for p in data]).to(torch.complex64).to(dev)
+        Xs = torch.stack([torch.from_numpy(p.vectors[1]) for p in data]).to(torch.complex64).to(dev)
+        for _ in range(steps):
+            hk.block_hankel_tvp_strided_batched(Hs, Xs, 3, 512, 512, True, True)
+    elif name == "mixed":
+        items = []
+        for p in data:
+            h = torch.from_numpy(p.h).to(torch.complex64).to(dev)
+            if p.equal:
+                x = torch.from_numpy(p.vectors[1]).to(torch.complex64).to(dev)
+                vecs = [None] + [x] * (p.m - 1)
+            else:
+                vecs = [None] + [torch.from_numpy(v).to(torch.complex64).to(dev) for v in p.vectors[1:]]
+            items.append({"m": p.m, "dims": p.dims, "h": h, "vectors": vecs})
+        plan = hk.Plan(items, flags=_lib.HK_PLAN_MULTIKERNEL)
+        for _ in range(steps):
+            plan.execute()
+        plan.status()
+        plan.close()
+    else:
+        H = torch.stack([torch.from_numpy(d["h"]) for d in data]).to(torch.complex64).to(dev)
+        X = torch.stack([torch.from_numpy(d["x"]) for d in data]).to(torch.complex64).to(dev)
+        V = torch.stack([torch.from_numpy(d["v"]) for d in data]).to(torch.complex64).to(dev)
+        PHI = torch.tensor([d["phi"] for d in data], dtype=torch.complex64, device=dev)
+        for _ in range(steps):
+            hk.hankel_tvp_strided_batched(H, X, 4, True, True)
+        for _ in range(steps):
+            hk.hankel_tvp_backward_strided_batched(H, X, 4, V, PHI)
+        for _ in range(steps):
+            _, _, XS = hk.hankel_tvp_save_spectrum(H, X, 4, True, True)
+        for _ in range(steps):
+            hk.hankel_tvp_backward_spectral_strided_batched(H, XS, 4, X.shape[1], V, PHI)
     torch.cuda.synchronize()
     if calib_mib:
         src = torch.empty(calib_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
@@ -419,7 +454,7 @@ def profile_block(steps, calib_mib):
         for _ in range(8):
             dst.copy_(src)
         torch.cuda.synchronize()
-    log(f"block batch: {steps} calls")
+    log(f"{name}: {steps} calls")
 
 
 def summarize_trace(trace_dir, command):
@@ -497,13 +532,13 @@ def main():
     ap.add_argument("--summarize-sq", nargs="+", metavar="DIR", help="write the per-pass SQ counter table")
     ap.add_argument("--summarize-block-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the block batch's per-pass HBM traffic from two rocprofv3 --pmc runs")
-    ap.add_argument("--profile-block", type=int, default=0, metavar="STEPS",
-                    help="run only the block batch STEPS times (for a profiler) and exit")
+    ap.add_argument("--profile-workload", nargs=2, metavar=("NAME", "STEPS"),
+                    help="run only workload NAME (block, mixed, adjoint) STEPS times (for a profiler) and exit")
     ap.add_argument("--profiled-command", default="", help="command line recorded in the summaries")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
-    if args.profile_block:
-        profile_block(args.profile_block, args.copy_calib)
+    if args.profile_workload:
+        profile_workload(args.profile_workload[0], int(args.profile_workload[1]), args.copy_calib, args.workers)
         return
     if args.summarize_trace or args.summarize_counters or args.summarize_stats or args.summarize_sq or \
             args.summarize_block_counters:
