@@ -725,6 +725,86 @@ struct RowBody {
     }
   }
 
+  // Pass B of the adjoint over K rows row0, row0 + rstride, ... in turn
+  // (power-of-two rows): the operands of a row (X, V, H) are all in flight
+  // before its first transform, and the next row's X and V load while this
+  // row's outputs are transformed and stored, its H once this row's H has
+  // been used.  Same arithmetic as run_bwd.
+  template <bool SPEC = false>
+  static __device__ __forceinline__ void run_bwd_rows(const Shape &sh, const PV &P, int64_t row0, int rstride,
+                                                      int K, int t, cx<T> *lds, const cx<T> *tw24,
+                                                      const cx<T> *tw4096) {
+    if constexpr (ODD > 1) {
+      for (int it = 0; it < K; ++it) {
+        const int64_t row = row0 + (int64_t)it * rstride;
+        run_bwd_odd(sh, P, row, row < pass_rows(sh), t, lds, false, tw24, tw4096);
+      }
+    } else {
+    const int64_t C = (int64_t)1 << sh.logC;
+    const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
+    cx<T> phc = czero<T>();  // conj(phi)
+    if (P.phi()) phc = cconj(*(const cx<T> *)P.phi());
+    const T m1 = T(sh.m - 1), m0 = T(sh.m);
+    const bool has_v = sh.nops > 1 && sh.ops[1].role == ROLE_V;
+    const bool x_spec = SPEC && (sh.ops[0].flags & OPF_SPEC) != 0;
+    const int oh = sh.nops - 1;  // H, present when grad_x is requested
+    cx<T> xs[EE], vs[EE], hs[EE], a[EE], gq[EE], w[EE];
+    int64_t row = row0;
+    bool valid = row < C;
+    load<SPEC>(xs, sh, P, 0, row, valid, t, false);
+    if (has_v) load(vs, sh, P, 1, row, valid, t, false);
+    if (sh.want_out1) load(hs, sh, P, oh, row, valid, t, false);
+    StageTw<T, L, E> stw;
+    stw.init(t, tw4096);
+    for (int it = 0; it < K; ++it) {
+      const bool tw_on = twiddles(w, sh, row, t, false, tw24, tw4096);
+      const int64_t nrow = row + rstride;
+      const bool more = it + 1 < K;
+      const bool nvalid = more && nrow < C;
+      if (!x_spec) {
+        twiddle_in(xs, w, tw_on);
+        fft(xs, t, lds, stw);
+      }
+      if (has_v) {
+        twiddle_in(vs, w, tw_on);
+        fft(vs, t, lds, stw);
+      } else {
+#pragma unroll
+        for (int s = 0; s < EE; ++s) vs[s] = czero<T>();
+      }
+#pragma unroll
+      for (int s = 0; s < EE; ++s) {
+        cx<T> p1 = mk(T(1), T(0));
+        for (int e = 0; e < sh.m - 2; ++e) p1 = cmul(p1, xs[s]);
+        // grad_x spectrum factor: x^{m-2} ((m-1) V + m conj(phi) x)
+        gq[s] = cmul(p1, cadd(cscale(vs[s], m1), cscale(cmul(phc, xs[s]), m0)));
+        // grad_h spectrum: conj(x^{m-1} (V + conj(phi) x)) / N, transformed forward
+        a[s] = cscale(cconj(cmul(cmul(p1, xs[s]), cfma(phc, xs[s], vs[s]))), invN);
+      }
+      // X and V of this row are used up: the next row's are loaded now
+      if (more) {
+        load<SPEC>(xs, sh, P, 0, nrow, nvalid, t, false);
+        if (has_v) load(vs, sh, P, 1, nrow, nvalid, t, false);
+      }
+      if (sh.want_y) {
+        fft(a, t, lds, stw);
+        store(a, sh, P, 0, row, valid, t, false, w);
+      }
+      if (sh.want_out1) {
+        twiddle_in(hs, w, tw_on);
+        fft(hs, t, lds, stw);
+#pragma unroll
+        for (int s = 0; s < EE; ++s) a[s] = cmul(cscale(cconj(hs[s]), invN), gq[s]);
+        if (more) load(hs, sh, P, oh, nrow, nvalid, t, false);
+        fft(a, t, lds, stw);
+        store(a, sh, P, 1, row, valid, t, false, w);
+      }
+      row = nrow;
+      valid = nvalid;
+    }
+    }
+  }
+
   // ---- Odd-factor rows (ODD > 1): the same row of ODD sequences. ----
 
   static __device__ __forceinline__ void load_seq(cx<T> (&a)[EE], const Shape &sh, const PV &P, int o,

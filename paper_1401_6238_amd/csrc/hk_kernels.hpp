@@ -59,11 +59,7 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
     const int K = sh.row_iters > 1 ? sh.row_iters : 1;
     const int64_t row0 = (int64_t)blockIdx.x * K * rows + rw;
     if (PROG == PROG_BWD || PROG == PROG_BWD_SPEC) {
-      for (int it = 0; it < K; ++it) {
-        const int64_t row = row0 + (int64_t)it * rows;
-        RB::template run_bwd<PROG == PROG_BWD_SPEC>(sh, P, row, row < ((int64_t)1 << sh.logC), t, lds, false,
-                                                     g_tw24, g_tw4096);
-      }
+      RB::template run_bwd_rows<PROG == PROG_BWD_SPEC>(sh, P, row0, rows, K, t, lds, g_tw24, g_tw4096);
       return;
     }
     const cx<T> part =
