@@ -739,6 +739,13 @@ struct RowBody {
         const int64_t row = row0 + (int64_t)it * rstride;
         run_bwd_odd(sh, P, row, row < pass_rows(sh), t, lds, false, tw24, tw4096);
       }
+    } else if constexpr (sizeof(T) == 8 && EE >= 16) {
+      // double rows of 16 elements per lane: five live operand sets would
+      // spill (over 1 KB per lane); one row at a time, operands in turn
+      for (int it = 0; it < K; ++it) {
+        const int64_t row = row0 + (int64_t)it * rstride;
+        run_bwd<SPEC>(sh, P, row, row < ((int64_t)1 << sh.logC), t, lds, false, tw24, tw4096);
+      }
     } else {
     const int64_t C = (int64_t)1 << sh.logC;
     const T invN = T(1) / T((int64_t)1 << (sh.logR + sh.logC));
