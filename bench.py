@@ -1266,6 +1266,21 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
                              "roofline": roof(64 * blk_bytes, ms5, "k_cols / k_rows (BHHB strided batch)")}
     log("block batch", ex["block_batch_c64"])
 
+    # BHHB adjoint of one tensor of the batch's shape (m=3, 512 blocks of 512, three
+    # distinct vectors, cotangents of vec(Y) and alpha): every gradient, against one
+    # forward call of the same tensor (y and alpha)
+    xs3 = [Xs[0], Xs[1], Xs[2]]
+    gy = Xs[3].clone()
+    ga = torch.ones(1, dtype=torch.complex64, device=dev)
+    ms_bf = time_region(torch, lambda: hk.block_hankel_tvp(Hs[0], xs3, [512] * 3, [512] * 3, True, True), 20)
+    ms_bb = time_region(torch, lambda: hk.block_hankel_tvp_backward(Hs[0], xs3, [512] * 3, [512] * 3, gy, ga), 5)
+    ex["block_adjoint_c64"] = {"shape": "m=3, 512 blocks of 512, distinct vectors, one tensor",
+                               "grid": list(hk.block_hankel_tvp_layout(torch.complex64, 3, [512] * 3, [512] * 3, 1)),
+                               "forward_ms": round(ms_bf, 4), "backward_ms": round(ms_bb, 4),
+                               "bwd_over_fwd_time": round(ms_bb / ms_bf, 3)}
+    log("block adjoint", ex["block_adjoint_c64"])
+    del xs3, gy, ga
+
     # level-k products: the same BHHB tensors through the level-k call (one 1D transform of
     # length >= 1534^2, here 3 * 2^20) against the native 2D passes on the 2048^2 grid, one
     # tensor at a time; and a level-3 tensor (m = 3, 64 x 64 x 16 per mode, generating tensor

@@ -863,7 +863,7 @@ struct RowBody {
     if (resident) {
       void *dst = which == 0 ? P.y() : P.out1();
       const int64_t lim = which == 0 ? sh.out_rows : sh.out1_len;
-      const bool cj = (sh.prog == PROG_BWD) && which == 1;
+      const bool cj = which == 1 ? sh.prog == PROG_BWD : (sh.fwd_flags & SHF_CONJ_Y) != 0;
       int64_t idx[EE];
       res_index(idx, q, t);
 #pragma unroll
@@ -974,6 +974,9 @@ struct RowBody {
                                                        const cx<T> *tw24, const cx<T> *tw4096) {
     const int64_t C = pass_rows(sh);
     const T invN = T(1) / T(fft_len(sh));
+    // SHF_CONV: no generating vector; the product of the spectra starts at 1
+    // and the output is conj(ifft(prod)), formed as fft(conj(prod) / N)
+    const bool conv = (sh.fwd_flags & SHF_CONV) != 0;
     cx<T> nx[EE], w[EE];
     Seqs h, acc;
     cx<T> part = czero<T>();
@@ -989,7 +992,7 @@ struct RowBody {
 #pragma unroll
       for (int q = 0; q < ODD; ++q)
 #pragma unroll
-        for (int s = 0; s < EE; ++s) acc[q][s] = czero<T>();
+        for (int s = 0; s < EE; ++s) acc[q][s] = mk(conv ? T(1) : T(0), T(0));
       for (int o = 0; o < sh.nops; ++o) {
 #pragma unroll
         for (int q = 0; q < ODD; ++q) {
@@ -1007,7 +1010,15 @@ struct RowBody {
         odd_dft(h);
         combine_fwd(acc, h, sh.ops[o], invN, part);
       }
-      if (sh.want_y) output(acc, sh, P, 0, row, valid, t, lds, resident, stw, w);
+      if (sh.want_y) {
+        if (conv) {
+#pragma unroll
+          for (int q = 0; q < ODD; ++q)
+#pragma unroll
+            for (int s = 0; s < EE; ++s) acc[q][s] = cscale(cconj(acc[q][s]), invN);
+        }
+        output(acc, sh, P, 0, row, valid, t, lds, resident, stw, w);
+      }
       row = nrow;
       valid = nvalid;
     }

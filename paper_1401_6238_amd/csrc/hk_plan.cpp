@@ -169,8 +169,6 @@ constexpr int64_t kOddWorkMin = (int64_t)1 << 18;
 
 Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int64_t batch) {
   const int policy = g_length_policy.load();
-  // the adjoint's forward variants run on power-of-two complex layouts
-  if (p.conv || p.conj_y) allow_odd = false;
   const bool allow_r2c = allow_odd && policy != HK_LENGTHS_POW2;
   if (policy == HK_LENGTHS_POW2) allow_odd = false;
   if (allow_odd && policy == HK_LENGTHS_AUTO) {

@@ -153,3 +153,58 @@ def test_equal_vectors_through_distinct_adjoint():
     total = sum(host(g) for g in gv)
     assert rel(total, ox) <= TOL[dt] and rel(host(gh), oh) <= TOL[dt]
     assert rel(total, host(gx_eq)) <= TOL[dt] and rel(host(gh), host(gh_eq)) <= TOL[dt]
+
+
+@pytest.fixture
+def smallest_lengths():
+    """Odd-factor lengths for every size (the 'smallest' length policy)."""
+    import paper_1401_6238_amd as hk
+    hk.hk_set_fft_lengths("smallest")
+    yield
+    hk.hk_set_fft_lengths("auto")
+
+
+# (dims, N for complex64): resident 3 * 64 and 5 * 1024, three-pass 3 * 8192
+ODD_1D = [((64, 80, 50), 192), ((1200, 900, 1500, 700), 5120), ((9000, 8000, 7002), 24576)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("dims,n_fft", ODD_1D)
+def test_mode_backward_odd_lengths(smallest_lengths, dtype, dims, n_fft):
+    """The distinct-vector adjoint on transform lengths 3 * 2^k and 5 * 2^k:
+    its conjugating and generating-vector-free forward programs run on the
+    odd-factor rows (resident and three-pass); every gradient against the
+    oracle."""
+    import paper_1401_6238_amd as hk
+    m = len(dims)
+    if dtype == torch.complex64:
+        assert hk.hk_fft_layout(sum(dims) - m + 1)[0] == n_fft
+    print_case(test="mode_backward_odd", dtype=dtype, dims=dims)
+    h, xs, v, phi = draw(3 * sum(dims), dims)
+    gv, gh = hk.hankel_mode_products_backward(to_dev(h, dtype), [to_dev(x, dtype) for x in xs], dims,
+                                              to_dev(v, dtype), to_dev(np.array([phi]), dtype))
+    torch.cuda.synchronize()
+    ov, oh = oracle.mode_backward(m, dims, seen(h, dtype), [seen(x, dtype) for x in xs], seen(v, dtype),
+                                  complex(seen(np.array([phi]), dtype)[0]))
+    check_grads(gv, gh, ov, oh, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("cot", ["both", "phi"])
+def test_block_backward_odd_grid(smallest_lengths, dtype, cot):
+    """The BHHB adjoint on a grid of 3 x 64 rows and 5 x 64 columns (n_p != N_p)
+    against the oracle."""
+    import paper_1401_6238_amd as hk
+    dims, bdims = (70, 60, 62), (100, 100, 102)
+    assert hk.block_hankel_tvp_layout(dtype, 3, dims, bdims, 1) == (192, 320)
+    print_case(test="block_backward_odd", dtype=dtype, cot=cot)
+    H, xs, v, phi = draw(911, dims, bdims, scale_x=0.3)
+    v = v if cot != "phi" else None
+    gv, gH = hk.block_hankel_tvp_backward(to_dev(H, dtype), [to_dev(x, dtype) for x in xs], dims, bdims,
+                                          to_dev(v, dtype) if v is not None else None,
+                                          to_dev(np.array([phi]), dtype))
+    torch.cuda.synchronize()
+    ov, oH = oracle.block_backward(3, dims, bdims, seen(H, dtype), [seen(x, dtype) for x in xs],
+                                   seen(v, dtype) if v is not None else None,
+                                   complex(seen(np.array([phi]), dtype)[0]))
+    check_grads(gv, gH, ov, oH, dtype)
