@@ -269,7 +269,12 @@ typedef struct hk_plan_s *hk_plan_t;
  * captured graph.  flags without PERSISTENT pick the grouped launches (the
  * faster schedule on MI355X); PERSISTENT runs the whole batch in one launch
  * whose resident workgroups pull each phase's tasks from a queue and meet in
- * a grid-wide barrier (bounded wait) between phases.  Grouped launches spread
+ * a grid-wide barrier (bounded wait) between phases.  That launch is a
+ * cooperative one (hipLaunchCooperativeKernel: the runtime refuses a grid that
+ * cannot be resident at once, and hk_plan_execute then fails with
+ * HK_ERR_HIP), except inside a stream capture (HK_PLAN_GRAPH) and while
+ * hk_profile_start timing is on, which launch the same occupancy-sized grid
+ * plainly.  Grouped launches spread
  * a phase's groups over the caller's stream and three streams of the plan;
  * the process's streams share its few hardware queues, so the eager plan's
  * time varies with the streams the process created before it (by up to ~15 %
@@ -283,9 +288,9 @@ hk_status_t hk_plan_workspace_size(hk_plan_t plan, size_t *bytes);
 hk_status_t hk_plan_execute(hk_plan_t plan, void *ws, size_t ws_bytes, hipStream_t stream);
 /* Synchronizes the last execute's stream and returns HK_SUCCESS or
  * HK_ERR_DEVICE_FAULT if the persistent kernel flagged an error (a barrier
- * wait that exceeded its bound: the device could not hold the whole grid at
- * once, for example while other work occupied it; results are then
- * unspecified). */
+ * wait that exceeded its bound: in a plain launch, the device could not hold
+ * the whole grid at once, for example while other work occupied it; results
+ * are then unspecified). */
 hk_status_t hk_plan_status(hk_plan_t plan);
 /* Diagnostics: the number of polling iterations (each a short sleep) a
  * persistent-plan workgroup waits at a grid barrier before it sets the error

@@ -352,7 +352,7 @@ hipError_t HK_CAT(launch_batch_, HK_SUFFIX)(const BatchArgs &args, int grid, hip
   if (e != hipSuccess) return e;
   BatchArgs a = args;
   void *kargs[] = {&a};
-  return launch_kernel((void *)&k_batch, dim3((unsigned)grid), dim3(blk), kargs, lds, st);
+  return launch_cooperative((void *)&k_batch, dim3((unsigned)grid), dim3(blk), kargs, lds, st);
 }
 
 hipError_t HK_CAT(launch_copy_cols_, HK_SUFFIX)(void *out, const void *src, const int32_t *pairs, int64_t npairs,

@@ -25,6 +25,7 @@ struct KernelLimits {
 // the dispatch's own begin and end (hipExtLaunchKernel), so the recorded
 // duration is the kernel's execution, without event-packet overhead.
 hipError_t launch_kernel(const void *fn, dim3 grid, dim3 block, void **args, size_t lds, hipStream_t st);
+hipError_t launch_cooperative(const void *fn, dim3 grid, dim3 block, void **args, size_t lds, hipStream_t st);
 
 #define HK_DECLARE_LAUNCHERS(SUFFIX)                                                                   \
   hipError_t init_tables_##SUFFIX(const double *tw4096_interleaved, const double *tw24_interleaved);   \

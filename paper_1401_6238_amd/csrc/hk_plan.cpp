@@ -614,6 +614,24 @@ hipError_t launch_kernel(const void *fn, dim3 grid, dim3 block, void **args, siz
   return hipLaunchKernel(fn, grid, block, args, lds, st);
 }
 
+// The persistent kernel's grid-wide barriers need every workgroup resident at
+// once: a cooperative launch makes the runtime check that (and fail instead of
+// starting a grid that cannot be co-resident).  Launches recorded into a
+// graph, and launches timed by the profiling events, are plain launches of
+// the same occupancy-sized grid.
+hipError_t launch_cooperative(const void *fn, dim3 grid, dim3 block, void **args, size_t lds, hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(st, &cs);
+  if (e != hipSuccess) return e;
+  bool timed = false;
+  if (g_prof.on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    timed = g_prof.armed && g_prof.used < g_prof.pool.size();
+  }
+  if (cs != hipStreamCaptureStatusNone || timed) return launch_kernel(fn, grid, block, args, lds, st);
+  return hipLaunchCooperativeKernel(fn, grid, block, args, (unsigned int)lds, st);
+}
+
 Status prof_start() {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   g_prof.on = true;
