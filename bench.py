@@ -300,6 +300,53 @@ def _per_dispatch(d, ctr_names):
     return out
 
 
+def summarize_requests(d, command):
+    """L2-to-memory read requests per dispatch of the large single product's
+    passes and of the copy calibration, from one --pmc run of
+    TCC_EA0_RDREQ_sum, TCC_EA0_RDREQ_32B_sum, TCC_BUBBLE_sum and
+    TCC_EA0_RDREQ_DRAM_sum."""
+    names = ["TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_BUBBLE_sum", "TCC_EA0_RDREQ_DRAM_sum"]
+    disp = _per_dispatch(d, set(names))
+    order = sorted(disp)
+    kinds = classify_passes([disp[k][0] for k in order])
+    groups = {}
+    for k, kind in zip(order, kinds):
+        nm = disp[k][0]
+        key = ("column pass (A and D)" if kind in ("pass_a", "pass_d") else "row pass (B)") if kind else (
+            "plain device copy (calibration)" if "copy" in nm.lower() else None)
+        if key is None:
+            continue
+        g = groups.setdefault(key, {"name": nm.split("(")[0].replace("void ", ""), "n": 0, "sum": {c: 0.0 for c in names}})
+        g["n"] += 1
+        for c in names:
+            g["sum"][c] += disp[k][1].get(c, 0.0)
+    lines = ["# L2-to-memory read requests per dispatch, large single product (order 4, n=2^18, N=2^20), c64",
+             "", "Command (one rocprofv3 --pmc pass, 4 TCC counters):", "", f"    {command}", "",
+             "| kernel | dispatches | TCC_EA0_RDREQ | of them 32 B | TCC_BUBBLE (128 B) | to DRAM |",
+             "|---|---|---|---|---|---|"]
+    for key in ("column pass (A and D)", "row pass (B)", "plain device copy (calibration)"):
+        if key not in groups:
+            continue
+        g = groups[key]
+        m = {c: g["sum"][c] / g["n"] for c in names}
+        lines.append(f"| {key}: {g['name']} | {g['n']} | {m[names[0]]:,.0f} | {m[names[1]]:,.0f} | "
+                     f"{m[names[2]]:,.0f} | {m[names[3]]:,.0f} |")
+    if "plain device copy (calibration)" in groups and "row pass (B)" in groups:
+        cp = groups["plain device copy (calibration)"]
+        rq = cp["sum"][names[0]] / cp["n"]
+        row = groups["row pass (B)"]["sum"][names[0]] / groups["row pass (B)"]["n"]
+        col = groups.get("column pass (A and D)", {"sum": {names[0]: 0.0}, "n": 1})
+        colq = col["sum"][names[0]] / max(1, col["n"])
+        lines += ["", f"The copy's requests ({rq:,.0f} per dispatch) times 128 bytes give its bytes: FETCH_SIZE, which",
+                  "counts every request as 64 bytes when TCC_BUBBLE (the 128-byte request count) reads zero,",
+                  "reads half of them. Row pass: whole lines, "
+                  f"{row:,.0f} x 128 B = {row * 128 / 1e6:.1f} MB per dispatch (16.8 MB algorithmic reads); "
+                  f"column passes: {colq:,.0f} requests per dispatch, 64-byte tile rows = {colq * 64 / 1e6:.2f} MB "
+                  "(the mean of pass A's 10.5 MB and pass D's 8.4 MB algorithmic reads). The traffic summary",
+                  "scales FETCH_SIZE accordingly."]
+    return "\n".join(lines) + "\n"
+
+
 def summarize_sq(dirs, command):
     """Per-pass SQ counters of the large single product from --pmc runs (each
     directory one set of counters), per wavefront."""
@@ -527,6 +574,7 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the per-pass HBM traffic summary from two rocprofv3 --pmc runs")
     ap.add_argument("--summarize-sq", nargs="+", metavar="DIR", help="write the per-pass SQ counter table")
+    ap.add_argument("--summarize-requests", metavar="DIR", help="write the read-request table of a TCC --pmc run")
     ap.add_argument("--summarize-block-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the block batch's per-pass HBM traffic from two rocprofv3 --pmc runs")
     ap.add_argument("--profile-workload", nargs=2, metavar=("NAME", "STEPS"),
@@ -538,8 +586,10 @@ def main():
         profile_workload(args.profile_workload[0], int(args.profile_workload[1]), args.copy_calib, args.workers)
         return
     if args.summarize_trace or args.summarize_counters or args.summarize_stats or args.summarize_sq or \
-            args.summarize_block_counters:
-        if args.summarize_sq:
+            args.summarize_block_counters or args.summarize_requests:
+        if args.summarize_requests:
+            txt = summarize_requests(args.summarize_requests, args.profiled_command)
+        elif args.summarize_sq:
             txt = summarize_sq(args.summarize_sq, args.profiled_command)
         elif args.summarize_block_counters:
             txt = summarize_block_counters(args.summarize_block_counters[0], args.summarize_block_counters[1],
