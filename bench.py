@@ -304,7 +304,9 @@ def summarize_requests(d, command):
     """L2-to-memory read requests per dispatch of the large single product's
     passes and of the copy calibration, from one --pmc run of
     TCC_EA0_RDREQ_sum, TCC_EA0_RDREQ_32B_sum, TCC_BUBBLE_sum and
-    TCC_EA0_RDREQ_DRAM_sum."""
+    TCC_EA0_RDREQ_DRAM_sum.  Passes: mean over their dispatches; the copy:
+    the median over copy dispatches (the calibration copies outnumber the
+    input uploads)."""
     names = ["TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_BUBBLE_sum", "TCC_EA0_RDREQ_DRAM_sum"]
     disp = _per_dispatch(d, set(names))
     order = sorted(disp)
@@ -312,38 +314,43 @@ def summarize_requests(d, command):
     groups = {}
     for k, kind in zip(order, kinds):
         nm = disp[k][0]
-        key = ("column pass (A and D)" if kind in ("pass_a", "pass_d") else "row pass (B)") if kind else (
-            "plain device copy (calibration)" if "copy" in nm.lower() else None)
-        if key is None:
+        if kind:
+            key = "column pass (A and D)" if kind in ("pass_a", "pass_d") else "row pass (B)"
+        elif "copy" in nm.lower():
+            key = "plain device copy of 1 GiB (calibration)"
+        else:
             continue
-        g = groups.setdefault(key, {"name": nm.split("(")[0].replace("void ", ""), "n": 0, "sum": {c: 0.0 for c in names}})
-        g["n"] += 1
-        for c in names:
-            g["sum"][c] += disp[k][1].get(c, 0.0)
+        g = groups.setdefault(key, {"name": nm.split("(")[0].replace("void ", ""), "vals": []})
+        g["vals"].append([disp[k][1].get(c, 0.0) for c in names])
+    stat = {}
+    for key, g in groups.items():
+        v = np.array(g["vals"])
+        if "copy" in key:
+            i = int(np.argsort(v[:, 0])[len(v) // 2])
+            stat[key] = v[i]
+        else:
+            stat[key] = v.mean(axis=0)
     lines = ["# L2-to-memory read requests per dispatch, large single product (order 4, n=2^18, N=2^20), c64",
              "", "Command (one rocprofv3 --pmc pass, 4 TCC counters):", "", f"    {command}", "",
              "| kernel | dispatches | TCC_EA0_RDREQ | of them 32 B | TCC_BUBBLE (128 B) | to DRAM |",
              "|---|---|---|---|---|---|"]
-    for key in ("column pass (A and D)", "row pass (B)", "plain device copy (calibration)"):
-        if key not in groups:
-            continue
-        g = groups[key]
-        m = {c: g["sum"][c] / g["n"] for c in names}
-        lines.append(f"| {key}: {g['name']} | {g['n']} | {m[names[0]]:,.0f} | {m[names[1]]:,.0f} | "
-                     f"{m[names[2]]:,.0f} | {m[names[3]]:,.0f} |")
-    if "plain device copy (calibration)" in groups and "row pass (B)" in groups:
-        cp = groups["plain device copy (calibration)"]
-        rq = cp["sum"][names[0]] / cp["n"]
-        row = groups["row pass (B)"]["sum"][names[0]] / groups["row pass (B)"]["n"]
-        col = groups.get("column pass (A and D)", {"sum": {names[0]: 0.0}, "n": 1})
-        colq = col["sum"][names[0]] / max(1, col["n"])
-        lines += ["", f"The copy's requests ({rq:,.0f} per dispatch) times 128 bytes give its bytes: FETCH_SIZE, which",
-                  "counts every request as 64 bytes when TCC_BUBBLE (the 128-byte request count) reads zero,",
-                  "reads half of them. Row pass: whole lines, "
-                  f"{row:,.0f} x 128 B = {row * 128 / 1e6:.1f} MB per dispatch (16.8 MB algorithmic reads); "
-                  f"column passes: {colq:,.0f} requests per dispatch, 64-byte tile rows = {colq * 64 / 1e6:.2f} MB "
-                  "(the mean of pass A's 10.5 MB and pass D's 8.4 MB algorithmic reads). The traffic summary",
-                  "scales FETCH_SIZE accordingly."]
+    for key in ("column pass (A and D)", "row pass (B)", "plain device copy of 1 GiB (calibration)"):
+        if key in stat:
+            m = stat[key]
+            lines.append(f"| {key}: {groups[key]['name']} | {len(groups[key]['vals'])} | {m[0]:,.0f} | {m[1]:,.0f} | "
+                         f"{m[2]:,.0f} | {m[3]:,.0f} |")
+    ck, rk, colk = "plain device copy of 1 GiB (calibration)", "row pass (B)", "column pass (A and D)"
+    if ck in stat and rk in stat and colk in stat:
+        rq, row, colq = stat[ck][0], stat[rk][0], stat[colk][0]
+        lines += ["",
+                  f"The copy reads 1 GiB in {rq:,.0f} requests ({2**30 / max(rq, 1):.0f} bytes each) while",
+                  "TCC_BUBBLE (the 128-byte request count that FETCH_SIZE weights) stays at zero:",
+                  "FETCH_SIZE counts every request as 64 bytes. The row pass reads whole lines",
+                  f"({row:,.0f} requests x 128 B = {row * 128 / 1e6:.1f} MB per dispatch against 16.8 MB",
+                  "algorithmic); the column passes read tile rows of 8 complex64 = 64 B",
+                  f"({colq:,.0f} requests x 64 B = {colq * 64 / 1e6:.2f} MB per dispatch, the mean of pass A's",
+                  "10.5 MB and pass D's 8.4 MB algorithmic reads). The traffic summary scales FETCH_SIZE",
+                  "accordingly."]
     return "\n".join(lines) + "\n"
 
 
