@@ -212,7 +212,7 @@ hk_status_t hankel_tvp_spectral_strided_batched(hk_dtype_t dt, const void *h_spe
 /* The transform grid of a BHHB shape (rows along the in-block index, columns
  * along the block index) for a call of `batch` instances under the current
  * length policy: each axis is the smallest of 2^k, 3 * 2^k, 5 * 2^k (complex
- * dtypes; odd column factors with an odd row factor) >= its extent
+ * dtypes; the axes' factors combine freely) >= its extent
  * (sum n_p - m + 1, sum N_p - m + 1) that has kernels, or the power of two.
  * An axis of length odd * 2^k is transformed as `odd` sequences of 2^k
  * through the Chinese-remainder index map.  Host-only. */
@@ -439,8 +439,9 @@ hk_status_t hankel_tvp_backward_spectral_strided_batched(
  *   grad_{x_p} = conj( H x_1 c x_q (q != 1, p) )         (mode p free, dims[p] values), p >= 2
  *   grad_{x_1} = phi conj( H x_2 ... x_m )               (zero when grad_alpha is NULL)
  * (* = linear convolution; 2D for BHHB; Section 2.1 mode products).  Each
- * is computed by the forward kernels on the power-of-two complex grid
- * (spectral correlations / convolutions), one after the other on `stream`.
+ * is computed by the forward kernels on the forward product's transform grid
+ * (N or each BHHB axis 2^k, 3 * 2^k or 5 * 2^k under the length policy:
+ * spectral correlations / convolutions), one after the other on `stream`.
  *   vectors      : host array of m device pointers; vectors[0] (x_1) is read
  *                  only when grad_alpha is given
  *   grad_y       : cotangent of y (dims[0] values; BHHB n_1 N_1) or NULL
