@@ -321,6 +321,22 @@ hk_status_t hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t 
 hk_status_t hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t count,
                                void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* The same one-shot batch restricted to one product kind: every problem a
+ * general (1D) Hankel tensor with dims and distinct or equal vectors
+ * (hankel_mode_products_batched, is_block = 0), or every problem a BHHB
+ * tensor (block_hankel_tvp_batched, is_block = 1).  A problem of the other
+ * kind is rejected with HK_ERR_INVALID_VALUE before anything is enqueued;
+ * otherwise arguments, workspace and blocking behaviour are those of
+ * hankel_tvp_batched. */
+hk_status_t hankel_mode_products_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs,
+                                                        int64_t count, size_t *bytes);
+hk_status_t hankel_mode_products_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t count,
+                                         void *ws, size_t ws_bytes, hipStream_t stream);
+hk_status_t block_hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs,
+                                                    int64_t count, size_t *bytes);
+hk_status_t block_hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t count,
+                                     void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* -------------------------------------------------------------------------
  * Level-k block Hankel tensor, 1 <= k <= 4 (Section 2.2: a block Hankel tensor
  * whose blocks are level-(k-1) block Hankel tensors; k = 2 is the BHHB tensor

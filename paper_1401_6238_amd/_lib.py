@@ -79,6 +79,10 @@ _SIGS = {
     "hk_plan_destroy": [_P],
     "hankel_tvp_batched_workspace_size": [_I, _P, _I64, _PSZ],
     "hankel_tvp_batched": [_I, _P, _I64, _P, _SZ, _P],
+    "hankel_mode_products_batched_workspace_size": [_I, _P, _I64, _PSZ],
+    "hankel_mode_products_batched": [_I, _P, _I64, _P, _SZ, _P],
+    "block_hankel_tvp_batched_workspace_size": [_I, _P, _I64, _PSZ],
+    "block_hankel_tvp_batched": [_I, _P, _I64, _P, _SZ, _P],
     "hankel_tvp_backward_workspace_size": [_I, _I, _I64, _PSZ],
     "hankel_tvp_save_spectrum_workspace_size": [_I, _I, _I64, _I64, _PSZ],
     "hankel_mode_products_backward_workspace_size": [_I, _I, _PI64, _I, _I, _PSZ],

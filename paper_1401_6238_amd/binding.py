@@ -576,6 +576,82 @@ def block_hankel_tvp_strided_batched(H: torch.Tensor, x: torch.Tensor, m: int, i
     return y, alpha
 
 
+def _problem_array(problems):
+    """hk_problem_t array of a sequence of problem dicts (keys m, dims, h,
+    vectors, optional block_dims, want_y, want_alpha), with the outputs it
+    allocates.  Returns (array, [(y, alpha)], tensors to keep alive, dtype,
+    device)."""
+    arr = (_lib.hk_problem_t * max(1, len(problems)))()
+    dtype = None
+    keep, outputs = [], []
+    ref = None
+    for i, p in enumerate(problems):
+        vecs = p["vectors"]
+        ref = next(v for v in vecs if v is not None)
+        _dev(ref)
+        dtype = ref.dtype if dtype is None else dtype
+        if ref.dtype != dtype:
+            raise TypeError("all problems of a batch share one dtype")
+        m = p["m"]
+        dims = p["dims"]
+        bd = p.get("block_dims")
+        want_y = p.get("want_y", True)
+        want_a = p.get("want_alpha", False)
+        if len(vecs) != m or len(dims) != m or (bd is not None and len(bd) != m):
+            raise ValueError(f"problem {i}: vectors, dims and block_dims need m entries")
+        hlen = _hlen(m, dims) * (_hlen(m, bd) if bd is not None else 1)
+        _arg(p["h"], f"problem {i} h", hlen, dtype, ref.device)
+        for k, v in enumerate(vecs):
+            if v is not None:
+                _arg(v, f"problem {i} vectors[{k}]", int(dims[k]) * (int(bd[k]) if bd is not None else 1),
+                     dtype, ref.device)
+            elif k > 0 or want_a:
+                raise ValueError(f"problem {i}: vectors[{k}] is needed")
+        ny = int(dims[0]) * (int(bd[0]) if bd is not None else 1)
+        y = torch.empty(ny, dtype=dtype, device=ref.device) if want_y else None
+        a = torch.empty(1, dtype=dtype, device=ref.device) if want_a else None
+        outputs.append((y, a))
+        keep.extend([y, a, p["h"]] + list(vecs))
+        q = arr[i]
+        q.m = m
+        q.is_block = 1 if bd is not None else 0
+        for k in range(m):
+            q.dims[k] = int(dims[k])
+            q.block_dims[k] = int(bd[k]) if bd is not None else 0
+            q.vectors[k] = None if vecs[k] is None else vecs[k].data_ptr()
+        q.h = p["h"].data_ptr()
+        q.y = None if y is None else y.data_ptr()
+        q.alpha = None if a is None else a.data_ptr()
+    device = ref.device if ref is not None else torch.device("cuda")
+    return arr, outputs, keep, dtype, device
+
+
+def _batched_oneshot(name: str, problems):
+    arr, outputs, keep, dtype, device = _problem_array(list(problems))
+    if not problems:
+        return outputs
+    dt = _DT[dtype]
+    nb = ctypes.c_size_t(0)
+    check(getattr(lib(), name + "_workspace_size")(dt, arr, len(problems), ctypes.byref(nb)),
+          name + "_workspace_size")
+    ws, ws_bytes = _workspace(max(256, nb.value), device)
+    check(getattr(lib(), name)(dt, arr, len(problems), _ptr(ws), ws_bytes, _stream(device)), name)
+    return outputs
+
+
+def hankel_mode_products_batched(problems):
+    """One-shot batch of general (1D) Hankel products through the C entry
+    point hankel_mode_products_batched; every problem without block_dims.
+    Returns a list of (y, alpha) per problem."""
+    return _batched_oneshot("hankel_mode_products_batched", problems)
+
+
+def block_hankel_tvp_batched(problems):
+    """One-shot batch of BHHB products (every problem with block_dims) through
+    the C entry point block_hankel_tvp_batched.  Returns a list of (y, alpha)."""
+    return _batched_oneshot("block_hankel_tvp_batched", problems)
+
+
 class Plan:
     """A batched plan over heterogeneous problems (hk_plan_*).
 
@@ -585,48 +661,7 @@ class Plan:
 
     def __init__(self, problems, flags: int = 0):
         self.problems = list(problems)
-        self.outputs = []
-        arr = (_lib.hk_problem_t * max(1, len(self.problems)))()
-        dtype = None
-        self._keep = []
-        for i, p in enumerate(self.problems):
-            vecs = p["vectors"]
-            ref = next(v for v in vecs if v is not None)
-            _dev(ref)
-            dtype = ref.dtype if dtype is None else dtype
-            if ref.dtype != dtype:
-                raise TypeError("all problems of a plan share one dtype")
-            m = p["m"]
-            dims = p["dims"]
-            bd = p.get("block_dims")
-            want_y = p.get("want_y", True)
-            want_a = p.get("want_alpha", False)
-            if len(vecs) != m or len(dims) != m or (bd is not None and len(bd) != m):
-                raise ValueError(f"problem {i}: vectors, dims and block_dims need m entries")
-            hlen = _hlen(m, dims) * (_hlen(m, bd) if bd is not None else 1)
-            _arg(p["h"], f"problem {i} h", hlen, dtype, ref.device)
-            for k, v in enumerate(vecs):
-                if v is not None:
-                    _arg(v, f"problem {i} vectors[{k}]", int(dims[k]) * (int(bd[k]) if bd is not None else 1),
-                         dtype, ref.device)
-                elif k > 0 or want_a:
-                    raise ValueError(f"problem {i}: vectors[{k}] is needed")
-            ny = int(dims[0]) * (int(bd[0]) if bd is not None else 1)
-            y = torch.empty(ny, dtype=dtype, device=ref.device) if want_y else None
-            a = torch.empty(1, dtype=dtype, device=ref.device) if want_a else None
-            self.outputs.append((y, a))
-            self._keep.extend([y, a, p["h"]] + list(vecs))
-            q = arr[i]
-            q.m = m
-            q.is_block = 1 if bd is not None else 0
-            for k in range(m):
-                q.dims[k] = int(dims[k])
-                q.block_dims[k] = int(bd[k]) if bd is not None else 0
-                q.vectors[k] = None if vecs[k] is None else vecs[k].data_ptr()
-            q.h = p["h"].data_ptr()
-            q.y = None if y is None else y.data_ptr()
-            q.alpha = None if a is None else a.data_ptr()
-        self.device = ref.device if self.problems else torch.device("cuda")
+        arr, self.outputs, self._keep, dtype, self.device = _problem_array(self.problems)
         self.dt = _DT[dtype] if dtype is not None else _lib.HK_C64
         self._arr = arr
         self._plan = ctypes.c_void_p()

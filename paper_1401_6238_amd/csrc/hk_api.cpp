@@ -1318,6 +1318,45 @@ hk_status_t hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t
   return finish(s);
 }
 
+// Batches of one product kind: the heterogeneous batch after a check that
+// every problem is of that kind (1D general Hankel tensors or BHHB tensors).
+static Status check_kind(const hk_problem_t *probs, int64_t count, int is_block) {
+  if (count > 0 && !probs) return fail(HK_ERR_NULL_POINTER, "probs is NULL");
+  for (int64_t i = 0; i < count; ++i)
+    if ((probs[i].is_block != 0) != (is_block != 0))
+      return fail(HK_ERR_INVALID_VALUE, is_block ? "problem " + std::to_string(i) + " is not a BHHB product"
+                                                 : "problem " + std::to_string(i) + " is a BHHB product");
+  return Status();
+}
+
+hk_status_t hankel_mode_products_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs, int64_t count,
+                                                        size_t *bytes) {
+  Status s = check_kind(probs, count, 0);
+  if (!s.ok()) return finish(s);
+  return hankel_tvp_batched_workspace_size(dt, probs, count, bytes);
+}
+
+hk_status_t hankel_mode_products_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t count, void *ws,
+                                         size_t ws_bytes, hipStream_t stream) {
+  Status s = check_kind(probs, count, 0);
+  if (!s.ok()) return finish(s);
+  return hankel_tvp_batched(dt, probs, count, ws, ws_bytes, stream);
+}
+
+hk_status_t block_hankel_tvp_batched_workspace_size(hk_dtype_t dt, const hk_problem_t *probs, int64_t count,
+                                                    size_t *bytes) {
+  Status s = check_kind(probs, count, 1);
+  if (!s.ok()) return finish(s);
+  return hankel_tvp_batched_workspace_size(dt, probs, count, bytes);
+}
+
+hk_status_t block_hankel_tvp_batched(hk_dtype_t dt, const hk_problem_t *probs, int64_t count, void *ws,
+                                     size_t ws_bytes, hipStream_t stream) {
+  Status s = check_kind(probs, count, 1);
+  if (!s.ok()) return finish(s);
+  return hankel_tvp_batched(dt, probs, count, ws, ws_bytes, stream);
+}
+
 // ---------------------------------------------------------------------------
 // Hankel tensor-matrix product T = H x_2 U ... x_m U (square H, the same U in
 // modes 2..m).  Column (j_2, ..., j_m) of T is the mode product with the

@@ -340,3 +340,28 @@ def test_spectral_batch_of_zero(L):
     P = ctypes.c_void_p
     assert L.hankel_tvp_spectral_strided_batched(HK_C64, P(256), 4, 1 << 14, P(256), 1 << 14, P(256), 1 << 14, None, 0,
                                                  None, 0, None) == OK
+
+
+def _problem(is_block):
+    q = _lib.hk_problem_t()
+    q.m = 3
+    q.is_block = is_block
+    for k in range(3):
+        q.dims[k] = 40
+        q.block_dims[k] = 30 if is_block else 0
+        q.vectors[k] = 0x10000 * (k + 1)
+    q.h = 0x100000
+    q.y = 0x200000
+    return q
+
+
+@pytest.mark.parametrize("fn,bad", [("hankel_mode_products_batched", 1), ("block_hankel_tvp_batched", 0)])
+def test_kind_restricted_batches_reject_the_other_kind(L, fn, bad):
+    """A problem of the other kind is rejected before any device work, in the
+    workspace query and in the call (every pointer here is a host-side dummy)."""
+    arr = (_lib.hk_problem_t * 2)(_problem(1 - bad), _problem(bad))
+    b = ctypes.c_size_t(0)
+    assert getattr(L, fn + "_workspace_size")(HK_C64, arr, 2, ctypes.byref(b)) == INVALID
+    assert getattr(L, fn)(HK_C64, arr, 2, ctypes.c_void_p(0x400000), 1 << 20, None) == INVALID
+    assert b"BHHB" in L.hk_last_error()
+    assert getattr(L, fn + "_workspace_size")(HK_C64, None, 1, ctypes.byref(b)) == NULLP

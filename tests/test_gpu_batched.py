@@ -95,6 +95,24 @@ def check_plan_outputs(probs, outs, dtype):
             check_alpha(av, ao, dtype)
 
 
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_kind_restricted_oneshot_batches(dtype):
+    """hankel_mode_products_batched and block_hankel_tvp_batched (the one-shot
+    C entry points for one product kind) against the oracle."""
+    import paper_1401_6238_amd as hk
+    probs = mixed_problems(4242, 40)
+    one_d = [p for p in probs if not p.is_block]
+    blocks = [wl.random_problem(4300 + i, m, [n] * m, i % 2 == 0, want_alpha=True, block_dims=[nb] * m)
+              for i, (m, n, nb) in enumerate([(3, 20, 15), (2, 33, 40), (4, 9, 12), (3, 64, 64)])]
+    print_case(test="kind_batches", dtype=dtype, n1d=len(one_d), nblock=len(blocks))
+    outs = hk.hankel_mode_products_batched(plan_inputs(one_d, dtype))
+    torch.cuda.synchronize()
+    check_plan_outputs(one_d, outs, dtype)
+    outs = hk.block_hankel_tvp_batched(plan_inputs(blocks, dtype))
+    torch.cuda.synchronize()
+    check_plan_outputs(blocks, outs, dtype)
+
+
 @pytest.mark.parametrize("flags", ["persistent", "multikernel"])
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 def test_plan_mixed(flags, dtype):
