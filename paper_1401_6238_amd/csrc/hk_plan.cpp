@@ -228,6 +228,11 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int6
         c.resident = true;
         c.logR = logM;
         c.logC = 0;
+      } else if (odd == 5 && policy == HK_LENGTHS_AUTO) {
+        // three-pass factor-5 rows hold five sequences per lane group and
+        // spill: measured slower than the next length (3 * 2^k or 2^k) for
+        // single products and for the mixed batch
+        continue;
       } else if (!split_of(logM, split, omax, &c.logR, &c.logC)) {
         continue;
       }
@@ -281,6 +286,7 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int6
         int lr = 0;
         const int64_t nr = axis(rows, orow, &lr);
         if (lr > odd_max_logl(p.dt, orow, p.prog)) continue;
+        if (orow == 5 && policy == HK_LENGTHS_AUTO) continue;  // the factor-5 row pass spills (see 1D)
         if (nr_odd < 0 || nr < nr_odd) {
           nr_odd = nr;
           orow_best = orow;

@@ -245,14 +245,16 @@ def test_levels_argument_errors(L):
 
 def test_length_policies(L):
     """auto: odd-factor lengths once the power-of-two length reaches 2^18 (one
-    product); pow2: never; smallest: always; unknown policies rejected."""
+    product), the factor 5 only where the transform is resident; pow2: never;
+    smallest: always; unknown policies rejected."""
     assert L.hk_get_fft_lengths() == 0
     assert fft_layout(L, 190)[0] == 256 and fft_layout(L, 12000)[0] == 16384
-    assert fft_layout(L, 196606)[0] == 3 << 16 and fft_layout(L, 1100000)[0] == 5 << 18
+    # 1,100,000 > 2^20: 5 * 2^18 would be three-pass, so auto takes 3 * 2^19
+    assert fft_layout(L, 196606)[0] == 3 << 16 and fft_layout(L, 1100000)[0] == 3 << 19
     assert L.hk_set_fft_lengths(1) == OK
     assert fft_layout(L, 196606)[0] == 1 << 18
     assert L.hk_set_fft_lengths(2) == OK
-    assert fft_layout(L, 190)[0] == 192
+    assert fft_layout(L, 190)[0] == 192 and fft_layout(L, 1100000)[0] == 5 << 18
     assert L.hk_set_fft_lengths(7) == INVALID
     assert L.hk_set_fft_lengths(0) == OK and L.hk_get_fft_lengths() == 0
 
