@@ -1155,9 +1155,7 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         for name, flags in (("persistent_graph", _lib.HK_PLAN_PERSISTENT | _lib.HK_PLAN_GRAPH),
-                            ("grouped_graph", _lib.HK_PLAN_MULTIKERNEL | _lib.HK_PLAN_GRAPH),
-                            ("grouped_autotune_graph", _lib.HK_PLAN_MULTIKERNEL | _lib.HK_PLAN_GRAPH |
-                             _lib.HK_PLAN_AUTOTUNE)):
+                            ("grouped_graph", _lib.HK_PLAN_MULTIKERNEL | _lib.HK_PLAN_GRAPH)):
             plan = hk.Plan(items, flags=flags)
             ms = time_region(torch, plan.execute, 10)
             plan.status()

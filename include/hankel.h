@@ -255,11 +255,13 @@ typedef struct hk_plan_s *hk_plan_t;
 #define HK_PLAN_MULTIKERNEL 0x2u /* grouped launches: per phase, one kernel specialised for each
                                    (task kind, transform length) group; no in-kernel waits      */
 #define HK_PLAN_GRAPH 0x4u      /* capture the plan's launches in a hipGraph on first execute */
-#define HK_PLAN_AUTOTUNE 0x8u   /* grouped plans: at the first execute, choose per length
-                                   bucket (log2 of the power-of-two length >= d_H) between
-                                   the odd-factor and the power-of-two transform lengths by
-                                   timing the whole plan (coordinate descent, longest bucket
-                                   first); the workspace size covers every candidate       */
+#define HK_PLAN_AUTOTUNE 0x8u   /* grouped eager plans: at the first execute, choose per
+                                   length bucket (log2 of the power-of-two length >= d_H)
+                                   between the odd-factor lengths, the odd lengths without
+                                   the factor 5 and the power-of-two lengths by timing the
+                                   whole plan (coordinate descent, longest bucket first);
+                                   the workspace size covers every candidate.  No effect
+                                   together with HK_PLAN_GRAPH                               */
 #define HK_PLAN_POW2 0x10u      /* power-of-two complex transforms only (no 3 * 2^k, 5 * 2^k,
                                    no half-length real transforms); implied by PERSISTENT      */
 

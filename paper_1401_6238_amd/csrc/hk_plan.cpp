@@ -167,7 +167,7 @@ void set_length_policy(int policy) { g_length_policy.store(policy); }
 int length_policy() { return g_length_policy.load(); }
 constexpr int64_t kOddWorkMin = (int64_t)1 << 18;
 
-Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int64_t batch) {
+Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int64_t batch, bool allow5) {
   const int policy = g_length_policy.load();
   const bool allow_r2c = allow_odd && policy != HK_LENGTHS_POW2;
   if (policy == HK_LENGTHS_POW2) allow_odd = false;
@@ -214,6 +214,7 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int6
     // The smallest N = odd * 2^logM >= d_H among the lengths with kernels.
     int64_t bestN = -1;
     for (int odd : {1, 3, 5}) {
+      if (odd == 5 && !allow5) continue;
       const int omax = odd == 1 ? MAX_LOGL : (allow_odd ? odd_max_logl(p.dt, odd, p.prog) : -1);
       if (omax < 0) continue;
       int logM = 0;

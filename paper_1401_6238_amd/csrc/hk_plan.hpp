@@ -92,7 +92,10 @@ Status validate_backward(const Problem &p);
 // with N <= 8192 a length-N real transform done as a length-N/2 complex one;
 // powers of two only when allow_odd is false), resident vs multipass and the
 // split.
-Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd = true, int64_t batch = 1);
+// allow5 = false leaves the factor 5 out of the 1D lengths (the plan
+// autotuner's per-bucket alternative).
+Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd = true, int64_t batch = 1,
+                  bool allow5 = true);
 // Process-wide transform-length policy (see hk_set_fft_lengths).
 void set_length_policy(int policy);
 int length_policy();
