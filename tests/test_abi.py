@@ -367,3 +367,48 @@ def test_kind_restricted_batches_reject_the_other_kind(L, fn, bad):
     assert getattr(L, fn)(HK_C64, arr, 2, ctypes.c_void_p(0x400000), 1 << 20, None) == INVALID
     assert b"BHHB" in L.hk_last_error()
     assert getattr(L, fn + "_workspace_size")(HK_C64, None, 1, ctypes.byref(b)) == NULLP
+
+
+def _mixed_problem_array(count=512, seed=11):
+    """Host-side descriptors with dummy (aligned, never dereferenced) device
+    pointers: orders 3..5, d_H from a few hundred to ~80 k, equal and
+    distinct vectors."""
+    import numpy as np
+    g = np.random.Generator(np.random.PCG64(seed))
+    arr = (_lib.hk_problem_t * count)()
+    base = 1 << 30
+    for i in range(count):
+        q = arr[i]
+        q.m = int(g.integers(3, 6))
+        n = int(np.exp(g.uniform(np.log(64), np.log(16384))))
+        equal = bool(g.integers(0, 2))
+        for k in range(q.m):
+            q.dims[k] = n
+            if k > 0:
+                q.vectors[k] = base + (256 if equal else 256 * k)
+        q.h = base + 4096
+        q.y = base + 8192
+        base += 1 << 20
+    return arr
+
+
+def test_autotune_workspace_covers_every_candidate(L):
+    """HK_PLAN_AUTOTUNE may rebuild any length bucket with powers of two or
+    without the factor 5: its workspace query must cover the default plan and
+    the all-powers-of-two plan (the plans need no device to be built)."""
+    arr = _mixed_problem_array()
+
+    def ws_of(flags):
+        plan = ctypes.c_void_p()
+        assert L.hk_plan_create(ctypes.byref(plan), HK_C64, arr, len(arr), flags) == OK, L.hk_last_error()
+        b = ctypes.c_size_t(0)
+        assert L.hk_plan_workspace_size(plan, ctypes.byref(b)) == OK
+        assert L.hk_plan_destroy(plan) == OK
+        return b.value
+
+    grouped = _lib.HK_PLAN_MULTIKERNEL
+    tuned = ws_of(grouped | _lib.HK_PLAN_AUTOTUNE)
+    assert tuned >= ws_of(grouped)
+    assert tuned >= ws_of(grouped | _lib.HK_PLAN_POW2)
+    # graph plans are not tuned: no extra workspace
+    assert ws_of(grouped | _lib.HK_PLAN_AUTOTUNE | _lib.HK_PLAN_GRAPH) == ws_of(grouped | _lib.HK_PLAN_GRAPH)
