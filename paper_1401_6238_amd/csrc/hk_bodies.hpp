@@ -307,6 +307,23 @@ __device__ __forceinline__ cx<T> segment_sum(cx<T> v, cx<T> *red, int tid, int S
   return red[tid];
 }
 
+// Sum over a workgroup of n lanes, any n, valid in thread 0: a tree over the
+// LDS that folds lanes [s, 2s) onto [0, s) for s = the halves of the next
+// power of two (fixed order, bitwise reproducible).  red holds n values.
+template <typename T>
+__device__ __forceinline__ cx<T> ragged_sum(cx<T> v, cx<T> *red, int tid, int n) {
+  __syncthreads();
+  red[tid] = v;
+  int s = 1;
+  while (s < n) s <<= 1;
+  for (s >>= 1; s > 0; s >>= 1) {
+    __syncthreads();
+    if (tid < s && tid + s < n) red[tid] = cadd(red[tid], red[tid + s]);
+  }
+  __syncthreads();
+  return red[0];
+}
+
 // Sum over the whole workgroup (blockDim.x a multiple of 64), valid in
 // thread 0: each wavefront folds its lanes with cross-lane shuffles (a fixed
 // butterfly order), then thread 0 adds the wavefronts' sums in index order.

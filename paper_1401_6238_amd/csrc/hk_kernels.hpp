@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
       // One partial sum per workgroup; the next kernel in the stream (pass D
       // or the reduction kernel) adds them in index order.  No cross-workgroup
       // fence is needed: the kernel boundary makes them visible.
-      const cx<T> tot = (blockDim.x & 63) == 0 ? block_sum(part, red, tid) : segment_sum(part, red, tid, (int)blockDim.x);
+      const cx<T> tot = (blockDim.x & 63) == 0 ? block_sum(part, red, tid) : ragged_sum(part, red, tid, (int)blockDim.x);
       if (tid == 0) ws_partials<T>(sh, P)[blockIdx.x] = tot;
     }
   }
@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(MAXT) k_rows_r2c_pairs(Shape sh, Ptrs p0, Stri
   const cx<T> part =
       PB::run_fwd(sh, P, valid ? pi : 0, g, valid, t, smem + pw * 2 * PB::SEQ_LDS, g_tw24, g_tw4096);
   if (sh.want_alpha) {
-    const cx<T> tot = segment_sum(part, smem, tid, (int)blockDim.x);
+    const cx<T> tot = ragged_sum(part, smem, tid, (int)blockDim.x);
     if (tid == 0) ws_partials<T>(sh, P)[blockIdx.x] = tot;
   }
 }

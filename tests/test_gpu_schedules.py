@@ -146,3 +146,37 @@ def test_autotuned_odd_and_real_shapes():
     yo, ao = oracle.tvp(m, [n] * m, seen(p.h, rdt), [seen(p.vectors[1], rdt)] * m, True, True)
     assert rel(host(y), yo) <= TOL[rdt]
     check_alpha(complex(host(a.reshape(1))[0]), ao, rdt)
+
+
+@pytest.mark.parametrize("rows", [1, 3, 5])
+def test_ragged_workgroup_sums(tmp_path, rows):
+    """Row-pass workgroups whose lane count is not a power of two (3 or 5
+    rows per workgroup): the scalar's per-workgroup partial sums on the
+    odd-factor rows (N = 3 * 2^12, complex, 16 lanes a row) and on the
+    mirrored real row pairs (real N = 2^14, 32 lanes a pair), y and alpha
+    against the oracle."""
+    import paper_1401_6238_amd as hk
+    hk.hk_set_fft_lengths("smallest")
+    try:
+        m, n = 3, 4096
+        dtype = torch.complex64
+        prob = wl.random_problem(4600 + rows, m, [n] * m, True, want_alpha=True)
+        yo, ao = oracle.tvp(m, [n] * m, seen(prob.h, dtype), [seen(prob.vectors[1], dtype)] * m, True, True)
+        print_case(test="ragged_sums_odd", rows=rows)
+        install(tmp_path, (0, 0, 0, 3, 12, -1, 0), (4, rows, 8, 8, 0, 0, 1))
+        y, a = hk.hankel_tvp(to_dev(prob.h, dtype), to_dev(prob.vectors[1], dtype), m, True, True)
+        torch.cuda.synchronize()
+        assert rel(host(y), yo) <= TOL[dtype]
+        check_alpha(complex(host(a.reshape(1))[0]), ao, dtype, rows)
+    finally:
+        hk.hk_set_fft_lengths("auto")
+    rdt = torch.float32
+    m, n = 3, 5000  # real N = 2^14: rows of 2^7 complex points in mirrored pairs
+    p = wl.random_problem(4700 + rows, m, [n] * m, True, complex_=False, want_alpha=True)
+    yo, ao = oracle.tvp(m, [n] * m, seen(p.h, rdt), [seen(p.vectors[1], rdt)] * m, True, True)
+    print_case(test="ragged_sums_real", rows=rows)
+    install(tmp_path, (2, 0, 0, 2, 13, -1, 0), (8, rows, 16, 8, 0, 0, 1))
+    y, a = hk.hankel_tvp(to_dev(p.h, rdt), to_dev(p.vectors[1], rdt), m, True, True)
+    torch.cuda.synchronize()
+    assert rel(host(y), yo) <= TOL[rdt]
+    check_alpha(complex(host(a.reshape(1))[0]), ao, rdt, rows)
