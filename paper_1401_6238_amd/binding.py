@@ -587,7 +587,9 @@ def _problem_array(problems):
     ref = None
     for i, p in enumerate(problems):
         vecs = p["vectors"]
-        ref = next(v for v in vecs if v is not None)
+        ref = next((v for v in vecs if v is not None), None)
+        if ref is None:
+            raise ValueError(f"problem {i}: no vector given")
         _dev(ref)
         dtype = ref.dtype if dtype is None else dtype
         if ref.dtype != dtype:

@@ -145,3 +145,11 @@ def test_cotangent_conj_view_is_materialized(B):
     got = B._cotangent(neg, "grad_y", 3, C, v.device)
     assert not got.is_neg() and not got.is_conj()
     assert torch.equal(got, -v)
+
+
+def test_batched_oneshot_rejects(B):
+    with pytest.raises(ValueError, match="problem 0: no vector given"):
+        B.hankel_mode_products_batched([dict(m=2, dims=[4, 3], h=z(6), vectors=[None, None])])
+    probs = [dict(m=3, dims=[4, 4, 4], h=z(9), vectors=[None, z(4), z(4)])]
+    with pytest.raises(ValueError, match="problem 0 h has 9"):
+        B.block_hankel_tvp_batched(probs)
