@@ -34,39 +34,44 @@ constexpr bool HAS_ODD5 = sizeof(T) == 4;
 
 constexpr bool has_bwd(int odd) { return sizeof(T) == 4 && odd == 3; }
 
+// resident instances and pass-B rows are separate kernels (k_rows_res,
+// k_rows_pass): each path gets its own register allocation
 template <int L, int ODD>
-static void *row_fn(int prog) {
+static void *row_fn(int prog, bool res) {
   if (prog == PROG_BWD) {
-    if constexpr (has_bwd(ODD)) return (void *)&k_rows<L, ODD_E, ODD_ROW_MAXT, PROG_BWD, ODD>;
+    if constexpr (has_bwd(ODD))
+      return res ? (void *)&k_rows_res<L, ODD_E, ODD_ROW_MAXT, PROG_BWD, ODD>
+                 : (void *)&k_rows_pass<L, ODD_E, ODD_ROW_MAXT, PROG_BWD, ODD>;
     return nullptr;
   }
-  return (void *)&k_rows<L, ODD_E, ODD_ROW_MAXT, PROG_FWD, ODD>;
+  return res ? (void *)&k_rows_res<L, ODD_E, ODD_ROW_MAXT, PROG_FWD, ODD>
+             : (void *)&k_rows_pass<L, ODD_E, ODD_ROW_MAXT, PROG_FWD, ODD>;
 }
 
 template <int ODD>
-static void *pick_row(int logL, int prog) {
+static void *pick_row(int logL, int prog, bool res) {
   switch (logL) {
-    case 0: return row_fn<1, ODD>(prog);
-    case 1: return row_fn<2, ODD>(prog);
-    case 2: return row_fn<4, ODD>(prog);
-    case 3: return row_fn<8, ODD>(prog);
-    case 4: return row_fn<16, ODD>(prog);
-    case 5: return row_fn<32, ODD>(prog);
-    case 6: return row_fn<64, ODD>(prog);
-    case 7: return row_fn<128, ODD>(prog);
-    case 8: return row_fn<256, ODD>(prog);
-    case 9: return row_fn<512, ODD>(prog);
-    case 10: return row_fn<1024, ODD>(prog);
-    case 11: return row_fn<2048, ODD>(prog);
+    case 0: return row_fn<1, ODD>(prog, res);
+    case 1: return row_fn<2, ODD>(prog, res);
+    case 2: return row_fn<4, ODD>(prog, res);
+    case 3: return row_fn<8, ODD>(prog, res);
+    case 4: return row_fn<16, ODD>(prog, res);
+    case 5: return row_fn<32, ODD>(prog, res);
+    case 6: return row_fn<64, ODD>(prog, res);
+    case 7: return row_fn<128, ODD>(prog, res);
+    case 8: return row_fn<256, ODD>(prog, res);
+    case 9: return row_fn<512, ODD>(prog, res);
+    case 10: return row_fn<1024, ODD>(prog, res);
+    case 11: return row_fn<2048, ODD>(prog, res);
   }
   return nullptr;
 }
 
-static void *row_kernel(int odd, int logL, int E, int prog) {
+static void *row_kernel(int odd, int logL, int E, int prog, bool res) {
   if (E != ODD_E || logL < 0 || logL > ODD_MAX_LOGL) return nullptr;
-  if (odd == 3) return pick_row<3>(logL, prog);
+  if (odd == 3) return pick_row<3>(logL, prog, res);
   if constexpr (HAS_ODD5)
-    if (odd == 5) return pick_row<5>(logL, prog);
+    if (odd == 5) return pick_row<5>(logL, prog, res);
   return nullptr;
 }
 
@@ -246,7 +251,7 @@ hipError_t HK_CAT(launch_rows_odd_, HK_SUFFIX)(int odd, int logL, int E, int row
                                                const Shape &sh, const Ptrs &p0, const Strides &str, int64_t count,
                                                hipStream_t st) {
   using namespace HK_NS;
-  void *fn = row_kernel(odd, logL, E, sh.prog);
+  void *fn = row_kernel(odd, logL, E, sh.prog, sh.resident != 0);
   KernelLimits k;
   if (!fn || sh.odd != odd || !HK_CAT(limits_odd_, HK_SUFFIX)(odd, logL, E, &k)) return hipErrorInvalidValue;
   const int threads = rows_per_wg * k.tps;

@@ -27,9 +27,11 @@ struct ColJobs {
 };
 
 // Rows of length L (ODD sequences each): resident instances
-// (blockIdx.x * rows + rw) or pass-B rows of instance blockIdx.y.
-template <int L, int E, int MAXT, int PROG, int ODD = 1>
-__global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, int64_t count) {
+// (blockIdx.x * rows + rw) or pass-B rows of instance blockIdx.y.  PATH
+// picks both at run time (sh.resident) or one of them at compile time.
+enum : int { ROWS_ANY = 0, ROWS_RES = 1, ROWS_PASS = 2 };
+template <int L, int E, int PROG, int ODD, int PATH>
+__device__ __forceinline__ void rows_body(const Shape &sh, const Ptrs &p0, const Strides &str, int64_t count) {
   using RB = RowBody<T, L, E, ODD>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T> *smem = (cx<T> *)smem_raw;
@@ -39,20 +41,24 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
   const int t = tid % RB::TPS;
   cx<T> *lds = smem + rw * RB::SEQ_LDS;
   cx<T> *red = smem;  // reused for reductions after the transforms
-  if (sh.resident) {
-    const int64_t inst = (int64_t)blockIdx.x * rows + rw;
-    const bool valid = inst < count;
-    const PV P{&p0, &str, valid ? inst : 0, nullptr};
-    if (PROG == PROG_BWD || PROG == PROG_BWD_SPEC) {
-      RB::template run_bwd<PROG == PROG_BWD_SPEC>(sh, P, 0, valid, t, lds, true, g_tw24, g_tw4096);
+  if constexpr (PATH != ROWS_PASS) {
+    if (PATH == ROWS_RES || sh.resident) {
+      const int64_t inst = (int64_t)blockIdx.x * rows + rw;
+      const bool valid = inst < count;
+      const PV P{&p0, &str, valid ? inst : 0, nullptr};
+      if (PROG == PROG_BWD || PROG == PROG_BWD_SPEC) {
+        RB::template run_bwd<PROG == PROG_BWD_SPEC>(sh, P, 0, valid, t, lds, true, g_tw24, g_tw4096);
+        return;
+      }
+      const cx<T> part = RB::run_fwd(sh, P, 0, valid, t, lds, true, g_tw24, g_tw4096);
+      if (sh.want_alpha) {
+        const cx<T> tot = segment_sum(part, red, tid, RB::TPS);
+        if (valid && t == 0) store_out<T>(P.alpha(), 0, tot, sh.real_out);
+      }
       return;
     }
-    const cx<T> part = RB::run_fwd(sh, P, 0, valid, t, lds, true, g_tw24, g_tw4096);
-    if (sh.want_alpha) {
-      const cx<T> tot = segment_sum(part, red, tid, RB::TPS);
-      if (valid && t == 0) store_out<T>(P.alpha(), 0, tot, sh.real_out);
-    }
-  } else {
+  }
+  if constexpr (PATH != ROWS_RES) {
     const int64_t inst = blockIdx.y;
     const PV P{&p0, &str, inst, nullptr};
     // rows of this workgroup: (blockIdx.x * K + it) * rows + rw, it < K
@@ -72,6 +78,23 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
       if (tid == 0) ws_partials<T>(sh, P)[blockIdx.x] = tot;
     }
   }
+}
+
+template <int L, int E, int MAXT, int PROG, int ODD = 1>
+__global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, int64_t count) {
+  rows_body<L, E, PROG, ODD, ROWS_ANY>(sh, p0, str, count);
+}
+// The odd-factor rows come as two kernels, resident instances and pass-B
+// rows: compiled together, the two paths' register needs add up (factor 3:
+// 205-225 VGPRs against 117-141 resident alone; factor 5 resident rows
+// spilled to scratch).
+template <int L, int E, int MAXT, int PROG, int ODD>
+__global__ void __launch_bounds__(MAXT) k_rows_res(Shape sh, Ptrs p0, Strides str, int64_t count) {
+  rows_body<L, E, PROG, ODD, ROWS_RES>(sh, p0, str, count);
+}
+template <int L, int E, int MAXT, int PROG, int ODD>
+__global__ void __launch_bounds__(MAXT) k_rows_pass(Shape sh, Ptrs p0, Strides str, int64_t count) {
+  rows_body<L, E, PROG, ODD, ROWS_PASS>(sh, p0, str, count);
 }
 
 // Real-input resident rows (RealRowBody): instance blockIdx.x * rows + rw.
