@@ -566,7 +566,10 @@ hk_status_t hk_autotune(hk_dtype_t dt, int kind, int m, int64_t n, const int64_t
  * loaded) to a text file, one line per shape key; hk_tune_load merges such a
  * file into the cache (*n_loaded = entries read, may be NULL) so that a
  * process can reuse schedules tuned earlier on the same kind of device
- * without running the autotuner.  A malformed or out-of-range line rejects
+ * without running the autotuner.  Values: E_row 4, 8 or 16; 1-64 rows per
+ * workgroup; E_col 8 or 16; a column-tile width that is a power of two from 1
+ * to 64; split -4..4; XCD numbering 0 or 1; 1, 2 or 4 rows in turn.  A
+ * malformed or out-of-range line rejects
  * the whole file with HK_ERR_INVALID_VALUE and leaves the cache unchanged;
  * loaded entries that the kernels cannot run are ignored at use time.  Host
  * only: no device work. */

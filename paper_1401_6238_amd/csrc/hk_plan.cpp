@@ -535,7 +535,8 @@ bool sched_valid(hk_dtype_t dt, const Layout &lay, const Sched &sc) {
   if (!lay.resident) {
     if (sc.E_col != 8 && sc.E_col != 16) return false;  // the column kernels built
     if (!lim(dt, lay.logC, sc.E_col, &kc)) return false;
-    if (sc.tw < 1 || sc.tw * kc.tps > COL_MAXT) return false;
+    // column tiles interleave TW columns in the LDS by log2(TW): powers of two only
+    if (sc.tw < 1 || (sc.tw & (sc.tw - 1)) != 0 || sc.tw * kc.tps > COL_MAXT) return false;
     if ((size_t)sc.tw * kc.lds_raw * kc.elem_bytes > 160 * 1024) return false;
   }
   return true;
@@ -955,7 +956,8 @@ Status sched_load(const char *path, int *loaded) {
     s.iters = v[6];
     // entries are re-checked against the kernel limits when used (sched_valid)
     const bool val_ok = (s.E_row == 4 || s.E_row == 8 || s.E_row == 16) && (s.E_col == 8 || s.E_col == 16) &&
-                        s.rows_per_wg >= 1 && s.rows_per_wg <= 64 && s.tw >= 1 && s.tw <= 64 && s.split >= -4 &&
+                        s.rows_per_wg >= 1 && s.rows_per_wg <= 64 && s.tw >= 1 && s.tw <= 64 &&
+                        (s.tw & (s.tw - 1)) == 0 && s.split >= -4 &&
                         s.split <= 4 && (s.xcd == 0 || s.xcd == 1) && (s.iters == 1 || s.iters == 2 || s.iters == 4);
     if (!key_ok || !val_ok) {
       st = fail(HK_ERR_INVALID_VALUE, std::string(path) + ": value out of range on line " + std::to_string(lineno));

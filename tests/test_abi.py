@@ -202,6 +202,10 @@ def test_tune_db_round_trip(L, tmp_path):
     three = tmp_path / "three.txt"
     three.write_text("0 0 0 20 -1 0 : 8 1 16 8 0 0 3\n")  # 3 rows in turn is not offered
     assert L.hk_tune_load(str(three).encode(), None) == INVALID
+    three.write_text("0 0 0 20 -1 0 : 8 1 16 3 0 0 1\n")  # column tiles are powers of two wide
+    assert L.hk_tune_load(str(three).encode(), None) == INVALID
+    three.write_text("0 0 0 21 -1 0 : 8 3 16 4 0 0 1\n")  # any number of rows per workgroup
+    assert L.hk_tune_load(str(three).encode(), None) == OK
     bad = tmp_path / "bad.txt"
     bad.write_text("0 0 0 20 -1 0 : 8 1 16 8\n")
     assert L.hk_tune_load(str(bad).encode(), None) == INVALID
