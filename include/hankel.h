@@ -77,7 +77,7 @@ typedef int hk_status_t;
 #define HK_ERR_DEVICE 6        /* current device is not gfx950                              */
 #define HK_ERR_HIP 7           /* a HIP runtime call or kernel launch failed                */
 #define HK_ERR_DEVICE_FAULT 8  /* a batched plan's kernel reported an error (see status)    */
-#define HK_ERR_NOT_SUPPORTED 9 /* valid request outside what this build implements          */
+#define HK_ERR_NOT_SUPPORTED 9 /* valid request outside what the library implements         */
 
 #define HK_MAX_ORDER 8
 #define HK_MAX_FFT_LOG2 24 /* 1D: N <= 2^24; BHHB: each grid axis <= 2^12 */
