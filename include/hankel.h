@@ -527,9 +527,11 @@ hk_status_t block_hankel_tvp_strided_batched(hk_dtype_t dt, const void *H, int64
  * work is large enough to fill the device (instances * the power-of-two
  * length >= 2^18: a plan's instances, a strided batch's count) and takes the
  * power of two otherwise, where the odd lengths' longer per-lane sequences
- * would cost latency; under AUTO the factor 5 is taken only for resident
- * transforms (5 * 2^k with 2^k <= 2048) and not for BHHB row axes, where its
- * three-pass row kernels are slower than the next length (3 * 2^k or 2^k);
+ * would cost latency; under AUTO the factor 5 is taken for resident
+ * transforms (5 * 2^k with 2^k <= 2048), for three-pass ones only where
+ * instances * N >= 2^22 (strided batches and single calls; not in plans), and
+ * not for BHHB row axes: with less work its three-pass row kernels are slower
+ * than the next length (3 * 2^k or 2^k);
  * HK_LENGTHS_POW2 takes power-of-two complex transforms
  * only.  Real forward products use their half-length transform under AUTO
  * and SMALLEST.  Workspace sizes depend on the policy: query them under the

@@ -305,7 +305,7 @@ static Status plan_build(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *prob
     const bool forced = !pr.is_block && ((pow2_buckets >> bucket) & 1u);
     const bool no5 = !pr.is_block && ((no5_buckets >> bucket) & 1u);
     // the grouped and persistent kernels run BHHB on power-of-two grids
-    s = layout_for(pr, 0, &lay, allow_odd && !forced && !pr.is_block, count, !no5);
+    s = layout_for(pr, 0, &lay, allow_odd && !forced && !pr.is_block, count, no5 ? F5_NONE : F5_RESIDENT);
     if (!s.ok()) {
       delete p;
       return fail(s.code, "problem " + std::to_string(i) + ": " + s.msg);

@@ -36,42 +36,48 @@ constexpr bool has_bwd(int odd) { return sizeof(T) == 4 && odd == 3; }
 
 // resident instances and pass-B rows are separate kernels (k_rows_res,
 // k_rows_pass): each path gets its own register allocation
+// Factor-5 forward pass-B rows one per lane group (no rows in turn):
+// k_rows_pass1, which fits the registers where the streamed kernel spills
+// (2-4 % faster); the factor-3 rows measured 1-2 % slower that way at three
+// waves per SIMD and keep the streamed kernel.
 template <int L, int ODD>
-static void *row_fn(int prog, bool res) {
+static void *row_fn(int prog, bool res, bool one_row) {
   if (prog == PROG_BWD) {
     if constexpr (has_bwd(ODD))
       return res ? (void *)&k_rows_res<L, ODD_E, ODD_ROW_MAXT, PROG_BWD, ODD>
                  : (void *)&k_rows_pass<L, ODD_E, ODD_ROW_MAXT, PROG_BWD, ODD>;
     return nullptr;
   }
-  return res ? (void *)&k_rows_res<L, ODD_E, ODD_ROW_MAXT, PROG_FWD, ODD>
-             : (void *)&k_rows_pass<L, ODD_E, ODD_ROW_MAXT, PROG_FWD, ODD>;
+  if (res) return (void *)&k_rows_res<L, ODD_E, ODD_ROW_MAXT, PROG_FWD, ODD>;
+  if constexpr (ODD == 5)
+    if (one_row) return (void *)&k_rows_pass1<L, ODD_E, ODD_ROW_MAXT, ODD>;
+  return (void *)&k_rows_pass<L, ODD_E, ODD_ROW_MAXT, PROG_FWD, ODD>;
 }
 
 template <int ODD>
-static void *pick_row(int logL, int prog, bool res) {
+static void *pick_row(int logL, int prog, bool res, bool one_row) {
   switch (logL) {
-    case 0: return row_fn<1, ODD>(prog, res);
-    case 1: return row_fn<2, ODD>(prog, res);
-    case 2: return row_fn<4, ODD>(prog, res);
-    case 3: return row_fn<8, ODD>(prog, res);
-    case 4: return row_fn<16, ODD>(prog, res);
-    case 5: return row_fn<32, ODD>(prog, res);
-    case 6: return row_fn<64, ODD>(prog, res);
-    case 7: return row_fn<128, ODD>(prog, res);
-    case 8: return row_fn<256, ODD>(prog, res);
-    case 9: return row_fn<512, ODD>(prog, res);
-    case 10: return row_fn<1024, ODD>(prog, res);
-    case 11: return row_fn<2048, ODD>(prog, res);
+    case 0: return row_fn<1, ODD>(prog, res, one_row);
+    case 1: return row_fn<2, ODD>(prog, res, one_row);
+    case 2: return row_fn<4, ODD>(prog, res, one_row);
+    case 3: return row_fn<8, ODD>(prog, res, one_row);
+    case 4: return row_fn<16, ODD>(prog, res, one_row);
+    case 5: return row_fn<32, ODD>(prog, res, one_row);
+    case 6: return row_fn<64, ODD>(prog, res, one_row);
+    case 7: return row_fn<128, ODD>(prog, res, one_row);
+    case 8: return row_fn<256, ODD>(prog, res, one_row);
+    case 9: return row_fn<512, ODD>(prog, res, one_row);
+    case 10: return row_fn<1024, ODD>(prog, res, one_row);
+    case 11: return row_fn<2048, ODD>(prog, res, one_row);
   }
   return nullptr;
 }
 
-static void *row_kernel(int odd, int logL, int E, int prog, bool res) {
+static void *row_kernel(int odd, int logL, int E, int prog, bool res, bool one_row) {
   if (E != ODD_E || logL < 0 || logL > ODD_MAX_LOGL) return nullptr;
-  if (odd == 3) return pick_row<3>(logL, prog, res);
+  if (odd == 3) return pick_row<3>(logL, prog, res, one_row);
   if constexpr (HAS_ODD5)
-    if (odd == 5) return pick_row<5>(logL, prog, res);
+    if (odd == 5) return pick_row<5>(logL, prog, res, one_row);
   return nullptr;
 }
 
@@ -251,7 +257,7 @@ hipError_t HK_CAT(launch_rows_odd_, HK_SUFFIX)(int odd, int logL, int E, int row
                                                const Shape &sh, const Ptrs &p0, const Strides &str, int64_t count,
                                                hipStream_t st) {
   using namespace HK_NS;
-  void *fn = row_kernel(odd, logL, E, sh.prog, sh.resident != 0);
+  void *fn = row_kernel(odd, logL, E, sh.prog, sh.resident != 0, sh.row_iters <= 1);
   KernelLimits k;
   if (!fn || sh.odd != odd || !HK_CAT(limits_odd_, HK_SUFFIX)(odd, logL, E, &k)) return hipErrorInvalidValue;
   const int threads = rows_per_wg * k.tps;

@@ -97,6 +97,29 @@ __global__ void __launch_bounds__(MAXT) k_rows_pass(Shape sh, Ptrs p0, Strides s
   rows_body<L, E, PROG, ODD, ROWS_PASS>(sh, p0, str, count);
 }
 
+// Pass-B rows one per lane group, without rows in turn (forward program):
+// the factor-5 rows when a schedule takes one row per lane group.  Without
+// the next row's operand in flight they need 219-231 VGPRs and no scratch
+// (the streamed form spills 12-152 bytes per lane).
+template <int L, int E, int MAXT, int ODD>
+__global__ void __launch_bounds__(MAXT) k_rows_pass1(Shape sh, Ptrs p0, Strides str, int64_t count) {
+  using RB = RowBody<T, L, E, ODD>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T> *smem = (cx<T> *)smem_raw;
+  const int tid = threadIdx.x;
+  const int rows = blockDim.x / RB::TPS;
+  const int rw = tid / RB::TPS;
+  const int t = tid % RB::TPS;
+  const PV P{&p0, &str, (int64_t)blockIdx.y, nullptr};
+  const int64_t row = (int64_t)blockIdx.x * rows + rw;
+  const bool valid = row < pass_rows(sh);
+  const cx<T> part = RB::run_fwd(sh, P, row, valid, t, smem + rw * RB::SEQ_LDS, false, g_tw24, g_tw4096);
+  if (sh.want_alpha) {
+    const cx<T> tot = (blockDim.x & 63) == 0 ? block_sum(part, smem, tid) : ragged_sum(part, smem, tid, (int)blockDim.x);
+    if (tid == 0) ws_partials<T>(sh, P)[blockIdx.x] = tot;
+  }
+}
+
 // Real-input resident rows (RealRowBody): instance blockIdx.x * rows + rw.
 template <int L, int E, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_rows_r2c(Shape sh, Ptrs p0, Strides str, int64_t count) {

@@ -161,13 +161,18 @@ static bool split_of(int logM, int split, int maxR, int *logR, int *logC) {
 // products gain from N ~ 2^18 on, batches of many small ones do), and cost
 // latency below.  HK_LENGTHS_AUTO therefore takes them when batch * (the
 // power-of-two length) >= 2^18; real inputs take their half-length transform
-// under every policy but HK_LENGTHS_POW2.
+// under every policy but HK_LENGTHS_POW2.  The three-pass factor-5 rows hold
+// five sequences per lane group: under HK_LENGTHS_AUTO they are taken where
+// batch * N >= 2^22 (measured on strided batches: from there on 8-20 %
+// faster than the next length, below it 4-46 % slower), and in grouped plans
+// not at all (F5_RESIDENT).
 static std::atomic<int> g_length_policy{HK_LENGTHS_AUTO};
 void set_length_policy(int policy) { g_length_policy.store(policy); }
 int length_policy() { return g_length_policy.load(); }
 constexpr int64_t kOddWorkMin = (int64_t)1 << 18;
+constexpr int64_t kFiveWorkMin = (int64_t)1 << 22;
 
-Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int64_t batch, bool allow5) {
+Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int64_t batch, int five) {
   const int policy = g_length_policy.load();
   const bool allow_r2c = allow_odd && policy != HK_LENGTHS_POW2;
   if (policy == HK_LENGTHS_POW2) allow_odd = false;
@@ -214,7 +219,7 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int6
     // The smallest N = odd * 2^logM >= d_H among the lengths with kernels.
     int64_t bestN = -1;
     for (int odd : {1, 3, 5}) {
-      if (odd == 5 && !allow5) continue;
+      if (odd == 5 && five == F5_NONE) continue;
       const int omax = odd == 1 ? MAX_LOGL : (allow_odd ? odd_max_logl(p.dt, odd, p.prog) : -1);
       if (omax < 0) continue;
       int logM = 0;
@@ -229,10 +234,10 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int6
         c.resident = true;
         c.logR = logM;
         c.logC = 0;
-      } else if (odd == 5 && policy == HK_LENGTHS_AUTO) {
-        // three-pass factor-5 rows hold five sequences per lane group and
-        // spill: measured slower than the next length (3 * 2^k or 2^k) for
-        // single products and for the mixed batch
+      } else if (odd == 5 && policy == HK_LENGTHS_AUTO &&
+                 (five != F5_AUTO || std::max<int64_t>(1, batch) * N < kFiveWorkMin)) {
+        // three-pass factor-5 rows (five sequences per lane group) pay only
+        // with enough work; in grouped plans they measured slower
         continue;
       } else if (!split_of(logM, split, omax, &c.logR, &c.logC)) {
         continue;

@@ -92,10 +92,12 @@ Status validate_backward(const Problem &p);
 // with N <= 8192 a length-N real transform done as a length-N/2 complex one;
 // powers of two only when allow_odd is false), resident vs multipass and the
 // split.
-// allow5 = false leaves the factor 5 out of the 1D lengths (the plan
-// autotuner's per-bucket alternative).
+// five: F5_AUTO takes the factor 5 in 1D lengths as the length policy says;
+// F5_RESIDENT only for resident lengths (grouped plans); F5_NONE not at all
+// (the plan autotuner's per-bucket alternative).
+enum : int { F5_NONE = 0, F5_RESIDENT = 1, F5_AUTO = 2 };
 Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd = true, int64_t batch = 1,
-                  bool allow5 = true);
+                  int five = F5_AUTO);
 // Process-wide transform-length policy (see hk_set_fft_lengths).
 void set_length_policy(int policy);
 int length_policy();

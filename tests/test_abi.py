@@ -249,7 +249,8 @@ def test_levels_argument_errors(L):
 
 def test_length_policies(L):
     """auto: odd-factor lengths once the power-of-two length reaches 2^18 (one
-    product), the factor 5 only where the transform is resident; pow2: never;
+    product), the factor 5 where the transform is resident (one product of a
+    three-pass 5 * 2^18 is too little work for it); pow2: never;
     smallest: always; unknown policies rejected."""
     assert L.hk_get_fft_lengths() == 0
     assert fft_layout(L, 190)[0] == 256 and fft_layout(L, 12000)[0] == 16384
@@ -261,6 +262,24 @@ def test_length_policies(L):
     assert fft_layout(L, 190)[0] == 192 and fft_layout(L, 1100000)[0] == 5 << 18
     assert L.hk_set_fft_lengths(7) == INVALID
     assert L.hk_set_fft_lengths(0) == OK and L.hk_get_fft_lengths() == 0
+
+
+def test_factor5_threepass_policy(L):
+    """auto takes the three-pass length 5 * 2^14 for d_H = 71,998 (m = 3,
+    n = 24,000) once instances * N >= 2^22: a strided batch of 64 sizes its
+    workspace as under 'smallest' (same length), a batch of 8 does not; the
+    per-instance workspace is N-proportional, so pow2 (2^17) needs more."""
+    def ws(policy, batch):
+        assert L.hk_set_fft_lengths(policy) == OK
+        b = ctypes.c_size_t(0)
+        assert L.hankel_tvp_strided_batched_workspace_size(HK_C64, 3, 24000, batch, ctypes.byref(b)) == OK
+        return b.value
+    try:
+        assert ws(0, 64) == ws(2, 64)
+        assert ws(0, 8) != ws(2, 8)
+        assert ws(1, 64) > ws(0, 64)
+    finally:
+        assert L.hk_set_fft_lengths(0) == OK
 
 
 def test_spectral_layout_and_errors(L):

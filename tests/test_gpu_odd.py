@@ -139,3 +139,38 @@ def test_tensor_matrix(m, n, R):
     torch.cuda.synchronize()
     To = oracle.tensor_matrix(m, seen(h, dtype), seen(U, dtype))
     assert rel(host(T), To) <= TOL[dtype]
+
+
+def test_factor5_threepass_under_default_policy():
+    """Under the default policy a strided batch with instances * N >= 2^22
+    takes the three-pass length 5 * 2^14 (d_H = 71,998 < 81,920): its result
+    is bit-identical to the smallest-length policy's (same length, same
+    kernels) and matches the oracle on sampled instances."""
+    import paper_1401_6238_amd as hk
+    dtype = torch.complex64
+    m, n, B = 3, 24000, 64
+    probs = [wl.random_problem(6100 + b, m, [n] * m, True, want_alpha=True) for b in (0, 31, 63)]
+    g = torch.Generator().manual_seed(61)
+    H = (torch.randn(B, m * (n - 1) + 1, generator=g, dtype=torch.float64) / 2 ** 0.5).to(dtype)
+    X = (torch.randn(B, n, generator=g, dtype=torch.float64) / (2 * n) ** 0.5).to(dtype)
+    for k, b in enumerate((0, 31, 63)):
+        H[b] = torch.from_numpy(probs[k].h).to(dtype)
+        X[b] = torch.from_numpy(probs[k].vectors[1]).to(dtype)
+    H, X = H.to("cuda"), X.to("cuda")
+    print_case(test="factor5_threepass_auto", m=m, n=n, B=B)
+    ys, a_s = hk.hankel_tvp_strided_batched(H, X, m, True, True)  # module policy: smallest
+    hk.hk_set_fft_lengths("auto")
+    try:
+        ya, aa = hk.hankel_tvp_strided_batched(H, X, m, True, True)
+        hk.hk_set_fft_lengths("pow2")
+        yp, _ = hk.hankel_tvp_strided_batched(H, X, m, True, True)
+    finally:
+        hk.hk_set_fft_lengths("smallest")
+    torch.cuda.synchronize()
+    assert torch.equal(ya, ys) and torch.equal(aa, a_s)
+    assert not torch.equal(ya, yp)
+    for k, b in enumerate((0, 31, 63)):
+        p = probs[k]
+        yo, ao = oracle.tvp(m, [n] * m, seen(p.h, dtype), [seen(p.vectors[1], dtype)] * m, True, True)
+        assert rel(host(ya[b]), yo) <= TOL[dtype], b
+        check_alpha(complex(host(aa[b:b + 1])[0]), ao, dtype, b)
