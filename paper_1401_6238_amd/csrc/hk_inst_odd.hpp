@@ -36,10 +36,12 @@ constexpr bool has_bwd(int odd) { return sizeof(T) == 4 && odd == 3; }
 
 // resident instances and pass-B rows are separate kernels (k_rows_res,
 // k_rows_pass): each path gets its own register allocation
-// Factor-5 forward pass-B rows one per lane group (no rows in turn):
-// k_rows_pass1, which fits the registers where the streamed kernel spills
-// (2-4 % faster); the factor-3 rows measured 1-2 % slower that way at three
-// waves per SIMD and keep the streamed kernel.
+// Forward pass-B rows one per lane group (no rows in turn) run k_rows_pass1
+// where it fits the registers and the streamed kernel spills: the float
+// factor 5 (2-4 % faster) and the double factor 3 with rows of up to 256
+// points (7-9 % faster; 1024-point rows measured 2-3 % slower).  The float
+// factor-3 rows measured 1-2 % slower that way at three waves per SIMD and
+// keep the streamed kernel.
 template <int L, int ODD>
 static void *row_fn(int prog, bool res, bool one_row) {
   if (prog == PROG_BWD) {
@@ -49,7 +51,7 @@ static void *row_fn(int prog, bool res, bool one_row) {
     return nullptr;
   }
   if (res) return (void *)&k_rows_res<L, ODD_E, ODD_ROW_MAXT, PROG_FWD, ODD>;
-  if constexpr (ODD == 5)
+  if constexpr (ODD == 5 || (sizeof(T) == 8 && L <= 256))
     if (one_row) return (void *)&k_rows_pass1<L, ODD_E, ODD_ROW_MAXT, ODD>;
   return (void *)&k_rows_pass<L, ODD_E, ODD_ROW_MAXT, PROG_FWD, ODD>;
 }

@@ -98,9 +98,9 @@ __global__ void __launch_bounds__(MAXT) k_rows_pass(Shape sh, Ptrs p0, Strides s
 }
 
 // Pass-B rows one per lane group, without rows in turn (forward program):
-// the factor-5 rows when a schedule takes one row per lane group.  Without
-// the next row's operand in flight they need 219-231 VGPRs and no scratch
-// (the streamed form spills 12-152 bytes per lane).
+// the float factor-5 and double factor-3 rows when a schedule takes one row
+// per lane group.  Without the next row's operand in flight they need
+// 216-231 VGPRs and no scratch (the streamed form spills 12-248 bytes per lane).
 template <int L, int E, int MAXT, int ODD>
 __global__ void __launch_bounds__(MAXT) k_rows_pass1(Shape sh, Ptrs p0, Strides str, int64_t count) {
   using RB = RowBody<T, L, E, ODD>;
