@@ -115,9 +115,9 @@ static void *group_kernel(int odd, int kind, int logL) {
   return nullptr;
 }
 
-template <int L>
+template <int L, int E = ODD_E>
 static KernelLimits lim_of() {
-  using S = FFTShape<L, ODD_E>;
+  using S = FFTShape<L, E>;
   KernelLimits k;
   k.tps = S::TPS;
   k.seq_lds = S::ROW_SEQ;
@@ -359,13 +359,46 @@ hipError_t HK_CAT(launch_group_r2cp_, HK_SUFFIX)(const BatchArgs &args, int logL
   return launch_kernel(fn, dim3((unsigned)ntasks), dim3(BATCH_BLK), kargs, lds, st);
 }
 
+namespace HK_NS {
+// Limits of the grouped pass-B rows (GroupRowbE elements per lane).
+template <int L, int ODD>
+static KernelLimits lim_rowb() {
+  return lim_of<L, GroupRowbE<L, ODD>::value>();
+}
+template <int ODD>
+static KernelLimits lim_rowb_pick(int logL) {
+  switch (logL) {
+    case 0: return lim_rowb<1, ODD>();
+    case 1: return lim_rowb<2, ODD>();
+    case 2: return lim_rowb<4, ODD>();
+    case 3: return lim_rowb<8, ODD>();
+    case 4: return lim_rowb<16, ODD>();
+    case 5: return lim_rowb<32, ODD>();
+    case 6: return lim_rowb<64, ODD>();
+    case 7: return lim_rowb<128, ODD>();
+    case 8: return lim_rowb<256, ODD>();
+    case 9: return lim_rowb<512, ODD>();
+    case 10: return lim_rowb<1024, ODD>();
+    default: return lim_rowb<2048, ODD>();
+  }
+}
+}  // namespace HK_NS
+
+int HK_CAT(group_rowb_tps_, HK_SUFFIX)(int odd, int logL) {
+  using namespace HK_NS;
+  if (logL < 0 || logL > ODD_MAX_LOGL) return 0;
+  return (odd == 5 ? lim_rowb_pick<5>(logL) : lim_rowb_pick<3>(logL)).tps;
+}
+
 hipError_t HK_CAT(launch_group_odd_, HK_SUFFIX)(const BatchArgs &args, int odd, int kind, int logL, int ntasks,
                                                 hipStream_t st) {
   using namespace HK_NS;
   if (ntasks <= 0) return hipSuccess;
   void *fn = group_kernel(odd, kind, logL);
   KernelLimits k;
-  if (!fn || !HK_CAT(limits_odd_, HK_SUFFIX)(odd, logL, ODD_E, &k) || k.tps > BATCH_BLK) return hipErrorInvalidValue;
+  if (!fn || !HK_CAT(limits_odd_, HK_SUFFIX)(odd, logL, ODD_E, &k)) return hipErrorInvalidValue;
+  if (kind == GK_ROWB) k = odd == 5 ? lim_rowb_pick<5>(logL) : lim_rowb_pick<3>(logL);
+  if (k.tps > BATCH_BLK) return hipErrorInvalidValue;
   const size_t lds = std::max((size_t)BATCH_BLK, (size_t)(BATCH_BLK / k.tps) * k.seq_lds) * sizeof(cx<T>);
   hipError_t e = ensure_lds(fn, lds);
   if (e != hipSuccess) return e;

@@ -277,10 +277,14 @@ struct BatchRowE {
 };
 // Elements per lane of the grouped pass-B rows: 4 up to 2048 points (fewer
 // registers, more waves per SIMD; pass B of large batches is latency-bound at
-// two waves), 8 beyond.  The persistent kernel keeps BATCH_E_ROW.
+// two waves), 8 beyond; the float factor-3 rows of 8-512 points take 8
+// (radix-8 passes, half the LDS exchanges; 195-203 VGPRs, no scratch).  The
+// persistent kernel keeps BATCH_E_ROW.
 template <int L, int ODD>
 struct GroupRowbE {
-  static constexpr int value = (ODD > 1 || L <= 2048) ? 4 : BATCH_E_ROW;
+  static constexpr int value = (ODD == 3 && sizeof(T) == 4 && L >= 8 && L <= 512)
+                                   ? 8
+                                   : ((ODD > 1 || L <= 2048) ? 4 : BATCH_E_ROW);
 };
 
 

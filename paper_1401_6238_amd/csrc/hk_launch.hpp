@@ -66,6 +66,7 @@ hipError_t launch_mode1_cotangent(bool dbl, void *out, const void *v, const void
   hipError_t init_tables_odd_##SUFFIX(const double *tw4096_interleaved, const double *tw24_interleaved);  \
   bool limits_odd_##SUFFIX(int odd, int logL, int E, KernelLimits *out);                                \
   int odd_row_e_##SUFFIX();                                                                             \
+  int group_rowb_tps_##SUFFIX(int odd, int logL);                                                       \
   bool odd_bwd_ok_##SUFFIX(int odd);                                                                    \
   hipError_t launch_rows_odd_##SUFFIX(int odd, int logL, int E, int rows_per_wg, dim3 grid, const Shape &sh, \
                                       const Ptrs &p0, const Strides &str, int64_t count, hipStream_t st);   \
