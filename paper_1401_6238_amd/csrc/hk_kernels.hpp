@@ -85,9 +85,9 @@ __global__ void __launch_bounds__(MAXT) k_rows(Shape sh, Ptrs p0, Strides str, i
   rows_body<L, E, PROG, ODD, ROWS_ANY>(sh, p0, str, count);
 }
 // The odd-factor rows come as two kernels, resident instances and pass-B
-// rows: compiled together, the two paths' register needs add up (factor 3:
-// 205-225 VGPRs against 117-141 resident alone; factor 5 resident rows
-// spilled to scratch).
+// rows: compiled as one kernel, both paths took the larger path's register
+// count (float factor 3: up to 225 VGPRs against up to 163 for the resident
+// rows alone; the factor-5 resident rows spilled to scratch).
 template <int L, int E, int MAXT, int PROG, int ODD>
 __global__ void __launch_bounds__(MAXT) k_rows_res(Shape sh, Ptrs p0, Strides str, int64_t count) {
   rows_body<L, E, PROG, ODD, ROWS_RES>(sh, p0, str, count);
@@ -99,8 +99,9 @@ __global__ void __launch_bounds__(MAXT) k_rows_pass(Shape sh, Ptrs p0, Strides s
 
 // Pass-B rows one per lane group, without rows in turn (forward program):
 // the float factor-5 and double factor-3 rows when a schedule takes one row
-// per lane group.  Without the next row's operand in flight they need
-// 216-231 VGPRs and no scratch (the streamed form spills 12-248 bytes per lane).
+// per lane group.  Without the next row's operand in flight they spill less:
+// none up to 256-point float and 64-point double rows, 8-72 bytes per lane
+// beyond, against 12-248 for the streamed form.
 template <int L, int E, int MAXT, int ODD>
 __global__ void __launch_bounds__(MAXT) k_rows_pass1(Shape sh, Ptrs p0, Strides str, int64_t count) {
   using RB = RowBody<T, L, E, ODD>;
@@ -278,7 +279,7 @@ struct BatchRowE {
 // Elements per lane of the grouped pass-B rows: 4 up to 2048 points (fewer
 // registers, more waves per SIMD; pass B of large batches is latency-bound at
 // two waves), 8 beyond; the float factor-3 rows of 8-512 points take 8
-// (radix-8 passes, half the LDS exchanges; 195-203 VGPRs, no scratch).  The
+// (radix-8 passes, half the LDS exchanges; 188-247 VGPRs, no scratch).  The
 // persistent kernel keeps BATCH_E_ROW.
 template <int L, int ODD>
 struct GroupRowbE {
