@@ -530,8 +530,8 @@ hk_status_t block_hankel_tvp_strided_batched(hk_dtype_t dt, const void *H, int64
  * would cost latency; under AUTO the factor 5 is taken for resident
  * transforms (5 * 2^k with 2^k <= 2048), for three-pass ones only where
  * instances * N >= 2^22 (strided batches and single calls; not in plans), and
- * not for BHHB row axes: with less work its three-pass row kernels are slower
- * than the next length (3 * 2^k or 2^k);
+ * for BHHB row axes where instances * grid >= 2^22: with less work its
+ * three-pass row kernels are slower than the next length (3 * 2^k or 2^k);
  * HK_LENGTHS_POW2 takes power-of-two complex transforms
  * only.  Real forward products use their half-length transform under AUTO
  * and SMALLEST.  Workspace sizes depend on the policy: query them under the

@@ -292,7 +292,11 @@ Status layout_for(const Problem &p, int split, Layout *out, bool allow_odd, int6
         int lr = 0;
         const int64_t nr = axis(rows, orow, &lr);
         if (lr > odd_max_logl(p.dt, orow, p.prog)) continue;
-        if (orow == 5 && policy == HK_LENGTHS_AUTO) continue;  // the factor-5 row pass spills (see 1D)
+        // factor-5 rows: with enough work only, as in 1D (measured on strided
+        // batches: from batch * grid >= 2^22 on 2-24 % faster, below 5-15 % slower)
+        if (orow == 5 && policy == HK_LENGTHS_AUTO &&
+            (five != F5_AUTO || std::max<int64_t>(1, batch) * nr * nc_best < kFiveWorkMin))
+          continue;
         if (nr_odd < 0 || nr < nr_odd) {
           nr_odd = nr;
           orow_best = orow;

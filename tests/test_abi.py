@@ -264,6 +264,24 @@ def test_length_policies(L):
     assert L.hk_set_fft_lengths(0) == OK and L.hk_get_fft_lengths() == 0
 
 
+def test_factor5_block_rows_policy(L):
+    """BHHB row axes take 5 * 2^k under auto once instances * grid >= 2^22:
+    rows 1228 (inner 410, m = 3) by 511 columns (171 blocks) give 1536 x 512
+    for one tensor and 1280 x 512 for a batch of 8 (8 * 1280 * 512 > 2^22)."""
+    def grid(policy, batch):
+        assert L.hk_set_fft_lengths(policy) == OK
+        inner, blocks = (ctypes.c_int64 * 3)(410, 410, 410), (ctypes.c_int64 * 3)(171, 171, 171)
+        r, c = ctypes.c_int64(0), ctypes.c_int64(0)
+        assert L.block_hankel_tvp_layout(HK_C64, 3, inner, blocks, batch, ctypes.byref(r), ctypes.byref(c)) == OK
+        return r.value, c.value
+    try:
+        assert grid(0, 1) == (1536, 512)
+        assert grid(0, 8) == (1280, 512) == grid(2, 8)
+        assert grid(1, 8) == (2048, 512)
+    finally:
+        assert L.hk_set_fft_lengths(0) == OK
+
+
 def test_factor5_threepass_policy(L):
     """auto takes the three-pass length 5 * 2^14 for d_H = 71,998 (m = 3,
     n = 24,000) once instances * N >= 2^22: a strided batch of 64 sizes its

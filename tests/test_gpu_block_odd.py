@@ -97,3 +97,46 @@ def test_block_odd_strided_batch(n, grid):
                                   True, True)
         assert rel(host(y[b]), yo) <= TOL[dtype]
         check_alpha(complex(host(a[b:b + 1])[0]), ao, dtype, b)
+
+
+def test_block_factor5_rows_under_default_policy():
+    """A strided batch of 64 BHHB tensors whose rows (307) take 5 * 2^6 under
+    the default policy (64 * 320 * 512 >= 2^22): bit-identical to the
+    smallest-length policy, different from powers of two, and sampled outputs
+    and alpha of two tensors against the oracle."""
+    import paper_1401_6238_amd as hk
+    dtype, m, inner, blocks, B = torch.complex64, 3, 103, 171, 64
+    dims, bdims = [inner] * m, [blocks] * m
+    probs = [wl.random_problem(3500 + b, m, dims, True, want_alpha=True, block_dims=bdims) for b in (0, 63)]
+    g = torch.Generator().manual_seed(35)
+    rows, cols = m * (inner - 1) + 1, m * (blocks - 1) + 1
+    Hs = (torch.randn(B, rows * cols, generator=g, dtype=torch.float64) / 2 ** 0.5).to(dtype)
+    Xs = (torch.randn(B, inner * blocks, generator=g, dtype=torch.float64) / 2 ** 0.5).to(dtype)
+    for k, b in enumerate((0, 63)):
+        Hs[b] = torch.from_numpy(probs[k].h).to(dtype)
+        Xs[b] = torch.from_numpy(probs[k].vectors[1]).to(dtype)
+    Hs, Xs = Hs.to("cuda"), Xs.to("cuda")
+    print_case(test="block_factor5_rows_auto", B=B)
+    assert hk.block_hankel_tvp_layout(dtype, m, dims, bdims, B) == (320, 512)  # module policy: smallest
+    ys, a_s = hk.block_hankel_tvp_strided_batched(Hs, Xs, m, inner, blocks, True, True)
+    hk.hk_set_fft_lengths("auto")
+    try:
+        assert hk.block_hankel_tvp_layout(dtype, m, dims, bdims, B) == (320, 512)
+        assert hk.block_hankel_tvp_layout(dtype, m, dims, bdims, 1) == (384, 512)
+        ya, aa = hk.block_hankel_tvp_strided_batched(Hs, Xs, m, inner, blocks, True, True)
+        hk.hk_set_fft_lengths("pow2")
+        yp, _ = hk.block_hankel_tvp_strided_batched(Hs, Xs, m, inner, blocks, True, True)
+    finally:
+        hk.hk_set_fft_lengths("smallest")
+    torch.cuda.synchronize()
+    assert torch.equal(ya, ys) and torch.equal(aa, a_s)
+    assert not torch.equal(ya, yp)
+    n_out = inner * blocks
+    idx = np.unique(np.concatenate([np.arange(64), np.arange(n_out - 64, n_out),
+                                    np.random.default_rng(35).integers(0, n_out, 128)]))
+    for k, b in enumerate((0, 63)):
+        p = probs[k]
+        hs, vs = seen(p.h, dtype), [seen(p.vectors[1], dtype)] * m
+        yo, ao = oracle.block_tvp_sampled(m, dims, bdims, hs, vs, idx, want_alpha=True)
+        assert rel(host(ya[b])[idx], yo) <= TOL[dtype], b
+        check_alpha(complex(host(aa[b:b + 1])[0]), ao, dtype, b)
