@@ -180,3 +180,28 @@ def test_ragged_workgroup_sums(tmp_path, rows):
     torch.cuda.synchronize()
     assert rel(host(y), yo) <= TOL[rdt]
     check_alpha(complex(host(a.reshape(1))[0]), ao, rdt, rows)
+
+
+def test_factor5_schedules(tmp_path):
+    """The three-pass length 5 * 2^12 (float) under schedules that run the
+    factor-5 rows one per lane group (no rows in turn: 1 or 3 rows per
+    workgroup) and streamed (2 or 4 rows in turn, split -1 / +1)."""
+    import paper_1401_6238_amd as hk
+    dtype = torch.complex64
+    m, n = 3, 6500  # d_H = 19,498 -> 5 * 2^12 under the smallest-length policy
+    hk.hk_set_fft_lengths("smallest")
+    try:
+        assert hk.hk_fft_layout(m * (n - 1) + 1)[0] == 5 << 12
+        prob = wl.random_problem(4800, m, [n] * m, True, want_alpha=True)
+        h, x = to_dev(prob.h, dtype), to_dev(prob.vectors[1], dtype)
+        yo, ao = oracle.tvp(m, [n] * m, seen(prob.h, dtype), [seen(prob.vectors[1], dtype)] * m, True, True)
+        for sched in [(4, 1, 8, 8, 0, 0, 1), (4, 3, 16, 16, 0, 0, 1), (4, 2, 8, 8, 0, 0, 2), (4, 1, 16, 4, 1, 1, 4),
+                      (4, 2, 16, 8, -1, 0, 1)]:
+            print_case(test="factor5_schedules", sched=sched)
+            install(tmp_path, (0, 0, 0, 5, 12, -1, 0), sched)
+            y, a = hk.hankel_tvp(h, x, m, True, True)
+            torch.cuda.synchronize()
+            assert rel(host(y), yo) <= TOL[dtype], sched
+            check_alpha(complex(host(a.reshape(1))[0]), ao, dtype, sched)
+    finally:
+        hk.hk_set_fft_lengths("auto")
