@@ -261,8 +261,10 @@ static Status plan_build(hk_plan_t *out, hk_dtype_t dt, const hk_problem_t *prob
       return k.tps;
     }
     if (sh.odd > 1) {
-      if (!sh.resident)  // grouped pass-B rows (GroupRowbE elements per lane)
-        return dbl(dt) ? group_rowb_tps_f64(sh.odd, sh.logR) : group_rowb_tps_f32(sh.odd, sh.logR);
+      if (!sh.resident) {  // grouped pass-B rows (GroupRowbE elements per lane)
+        const int t = dbl(dt) ? group_rowb_tps_f64(sh.odd, sh.logR) : group_rowb_tps_f32(sh.odd, sh.logR);
+        return std::max(1, t);
+      }
       row_limits(dt, sh.odd, sh.logR, e_odd, &k);
       return k.tps;
     }
