@@ -1,6 +1,8 @@
 """GPU parity at the largest transform lengths the library accepts
-(N <= 2^24): m = 2 products whose d_H fills N = 2^24 (a power of two) and
-N = 3 * 2^22 (the longest odd-factor length below the limit), in complex64 and
+(N <= 2^24): m = 2 products whose d_H fills N = 2^24 (a power of two),
+N = 3 * 2^22 (the longest odd-factor length below the limit) and N = 5 * 2^21
+(the longest factor-5 length, three-pass with 2048-point rows; complex128,
+which has no factor-5 kernels, takes 3 * 2^22 there), in complex64 and
 complex128, on inputs shaped like the large single product (h an 8-term
 exponential sum plus CN(0, 1e-6) noise, x ~ CN(0, 1/n)).  Sampled outputs y_i
 are compared with the oracle's direct sums on exactly the inputs the GPU sees;
@@ -21,7 +23,7 @@ pytestmark = pytest.mark.gpu
 from gpu_util import TOL, check_alpha, host, print_case, rel, seen, to_dev  # noqa: E402
 
 # (n, expected transform length): d_H = 2n - 1
-CASES = [((1 << 23), 1 << 24), (3 << 21, 3 << 22)]
+CASES = [((1 << 23), 1 << 24), (3 << 21, 3 << 22), (5 << 20, 5 << 21)]
 
 
 @functools.lru_cache(maxsize=None)
