@@ -38,6 +38,8 @@ CASES = [
     ((100, 60, 50), (130, 100, 102), torch.complex64, (256, 384)),    # power-of-two rows, 3 x 128 columns
     ((100, 60, 50), (130, 100, 102), torch.complex128, (256, 384)),
     ((100, 60, 50), (100, 100, 102), torch.complex64, (256, 320)),    # power-of-two rows, 5 x 64 columns
+    ((100, 100, 102), (120, 100, 102), torch.complex64, (320, 320)),  # 5 x 64 on both axes
+    ((100, 100, 102), (120, 100, 102), torch.complex128, (384, 320)),  # double: 3 x 128 rows, 5 x 64 columns
 ]
 
 
