@@ -4,8 +4,9 @@
 // column kernels (which take the odd factor at run time) come from the
 // power-of-two unit.  A lane of these rows holds the same bins of all `odd`
 // sequences (the operand being transformed and the running spectral product:
-// 2 * odd * E complex values), so their elements per lane are fixed low, 4,
-// with up to 512 lanes per row; double precision has the factor 3 only (a
+// 2 * odd * E complex values), so their elements per lane are low, 4 (8 for
+// the grouped float factor-3 pass-B rows of up to 512 points), with up to
+// 512 lanes per row; double precision has the factor 3 only (a
 // factor-5 lane would not fit its registers).  The adjoint program keeps four
 // spectra per lane and is built for float with the factor 3 only (the other
 // variants spill to scratch); other adjoint shapes use power-of-two lengths.
@@ -34,8 +35,8 @@ constexpr bool HAS_ODD5 = sizeof(T) == 4;
 
 constexpr bool has_bwd(int odd) { return sizeof(T) == 4 && odd == 3; }
 
-// resident instances and pass-B rows are separate kernels (k_rows_res,
-// k_rows_pass): each path gets its own register allocation
+// Resident instances and pass-B rows are separate kernels (k_rows_res,
+// k_rows_pass): each path gets its own register allocation.
 // Forward pass-B rows one per lane group (no rows in turn) run k_rows_pass1
 // where it fits the registers and the streamed kernel spills: the float
 // factor 5 (2-4 % faster) and the double factor 3 with rows of up to 256
