@@ -1198,6 +1198,24 @@ def run_extras(args, data, hk, _lib, L, torch, dev):
     log("real batch", resr)
     del ritems
 
+    # factor-5 three-pass strided batch: 64 products of m = 4, n = 18,000 (d_H =
+    # 71,997): N = 5 * 2^14 under the default policy (64 * N >= 2^22), against
+    # 3 * 2^15 without the factor 5 in three passes and 2^17 with powers of two
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    mf, nf, bf = 4, 18000, 64
+    Hf = (torch.randn(bf, mf * (nf - 1) + 1, dtype=torch.complex64, generator=gen)).to(dev)
+    Xf = (torch.randn(bf, nf, dtype=torch.complex64, generator=gen) / nf ** 0.5).to(dev)
+    res5 = {}
+    for name, pol in (("default", "auto"), ("pow2", "pow2")):
+        hk.hk_set_fft_lengths(pol)
+        ms = time_region(torch, lambda: hk.hankel_tvp_strided_batched(Hf, Xf, mf, True, True), 10)
+        res5[name] = {"TVP_s": round(bf / ms * 1000, 1), "us_per_batch": round(ms * 1e3, 1)}
+    hk.hk_set_fft_lengths("auto")
+    res5["N_default"] = 5 << 14
+    ex["factor5_batch_c64"] = res5
+    log("factor-5 batch", res5)
+    del Hf, Xf
+
     # adjoint batch: 256 instances, m=4, n=2^16: forward (g, f) and adjoint, c64 and c128
     adj = data["adjoint"]
     res4 = {}
